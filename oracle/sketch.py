@@ -1,0 +1,76 @@
+"""Sketches S*X (Sec. 2.1; Algorithm 2 step 1), plain FP64 loops.
+
+CountSketch follows the streaming model of Sec. 3.1.2: rows are read in
+ascending order and row i is added, with sign s(i), into sketch row h(i). The
+sums are FP64 and taken in ascending row order within each bucket.
+
+The Gaussian sketch is S = G / sqrt(r) with G_{j,i} standard normal, so that
+E[S^T S] = I (the scaling reading of the Gaussian family listed in Sec. 2.1).
+
+Column equilibration: D_j = 2^-e_j with e_j = floor(log2 max_i |X_ij|)
+(D_j = 1 for an all-zero column). Because D is a power of two,
+S (X D) = (S X) D exactly, and leverage scores are invariant under X -> X D;
+D only conditions the rank decision and the rounding.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import streams
+
+
+def column_scale(colmax: np.ndarray) -> np.ndarray:
+    """Power-of-two column scales from column max-abs values."""
+    out = np.ones(colmax.shape[0], dtype=np.float64)
+    for j, m in enumerate(colmax):
+        m = float(m)
+        if m > 0.0 and math.isfinite(m):
+            _, e = math.frexp(m)            # m = f * 2^e, f in [0.5, 1)
+            out[j] = math.ldexp(1.0, -(e - 1))
+    return out
+
+
+def colmax_dense(x: np.ndarray) -> np.ndarray:
+    return np.abs(np.asarray(x, dtype=np.float64)).max(axis=0)
+
+
+def colmax_csr(csr) -> np.ndarray:
+    out = np.zeros(csr.d, dtype=np.float64)
+    np.maximum.at(out, csr.col_idx, np.abs(csr.val.astype(np.float64)))
+    return out
+
+
+def countsketch_dense(x: np.ndarray, seed: int, r: int,
+                      row_offset: int = 0) -> np.ndarray:
+    """SX (r x d, FP64): SX[h(i)] += s(i) x_i for i ascending."""
+    n, d = x.shape
+    bucket, sign = streams.bucket_sign(seed, r, np.arange(n) + row_offset)
+    sx = np.zeros((r, d), dtype=np.float64)
+    xf = np.asarray(x, dtype=np.float64)
+    for i in range(n):
+        sx[bucket[i]] += float(sign[i]) * xf[i]
+    return sx
+
+
+def countsketch_csr(csr, seed: int, r: int) -> np.ndarray:
+    """CountSketch of a CSR matrix, same order as the dense form."""
+    bucket, sign = streams.bucket_sign(seed, r, np.arange(csr.n))
+    sx = np.zeros((r, csr.d), dtype=np.float64)
+    rp = csr.row_ptr
+    for i in range(csr.n):
+        a, b = int(rp[i]), int(rp[i + 1])
+        if b > a:
+            sx[bucket[i], csr.col_idx[a:b]] += float(sign[i]) * \
+                csr.val[a:b].astype(np.float64)
+    return sx
+
+
+def gaussian_sketch_dense(x: np.ndarray, seed: int, r: int,
+                          g: np.ndarray | None = None) -> np.ndarray:
+    """SX = G X / sqrt(r) in FP64 (G from the Gaussian stream unless given)."""
+    n = x.shape[0]
+    if g is None:
+        g = streams.gaussian_sketch_matrix(seed, r, n)
+    return (g @ np.asarray(x, dtype=np.float64)) / math.sqrt(r)

@@ -1,0 +1,153 @@
+"""Seeded random streams, written from their published definitions.
+
+The paper implements CountSketch "as a pair of hash functions" (Sec. 3.1.2)
+without naming the family, and draws Gaussian sketches (Sec. 2.1) without
+naming a generator. The readings used here (and, separately, by the GPU
+library) are:
+
+* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): state += 0x9E3779B97F4A7C15,
+  then the 64-bit finaliser z ^= z>>30; z *= 0xBF58476D1CE4E5B9; z ^= z>>27;
+  z *= 0x94D049BB133111EB; z ^= z>>31.
+* Hash coefficients for stream ``s``: start from seed XOR (s * 0xD1B54A32D192ED03
+  mod 2^64), draw four SplitMix64 outputs, reduce each mod p = 2^61 - 1.
+* Degree-3 Carter-Wegman polynomial P(i) = a3 i^3 + a2 i^2 + a1 i + a0 mod p
+  (4-wise independent over the prime field), evaluated by Horner's rule.
+  Bucket h(i) = P_1(i) mod r; sign s(i) = +1 if P_2(i) is even, else -1.
+* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): multipliers
+  0xD2511F53, 0xCD9E8D57, Weyl key increments 0x9E3779B9, 0xBB67AE85.
+* Gaussian entry (a, b) of stream s: one Philox block with counter
+  (b >> 1, lo32(a), hi32(a), s) and key (lo32(seed), hi32(seed)); two 53-bit
+  uniforms u1 = (m1 + 1) 2^-53 in (0, 1] from words (0, 1) and u2 = m2 2^-53
+  from words (2, 3); Box-Muller z0 = sqrt(-2 ln u1) cos(2 pi u2),
+  z1 = sqrt(-2 ln u1) sin(2 pi u2); entry (a, b) takes z0 if b is even.
+  For the sketch S (r x n), a is the row index of X and b the sketch row; for
+  Pi_2 (d x k), a is the row of Pi_2 and b its column.
+
+Stream ids: 1 bucket hash, 2 sign hash, 3 Gaussian sketch, 4 Pi_2.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+MASK64 = (1 << 64) - 1
+MASK32 = 0xFFFFFFFF
+P61 = (1 << 61) - 1
+
+STREAM_BUCKET = 1
+STREAM_SIGN = 2
+STREAM_GAUSS_S = 3
+STREAM_PI2 = 4
+
+
+def splitmix64_mix(z: int) -> int:
+    """SplitMix64 output finaliser on a 64-bit integer."""
+    z &= MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def splitmix64_sequence(state: int, count: int) -> list[int]:
+    """First ``count`` SplitMix64 outputs from ``state``."""
+    out = []
+    for _ in range(count):
+        state = (state + 0x9E3779B97F4A7C15) & MASK64
+        out.append(splitmix64_mix(state))
+    return out
+
+
+def hash_coeffs(seed: int, stream: int) -> list[int]:
+    """(a0, a1, a2, a3) of the degree-3 polynomial hash for ``stream``."""
+    state = (seed ^ ((stream * 0xD1B54A32D192ED03) & MASK64)) & MASK64
+    return [z % P61 for z in splitmix64_sequence(state, 4)]
+
+
+def poly_hash(coeffs: list[int], idx) -> np.ndarray:
+    """P(i) mod 2^61-1 for every i in ``idx`` (exact Python-integer arithmetic)."""
+    a0, a1, a2, a3 = coeffs
+    i = np.asarray(idx, dtype=np.int64).astype(object)
+    acc = (a3 * i + a2) % P61
+    acc = (acc * i + a1) % P61
+    acc = (acc * i + a0) % P61
+    return acc
+
+
+def bucket_sign(seed: int, r: int, idx) -> tuple[np.ndarray, np.ndarray]:
+    """CountSketch bucket h(i) in [0, r) and sign s(i) in {+1, -1}."""
+    hb = poly_hash(hash_coeffs(seed, STREAM_BUCKET), idx)
+    hs = poly_hash(hash_coeffs(seed, STREAM_SIGN), idx)
+    bucket = np.array([int(v) % r for v in hb], dtype=np.int64)
+    sign = np.array([1 - 2 * (int(v) & 1) for v in hs], dtype=np.int64)
+    return bucket, sign
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10
+# --------------------------------------------------------------------------
+_PHILOX_M0 = 0xD2511F53
+_PHILOX_M1 = 0xCD9E8D57
+_PHILOX_W0 = 0x9E3779B9
+_PHILOX_W1 = 0xBB67AE85
+
+
+def philox4x32_10(c0, c1, c2, c3, k0, k1):
+    """Philox4x32 with 10 rounds on arrays of 32-bit counter words.
+
+    Returns the four 32-bit output words as uint64 arrays.
+    """
+    c0 = np.asarray(c0, dtype=np.uint64) & MASK32
+    c1 = np.asarray(c1, dtype=np.uint64) & MASK32
+    c2 = np.asarray(c2, dtype=np.uint64) & MASK32
+    c3 = np.asarray(c3, dtype=np.uint64) & MASK32
+    k0 = np.uint64(k0 & MASK32)
+    k1 = np.uint64(k1 & MASK32)
+    m0 = np.uint64(_PHILOX_M0)
+    m1 = np.uint64(_PHILOX_M1)
+    lo_mask = np.uint64(MASK32)
+    sh = np.uint64(32)
+    for rnd in range(10):
+        if rnd > 0:
+            k0 = np.uint64((int(k0) + _PHILOX_W0) & MASK32)
+            k1 = np.uint64((int(k1) + _PHILOX_W1) & MASK32)
+        p0 = c0 * m0            # < 2^64, exact in uint64
+        p1 = c2 * m1
+        hi0, lo0 = p0 >> sh, p0 & lo_mask
+        hi1, lo1 = p1 >> sh, p1 & lo_mask
+        c0, c1, c2, c3 = hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0
+    return c0, c1, c2, c3
+
+
+def gaussian(seed: int, stream: int, a, b) -> np.ndarray:
+    """Standard normal entry (a, b) of ``stream`` (arrays broadcast), FP64."""
+    a = np.asarray(a, dtype=np.uint64)
+    b = np.asarray(b, dtype=np.uint64)
+    a, b = np.broadcast_arrays(a, b)
+    w0, w1, w2, w3 = philox4x32_10(b >> np.uint64(1), a & np.uint64(MASK32),
+                                   a >> np.uint64(32),
+                                   np.full(a.shape, stream, dtype=np.uint64),
+                                   seed & MASK32, (seed >> 32) & MASK32)
+    m1 = (w0 << np.uint64(21)) | (w1 >> np.uint64(11))
+    m2 = (w2 << np.uint64(21)) | (w3 >> np.uint64(11))
+    m1 &= np.uint64((1 << 53) - 1)
+    m2 &= np.uint64((1 << 53) - 1)
+    u1 = (m1.astype(np.float64) + 1.0) * 2.0 ** -53
+    u2 = m2.astype(np.float64) * 2.0 ** -53
+    rad = np.sqrt(-2.0 * np.log(u1))
+    ang = 2.0 * np.pi * u2
+    odd = (b & np.uint64(1)).astype(bool)
+    return np.where(odd, rad * np.sin(ang), rad * np.cos(ang))
+
+
+def pi2_matrix(seed: int, d: int, k: int) -> np.ndarray:
+    """Second JL projection Pi_2 (d x k), entries N(0, 1/k)."""
+    j = np.arange(d, dtype=np.uint64)[:, None]
+    c = np.arange(k, dtype=np.uint64)[None, :]
+    return gaussian(seed, STREAM_PI2, j, c) / np.sqrt(k)
+
+
+def gaussian_sketch_matrix(seed: int, r: int, n: int) -> np.ndarray:
+    """Gaussian sketch G (r x n), entries N(0, 1) (the 1/sqrt(r) is applied
+    to the sketch product, not here)."""
+    i = np.arange(n, dtype=np.uint64)[None, :]
+    j = np.arange(r, dtype=np.uint64)[:, None]
+    return gaussian(seed, STREAM_GAUSS_S, i, j)

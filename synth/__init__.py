@@ -1,0 +1,169 @@
+"""Seeded synthetic inputs shaped like the workloads of Chin & Liang (ACML 2018).
+
+This module only draws input matrices. It holds none of the leverage-score
+arithmetic: the sketch, the factorisations and the scores live elsewhere (the
+HIP library and, separately, the CPU oracle), and both read their inputs from
+here. Every generator is a pure function of its seed (numpy PCG64).
+
+Shapes and distributions:
+
+* ``lowrank_dense`` -- X = diag(rho) (U diag(sigma) V^T + E) with U, V Haar
+  (QR of a Gaussian with the sign fix of Mezzadri 2007), E Gaussian noise and
+  rho log-normal row scales, so leverage is non-uniform. ``config0`` uses
+  n=20000, d=64, rank 32, sigma_j = 2^(-j/4), noise std 1e-3, rho = e^N(0,1).
+* ``image_like`` -- stands in for a 60000 x 784 image matrix (the paper's
+  MNIST experiment; the dataset itself is not used): entries clipped to [0, 1]
+  from 0.5 + alpha * Z W^T + N(0, 0.02^2), Z drawn from 10 Gaussian clusters in
+  a 50-dim latent space, W Haar 784 x 50, alpha chosen so the pre-clip spread
+  is 0.25.
+* ``text_like_csr`` -- stands in for a bag-of-words/tf-idf matrix: n rows over
+  d columns, row nnz log-normal (mean about 0.5 % of d), column ranks drawn
+  from Zipf(1.1) truncated to d and mapped through a seeded permutation,
+  duplicate draws merged, values log(1 + c) * idf_j with c a zero-truncated
+  Poisson(2) count.
+* ``precision_dense`` -- rank-256 signal with sigma_j = j^-1.5 in d=512,
+  noise 1e-4, row scales e^N(0, 1.5^2) (the reduced-precision workload).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "haar", "lowrank_dense", "config0", "image_like", "config1",
+    "text_like_csr", "config2", "precision_dense", "to_bf16_bits",
+    "bf16_bits_to_f64", "Csr",
+]
+
+
+def haar(rng: np.random.Generator, n: int, k: int) -> np.ndarray:
+    """n x k matrix with orthonormal columns, Haar-distributed (n >= k)."""
+    g = rng.standard_normal((n, k))
+    q, r = np.linalg.qr(g)
+    s = np.sign(np.diag(r))
+    s[s == 0] = 1.0
+    return q * s
+
+
+def lowrank_dense(n: int, d: int, rank: int, sigma: np.ndarray, noise: float,
+                  row_sigma: float, seed: int) -> np.ndarray:
+    """FP64 X = diag(rho) (U diag(sigma) V^T + E)."""
+    rng = np.random.default_rng(seed)
+    u = haar(rng, n, rank)
+    v = haar(rng, d, rank)
+    x = (u * sigma[None, :]) @ v.T
+    if noise > 0:
+        x += noise * rng.standard_normal((n, d))
+    if row_sigma > 0:
+        rho = np.exp(row_sigma * rng.standard_normal(n))
+        x *= rho[:, None]
+    return x
+
+
+def config0(n: int = 20000, d: int = 64, seed: int = 1000) -> np.ndarray:
+    """Plain method, small: dense FP64, rank d/2, sigma_j = 2^(-j/4)."""
+    rank = d // 2
+    sigma = 2.0 ** (-np.arange(rank) / 4.0)
+    return lowrank_dense(n, d, rank, sigma, 1e-3, 1.0, seed)
+
+
+def image_like(n: int, d: int, latent: int = 50, clusters: int = 10,
+               seed: int = 1001) -> np.ndarray:
+    """FP32 image-like matrix in [0, 1] (see module docstring)."""
+    rng = np.random.default_rng(seed)
+    mu = rng.standard_normal((clusters, latent))
+    c = rng.integers(0, clusters, n)
+    z = mu[c] + 0.5 * rng.standard_normal((n, latent))
+    w = haar(rng, d, latent)
+    s = z @ w.T
+    alpha = 0.25 / s.std()
+    x = 0.5 + alpha * s + 0.02 * rng.standard_normal((n, d))
+    return np.clip(x, 0.0, 1.0).astype(np.float32)
+
+
+def config1(n: int = 60000, d: int = 784, seed: int = 1001) -> np.ndarray:
+    return image_like(n, d, seed=seed)
+
+
+class Csr:
+    """Plain CSR triple (row_ptr int64[n+1], col_idx int32[nnz], val)."""
+
+    def __init__(self, n, d, row_ptr, col_idx, val):
+        self.n, self.d = int(n), int(d)
+        self.row_ptr = row_ptr
+        self.col_idx = col_idx
+        self.val = val
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    def to_dense(self, dtype=np.float64) -> np.ndarray:
+        x = np.zeros((self.n, self.d), dtype=dtype)
+        rows = np.repeat(np.arange(self.n), np.diff(self.row_ptr))
+        x[rows, self.col_idx] = self.val
+        return x
+
+
+def text_like_csr(n: int, d: int, density: float = 0.005, zipf_s: float = 1.1,
+                  seed: int = 1002) -> Csr:
+    """Sparse tf-idf-like FP32 CSR matrix (see module docstring)."""
+    rng = np.random.default_rng(seed)
+    mean_nnz = density * d
+    mu = math.log(mean_nnz) - 0.5
+    m = np.rint(np.exp(mu + rng.standard_normal(n))).astype(np.int64)
+    m = np.clip(m, 1, d)
+    # Zipf(s) over ranks 1..d, inverse CDF sampling
+    p = np.arange(1, d + 1, dtype=np.float64) ** (-zipf_s)
+    cdf = np.cumsum(p)
+    cdf /= cdf[-1]
+    total = int(m.sum())
+    ranks = np.searchsorted(cdf, rng.random(total), side="right")
+    ranks = np.minimum(ranks, d - 1)
+    perm = rng.permutation(d)
+    cols = perm[ranks].astype(np.int64)
+    rows = np.repeat(np.arange(n, dtype=np.int64), m)
+    key = np.unique(rows * d + cols)          # merge duplicate draws, sort
+    rows = key // d
+    cols = (key % d).astype(np.int32)
+    counts = np.bincount(rows, minlength=n)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    df = np.bincount(cols, minlength=d).astype(np.float64)
+    idf = np.log(n / (1.0 + df))
+    # zero-truncated Poisson(2) by rejection of zeros
+    c = rng.poisson(2.0, key.size)
+    while True:
+        z = c == 0
+        if not z.any():
+            break
+        c[z] = rng.poisson(2.0, int(z.sum()))
+    val = (np.log1p(c) * idf[cols]).astype(np.float32)
+    return Csr(n, d, row_ptr, cols, val)
+
+
+def config2(n: int = 500000, d: int = 4096, seed: int = 1002) -> Csr:
+    return text_like_csr(n, d, seed=seed)
+
+
+def precision_dense(n: int = 4_000_000, d: int = 512, rank: int = 256,
+                    seed: int = 1003) -> np.ndarray:
+    """FP64 rank-256 signal, sigma_j = j^-1.5, noise 1e-4, rho = e^N(0,1.5^2)."""
+    sigma = np.arange(1, rank + 1, dtype=np.float64) ** -1.5
+    return lowrank_dense(n, d, rank, sigma, 1e-4, 1.5, seed)
+
+
+def to_bf16_bits(x: np.ndarray) -> np.ndarray:
+    """Round FP32/FP64 values to bfloat16 (round to nearest even); uint16 bits."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = (u + 0x7FFF + lsb) >> 16
+    return u.astype(np.uint16)
+
+
+def bf16_bits_to_f64(b: np.ndarray) -> np.ndarray:
+    """Exact decode of bfloat16 bit patterns."""
+    u = (np.asarray(b, dtype=np.uint32) << 16).astype(np.uint32)
+    return u.view(np.float32).astype(np.float64)

@@ -1,0 +1,188 @@
+"""Pins for the oracle's exact and sketched leverage scores (CPU only).
+
+Exact scores are pinned to the hat-matrix definition (pseudo-inverse brute
+force), closed forms and invariants; sketched scores to the deterministic
+subspace-embedding bound realised by the drawn sketch (Definition 1 and
+Theorem 1), to the SVD form of Algorithm 2, and to the chi-square law of the
+second projection.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import synth
+from oracle import leverage as lv
+from oracle import sketch as sk
+from oracle import streams
+
+
+def _hat_diag(x):
+    """Brute force: diag(X X^+) with numpy's pseudo-inverse."""
+    return np.einsum("ij,ji->i", x, np.linalg.pinv(x))
+
+
+@pytest.mark.parametrize("n,d", [(12, 3), (40, 7), (64, 16)])
+def test_exact_matches_pinv_bruteforce(n, d):
+    x = np.random.default_rng(n).standard_normal((n, d)) * \
+        np.exp(np.random.default_rng(d).standard_normal(n))[:, None]
+    lev, rank = lv.exact_leverage(x)
+    assert rank == d
+    np.testing.assert_allclose(lev, _hat_diag(x), rtol=1e-10, atol=1e-14)
+
+
+def test_exact_invariants_and_rank_deficient_bruteforce():
+    rng = np.random.default_rng(2)
+    n, d, k = 60, 10, 4
+    x = rng.standard_normal((n, k)) @ rng.standard_normal((k, d))
+    lev, rank = lv.exact_leverage(x)
+    assert rank == k
+    assert abs(lev.sum() - k) < 1e-10
+    assert lev.min() >= -1e-15 and lev.max() <= 1 + 1e-12
+    np.testing.assert_allclose(lev, _hat_diag(x), rtol=1e-8, atol=1e-12)
+
+
+def test_closed_forms():
+    rng = np.random.default_rng(3)
+    # orthonormal columns: l_i = ||x_i||^2
+    q = synth.haar(rng, 200, 6)
+    lev, _ = lv.exact_leverage(q)
+    np.testing.assert_allclose(lev, (q * q).sum(1), rtol=1e-11, atol=1e-15)
+    # rank one: l_i = u_i^2 / ||u||^2
+    u = rng.standard_normal(50)
+    lev, rank = lv.exact_leverage(np.outer(u, [1.0, -2.0, 0.5]))
+    assert rank == 1
+    np.testing.assert_allclose(lev, u * u / (u @ u), rtol=1e-10)
+    # [I_d; 0]: ones on the first d rows, zeros below
+    x = np.vstack([np.eye(5), np.zeros((20, 5))])
+    lev, _ = lv.exact_leverage(x)
+    np.testing.assert_allclose(lev[:5], 1.0, rtol=1e-14)
+    assert np.all(lev[5:] == 0.0)
+
+
+def test_zero_row_scores_zero_and_equivariance():
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((80, 6))
+    x[17] = 0.0
+    lev, _ = lv.exact_leverage(x)
+    assert lev[17] == 0.0
+    # X -> X T (invertible T) leaves the scores unchanged
+    t = rng.standard_normal((6, 6)) + 3 * np.eye(6)
+    lev2, _ = lv.exact_leverage(x @ t)
+    np.testing.assert_allclose(lev2, lev, rtol=1e-9, atol=1e-15)
+    # a row permutation permutes the scores
+    p = rng.permutation(80)
+    lev3, _ = lv.exact_leverage(x[p])
+    np.testing.assert_allclose(lev3, lev[p], rtol=1e-10, atol=1e-15)
+
+
+def _alg2_svd_form(x, sx):
+    """Algorithm 2 as printed (SVD of SA, then A V Sigma^-1), for comparison."""
+    _, s, vt = np.linalg.svd(sx, full_matrices=False)
+    ua = (x @ vt.T) / s[None, :]
+    return (ua * ua).sum(1)
+
+
+def test_qr_form_equals_svd_form_of_algorithm2():
+    x = synth.config0(n=3000, d=16, seed=11)
+    out = lv.sketched_leverage(x, seed=5, r=512, k=0)
+    ref = _alg2_svd_form(x, out["SX"])
+    np.testing.assert_allclose(out["scores"], ref, rtol=1e-11)
+
+
+def test_sketched_scores_within_realised_embedding_bound():
+    """Def. 1 / Thm. 1: with X = U T (U orthonormal), the sketched score of
+    every row lies in [l_i / sigma_max(SU)^2, l_i / sigma_min(SU)^2]."""
+    x = synth.config0(n=5000, d=12, seed=12)
+    lev, _ = lv.exact_leverage(x)
+    q, _ = np.linalg.qr(x)
+    out = lv.sketched_leverage(x, seed=9, r=1024, k=0)
+    sq = sk.countsketch_dense(q, 9, 1024)
+    sv = np.linalg.svd(sq, compute_uv=False)
+    ratio = out["scores"] / lev
+    assert ratio.min() >= (1 - 1e-9) / sv[0] ** 2
+    assert ratio.max() <= (1 + 1e-9) / sv[-1] ** 2
+    eps_hat = max(sv[0] ** 2 - 1, 1 - sv[-1] ** 2)
+    assert eps_hat < 0.5
+
+
+def test_injective_sketch_gives_exact_scores():
+    n, d, r = 60, 5, 1 << 16
+    for seed in range(100):
+        b, _ = streams.bucket_sign(seed, r, np.arange(n))
+        if len(set(b.tolist())) == n:
+            break
+    x = np.random.default_rng(6).standard_normal((n, d))
+    out = lv.sketched_leverage(x, seed=seed, r=r, k=0)
+    lev, _ = lv.exact_leverage(x)
+    np.testing.assert_allclose(out["scores"], lev, rtol=1e-11)
+
+
+def test_k0_is_no_projection():
+    x = synth.config0(n=2000, d=10, seed=13)
+    out = lv.sketched_leverage(x, seed=3, r=256, k=0)
+    rinv = np.linalg.inv(lv.qr_r(out["SX"]))
+    y = x @ rinv
+    np.testing.assert_allclose(out["scores"], (y * y).sum(1), rtol=1e-10)
+
+
+def test_pi2_ratio_is_chi2_over_k():
+    """For a fixed row, l_hat / l_tilde ~ chi2_k / k over Pi_2 draws."""
+    x = synth.config0(n=400, d=8, seed=14)
+    sx = sk.countsketch_dense(x, 1, 128)
+    base = lv.sketched_leverage(x, seed=1, r=128, k=0, sx=sx)["scores"]
+    k = 16
+    ratios = []
+    for seed in range(300):
+        s = lv.sketched_leverage(x, seed=seed, r=128, k=k, sx=sx)["scores"]
+        ratios.append(s[0] / base[0])
+    p = stats.kstest(np.array(ratios) * k, stats.chi2(k).cdf).pvalue
+    assert p > 1e-3
+
+
+def test_refined_equals_exact():
+    x = synth.config0(n=3000, d=16, seed=15)
+    out = lv.sketched_leverage(x, seed=2, r=256, k=0, refine=True)
+    lev, _ = lv.exact_leverage(x)
+    np.testing.assert_allclose(out["scores"], lev, rtol=1e-10)
+
+
+def test_rank_deficient_truncation_restores_bound():
+    """Figs. 2-3 analog: noise-free rank d/2 input. Without truncation
+    (tau = 0) the scores are far off or non-finite; with the default tau the
+    rank is found and the scores obey the embedding bound against the exact
+    rank-d/2 leverage."""
+    rng = np.random.default_rng(16)
+    n, d, k = 4000, 16, 8
+    u = synth.haar(rng, n, k)
+    x = (u * np.exp(rng.standard_normal(n))[:, None]) @ rng.standard_normal((k, d))
+    lev, rank = lv.exact_leverage(x)
+    assert rank == k
+    bad = lv.sketched_leverage(x, seed=4, r=1024, k=0, rank_tol=0.0)["scores"]
+    assert (not np.all(np.isfinite(bad))) or \
+        np.max(np.abs(bad - lev) / np.maximum(lev, 1e-300)) > 1.0
+    good = lv.sketched_leverage(x, seed=4, r=1024, k=0)
+    assert good["rank"] == k
+    q, _ = np.linalg.qr(x)
+    sq = sk.countsketch_dense(q, 4, 1024)
+    # basis of the column space: the first k left singular vectors of X
+    ux = np.linalg.svd(x, full_matrices=False)[0][:, :k]
+    sv = np.linalg.svd(sk.countsketch_dense(ux, 4, 1024), compute_uv=False)
+    ratio = good["scores"] / lev
+    assert ratio.min() >= (1 - 1e-6) / sv[0] ** 2
+    assert ratio.max() <= (1 + 1e-6) / sv[-1] ** 2
+
+
+def test_small_singular_values_truncated_by_threshold():
+    """Fig. 5 analog: exact low rank plus tiny noise looks full rank; a rank
+    tolerance above the noise level truncates it, one below keeps it."""
+    rng = np.random.default_rng(17)
+    n, d, k = 3000, 12, 6
+    x = synth.haar(rng, n, k) @ rng.standard_normal((k, d))
+    x += 1e-9 * rng.standard_normal((n, d))
+    lo = lv.sketched_leverage(x, seed=1, r=512, k=0, rank_tol=1e-14)
+    hi = lv.sketched_leverage(x, seed=1, r=512, k=0, rank_tol=1e-6)
+    assert lo["rank"] == d
+    assert hi["rank"] == k
+    assert abs(hi["scores"].sum() - k) < 0.5

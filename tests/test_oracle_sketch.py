@@ -1,0 +1,86 @@
+"""Pins for the oracle's sketches and column equilibration (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import sketch as sk
+from oracle import streams
+
+
+def _explicit_countsketch(seed, r, n):
+    """S as a dense r x n matrix, built entry by entry."""
+    bucket, sign = streams.bucket_sign(seed, r, np.arange(n))
+    s = np.zeros((r, n))
+    for i in range(n):
+        s[bucket[i], i] = sign[i]
+    return s
+
+
+def test_countsketch_equals_explicit_product():
+    rng = np.random.default_rng(0)
+    # small integers: every FP64 sum is exact, so the two orders agree exactly
+    x = rng.integers(-50, 50, (300, 7)).astype(np.float64)
+    s = _explicit_countsketch(11, 40, 300)
+    assert np.array_equal(sk.countsketch_dense(x, 11, 40), s @ x)
+
+
+def test_countsketch_ascending_order_fp64():
+    # values whose FP64 sum depends on order: check the stated order
+    x = np.array([[1e16], [1.0], [-1e16], [1.0]])
+    bucket, sign = streams.bucket_sign(5, 1, np.arange(4))
+    want = 0.0
+    for i in range(4):
+        want += sign[i] * x[i, 0]
+    assert sk.countsketch_dense(x, 5, 1)[0, 0] == want
+
+
+def test_injective_countsketch_is_signed_permutation():
+    n, r = 50, 4096
+    # find a seed whose bucket hash is collision-free on 50 rows
+    for seed in range(100):
+        b, s = streams.bucket_sign(seed, r, np.arange(n))
+        if len(set(b.tolist())) == n:
+            break
+    x = np.random.default_rng(1).standard_normal((n, 5))
+    sx = sk.countsketch_dense(x, seed, r)
+    for i in range(n):
+        assert np.array_equal(sx[b[i]], s[i] * x[i])
+
+
+def test_csr_sketch_equals_dense_sketch():
+    csr = synth.text_like_csr(2000, 300, density=0.02, seed=3)
+    dense = csr.to_dense()
+    a = sk.countsketch_csr(csr, 77, 128)
+    b = sk.countsketch_dense(dense, 77, 128)
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * np.abs(b).max())
+
+
+def test_gaussian_sketch_is_unbiased_embedding():
+    # E[S^T S] = I for S = G / sqrt(r): average over many columns
+    r, n = 4000, 6
+    g = streams.gaussian_sketch_matrix(3, r, n)
+    sts = (g.T @ g) / r
+    assert np.abs(sts - np.eye(n)).max() < 6 / math.sqrt(r)
+    x = np.eye(n)
+    np.testing.assert_allclose(sk.gaussian_sketch_dense(x, 3, r), g / math.sqrt(r))
+
+
+def test_column_scale_powers_of_two():
+    cm = np.array([0.0, 1.0, 1.5, 2.0, 3.999, 1e-300, 7e200, 0.75])
+    d = sk.column_scale(cm)
+    assert d[0] == 1.0
+    for m, s in zip(cm[1:], d[1:]):
+        assert 1.0 <= m * s < 2.0
+        mant, _ = math.frexp(s)
+        assert mant == 0.5          # exact power of two
+
+
+def test_scaled_sketch_is_exact():
+    x = np.random.default_rng(4).standard_normal((500, 9)) * \
+        np.array([1e-3, 1, 10, 1e5, 3, 0.1, 7, 2e-8, 1])
+    dsc = sk.column_scale(sk.colmax_dense(x))
+    a = sk.countsketch_dense(x * dsc, 8, 64)
+    b = sk.countsketch_dense(x, 8, 64) * dsc
+    assert np.array_equal(a, b)
