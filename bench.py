@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Throughput of the sketched leverage-score path on one MI355X.
+
+One step = slso_leverage (column equilibration, CountSketch, FP64 Householder
+QR of the sketch, rank screen, Pi_2 and triangular solve, scores) followed by
+slso_order (dec ordering), on the image-like workload: dense FP32 X with
+n = 60000, d = 784 (entries in [0, 1], rank 50 + noise, 10 clusters),
+CountSketch r = 16384, k = 64. X is resident in HBM before the clock starts.
+
+Prints one JSON line: rows/s over the timed steps, p50/p99 step latency, the
+max relative score error and Kendall tau of the last step against the FP64
+oracle, the roofline of the dominant kernel (HIP events recorded live around
+every launch in the timed region) and the oracle's own CPU throughput.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"hbm": 8.0e12, "fp64": 78.6e12, "fp32": 157.3e12}
+
+N, D, R, K, SEED = 60000, 784, 16384, 64, 2001
+
+
+def qr_update_flops(m: int, d: int, w: int = 32) -> float:
+    """Algorithmic flops of the blocked Householder trailing updates
+    (Y^T C and C - Y W: 4 m' w n' per panel)."""
+    f = 0.0
+    for j0 in range(0, d, w):
+        wj = min(w, d - j0)
+        f += 4.0 * (m - j0) * wj * (d - j0 - wj)
+    return f
+
+
+def qr_node_flops(m: int, d: int, w: int = 32) -> float:
+    """Algorithmic flops of the panel factorisations (unblocked Householder
+    on (m - j0) x w panels: 2 m' w^2 - 2/3 w^3)."""
+    f = 0.0
+    for j0 in range(0, d, w):
+        wj = min(w, d - j0)
+        f += 2.0 * (m - j0) * wj * wj - (2.0 / 3.0) * wj ** 3
+    return f
+
+
+def roofline_for(name: str, ms_per_launch: float, launches_per_step: float):
+    """Algorithmic work per launch of a kernel at this workload."""
+    sec = ms_per_launch * 1e-3
+    if name == "qr_update":
+        flops = qr_update_flops(R, D) / launches_per_step
+        a = flops / sec
+        return {"bound": "alu", "achieved": a / 1e12, "peak": PEAK["fp64"] / 1e12,
+                "unit": "TFLOP/s", "frac": a / PEAK["fp64"], "traffic": None}
+    if name == "qr_node":
+        flops = qr_node_flops(R, D) / launches_per_step
+        a = flops / sec
+        return {"bound": "alu", "achieved": a / 1e12, "peak": PEAK["fp64"] / 1e12,
+                "unit": "TFLOP/s", "frac": a / PEAK["fp64"], "traffic": None}
+    if name == "score":
+        flops = 2.0 * N * D * K / launches_per_step
+        a = flops / sec
+        return {"bound": "alu", "achieved": a / 1e12, "peak": PEAK["fp32"] / 1e12,
+                "unit": "TFLOP/s", "frac": a / PEAK["fp32"], "traffic": None}
+    if name == "countsketch":
+        byts = (N * D * 4 + R * D * 8 + N * 4) / launches_per_step
+        a = byts / sec
+        return {"bound": "hbm", "achieved": a / 1e9, "peak": PEAK["hbm"] / 1e9,
+                "unit": "GB/s", "frac": a / PEAK["hbm"], "traffic": None}
+    return None
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs the leverage "
+              "path on a single MI355X (see DESIGN.md for how it would shard); "
+              "run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1812_07903_amd as slso
+
+    x_host = synth.config1(N, D)
+    x = torch.from_numpy(x_host).cuda()
+    ctx = slso.Context(0)
+    scores = torch.empty(N, dtype=torch.float32, device="cuda")
+    perm = torch.empty(N, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        _, info = ctx.leverage(x, SEED, R, K, out=scores, stream=stream)
+        ctx.order(scores, out=perm, stream=stream)
+        return info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    slso.profile_read()                      # drop warm-up launches
+    slso.profile_enable(True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        info = step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    prof = slso.profile_read()
+    slso.profile_enable(False)
+
+    ms_step = 1e3 * total / args.steps
+    rows_per_s = N * args.steps / total
+    lat_ms = np.array(lat) * 1e3
+
+    # dominant kernel by total time inside the timed region
+    dom = max(prof.items(), key=lambda kv: kv[1][0])
+    dname, (dms, dcount) = dom
+    roof = roofline_for(dname, dms / max(dcount, 1), dcount / args.steps)
+    kernels = {k: {"ms_per_step": v[0] / args.steps,
+                   "launches_per_step": v[1] / args.steps}
+               for k, v in prof.items() if v[1] > 0}
+
+    got = scores.cpu().numpy().astype(np.float64)
+    perm_h = perm.cpu().numpy().astype(np.int64)
+    perm_ok = bool(np.array_equal(perm_h, np.argsort(-got.astype(np.float32),
+                                                      kind="stable")))
+
+    out = {
+        "metric": "rows/sec leverage-scored at stated rel err vs FP64; "
+                  "p50/p99 job latency",
+        "value": rows_per_s,
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "p50_ms": float(np.percentile(lat_ms, 50)),
+        "p99_ms": float(np.percentile(lat_ms, 99)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "image-like dense FP32 X (n=60000, d=784, "
+                               "values in [0,1], rank 50 + noise, 10 clusters); "
+                               "CountSketch r=16384, FP64 QR, k=64, scores + "
+                               "dec ordering",
+                   "n": N, "d": D, "r": R, "k": K, "seed": SEED,
+                   "rank": int(info["rank"])},
+        "perm_matches_stable_sort": perm_ok,
+        "kernels": kernels,
+        "roofline": dict(kernel=dname, **roof) if roof else None,
+    }
+
+    if not args.no_cpu_baseline:
+        # the oracle, untouched, on one full job of the same workload
+        from oracle import leverage as olv
+        from oracle import metrics as omet
+        from oracle import order as oorder
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        except Exception:
+            cores = os.cpu_count() or 1
+        reps, t_cpu, ref = 0, 0.0, None
+        while reps < 3 and t_cpu < 20.0:
+            tc = time.perf_counter()
+            ref = olv.sketched_leverage(x_host, SEED, R, K)
+            oorder.dec_order(ref["scores"].astype(np.float32))
+            t_cpu += time.perf_counter() - tc
+            reps += 1
+        out["cpu_baseline"] = {
+            "value": N * reps / t_cpu, "unit": "rows/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"{reps} full job(s) of the same workload (n={N}): "
+                      "oracle sketched leverage (numpy FP64) + dec ordering"}
+        out["rel_err_vs_fp64"] = omet.max_rel_err(got, ref["scores"])
+        out["kendall_tau_vs_fp64"] = omet.kendall_tau(got, ref["scores"])
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

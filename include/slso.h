@@ -1,0 +1,208 @@
+/*
+ * slso.h -- C ABI of a GPU (AMD MI355X / gfx950) library for sketched
+ * leverage scores and leverage-score ordering, after Chin & Liang,
+ * "An Empirical Evaluation of Sketched SVD and its Application to Leverage
+ * Score Ordering" (ACML 2018).
+ *
+ * What is computed (paper references are to its sections and algorithms):
+ *   - leverage of row i of an n x d matrix A: the i-th diagonal entry of the
+ *     hat matrix A (A^T A)^+ A^T, equal to ||U_i||^2 for A = U S V^T (Sec. 2.2);
+ *   - the sketched approximation of Algorithm 2, in QR form: sketch S*X
+ *     (Sec. 2.1), R from a Householder QR of the small sketch, scores
+ *     ||x_i R^{-1} Pi_2||^2 with a second Gaussian projection Pi_2 (d x k),
+ *     with the truncation of small singular values of Algorithm 3;
+ *   - the "dec" ordering of Sec. 5.2: rows by decreasing score.
+ *
+ * Conventions shared by every entry point:
+ *   - Array pointers marked (device) are device pointers into memory the
+ *     caller allocated on the context's device; the library never frees or
+ *     retains them past the call's stream work. (host) pointers are read or
+ *     written before the call returns.
+ *   - ``stream`` is a hipStream_t passed as void* (NULL = the legacy default
+ *     stream). Work is enqueued on it; outputs are valid once it has been
+ *     synchronised, except where an entry point says it synchronises itself.
+ *   - Dense matrices are row-major with a leading dimension ``ld`` (elements
+ *     between consecutive rows, ld >= d). CSR matrices use int64 row_ptr[n+1]
+ *     and int32 col_idx[nnz], columns sorted and distinct within a row.
+ *   - Return value: SLSO_OK (0) or a positive warning on success, a negative
+ *     slso_status on failure. On failure no kernel has been enqueued unless
+ *     the status is SLSO_EDEVICE, and outputs are unspecified. The text of the
+ *     last error of a context is returned by slso_last_error.
+ *   - A context is used by one host thread at a time. It owns a device
+ *     workspace that grows to the largest problem seen and is reused; after a
+ *     first call of a given size, later calls of that size allocate nothing.
+ */
+#ifndef SLSO_H
+#define SLSO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct slso_ctx slso_ctx;
+
+typedef enum {
+  SLSO_OK = 0,
+  SLSO_RANK_DEFICIENT = 1, /* success; the numerical rank is below d        */
+  SLSO_EINVAL = -1,        /* invalid argument (see each entry point)        */
+  SLSO_ENOMEM = -2,        /* device workspace could not be allocated        */
+  SLSO_ENONFINITE = -3,    /* the input holds Inf or NaN                      */
+  SLSO_EDEVICE = -4,       /* a HIP runtime call failed                       */
+  SLSO_EUNSUPPORTED = -5   /* combination of format/dtype/kind not provided  */
+} slso_status;
+
+typedef enum {
+  SLSO_F64 = 0,       /* double                                               */
+  SLSO_F32 = 1,       /* float                                                */
+  SLSO_BF16 = 2,      /* bfloat16 bit patterns (uint16)                      */
+  SLSO_FP8_E4M3 = 3   /* OCP fp8 e4m3fn bytes, dequantised by the scales     */
+} slso_dtype;
+
+typedef enum { SLSO_DENSE = 0, SLSO_CSR = 1 } slso_format;
+
+typedef enum {
+  SLSO_COUNTSKETCH = 0, /* one signed nonzero per column of S (Sec. 2.1)     */
+  SLSO_GAUSSIAN = 1     /* S = G / sqrt(r), G i.i.d. N(0, 1) (Sec. 2.1)      */
+} slso_sketch_kind;
+
+/* An n x d input matrix. Dense: ``values`` (device) holds n rows of ``ld``
+ * elements of ``dtype``. CSR: ``values`` (device) holds nnz entries of
+ * ``dtype``, with ``row_ptr`` (device, n+1 int64, row_ptr[0] = 0,
+ * row_ptr[n] = nnz) and ``col_idx`` (device, nnz int32 in [0, d)).
+ * For SLSO_FP8_E4M3 the represented value is q * col_scale[j] (* row_scale[i]
+ * when row_scale is not NULL); col_scale (device, d floats) is required.   */
+typedef struct {
+  int64_t n, d;
+  int32_t format; /* slso_format */
+  int32_t dtype;  /* slso_dtype  */
+  const void* values;
+  int64_t ld;
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  int64_t nnz;
+  const float* col_scale;
+  const float* row_scale;
+} slso_matrix;
+
+/* Options. Zero-initialised options select: CountSketch, no refinement and
+ * the default rank tolerance. */
+typedef struct {
+  int32_t sketch;   /* slso_sketch_kind                                       */
+  int32_t refine;   /* 1: sketch-preconditioned Cholesky-QR refinement of R  */
+  double rank_tol;  /* relative threshold of Algorithm 3 step 3; 0 selects   */
+                    /* the default 1e-10; a negative value disables          */
+                    /* truncation (R^{-1} is used whatever its conditioning) */
+} slso_options;
+
+/* Host-side report of one leverage computation. */
+typedef struct {
+  int64_t rank;        /* numerical rank used (d when nothing is truncated) */
+  int32_t screen_full; /* 1 when the diag(R_D) screen declared full rank    */
+  int32_t flags;       /* reserved, 0                                        */
+  double diag_min;     /* min |R_D[j][j]| of the equilibrated sketch factor  */
+  double diag_max;     /* max |R_D[j][j]|                                    */
+} slso_info;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device ``device``. EINVAL: ctx NULL or no such
+ * device; EDEVICE: HIP failure. */
+int slso_create(slso_ctx** ctx, int device);
+
+/* Release the context and its workspace (synchronises the device first). */
+int slso_destroy(slso_ctx* ctx);
+
+/* Static text for a status code; the last error text of a context (never
+ * NULL; empty when no error has occurred). */
+const char* slso_status_string(int status);
+const char* slso_last_error(const slso_ctx* ctx);
+
+/* ---- the hot path -------------------------------------------------------- */
+
+/* Sketch S*X (Algorithm 2 step 1; Sec. 2.1; Sec. 3.1.2 "pair of hash
+ * functions" for CountSketch).
+ *   X      matrix as above (dense F64/F32/BF16 or CSR F32 for CountSketch;
+ *          dense BF16/F32/FP8 for Gaussian).
+ *   seed   64-bit seed; the bucket hash, sign hash and Gaussian entries are
+ *          derived from it per row index (0-based global row i).
+ *   r      sketch rows, r >= d (EINVAL otherwise).
+ *   sx     (device) r x d doubles, row-major, overwritten with S*X (without
+ *          column equilibration).
+ * CountSketch: sx[h(i)] += s(i) x_i, summed in FP64 in ascending i within
+ * each bucket (deterministic). Gaussian: S = G/sqrt(r), FP32 accumulation
+ * of BF16 products in chunks, FP64 across chunks. */
+int slso_sketch(slso_ctx* ctx, const slso_matrix* X, uint64_t seed, int64_t r,
+                const slso_options* opt, double* sx, void* stream);
+
+/* Sketched leverage scores (Algorithms 2 and 3, QR form, with Pi_2).
+ *   k       columns of Pi_2 (k >= 0; k = 0 means Pi_2 = I, exact sketched
+ *           scores ||x_i R^{-1}||^2).
+ *   scores  (device) n floats, overwritten with l_i = ||x_i M||^2, where
+ *           M = D pinv_rank(R_D) Pi_2, D the power-of-two column
+ *           equilibration of X and R_D the R factor (non-negative diagonal)
+ *           of the equilibrated sketch.
+ *   info    (host, may be NULL) filled with the rank decision.
+ * Synchronises ``stream`` once (to read the rank screen). Returns
+ * SLSO_RANK_DEFICIENT when the rank used is below d. ENONFINITE when X holds
+ * Inf/NaN; EINVAL for n < 1, d < 1, r < d, k < 0 or a malformed matrix. */
+int slso_leverage(slso_ctx* ctx, const slso_matrix* X, uint64_t seed,
+                  int64_t r, int64_t k, const slso_options* opt,
+                  float* scores, slso_info* info, void* stream);
+
+/* "dec" ordering (Sec. 5.2): perm[0] is the row of the largest score; equal
+ * scores keep ascending row index (stable). scores (device) n floats,
+ * perm (device) n int32. EINVAL for n < 1 or n >= 2^31. */
+int slso_order(slso_ctx* ctx, const float* scores, int64_t n, int32_t* perm,
+               void* stream);
+
+/* ---- stages, exposed for verification and composition -------------------- */
+
+/* CountSketch bucket and sign of rows row0 .. row0+n-1 (Sec. 3.1.2):
+ * bucket (device) n int32 in [0, r), sign (device) n int8 in {+1, -1}. */
+int slso_hash(uint64_t seed, int64_t r, int64_t row0, int64_t n,
+              int32_t* bucket, int8_t* sign, void* stream);
+
+/* Gaussian stream entries z(a, b) for a in [0, rows), b in [0, cols)
+ * (stream_id 3: sketch entries with a = row of X, b = sketch row;
+ * stream_id 4: Pi_2 before its 1/sqrt(k) scale). out (device) rows x cols
+ * doubles, row-major. */
+int slso_gaussian(uint64_t seed, int32_t stream_id, int64_t rows, int64_t cols,
+                  double* out, void* stream);
+
+/* R factor of a Householder QR (Algorithm 2 step 2, QR form) of the m x d
+ * matrix a (device, row-major, lda = d, m >= d), which is overwritten.
+ * r_out (device) d x d doubles: upper triangle of R with a non-negative
+ * diagonal, zeros below. */
+int slso_qr_r(slso_ctx* ctx, double* a, int64_t m, int64_t d, double* r_out,
+              void* stream);
+
+/* Solve R X = B in place for upper-triangular R (device, d x d, row-major)
+ * and B (device, d x k, row-major) -- the R^{-1} Pi_2 of Algorithm 2 step 3. */
+int slso_solve_upper(slso_ctx* ctx, const double* r, int64_t d, double* b,
+                     int64_t k, void* stream);
+
+/* Row scores l_i = ||x_i M||^2 for a given M (device, d x k doubles,
+ * row-major), Algorithm 2 step 4; scores (device) n floats. */
+int slso_scores(slso_ctx* ctx, const slso_matrix* X, const double* m,
+                int64_t k, float* scores, void* stream);
+
+/* ---- measurement ---------------------------------------------------------- */
+
+/* Process-wide launch profiler. While enabled, HIP events are recorded on
+ * the launch stream around every launch of the library's kernels (grouped by
+ * kernel id). slso_profile_read synchronises the current device, adds the
+ * elapsed milliseconds and launch counts of kernel ids 0 .. n-1 into ms and
+ * launches (host arrays of n entries, each may be NULL), resets the totals
+ * and returns the number of kernel ids; slso_profile_name gives the name of
+ * an id ("" when out of range). */
+int slso_profile_enable(int on);
+int slso_profile_read(double* ms, int64_t* launches, int n);
+const char* slso_profile_name(int id);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLSO_H */

@@ -1,0 +1,297 @@
+"""Python binding of libslso (sketched leverage scores on AMD MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libslso.so``; torch tensors supply device memory and streams.
+The binding fails loudly when the library has not been built; there is no
+CPU fallback.
+
+Names mirror the C ABI (``include/slso.h``): ``sketch``, ``leverage``,
+``order``, and the stage entry points ``hash``, ``gaussian``, ``qr_r``,
+``solve_upper`` and ``scores``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libslso.so")
+
+# status codes (slso_status)
+OK, RANK_DEFICIENT = 0, 1
+EINVAL, ENOMEM, ENONFINITE, EDEVICE, EUNSUPPORTED = -1, -2, -3, -4, -5
+# slso_dtype / slso_format / slso_sketch_kind
+F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
+DENSE, CSR = 0, 1
+COUNTSKETCH, GAUSSIAN = 0, 1
+STREAM_GAUSS_S, STREAM_PI2 = 3, 4
+
+EXPORTED = (
+    "slso_create", "slso_destroy", "slso_status_string", "slso_last_error",
+    "slso_sketch", "slso_leverage", "slso_order", "slso_hash",
+    "slso_gaussian", "slso_qr_r", "slso_solve_upper", "slso_scores",
+    "slso_profile_enable", "slso_profile_read", "slso_profile_name",
+)
+
+
+class SlsoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"slso status {status}: {msg}")
+        self.status = status
+
+
+class _Matrix(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("d", ctypes.c_int64),
+        ("format", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("values", ctypes.c_void_p), ("ld", ctypes.c_int64),
+        ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+        ("nnz", ctypes.c_int64),
+        ("col_scale", ctypes.c_void_p), ("row_scale", ctypes.c_void_p),
+    ]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("sketch", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("rank_tol", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int64), ("screen_full", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("diag_min", ctypes.c_double),
+                ("diag_max", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libslso.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it with paper_1812_07903_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
+    sig = {
+        "slso_create": ([ctypes.POINTER(vp), ctypes.c_int], ctypes.c_int),
+        "slso_destroy": ([vp], ctypes.c_int),
+        "slso_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "slso_last_error": ([vp], ctypes.c_char_p),
+        "slso_sketch": ([vp, ctypes.POINTER(_Matrix), u64, i64,
+                         ctypes.POINTER(_Options), vp, vp], ctypes.c_int),
+        "slso_leverage": ([vp, ctypes.POINTER(_Matrix), u64, i64, i64,
+                           ctypes.POINTER(_Options), vp, ctypes.POINTER(_Info),
+                           vp], ctypes.c_int),
+        "slso_order": ([vp, vp, i64, vp, vp], ctypes.c_int),
+        "slso_hash": ([u64, i64, i64, i64, vp, vp, vp], ctypes.c_int),
+        "slso_gaussian": ([u64, i32, i64, i64, vp, vp], ctypes.c_int),
+        "slso_qr_r": ([vp, vp, i64, i64, vp, vp], ctypes.c_int),
+        "slso_solve_upper": ([vp, vp, i64, vp, i64, vp], ctypes.c_int),
+        "slso_scores": ([vp, ctypes.POINTER(_Matrix), vp, i64, vp, vp],
+                        ctypes.c_int),
+        "slso_profile_enable": ([ctypes.c_int], ctypes.c_int),
+        "slso_profile_read": ([vp, vp, ctypes.c_int], ctypes.c_int),
+        "slso_profile_name": ([ctypes.c_int], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+@dataclass
+class CsrMatrix:
+    """Device CSR matrix: row_ptr int64[n+1], col_idx int32[nnz], val f32."""
+    n: int
+    d: int
+    row_ptr: object
+    col_idx: object
+    val: object
+
+
+def _matrix(x) -> _Matrix:
+    import torch
+    m = _Matrix()
+    if isinstance(x, CsrMatrix):
+        if x.val.dtype != torch.float32:
+            raise TypeError("CSR values must be float32")
+        if x.row_ptr.dtype != torch.int64 or x.col_idx.dtype != torch.int32:
+            raise TypeError("CSR row_ptr must be int64 and col_idx int32")
+        m.n, m.d, m.format, m.dtype = x.n, x.d, CSR, F32
+        m.values = x.val.data_ptr()
+        m.ld = x.d
+        m.row_ptr = x.row_ptr.data_ptr()
+        m.col_idx = x.col_idx.data_ptr()
+        m.nnz = int(x.col_idx.numel())
+        return m
+    if x.dim() != 2 or x.stride(1) != 1:
+        raise ValueError("dense X must be 2-D with unit column stride")
+    code = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}.get(x.dtype)
+    if code is None:
+        raise TypeError(f"unsupported dtype {x.dtype}")
+    m.n, m.d = x.shape
+    m.format, m.dtype = DENSE, code
+    m.values = x.data_ptr()
+    m.ld = x.stride(0)
+    return m
+
+
+def _check(st: int, ctx=None):
+    if st < 0:
+        lib = load_library()
+        msg = lib.slso_last_error(ctx).decode() if ctx else ""
+        if not msg:
+            msg = lib.slso_status_string(st).decode()
+        raise SlsoError(st, msg)
+    return st
+
+
+class Context:
+    """Owns a library context (device workspace) on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.slso_create(ctypes.byref(h), device))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load_library().slso_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- hot path ----------------------------------------------------------
+    def sketch(self, x, seed: int, r: int, sketch: int = COUNTSKETCH, out=None,
+               stream=None):
+        import torch
+        d = x.d if isinstance(x, CsrMatrix) else x.shape[1]
+        dev = (x.val if isinstance(x, CsrMatrix) else x).device
+        if out is None:
+            out = torch.empty((r, d), dtype=torch.float64, device=dev)
+        m = _matrix(x)
+        opt = _Options(sketch, 0, 0.0)
+        _check(load_library().slso_sketch(self._h, ctypes.byref(m), seed, r,
+                                          ctypes.byref(opt), _ptr(out),
+                                          _stream(stream)), self._h)
+        return out
+
+    def leverage(self, x, seed: int, r: int, k: int, sketch: int = COUNTSKETCH,
+                 refine: bool = False, rank_tol: float = 0.0, out=None,
+                 stream=None):
+        """Scores (float32 device tensor) and the rank-decision info dict."""
+        import torch
+        n = x.n if isinstance(x, CsrMatrix) else x.shape[0]
+        dev = (x.val if isinstance(x, CsrMatrix) else x).device
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=dev)
+        m = _matrix(x)
+        opt = _Options(sketch, 1 if refine else 0, rank_tol)
+        info = _Info()
+        st = _check(load_library().slso_leverage(
+            self._h, ctypes.byref(m), seed, r, k, ctypes.byref(opt), _ptr(out),
+            ctypes.byref(info), _stream(stream)), self._h)
+        return out, {"status": st, "rank": info.rank,
+                     "screen_full": bool(info.screen_full),
+                     "diag_min": info.diag_min, "diag_max": info.diag_max}
+
+    def order(self, scores, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(scores.numel(), dtype=torch.int32,
+                              device=scores.device)
+        _check(load_library().slso_order(self._h, _ptr(scores), scores.numel(),
+                                         _ptr(out), _stream(stream)), self._h)
+        return out
+
+    # ---- stages ---------------------------------------------------------------
+    def qr_r(self, a, stream=None):
+        """R (non-negative diagonal) of a Householder QR; ``a`` is overwritten."""
+        import torch
+        m, d = a.shape
+        r = torch.empty((d, d), dtype=torch.float64, device=a.device)
+        _check(load_library().slso_qr_r(self._h, _ptr(a), m, d, _ptr(r),
+                                        _stream(stream)), self._h)
+        return r
+
+    def solve_upper(self, r, b, stream=None):
+        """Solve R X = B in place (B is d x k, float64)."""
+        d, k = b.shape
+        _check(load_library().slso_solve_upper(self._h, _ptr(r), d, _ptr(b), k,
+                                               _stream(stream)), self._h)
+        return b
+
+    def scores(self, x, m, out=None, stream=None):
+        import torch
+        n = x.n if isinstance(x, CsrMatrix) else x.shape[0]
+        dev = (x.val if isinstance(x, CsrMatrix) else x).device
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=dev)
+        mm = _matrix(x)
+        _check(load_library().slso_scores(self._h, ctypes.byref(mm), _ptr(m),
+                                          m.shape[1], _ptr(out),
+                                          _stream(stream)), self._h)
+        return out
+
+
+def profile_enable(on: bool = True) -> None:
+    """Record HIP events around every library kernel launch (process-wide)."""
+    load_library().slso_profile_enable(1 if on else 0)
+
+
+def profile_read() -> dict:
+    """{kernel name: (total ms, launches)} since the last read; synchronises."""
+    lib = load_library()
+    n = 64
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    k = lib.slso_profile_read(ms, cnt, n)
+    if k < 0:
+        raise SlsoError(k, "profile read failed")
+    return {lib.slso_profile_name(i).decode(): (ms[i], cnt[i]) for i in range(k)}
+
+
+def hash(seed: int, r: int, n: int, row0: int = 0, device="cuda", stream=None):
+    """CountSketch bucket (int32) and sign (int8) of rows row0..row0+n-1."""
+    import torch
+    b = torch.empty(n, dtype=torch.int32, device=device)
+    s = torch.empty(n, dtype=torch.int8, device=device)
+    _check(load_library().slso_hash(seed, r, row0, n, _ptr(b), _ptr(s),
+                                    _stream(stream)))
+    return b, s
+
+
+def gaussian(seed: int, stream_id: int, rows: int, cols: int, device="cuda",
+             stream=None):
+    """Gaussian stream entries z(a, b), a < rows, b < cols (float64)."""
+    import torch
+    out = torch.empty((rows, cols), dtype=torch.float64, device=device)
+    _check(load_library().slso_gaussian(seed, stream_id, rows, cols, _ptr(out),
+                                        _stream(stream)))
+    return out

@@ -1,0 +1,112 @@
+// Host-side launch interfaces between the kernel translation units and the
+// C ABI layer. Every launcher enqueues on the given stream and never
+// synchronises.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace slso {
+
+// ---- launch profiler (slso_capi.hip) ----------------------------------------
+// When enabled (slso_profile_enable), HIP events are recorded on the launch
+// stream around every launch of the listed kernels and resolved on read.
+enum KernelId : int {
+  kKHash = 0,
+  kKSortHist,
+  kKSortScan,
+  kKSortScatter,
+  kKOffsets,
+  kKColmax,
+  kKSketch,
+  kKQrNode,
+  kKQrUpdate,
+  kKQrExtract,
+  kKTrsm,
+  kKScore,
+  kKGauss,
+  kKCount
+};
+void prof_begin(int kid, hipStream_t s);
+void prof_end(int kid, hipStream_t s);
+
+// ---- streams / ordering (k_sort.hip) ----------------------------------------
+// keys[i] = bucket h(row0+i), vals[i] = i | (sign bit << 31).
+void launch_hash_pack(const HashCoeffs& hb, const HashCoeffs& hs, int64_t r,
+                      int64_t row0, int64_t n, uint32_t* keys, uint32_t* vals,
+                      hipStream_t s);
+void launch_hash_out(const HashCoeffs& hb, const HashCoeffs& hs, int64_t r,
+                     int64_t row0, int64_t n, int32_t* bucket, int8_t* sign,
+                     hipStream_t s);
+// out[a * cols + b] = z(a, b) / divisor
+void launch_gaussian(uint64_t seed, uint32_t stream_id, int64_t rows,
+                     int64_t cols, double divisor, double* out, hipStream_t s);
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+// Order-preserving descending keys of FP32 scores.
+void launch_score_keys(const float* scores, int64_t n, uint32_t* keys,
+                       hipStream_t s);
+// Stable LSD radix sort of (key, value) pairs on bits [0, nbits); vals_in may
+// be NULL (values = input positions). Results land in keys_out / vals_out.
+size_t radix_sort_scratch_bytes(int64_t n);
+void radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in,
+                      uint32_t* keys_out, uint32_t* vals_out,
+                      uint32_t* keys_tmp, uint32_t* vals_tmp, int64_t n,
+                      int nbits, void* scratch, hipStream_t s);
+// offsets[b] = first sorted position with key >= b, b in [0, r]
+void launch_bucket_offsets(const uint32_t* sorted_keys, int64_t n, int64_t r,
+                           int32_t* offsets, hipStream_t s);
+
+// ---- sketch (k_sketch.hip) ---------------------------------------------------
+void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
+// colmax_bits: d u64 (bit patterns of non-negative doubles), zero-filled by
+// the caller; nonfinite: int flag set to 1 on Inf/NaN.
+void launch_colmax(const void* x, int dtype, int format, int64_t n, int64_t d,
+                   int64_t ld, const int64_t* row_ptr, const int32_t* col_idx,
+                   int64_t nnz, const float* col_scale, const float* row_scale,
+                   uint64_t* colmax_bits, int* nonfinite, hipStream_t s);
+void launch_colscale(const uint64_t* colmax_bits, int64_t d, double* dscale,
+                     hipStream_t s);
+// sx[b] = dscale * sum_{rows in bucket b, ascending} sign * x_row
+void launch_countsketch(const void* x, int dtype, int format, int64_t n,
+                        int64_t d, int64_t ld, const int64_t* row_ptr,
+                        const int32_t* col_idx, const float* col_scale,
+                        const float* row_scale, const uint32_t* sorted_vals,
+                        const int32_t* offsets, int64_t r,
+                        const double* dscale, double* sx, hipStream_t s);
+
+// ---- QR (k_qr.hip) -----------------------------------------------------------
+size_t qr_scratch_bytes(int64_t m, int64_t d);
+// Householder QR of a (m x d, lda = d) in place; r_out (d x d) receives R with
+// a non-negative diagonal and zeros below it.
+void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
+               hipStream_t s);
+// diag stats of upper-triangular r (d x d): out[0] = min |r_jj|, out[1] = max
+void launch_diag_stats(const double* r, int64_t d, double* out, hipStream_t s);
+
+// ---- triangular solve / Jacobi (k_solve.hip) --------------------------------------
+void solve_upper(const double* r, int64_t d, double* b, int64_t k,
+                 hipStream_t s);
+// pinv of the rank-`rank` truncation of r applied to b: out = V' S'^-1 U'^T b.
+// Works on copies; sigma (host) receives the d singular values, descending.
+size_t jacobi_scratch_bytes(int64_t d, int64_t k);
+int jacobi_truncated_apply(const double* r, int64_t d, const double* b,
+                           int64_t k, double rank_tol, double* out,
+                           int64_t* rank_out, void* scratch, hipStream_t s);
+// out = I (d x d)
+void launch_eye(double* out, int64_t d, hipStream_t s);
+// m_out[j][c] = scale_row[j] * m[j][c] as float (m_out32) and/or double
+void launch_scale_rows(const double* m, const double* scale_row, int64_t d,
+                       int64_t k, double* out64, float* out32, hipStream_t s);
+
+// ---- scoring (k_score.hip) ---------------------------------------------------
+void launch_scores(const void* x, int dtype, int format, int64_t n, int64_t d,
+                   int64_t ld, const int64_t* row_ptr, const int32_t* col_idx,
+                   const float* col_scale, const float* row_scale,
+                   const double* m64, const float* m32, int64_t k,
+                   float* scores, hipStream_t s, double* partial);
+// bytes of the FP64 partial-sum buffer needed by launch_scores (0 if none)
+size_t scores_partial_bytes(int64_t n, int64_t k, int format);
+
+}  // namespace slso

@@ -1,0 +1,291 @@
+// CountSketch S*X (Algorithm 2 step 1; Sec. 2.1) and the power-of-two column
+// equilibration applied before sketching.
+//
+// Design: rows are first grouped by bucket with the stable radix sort
+// (k_sort.hip), so every sketch row is owned by exactly one wave, which
+// streams the rows of its bucket in ascending order and accumulates the
+// signed sums privately (registers for dense input, an LDS row segment for
+// CSR input), then writes its sketch row once. No atomics touch S*X: the FP64
+// sums are deterministic and taken in the same order as the streaming model
+// of Sec. 3.1.2. Dense rows are read contiguously (64 lanes x 4 columns per
+// pass); CSR rows are read as contiguous (col_idx, value) runs.
+#include "internal.h"
+
+namespace slso {
+namespace {
+
+template <typename T>
+struct Elem;
+template <>
+struct Elem<double> {
+  __device__ static double get(const double* p, int64_t i) { return p[i]; }
+};
+template <>
+struct Elem<float> {
+  __device__ static double get(const float* p, int64_t i) {
+    return static_cast<double>(p[i]);
+  }
+};
+template <>
+struct Elem<uint16_t> {
+  __device__ static double get(const uint16_t* p, int64_t i) {
+    return static_cast<double>(bf16_to_f32(p[i]));
+  }
+};
+
+__global__ void fill_u64_kernel(uint64_t* p, int64_t n, uint64_t v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    colmax_dense_kernel(const T* __restrict__ x, int64_t n, int64_t d,
+                        int64_t ld, int64_t rows_per_block,
+                        unsigned long long* __restrict__ colmax, int* nonfinite) {
+  const int64_t col = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (col >= d) return;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.y) * rows_per_block;
+  const int64_t r1 = r0 + rows_per_block < n ? r0 + rows_per_block : n;
+  double m = 0.0;
+  bool bad = false;
+  for (int64_t row = r0; row < r1; ++row) {
+    const double v = fabs(Elem<T>::get(x, row * ld + col));
+    bad |= !isfinite(v);
+    m = fmax(m, v);
+  }
+  if (bad) atomicExch(nonfinite, 1);
+  if (m > 0.0) atomicMax(&colmax[col], static_cast<unsigned long long>(__double_as_longlong(m)));
+}
+
+// CSR column max: LDS-privatised per workgroup when d fits (d <= 8192).
+__global__ void __launch_bounds__(256)
+    colmax_csr_kernel(const int32_t* __restrict__ col_idx,
+                      const float* __restrict__ val, int64_t nnz, int64_t d,
+                      int64_t per_block, unsigned long long* __restrict__ colmax,
+                      int* nonfinite) {
+  extern __shared__ unsigned long long lmax[];
+  const bool priv = d <= 8192;
+  if (priv)
+    for (int64_t c = threadIdx.x; c < d; c += 256) lmax[c] = 0ull;
+  __syncthreads();
+  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * per_block;
+  const int64_t p1 = p0 + per_block < nnz ? p0 + per_block : nnz;
+  bool bad = false;
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
+    const double v = fabs(static_cast<double>(val[p]));
+    bad |= !isfinite(v);
+    const unsigned long long b =
+        static_cast<unsigned long long>(__double_as_longlong(v));
+    if (priv)
+      atomicMax(&lmax[col_idx[p]], b);
+    else
+      atomicMax(&colmax[col_idx[p]], b);
+  }
+  if (bad) atomicExch(nonfinite, 1);
+  __syncthreads();
+  if (priv)
+    for (int64_t c = threadIdx.x; c < d; c += 256)
+      if (lmax[c]) atomicMax(&colmax[c], lmax[c]);
+}
+
+__global__ void colscale_kernel(const unsigned long long* __restrict__ colmax,
+                                int64_t d, double* __restrict__ dscale) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= d) return;
+  const double m = __longlong_as_double(static_cast<long long>(colmax[j]));
+  double s = 1.0;
+  if (m > 0.0 && isfinite(m)) {
+    int e;
+    frexp(m, &e);           // m = f 2^e, f in [0.5, 1)
+    s = ldexp(1.0, -(e - 1));  // m * s in [1, 2)
+  }
+  dscale[j] = s;
+}
+
+// One wave per bucket; 4 columns per lane per pass (256 columns).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    countsketch_dense_kernel(const T* __restrict__ x, int64_t d, int64_t ld,
+                             const uint32_t* __restrict__ sorted_vals,
+                             const int32_t* __restrict__ off, int64_t r,
+                             const double* __restrict__ dscale,
+                             double* __restrict__ sx) {
+  const int lane = threadIdx.x & 63;
+  const int64_t b = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (b >= r) return;
+  const int p0 = off[b], p1 = off[b + 1];
+  for (int64_t c0 = 0; c0 < d; c0 += 256) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int p = p0; p < p1; ++p) {
+      const uint32_t v = sorted_vals[p];
+      const int64_t row = static_cast<int64_t>(v & 0x7fffffffu);
+      const bool neg = (v >> 31) != 0;
+      const int64_t rb = row * ld;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t c = c0 + lane + 64 * u;
+        if (c < d) {
+          const double xv = Elem<T>::get(x, rb + c);
+          acc[u] += neg ? -xv : xv;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t c = c0 + lane + 64 * u;
+      if (c < d) sx[b * d + c] = acc[u] * (dscale ? dscale[c] : 1.0);
+    }
+  }
+}
+
+// One wave per bucket; LDS accumulator covering kChunk columns at a time.
+constexpr int kCsrChunk = 1024;
+
+__global__ void __launch_bounds__(256)
+    countsketch_csr_kernel(const int64_t* __restrict__ row_ptr,
+                           const int32_t* __restrict__ col_idx,
+                           const float* __restrict__ val, int64_t d,
+                           const uint32_t* __restrict__ sorted_vals,
+                           const int32_t* __restrict__ off, int64_t r,
+                           const double* __restrict__ dscale,
+                           double* __restrict__ sx) {
+  __shared__ double acc_all[4][kCsrChunk];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  double* acc = acc_all[wave];
+  const int64_t b = static_cast<int64_t>(blockIdx.x) * 4 + wave;
+  if (b >= r) return;
+  const int p0 = off[b], p1 = off[b + 1];
+  for (int64_t c0 = 0; c0 < d; c0 += kCsrChunk) {
+    const int64_t c1 = c0 + kCsrChunk < d ? c0 + kCsrChunk : d;
+    for (int c = lane; c < kCsrChunk; c += 64) acc[c] = 0.0;
+    for (int p = p0; p < p1; ++p) {
+      const uint32_t v = sorted_vals[p];
+      const int64_t row = static_cast<int64_t>(v & 0x7fffffffu);
+      const bool neg = (v >> 31) != 0;
+      const int64_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
+      // columns are distinct within a row: no two lanes of one pass collide,
+      // and successive rows are applied in program order by this wave
+      for (int64_t e = e0 + lane; e < e1; e += 64) {
+        const int64_t c = col_idx[e];
+        if (c >= c0 && c < c1) {
+          const double xv = static_cast<double>(val[e]);
+          acc[c - c0] += neg ? -xv : xv;
+        }
+      }
+    }
+    for (int64_t c = c0 + lane; c < c1; c += 64)
+      sx[b * d + c] = acc[c - c0] * (dscale ? dscale[c] : 1.0);
+  }
+}
+
+inline unsigned grid1(int64_t n, int t) {
+  return static_cast<unsigned>((n + t - 1) / t);
+}
+
+}  // namespace
+
+void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
+  if (n <= 0) return;
+  fill_u64_kernel<<<grid1(n, 256), 256, 0, s>>>(p, n, v);
+}
+
+void launch_colmax(const void* x, int dtype, int format, int64_t n, int64_t d,
+                   int64_t ld, const int64_t* row_ptr, const int32_t* col_idx,
+                   int64_t nnz, const float* col_scale, const float* row_scale,
+                   uint64_t* colmax_bits, int* nonfinite, hipStream_t s) {
+  (void)row_ptr;
+  (void)col_scale;
+  (void)row_scale;
+  auto* cm = reinterpret_cast<unsigned long long*>(colmax_bits);
+  if (format == 1) {  // CSR, FP32 values
+    if (nnz <= 0) return;
+    const int64_t per_block = 16384;
+    const size_t shm = d <= 8192 ? static_cast<size_t>(d) * 8 : 0;
+    prof_begin(kKColmax, s);
+    colmax_csr_kernel<<<grid1(nnz, static_cast<int>(per_block)), 256, shm, s>>>(
+        col_idx, static_cast<const float*>(x), nnz, d, per_block, cm, nonfinite);
+    prof_end(kKColmax, s);
+    return;
+  }
+  const int64_t cb = (d + 255) / 256;
+  int64_t rpb = 64;
+  while ((n + rpb - 1) / rpb * cb > 4096) rpb *= 2;
+  dim3 grid(static_cast<unsigned>(cb), static_cast<unsigned>((n + rpb - 1) / rpb));
+  switch (dtype) {
+    case 0:
+      prof_begin(kKColmax, s);
+      colmax_dense_kernel<double><<<grid, 256, 0, s>>>(
+          static_cast<const double*>(x), n, d, ld, rpb, cm, nonfinite);
+      prof_end(kKColmax, s);
+      break;
+    case 1:
+      prof_begin(kKColmax, s);
+      colmax_dense_kernel<float><<<grid, 256, 0, s>>>(
+          static_cast<const float*>(x), n, d, ld, rpb, cm, nonfinite);
+      prof_end(kKColmax, s);
+      break;
+    case 2:
+      prof_begin(kKColmax, s);
+      colmax_dense_kernel<uint16_t><<<grid, 256, 0, s>>>(
+          static_cast<const uint16_t*>(x), n, d, ld, rpb, cm, nonfinite);
+      prof_end(kKColmax, s);
+      break;
+    default:
+      break;
+  }
+}
+
+void launch_colscale(const uint64_t* colmax_bits, int64_t d, double* dscale,
+                     hipStream_t s) {
+  colscale_kernel<<<grid1(d, 256), 256, 0, s>>>(
+      reinterpret_cast<const unsigned long long*>(colmax_bits), d, dscale);
+}
+
+void launch_countsketch(const void* x, int dtype, int format, int64_t n,
+                        int64_t d, int64_t ld, const int64_t* row_ptr,
+                        const int32_t* col_idx, const float* col_scale,
+                        const float* row_scale, const uint32_t* sorted_vals,
+                        const int32_t* offsets, int64_t r,
+                        const double* dscale, double* sx, hipStream_t s) {
+  (void)n;
+  (void)col_scale;
+  (void)row_scale;
+  const unsigned grid = grid1(r, 4);
+  if (format == 1) {
+    prof_begin(kKSketch, s);
+    countsketch_csr_kernel<<<grid, 256, 0, s>>>(
+        row_ptr, col_idx, static_cast<const float*>(x), d, sorted_vals, offsets,
+        r, dscale, sx);
+    prof_end(kKSketch, s);
+    return;
+  }
+  switch (dtype) {
+    case 0:
+      prof_begin(kKSketch, s);
+      countsketch_dense_kernel<double><<<grid, 256, 0, s>>>(
+          static_cast<const double*>(x), d, ld, sorted_vals, offsets, r, dscale,
+          sx);
+      prof_end(kKSketch, s);
+      break;
+    case 1:
+      prof_begin(kKSketch, s);
+      countsketch_dense_kernel<float><<<grid, 256, 0, s>>>(
+          static_cast<const float*>(x), d, ld, sorted_vals, offsets, r, dscale,
+          sx);
+      prof_end(kKSketch, s);
+      break;
+    case 2:
+      prof_begin(kKSketch, s);
+      countsketch_dense_kernel<uint16_t><<<grid, 256, 0, s>>>(
+          static_cast<const uint16_t*>(x), d, ld, sorted_vals, offsets, r,
+          dscale, sx);
+      prof_end(kKSketch, s);
+      break;
+    default:
+      break;
+  }
+}
+
+}  // namespace slso

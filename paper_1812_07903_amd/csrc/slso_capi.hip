@@ -1,0 +1,539 @@
+// C ABI of the slso library: argument validation, the context's device
+// workspace, and the order of stages of the sketched leverage path
+// (Algorithms 2 and 3 in QR form with the second projection Pi_2, and the
+// "dec" ordering of Sec. 5.2).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "slso.h"
+
+struct slso_ctx {
+  int device = 0;
+  void* ws = nullptr;       // device workspace
+  size_t ws_bytes = 0;
+  void* host_buf = nullptr; // pinned host staging for small read-backs
+  std::string err;
+};
+
+
+// ---- launch profiler -------------------------------------------------------
+namespace slso {
+namespace {
+struct ProfEntry {
+  int kid;
+  hipEvent_t a, b;
+};
+struct Profiler {
+  bool on = false;
+  std::mutex mu;
+  std::vector<hipEvent_t> pool;
+  std::vector<ProfEntry> pending;
+  int open_kid = -1;
+  hipEvent_t open_ev = nullptr;
+  double ms[kKCount] = {};
+  int64_t count[kKCount] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Profiler& prof() {
+  static Profiler p;
+  return p;
+}
+}  // namespace
+
+void prof_begin(int kid, hipStream_t s) {
+  Profiler& p = prof();
+  if (!p.on) return;
+  std::lock_guard<std::mutex> g(p.mu);
+  hipEvent_t e = p.get();
+  if (!e) return;
+  if (hipEventRecord(e, s) != hipSuccess) {
+    p.pool.push_back(e);
+    return;
+  }
+  p.open_kid = kid;
+  p.open_ev = e;
+}
+
+void prof_end(int kid, hipStream_t s) {
+  Profiler& p = prof();
+  if (!p.on) return;
+  std::lock_guard<std::mutex> g(p.mu);
+  if (p.open_kid != kid || !p.open_ev) return;
+  hipEvent_t e = p.get();
+  if (!e) return;
+  if (hipEventRecord(e, s) != hipSuccess) {
+    p.pool.push_back(e);
+    return;
+  }
+  p.pending.push_back({kid, p.open_ev, e});
+  p.open_kid = -1;
+  p.open_ev = nullptr;
+}
+}  // namespace slso
+
+namespace {
+
+using namespace slso;
+
+constexpr size_t kAlign = 256;
+
+struct Arena {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = reinterpret_cast<T*>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// Bytes an arena layout needs: replay the same sequence of take() calls.
+struct Sizer {
+  size_t off = 0;
+  template <typename T>
+  void take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    off += count * sizeof(T);
+  }
+};
+
+int set_err(slso_ctx* c, int st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+#define SLSO_HIP(ctx, call)                                                  \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return set_err(ctx, SLSO_EDEVICE,                                      \
+                     std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+int ensure_ws(slso_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_bytes) return SLSO_OK;
+  SLSO_HIP(c, hipSetDevice(c->device));
+  if (c->ws) {
+    SLSO_HIP(c, hipDeviceSynchronize());
+    SLSO_HIP(c, hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  const size_t want = bytes + bytes / 8 + (1u << 20);
+  if (hipMalloc(&c->ws, want) != hipSuccess) {
+    c->ws = nullptr;
+    (void)hipGetLastError();
+    return set_err(c, SLSO_ENOMEM,
+                   "workspace allocation of " + std::to_string(want) +
+                       " bytes failed");
+  }
+  c->ws_bytes = want;
+  return SLSO_OK;
+}
+
+int check_launch(slso_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return set_err(c, SLSO_EDEVICE,
+                   std::string(what) + ": " + hipGetErrorString(e));
+  return SLSO_OK;
+}
+
+int bits_for(int64_t r) {
+  int b = 0;
+  while ((static_cast<int64_t>(1) << b) < r) ++b;
+  return b;
+}
+
+int validate_matrix(slso_ctx* c, const slso_matrix* X) {
+  if (!X) return set_err(c, SLSO_EINVAL, "X is NULL");
+  if (X->n < 1 || X->d < 1) return set_err(c, SLSO_EINVAL, "n and d must be >= 1");
+  if (X->n >= (static_cast<int64_t>(1) << 31))
+    return set_err(c, SLSO_EINVAL, "n must be < 2^31");
+  if (!X->values) return set_err(c, SLSO_EINVAL, "X->values is NULL");
+  if (X->format == SLSO_DENSE) {
+    if (X->ld < X->d) return set_err(c, SLSO_EINVAL, "ld must be >= d");
+    if (X->dtype != SLSO_F64 && X->dtype != SLSO_F32 && X->dtype != SLSO_BF16)
+      return set_err(c, SLSO_EUNSUPPORTED,
+                     "dense input must be F64, F32 or BF16 on this path");
+  } else if (X->format == SLSO_CSR) {
+    if (!X->row_ptr || !X->col_idx)
+      return set_err(c, SLSO_EINVAL, "CSR needs row_ptr and col_idx");
+    if (X->nnz < 0) return set_err(c, SLSO_EINVAL, "nnz must be >= 0");
+    if (X->dtype != SLSO_F32)
+      return set_err(c, SLSO_EUNSUPPORTED, "CSR values must be F32");
+  } else {
+    return set_err(c, SLSO_EINVAL, "unknown format");
+  }
+  return SLSO_OK;
+}
+
+struct SketchBufs {
+  uint32_t *keys, *vals, *keys_s, *vals_s, *keys_t, *vals_t;
+  int32_t* off;
+  void* sort_ws;
+};
+
+template <typename A>
+SketchBufs take_sketch_bufs(A& a, int64_t n, int64_t r) {
+  SketchBufs b{};
+  b.keys = a.template take<uint32_t>(n);
+  b.vals = a.template take<uint32_t>(n);
+  b.keys_s = a.template take<uint32_t>(n);
+  b.vals_s = a.template take<uint32_t>(n);
+  b.keys_t = a.template take<uint32_t>(n);
+  b.vals_t = a.template take<uint32_t>(n);
+  b.off = a.template take<int32_t>(r + 1);
+  b.sort_ws = a.template take<char>(radix_sort_scratch_bytes(n));
+  return b;
+}
+
+void size_sketch_bufs(Sizer& z, int64_t n, int64_t r) {
+  for (int i = 0; i < 6; ++i) z.take<uint32_t>(n);
+  z.take<int32_t>(r + 1);
+  z.take<char>(radix_sort_scratch_bytes(n));
+}
+
+// Bucket partition + CountSketch into sx (r x d), optionally column-scaled.
+void enqueue_countsketch(const slso_matrix* X, uint64_t seed, int64_t r,
+                         const SketchBufs& b, const double* dscale, double* sx,
+                         hipStream_t s) {
+  const HashCoeffs hb = make_hash_coeffs(seed, kStreamBucket);
+  const HashCoeffs hs = make_hash_coeffs(seed, kStreamSign);
+  launch_hash_pack(hb, hs, r, 0, X->n, b.keys, b.vals, s);
+  radix_sort_pairs(b.keys, b.vals, b.keys_s, b.vals_s, b.keys_t, b.vals_t, X->n,
+                   bits_for(r), b.sort_ws, s);
+  launch_bucket_offsets(b.keys_s, X->n, r, b.off, s);
+  launch_countsketch(X->values, X->dtype, X->format, X->n, X->d, X->ld,
+                     X->row_ptr, X->col_idx, X->col_scale, X->row_scale,
+                     b.vals_s, b.off, r, dscale, sx, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* slso_status_string(int status) {
+  switch (status) {
+    case SLSO_OK: return "ok";
+    case SLSO_RANK_DEFICIENT: return "rank deficient (truncated)";
+    case SLSO_EINVAL: return "invalid argument";
+    case SLSO_ENOMEM: return "out of device memory";
+    case SLSO_ENONFINITE: return "input holds Inf or NaN";
+    case SLSO_EDEVICE: return "HIP runtime error";
+    case SLSO_EUNSUPPORTED: return "unsupported combination";
+    default: return "unknown status";
+  }
+}
+
+const char* slso_last_error(const slso_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : "";
+}
+
+int slso_create(slso_ctx** out, int device) {
+  if (!out) return SLSO_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return SLSO_EINVAL;
+  slso_ctx* c = new slso_ctx();
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipHostMalloc(&c->host_buf, 4096, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return SLSO_EDEVICE;
+  }
+  *out = c;
+  return SLSO_OK;
+}
+
+int slso_destroy(slso_ctx* c) {
+  if (!c) return SLSO_EINVAL;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->host_buf) (void)hipHostFree(c->host_buf);
+  delete c;
+  return SLSO_OK;
+}
+
+int slso_hash(uint64_t seed, int64_t r, int64_t row0, int64_t n,
+              int32_t* bucket, int8_t* sign, void* stream) {
+  if (r < 1 || r >= (static_cast<int64_t>(1) << 31) || n < 0 || row0 < 0 ||
+      (n > 0 && (!bucket || !sign)))
+    return SLSO_EINVAL;
+  launch_hash_out(make_hash_coeffs(seed, kStreamBucket),
+                  make_hash_coeffs(seed, kStreamSign), r, row0, n, bucket, sign,
+                  static_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? SLSO_OK : SLSO_EDEVICE;
+}
+
+int slso_gaussian(uint64_t seed, int32_t stream_id, int64_t rows, int64_t cols,
+                  double* out, void* stream) {
+  if (rows < 0 || cols < 0 || (rows * cols > 0 && !out)) return SLSO_EINVAL;
+  launch_gaussian(seed, static_cast<uint32_t>(stream_id), rows, cols, 1.0, out,
+                  static_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? SLSO_OK : SLSO_EDEVICE;
+}
+
+int slso_sketch(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
+                const slso_options* opt, double* sx, void* stream) {
+  if (!c) return SLSO_EINVAL;
+  int st = validate_matrix(c, X);
+  if (st) return st;
+  if (r < X->d || r >= (static_cast<int64_t>(1) << 31))
+    return set_err(c, SLSO_EINVAL, "need d <= r < 2^31");
+  if (!sx) return set_err(c, SLSO_EINVAL, "sx is NULL");
+  const int kind = opt ? opt->sketch : SLSO_COUNTSKETCH;
+  if (kind != SLSO_COUNTSKETCH)
+    return set_err(c, SLSO_EUNSUPPORTED, "sketch kind not provided");
+  SLSO_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Sizer z;
+  size_sketch_bufs(z, X->n, r);
+  if ((st = ensure_ws(c, z.off))) return st;
+  Arena a{static_cast<char*>(c->ws)};
+  SketchBufs b = take_sketch_bufs(a, X->n, r);
+  enqueue_countsketch(X, seed, r, b, nullptr, sx, s);
+  return check_launch(c, "slso_sketch");
+}
+
+int slso_qr_r(slso_ctx* c, double* a, int64_t m, int64_t d, double* r_out,
+              void* stream) {
+  if (!c) return SLSO_EINVAL;
+  if (!a || !r_out || d < 1 || m < d)
+    return set_err(c, SLSO_EINVAL, "need a, r_out and m >= d >= 1");
+  SLSO_HIP(c, hipSetDevice(c->device));
+  int st = ensure_ws(c, qr_scratch_bytes(m, d) + kAlign);
+  if (st) return st;
+  qr_factor(a, m, d, r_out, c->ws, static_cast<hipStream_t>(stream));
+  return check_launch(c, "slso_qr_r");
+}
+
+int slso_solve_upper(slso_ctx* c, const double* r, int64_t d, double* b,
+                     int64_t k, void* stream) {
+  if (!c) return SLSO_EINVAL;
+  if (!r || !b || d < 1 || k < 1)
+    return set_err(c, SLSO_EINVAL, "need r, b, d >= 1, k >= 1");
+  SLSO_HIP(c, hipSetDevice(c->device));
+  solve_upper(r, d, b, k, static_cast<hipStream_t>(stream));
+  return check_launch(c, "slso_solve_upper");
+}
+
+int slso_scores(slso_ctx* c, const slso_matrix* X, const double* m, int64_t k,
+                float* scores, void* stream) {
+  if (!c) return SLSO_EINVAL;
+  int st = validate_matrix(c, X);
+  if (st) return st;
+  if (!m || !scores || k < 1)
+    return set_err(c, SLSO_EINVAL, "need m, scores and k >= 1");
+  SLSO_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Sizer z;
+  z.take<float>(X->d * k);
+  z.take<char>(scores_partial_bytes(X->n, k, X->format));
+  if ((st = ensure_ws(c, z.off))) return st;
+  Arena a{static_cast<char*>(c->ws)};
+  float* m32 = a.take<float>(X->d * k);
+  double* part = a.take<double>(scores_partial_bytes(X->n, k, X->format) / 8);
+  launch_scale_rows(m, nullptr, X->d, k, nullptr, m32, s);
+  launch_scores(X->values, X->dtype, X->format, X->n, X->d, X->ld, X->row_ptr,
+                X->col_idx, X->col_scale, X->row_scale, m, m32, k, scores, s,
+                part);
+  return check_launch(c, "slso_scores");
+}
+
+int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
+                  int64_t k, const slso_options* opt, float* scores,
+                  slso_info* info, void* stream) {
+  if (!c) return SLSO_EINVAL;
+  int st = validate_matrix(c, X);
+  if (st) return st;
+  if (r < X->d || r >= (static_cast<int64_t>(1) << 31))
+    return set_err(c, SLSO_EINVAL, "need d <= r < 2^31");
+  if (k < 0) return set_err(c, SLSO_EINVAL, "k must be >= 0");
+  if (!scores) return set_err(c, SLSO_EINVAL, "scores is NULL");
+  slso_options o{};
+  if (opt) o = *opt;
+  if (o.sketch != SLSO_COUNTSKETCH)
+    return set_err(c, SLSO_EUNSUPPORTED, "sketch kind not provided");
+  if (o.refine) return set_err(c, SLSO_EUNSUPPORTED, "refinement not provided");
+  const double tol = o.rank_tol == 0.0 ? 1e-10 : o.rank_tol;
+  const int64_t n = X->n, d = X->d;
+  const int64_t kk = k == 0 ? d : k;
+  SLSO_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  // workspace plan
+  Sizer z;
+  size_sketch_bufs(z, n, r);
+  z.take<uint64_t>(d);             // colmax bits
+  z.take<double>(d);               // dscale
+  z.take<int>(64);                 // flags
+  z.take<double>(4);               // diag stats
+  z.take<double>(r * d);           // sketch
+  z.take<char>(qr_scratch_bytes(r, d));
+  z.take<double>(d * d);           // R_D
+  z.take<double>(d * kk);          // Pi_2 -> M'
+  z.take<double>(d * kk);          // M (FP64)
+  z.take<float>(d * kk);           // M (FP32)
+  z.take<char>(scores_partial_bytes(n, kk, X->format));
+  if ((st = ensure_ws(c, z.off))) return st;
+  Arena a{static_cast<char*>(c->ws)};
+  SketchBufs sb = take_sketch_bufs(a, n, r);
+  uint64_t* colmax = a.take<uint64_t>(d);
+  double* dscale = a.take<double>(d);
+  int* flags = a.take<int>(64);
+  double* dstat = a.take<double>(4);
+  double* sx = a.take<double>(r * d);
+  void* qws = a.take<char>(qr_scratch_bytes(r, d));
+  double* R = a.take<double>(d * d);
+  double* pi = a.take<double>(d * kk);
+  double* m64 = a.take<double>(d * kk);
+  float* m32 = a.take<float>(d * kk);
+  double* part = a.take<double>(scores_partial_bytes(n, kk, X->format) / 8);
+
+  // 1. column equilibration D (power of two) from column max-abs of X
+  launch_fill_u64(colmax, d, 0, s);
+  launch_fill_i32(flags, 64, 0, s);
+  launch_colmax(X->values, X->dtype, X->format, n, d, X->ld, X->row_ptr,
+                X->col_idx, X->nnz, X->col_scale, X->row_scale, colmax, flags, s);
+  launch_colscale(colmax, d, dscale, s);
+  // 2. CountSketch of X D (Algorithm 2 step 1)
+  enqueue_countsketch(X, seed, r, sb, dscale, sx, s);
+  // 3. Householder QR of the sketch (Algorithm 2 step 2, QR form)
+  qr_factor(sx, r, d, R, qws, s);
+  launch_diag_stats(R, d, dstat, s);
+  if ((st = check_launch(c, "slso_leverage: sketch/QR"))) return st;
+  // 4. rank screen read-back
+  char* hb = static_cast<char*>(c->host_buf);
+  SLSO_HIP(c, hipMemcpyAsync(hb, dstat, 2 * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+  SLSO_HIP(c, hipMemcpyAsync(hb + 64, flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  SLSO_HIP(c, hipStreamSynchronize(s));
+  double dmin, dmax;
+  int nonfinite;
+  std::memcpy(&dmin, hb, 8);
+  std::memcpy(&dmax, hb + 8, 8);
+  std::memcpy(&nonfinite, hb + 64, sizeof(int));
+  if (nonfinite) return set_err(c, SLSO_ENONFINITE, "X holds Inf or NaN");
+  bool full = true;
+  if (tol >= 0.0) full = dmax > 0.0 && dmin > std::sqrt(tol) * dmax;
+  // 5. Pi_2 and M = D pinv(R_D) Pi_2 (Algorithm 2 step 3 / Algorithm 3 step 4)
+  if (k == 0)
+    launch_eye(pi, d, s);
+  else
+    launch_gaussian(seed, kStreamPi2, d, k, std::sqrt(static_cast<double>(k)),
+                    pi, s);
+  int64_t rank = d;
+  if (full) {
+    solve_upper(R, d, pi, kk, s);
+    launch_scale_rows(pi, dscale, d, kk, m64, m32, s);
+  } else {
+    Sizer jz;
+    jz.take<char>(jacobi_scratch_bytes(d, kk));
+    // the Jacobi scratch reuses the sketch area, which is no longer needed
+    if (static_cast<size_t>(r * d) * sizeof(double) < jz.off) {
+      return set_err(c, SLSO_EUNSUPPORTED,
+                     "truncation scratch exceeds the sketch area");
+    }
+    if (jacobi_truncated_apply(R, d, pi, kk, tol, m64, &rank, sx, s) != 0)
+      return set_err(c, SLSO_EDEVICE, "Jacobi SVD failed");
+    launch_scale_rows(m64, dscale, d, kk, pi, m32, s);
+    m64 = pi;
+  }
+  // 6. scores l_i = ||x_i M||^2 (Algorithm 2 step 4)
+  launch_scores(X->values, X->dtype, X->format, n, d, X->ld, X->row_ptr,
+                X->col_idx, X->col_scale, X->row_scale, m64, m32, kk, scores, s,
+                part);
+  if ((st = check_launch(c, "slso_leverage: scores"))) return st;
+  if (info) {
+    info->rank = rank;
+    info->screen_full = full ? 1 : 0;
+    info->flags = 0;
+    info->diag_min = dmin;
+    info->diag_max = dmax;
+  }
+  return rank < d ? SLSO_RANK_DEFICIENT : SLSO_OK;
+}
+
+int slso_order(slso_ctx* c, const float* scores, int64_t n, int32_t* perm,
+               void* stream) {
+  if (!c) return SLSO_EINVAL;
+  if (!scores || !perm || n < 1 || n >= (static_cast<int64_t>(1) << 31))
+    return set_err(c, SLSO_EINVAL, "need scores, perm and 1 <= n < 2^31");
+  SLSO_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Sizer z;
+  for (int i = 0; i < 4; ++i) z.take<uint32_t>(n);
+  z.take<char>(radix_sort_scratch_bytes(n));
+  int st = ensure_ws(c, z.off);
+  if (st) return st;
+  Arena a{static_cast<char*>(c->ws)};
+  uint32_t* keys = a.take<uint32_t>(n);
+  uint32_t* keys_o = a.take<uint32_t>(n);
+  uint32_t* keys_t = a.take<uint32_t>(n);
+  uint32_t* vals_t = a.take<uint32_t>(n);
+  void* sws = a.take<char>(radix_sort_scratch_bytes(n));
+  launch_score_keys(scores, n, keys, s);
+  radix_sort_pairs(keys, nullptr, keys_o, reinterpret_cast<uint32_t*>(perm),
+                   keys_t, vals_t, n, 32, sws, s);
+  return check_launch(c, "slso_order");
+}
+
+int slso_profile_enable(int on) {
+  slso::Profiler& p = slso::prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  p.on = on != 0;
+  return SLSO_OK;
+}
+
+int slso_profile_read(double* ms, int64_t* launches, int n) {
+  slso::Profiler& p = slso::prof();
+  if (hipDeviceSynchronize() != hipSuccess) return SLSO_EDEVICE;
+  std::lock_guard<std::mutex> g(p.mu);
+  for (const auto& e : p.pending) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, e.a, e.b) == hipSuccess) {
+      p.ms[e.kid] += t;
+      p.count[e.kid] += 1;
+    }
+    p.pool.push_back(e.a);
+    p.pool.push_back(e.b);
+  }
+  p.pending.clear();
+  for (int i = 0; i < n && i < slso::kKCount; ++i) {
+    if (ms) ms[i] = p.ms[i];
+    if (launches) launches[i] = p.count[i];
+    p.ms[i] = 0.0;
+    p.count[i] = 0;
+  }
+  return slso::kKCount;
+}
+
+const char* slso_profile_name(int id) {
+  static const char* names[] = {
+      "hash_pack", "sort_hist", "sort_scan", "sort_scatter", "bucket_offsets",
+      "colmax", "countsketch", "qr_node", "qr_update", "qr_extract", "trsm",
+      "score", "gaussian"};
+  if (id < 0 || id >= slso::kKCount) return "";
+  return names[id];
+}
+
+}  // extern "C"

@@ -1,0 +1,191 @@
+"""GPU parity of every stage of the sketched leverage path against the CPU
+oracle, through the C ABI (gfx950). Integer outputs (hash, bucket partition,
+permutation) must be bit-exact; FP64 sketches of the same rows in the same
+order are bit-exact as well; floating-point stages carry the tolerances
+stated per test."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synth
+from oracle import leverage as olv
+from oracle import metrics as omet
+from oracle import order as oorder
+from oracle import sketch as osk
+from oracle import streams as ost
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def slso():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1812_07903_amd as m
+    m.load_library()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(slso):
+    c = slso.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def csr_dev(slso, c):
+    return slso.CsrMatrix(c.n, c.d, dev(c.row_ptr.astype(np.int64)),
+                          dev(c.col_idx.astype(np.int32)),
+                          dev(c.val.astype(np.float32)))
+
+
+# ---- streams -----------------------------------------------------------------
+@pytest.mark.parametrize("seed,r,row0,n", [
+    (0, 1, 0, 1), (2025, 7, 0, 5003), (2025, 4096, 0, 20011),
+    (2**63 + 5, 16384, 2**33 + 17, 4097), (77, 32768, 123456, 20000),
+    (1002, 1000, 0, 3001)])
+def test_hash_bit_exact(slso, seed, r, row0, n):
+    b, s = slso.hash(seed, r, n, row0=row0)
+    rb, rs = ost.bucket_sign(seed, r, np.arange(n) + row0)
+    assert np.array_equal(host(b).astype(np.int64), rb)
+    assert np.array_equal(host(s).astype(np.int64), rs)
+
+
+@pytest.mark.parametrize("stream_id", [3, 4])
+def test_gaussian_stream_matches(slso, stream_id):
+    seed, rows, cols = 2**40 + 3, 301, 67
+    z = host(slso.gaussian(seed, stream_id, rows, cols))
+    ref = ost.gaussian(seed, stream_id, np.arange(rows)[:, None],
+                       np.arange(cols)[None, :])
+    assert np.max(np.abs(z - ref) / np.maximum(1.0, np.abs(ref))) < 1e-13
+
+
+# ---- ordering ----------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 4095, 4096, 4097, 100003])
+def test_order_is_stable_descending(slso, ctx, n):
+    rng = np.random.default_rng(n)
+    s = rng.integers(0, 50, n).astype(np.float32) * np.float32(0.125)
+    s[rng.integers(0, n, max(1, n // 10))] = 0.0
+    perm = host(ctx.order(dev(s)))
+    assert np.array_equal(perm.astype(np.int64), np.argsort(-s, kind="stable"))
+    if n <= 5000:
+        assert np.array_equal(perm.astype(np.int64), oorder.dec_order(s))
+
+
+def test_order_all_equal_and_continuous(slso, ctx):
+    assert np.array_equal(host(ctx.order(dev(np.full(9999, 3.5, np.float32)))),
+                          np.arange(9999))
+    s = np.random.default_rng(3).random(65537).astype(np.float32)
+    perm = host(ctx.order(dev(s))).astype(np.int64)
+    assert np.array_equal(perm, np.argsort(-s, kind="stable"))
+
+
+# ---- sketches ----------------------------------------------------------------
+def test_countsketch_dense_f64_bit_exact(slso, ctx):
+    x = synth.config0(n=5000, d=64, seed=3)
+    sx = host(ctx.sketch(dev(x), 11, 512))
+    assert np.array_equal(sx, osk.countsketch_dense(x, 11, 512))
+
+
+@pytest.mark.parametrize("n,d,r", [(3000, 100, 1024), (1, 1, 1), (777, 300, 1000),
+                                   (5000, 784, 2048), (40, 3, 5)])
+def test_countsketch_dense_f32_bit_exact(slso, ctx, n, d, r):
+    if d >= 50:
+        x = synth.image_like(n, d, seed=n + d)
+    else:
+        x = np.random.default_rng(n).random((n, d)).astype(np.float32)
+    sx = host(ctx.sketch(dev(x), 5, r))
+    assert np.array_equal(sx, osk.countsketch_dense(x, 5, r))
+
+
+def test_countsketch_bf16_bit_exact(slso, ctx):
+    x = synth.config0(n=4000, d=48, seed=9)
+    bits = synth.to_bf16_bits(x)
+    xt = dev(bits.view(np.int16)).view(torch.bfloat16)
+    sx = host(ctx.sketch(xt, 21, 256))
+    ref = osk.countsketch_dense(synth.bf16_bits_to_f64(bits), 21, 256)
+    assert np.array_equal(sx, ref)
+
+
+@pytest.mark.parametrize("n,d,r", [(20000, 1500, 2048), (3000, 2500, 2500)])
+def test_countsketch_csr_bit_exact(slso, ctx, n, d, r):
+    c = synth.text_like_csr(n, d, density=0.01, seed=d)
+    sx = host(ctx.sketch(csr_dev(slso, c), 8, r))
+    assert np.array_equal(sx, osk.countsketch_csr(c, 8, r))
+
+
+# ---- QR ------------------------------------------------------------------------
+@pytest.mark.parametrize("m,d", [(64, 64), (100, 37), (256, 32), (257, 33),
+                                 (1000, 96), (3000, 200), (5000, 64),
+                                 (70000, 40), (2048, 512)])
+def test_qr_r_matches_householder(slso, ctx, m, d):
+    rng = np.random.default_rng(m * 7 + d)
+    a = rng.standard_normal((m, d)) * np.exp(rng.standard_normal(d))[None, :]
+    r = host(ctx.qr_r(dev(a.copy())))
+    ref = olv.qr_r(a)
+    assert np.all(np.diag(r) >= 0) and np.all(np.tril(r, -1) == 0)
+    err = np.abs(r - ref).max() / np.abs(ref).max()
+    assert err < 1e-12, err
+
+
+def test_qr_r_zero_column_is_finite(slso, ctx):
+    a = np.random.default_rng(1).standard_normal((600, 40))
+    a[:, 7] = 0.0
+    r = host(ctx.qr_r(dev(a.copy())))
+    assert np.all(np.isfinite(r))
+    # past a zero column R is not unique; R^T R = A^T A is
+    g = a.T @ a
+    assert np.abs(r.T @ r - g).max() < 1e-12 * np.abs(g).max()
+    assert r[7, 7] == 0.0
+
+
+# ---- triangular solve ------------------------------------------------------------
+@pytest.mark.parametrize("d,k", [(1, 1), (63, 32), (64, 64), (65, 7), (200, 100)])
+def test_solve_upper(slso, ctx, d, k):
+    rng = np.random.default_rng(d + k)
+    r = np.triu(rng.standard_normal((d, d))) + 4 * np.eye(d)
+    b = rng.standard_normal((d, k))
+    x = host(ctx.solve_upper(dev(r), dev(b.copy())))
+    ref = sla.solve_triangular(r, b)
+    assert np.abs(x - ref).max() / np.abs(ref).max() < 1e-12
+
+
+# ---- scores ----------------------------------------------------------------------
+@pytest.mark.parametrize("dtype,k", [("f64", 32), ("f32", 64), ("f32", 200),
+                                     ("bf16", 16)])
+def test_scores_dense(slso, ctx, dtype, k):
+    rng = np.random.default_rng(k)
+    n, d = 5003, 97
+    x64 = rng.standard_normal((n, d))
+    m = rng.standard_normal((d, k)) / np.sqrt(d)
+    if dtype == "f64":
+        xt, xref, tol = dev(x64), x64, 1e-7
+    elif dtype == "f32":
+        x32 = x64.astype(np.float32)
+        xt, xref, tol = dev(x32), x32.astype(np.float64), 1e-5
+    else:
+        bits = synth.to_bf16_bits(x64)
+        xt = dev(bits.view(np.int16)).view(torch.bfloat16)
+        xref, tol = synth.bf16_bits_to_f64(bits), 1e-5
+    got = host(ctx.scores(xt, dev(m)))
+    ref = olv.row_scores(xref, m)
+    assert omet.max_rel_err(got, ref) < tol
+
+
+def test_scores_csr(slso, ctx):
+    c = synth.text_like_csr(20000, 700, density=0.02, seed=4)
+    m = np.random.default_rng(2).standard_normal((700, 64)) / 8
+    got = host(ctx.scores(csr_dev(slso, c), dev(m)))
+    ref = olv.row_scores(c, m)
+    assert omet.max_rel_err(got, ref) < 1e-6

@@ -1,0 +1,151 @@
+"""End-to-end GPU parity of slso_leverage / slso_order against the oracle's
+sketched leverage (same seed, hash, sign and Pi_2 streams), at the sizes of
+the paper-shaped workloads. Tolerance: the FP32 gate, max relative score
+error <= 1e-5 against the FP64 oracle; permutations bit-exact against a
+stable descending sort of the GPU's own scores."""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import leverage as olv
+from oracle import metrics as omet
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def slso():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1812_07903_amd as m
+    m.load_library()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(slso):
+    c = slso.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _report(name, got, ref, extra=""):
+    err = omet.max_rel_err(got, ref)
+    tau = omet.kendall_tau(got, ref)
+    print(f"[{name}] max_rel={err:.3e} kendall_tau={tau:.6f} {extra}", flush=True)
+    return err, tau
+
+
+def test_config0_full(slso, ctx):
+    """n=20000, d=64, FP64, CountSketch r=4096, k=32 (plain-method workload)."""
+    x = synth.config0()
+    seed = 2000
+    got, info = ctx.leverage(dev(x), seed, 4096, 32)
+    got = host(got)
+    ref = olv.sketched_leverage(x, seed, 4096, 32)
+    assert info["rank"] == 64 and info["screen_full"]
+    err, _ = _report("c0", got, ref["scores"])
+    assert err < 1e-5
+    exact, _ = olv.exact_leverage(x)
+    _report("c0 vs exact (context)", got, exact)
+    perm = host(ctx.order(dev(got))).astype(np.int64)
+    assert np.array_equal(perm, np.argsort(-got, kind="stable"))
+
+
+def test_config0_k0_exact_sketched_scores(slso, ctx):
+    x = synth.config0(n=6000, d=40, seed=5)
+    got, _ = ctx.leverage(dev(x), 7, 1024, 0)
+    ref = olv.sketched_leverage(x, 7, 1024, 0)
+    err, _ = _report("c0 k=0", host(got), ref["scores"])
+    assert err < 1e-5
+
+
+def test_config1_full(slso, ctx):
+    """n=60000, d=784, FP32 in [0,1], CountSketch r=16384, k=64."""
+    x = synth.config1()
+    seed = 2001
+    t0 = time.time()
+    got, info = ctx.leverage(dev(x), seed, 16384, 64)
+    got = host(got)
+    t1 = time.time()
+    ref = olv.sketched_leverage(x, seed, 16384, 64)
+    t2 = time.time()
+    assert info["rank"] == 784
+    err, tau = _report("c1", got, ref["scores"],
+                       f"gpu {t1 - t0:.2f}s oracle {t2 - t1:.2f}s")
+    assert err < 1e-5
+    assert tau > 0.999
+    perm = host(ctx.order(dev(got))).astype(np.int64)
+    assert np.array_equal(perm, np.argsort(-got, kind="stable"))
+
+
+def test_config1_ragged_small(slso, ctx):
+    x = synth.image_like(2999, 130, seed=8)
+    got, _ = ctx.leverage(dev(x), 3, 1000, 17)
+    ref = olv.sketched_leverage(x, 3, 1000, 17)
+    err, _ = _report("c1 ragged", host(got), ref["scores"])
+    assert err < 1e-5
+
+
+def test_csr_small(slso, ctx):
+    c = synth.text_like_csr(30000, 800, seed=6)
+    xc = slso.CsrMatrix(c.n, c.d, dev(c.row_ptr.astype(np.int64)),
+                        dev(c.col_idx.astype(np.int32)),
+                        dev(c.val.astype(np.float32)))
+    got, info = ctx.leverage(xc, 9, 4096, 64)
+    ref = olv.sketched_leverage(c, 9, 4096, 64)
+    assert info["rank"] == ref["rank"]
+    err, _ = _report("csr small", host(got), ref["scores"])
+    assert err < 1e-5
+
+
+def test_rank_deficient_truncation(slso, ctx):
+    """Noise-free rank-16 input in d=32: the screen trips, the Jacobi SVD finds
+    rank 16, and the truncated scores match the oracle's; with truncation
+    disabled the scores are far from the exact ones (Figs. 2-3 analog)."""
+    rng = np.random.default_rng(16)
+    n, d, k = 4000, 32, 16
+    u = synth.haar(rng, n, k)
+    x = (u * np.exp(rng.standard_normal(n))[:, None]) @ rng.standard_normal((k, d))
+    got, info = ctx.leverage(dev(x), 4, 1024, 0)
+    assert info["rank"] == k and not info["screen_full"]
+    assert info["status"] == slso.RANK_DEFICIENT
+    ref = olv.sketched_leverage(x, 4, 1024, 0)
+    assert ref["rank"] == k
+    err, _ = _report("rank-deficient", host(got), ref["scores"])
+    assert err < 1e-5
+    exact, _ = olv.exact_leverage(x)
+    bad, info2 = ctx.leverage(dev(x), 4, 1024, 0, rank_tol=-1.0)
+    bad = host(bad)
+    assert info2["rank"] == d
+    assert (not np.all(np.isfinite(bad))) or omet.max_rel_err(bad, exact) > 1.0
+
+
+def test_nonfinite_input_rejected(slso, ctx):
+    x = synth.config0(n=500, d=8, seed=1)
+    x[17, 3] = np.nan
+    with pytest.raises(slso.SlsoError) as ei:
+        ctx.leverage(dev(x), 1, 64, 4)
+    assert ei.value.status == slso.ENONFINITE
+
+
+def test_invalid_sizes_rejected(slso, ctx):
+    x = synth.config0(n=500, d=8, seed=1)
+    with pytest.raises(slso.SlsoError) as ei:
+        ctx.leverage(dev(x), 1, 4, 4)      # r < d
+    assert ei.value.status == slso.EINVAL
+    with pytest.raises(slso.SlsoError):
+        ctx.leverage(dev(x), 1, 64, -1)    # k < 0
