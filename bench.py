@@ -29,7 +29,7 @@ PEAK = {"hbm": 8.0e12, "fp64": 78.6e12, "fp32": 157.3e12}
 N, D, R, K, SEED = 60000, 784, 16384, 64, 2001
 
 
-def qr_update_flops(m: int, d: int, w: int = 32) -> float:
+def qr_update_flops(m: int, d: int, w: int = 16) -> float:
     """Algorithmic flops of the blocked Householder trailing updates
     (Y^T C and C - Y W: 4 m' w n' per panel)."""
     f = 0.0
@@ -39,7 +39,7 @@ def qr_update_flops(m: int, d: int, w: int = 32) -> float:
     return f
 
 
-def qr_node_flops(m: int, d: int, w: int = 32) -> float:
+def qr_node_flops(m: int, d: int, w: int = 16) -> float:
     """Algorithmic flops of the panel factorisations (unblocked Householder
     on (m - j0) x w panels: 2 m' w^2 - 2/3 w^3)."""
     f = 0.0

@@ -1,324 +1,667 @@
 // Blocked Householder QR of the r x d sketch in FP64 (Algorithm 2 step 2 in
 // QR form; only R is kept).
 //
-// The factorisation is right-looking with panels of W = 32 columns. Each
-// panel is reduced by a tree of Householder factorisations (the
-// communication-avoiding ordering of tall-skinny QR): the active rows are
-// cut into leaves of L = 256 rows; every tree node factors its <= 256 rows x
-// W panel columns in registers (one workgroup, one row per thread), stores
-// its reflectors in compact-WY form (Y, T with Q = I - Y T Y^T) and leaves
-// its triangle in its first rows (its "head"); the parent stacks the heads of
-// up to F = L / W = 8 children and repeats, until one node remains, whose
-// head holds the panel's rows of R. After every node level, Q^T = I - Y T^T
-// Y^T is applied to the trailing columns of the node's rows. All reflectors
-// are Householder reflectors, so R is the R of a Householder QR (rows differ
-// from LAPACK's only by sign, which is normalised to a non-negative
-// diagonal at the end).
+// Right-looking, panels of W = 16 columns. Each panel is reduced by a tree of
+// Householder factorisations (the communication-avoiding ordering of
+// tall-skinny QR): the active rows are cut into leaves of L = 256 rows; a node
+// factors its <= 256 rows x W panel columns, keeps its reflectors in
+// compact-WY form (Y, T: Q = I - Y T Y^T) and leaves its triangle in its first
+// W rows (its "head"); a parent stacks the heads of up to F = L / W = 16
+// children. Every node is a Householder factorisation, so R is the R of a
+// Householder QR (rows normalised to a non-negative diagonal at the end). One
+// launch per tree level: kernel boundaries order the levels, no inter-block
+// synchronisation.
 //
-// Node kernel, one column step c: a single block-wide reduction of the
-// 32-vector  g_j = sum_{t > c} a_tc a_tj  (j >= c) gives the column norm
-// (g_c) and, with the broadcast pivot row, the dots v^T a_j; the same
-// reduction carries z_j = y_j^T y_{c-1} (j < c-1) for the T recurrence
-// T[0:i, i] = -tau_i T[0:i, 0:i] (Y[:, 0:i]^T y_i). Each wave reduces its 32
-// values by recursive halving (31 shuffles instead of 6 x 32), the four waves
-// combine through LDS.
+// Node factorisation (four waves, one row per thread). Fast path, used when
+// the node's Gram matrix is numerically well conditioned: Cholesky-QR twice
+// (the Gram matrix on FP64 MFMA, Cholesky and the triangular solves in FP64)
+// gives an orthonormal Q and R; Householder reconstruction (Ballard, Demmel,
+// Grigori, Jacquelin, Knight & Nguyen, "Reconstructing Householder vectors
+// from tall-skinny QR", 2014) then yields the Householder vectors exactly:
+// a sign-choosing LU without pivoting, Q - [S; 0] = Y U with every pivot of
+// magnitude >= 1, T = -U S Y1^{-T}, and the Householder R is S R. Otherwise
+// (a Cholesky pivot below 1e-10 of its column's squared norm, fewer than W
+// rows, or a ragged last panel) wave 0 factors the node column by column:
+// per column one wave-wide reduction of the 16-vector g_j = sum_{t > c}
+// a_tc a_tj (norm and all dots) plus z_j = y_j . y_{c-1} for the T recurrence
+// T[0:i, i] = -tau_i T[0:i, 0:i] (Y[:, 0:i]^T y_i).
+//
+// Trailing update: one workgroup of four waves per (node, 64 columns), each
+// wave a 16-column strip held in registers, on FP64 MFMA
+// (v_mfma_f64_16x16x4f64: A operand lane l = A[l%16][l/16], B operand
+// B[l/16][l%16], result register v of lane l = D[4v + l/16][l%16]). The result
+// layout of W1 = Y^T C is the B-operand layout of T^T W1 and of C - Y W2, so
+// the 16 x 16 intermediates never leave registers.
 #include "internal.h"
 
 namespace slso {
 namespace {
 
-constexpr int kW = 32;    // panel width
-constexpr int kL = 256;   // rows per tree node (threads per workgroup)
-constexpr int kF = kL / kW;
+constexpr int kW = 16;       // panel width
+constexpr int kR = 4;        // rows per lane (wave-0 fallback layout)
+constexpr int kL = 64 * kR;  // rows per tree node
+constexpr int kF = kL / kW;  // fan-in
+constexpr int kMaxLevels = 8;
+constexpr int kYP = kW + 1;  // padded LDS row of a W-wide block
+#ifndef SLSO_QR_PIVOT_TOL
+#define SLSO_QR_PIVOT_TOL 1e-10
+#endif
+#ifndef SLSO_QR_FORCE_FALLBACK
+#define SLSO_QR_FORCE_FALLBACK 0
+#endif
+constexpr double kPivotTol = SLSO_QR_PIVOT_TOL;
 
-struct NodeGeom {
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+struct Panel {
   int64_t m, j0;
-  int w;
-  int level;
-  int64_t child_span;     // rows spanned by a node of level-1 (level >= 1)
-  int64_t child_leaves;   // leaves per node of level-1
-  int64_t nchild;         // number of nodes at level-1
-  int64_t nleaves;
+  int w;                        // panel width (<= kW)
+  int nlev;                     // tree levels
+  int64_t nodes[kMaxLevels];    // nodes per level
+  int64_t off[kMaxLevels];      // first node id of a level
+  int64_t span[kMaxLevels];     // leaves per node of a level
 };
 
-__device__ __forceinline__ int64_t leaf_count(const NodeGeom& g, int64_t leaf) {
-  const int64_t rem = g.m - g.j0 - leaf * kL;
+__device__ __forceinline__ int64_t leaf_rows(const Panel& P, int64_t leaf) {
+  const int64_t rem = P.m - P.j0 - leaf * kL;
   return rem < kL ? rem : kL;
 }
 
-// Fills rows[0..255] (global row of local row t, -1 when absent) and returns
-// the node's row count. All threads of the block call it; uses a barrier.
-__device__ int node_rows(const NodeGeom& g, int64_t q, int64_t* rows) {
-  const int t = threadIdx.x;
-  if (g.level == 0) {
-    const int64_t cnt = leaf_count(g, q);
-    rows[t] = t < cnt ? g.j0 + q * kL + t : -1;
-    __syncthreads();
-    return static_cast<int>(cnt);
+// Global row of local row t of node (level, q) (-1 when absent), and the
+// node's row count.
+__device__ __forceinline__ int64_t node_row(const Panel& P, int level,
+                                            int64_t q, int t, int* cnt_out) {
+  int64_t row = -1;
+  if (level == 0) {
+    const int cnt = static_cast<int>(leaf_rows(P, q));
+    if (t < cnt) row = P.j0 + q * kL + t;
+    *cnt_out = cnt;
+    return row;
   }
-  int64_t start[kF];
-  int pre[kF + 1];
-  pre[0] = 0;
+  const int64_t cs = P.span[level - 1];
+  int pre = 0;
 #pragma unroll
   for (int c = 0; c < kF; ++c) {
     const int64_t cq = kF * q + c;
-    int h = 0;
-    if (cq < g.nchild) {
-      const int64_t lc = leaf_count(g, cq * g.child_leaves);
-      h = static_cast<int>(lc < g.w ? lc : g.w);
-      start[c] = g.j0 + cq * g.child_span;
-    } else {
-      start[c] = 0;
+    if (cq < P.nodes[level - 1]) {
+      const int64_t lc = leaf_rows(P, cq * cs);
+      const int h = static_cast<int>(lc < P.w ? lc : P.w);
+      if (t >= pre && t < pre + h) row = P.j0 + cq * cs * kL + (t - pre);
+      pre += h;
     }
-    pre[c + 1] = pre[c] + h;
   }
-  int64_t row = -1;
-#pragma unroll
-  for (int c = 0; c < kF; ++c)
-    if (t >= pre[c] && t < pre[c + 1]) row = start[c] + (t - pre[c]);
-  rows[t] = row;
-  __syncthreads();
-  return pre[kF];
+  *cnt_out = pre;
+  return row;
 }
 
-// Recursive-halving reduction of 32 values over the 64 lanes of a wave: on
-// return lane l holds in v[0] the wave sum of entry (l >> 1).
-__device__ __forceinline__ void wave_reduce32(double (&v)[kW], int lane) {
+// LDS ordering among the lanes of one wave (no block barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Cross-lane moves of doubles: DPP (within rows of 16 lanes), ds_swizzle
+// (within 32 lanes) and ds_bpermute (across the 32-lane halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false));
+}
+template <int PAT>
+__device__ __forceinline__ double swz_d(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(__builtin_amdgcn_ds_swizzle(hi, PAT),
+                          __builtin_amdgcn_ds_swizzle(lo, PAT));
+}
+constexpr int kDppRowMirror = 0x140;      // lane i <-> 15 - i within 16
+constexpr int kDppRowHalfMirror = 0x141;  // lane i <-> 7 - i within 8
+constexpr int kDppQuadSwap2 = 0x4E;       // quad_perm [2,3,0,1]
+constexpr int kDppQuadSwap1 = 0xB1;       // quad_perm [1,0,3,2]
+constexpr int kSwzXor16 = (16 << 10) | 0x1f;
+
+// Recursive halving of 16 values over 64 lanes: on return every lane holds in
+// v[0] the wave sum of entry (lane >> 2) & 15. Each stage pairs every lane
+// with a partner whose deciding bit differs (xor 32, xor 16, mirror within 16,
+// mirror within 8), so the kept halves of the 16 entries line up; the lanes
+// merged into one partial sum are l ^ {0,7,8,15,...,63}, and the last two
+// quad exchanges add the four disjoint partials of each entry.
+__device__ __forceinline__ void reduce16(double (&v)[kW], int lane) {
   {
     const bool hi = lane & 32;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const double send = hi ? v[i] : v[i + 16];
-      const double keep = hi ? v[i + 16] : v[i];
+    for (int i = 0; i < 8; ++i) {
+      const double send = hi ? v[i] : v[i + 8];
+      const double keep = hi ? v[i + 8] : v[i];
       v[i] = keep + __shfl_xor(send, 32, 64);
     }
   }
   {
     const bool hi = lane & 16;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const double send = hi ? v[i] : v[i + 8];
-      const double keep = hi ? v[i + 8] : v[i];
-      v[i] = keep + __shfl_xor(send, 16, 64);
+    for (int i = 0; i < 4; ++i) {
+      const double send = hi ? v[i] : v[i + 4];
+      const double keep = hi ? v[i + 4] : v[i];
+      v[i] = keep + swz_d<kSwzXor16>(send);
     }
   }
   {
     const bool hi = lane & 8;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const double send = hi ? v[i] : v[i + 4];
-      const double keep = hi ? v[i + 4] : v[i];
-      v[i] = keep + __shfl_xor(send, 8, 64);
+    for (int i = 0; i < 2; ++i) {
+      const double send = hi ? v[i] : v[i + 2];
+      const double keep = hi ? v[i + 2] : v[i];
+      v[i] = keep + dpp_d<kDppRowMirror>(send);
     }
   }
   {
     const bool hi = lane & 4;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const double send = hi ? v[i] : v[i + 2];
-      const double keep = hi ? v[i + 2] : v[i];
-      v[i] = keep + __shfl_xor(send, 4, 64);
-    }
-  }
-  {
-    const bool hi = lane & 2;
     const double send = hi ? v[0] : v[1];
     const double keep = hi ? v[1] : v[0];
-    v[0] = keep + __shfl_xor(send, 2, 64);
+    v[0] = keep + dpp_d<kDppRowHalfMirror>(send);
   }
-  v[0] += __shfl_xor(v[0], 1, 64);
+  v[0] += dpp_d<kDppQuadSwap2>(v[0]);
+  v[0] += dpp_d<kDppQuadSwap1>(v[0]);
 }
 
-__global__ void __launch_bounds__(kL)
-    qr_node_kernel(double* __restrict__ A, int64_t lda, NodeGeom g,
-                   double* __restrict__ Yws, double* __restrict__ Tws) {
-  __shared__ int64_t rows[kL];
-  __shared__ double red[4][kW];
-  __shared__ double gsum[kW];
-  __shared__ double rowc[kW];
-  __shared__ double T[kW][kW + 1];
-  __shared__ double taus[kW];
+struct FactorLds {
+  double gsum[kW];
+  double rowc[kW];
+  double T[kW][kW + 1];
+  double taus[kW];
+};
 
-  const int t = threadIdx.x;
-  const int lane = t & 63;
-  const int wave = t >> 6;
-  const int64_t q = blockIdx.x;
-  const int cnt = node_rows(g, q, rows);
-  const int nsteps = cnt < g.w ? cnt : g.w;
-  const int64_t row = rows[t];
-
-  double a[kW];
+template <int C>
+__device__ __forceinline__ void fstep(double (&a)[kR][kW], FactorLds& sh,
+                                      int lane, int nsteps) {
+  if (C > nsteps) return;  // wave-uniform
+  constexpr int cm1 = C > 0 ? C - 1 : 0;
+  constexpr int cc = C < kW ? C : kW - 1;
+  const bool piv = C < nsteps;
+  // Rows in register slots r >= 1 have t = lane + 64 r > every column index,
+  // so only slot 0 needs the position tests below/at/above the diagonal.
+  double v[kW];
 #pragma unroll
-  for (int j = 0; j < kW; ++j)
-    a[j] = (row >= 0 && j < g.w) ? A[row * lda + g.j0 + j] : 0.0;
-  for (int j = t; j < kW * (kW + 1); j += kL) (&T[0][0])[j] = 0.0;
-  if (t < kW) taus[t] = 0.0;
-  __syncthreads();
-
+  for (int j = 0; j < kW; ++j) v[j] = 0.0;
+  if (C >= 2) {
+    const double yp0 = lane > cm1 ? a[0][cm1] : (lane == cm1 ? 1.0 : 0.0);
 #pragma unroll
-  for (int c = 0; c <= kW; ++c) {
-    if (c <= nsteps) {
-      // static indices clamped for the first and the closing step
-      const int cm1 = c > 0 ? c - 1 : 0;
-      const int cc0 = c < kW ? c : kW - 1;
-      const double yprev = t > cm1 ? a[cm1] : (t == cm1 ? 1.0 : 0.0);
-      double v[kW];
+    for (int j = 0; j + 1 < C; ++j) {
+      const double yj = lane > j ? a[0][j] : (lane == j ? 1.0 : 0.0);
+      v[j] = yj * yp0;
 #pragma unroll
-      for (int j = 0; j < kW; ++j) {
-        double val = 0.0;
-        if (j + 1 < c) {
-          // z_{c-1}[j] = y_j . y_{c-1}, y_t[j] = (t>j ? a_j : t==j ? 1 : 0)
-          const double yj = t > j ? a[j] : (t == j ? 1.0 : 0.0);
-          val = yj * yprev;
-        } else if (j >= c && c < nsteps) {
-          val = t > c ? a[cc0] * a[j] : 0.0;
-        }
-        v[j] = val;
-      }
-      wave_reduce32(v, lane);
-      if ((lane & 1) == 0) red[wave][lane >> 1] = v[0];
-      __syncthreads();
-      if (t < kW) gsum[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
-      if (c < nsteps && t == c) {
-#pragma unroll
-        for (int j = 0; j < kW; ++j) rowc[j] = a[j];
-      }
-      __syncthreads();
-      if (c >= 1 && t < c) {
-        // column c-1 of T
-        const int i = t;
-        const int cc = c - 1;
-        if (i == cc) {
-          T[cc][cc] = taus[cc];
-        } else {
-          double s = 0.0;
-          for (int l = i; l < cc; ++l) s += T[i][l] * gsum[l];
-          T[i][cc] = -taus[cc] * s;
-        }
-      }
-      if (c < nsteps) {
-        const double s2 = gsum[cc0];
-        const double alpha = rowc[cc0];
-        double tau = 0.0, beta = alpha, scal = 0.0;
-        if (s2 > 0.0) {
-          const double nrm = sqrt(alpha * alpha + s2);
-          beta = alpha >= 0.0 ? -nrm : nrm;
-          tau = (beta - alpha) / beta;
-          scal = 1.0 / (alpha - beta);
-        }
-        if (t > c) {
-          const double vt = a[cc0] * scal;
-#pragma unroll
-          for (int j = 0; j < kW; ++j)
-            if (j > c) a[j] -= tau * vt * (rowc[j] + scal * gsum[j]);
-          a[cc0] = vt;
-        } else if (t == c) {
-#pragma unroll
-          for (int j = 0; j < kW; ++j)
-            if (j > c) a[j] -= tau * (rowc[j] + scal * gsum[j]);
-          a[cc0] = beta;
-        }
-        if (t == 0) taus[cc0] = tau;
-      }
-      // the T update above reads taus[c-1] written in the previous step and
-      // gsum of this step; the next step rewrites gsum only after its first
-      // barrier, which every thread reaches after finishing this step.
+      for (int r = 1; r < kR; ++r) v[j] += a[r][j] * a[r][cm1];
     }
   }
-  __syncthreads();
+  if (piv) {
+    const double ac0 = lane > C ? a[0][cc] : 0.0;
+#pragma unroll
+    for (int j = cc; j < kW; ++j) {
+      v[j] += ac0 * a[0][j];
+#pragma unroll
+      for (int r = 1; r < kR; ++r) v[j] += a[r][cc] * a[r][j];
+    }
+  }
+  reduce16(v, lane);
+  if ((lane & 3) == 0) sh.gsum[lane >> 2] = v[0];
+  if (piv && lane == C) {
+#pragma unroll
+    for (int j = 0; j < kW; ++j) sh.rowc[j] = a[0][j];
+  }
+  wave_sync();
+  if (C >= 1 && lane < C) {
+    // column C-1 of T: T[i][C-1] = -tau_{C-1} sum_{l=i}^{C-2} T[i][l] z[l]
+    const int i = lane;
+    if (i == cm1) {
+      sh.T[cm1][cm1] = sh.taus[cm1];
+    } else {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < cm1; ++l)
+        if (l >= i) s += sh.T[i][l] * sh.gsum[l];
+      sh.T[i][cm1] = -sh.taus[cm1] * s;
+    }
+  }
+  if (piv) {
+    const double s2 = sh.gsum[cc];
+    const double alpha = sh.rowc[cc];
+    double tau = 0.0, beta = alpha, scal = 0.0;
+    if (s2 > 0.0) {
+      const double nrm = sqrt(alpha * alpha + s2);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    double p[kW];
+#pragma unroll
+    for (int j = cc + 1; j < kW; ++j) p[j] = sh.rowc[j] + scal * sh.gsum[j];
+    {
+      const double vt = lane > C ? a[0][cc] * scal : (lane == C ? 1.0 : 0.0);
+      const double f = tau * vt;
+#pragma unroll
+      for (int j = cc + 1; j < kW; ++j) a[0][j] -= f * p[j];
+      a[0][cc] = lane > C ? vt : (lane == C ? beta : a[0][cc]);
+    }
+#pragma unroll
+    for (int r = 1; r < kR; ++r) {
+      const double vt = a[r][cc] * scal;
+      const double f = tau * vt;
+#pragma unroll
+      for (int j = cc + 1; j < kW; ++j) a[r][j] -= f * p[j];
+      a[r][cc] = vt;
+    }
+    if (lane == 0) sh.taus[cc] = tau;
+  }
+  wave_sync();
+}
 
-  // reflectors (unit lower trapezoid), T, and the triangle in the head rows
-  double* Y = Yws + q * (kL * kW);
+template <int C>
+__device__ __forceinline__ void fsteps(double (&a)[kR][kW], FactorLds& sh,
+                                       int lane, int nsteps) {
+  fstep<C>(a, sh, lane, nsteps);
+  if constexpr (C < kW) fsteps<C + 1>(a, sh, lane, nsteps);
+}
+
+
+struct NodeLds {
+  int64_t rows[kL];
+  double Ash[kL * kYP];        // staged rows of the node (A, then Q1)
+  double Gp[4][kW * kW];       // per-wave partial Gram matrices
+  double G[kW][kYP];
+  double Gd[kW];               // diagonal of the first Gram matrix
+  double R1[kW][kYP];
+  double R2[kW][kYP];
+  double Rf[kW][kYP];
+  double Wl[kW][kYP];          // sign-choosing LU of the top block of Q
+  double Z[kW][kYP];           // Y1^{-T}
+  double Tm[kW][kYP];
+  double inv1[kW], inv2[kW], invu[kW], sgn[kW];
+  int flag;
+  FactorLds fb;
+};
+
+// G = X^T X of the staged rows (256 x 16) on MFMA, four waves x 64 rows.
+__device__ __forceinline__ void gram(NodeLds& sh, int t) {
+  const int lane = t & 63, wv = t >> 6, p = lane & 15, qd = lane >> 4;
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const double x = sh.Ash[(64 * wv + 4 * kk + qd) * kYP + p];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) sh.Gp[wv][(4 * v + qd) * kW + p] = acc[v];
+  __syncthreads();
+  {
+    const int i = t / kW, j = t % kW;
+    sh.G[i][j] = sh.Gp[0][t] + sh.Gp[1][t] + sh.Gp[2][t] + sh.Gp[3][t];
+  }
+  __syncthreads();
+}
+
+// 1/x and sqrt(x) from the hardware approximations refined by Newton steps
+// (two steps take the approximations to full double precision), shorter
+// dependency chains than the correctly rounded library sequences.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ double rsq_nr(double x) {  // 1/sqrt(x), x > 0
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+
+// Cholesky G = R^T R by wave 0 with lane l < 16 owning column l of G in
+// registers (pivots and rows of R broadcast by readlane). Writes R and the
+// inverse diagonal to LDS; sets the fallback flag when a pivot falls below
+// kPivotTol times its reference (the column's squared norm; 1 when ref is
+// NULL).
+__device__ void cholesky16(NodeLds& sh, double (*R)[kYP], double* inv,
+                           const double* ref, int lane) {
+  const int l = lane;
+  double gc[kW], rc[kW];
+#pragma unroll
+  for (int i = 0; i < kW; ++i) {
+    gc[i] = l < kW ? sh.G[i][l] : 0.0;
+    rc[i] = 0.0;
+  }
+  bool ok = true;
 #pragma unroll
   for (int j = 0; j < kW; ++j) {
-    double y = 0.0;
-    if (j < nsteps && t < cnt) y = t > j ? a[j] : (t == j ? 1.0 : 0.0);
-    Y[t * kW + j] = y;
-  }
-  double* Tg = Tws + q * (kW * kW);
-  for (int e = t; e < kW * kW; e += kL) {
-    const int i = e / kW, j = e % kW;
-    Tg[e] = (i < nsteps && j < nsteps) ? T[i][j] : 0.0;
-  }
-  if (row >= 0) {
+    const double piv = readlane_d(gc[j], j);
+    ok = ok && (piv > kPivotTol * (ref ? ref[j] : 1.0));
+    const double ir = rsq_nr(ok ? piv : 1.0);
+    const double rjj = (ok ? piv : 1.0) * ir;
+    const double rjl = l > j ? gc[j] * ir : (l == j ? rjj : 0.0);
+    rc[j] = rjl;
+    if (l == j) inv[j] = ir;
 #pragma unroll
-    for (int j = 0; j < kW; ++j)
-      if (j < g.w) A[row * lda + g.j0 + j] = (t < nsteps && j >= t) ? a[j] : 0.0;
+    for (int i = j + 1; i < kW; ++i) gc[i] -= readlane_d(rjl, i) * rjl;
+  }
+  if (!ok) {
+    if (lane == 0) sh.flag = 1;
+    return;
+  }
+  if (l < kW) {
+#pragma unroll
+    for (int i = 0; i < kW; ++i) R[i][l] = rc[i];
   }
 }
 
-// C <- (I - Y T^T Y^T) C on the node's rows, 64 trailing columns per block.
-constexpr int kUC = 64;
+// x = a R^{-1} for one row (R upper triangular, inverse diagonal given)
+__device__ __forceinline__ void row_solve(const double (&a)[kW], double (&x)[kW],
+                                          const double (*R)[kYP],
+                                          const double* inv) {
+#pragma unroll
+  for (int j = 0; j < kW; ++j) {
+    double s = a[j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= x[k] * R[k][j];
+    x[j] = s * inv[j];
+  }
+}
 
-__global__ void __launch_bounds__(kL)
-    qr_update_kernel(double* __restrict__ A, int64_t lda, NodeGeom g,
+__global__ void __launch_bounds__(256)
+    qr_node_kernel(double* __restrict__ A, int64_t lda, Panel P, int level,
+                   double* __restrict__ Yws, double* __restrict__ Tws) {
+  __shared__ NodeLds sh;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wv = t >> 6;
+  const int64_t q = blockIdx.x;
+  int cnt;
+  const int64_t row = node_row(P, level, q, t, &cnt);
+  sh.rows[t] = row;
+  const int nsteps = cnt < P.w ? cnt : P.w;
+  __syncthreads();
+  // coalesced load: 16 consecutive threads read one row's 16 panel entries;
+  // all loads are issued before any LDS store waits on them
+  {
+    const int j = t & 15;
+    double ld[kW];
+#pragma unroll
+    for (int k = 0; k < kW; ++k) {
+      const int64_t rr = sh.rows[16 * k + (t >> 4)];
+      ld[k] = (rr >= 0 && j < P.w) ? A[rr * lda + P.j0 + j] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kW; ++k) sh.Ash[(16 * k + (t >> 4)) * kYP + j] = ld[k];
+  }
+  __syncthreads();
+  double a[kW];
+#pragma unroll
+  for (int j = 0; j < kW; ++j) a[j] = sh.Ash[t * kYP + j];
+  if (t == 0)
+    sh.flag = (SLSO_QR_FORCE_FALLBACK || P.w != kW || cnt < kW) ? 1 : 0;
+  __syncthreads();
+  const int64_t nid = P.off[level] + q;
+  double* Y = Yws + nid * (kL * kW);
+  double* Tn = Tws + nid * (kW * kW);
+
+  double x[kW];
+  if (!sh.flag) {
+    // ---- Cholesky-QR, first pass: R1, x = a R1^{-1} -------------------------
+    gram(sh, t);
+    if (t < kW) sh.Gd[t] = sh.G[t][t];
+    __syncthreads();
+    if (wv == 0) cholesky16(sh, sh.R1, sh.inv1, sh.Gd, lane);
+    __syncthreads();
+  }
+  if (!sh.flag) {
+    row_solve(a, x, sh.R1, sh.inv1);
+#pragma unroll
+    for (int j = 0; j < kW; ++j) sh.Ash[t * kYP + j] = x[j];
+    __syncthreads();
+    // ---- second pass: R2, q = x R2^{-1} -----------------------------------
+    gram(sh, t);
+    if (wv == 0) cholesky16(sh, sh.R2, sh.inv2, nullptr, lane);  // G2 ~ I
+    __syncthreads();
+  }
+  if (!sh.flag) {
+    double qv[kW];
+    row_solve(x, qv, sh.R2, sh.inv2);
+    {
+      // R = R2 R1
+      const int i = t / kW, j = t % kW;
+      double sres = 0.0;
+#pragma unroll
+      for (int k = 0; k < kW; ++k)
+        if (k >= i && k <= j) sres += sh.R2[i][k] * sh.R1[k][j];
+      sh.Rf[i][j] = sres;
+    }
+    if (t < kW) {
+#pragma unroll
+      for (int j = 0; j < kW; ++j) sh.Wl[t][j] = qv[j];
+    }
+    __syncthreads();
+    // ---- Householder reconstruction: sign-choosing LU of the top block ------
+    // wave 0, lane l < 16 owning column l of the top 16 x 16 block of Q
+    if (wv == 0) {
+      const int l = lane;
+      double wc[kW], z[kW];
+#pragma unroll
+      for (int r = 0; r < kW; ++r) wc[r] = l < kW ? sh.Wl[r][l] : 0.0;
+#pragma unroll
+      for (int i = 0; i < kW; ++i) {
+        const double pv = readlane_d(wc[i], i);
+        const double sg = pv >= 0.0 ? -1.0 : 1.0;
+        const double piv = pv - sg;  // |piv| >= 1
+        const double ip = rcp_nr(piv);
+        if (l == i) {
+          wc[i] = piv;
+#pragma unroll
+          for (int r = i + 1; r < kW; ++r) wc[r] *= ip;
+        }
+        if (lane == 0) {
+          sh.sgn[i] = sg;
+          sh.invu[i] = ip;
+        }
+        const double wil = wc[i];
+#pragma unroll
+        for (int r = i + 1; r < kW; ++r) {
+          const double mr = readlane_d(wc[r], i);
+          if (l > i) wc[r] -= mr * wil;
+        }
+      }
+      // lane c: column c of Y1^{-1} (Y1 unit lower, multipliers of the LU)
+#pragma unroll
+      for (int i = 0; i < kW; ++i) z[i] = (i == l) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < kW; ++k)
+#pragma unroll
+        for (int i = k + 1; i < kW; ++i) z[i] -= readlane_d(wc[i], k) * z[k];
+      if (l < kW) {
+#pragma unroll
+        for (int r = 0; r < kW; ++r) {
+          sh.Wl[r][l] = wc[r];   // U on and above the diagonal, L below
+          sh.Z[l][r] = z[r];     // Z = Y1^{-T}: row l of Z = column l of Y1^{-1}
+        }
+      }
+    }
+    __syncthreads();
+    {
+      // T = -U S Z (upper triangular)
+      const int i = t / kW, j = t % kW;
+      double st = 0.0;
+#pragma unroll
+      for (int k = 0; k < kW; ++k)
+        if (k >= i && k <= j) st += sh.Wl[i][k] * sh.sgn[k] * sh.Z[k][j];
+      Tn[t] = i <= j ? -st : 0.0;
+    }
+    // Y rows: top block from the LU, the rest y = q U^{-1}
+    double yv[kW];
+    if (t < kW) {
+#pragma unroll
+      for (int j = 0; j < kW; ++j)
+        yv[j] = j < t ? sh.Wl[t][j] : (j == t ? 1.0 : 0.0);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kW; ++j) {
+        double sy = qv[j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) sy -= yv[k] * sh.Wl[k][j];
+        yv[j] = sy * sh.invu[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kW; ++j) Y[t * kW + j] = t < cnt ? yv[j] : 0.0;
+    // Householder R = S R in the head rows, zeros in the rest of the panel
+    if (row >= 0) {
+#pragma unroll
+      for (int j = 0; j < kW; ++j)
+        A[row * lda + P.j0 + j] =
+            (t < kW && j >= t) ? sh.sgn[t] * sh.Rf[t][j] : 0.0;
+    }
+    return;
+  }
+
+  // ---- fallback: column-by-column Householder by wave 0 ----------------------
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kW; ++j) sh.Ash[t * kYP + j] = a[j];
+  __syncthreads();
+  if (wv != 0) return;
+  FactorLds& fb = sh.fb;
+  double a4[kR][kW];
+#pragma unroll
+  for (int r = 0; r < kR; ++r)
+#pragma unroll
+    for (int j = 0; j < kW; ++j) a4[r][j] = sh.Ash[(lane + 64 * r) * kYP + j];
+  for (int e = lane; e < kW * (kW + 1); e += 64) (&fb.T[0][0])[e] = 0.0;
+  if (lane < kW) fb.taus[lane] = 0.0;
+  wave_sync();
+  fsteps<0>(a4, fb, lane, nsteps);
+#pragma unroll
+  for (int r = 0; r < kR; ++r) {
+    const int tt = lane + 64 * r;
+#pragma unroll
+    for (int j = 0; j < kW; ++j) {
+      double y = 0.0;
+      if (j < nsteps && tt < cnt) y = tt > j ? a4[r][j] : (tt == j ? 1.0 : 0.0);
+      Y[tt * kW + j] = y;
+    }
+    const int64_t rr = sh.rows[tt];
+    if (rr >= 0) {
+#pragma unroll
+      for (int j = 0; j < kW; ++j)
+        if (j < P.w)
+          A[rr * lda + P.j0 + j] = (tt < nsteps && j >= tt) ? a4[r][j] : 0.0;
+    }
+  }
+  for (int e = lane; e < kW * kW; e += 64) {
+    const int i = e / kW, j = e % kW;
+    Tn[e] = (i < nsteps && j < nsteps) ? fb.T[i][j] : 0.0;
+  }
+}
+
+// Q^T of the nodes of one tree level applied to the trailing matrix: one
+// workgroup of four waves per (node, 64 columns), each wave a 16-column strip
+// of the node's rows held in registers (rows t = 4 m + l/16).
+__global__ void __launch_bounds__(256)
+    qr_update_kernel(double* __restrict__ A, int64_t lda, Panel P, int level,
                      const double* __restrict__ Yws,
                      const double* __restrict__ Tws, int64_t col0,
                      int64_t ncols) {
   __shared__ int64_t rows[kL];
-  __shared__ double Ys[kL][kW];
-  __shared__ double Wp[4][kW][kUC];
-  __shared__ double Ts[kW][kW];
-
+  __shared__ double Ys[kL * kYP];
+  __shared__ double Ts[kW * kW];
   const int t = threadIdx.x;
-  const int lc = t & 63;
-  const int grp = t >> 6;
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const int p = lane & 15;
+  const int qd = lane >> 4;
   const int64_t q = blockIdx.x;
-  const int cnt = node_rows(g, q, rows);
-  const double* Y = Yws + q * (kL * kW);
-  for (int e = t; e < kL * kW; e += kL) (&Ys[0][0])[e] = Y[e];
-  const double* Tg = Tws + q * (kW * kW);
-  for (int e = t; e < kW * kW; e += kL) (&Ts[0][0])[e] = Tg[e];
-  __syncthreads();
-
-  const int64_t col = col0 + static_cast<int64_t>(blockIdx.y) * kUC + lc;
+  const int64_t col = col0 + static_cast<int64_t>(blockIdx.y) * 64 + wave * 16 + p;
   const bool cok = col < col0 + ncols;
+  int cnt;
+  rows[t] = node_row(P, level, q, t, &cnt);
+  const int64_t nid = P.off[level] + q;
+  const double* Y = Yws + nid * (kL * kW);
+  for (int e = t; e < kL * kW; e += 256) Ys[(e / kW) * kYP + (e % kW)] = Y[e];
+  Ts[t] = Tws[nid * (kW * kW) + t];
+  __syncthreads();
 
-  double w1[kW];
+  double creg[kL / 4];
 #pragma unroll
-  for (int i = 0; i < kW; ++i) w1[i] = 0.0;
-  const int rlo = grp * 64;
-  const int rhi = cnt < rlo + 64 ? cnt : rlo + 64;
-  if (cok) {
-#pragma unroll 2
-    for (int tt = rlo; tt < rhi; ++tt) {
-      const double cv = A[rows[tt] * lda + col];
+  for (int m = 0; m < kL / 4; ++m) {
+    const int tt = 4 * m + qd;
+    creg[m] = (tt < cnt && cok) ? A[rows[tt] * lda + col] : 0.0;
+  }
+  // W1 = Y^T C
+  dbl4 w1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int i = 0; i < kW; ++i) w1[i] += Ys[tt][i] * cv;
+  for (int m = 0; m < kL / 4; ++m)
+    if (4 * m < cnt)
+      w1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ys[(4 * m + qd) * kYP + p],
+                                                creg[m], w1, 0, 0, 0);
+  // W2 = T^T W1 (W1 in result layout is the B operand of k-steps 0..3)
+  dbl4 w2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk)
+    w2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ts[(4 * kk + qd) * kW + p],
+                                              w1[kk], w2, 0, 0, 0);
+  // C = C - Y W2, 16 rows at a time with the C tile as accumulator
+#pragma unroll
+  for (int rt = 0; rt < kL / 16; ++rt) {
+    if (16 * rt < cnt) {
+      dbl4 acc = {creg[4 * rt], creg[4 * rt + 1], creg[4 * rt + 2],
+                  creg[4 * rt + 3]};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(
+            Ys[(16 * rt + p) * kYP + 4 * kk + qd], -w2[kk], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) creg[4 * rt + v] = acc[v];
     }
   }
 #pragma unroll
-  for (int i = 0; i < kW; ++i) Wp[grp][i][lc] = w1[i];
-  __syncthreads();
-  // W1 = sum over the four row groups (kept in Wp[0])
-#pragma unroll
-  for (int ii = 0; ii < kW / 4; ++ii) {
-    const int i = grp * (kW / 4) + ii;
-    Wp[0][i][lc] = Wp[0][i][lc] + Wp[1][i][lc] + Wp[2][i][lc] + Wp[3][i][lc];
+  for (int m = 0; m < kL / 4; ++m) {
+    const int tt = 4 * m + qd;
+    if (tt < cnt && cok) A[rows[tt] * lda + col] = creg[m];
   }
-  __syncthreads();
-  // W2 = T^T W1 -> Wp[1]
-#pragma unroll
-  for (int ii = 0; ii < kW / 4; ++ii) {
-    const int i = grp * (kW / 4) + ii;
-    double s = 0.0;
-    for (int l = 0; l <= i; ++l) s += Ts[l][i] * Wp[0][l][lc];
-    Wp[1][i][lc] = s;
+}
+
+Panel make_panel(int64_t m, int64_t d, int64_t j0) {
+  Panel P{};
+  P.m = m;
+  P.j0 = j0;
+  P.w = static_cast<int>(d - j0 < kW ? d - j0 : kW);
+  int64_t nodes = (m - j0 + kL - 1) / kL;
+  int64_t off = 0, span = 1;
+  int lev = 0;
+  for (;;) {
+    P.nodes[lev] = nodes;
+    P.off[lev] = off;
+    P.span[lev] = span;
+    off += nodes;
+    ++lev;
+    if (nodes == 1) break;
+    nodes = (nodes + kF - 1) / kF;
+    span *= kF;
   }
-  __syncthreads();
-  double w2[kW];
-#pragma unroll
-  for (int i = 0; i < kW; ++i) w2[i] = Wp[1][i][lc];
-  if (cok) {
-#pragma unroll 2
-    for (int tt = rlo; tt < rhi; ++tt) {
-      double u = 0.0;
-#pragma unroll
-      for (int i = 0; i < kW; ++i) u += Ys[tt][i] * w2[i];
-      double* p = A + rows[tt] * lda + col;
-      *p = *p - u;
-    }
+  P.nlev = lev;
+  return P;
+}
+
+int64_t total_nodes(int64_t m) {
+  int64_t nodes = (m + kL - 1) / kL, tot = 0;
+  for (;;) {
+    tot += nodes;
+    if (nodes == 1) break;
+    nodes = (nodes + kF - 1) / kF;
   }
+  return tot;
 }
 
 __global__ void extract_r_kernel(const double* __restrict__ A, int64_t lda,
@@ -361,50 +704,33 @@ __global__ void __launch_bounds__(256)
 
 size_t qr_scratch_bytes(int64_t m, int64_t d) {
   (void)d;
-  const int64_t leaves = (m + kL - 1) / kL;
-  return static_cast<size_t>(leaves) * (kL * kW + kW * kW) * sizeof(double);
+  const int64_t tn = total_nodes(m);
+  return static_cast<size_t>(tn) * (kL * kW + kW * kW) * sizeof(double) + 512;
 }
 
 void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
                hipStream_t s) {
-  const int64_t leaves_max = (m + kL - 1) / kL;
+  const int64_t tn = total_nodes(m);
   double* Yws = static_cast<double*>(scratch);
-  double* Tws = Yws + leaves_max * (kL * kW);
+  double* Tws = Yws + tn * (kL * kW);
   for (int64_t j0 = 0; j0 < d; j0 += kW) {
-    NodeGeom g;
-    g.m = m;
-    g.j0 = j0;
-    g.w = static_cast<int>(d - j0 < kW ? d - j0 : kW);
-    g.nleaves = (m - j0 + kL - 1) / kL;
-    g.level = 0;
-    g.child_span = 0;
-    g.child_leaves = 0;
-    g.nchild = 0;
-    int64_t nodes = g.nleaves;
-    int64_t span = kL;       // rows spanned by a node of the current level
-    int64_t leaves_per = 1;  // leaves per node of the current level
-    const int64_t tc0 = j0 + g.w;
+    const Panel P = make_panel(m, d, j0);
+    const int64_t tc0 = j0 + P.w;
     const int64_t tcols = d - tc0;
-    for (;;) {
+    const unsigned groups = static_cast<unsigned>((tcols + 63) / 64);
+    for (int lev = 0; lev < P.nlev; ++lev) {
       prof_begin(kKQrNode, s);
-      qr_node_kernel<<<static_cast<unsigned>(nodes), kL, 0, s>>>(a, d, g, Yws,
-                                                                 Tws);
+      qr_node_kernel<<<static_cast<unsigned>(P.nodes[lev]), 256, 0, s>>>(
+          a, d, P, lev, Yws, Tws);
       prof_end(kKQrNode, s);
-      if (tcols > 0) {
-        dim3 grid(static_cast<unsigned>(nodes),
-                  static_cast<unsigned>((tcols + kUC - 1) / kUC));
+    }
+    if (tcols > 0) {
+      for (int lev = 0; lev < P.nlev; ++lev) {
         prof_begin(kKQrUpdate, s);
-        qr_update_kernel<<<grid, kL, 0, s>>>(a, d, g, Yws, Tws, tc0, tcols);
+        qr_update_kernel<<<dim3(static_cast<unsigned>(P.nodes[lev]), groups),
+                           256, 0, s>>>(a, d, P, lev, Yws, Tws, tc0, tcols);
         prof_end(kKQrUpdate, s);
       }
-      if (nodes == 1) break;
-      g.level += 1;
-      g.child_span = span;
-      g.child_leaves = leaves_per;
-      g.nchild = nodes;
-      span *= kF;
-      leaves_per *= kF;
-      nodes = (nodes + kF - 1) / kF;
     }
   }
   const int64_t dd = d * d;

@@ -23,27 +23,32 @@ namespace {
 
 constexpr int kB = 64;
 
-__global__ void __launch_bounds__(64)
+// One wave per right-hand side, lane i = row i of the diagonal block:
+// x_l = b_l / R_ll is broadcast from lane l, then b_i -= R_il x_l for i < l.
+__global__ void __launch_bounds__(256)
     trsm_diag_kernel(const double* __restrict__ R, int64_t d, int64_t r0,
                      int bs, double* __restrict__ B, int64_t k) {
   __shared__ double Rs[kB][kB + 1];
-  __shared__ double Xs[kB][kB + 1];
   const int t = threadIdx.x;
-  for (int e = t; e < bs * bs; e += 64) {
-    const int i = e / bs, j = e % bs;
-    Rs[i][j] = R[(r0 + i) * d + r0 + j];
+  const int lane = t & 63;
+  for (int e = t; e < kB * kB; e += 256) {
+    const int i = e / kB, j = e % kB;
+    double v = 0.0;
+    if (i < bs && j < bs && j >= i) v = R[(r0 + i) * d + r0 + j];
+    Rs[i][j] = v;
   }
-  const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + t;
-  const bool ok = c < k;
-  for (int i = 0; i < bs; ++i) Xs[i][t] = ok ? B[(r0 + i) * k + c] : 0.0;
   __syncthreads();
-  for (int i = bs - 1; i >= 0; --i) {
-    double s = Xs[i][t];
-    for (int l = i + 1; l < bs; ++l) s -= Rs[i][l] * Xs[l][t];
-    Xs[i][t] = s / Rs[i][i];
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * 4 + (t >> 6);
+  if (c >= k) return;
+  double b = lane < bs ? B[(r0 + lane) * k + c] : 0.0;
+  double x = 0.0;
+  for (int l = bs - 1; l >= 0; --l) {
+    const double bl = __shfl(b, l, 64);
+    const double xl = bl / Rs[l][l];
+    if (lane == l) x = xl;
+    b -= Rs[lane][l] * xl;
   }
-  if (ok)
-    for (int i = 0; i < bs; ++i) B[(r0 + i) * k + c] = Xs[i][t];
+  if (lane < bs) B[(r0 + lane) * k + c] = x;
 }
 
 // B[0:r0, :] -= R[0:r0, r0:r0+bs] X, X = B[r0:r0+bs, :]; 4 rows x 64 columns
@@ -214,7 +219,8 @@ void solve_upper(const double* r, int64_t d, double* b, int64_t k,
     const int64_t r0 = bi * kB;
     const int bs = static_cast<int>(d - r0 < kB ? d - r0 : kB);
     prof_begin(kKTrsm, s);
-    trsm_diag_kernel<<<cgrid, 64, 0, s>>>(r, d, r0, bs, b, k);
+    trsm_diag_kernel<<<static_cast<unsigned>((k + 3) / 4), 256, 0, s>>>(
+        r, d, r0, bs, b, k);
     prof_end(kKTrsm, s);
     if (r0 > 0) {
       dim3 grid(static_cast<unsigned>((r0 + 3) / 4), cgrid);
