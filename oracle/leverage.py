@@ -134,8 +134,11 @@ def exact_leverage(x: np.ndarray, rank_tol: float = DEFAULT_RANK_TOL):
     return np.einsum("ij,ij->i", qu, qu), rank
 
 
-def sketch_of(x, seed: int, r: int, kind: str = "countsketch") -> np.ndarray:
-    """Unscaled sketch S X (FP64)."""
+def sketch_of(x, seed: int, r: int, kind: str = "countsketch",
+              precision: str = "bf16") -> np.ndarray:
+    """Unscaled sketch S X (FP64). For the Gaussian sketch, ``precision``
+    names the entries of S ("bf16": reduced-precision inputs, "f32": the
+    plain FP32 path, "f64": the FP64 stream)."""
     if kind == "countsketch":
         if isinstance(x, np.ndarray):
             return sk.countsketch_dense(x, seed, r)
@@ -143,13 +146,13 @@ def sketch_of(x, seed: int, r: int, kind: str = "countsketch") -> np.ndarray:
     if kind == "gaussian":
         if not isinstance(x, np.ndarray):
             x = x.to_dense()
-        return sk.gaussian_sketch_dense(x, seed, r)
+        return sk.gaussian_sketch_dense(x, seed, r, precision=precision)
     raise ValueError(kind)
 
 
 def sketched_leverage(x, seed: int, r: int, k: int, kind: str = "countsketch",
                       rank_tol: float = DEFAULT_RANK_TOL, sx=None,
-                      refine: bool = False):
+                      refine: bool = False, precision: str = "bf16"):
     """Algorithm 3 in QR form with the second projection Pi_2.
 
     ``sx`` may carry a precomputed unscaled sketch. With ``refine`` the factor
@@ -165,7 +168,7 @@ def sketched_leverage(x, seed: int, r: int, k: int, kind: str = "countsketch",
         rd = qr_r(xd)
     else:
         if sx is None:
-            sx = sketch_of(x, seed, r, kind)
+            sx = sketch_of(x, seed, r, kind, precision)
         rd = qr_r(sx * dsc[None, :])
     pi = np.eye(d) if k == 0 else streams.pi2_matrix(seed, d, k)
     mp, rank, info = truncated_apply(rd, pi, rank_tol)

@@ -68,9 +68,23 @@ def countsketch_csr(csr, seed: int, r: int) -> np.ndarray:
 
 
 def gaussian_sketch_dense(x: np.ndarray, seed: int, r: int,
-                          g: np.ndarray | None = None) -> np.ndarray:
-    """SX = G X / sqrt(r) in FP64 (G from the Gaussian stream unless given)."""
+                          g: np.ndarray | None = None,
+                          precision: str = "f64") -> np.ndarray:
+    """SX = G X / sqrt(r) in FP64.
+
+    ``precision`` selects the entries of G: "f64" the FP64 Box-Muller stream,
+    "f32" the FP32 generator (plain FP32 path), "bf16" the FP32 generator
+    rounded to bfloat16 (reduced-precision inputs). The product is FP64.
+    """
     n = x.shape[0]
     if g is None:
-        g = streams.gaussian_sketch_matrix(seed, r, n)
-    return (g @ np.asarray(x, dtype=np.float64)) / math.sqrt(r)
+        if precision == "f64":
+            g = streams.gaussian_sketch_matrix(seed, r, n)
+        elif precision == "f32":
+            g = streams.gaussian_sketch_matrix_f32(seed, r, n)
+        elif precision == "bf16":
+            g = streams.gaussian_sketch_matrix_bf16(seed, r, n)
+        else:
+            raise ValueError(precision)
+    return (np.asarray(g, dtype=np.float64) @ np.asarray(x, dtype=np.float64)) \
+        / math.sqrt(r)

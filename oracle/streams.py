@@ -151,3 +151,136 @@ def gaussian_sketch_matrix(seed: int, r: int, n: int) -> np.ndarray:
     i = np.arange(n, dtype=np.uint64)[None, :]
     j = np.arange(r, dtype=np.uint64)[:, None]
     return gaussian(seed, STREAM_GAUSS_S, i, j)
+
+
+# --------------------------------------------------------------------------
+# FP32 Gaussian entries of the sketch matrix S (the reduced-precision path)
+# --------------------------------------------------------------------------
+# Definition (shared with the GPU by specification only): for data row i and
+# sketch row j, one Philox4x32-10 block with counter (lo32(i >> 2),
+# hi32(i >> 2), j, stream) and key (lo32(seed), hi32(seed)) gives four 32-bit
+# words; words (0, 1) make a Box-Muller pair for rows i = 4q, 4q+1 and words
+# (2, 3) one for 4q+2, 4q+3. Every step below is a separately rounded FP32
+# operation (no fused multiply-add), so the value is reproducible bit for bit:
+#   u1 = ((w >> 8) + 1) 2^-24 in (0, 1],  u2 = (w' >> 8) 2^-24 in [0, 1)
+#   ln u1 = e ln2 + t q(t), u1 = 2^e m, m in [sqrt(1/2), sqrt(2)), t = m - 1,
+#           q a degree-7 least-squares fit of ln(1+t)/t (coefficients below)
+#   rad = L y with L = -2 ln u1 and y = 1/sqrt(L) from the bit-level initial
+#         guess 0x5F3759DF - (bits(L) >> 1) refined by three Newton steps
+#         (rad = 0 when L = 0)
+#   angle 2 pi u2 = (2k+1) pi/4 + x, k = floor(4 u2), x = (4 u2 - k - 1/2) pi/2,
+#         cos x, sin x by Taylor polynomials to x^8 / x^9, rotated by the
+#         quadrant angle with sqrt(1/2) factors
+#   z = rad cos(angle), z' = rad sin(angle).
+F32 = np.float32
+_LN_Q = [F32(0.9999999403953552), F32(-0.5000036358833313),
+         F32(0.33335113525390625), F32(-0.24970071017742157),
+         F32(0.19898565113544464), F32(-0.17247013747692108),
+         F32(0.1623418927192688), F32(-0.10134056955575943)]
+_LN2 = F32(0.6931471824645996)
+_SQRT2 = F32(1.4142135381698608)
+_HALF_PI = F32(1.5707963705062866)
+_RSQRT_HALF = F32(0.7071067690849304)
+_COS_T = [F32(1.0 / 40320.0), F32(-1.0 / 720.0), F32(1.0 / 24.0), F32(-0.5)]
+_SIN_T = [F32(1.0 / 362880.0), F32(-1.0 / 5040.0), F32(1.0 / 120.0),
+          F32(-1.0 / 6.0)]
+
+
+def _box_muller_f32(wa, wb):
+    """FP32 Box-Muller pair from two 32-bit words (arrays of uint64)."""
+    ua = (wa >> np.uint64(8)).astype(np.uint32)
+    ub = (wb >> np.uint64(8)).astype(np.uint32)
+    two_m24 = F32(2.0 ** -24)
+    u1 = (ua.astype(F32) + F32(1.0)) * two_m24
+    u2 = ub.astype(F32) * two_m24
+    # ln u1
+    bits = u1.view(np.uint32)
+    e = (bits >> np.uint32(23)).astype(np.int32) - 127
+    m = ((bits & np.uint32(0x7FFFFF)) | np.uint32(0x3F800000)).view(F32)
+    big = m > _SQRT2
+    m = np.where(big, m * F32(0.5), m).astype(F32)
+    e = np.where(big, e + 1, e)
+    t = m - F32(1.0)
+    q = _LN_Q[7]
+    for c in _LN_Q[6::-1]:
+        q = q * t
+        q = q + c
+    lnm = t * q
+    ln_u = e.astype(F32) * _LN2
+    ln_u = ln_u + lnm
+    L = F32(-2.0) * ln_u
+    # sqrt(L) = L / sqrt(L) via Newton steps on 1/sqrt(L)
+    li = L.view(np.uint32)
+    y = (np.uint32(0x5F3759DF) - (li >> np.uint32(1))).view(F32)
+    hl = F32(0.5) * L
+    for _ in range(3):
+        y2 = y * y
+        t2 = hl * y2
+        t3 = F32(1.5) - t2
+        y = y * t3
+    rad = np.where(L == F32(0.0), F32(0.0), L * y).astype(F32)
+    # angle
+    q4 = u2 * F32(4.0)
+    k = q4.astype(np.int32)
+    f = q4 - k.astype(F32)
+    x = (f - F32(0.5)) * _HALF_PI
+    x2 = x * x
+    c = _COS_T[0]
+    for ct in _COS_T[1:]:
+        c = c * x2
+        c = c + ct
+    cosx = c * x2
+    cosx = cosx + F32(1.0)
+    s = _SIN_T[0]
+    for st in _SIN_T[1:]:
+        s = s * x2
+        s = s + st
+    sinx = s * x2
+    sinx = sinx * x
+    sinx = sinx + x
+    ca = np.where((k == 0) | (k == 3), _RSQRT_HALF, -_RSQRT_HALF).astype(F32)
+    sa = np.where(k < 2, _RSQRT_HALF, -_RSQRT_HALF).astype(F32)
+    cos_t = ca * cosx - sa * sinx
+    sin_t = sa * cosx + ca * sinx
+    return (rad * cos_t).astype(F32), (rad * sin_t).astype(F32)
+
+
+def gaussian_f32(seed: int, stream: int, i, j) -> np.ndarray:
+    """FP32 Gaussian entry for data row i and sketch row j (broadcast)."""
+    i = np.asarray(i, dtype=np.uint64)
+    j = np.asarray(j, dtype=np.uint64)
+    i, j = np.broadcast_arrays(i, j)
+    g = i >> np.uint64(2)
+    w0, w1, w2, w3 = philox4x32_10(g & np.uint64(MASK32), g >> np.uint64(32),
+                                   j, np.full(i.shape, stream, np.uint64),
+                                   seed & MASK32, (seed >> 32) & MASK32)
+    z0, z1 = _box_muller_f32(w0, w1)
+    z2, z3 = _box_muller_f32(w2, w3)
+    r = (i & np.uint64(3)).astype(np.int64)
+    return np.select([r == 0, r == 1, r == 2], [z0, z1, z2], z3).astype(F32)
+
+
+def bf16_round(x) -> np.ndarray:
+    """Round FP32 values to the nearest bfloat16 (ties to even), as FP32."""
+    u = np.asarray(x, dtype=F32).view(np.uint32).astype(np.uint64)
+    u = ((u + np.uint64(0x7FFF) + ((u >> np.uint64(16)) & np.uint64(1)))
+         >> np.uint64(16)) << np.uint64(16)
+    return u.astype(np.uint32).view(F32)
+
+
+def gaussian_sketch_matrix_f32(seed: int, r: int, n: int, row0: int = 0):
+    """Sketch G (r x n) with FP32 entries (the plain FP32 path), generated a
+    few sketch rows at a time to bound the temporaries."""
+    out = np.empty((r, n), dtype=F32)
+    i = np.arange(row0, row0 + n, dtype=np.uint64)[None, :]
+    step = max(1, (1 << 20) // max(n, 1))
+    for j0 in range(0, r, step):
+        j = np.arange(j0, min(r, j0 + step), dtype=np.uint64)[:, None]
+        out[j0:j0 + j.shape[0]] = gaussian_f32(seed, STREAM_GAUSS_S, i, j)
+    return out
+
+
+def gaussian_sketch_matrix_bf16(seed: int, r: int, n: int, row0: int = 0):
+    """Sketch G (r x n) with entries bf16(gaussian_f32): the reduced-precision
+    path's S = G / sqrt(r)."""
+    return bf16_round(gaussian_sketch_matrix_f32(seed, r, n, row0))

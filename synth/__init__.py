@@ -33,7 +33,7 @@ import numpy as np
 __all__ = [
     "haar", "lowrank_dense", "config0", "image_like", "config1",
     "text_like_csr", "config2", "precision_dense", "to_bf16_bits",
-    "bf16_bits_to_f64", "Csr",
+    "bf16_bits_to_f64", "to_fp8_e4m3", "fp8_e4m3_to_f64", "Csr",
 ]
 
 
@@ -167,3 +167,40 @@ def bf16_bits_to_f64(b: np.ndarray) -> np.ndarray:
     """Exact decode of bfloat16 bit patterns."""
     u = (np.asarray(b, dtype=np.uint32) << 16).astype(np.uint32)
     return u.view(np.float32).astype(np.float64)
+
+
+# Non-negative finite values of the OCP fp8 e4m3fn format, by code 0 .. 126
+# (code 127 is NaN): subnormals m 2^-9, normals (1 + m/8) 2^(e-7).
+_E4M3 = np.array([(m * 2.0 ** -9) if e == 0 else (1.0 + m / 8.0) * 2.0 ** (e - 7)
+                  for e in range(16) for m in range(8)][:127])
+
+
+def to_fp8_e4m3(x: np.ndarray):
+    """Quantise a dense matrix to fp8 e4m3fn with one FP32 scale per column.
+
+    The scale of column j is max_i |x_ij| / 448 (1 for an all-zero column);
+    codes round x_ij / scale_j to the nearest representable value, ties to the
+    even code. Returns (codes uint8 n x d, col_scale float32 d); the value a
+    code stands for is ``fp8_e4m3_to_f64(codes, col_scale)``.
+    """
+    xf = np.asarray(x, dtype=np.float64)
+    cm = np.abs(xf).max(axis=0)
+    cs = np.where(cm > 0, cm / 448.0, 1.0).astype(np.float32)
+    v = xf / cs.astype(np.float64)[None, :]
+    a = np.minimum(np.abs(v), 448.0)
+    hi = np.searchsorted(_E4M3, a, side="left").clip(0, 126)
+    lo = (hi - 1).clip(0, 126)
+    dl, dh = a - _E4M3[lo], _E4M3[hi] - a
+    pick_hi = (dh < dl) | ((dh == dl) & (hi % 2 == 0))
+    code = np.where(pick_hi, hi, lo).astype(np.uint8)
+    code |= np.where((v < 0) & (code != 0), 0x80, 0).astype(np.uint8)
+    return code, cs
+
+
+def fp8_e4m3_to_f64(codes: np.ndarray, col_scale: np.ndarray) -> np.ndarray:
+    """Exact value of e4m3fn codes times their FP32 column scales (FP64)."""
+    c = np.asarray(codes, dtype=np.uint8)
+    mag = _E4M3[np.minimum(c & 0x7F, 126)]
+    mag = np.where((c & 0x7F) == 127, np.nan, mag)
+    val = np.where(c & 0x80, -mag, mag)
+    return val * np.asarray(col_scale, dtype=np.float64)[None, :]

@@ -77,3 +77,35 @@ def test_pi2_scale():
     assert p.shape == (400, 64)
     # column norms^2 ~ d/k
     assert abs((p * p).sum(0).mean() - 400 / 64) < 0.5
+
+
+def test_gaussian_f32_matches_exact_box_muller():
+    """The FP32 generator equals the Box-Muller transform of the same two
+    24-bit uniforms (computed in FP64 with libm) to FP32 accuracy."""
+    i = np.arange(4000, dtype=np.uint64)
+    j = np.full(4000, 7, dtype=np.uint64)
+    g = i >> np.uint64(2)
+    w = streams.philox4x32_10(g, np.zeros_like(g), j, np.full(4000, 3, np.uint64), 11, 0)
+    r = (i & np.uint64(3)).astype(int)
+    wa = np.where(r < 2, w[0], w[2])
+    wb = np.where(r < 2, w[1], w[3])
+    u1 = ((wa >> np.uint64(8)).astype(np.float64) + 1.0) * 2.0 ** -24
+    u2 = (wb >> np.uint64(8)).astype(np.float64) * 2.0 ** -24
+    rad = np.sqrt(-2.0 * np.log(u1))
+    ex = np.where(r % 2 == 0, rad * np.cos(2 * np.pi * u2), rad * np.sin(2 * np.pi * u2))
+    got = streams.gaussian_f32(11, 3, i, j).astype(np.float64)
+    assert np.max(np.abs(got - ex)) < 4e-6
+
+
+def test_gaussian_f32_distribution():
+    z = streams.gaussian_f32(5, 3, np.arange(100000)[:, None],
+                             np.arange(4)[None, :]).ravel().astype(np.float64)
+    assert abs(z.mean()) < 5 / np.sqrt(z.size)
+    assert abs(z.var() - 1) < 6 * np.sqrt(2 / z.size)
+    assert stats.kstest(z, "norm").pvalue > 1e-4
+
+
+def test_bf16_round_ties_to_even():
+    x = np.array([1.0, 1.00390625, 1.01171875, -3.3, 0.0], np.float32)
+    want = np.array([1.0, 1.0, 1.015625, -3.296875, 0.0], np.float32)
+    assert np.array_equal(streams.bf16_round(x), want)
