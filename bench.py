@@ -84,9 +84,9 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the leverage "
-              "path on a single MI355X (see DESIGN.md for how it would shard); "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the leverage path runs on a "
+              "single MI355X (rows would shard across GPUs with one reduction "
+              "of the sketch); run with --gpus 1", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -72,8 +72,10 @@ typedef enum {
  * elements of ``dtype``. CSR: ``values`` (device) holds nnz entries of
  * ``dtype``, with ``row_ptr`` (device, n+1 int64, row_ptr[0] = 0,
  * row_ptr[n] = nnz) and ``col_idx`` (device, nnz int32 in [0, d)).
- * For SLSO_FP8_E4M3 the represented value is q * col_scale[j] (* row_scale[i]
- * when row_scale is not NULL); col_scale (device, d floats) is required.   */
+ * For SLSO_FP8_E4M3 the represented value is q * col_scale[j], with q the
+ * e4m3fn value of the code; col_scale (device, d floats) is required for FP8
+ * (EUNSUPPORTED without it) and must be NULL for other dtypes (EINVAL).
+ * row_scale is reserved and must be NULL (EUNSUPPORTED otherwise).        */
 typedef struct {
   int64_t n, d;
   int32_t format; /* slso_format */
@@ -101,10 +103,17 @@ typedef struct {
 typedef struct {
   int64_t rank;        /* numerical rank used (d when nothing is truncated) */
   int32_t screen_full; /* 1 when the diag(R_D) screen declared full rank    */
-  int32_t flags;       /* reserved, 0                                        */
-  double diag_min;     /* min |R_D[j][j]| of the equilibrated sketch factor  */
-  double diag_max;     /* max |R_D[j][j]|                                    */
+  int32_t flags;       /* SLSO_INFO_* bits                                   */
+  double diag_min;     /* min |R[j][j]| of the factor used (the refined one  */
+  double diag_max;     /* when SLSO_INFO_REFINED is set, else R_D's)         */
 } slso_info;
+
+/* slso_info.flags bits */
+#define SLSO_INFO_REFINED 1       /* R is the refined factor of X D          */
+#define SLSO_INFO_REFINE_FAILED 2 /* refinement asked for but its Cholesky   */
+                                  /* met a non-positive pivot (X D is, in    */
+                                  /* working precision, rank deficient); the */
+                                  /* sketch factor R_D was used instead      */
 
 /* ---- context ------------------------------------------------------------ */
 
@@ -124,7 +133,7 @@ const char* slso_last_error(const slso_ctx* ctx);
 
 /* Sketch S*X (Algorithm 2 step 1; Sec. 2.1; Sec. 3.1.2 "pair of hash
  * functions" for CountSketch).
- *   X      matrix as above (dense F64/F32/BF16 or CSR F32 for CountSketch;
+ *   X      matrix as above (dense F64/F32/BF16/FP8 or CSR F32 for CountSketch;
  *          dense BF16/F32/FP8 for Gaussian).
  *   seed   64-bit seed; the bucket hash, sign hash and Gaussian entries are
  *          derived from it per row index (0-based global row i).
@@ -132,8 +141,12 @@ const char* slso_last_error(const slso_ctx* ctx);
  *   sx     (device) r x d doubles, row-major, overwritten with S*X (without
  *          column equilibration).
  * CountSketch: sx[h(i)] += s(i) x_i, summed in FP64 in ascending i within
- * each bucket (deterministic). Gaussian: S = G/sqrt(r), FP32 accumulation
- * of BF16 products in chunks, FP64 across chunks. */
+ * each bucket (deterministic). Gaussian: S = G/sqrt(r) with G[j][i] the
+ * FP32 generator value of slso_gaussian_sketch_entries (rounded to BF16 for
+ * BF16 and FP8 input); products on MFMA, sums in FP32 within chunks of at
+ * most 65536 rows and in FP64 across chunks, in a fixed order
+ * (deterministic); the 1/sqrt(r) (and for FP8 the column scale) is applied
+ * once to the FP64 sum. EUNSUPPORTED: Gaussian with F64 or CSR input. */
 int slso_sketch(slso_ctx* ctx, const slso_matrix* X, uint64_t seed, int64_t r,
                 const slso_options* opt, double* sx, void* stream);
 
@@ -144,6 +157,14 @@ int slso_sketch(slso_ctx* ctx, const slso_matrix* X, uint64_t seed, int64_t r,
  *           M = D pinv_rank(R_D) Pi_2, D the power-of-two column
  *           equilibration of X and R_D the R factor (non-negative diagonal)
  *           of the equilibrated sketch.
+ *   opt     (host, may be NULL) sketch kind, refinement, rank tolerance.
+ *           refine = 1 (dense F32/BF16/FP8 input only, EUNSUPPORTED
+ *           otherwise): one more pass over X forms G = (X D)^T (X D) on MFMA
+ *           (FP32 accumulation within row chunks, FP64 across them); then
+ *           in FP64, G' = R_D^{-T} G R_D^{-1}, R1 = chol(G') and R = R1 R_D,
+ *           the R factor of X D itself (a Cholesky-QR step preconditioned by
+ *           the sketch; the sketch only needs to make G' well conditioned).
+ *           R replaces R_D below (info.flags reports which was used).
  *   info    (host, may be NULL) filled with the rank decision.
  * Synchronises ``stream`` once (to read the rank screen). Returns
  * SLSO_RANK_DEFICIENT when the rank used is below d. ENONFINITE when X holds
@@ -171,6 +192,21 @@ int slso_hash(uint64_t seed, int64_t r, int64_t row0, int64_t n,
  * doubles, row-major. */
 int slso_gaussian(uint64_t seed, int32_t stream_id, int64_t rows, int64_t cols,
                   double* out, void* stream);
+
+/* FP32 Gaussian sketch entries G[j][row0 + i] for j in [0, r), i in
+ * [0, n): out (device) r x n floats, row-major. Definition (Sec. 2.1 asks
+ * for i.i.d. N(0,1) entries; this is the counter-based form used): with
+ * (w0, w1, w2, w3) = Philox4x32-10(counter (lo32(q), hi32(q), j, 3),
+ * key (lo32(seed), hi32(seed))), q = floor(c / 4) for column c = row0 + i,
+ * the pair (wa, wb) = (w0, w1) for c mod 4 in {0, 1} and (w2, w3) otherwise;
+ * u1 = ((wa >> 8) + 1) 2^-24, u2 = (wb >> 8) 2^-24, and the value is
+ * sqrt(-2 ln u1) cos(2 pi u2) for even c, sin(2 pi u2) for odd c (Box-Muller),
+ * evaluated in a fixed sequence of separately rounded FP32 operations
+ * (degree-7 polynomial logarithm, Newton reciprocal square root, Taylor
+ * cosine and sine by quadrant), so every value is reproducible bit for bit.
+ * EINVAL for negative sizes. */
+int slso_gaussian_sketch_entries(uint64_t seed, int64_t r, int64_t row0,
+                                 int64_t n, float* out, void* stream);
 
 /* R factor of a Householder QR (Algorithm 2 step 2, QR form) of the m x d
  * matrix a (device, row-major, lda = d, m >= d), which is overwritten.

@@ -6,8 +6,10 @@ The binding fails loudly when the library has not been built; there is no
 CPU fallback.
 
 Names mirror the C ABI (``include/slso.h``): ``sketch``, ``leverage``,
-``order``, and the stage entry points ``hash``, ``gaussian``, ``qr_r``,
-``solve_upper`` and ``scores``.
+``order``, and the stage entry points ``hash``, ``gaussian``,
+``gaussian_sketch_entries``, ``qr_r``, ``solve_upper`` and ``scores``.
+Inputs: dense torch tensors (float64, float32, bfloat16), ``Fp8Matrix``
+(e4m3fn codes with per-column scales) and ``CsrMatrix``.
 """
 from __future__ import annotations
 
@@ -30,9 +32,12 @@ STREAM_GAUSS_S, STREAM_PI2 = 3, 4
 EXPORTED = (
     "slso_create", "slso_destroy", "slso_status_string", "slso_last_error",
     "slso_sketch", "slso_leverage", "slso_order", "slso_hash",
-    "slso_gaussian", "slso_qr_r", "slso_solve_upper", "slso_scores",
+    "slso_gaussian", "slso_gaussian_sketch_entries", "slso_qr_r",
+    "slso_solve_upper", "slso_scores",
     "slso_profile_enable", "slso_profile_read", "slso_profile_name",
 )
+# slso_info.flags bits
+INFO_REFINED, INFO_REFINE_FAILED = 1, 2
 
 
 class SlsoError(RuntimeError):
@@ -89,6 +94,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "slso_order": ([vp, vp, i64, vp, vp], ctypes.c_int),
         "slso_hash": ([u64, i64, i64, i64, vp, vp, vp], ctypes.c_int),
         "slso_gaussian": ([u64, i32, i64, i64, vp, vp], ctypes.c_int),
+        "slso_gaussian_sketch_entries": ([u64, i64, i64, i64, vp, vp],
+                                         ctypes.c_int),
         "slso_qr_r": ([vp, vp, i64, i64, vp, vp], ctypes.c_int),
         "slso_solve_upper": ([vp, vp, i64, vp, i64, vp], ctypes.c_int),
         "slso_scores": ([vp, ctypes.POINTER(_Matrix), vp, i64, vp, vp],
@@ -125,9 +132,53 @@ class CsrMatrix:
     val: object
 
 
+@dataclass
+class Fp8Matrix:
+    """Dense FP8-e4m3fn matrix: codes (n x d, uint8 or float8_e4m3fn, unit
+    column stride) standing for e4m3(code) * col_scale[j] (float32[d])."""
+    codes: object
+    col_scale: object
+
+    @property
+    def shape(self):
+        return self.codes.shape
+
+    @property
+    def device(self):
+        return self.codes.device
+
+
+def _rows(x) -> int:
+    return x.n if isinstance(x, CsrMatrix) else x.shape[0]
+
+
+def _cols(x) -> int:
+    return x.d if isinstance(x, CsrMatrix) else x.shape[1]
+
+
+def _device(x):
+    return x.val.device if isinstance(x, CsrMatrix) else x.device
+
+
 def _matrix(x) -> _Matrix:
     import torch
     m = _Matrix()
+    if isinstance(x, Fp8Matrix):
+        c = x.codes
+        if c.dtype not in (torch.uint8, torch.float8_e4m3fn):
+            raise TypeError("FP8 codes must be uint8 or float8_e4m3fn")
+        if c.dim() != 2 or c.stride(1) != 1:
+            raise ValueError("FP8 codes must be 2-D with unit column stride")
+        cs = x.col_scale
+        if cs.dtype != torch.float32 or cs.numel() != c.shape[1] or \
+                not cs.is_contiguous():
+            raise TypeError("col_scale must be a contiguous float32[d]")
+        m.n, m.d = c.shape
+        m.format, m.dtype = DENSE, FP8_E4M3
+        m.values = c.data_ptr()
+        m.ld = c.stride(0)
+        m.col_scale = cs.data_ptr()
+        return m
     if isinstance(x, CsrMatrix):
         if x.val.dtype != torch.float32:
             raise TypeError("CSR values must be float32")
@@ -191,10 +242,9 @@ class Context:
     def sketch(self, x, seed: int, r: int, sketch: int = COUNTSKETCH, out=None,
                stream=None):
         import torch
-        d = x.d if isinstance(x, CsrMatrix) else x.shape[1]
-        dev = (x.val if isinstance(x, CsrMatrix) else x).device
         if out is None:
-            out = torch.empty((r, d), dtype=torch.float64, device=dev)
+            out = torch.empty((r, _cols(x)), dtype=torch.float64,
+                              device=_device(x))
         m = _matrix(x)
         opt = _Options(sketch, 0, 0.0)
         _check(load_library().slso_sketch(self._h, ctypes.byref(m), seed, r,
@@ -207,10 +257,8 @@ class Context:
                  stream=None):
         """Scores (float32 device tensor) and the rank-decision info dict."""
         import torch
-        n = x.n if isinstance(x, CsrMatrix) else x.shape[0]
-        dev = (x.val if isinstance(x, CsrMatrix) else x).device
         if out is None:
-            out = torch.empty(n, dtype=torch.float32, device=dev)
+            out = torch.empty(_rows(x), dtype=torch.float32, device=_device(x))
         m = _matrix(x)
         opt = _Options(sketch, 1 if refine else 0, rank_tol)
         info = _Info()
@@ -219,6 +267,8 @@ class Context:
             ctypes.byref(info), _stream(stream)), self._h)
         return out, {"status": st, "rank": info.rank,
                      "screen_full": bool(info.screen_full),
+                     "flags": info.flags,
+                     "refined": bool(info.flags & INFO_REFINED),
                      "diag_min": info.diag_min, "diag_max": info.diag_max}
 
     def order(self, scores, out=None, stream=None):
@@ -249,10 +299,8 @@ class Context:
 
     def scores(self, x, m, out=None, stream=None):
         import torch
-        n = x.n if isinstance(x, CsrMatrix) else x.shape[0]
-        dev = (x.val if isinstance(x, CsrMatrix) else x).device
         if out is None:
-            out = torch.empty(n, dtype=torch.float32, device=dev)
+            out = torch.empty(_rows(x), dtype=torch.float32, device=_device(x))
         mm = _matrix(x)
         _check(load_library().slso_scores(self._h, ctypes.byref(mm), _ptr(m),
                                           m.shape[1], _ptr(out),
@@ -294,4 +342,15 @@ def gaussian(seed: int, stream_id: int, rows: int, cols: int, device="cuda",
     out = torch.empty((rows, cols), dtype=torch.float64, device=device)
     _check(load_library().slso_gaussian(seed, stream_id, rows, cols, _ptr(out),
                                         _stream(stream)))
+    return out
+
+
+def gaussian_sketch_entries(seed: int, r: int, n: int, row0: int = 0,
+                            device="cuda", stream=None):
+    """FP32 Gaussian sketch entries G[j][row0 + i] (r x n float32)."""
+    import torch
+    out = torch.empty((r, n), dtype=torch.float32, device=device)
+    _check(load_library().slso_gaussian_sketch_entries(seed, r, row0, n,
+                                                       _ptr(out),
+                                                       _stream(stream)))
     return out

@@ -27,6 +27,9 @@ enum KernelId : int {
   kKTrsm,
   kKScore,
   kKGauss,
+  kKGaussSketch,
+  kKGram,
+  kKChol,
   kKCount
 };
 void prof_begin(int kid, hipStream_t s);
@@ -68,7 +71,11 @@ void launch_colmax(const void* x, int dtype, int format, int64_t n, int64_t d,
                    uint64_t* colmax_bits, int* nonfinite, hipStream_t s);
 void launch_colscale(const uint64_t* colmax_bits, int64_t d, double* dscale,
                      hipStream_t s);
-// sx[b] = dscale * sum_{rows in bucket b, ascending} sign * x_row
+// out[j] = a[j] * b[j] (a NULL: 1)
+void launch_mul_scale(const double* a, const float* b, int64_t d, double* out,
+                      hipStream_t s);
+// sx[b] = dscale * sum_{rows in bucket b, ascending} sign * x_row (FP8: codes;
+// the caller folds the column scales into dscale)
 void launch_countsketch(const void* x, int dtype, int format, int64_t n,
                         int64_t d, int64_t ld, const int64_t* row_ptr,
                         const int32_t* col_idx, const float* col_scale,
@@ -99,6 +106,38 @@ void launch_eye(double* out, int64_t d, hipStream_t s);
 // m_out[j][c] = scale_row[j] * m[j][c] as float (m_out32) and/or double
 void launch_scale_rows(const double* m, const double* scale_row, int64_t d,
                        int64_t k, double* out64, float* out32, hipStream_t s);
+
+// ---- Gaussian sketch and Gram matrix (k_gauss.hip) -------------------------
+// dtype: slso_dtype of a dense X (F32, BF16 or FP8-e4m3 with col_scale)
+size_t gauss_partial_bytes(int64_t n, int64_t r, int64_t d);
+// sx = G X / sqrt(r) (times col_scale for FP8 and dscale when given)
+void launch_gauss_sketch(const void* x, int dtype, int64_t n, int64_t d,
+                         int64_t ld, const float* col_scale, uint64_t seed,
+                         int64_t r, const double* dscale, float* partial,
+                         double* sx, hipStream_t s);
+size_t gram_partial_bytes(int64_t n, int64_t d, int dtype);
+// g (d x d) = Dc X^T X Dc with Dc = diag(col_scale (FP8) * dscale); FP32
+// input on the FP64 MFMA (exact products, FP64 sums), BF16/FP8 on the BF16
+// MFMA (exact products, FP32 sums within row chunks, FP64 across them)
+void launch_gram(const void* x, int dtype, int64_t n, int64_t d, int64_t ld,
+                 const float* col_scale, const double* dscale, void* scratch,
+                 double* g, hipStream_t s);
+// out[j * n + i] = FP32 Gaussian sketch entry G[j][row0 + i]
+void launch_gauss_entries(uint64_t seed, int64_t r, int64_t n, int64_t row0,
+                          float* out, hipStream_t s);
+
+// ---- Cholesky refinement (k_chol.hip) ----------------------------------------
+// Solve R^T X = B in place (R upper triangular d x d, B d x k).
+void solve_upper_trans(const double* r, int64_t d, double* b, int64_t k,
+                       hipStream_t s);
+void launch_transpose(const double* a, int64_t d, double* out, hipStream_t s);
+// Upper Cholesky factor of symmetric positive definite g (d x d, overwritten)
+// into r (zeros below the diagonal); *flag (device int) set to 1 on a
+// non-positive pivot.
+void cholesky(double* g, int64_t d, double* r, int* flag, hipStream_t s);
+// c = a b for upper-triangular a, b (d x d)
+void launch_trmm_upper(const double* a, const double* b, int64_t d, double* c,
+                       hipStream_t s);
 
 // ---- scoring (k_score.hip) ---------------------------------------------------
 void launch_scores(const void* x, int dtype, int format, int64_t n, int64_t d,

@@ -31,6 +31,13 @@ struct Ld<uint16_t> {
   }
 };
 template <>
+struct Ld<uint8_t> {  // FP8-e4m3 code; the column scale is folded into M
+  using acc = float;
+  __device__ static float get(const uint8_t* p, int64_t i) {
+    return e4m3_to_f32(p[i]);
+  }
+};
+template <>
 struct Ld<double> {
   using acc = double;
   __device__ static double get(const double* p, int64_t i) { return p[i]; }
@@ -186,6 +193,12 @@ void launch_scores(const void* x, int dtype, int format, int64_t n, int64_t d,
       prof_begin(kKScore, s);
       score_dense_kernel<float, float><<<grid, 256, 0, s>>>(
           static_cast<const float*>(x), n, d, ld, m32, k, part, scores);
+      prof_end(kKScore, s);
+      break;
+    case 3:
+      prof_begin(kKScore, s);
+      score_dense_kernel<uint8_t, float><<<grid, 256, 0, s>>>(
+          static_cast<const uint8_t*>(x), n, d, ld, m32, k, part, scores);
       prof_end(kKScore, s);
       break;
     case 2:

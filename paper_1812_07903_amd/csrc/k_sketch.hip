@@ -32,6 +32,12 @@ struct Elem<uint16_t> {
     return static_cast<double>(bf16_to_f32(p[i]));
   }
 };
+template <>
+struct Elem<uint8_t> {  // FP8-e4m3 code (the column scale is applied apart)
+  __device__ static double get(const uint8_t* p, int64_t i) {
+    return static_cast<double>(e4m3_to_f32(p[i]));
+  }
+};
 
 __global__ void fill_u64_kernel(uint64_t* p, int64_t n, uint64_t v) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -42,15 +48,17 @@ template <typename T>
 __global__ void __launch_bounds__(256)
     colmax_dense_kernel(const T* __restrict__ x, int64_t n, int64_t d,
                         int64_t ld, int64_t rows_per_block,
-                        unsigned long long* __restrict__ colmax, int* nonfinite) {
+                        unsigned long long* __restrict__ colmax, int* nonfinite,
+                        const float* __restrict__ col_scale) {
   const int64_t col = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (col >= d) return;
+  const double cs = col_scale ? fabs(static_cast<double>(col_scale[col])) : 1.0;
   const int64_t r0 = static_cast<int64_t>(blockIdx.y) * rows_per_block;
   const int64_t r1 = r0 + rows_per_block < n ? r0 + rows_per_block : n;
   double m = 0.0;
   bool bad = false;
   for (int64_t row = r0; row < r1; ++row) {
-    const double v = fabs(Elem<T>::get(x, row * ld + col));
+    const double v = fabs(Elem<T>::get(x, row * ld + col)) * cs;
     bad |= !isfinite(v);
     m = fmax(m, v);
   }
@@ -180,11 +188,24 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+__global__ void mul_scale_kernel(const double* __restrict__ a,
+                                 const float* __restrict__ b, int64_t d,
+                                 double* __restrict__ out) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < d) out[j] = (a ? a[j] : 1.0) * static_cast<double>(b[j]);
+}
+
 inline unsigned grid1(int64_t n, int t) {
   return static_cast<unsigned>((n + t - 1) / t);
 }
 
 }  // namespace
+
+void launch_mul_scale(const double* a, const float* b, int64_t d, double* out,
+                      hipStream_t s) {
+  if (d <= 0) return;
+  mul_scale_kernel<<<grid1(d, 256), 256, 0, s>>>(a, b, d, out);
+}
 
 void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
   if (n <= 0) return;
@@ -196,7 +217,6 @@ void launch_colmax(const void* x, int dtype, int format, int64_t n, int64_t d,
                    int64_t nnz, const float* col_scale, const float* row_scale,
                    uint64_t* colmax_bits, int* nonfinite, hipStream_t s) {
   (void)row_ptr;
-  (void)col_scale;
   (void)row_scale;
   auto* cm = reinterpret_cast<unsigned long long*>(colmax_bits);
   if (format == 1) {  // CSR, FP32 values
@@ -217,19 +237,26 @@ void launch_colmax(const void* x, int dtype, int format, int64_t n, int64_t d,
     case 0:
       prof_begin(kKColmax, s);
       colmax_dense_kernel<double><<<grid, 256, 0, s>>>(
-          static_cast<const double*>(x), n, d, ld, rpb, cm, nonfinite);
+          static_cast<const double*>(x), n, d, ld, rpb, cm, nonfinite, nullptr);
       prof_end(kKColmax, s);
       break;
     case 1:
       prof_begin(kKColmax, s);
       colmax_dense_kernel<float><<<grid, 256, 0, s>>>(
-          static_cast<const float*>(x), n, d, ld, rpb, cm, nonfinite);
+          static_cast<const float*>(x), n, d, ld, rpb, cm, nonfinite, nullptr);
+      prof_end(kKColmax, s);
+      break;
+    case 3:
+      prof_begin(kKColmax, s);
+      colmax_dense_kernel<uint8_t><<<grid, 256, 0, s>>>(
+          static_cast<const uint8_t*>(x), n, d, ld, rpb, cm, nonfinite,
+          col_scale);
       prof_end(kKColmax, s);
       break;
     case 2:
       prof_begin(kKColmax, s);
       colmax_dense_kernel<uint16_t><<<grid, 256, 0, s>>>(
-          static_cast<const uint16_t*>(x), n, d, ld, rpb, cm, nonfinite);
+          static_cast<const uint16_t*>(x), n, d, ld, rpb, cm, nonfinite, nullptr);
       prof_end(kKColmax, s);
       break;
     default:
@@ -280,6 +307,13 @@ void launch_countsketch(const void* x, int dtype, int format, int64_t n,
       prof_begin(kKSketch, s);
       countsketch_dense_kernel<uint16_t><<<grid, 256, 0, s>>>(
           static_cast<const uint16_t*>(x), d, ld, sorted_vals, offsets, r,
+          dscale, sx);
+      prof_end(kKSketch, s);
+      break;
+    case 3:
+      prof_begin(kKSketch, s);
+      countsketch_dense_kernel<uint8_t><<<grid, 256, 0, s>>>(
+          static_cast<const uint8_t*>(x), d, ld, sorted_vals, offsets, r,
           dscale, sx);
       prof_end(kKSketch, s);
       break;

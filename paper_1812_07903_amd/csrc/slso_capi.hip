@@ -2,6 +2,7 @@
 // workspace, and the order of stages of the sketched leverage path
 // (Algorithms 2 and 3 in QR form with the second projection Pi_2, and the
 // "dec" ordering of Sec. 5.2).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -167,11 +168,19 @@ int validate_matrix(slso_ctx* c, const slso_matrix* X) {
   if (X->n >= (static_cast<int64_t>(1) << 31))
     return set_err(c, SLSO_EINVAL, "n must be < 2^31");
   if (!X->values) return set_err(c, SLSO_EINVAL, "X->values is NULL");
+  if (X->row_scale)
+    return set_err(c, SLSO_EUNSUPPORTED, "row_scale is not provided");
+  if (X->dtype == SLSO_FP8_E4M3) {
+    if (!X->col_scale)
+      return set_err(c, SLSO_EUNSUPPORTED, "FP8 input needs col_scale");
+  } else if (X->col_scale) {
+    return set_err(c, SLSO_EINVAL, "col_scale is only read for FP8 input");
+  }
   if (X->format == SLSO_DENSE) {
     if (X->ld < X->d) return set_err(c, SLSO_EINVAL, "ld must be >= d");
-    if (X->dtype != SLSO_F64 && X->dtype != SLSO_F32 && X->dtype != SLSO_BF16)
-      return set_err(c, SLSO_EUNSUPPORTED,
-                     "dense input must be F64, F32 or BF16 on this path");
+    if (X->dtype != SLSO_F64 && X->dtype != SLSO_F32 &&
+        X->dtype != SLSO_BF16 && X->dtype != SLSO_FP8_E4M3)
+      return set_err(c, SLSO_EINVAL, "unknown dtype");
   } else if (X->format == SLSO_CSR) {
     if (!X->row_ptr || !X->col_idx)
       return set_err(c, SLSO_EINVAL, "CSR needs row_ptr and col_idx");
@@ -182,6 +191,14 @@ int validate_matrix(slso_ctx* c, const slso_matrix* X) {
     return set_err(c, SLSO_EINVAL, "unknown format");
   }
   return SLSO_OK;
+}
+
+// The Gaussian sketch and the Gram pass of the refinement run on MFMA for
+// dense F32, BF16 and FP8 input.
+bool mfma_input(const slso_matrix* X) {
+  return X->format == SLSO_DENSE &&
+         (X->dtype == SLSO_F32 || X->dtype == SLSO_BF16 ||
+          X->dtype == SLSO_FP8_E4M3);
 }
 
 struct SketchBufs {
@@ -292,6 +309,13 @@ int slso_gaussian(uint64_t seed, int32_t stream_id, int64_t rows, int64_t cols,
   return hipGetLastError() == hipSuccess ? SLSO_OK : SLSO_EDEVICE;
 }
 
+int slso_gaussian_sketch_entries(uint64_t seed, int64_t r, int64_t row0,
+                                 int64_t n, float* out, void* stream) {
+  if (r < 0 || n < 0 || row0 < 0 || (r * n > 0 && !out)) return SLSO_EINVAL;
+  launch_gauss_entries(seed, r, n, row0, out, static_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? SLSO_OK : SLSO_EDEVICE;
+}
+
 int slso_sketch(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
                 const slso_options* opt, double* sx, void* stream) {
   if (!c) return SLSO_EINVAL;
@@ -301,16 +325,34 @@ int slso_sketch(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
     return set_err(c, SLSO_EINVAL, "need d <= r < 2^31");
   if (!sx) return set_err(c, SLSO_EINVAL, "sx is NULL");
   const int kind = opt ? opt->sketch : SLSO_COUNTSKETCH;
-  if (kind != SLSO_COUNTSKETCH)
-    return set_err(c, SLSO_EUNSUPPORTED, "sketch kind not provided");
+  if (kind != SLSO_COUNTSKETCH && kind != SLSO_GAUSSIAN)
+    return set_err(c, SLSO_EINVAL, "unknown sketch kind");
+  if (kind == SLSO_GAUSSIAN && !mfma_input(X))
+    return set_err(c, SLSO_EUNSUPPORTED,
+                   "the Gaussian sketch takes dense F32, BF16 or FP8 input");
   SLSO_HIP(c, hipSetDevice(c->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   Sizer z;
-  size_sketch_bufs(z, X->n, r);
+  if (kind == SLSO_COUNTSKETCH) {
+    size_sketch_bufs(z, X->n, r);
+    z.take<double>(X->d);
+  } else {
+    z.take<char>(gauss_partial_bytes(X->n, r, X->d));
+  }
   if ((st = ensure_ws(c, z.off))) return st;
   Arena a{static_cast<char*>(c->ws)};
-  SketchBufs b = take_sketch_bufs(a, X->n, r);
-  enqueue_countsketch(X, seed, r, b, nullptr, sx, s);
+  if (kind == SLSO_COUNTSKETCH) {
+    SketchBufs b = take_sketch_bufs(a, X->n, r);
+    double* cs = a.take<double>(X->d);
+    if (X->dtype == SLSO_FP8_E4M3)
+      launch_mul_scale(nullptr, X->col_scale, X->d, cs, s);
+    enqueue_countsketch(X, seed, r, b,
+                        X->dtype == SLSO_FP8_E4M3 ? cs : nullptr, sx, s);
+  } else {
+    float* part = a.take<float>(gauss_partial_bytes(X->n, r, X->d) / 4);
+    launch_gauss_sketch(X->values, X->dtype, X->n, X->d, X->ld, X->col_scale,
+                        seed, r, nullptr, part, sx, s);
+  }
   return check_launch(c, "slso_sketch");
 }
 
@@ -346,13 +388,18 @@ int slso_scores(slso_ctx* c, const slso_matrix* X, const double* m, int64_t k,
   SLSO_HIP(c, hipSetDevice(c->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   Sizer z;
+  z.take<double>(X->d);
   z.take<float>(X->d * k);
   z.take<char>(scores_partial_bytes(X->n, k, X->format));
   if ((st = ensure_ws(c, z.off))) return st;
   Arena a{static_cast<char*>(c->ws)};
+  double* cs = a.take<double>(X->d);
   float* m32 = a.take<float>(X->d * k);
   double* part = a.take<double>(scores_partial_bytes(X->n, k, X->format) / 8);
-  launch_scale_rows(m, nullptr, X->d, k, nullptr, m32, s);
+  // FP8 codes: the column scales are folded into the rows of M
+  const bool fp8 = X->dtype == SLSO_FP8_E4M3;
+  if (fp8) launch_mul_scale(nullptr, X->col_scale, X->d, cs, s);
+  launch_scale_rows(m, fp8 ? cs : nullptr, X->d, k, nullptr, m32, s);
   launch_scores(X->values, X->dtype, X->format, X->n, X->d, X->ld, X->row_ptr,
                 X->col_idx, X->col_scale, X->row_scale, m, m32, k, scores, s,
                 part);
@@ -371,9 +418,17 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   if (!scores) return set_err(c, SLSO_EINVAL, "scores is NULL");
   slso_options o{};
   if (opt) o = *opt;
-  if (o.sketch != SLSO_COUNTSKETCH)
-    return set_err(c, SLSO_EUNSUPPORTED, "sketch kind not provided");
-  if (o.refine) return set_err(c, SLSO_EUNSUPPORTED, "refinement not provided");
+  if (o.sketch != SLSO_COUNTSKETCH && o.sketch != SLSO_GAUSSIAN)
+    return set_err(c, SLSO_EINVAL, "unknown sketch kind");
+  if (o.refine != 0 && o.refine != 1)
+    return set_err(c, SLSO_EINVAL, "refine must be 0 or 1");
+  const bool gauss = o.sketch == SLSO_GAUSSIAN;
+  const bool refine = o.refine == 1;
+  if ((gauss || refine) && !mfma_input(X))
+    return set_err(c, SLSO_EUNSUPPORTED,
+                   "the Gaussian sketch and the refinement take dense F32, "
+                   "BF16 or FP8 input");
+  const bool fp8 = X->dtype == SLSO_FP8_E4M3;
   const double tol = o.rank_tol == 0.0 ? 1e-10 : o.rank_tol;
   const int64_t n = X->n, d = X->d;
   const int64_t kk = k == 0 ? d : k;
@@ -381,29 +436,46 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   hipStream_t s = static_cast<hipStream_t>(stream);
 
   // workspace plan
+  const size_t gemm_part =
+      gauss ? std::max(gauss_partial_bytes(n, r, d),
+                       refine ? gram_partial_bytes(n, d, X->dtype) : size_t{0})
+            : (refine ? gram_partial_bytes(n, d, X->dtype) : size_t{0});
   Sizer z;
-  size_sketch_bufs(z, n, r);
+  if (!gauss) size_sketch_bufs(z, n, r);
   z.take<uint64_t>(d);             // colmax bits
-  z.take<double>(d);               // dscale
+  z.take<double>(d);               // dscale D
+  z.take<double>(d);               // D * col_scale (FP8)
   z.take<int>(64);                 // flags
-  z.take<double>(4);               // diag stats
+  z.take<double>(8);               // diag stats
   z.take<double>(r * d);           // sketch
+  z.take<char>(gemm_part);         // split-K partial sums
   z.take<char>(qr_scratch_bytes(r, d));
-  z.take<double>(d * d);           // R_D
+  z.take<double>(d * d);           // R_D of the sketch
+  if (refine)
+    for (int i = 0; i < 3; ++i) z.take<double>(d * d);  // G, R1, refined R
   z.take<double>(d * kk);          // Pi_2 -> M'
   z.take<double>(d * kk);          // M (FP64)
   z.take<float>(d * kk);           // M (FP32)
   z.take<char>(scores_partial_bytes(n, kk, X->format));
   if ((st = ensure_ws(c, z.off))) return st;
   Arena a{static_cast<char*>(c->ws)};
-  SketchBufs sb = take_sketch_bufs(a, n, r);
+  SketchBufs sb{};
+  if (!gauss) sb = take_sketch_bufs(a, n, r);
   uint64_t* colmax = a.take<uint64_t>(d);
   double* dscale = a.take<double>(d);
+  double* eff = a.take<double>(d);
   int* flags = a.take<int>(64);
-  double* dstat = a.take<double>(4);
+  double* dstat = a.take<double>(8);
   double* sx = a.take<double>(r * d);
+  void* gpart = a.take<char>(gemm_part);
   void* qws = a.take<char>(qr_scratch_bytes(r, d));
-  double* R = a.take<double>(d * d);
+  double* RS = a.take<double>(d * d);
+  double *G = nullptr, *R1 = nullptr, *RR = nullptr;
+  if (refine) {
+    G = a.take<double>(d * d);
+    R1 = a.take<double>(d * d);
+    RR = a.take<double>(d * d);
+  }
   double* pi = a.take<double>(d * kk);
   double* m64 = a.take<double>(d * kk);
   float* m32 = a.take<float>(d * kk);
@@ -415,24 +487,60 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   launch_colmax(X->values, X->dtype, X->format, n, d, X->ld, X->row_ptr,
                 X->col_idx, X->nnz, X->col_scale, X->row_scale, colmax, flags, s);
   launch_colscale(colmax, d, dscale, s);
-  // 2. CountSketch of X D (Algorithm 2 step 1)
-  enqueue_countsketch(X, seed, r, sb, dscale, sx, s);
+  // per-column factor applied to stored values: D, times the FP8 scales
+  const double* rowfac = dscale;
+  if (fp8) {
+    launch_mul_scale(dscale, X->col_scale, d, eff, s);
+    rowfac = eff;
+  }
+  // 2. sketch of X D (Algorithm 2 step 1)
+  if (gauss)
+    launch_gauss_sketch(X->values, X->dtype, n, d, X->ld, X->col_scale, seed,
+                        r, dscale, static_cast<float*>(gpart), sx, s);
+  else
+    enqueue_countsketch(X, seed, r, sb, rowfac, sx, s);
   // 3. Householder QR of the sketch (Algorithm 2 step 2, QR form)
-  qr_factor(sx, r, d, R, qws, s);
-  launch_diag_stats(R, d, dstat, s);
+  qr_factor(sx, r, d, RS, qws, s);
+  launch_diag_stats(RS, d, dstat, s);
+  // 3b. refinement: G = (X D)^T (X D); G' = R_S^-T G R_S^-1 = R1^T R1;
+  //     R = R1 R_S is the R factor of X D
+  if (refine) {
+    launch_gram(X->values, X->dtype, n, d, X->ld, X->col_scale, dscale, gpart,
+                G, s);
+    solve_upper_trans(RS, d, G, d, s);     // W = R_S^-T G
+    launch_transpose(G, d, R1, s);         // W^T
+    solve_upper_trans(RS, d, R1, d, s);    // R_S^-T W^T = G'
+    cholesky(R1, d, G, flags + 1, s);      // G (reused) = R1
+    launch_trmm_upper(G, RS, d, RR, s);    // R = R1 R_S
+    launch_diag_stats(RR, d, dstat + 2, s);
+  }
   if ((st = check_launch(c, "slso_leverage: sketch/QR"))) return st;
   // 4. rank screen read-back
   char* hb = static_cast<char*>(c->host_buf);
-  SLSO_HIP(c, hipMemcpyAsync(hb, dstat, 2 * sizeof(double),
+  SLSO_HIP(c, hipMemcpyAsync(hb, dstat, 4 * sizeof(double),
                              hipMemcpyDeviceToHost, s));
-  SLSO_HIP(c, hipMemcpyAsync(hb + 64, flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  SLSO_HIP(c, hipMemcpyAsync(hb + 64, flags, 2 * sizeof(int),
+                             hipMemcpyDeviceToHost, s));
   SLSO_HIP(c, hipStreamSynchronize(s));
-  double dmin, dmax;
-  int nonfinite;
-  std::memcpy(&dmin, hb, 8);
-  std::memcpy(&dmax, hb + 8, 8);
-  std::memcpy(&nonfinite, hb + 64, sizeof(int));
-  if (nonfinite) return set_err(c, SLSO_ENONFINITE, "X holds Inf or NaN");
+  double ds[4];
+  int fl[2];
+  std::memcpy(ds, hb, sizeof(ds));
+  std::memcpy(fl, hb + 64, sizeof(fl));
+  if (fl[0]) return set_err(c, SLSO_ENONFINITE, "X holds Inf or NaN");
+  int32_t info_flags = 0;
+  const double* R = RS;
+  double dmin = ds[0], dmax = ds[1];
+  if (refine) {
+    const bool ok = fl[1] == 0 && std::isfinite(ds[2]) && std::isfinite(ds[3]);
+    if (ok) {
+      R = RR;
+      dmin = ds[2];
+      dmax = ds[3];
+      info_flags |= SLSO_INFO_REFINED;
+    } else {
+      info_flags |= SLSO_INFO_REFINE_FAILED;
+    }
+  }
   bool full = true;
   if (tol >= 0.0) full = dmax > 0.0 && dmin > std::sqrt(tol) * dmax;
   // 5. Pi_2 and M = D pinv(R_D) Pi_2 (Algorithm 2 step 3 / Algorithm 3 step 4)
@@ -444,7 +552,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   int64_t rank = d;
   if (full) {
     solve_upper(R, d, pi, kk, s);
-    launch_scale_rows(pi, dscale, d, kk, m64, m32, s);
+    launch_scale_rows(pi, rowfac, d, kk, m64, m32, s);
   } else {
     Sizer jz;
     jz.take<char>(jacobi_scratch_bytes(d, kk));
@@ -455,7 +563,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
     }
     if (jacobi_truncated_apply(R, d, pi, kk, tol, m64, &rank, sx, s) != 0)
       return set_err(c, SLSO_EDEVICE, "Jacobi SVD failed");
-    launch_scale_rows(m64, dscale, d, kk, pi, m32, s);
+    launch_scale_rows(m64, rowfac, d, kk, pi, m32, s);
     m64 = pi;
   }
   // 6. scores l_i = ||x_i M||^2 (Algorithm 2 step 4)
@@ -466,7 +574,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   if (info) {
     info->rank = rank;
     info->screen_full = full ? 1 : 0;
-    info->flags = 0;
+    info->flags = info_flags;
     info->diag_min = dmin;
     info->diag_max = dmax;
   }
@@ -531,7 +639,7 @@ const char* slso_profile_name(int id) {
   static const char* names[] = {
       "hash_pack", "sort_hist", "sort_scan", "sort_scatter", "bucket_offsets",
       "colmax", "countsketch", "qr_node", "qr_update", "qr_extract", "trsm",
-      "score", "gaussian"};
+      "score", "gaussian", "gauss_sketch", "gram", "cholesky"};
   if (id < 0 || id >= slso::kKCount) return "";
   return names[id];
 }

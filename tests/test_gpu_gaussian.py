@@ -1,0 +1,206 @@
+"""GPU parity of the Gaussian sketch, the FP8 input path and the Cholesky-QR
+refinement against the CPU oracle, through the C ABI (gfx950).
+
+Tolerances:
+* generator entries: bit-exact (both sides evaluate the same sequence of
+  separately rounded FP32 operations);
+* Gaussian sketch: the GPU sums exact BF16 (or FP32) products in FP32 within
+  row chunks of at most 65536 rows and in FP64 across chunks; the oracle sums
+  in FP64. The error bound used is 1e-4 of sum_i |g_ji x_ic| / sqrt(r), about
+  25x the random-walk estimate sqrt(n / 16) 2^-24 at n = 66000;
+* refined scores: the spec bar for the reduced-precision path, max
+  relative error <= 1e-2 and Kendall tau >= 0.99 against the FP64 oracle;
+  observed errors are far smaller and are printed.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import leverage as olv
+from oracle import metrics as omet
+from oracle import sketch as osk
+from oracle import streams as ost
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def slso():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1812_07903_amd as m
+    m.load_library()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(slso):
+    c = slso.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _report(name, got, ref, extra=""):
+    err = omet.max_rel_err(got, ref)
+    print(f"[{name}] max_rel={err:.3e} {extra}", flush=True)
+    return err
+
+
+def as_input(slso, x64, kind):
+    """(device input, FP64 values it stands for, oracle generator precision)."""
+    if kind == "f32":
+        x32 = x64.astype(np.float32)
+        return dev(x32), x32.astype(np.float64), "f32"
+    if kind == "bf16":
+        b = synth.to_bf16_bits(x64)
+        t = dev(b.view(np.int16)).view(torch.bfloat16)
+        return t, synth.bf16_bits_to_f64(b), "bf16"
+    if kind == "fp8":
+        codes, cs = synth.to_fp8_e4m3(x64)
+        return (slso.Fp8Matrix(dev(codes), dev(cs)),
+                synth.fp8_e4m3_to_f64(codes, cs), "bf16")
+    raise ValueError(kind)
+
+
+# ---- generator -----------------------------------------------------------------
+@pytest.mark.parametrize("seed,r,row0,n", [
+    (0, 1, 0, 1), (11, 7, 0, 4099), (2025, 300, 3, 1001),
+    (2**63 + 5, 33, 2**33 + 17, 517), (1003, 2048, 123457, 64)])
+def test_gaussian_sketch_entries_bit_exact(slso, seed, r, row0, n):
+    g = host(slso.gaussian_sketch_entries(seed, r, n, row0=row0))
+    ref = ost.gaussian_sketch_matrix_f32(seed, r, n, row0=row0)
+    assert g.dtype == np.float32
+    assert np.array_equal(g.view(np.uint32), ref.view(np.uint32))
+
+
+# ---- sketch ----------------------------------------------------------------------
+@pytest.mark.parametrize("kind,n,d,r", [
+    ("f32", 3001, 40, 300), ("bf16", 3001, 40, 300), ("fp8", 2999, 37, 257),
+    ("bf16", 66000, 33, 257), ("f32", 520, 300, 520)])
+def test_gaussian_sketch_matches_oracle(slso, ctx, kind, n, d, r):
+    rng = np.random.default_rng(n + d)
+    x64 = rng.standard_normal((n, d)) * np.exp(rng.standard_normal(n))[:, None]
+    xin, xval, prec = as_input(slso, x64, kind)
+    sx = host(ctx.sketch(xin, 99, r, sketch=slso.GAUSSIAN))
+    g = (ost.gaussian_sketch_matrix_f32(99, r, n) if prec == "f32"
+         else ost.gaussian_sketch_matrix_bf16(99, r, n)).astype(np.float64)
+    ref = osk.gaussian_sketch_dense(xval, 99, r, g=g)
+    bound = 1e-4 * (np.abs(g) @ np.abs(xval)) / math.sqrt(r)
+    err = np.abs(sx - ref)
+    print(f"[gsketch {kind} {n}x{d} r={r}] max err/bound = "
+          f"{(err / bound).max():.3e}", flush=True)
+    assert np.all(err <= bound)
+
+
+def test_fp8_countsketch_matches_oracle(slso, ctx):
+    x64 = synth.config0(n=5000, d=48, seed=5)
+    xin, xval, _ = as_input(slso, x64, "fp8")
+    sx = host(ctx.sketch(xin, 3, 1024))
+    ref = osk.countsketch_dense(xval, 3, 1024)
+    # per-bucket FP64 sums of codes, scaled once: rounding-level difference
+    scale = osk.countsketch_dense(np.abs(xval), 3, 1024) + 1e-300
+    assert np.max(np.abs(sx - ref) / scale) < 1e-14
+
+
+# ---- leverage with the Gaussian sketch (no refinement) -------------------------
+@pytest.mark.parametrize("kind", ["f32", "bf16"])
+def test_gaussian_leverage_matches_sketched_oracle(slso, ctx, kind):
+    x64 = synth.config0(n=20000, d=64, seed=21)
+    xin, xval, prec = as_input(slso, x64, kind)
+    got, info = ctx.leverage(xin, 8, 512, 32, sketch=slso.GAUSSIAN)
+    got = host(got)
+    ref = olv.sketched_leverage(xval, 8, 512, 32, kind="gaussian",
+                                precision=prec)
+    assert info["rank"] == ref["rank"] == 64
+    assert not info["refined"]
+    err = _report(f"gauss lev {kind}", got, ref["scores"])
+    # sketch entries differ from the FP64 sums by ~1e-6 relative; R and the
+    # scores inherit that times the conditioning of the equilibrated sketch
+    assert err < 1e-3
+
+
+def test_fp8_countsketch_leverage(slso, ctx):
+    x64 = synth.config0(n=20000, d=64, seed=22)
+    xin, xval, _ = as_input(slso, x64, "fp8")
+    got, info = ctx.leverage(xin, 4, 4096, 32)
+    got = host(got)
+    ref = olv.sketched_leverage(xval, 4, 4096, 32)
+    assert info["rank"] == ref["rank"]
+    assert _report("fp8 countsketch lev", got, ref["scores"]) < 1e-5
+
+
+# ---- refinement ---------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def precision_case():
+    """Reduced-size precision workload (rank 256 in d = 512, sigma_j = j^-1.5,
+    noise 1e-4, row scales e^N(0, 1.5^2)) with n = 100000."""
+    return synth.precision_dense(n=100000, d=512, seed=1003)
+
+
+@pytest.mark.parametrize("kind,sketch,k", [
+    ("bf16", "gaussian", 64), ("fp8", "gaussian", 64), ("f32", "gaussian", 0),
+    ("bf16", "countsketch", 64)])
+def test_refined_leverage_vs_fp64_oracle(slso, ctx, precision_case, kind,
+                                         sketch, k):
+    xin, xval, _ = as_input(slso, precision_case, kind)
+    sk = slso.GAUSSIAN if sketch == "gaussian" else slso.COUNTSKETCH
+    r = 2048 if sketch == "gaussian" else 8192
+    got, info = ctx.leverage(xin, 31, r, k, sketch=sk, refine=True)
+    got = host(got)
+    assert info["refined"], info
+    ref = olv.sketched_leverage(xval, 31, r, k, refine=True)
+    err = omet.max_rel_err(got, ref["scores"])
+    tau = omet.kendall_tau(got, ref["scores"])
+    print(f"[refined {kind} {sketch} k={k}] max_rel={err:.3e} tau={tau:.6f}",
+          flush=True)
+    assert info["rank"] == ref["rank"]
+    assert err <= 1e-2 and tau >= 0.99
+
+
+def test_refined_countsketch_f32_image_like(slso, ctx):
+    x = synth.image_like(20000, 784, seed=44).astype(np.float32)
+    got, info = ctx.leverage(dev(x), 6, 16384, 64, refine=True)
+    got = host(got)
+    ref = olv.sketched_leverage(x.astype(np.float64), 6, 16384, 64,
+                                refine=True)
+    assert info["refined"]
+    err = _report("refined image-like f32", got, ref["scores"])
+    assert err <= 1e-2 and omet.kendall_tau(got, ref["scores"]) >= 0.99
+
+
+def test_refine_falls_back_on_rank_deficient_input(slso, ctx):
+    """A zero column makes X D rank deficient: the refinement reports failure
+    and the sketch factor with its truncation is used, so the scores equal
+    those of the unrefined call."""
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((6000, 40)).astype(np.float32)
+    x[:, 17] = 0.0
+    xt = dev(x)
+    got, info = ctx.leverage(xt, 2, 512, 16, sketch=slso.GAUSSIAN, refine=True)
+    base, binfo = ctx.leverage(xt, 2, 512, 16, sketch=slso.GAUSSIAN)
+    assert info["flags"] == slso.INFO_REFINE_FAILED
+    assert info["rank"] == binfo["rank"] == 39
+    assert np.array_equal(host(got), host(base))
+
+
+def test_gaussian_rejects_unsupported_inputs(slso, ctx):
+    x = dev(np.zeros((100, 4)))
+    with pytest.raises(slso.SlsoError) as e:
+        ctx.leverage(x, 1, 16, 4, sketch=slso.GAUSSIAN)
+    assert e.value.status == slso.EUNSUPPORTED
+    with pytest.raises(slso.SlsoError) as e:
+        ctx.leverage(x, 1, 16, 4, refine=True)
+    assert e.value.status == slso.EUNSUPPORTED
