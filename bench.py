@@ -49,8 +49,46 @@ def qr_node_flops(m: int, d: int, w: int = 16) -> float:
     return f
 
 
+# profiler name -> (kernel symbol in the PMC summary, source file)
+KERNEL_SRC = {
+    "qr_node": ("qr_node_kernel", "k_qr.hip"),
+    "qr_update": ("qr_update_kernel", "k_qr.hip"),
+    "score": ("score_dense_kernel<float,float>", "k_score.hip"),
+    "countsketch": ("countsketch_dense_kernel<float>", "k_sketch.hip"),
+    "colmax": ("colmax_dense_kernel<float>", "k_sketch.hip"),
+}
+PMC_SUMMARY = os.path.join(ROOT, "profiles",
+                           "pmc_traffic_image_like_n60000_d784.txt")
+
+
+def measured_traffic(name: str):
+    """Calibrated HBM bytes per launch from the committed rocprofv3 PMC
+    summary, or None when there is none or the kernel's source has changed
+    since the counters were taken."""
+    import hashlib
+    if name not in KERNEL_SRC or not os.path.exists(PMC_SUMMARY):
+        return None
+    sym, src = KERNEL_SRC[name]
+    path = os.path.join(ROOT, "paper_1812_07903_amd", "csrc", src)
+    with open(path, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    with open(PMC_SUMMARY) as f:
+        for line in f:
+            t = line.split()
+            if len(t) == 8 and t[0] == "traffic" and t[1] == sym:
+                return float(t[7]) if t[2] == src and t[3] == sha else None
+    return None
+
+
 def roofline_for(name: str, ms_per_launch: float, launches_per_step: float):
     """Algorithmic work per launch of a kernel at this workload."""
+    r = _roofline(name, ms_per_launch, launches_per_step)
+    if r is not None:
+        r["traffic"] = measured_traffic(name)
+    return r
+
+
+def _roofline(name: str, ms_per_launch: float, launches_per_step: float):
     sec = ms_per_launch * 1e-3
     if name == "qr_update":
         flops = qr_update_flops(R, D) / launches_per_step
@@ -68,11 +106,33 @@ def roofline_for(name: str, ms_per_launch: float, launches_per_step: float):
         return {"bound": "alu", "achieved": a / 1e12, "peak": PEAK["fp32"] / 1e12,
                 "unit": "TFLOP/s", "frac": a / PEAK["fp32"], "traffic": None}
     if name == "countsketch":
+        # X once, the sketch written once, the sorted row list once
         byts = (N * D * 4 + R * D * 8 + N * 4) / launches_per_step
         a = byts / sec
         return {"bound": "hbm", "achieved": a / 1e9, "peak": PEAK["hbm"] / 1e9,
                 "unit": "GB/s", "frac": a / PEAK["hbm"], "traffic": None}
+    if name == "colmax":
+        byts = N * D * 4 / launches_per_step
+        a = byts / sec
+        return {"bound": "hbm", "achieved": a / 1e9, "peak": PEAK["hbm"] / 1e9,
+                "unit": "GB/s", "frac": a / PEAK["hbm"], "traffic": None}
     return None
+
+
+def copy_calibration(mib: int) -> int:
+    """A plain elementwise copy y = 1.0 * x of known size, five launches."""
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.rand(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4,
+                      "copy_calibration_bytes_written": n * 4,
+                      "launches": 5}), flush=True)
+    return 0
 
 
 def main() -> int:
@@ -81,7 +141,13 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times "
+                         "(reads MIB, writes MIB per launch): the reference "
+                         "kernel for scaling HBM byte counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the leverage path runs on a "
@@ -167,6 +233,11 @@ def main() -> int:
         "perm_matches_stable_sort": perm_ok,
         "kernels": kernels,
         "roofline": dict(kernel=dname, **roof) if roof else None,
+        "roofline_other": {
+            k: dict(kernel=k, **rr) for k in ("countsketch", "score", "colmax")
+            if k in prof and prof[k][1] > 0 and k != dname
+            for rr in [roofline_for(k, prof[k][0] / prof[k][1],
+                                    prof[k][1] / args.steps)] if rr},
     }
 
     if not args.no_cpu_baseline:

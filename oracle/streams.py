@@ -23,6 +23,16 @@ library) are:
   For the sketch S (r x n), a is the row index of X and b the sketch row; for
   Pi_2 (d x k), a is the row of Pi_2 and b its column.
 
+* FP32 Gaussian sketch entry G[j][i] (``gaussian_f32``; stream 3): one
+  Philox block per four consecutive data rows, counter (lo32(q), hi32(q), j, 3)
+  with q = i >> 2, words (0, 1) for i mod 4 in {0, 1} and (2, 3) otherwise;
+  u1 = ((w >> 8) + 1) 2^-24, u2 = (w' >> 8) 2^-24; Box-Muller with every step
+  a separately rounded FP32 operation (ln by a degree-7 polynomial after a
+  sqrt(2) range split, sqrt(L) = L rsqrt(L) with the 0x5F3759DF seed and three
+  Newton steps, cos/sin of 2 pi u2 by quadrant: Taylor polynomials at the
+  quadrant's centre rotated by +-sqrt(1/2)); cos for even i, sin for odd i.
+  Reduced-precision inputs take it rounded to BF16 (ties to even).
+
 Stream ids: 1 bucket hash, 2 sign hash, 3 Gaussian sketch, 4 Pi_2.
 """
 from __future__ import annotations
