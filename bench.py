@@ -135,12 +135,105 @@ def copy_calibration(mib: int) -> int:
     return 0
 
 
+def serving_bench(args) -> int:
+    """Continuous serving: jobs arrive as a Poisson stream and are admitted
+    by the library's server (slots under an HBM budget); reports aggregate
+    rows/s and p50/p99 latency from arrival to resident outputs per rate."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1812_07903_amd as slso
+
+    rates = [float(v) for v in args.rates.split(",") if v]
+    t_gen = time.perf_counter()
+    pool = synth.serving_pool(n=args.pool_n)
+    torch.cuda.synchronize()
+    print(f"[serving] pool of {len(pool)} base matrices ready in "
+          f"{time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    per_rate = {}
+    checked = None
+    for rate in rates:
+        jobs = synth.serving_jobs(args.jobs, rate, pool_n=args.pool_n)
+        srv = slso.Server(0, slots=args.slots, hbm_budget=96 << 30)
+        tickets = []
+        t0 = time.perf_counter()
+        for jb in jobs:
+            delay = t0 + jb["arrival_s"] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            x = pool[(jb["d"], jb["dtype"])][jb["row0"]:jb["row0"] + jb["n"]]
+            tickets.append(srv.submit(x, jb["seed"], jb["r"], jb["k"]))
+        res = [srv.wait(t) for t in tickets]
+        stats = srv.stats()
+        srv.close()
+        bad = [r for r in res if r["status"] < 0]
+        lat = np.array([r["latency_ms"] for r in res])
+        span_ms = max(r["end_ms"] for r in res) - min(r["submit_ms"] for r in res)
+        rows = sum(jb["n"] for jb in jobs)
+        per_rate[str(int(rate))] = {
+            "rows_per_s": rows / (span_ms * 1e-3), "jobs": len(jobs),
+            "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)),
+            "max_running": stats["max_running"], "failed": len(bad)}
+        print(f"[serving] rate {rate:g}/s: {per_rate[str(int(rate))]}",
+              file=sys.stderr, flush=True)
+        if checked is None and not args.no_cpu_baseline:
+            # accuracy of the three smallest jobs against the FP64 oracle
+            from oracle import leverage as olv
+            from oracle import metrics as omet
+            errs, taus = [], []
+            for i in sorted(range(len(jobs)), key=lambda i: jobs[i]["n"])[:3]:
+                jb, t = jobs[i], tickets[i]
+                xv = t.x.double().cpu().numpy()
+                ref = olv.sketched_leverage(xv, jb["seed"], jb["r"], jb["k"])
+                got = t.scores.cpu().numpy()
+                errs.append(omet.max_rel_err(got, ref["scores"]))
+                taus.append(omet.kendall_tau(got, ref["scores"]))
+            checked = (max(errs), min(taus))
+        del tickets, res
+    top = per_rate[str(int(rates[-1]))]
+    out = {
+        "metric": "rows/sec leverage-scored at stated rel err vs FP64; "
+                  "p50/p99 job latency",
+        "value": top["rows_per_s"], "unit": "rows/s", "n_gpus": 1,
+        "steps": args.jobs, "warmup": 0,
+        "ms_per_step": None,
+        "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32+bf16", "data": "synthetic",
+        "config": {"workload": "serving: Poisson stream of leverage jobs, n "
+                               "log-uniform [1e4, 2e6], d in {64..1024}, "
+                               "FP32/BF16, CountSketch r=4d..8d, k=32, "
+                               "scores + dec ordering",
+                   "jobs_per_rate": args.jobs, "slots": args.slots,
+                   "pool_rows": args.pool_n},
+        "per_rate": per_rate,
+    }
+    if checked is not None:
+        out["rel_err_vs_fp64"], out["kendall_tau_vs_fp64"] = checked
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("image", "serving"),
+                    default="image",
+                    help="image: the image-like single-job workload (default); "
+                         "serving: a Poisson stream of mixed jobs")
+    ap.add_argument("--rates", default="50,200,800",
+                    help="serving: arrival rates in jobs/s")
+    ap.add_argument("--jobs", type=int, default=1024,
+                    help="serving: jobs per rate")
+    ap.add_argument("--slots", type=int, default=4,
+                    help="serving: concurrent jobs (server slots)")
+    ap.add_argument("--pool-n", type=int, default=2_000_000,
+                    help="serving: rows of each base matrix")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times "
                          "(reads MIB, writes MIB per launch): the reference "
@@ -148,6 +241,12 @@ def main() -> int:
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
+    if args.workload == "serving":
+        if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+            print("bench.py measures one GPU only; run with --gpus 1",
+                  file=sys.stderr)
+            return 2
+        return serving_bench(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the leverage path runs on a "

@@ -179,6 +179,70 @@ int slso_leverage(slso_ctx* ctx, const slso_matrix* X, uint64_t seed,
 int slso_order(slso_ctx* ctx, const float* scores, int64_t n, int32_t* perm,
                void* stream);
 
+/* Device workspace (bytes) a context allocates to run slso_leverage and then
+ * slso_order on X with these arguments; nothing is enqueued. Same argument
+ * checks and error codes as slso_leverage. */
+int slso_workspace_size(const slso_matrix* X, int64_t r, int64_t k,
+                        const slso_options* opt, size_t* bytes);
+
+/* ---- serving --------------------------------------------------------------- */
+/* A server runs leverage-score jobs that arrive at any time.
+ *   - Slots: it has ``slots`` of them, each a context with its own stream and
+ *     worker thread; jobs on different slots overlap on the device.
+ *   - Admission: a queued job starts when a slot is idle and the workspaces
+ *     all slots then hold (slso_workspace_size of their jobs) stay within
+ *     ``hbm_budget`` bytes. Idle slots release their workspaces when the head
+ *     of the queue waits for memory.
+ *   - Order: first in, first out, with backfilling of later jobs that fit,
+ *     at most 2 * slots times past a waiting head.
+ *   - Results: a job's result equals that of the same slso_leverage
+ *     (+ slso_order) call made alone.
+ * The caller keeps X, scores and perm allocated until the job has completed,
+ * and X must hold its final values when the job is submitted (synchronise the
+ * stream that produced it). */
+typedef struct slso_server slso_server;
+
+typedef struct {
+  slso_matrix X;       /* input, as for slso_leverage                       */
+  uint64_t seed;
+  int64_t r, k;
+  slso_options opt;
+  float* scores;       /* (device) n floats                                  */
+  int32_t* perm;       /* (device) n int32 "dec" ordering, or NULL          */
+} slso_job;
+
+typedef struct {
+  int32_t status;      /* slso_leverage / slso_order status of the job       */
+  int32_t slot;        /* slot that ran it                                   */
+  slso_info info;
+  double submit_ms;    /* host steady clock, ms since the server was created */
+  double start_ms;     /* admitted to a slot                                 */
+  double end_ms;       /* outputs resident (the slot's stream synchronised)  */
+} slso_job_result;
+
+typedef struct {
+  int64_t queued, running, max_running, completed;
+  size_t allocated_bytes, budget_bytes;
+} slso_server_counters;
+
+/* EINVAL: out NULL, slots outside [1, 64], hbm_budget 0, or no such device. */
+int slso_server_create(slso_server** server, int device, int slots,
+                       size_t hbm_budget);
+/* Queue a job (the descriptor is copied); *ticket identifies it. Argument
+ * errors as slso_leverage; ENOMEM when the job alone exceeds the budget. */
+int slso_server_submit(slso_server* server, const slso_job* job,
+                       int64_t* ticket);
+/* 1 and *result filled when the job has completed (the ticket is then
+ * retired), 0 while it is queued or running, EINVAL for an unknown ticket. */
+int slso_server_poll(slso_server* server, int64_t ticket,
+                     slso_job_result* result);
+/* Block until the job completes; fills *result and retires the ticket. */
+int slso_server_wait(slso_server* server, int64_t ticket,
+                     slso_job_result* result);
+int slso_server_stats(slso_server* server, slso_server_counters* stats);
+/* Run every queued job to completion, then release the slots. */
+int slso_server_destroy(slso_server* server);
+
 /* ---- stages, exposed for verification and composition -------------------- */
 
 /* CountSketch bucket and sign of rows row0 .. row0+n-1 (Sec. 3.1.2):

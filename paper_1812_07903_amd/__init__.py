@@ -33,7 +33,9 @@ EXPORTED = (
     "slso_create", "slso_destroy", "slso_status_string", "slso_last_error",
     "slso_sketch", "slso_leverage", "slso_order", "slso_hash",
     "slso_gaussian", "slso_gaussian_sketch_entries", "slso_qr_r",
-    "slso_solve_upper", "slso_scores",
+    "slso_solve_upper", "slso_scores", "slso_workspace_size",
+    "slso_server_create", "slso_server_submit", "slso_server_poll",
+    "slso_server_wait", "slso_server_stats", "slso_server_destroy",
     "slso_profile_enable", "slso_profile_read", "slso_profile_name",
 )
 # slso_info.flags bits
@@ -68,6 +70,25 @@ class _Info(ctypes.Structure):
                 ("diag_max", ctypes.c_double)]
 
 
+class _Job(ctypes.Structure):
+    _fields_ = [("X", _Matrix), ("seed", ctypes.c_uint64), ("r", ctypes.c_int64),
+                ("k", ctypes.c_int64), ("opt", _Options),
+                ("scores", ctypes.c_void_p), ("perm", ctypes.c_void_p)]
+
+
+class _JobResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("info", _Info), ("submit_ms", ctypes.c_double),
+                ("start_ms", ctypes.c_double), ("end_ms", ctypes.c_double)]
+
+
+class _Counters(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("max_running", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("allocated_bytes", ctypes.c_size_t),
+                ("budget_bytes", ctypes.c_size_t)]
+
+
 _lib = None
 
 
@@ -100,6 +121,17 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "slso_solve_upper": ([vp, vp, i64, vp, i64, vp], ctypes.c_int),
         "slso_scores": ([vp, ctypes.POINTER(_Matrix), vp, i64, vp, vp],
                         ctypes.c_int),
+        "slso_workspace_size": ([ctypes.POINTER(_Matrix), i64, i64,
+                                 ctypes.POINTER(_Options),
+                                 ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "slso_server_create": ([ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
+                                ctypes.c_size_t], ctypes.c_int),
+        "slso_server_submit": ([vp, ctypes.POINTER(_Job),
+                                ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "slso_server_poll": ([vp, i64, ctypes.POINTER(_JobResult)], ctypes.c_int),
+        "slso_server_wait": ([vp, i64, ctypes.POINTER(_JobResult)], ctypes.c_int),
+        "slso_server_stats": ([vp, ctypes.POINTER(_Counters)], ctypes.c_int),
+        "slso_server_destroy": ([vp], ctypes.c_int),
         "slso_profile_enable": ([ctypes.c_int], ctypes.c_int),
         "slso_profile_read": ([vp, vp, ctypes.c_int], ctypes.c_int),
         "slso_profile_name": ([ctypes.c_int], ctypes.c_char_p),
@@ -265,11 +297,7 @@ class Context:
         st = _check(load_library().slso_leverage(
             self._h, ctypes.byref(m), seed, r, k, ctypes.byref(opt), _ptr(out),
             ctypes.byref(info), _stream(stream)), self._h)
-        return out, {"status": st, "rank": info.rank,
-                     "screen_full": bool(info.screen_full),
-                     "flags": info.flags,
-                     "refined": bool(info.flags & INFO_REFINED),
-                     "diag_min": info.diag_min, "diag_max": info.diag_max}
+        return out, _info_dict(info, st)
 
     def order(self, scores, out=None, stream=None):
         import torch
@@ -306,6 +334,104 @@ class Context:
                                           m.shape[1], _ptr(out),
                                           _stream(stream)), self._h)
         return out
+
+
+def _info_dict(info, st):
+    return {"status": st, "rank": info.rank,
+            "screen_full": bool(info.screen_full), "flags": info.flags,
+            "refined": bool(info.flags & INFO_REFINED),
+            "diag_min": info.diag_min, "diag_max": info.diag_max}
+
+
+def workspace_size(x, r: int, k: int, sketch: int = COUNTSKETCH,
+                   refine: bool = False, rank_tol: float = 0.0) -> int:
+    """Device workspace bytes a context allocates for leverage + order."""
+    m = _matrix(x)
+    opt = _Options(sketch, 1 if refine else 0, rank_tol)
+    out = ctypes.c_size_t()
+    _check(load_library().slso_workspace_size(ctypes.byref(m), r, k,
+                                              ctypes.byref(opt),
+                                              ctypes.byref(out)))
+    return out.value
+
+
+class Ticket:
+    """A submitted job: keeps its input and outputs alive until collected."""
+
+    def __init__(self, tid, x, scores, perm):
+        self.id = tid
+        self.x = x
+        self.scores = scores
+        self.perm = perm
+
+
+class Server:
+    """Serving loop of the C ABI (slso_server_*): ``slots`` concurrent jobs
+    admitted under an HBM budget for the slots' workspaces."""
+
+    def __init__(self, device: int = 0, slots: int = 4,
+                 hbm_budget: int = 64 << 30):
+        h = ctypes.c_void_p()
+        _check(load_library().slso_server_create(ctypes.byref(h), device, slots,
+                                                 hbm_budget))
+        self._h = h
+
+    def submit(self, x, seed: int, r: int, k: int, sketch: int = COUNTSKETCH,
+               refine: bool = False, rank_tol: float = 0.0, order: bool = True,
+               scores=None, perm=None) -> Ticket:
+        """Queue a job; X must already hold its values (synchronise first)."""
+        import torch
+        n = _rows(x)
+        if scores is None:
+            scores = torch.empty(n, dtype=torch.float32, device=_device(x))
+        if order and perm is None:
+            perm = torch.empty(n, dtype=torch.int32, device=_device(x))
+        job = _Job()
+        job.X = _matrix(x)
+        job.seed, job.r, job.k = seed, r, k
+        job.opt = _Options(sketch, 1 if refine else 0, rank_tol)
+        job.scores = scores.data_ptr()
+        job.perm = perm.data_ptr() if order else None
+        tid = ctypes.c_int64()
+        _check(load_library().slso_server_submit(self._h, ctypes.byref(job),
+                                                 ctypes.byref(tid)))
+        return Ticket(tid.value, x, scores, perm if order else None)
+
+    @staticmethod
+    def _result(res):
+        return {"status": res.status, "slot": res.slot,
+                "info": _info_dict(res.info, res.status),
+                "submit_ms": res.submit_ms, "start_ms": res.start_ms,
+                "end_ms": res.end_ms,
+                "latency_ms": res.end_ms - res.submit_ms}
+
+    def poll(self, t: Ticket):
+        """None while running, else the result dict (ticket retired)."""
+        res = _JobResult()
+        st = _check(load_library().slso_server_poll(self._h, t.id,
+                                                    ctypes.byref(res)))
+        return self._result(res) if st == 1 else None
+
+    def wait(self, t: Ticket) -> dict:
+        res = _JobResult()
+        _check(load_library().slso_server_wait(self._h, t.id, ctypes.byref(res)))
+        return self._result(res)
+
+    def stats(self) -> dict:
+        c = _Counters()
+        _check(load_library().slso_server_stats(self._h, ctypes.byref(c)))
+        return {f: getattr(c, f) for f, _ in _Counters._fields_}
+
+    def close(self):
+        if self._h:
+            load_library().slso_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def profile_enable(on: bool = True) -> None:

@@ -66,7 +66,7 @@ def build(verbose: bool = True, jobs: int | None = None) -> str:
         raise RuntimeError("hipcc failed for: " + ", ".join(failed))
     tmp = LIB + ".tmp"
     rc, out = _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}",
-                    *objs, "-o", tmp])
+                    *objs, "-pthread", "-o", tmp])
     if rc != 0:
         raise RuntimeError("link failed:\n" + out)
     shutil.move(tmp, LIB)

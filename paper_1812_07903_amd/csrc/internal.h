@@ -8,6 +8,8 @@
 
 #include "common.h"
 
+struct slso_ctx;
+
 namespace slso {
 
 // ---- launch profiler (slso_capi.hip) ----------------------------------------
@@ -34,6 +36,10 @@ enum KernelId : int {
 };
 void prof_begin(int kid, hipStream_t s);
 void prof_end(int kid, hipStream_t s);
+
+// ---- context internals used by the serving loop (slso_capi.hip) -------------
+// Wait for the context's last use of its workspace and free it.
+int ctx_release_workspace(::slso_ctx* c);
 
 // ---- streams / ordering (k_sort.hip) ----------------------------------------
 // keys[i] = bucket h(row0+i), vals[i] = i | (sign bit << 31).

@@ -17,6 +17,7 @@ struct slso_ctx {
   int device = 0;
   void* ws = nullptr;       // device workspace
   size_t ws_bytes = 0;
+  hipEvent_t ws_done = nullptr;  // recorded after the last work using ws
   void* host_buf = nullptr; // pinned host staging for small read-backs
   std::string err;
 };
@@ -34,8 +35,6 @@ struct Profiler {
   std::mutex mu;
   std::vector<hipEvent_t> pool;
   std::vector<ProfEntry> pending;
-  int open_kid = -1;
-  hipEvent_t open_ev = nullptr;
   double ms[kKCount] = {};
   int64_t count[kKCount] = {};
   hipEvent_t get() {
@@ -53,6 +52,9 @@ Profiler& prof() {
   static Profiler p;
   return p;
 }
+// the launch being timed by this host thread (threads may share a process)
+thread_local int open_kid = -1;
+thread_local hipEvent_t open_ev = nullptr;
 }  // namespace
 
 void prof_begin(int kid, hipStream_t s) {
@@ -65,24 +67,35 @@ void prof_begin(int kid, hipStream_t s) {
     p.pool.push_back(e);
     return;
   }
-  p.open_kid = kid;
-  p.open_ev = e;
+  open_kid = kid;
+  open_ev = e;
 }
 
 void prof_end(int kid, hipStream_t s) {
   Profiler& p = prof();
   if (!p.on) return;
   std::lock_guard<std::mutex> g(p.mu);
-  if (p.open_kid != kid || !p.open_ev) return;
+  if (open_kid != kid || !open_ev) return;
   hipEvent_t e = p.get();
   if (!e) return;
   if (hipEventRecord(e, s) != hipSuccess) {
     p.pool.push_back(e);
     return;
   }
-  p.pending.push_back({kid, p.open_ev, e});
-  p.open_kid = -1;
-  p.open_ev = nullptr;
+  p.pending.push_back({kid, open_ev, e});
+  open_kid = -1;
+  open_ev = nullptr;
+}
+int ctx_release_workspace(slso_ctx* c) {
+  if (!c) return SLSO_EINVAL;
+  if (!c->ws) return SLSO_OK;
+  if (hipSetDevice(c->device) != hipSuccess ||
+      hipEventSynchronize(c->ws_done) != hipSuccess ||
+      hipFree(c->ws) != hipSuccess)
+    return SLSO_EDEVICE;
+  c->ws = nullptr;
+  c->ws_bytes = 0;
+  return SLSO_OK;
 }
 }  // namespace slso
 
@@ -108,9 +121,10 @@ struct Arena {
 struct Sizer {
   size_t off = 0;
   template <typename T>
-  void take(size_t count) {
+  T* take(size_t count) {
     off = (off + kAlign - 1) / kAlign * kAlign;
     off += count * sizeof(T);
+    return nullptr;
   }
 };
 
@@ -127,16 +141,31 @@ int set_err(slso_ctx* c, int st, const std::string& msg) {
                      std::string(#call) + ": " + hipGetErrorString(e_));     \
   } while (0)
 
+// Bytes a context allocates for a workspace request (rounded to 2 MiB).
+size_t ws_alloc_bytes(size_t need) {
+  const size_t g = size_t{1} << 21;
+  return (need + g - 1) / g * g;
+}
+
+// Records ws_done on the call's stream when the call returns, after all of
+// its work on the workspace has been enqueued.
+struct WsMark {
+  slso_ctx* c;
+  hipStream_t s;
+  ~WsMark() { (void)hipEventRecord(c->ws_done, s); }
+};
+
 int ensure_ws(slso_ctx* c, size_t bytes) {
   if (bytes <= c->ws_bytes) return SLSO_OK;
   SLSO_HIP(c, hipSetDevice(c->device));
   if (c->ws) {
-    SLSO_HIP(c, hipDeviceSynchronize());
+    // only this context's own earlier work can still be using the buffer
+    SLSO_HIP(c, hipEventSynchronize(c->ws_done));
     SLSO_HIP(c, hipFree(c->ws));
     c->ws = nullptr;
     c->ws_bytes = 0;
   }
-  const size_t want = bytes + bytes / 8 + (1u << 20);
+  const size_t want = ws_alloc_bytes(bytes);
   if (hipMalloc(&c->ws, want) != hipSuccess) {
     c->ws = nullptr;
     (void)hipGetLastError();
@@ -242,6 +271,67 @@ void enqueue_countsketch(const slso_matrix* X, uint64_t seed, int64_t r,
                      b.vals_s, b.off, r, dscale, sx, s);
 }
 
+size_t gemm_partial_bytes(const slso_matrix* X, int64_t r, bool gauss,
+                          bool refine) {
+  const int64_t n = X->n, d = X->d;
+  const size_t g = gauss ? gauss_partial_bytes(n, r, d) : size_t{0};
+  const size_t m = refine ? gram_partial_bytes(n, d, X->dtype) : size_t{0};
+  return std::max(g, m);
+}
+
+// Workspace of slso_leverage; the arena in slso_leverage takes the same
+// buffers in the same order.
+size_t leverage_ws_bytes(const slso_matrix* X, int64_t r, int64_t k,
+                         bool gauss, bool refine) {
+  const int64_t n = X->n, d = X->d;
+  const int64_t kk = k == 0 ? d : k;
+  Sizer z;
+  if (!gauss) size_sketch_bufs(z, n, r);
+  z.take<uint64_t>(d);             // colmax bits
+  z.take<double>(d);               // dscale D
+  z.take<double>(d);               // D * col_scale (FP8)
+  z.take<int>(64);                 // flags
+  z.take<double>(8);               // diag stats
+  z.take<double>(r * d);           // sketch
+  z.take<char>(gemm_partial_bytes(X, r, gauss, refine));
+  z.take<char>(qr_scratch_bytes(r, d));
+  z.take<double>(d * d);           // R_D of the sketch
+  if (refine)
+    for (int i = 0; i < 3; ++i) z.take<double>(d * d);  // G, R1, refined R
+  z.take<double>(d * kk);          // Pi_2 -> M'
+  z.take<double>(d * kk);          // M (FP64)
+  z.take<float>(d * kk);           // M (FP32)
+  z.take<char>(scores_partial_bytes(n, kk, X->format));
+  return z.off;
+}
+
+size_t order_ws_bytes(int64_t n) {
+  Sizer z;
+  for (int i = 0; i < 4; ++i) z.take<uint32_t>(n);
+  z.take<char>(radix_sort_scratch_bytes(n));
+  return z.off;
+}
+
+int check_leverage(slso_ctx* c, const slso_matrix* X, int64_t r, int64_t k,
+                   const slso_options* opt, slso_options* o) {
+  int st = validate_matrix(c, X);
+  if (st) return st;
+  if (r < X->d || r >= (static_cast<int64_t>(1) << 31))
+    return set_err(c, SLSO_EINVAL, "need d <= r < 2^31");
+  if (k < 0) return set_err(c, SLSO_EINVAL, "k must be >= 0");
+  *o = slso_options{};
+  if (opt) *o = *opt;
+  if (o->sketch != SLSO_COUNTSKETCH && o->sketch != SLSO_GAUSSIAN)
+    return set_err(c, SLSO_EINVAL, "unknown sketch kind");
+  if (o->refine != 0 && o->refine != 1)
+    return set_err(c, SLSO_EINVAL, "refine must be 0 or 1");
+  if ((o->sketch == SLSO_GAUSSIAN || o->refine == 1) && !mfma_input(X))
+    return set_err(c, SLSO_EUNSUPPORTED,
+                   "the Gaussian sketch and the refinement take dense F32, "
+                   "BF16 or FP8 input");
+  return SLSO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -272,7 +362,9 @@ int slso_create(slso_ctx** out, int device) {
   slso_ctx* c = new slso_ctx();
   c->device = device;
   if (hipSetDevice(device) != hipSuccess ||
-      hipHostMalloc(&c->host_buf, 4096, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc(&c->host_buf, 4096, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ws_done, hipEventDisableTiming) != hipSuccess) {
+    if (c->host_buf) (void)hipHostFree(c->host_buf);
     delete c;
     return SLSO_EDEVICE;
   }
@@ -283,8 +375,9 @@ int slso_create(slso_ctx** out, int device) {
 int slso_destroy(slso_ctx* c) {
   if (!c) return SLSO_EINVAL;
   (void)hipSetDevice(c->device);
-  (void)hipDeviceSynchronize();
+  (void)hipEventSynchronize(c->ws_done);
   if (c->ws) (void)hipFree(c->ws);
+  (void)hipEventDestroy(c->ws_done);
   if (c->host_buf) (void)hipHostFree(c->host_buf);
   delete c;
   return SLSO_OK;
@@ -340,6 +433,7 @@ int slso_sketch(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
     z.take<char>(gauss_partial_bytes(X->n, r, X->d));
   }
   if ((st = ensure_ws(c, z.off))) return st;
+  WsMark mark_{c, s};
   Arena a{static_cast<char*>(c->ws)};
   if (kind == SLSO_COUNTSKETCH) {
     SketchBufs b = take_sketch_bufs(a, X->n, r);
@@ -364,6 +458,7 @@ int slso_qr_r(slso_ctx* c, double* a, int64_t m, int64_t d, double* r_out,
   SLSO_HIP(c, hipSetDevice(c->device));
   int st = ensure_ws(c, qr_scratch_bytes(m, d) + kAlign);
   if (st) return st;
+  WsMark mark_{c, static_cast<hipStream_t>(stream)};
   qr_factor(a, m, d, r_out, c->ws, static_cast<hipStream_t>(stream));
   return check_launch(c, "slso_qr_r");
 }
@@ -392,6 +487,7 @@ int slso_scores(slso_ctx* c, const slso_matrix* X, const double* m, int64_t k,
   z.take<float>(X->d * k);
   z.take<char>(scores_partial_bytes(X->n, k, X->format));
   if ((st = ensure_ws(c, z.off))) return st;
+  WsMark mark_{c, s};
   Arena a{static_cast<char*>(c->ws)};
   double* cs = a.take<double>(X->d);
   float* m32 = a.take<float>(X->d * k);
@@ -410,24 +506,12 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
                   int64_t k, const slso_options* opt, float* scores,
                   slso_info* info, void* stream) {
   if (!c) return SLSO_EINVAL;
-  int st = validate_matrix(c, X);
-  if (st) return st;
-  if (r < X->d || r >= (static_cast<int64_t>(1) << 31))
-    return set_err(c, SLSO_EINVAL, "need d <= r < 2^31");
-  if (k < 0) return set_err(c, SLSO_EINVAL, "k must be >= 0");
   if (!scores) return set_err(c, SLSO_EINVAL, "scores is NULL");
   slso_options o{};
-  if (opt) o = *opt;
-  if (o.sketch != SLSO_COUNTSKETCH && o.sketch != SLSO_GAUSSIAN)
-    return set_err(c, SLSO_EINVAL, "unknown sketch kind");
-  if (o.refine != 0 && o.refine != 1)
-    return set_err(c, SLSO_EINVAL, "refine must be 0 or 1");
+  int st = check_leverage(c, X, r, k, opt, &o);
+  if (st) return st;
   const bool gauss = o.sketch == SLSO_GAUSSIAN;
   const bool refine = o.refine == 1;
-  if ((gauss || refine) && !mfma_input(X))
-    return set_err(c, SLSO_EUNSUPPORTED,
-                   "the Gaussian sketch and the refinement take dense F32, "
-                   "BF16 or FP8 input");
   const bool fp8 = X->dtype == SLSO_FP8_E4M3;
   const double tol = o.rank_tol == 0.0 ? 1e-10 : o.rank_tol;
   const int64_t n = X->n, d = X->d;
@@ -435,29 +519,11 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   SLSO_HIP(c, hipSetDevice(c->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
 
-  // workspace plan
-  const size_t gemm_part =
-      gauss ? std::max(gauss_partial_bytes(n, r, d),
-                       refine ? gram_partial_bytes(n, d, X->dtype) : size_t{0})
-            : (refine ? gram_partial_bytes(n, d, X->dtype) : size_t{0});
+  const size_t gemm_part = gemm_partial_bytes(X, r, gauss, refine);
   Sizer z;
-  if (!gauss) size_sketch_bufs(z, n, r);
-  z.take<uint64_t>(d);             // colmax bits
-  z.take<double>(d);               // dscale D
-  z.take<double>(d);               // D * col_scale (FP8)
-  z.take<int>(64);                 // flags
-  z.take<double>(8);               // diag stats
-  z.take<double>(r * d);           // sketch
-  z.take<char>(gemm_part);         // split-K partial sums
-  z.take<char>(qr_scratch_bytes(r, d));
-  z.take<double>(d * d);           // R_D of the sketch
-  if (refine)
-    for (int i = 0; i < 3; ++i) z.take<double>(d * d);  // G, R1, refined R
-  z.take<double>(d * kk);          // Pi_2 -> M'
-  z.take<double>(d * kk);          // M (FP64)
-  z.take<float>(d * kk);           // M (FP32)
-  z.take<char>(scores_partial_bytes(n, kk, X->format));
+  z.off = leverage_ws_bytes(X, r, k, gauss, refine);
   if ((st = ensure_ws(c, z.off))) return st;
+  WsMark mark_{c, s};
   Arena a{static_cast<char*>(c->ws)};
   SketchBufs sb{};
   if (!gauss) sb = take_sketch_bufs(a, n, r);
@@ -581,6 +647,18 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   return rank < d ? SLSO_RANK_DEFICIENT : SLSO_OK;
 }
 
+int slso_workspace_size(const slso_matrix* X, int64_t r, int64_t k,
+                        const slso_options* opt, size_t* bytes) {
+  if (!bytes) return SLSO_EINVAL;
+  slso_options o{};
+  const int st = check_leverage(nullptr, X, r, k, opt, &o);
+  if (st) return st;
+  *bytes = ws_alloc_bytes(std::max(
+      leverage_ws_bytes(X, r, k, o.sketch == SLSO_GAUSSIAN, o.refine == 1),
+      order_ws_bytes(X->n)));
+  return SLSO_OK;
+}
+
 int slso_order(slso_ctx* c, const float* scores, int64_t n, int32_t* perm,
                void* stream) {
   if (!c) return SLSO_EINVAL;
@@ -588,11 +666,9 @@ int slso_order(slso_ctx* c, const float* scores, int64_t n, int32_t* perm,
     return set_err(c, SLSO_EINVAL, "need scores, perm and 1 <= n < 2^31");
   SLSO_HIP(c, hipSetDevice(c->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  Sizer z;
-  for (int i = 0; i < 4; ++i) z.take<uint32_t>(n);
-  z.take<char>(radix_sort_scratch_bytes(n));
-  int st = ensure_ws(c, z.off);
+  int st = ensure_ws(c, order_ws_bytes(n));
   if (st) return st;
+  WsMark mark_{c, s};
   Arena a{static_cast<char*>(c->ws)};
   uint32_t* keys = a.take<uint32_t>(n);
   uint32_t* keys_o = a.take<uint32_t>(n);

@@ -23,6 +23,11 @@ Shapes and distributions:
   Poisson(2) count.
 * ``precision_dense`` -- rank-256 signal with sigma_j = j^-1.5 in d=512,
   noise 1e-4, row scales e^N(0, 1.5^2) (the reduced-precision workload).
+* ``serving_pool`` / ``serving_jobs`` -- the serving workload: a Poisson
+  stream of jobs with n log-uniform in [1e4, 2e6], d from {64, ..., 1024},
+  FP32 or BF16, each a row window of one of ten base matrices (one per d and
+  dtype, 2e6 rows, drawn on the device like the plain small workload) with
+  its own sketch seed.
 """
 from __future__ import annotations
 
@@ -34,6 +39,7 @@ __all__ = [
     "haar", "lowrank_dense", "config0", "image_like", "config1",
     "text_like_csr", "config2", "precision_dense", "to_bf16_bits",
     "bf16_bits_to_f64", "to_fp8_e4m3", "fp8_e4m3_to_f64", "Csr",
+    "lowrank_dense_device", "serving_pool", "serving_jobs",
 ]
 
 
@@ -204,3 +210,84 @@ def fp8_e4m3_to_f64(codes: np.ndarray, col_scale: np.ndarray) -> np.ndarray:
     mag = np.where((c & 0x7F) == 127, np.nan, mag)
     val = np.where(c & 0x80, -mag, mag)
     return val * np.asarray(col_scale, dtype=np.float64)[None, :]
+
+
+def lowrank_dense_device(n: int, d: int, rank: int, sigma, noise: float,
+                         row_sigma: float, seed: int, device="cuda",
+                         chunk: int = 1 << 18):
+    """``lowrank_dense`` drawn on a torch device (FP64), for inputs too large
+    to draw on the host in reasonable time: U Haar (QR of a Gaussian with the
+    sign fix), V Haar, Gaussian noise and log-normal row scales, all from one
+    seeded torch generator. Same distribution as ``lowrank_dense``, different
+    random numbers."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+
+    def haar_t(m, k):
+        a = torch.randn(m, k, generator=g, device=device, dtype=torch.float64)
+        q, r = torch.linalg.qr(a)
+        s = torch.sign(torch.diagonal(r))
+        s[s == 0] = 1.0
+        return q * s
+
+    u = haar_t(n, rank)
+    v = haar_t(d, rank)
+    sv = torch.as_tensor(np.asarray(sigma, dtype=np.float64), device=device)
+    w = (v * sv[None, :]).T.contiguous()          # rank x d
+    x = torch.empty(n, d, device=device, dtype=torch.float64)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        blk = u[a:b] @ w
+        if noise > 0:
+            blk += noise * torch.randn(b - a, d, generator=g, device=device,
+                                       dtype=torch.float64)
+        x[a:b] = blk
+    del u
+    if row_sigma > 0:
+        rho = torch.exp(row_sigma * torch.randn(n, generator=g, device=device,
+                                                dtype=torch.float64))
+        x *= rho[:, None]
+    return x
+
+
+def serving_pool(d_values=(64, 128, 256, 512, 1024), n: int = 2_000_000,
+                 seed: int = 1004, device="cuda"):
+    """Base matrices of the serving workload, one per (d, dtype), FP32 and
+    BF16 torch tensors on ``device``: rank d/2, sigma_j = 2^(-j/4), noise
+    1e-3, row scales e^N(0,1) (the plain small recipe at larger n). A job is a
+    seeded window of rows of one of them."""
+    import torch
+    pool = {}
+    for i, d in enumerate(d_values):
+        rank = d // 2
+        sigma = 2.0 ** (-np.arange(rank) / 4.0)
+        x = lowrank_dense_device(n, d, rank, sigma, 1e-3, 1.0, seed + 17 * i,
+                                 device)
+        pool[(d, "f32")] = x.to(torch.float32)
+        pool[(d, "bf16")] = x.to(torch.bfloat16)
+        del x
+    return pool
+
+
+def serving_jobs(n_jobs: int = 1024, rate: float = 200.0, seed: int = 1005,
+                 n_lo: float = 1e4, n_hi: float = 2e6,
+                 d_values=(64, 128, 256, 512, 1024), pool_n: int = 2_000_000):
+    """Job descriptors of the serving workload: Poisson arrivals at ``rate``
+    jobs/s, n log-uniform in [n_lo, n_hi], d uniform over ``d_values``,
+    FP32/BF16 with equal odds, r = d * U{4..8}, k = 32, a row window of the
+    pool matrix and a per-job sketch seed."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n_jobs))
+    jobs = []
+    for j in range(n_jobs):
+        n = int(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+        n = min(n, pool_n)
+        d = int(rng.choice(d_values))
+        dt = "f32" if rng.random() < 0.5 else "bf16"
+        row0 = int(rng.integers(0, pool_n - n + 1))
+        r = d * int(rng.integers(4, 9))
+        jobs.append({"arrival_s": float(t[j]), "n": n, "d": d, "dtype": dt,
+                     "row0": row0, "r": r, "k": 32,
+                     "seed": 3_000_000 + j})
+    return jobs

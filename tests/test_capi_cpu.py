@@ -62,3 +62,58 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(slso, "_lib", None)
     with pytest.raises(ImportError):
         slso.load_library(str(tmp_path / "missing.so"))
+
+
+def _mat(n, d, dtype=slso.F32, fmt=slso.DENSE, col_scale=None):
+    m = slso._Matrix()
+    m.n, m.d, m.format, m.dtype = n, d, fmt, dtype
+    m.values = 0x1000            # never dereferenced by the size query
+    m.ld = d
+    m.col_scale = col_scale
+    return m
+
+
+def _ws(lib, m, r, k, sketch=slso.COUNTSKETCH, refine=0):
+    opt = slso._Options(sketch, refine, 0.0)
+    out = ctypes.c_size_t()
+    st = lib.slso_workspace_size(ctypes.byref(m), r, k, ctypes.byref(opt),
+                                 ctypes.byref(out))
+    return st, out.value
+
+
+def test_workspace_size_is_a_host_computation(lib):
+    n, d, r, k = 60000, 784, 16384, 64
+    st, b = _ws(lib, _mat(n, d), r, k)
+    assert st == slso.OK
+    assert b % (2 << 20) == 0
+    # at least the FP64 sketch, the partition arrays and R
+    assert b >= r * d * 8 + 6 * n * 4 + d * d * 8
+    st2, b2 = _ws(lib, _mat(n, d), r, k, refine=1)
+    assert st2 == slso.OK and b2 >= b + 3 * d * d * 8 - (2 << 20)
+    st3, b3 = _ws(lib, _mat(4000, 512, slso.BF16), 2048, 64,
+                  sketch=slso.GAUSSIAN, refine=1)
+    assert st3 == slso.OK and b3 >= 2048 * 512 * 4  # split-K partial sums
+
+
+def test_workspace_size_argument_errors(lib):
+    assert _ws(lib, _mat(100, 10), 5, 4)[0] == slso.EINVAL          # r < d
+    assert _ws(lib, _mat(100, 10), 16, -1)[0] == slso.EINVAL        # k < 0
+    assert _ws(lib, _mat(0, 10), 16, 4)[0] == slso.EINVAL           # n < 1
+    assert _ws(lib, _mat(100, 10, slso.F64), 16, 4,
+               sketch=slso.GAUSSIAN)[0] == slso.EUNSUPPORTED
+    assert _ws(lib, _mat(100, 10, slso.FP8_E4M3), 16, 4)[0] == slso.EUNSUPPORTED
+    assert _ws(lib, _mat(100, 10, slso.F32, col_scale=0x2000), 16, 4)[0] == slso.EINVAL
+    assert lib.slso_workspace_size(None, 16, 4, None, None) == slso.EINVAL
+
+
+def test_server_rejects_invalid_arguments(lib):
+    h = ctypes.c_void_p()
+    assert lib.slso_server_create(None, 0, 2, 1 << 30) == slso.EINVAL
+    assert lib.slso_server_create(ctypes.byref(h), 0, 0, 1 << 30) == slso.EINVAL
+    assert lib.slso_server_create(ctypes.byref(h), 0, 65, 1 << 30) == slso.EINVAL
+    assert lib.slso_server_create(ctypes.byref(h), 0, 2, 0) == slso.EINVAL
+    assert lib.slso_server_submit(None, None, None) == slso.EINVAL
+    assert lib.slso_server_poll(None, 1, None) == slso.EINVAL
+    assert lib.slso_server_wait(None, 1, None) == slso.EINVAL
+    assert lib.slso_server_stats(None, None) == slso.EINVAL
+    assert lib.slso_server_destroy(None) == slso.EINVAL
