@@ -32,6 +32,14 @@ enum KernelId : int {
   kKGaussSketch,
   kKGram,
   kKChol,
+  kKCqGram,
+  kKCqSum,
+  kKCqChol,
+  kKCqQ1,
+  kKCqZ,
+  kKCqRecon,
+  kKCqW,
+  kKCqUpdate,
   kKCount
 };
 void prof_begin(int kid, hipStream_t s);
@@ -92,9 +100,21 @@ void launch_countsketch(const void* x, int dtype, int format, int64_t n,
 // ---- QR (k_qr.hip) -----------------------------------------------------------
 size_t qr_scratch_bytes(int64_t m, int64_t d);
 // Householder QR of a (m x d, lda = d) in place; r_out (d x d) receives R with
-// a non-negative diagonal and zeros below it.
+// a non-negative diagonal and zeros below it. 64-column panels by Cholesky-QR2
+// with Householder reconstruction (k_cqr.hip), the remaining columns by the
+// tree path. *fail (device int) is set to 1 when a panel is too ill-
+// conditioned for Cholesky-QR: a and r_out are then unusable and the caller
+// reruns qr_factor_robust on the original matrix.
 void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
-               hipStream_t s);
+               int* fail, hipStream_t s);
+// The same factorisation by the tree path alone (every column).
+void qr_factor_robust(double* a, int64_t m, int64_t d, double* r_out,
+                      void* scratch, hipStream_t s);
+// 64-column panel path (k_cqr.hip)
+size_t cqr_scratch_bytes(int64_t m, int64_t d);
+int64_t cqr_panels(int64_t m, int64_t d);
+void cqr_panel(double* a, int64_t m, int64_t d, int64_t j0, void* scratch,
+               int* flag, hipStream_t s);
 // diag stats of upper-triangular r (d x d): out[0] = min |r_jj|, out[1] = max
 void launch_diag_stats(const double* r, int64_t d, double* out, hipStream_t s);
 

@@ -702,18 +702,20 @@ __global__ void __launch_bounds__(256)
 
 }  // namespace
 
-size_t qr_scratch_bytes(int64_t m, int64_t d) {
-  (void)d;
+namespace {
+
+size_t tree_scratch_bytes(int64_t m) {
   const int64_t tn = total_nodes(m);
-  return static_cast<size_t>(tn) * (kL * kW + kW * kW) * sizeof(double) + 512;
+  return static_cast<size_t>(tn) * (kL * kW + kW * kW) * sizeof(double);
 }
 
-void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
-               hipStream_t s) {
+// Tree-path panels of columns [j_start, d)
+void tree_panels(double* a, int64_t m, int64_t d, int64_t j_start,
+                 void* scratch, hipStream_t s) {
   const int64_t tn = total_nodes(m);
   double* Yws = static_cast<double*>(scratch);
   double* Tws = Yws + tn * (kL * kW);
-  for (int64_t j0 = 0; j0 < d; j0 += kW) {
+  for (int64_t j0 = j_start; j0 < d; j0 += kW) {
     const Panel P = make_panel(m, d, j0);
     const int64_t tc0 = j0 + P.w;
     const int64_t tcols = d - tc0;
@@ -733,11 +735,40 @@ void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
       }
     }
   }
+}
+
+void extract_r(const double* a, int64_t d, double* r_out, hipStream_t s) {
   const int64_t dd = d * d;
   prof_begin(kKQrExtract, s);
   extract_r_kernel<<<static_cast<unsigned>((dd + 255) / 256), 256, 0, s>>>(
       a, d, d, r_out);
   prof_end(kKQrExtract, s);
+}
+
+size_t tree_part(int64_t m) {
+  return (tree_scratch_bytes(m) + 255) / 256 * 256;
+}
+
+}  // namespace
+
+size_t qr_scratch_bytes(int64_t m, int64_t d) {
+  return tree_part(m) + cqr_scratch_bytes(m, d) + 512;
+}
+
+void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
+               int* fail, hipStream_t s) {
+  launch_fill_i32(fail, 1, 0, s);
+  void* cws = static_cast<char*>(scratch) + tree_part(m);
+  const int64_t np = cqr_panels(m, d);
+  for (int64_t p = 0; p < np; ++p) cqr_panel(a, m, d, 64 * p, cws, fail, s);
+  tree_panels(a, m, d, 64 * np, scratch, s);
+  extract_r(a, d, r_out, s);
+}
+
+void qr_factor_robust(double* a, int64_t m, int64_t d, double* r_out,
+                      void* scratch, hipStream_t s) {
+  tree_panels(a, m, d, 0, scratch, s);
+  extract_r(a, d, r_out, s);
 }
 
 void launch_diag_stats(const double* r, int64_t d, double* out,

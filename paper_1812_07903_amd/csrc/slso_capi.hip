@@ -456,10 +456,29 @@ int slso_qr_r(slso_ctx* c, double* a, int64_t m, int64_t d, double* r_out,
   if (!a || !r_out || d < 1 || m < d)
     return set_err(c, SLSO_EINVAL, "need a, r_out and m >= d >= 1");
   SLSO_HIP(c, hipSetDevice(c->device));
-  int st = ensure_ws(c, qr_scratch_bytes(m, d) + kAlign);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Sizer z;
+  z.take<char>(qr_scratch_bytes(m, d));
+  z.take<double>(m * d);  // copy of a for the fallback
+  z.take<int>(64);
+  int st = ensure_ws(c, z.off);
   if (st) return st;
-  WsMark mark_{c, static_cast<hipStream_t>(stream)};
-  qr_factor(a, m, d, r_out, c->ws, static_cast<hipStream_t>(stream));
+  WsMark mark_{c, s};
+  Arena ar{static_cast<char*>(c->ws)};
+  void* qws = ar.take<char>(qr_scratch_bytes(m, d));
+  double* copy = ar.take<double>(m * d);
+  int* fail = ar.take<int>(64);
+  const size_t bytes = static_cast<size_t>(m * d) * sizeof(double);
+  SLSO_HIP(c, hipMemcpyAsync(copy, a, bytes, hipMemcpyDeviceToDevice, s));
+  qr_factor(a, m, d, r_out, qws, fail, s);
+  if ((st = check_launch(c, "slso_qr_r"))) return st;
+  int* hf = static_cast<int*>(c->host_buf);
+  SLSO_HIP(c, hipMemcpyAsync(hf, fail, sizeof(int), hipMemcpyDeviceToHost, s));
+  SLSO_HIP(c, hipStreamSynchronize(s));
+  if (*hf) {
+    SLSO_HIP(c, hipMemcpyAsync(a, copy, bytes, hipMemcpyDeviceToDevice, s));
+    qr_factor_robust(a, m, d, r_out, qws, s);
+  }
   return check_launch(c, "slso_qr_r");
 }
 
@@ -559,40 +578,59 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
     launch_mul_scale(dscale, X->col_scale, d, eff, s);
     rowfac = eff;
   }
-  // 2. sketch of X D (Algorithm 2 step 1)
-  if (gauss)
-    launch_gauss_sketch(X->values, X->dtype, n, d, X->ld, X->col_scale, seed,
-                        r, dscale, static_cast<float*>(gpart), sx, s);
-  else
-    enqueue_countsketch(X, seed, r, sb, rowfac, sx, s);
-  // 3. Householder QR of the sketch (Algorithm 2 step 2, QR form)
-  qr_factor(sx, r, d, RS, qws, s);
-  launch_diag_stats(RS, d, dstat, s);
-  // 3b. refinement: G = (X D)^T (X D); G' = R_S^-T G R_S^-1 = R1^T R1;
-  //     R = R1 R_S is the R factor of X D
-  if (refine) {
-    launch_gram(X->values, X->dtype, n, d, X->ld, X->col_scale, dscale, gpart,
-                G, s);
-    solve_upper_trans(RS, d, G, d, s);     // W = R_S^-T G
-    launch_transpose(G, d, R1, s);         // W^T
-    solve_upper_trans(RS, d, R1, d, s);    // R_S^-T W^T = G'
-    cholesky(R1, d, G, flags + 1, s);      // G (reused) = R1
-    launch_trmm_upper(G, RS, d, RR, s);    // R = R1 R_S
-    launch_diag_stats(RR, d, dstat + 2, s);
-  }
-  if ((st = check_launch(c, "slso_leverage: sketch/QR"))) return st;
+  // 2. sketch of X D (Algorithm 2 step 1), 3. Householder QR of the sketch
+  // (Algorithm 2 step 2, QR form), 3b. refinement: G = (X D)^T (X D);
+  // G' = R_S^-T G R_S^-1 = R1^T R1; R = R1 R_S is the R factor of X D.
+  // The QR's 64-column panels use Cholesky-QR2; when one is too ill-
+  // conditioned for it (flags[2]), the sketch is formed again and factored
+  // column by column.
+  auto factor = [&](bool robust) {
+    if (gauss)
+      launch_gauss_sketch(X->values, X->dtype, n, d, X->ld, X->col_scale, seed,
+                          r, dscale, static_cast<float*>(gpart), sx, s);
+    else
+      enqueue_countsketch(X, seed, r, sb, rowfac, sx, s);
+    if (robust)
+      qr_factor_robust(sx, r, d, RS, qws, s);
+    else
+      qr_factor(sx, r, d, RS, qws, flags + 2, s);
+    launch_diag_stats(RS, d, dstat, s);
+    if (refine) {
+      launch_fill_i32(flags + 1, 1, 0, s);
+      launch_gram(X->values, X->dtype, n, d, X->ld, X->col_scale, dscale, gpart,
+                  G, s);
+      solve_upper_trans(RS, d, G, d, s);     // W = R_S^-T G
+      launch_transpose(G, d, R1, s);         // W^T
+      solve_upper_trans(RS, d, R1, d, s);    // R_S^-T W^T = G'
+      cholesky(R1, d, G, flags + 1, s);      // G (reused) = R1
+      launch_trmm_upper(G, RS, d, RR, s);    // R = R1 R_S
+      launch_diag_stats(RR, d, dstat + 2, s);
+    }
+  };
   // 4. rank screen read-back
   char* hb = static_cast<char*>(c->host_buf);
-  SLSO_HIP(c, hipMemcpyAsync(hb, dstat, 4 * sizeof(double),
-                             hipMemcpyDeviceToHost, s));
-  SLSO_HIP(c, hipMemcpyAsync(hb + 64, flags, 2 * sizeof(int),
-                             hipMemcpyDeviceToHost, s));
-  SLSO_HIP(c, hipStreamSynchronize(s));
   double ds[4];
-  int fl[2];
-  std::memcpy(ds, hb, sizeof(ds));
-  std::memcpy(fl, hb + 64, sizeof(fl));
+  int fl[3];
+  auto readback = [&]() -> int {
+    SLSO_HIP(c, hipMemcpyAsync(hb, dstat, 4 * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    SLSO_HIP(c, hipMemcpyAsync(hb + 64, flags, 3 * sizeof(int),
+                               hipMemcpyDeviceToHost, s));
+    SLSO_HIP(c, hipStreamSynchronize(s));
+    std::memcpy(ds, hb, sizeof(ds));
+    std::memcpy(fl, hb + 64, sizeof(fl));
+    return SLSO_OK;
+  };
+  factor(false);
+  if ((st = check_launch(c, "slso_leverage: sketch/QR"))) return st;
+  if ((st = readback())) return st;
   if (fl[0]) return set_err(c, SLSO_ENONFINITE, "X holds Inf or NaN");
+  const bool qr_fallback = fl[2] != 0;
+  if (qr_fallback) {
+    factor(true);
+    if ((st = check_launch(c, "slso_leverage: sketch/QR"))) return st;
+    if ((st = readback())) return st;
+  }
   int32_t info_flags = 0;
   const double* R = RS;
   double dmin = ds[0], dmax = ds[1];
@@ -715,7 +753,8 @@ const char* slso_profile_name(int id) {
   static const char* names[] = {
       "hash_pack", "sort_hist", "sort_scan", "sort_scatter", "bucket_offsets",
       "colmax", "countsketch", "qr_node", "qr_update", "qr_extract", "trsm",
-      "score", "gaussian", "gauss_sketch", "gram", "cholesky"};
+      "score", "gaussian", "gauss_sketch", "gram", "cholesky", "cq_gram",
+      "cq_sum", "cq_chol", "cq_q1", "cq_z", "cq_recon", "cq_w", "cq_update"};
   if (id < 0 || id >= slso::kKCount) return "";
   return names[id];
 }

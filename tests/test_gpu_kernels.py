@@ -139,6 +139,58 @@ def test_qr_r_matches_householder(slso, ctx, m, d):
     assert err < 1e-12, err
 
 
+@pytest.mark.parametrize("m,d", [(64, 64), (128, 64), (1000, 130), (3000, 200),
+                                 (16384, 784), (70001, 128), (256, 256),
+                                 (4096, 192)])
+def test_qr_r_panel_path_matches_householder(slso, ctx, m, d):
+    """Shapes with d >= 64 go through the 64-column Cholesky-QR2 panels
+    (ragged row blocks, ragged trailing columns, d a multiple of 64, square)."""
+    rng = np.random.default_rng(m + 3 * d)
+    a = rng.standard_normal((m, d)) * np.exp(rng.standard_normal(d))[None, :]
+    r = host(ctx.qr_r(dev(a.copy())))
+    ref = olv.qr_r(a)
+    assert np.all(np.diag(r) >= 0) and np.all(np.tril(r, -1) == 0)
+    err = np.abs(r - ref).max() / np.abs(ref).max()
+    print(f"[qr panel {m}x{d}] rel err {err:.2e}", flush=True)
+    assert err < 1e-12, err
+
+
+@pytest.mark.parametrize("kappa", [1e2, 5e4])
+def test_qr_r_ill_conditioned_panel(slso, ctx, kappa):
+    """First 64-column panel with condition number kappa: at 5e4 the Gram of
+    the first Cholesky-QR pass is still factorable, but the second pass is
+    not close enough to the identity for its near-identity form, so the
+    blocked Cholesky runs. R is compared through R^T R = A^T A (backward
+    error), the meaningful measure once kappa is large."""
+    rng = np.random.default_rng(int(kappa))
+    m, d = 3000, 160
+    u, _ = np.linalg.qr(rng.standard_normal((m, 64)))
+    v, _ = np.linalg.qr(rng.standard_normal((64, 64)))
+    s = np.logspace(0, -np.log10(kappa), 64)
+    a = np.empty((m, d))
+    a[:, :64] = (u * s) @ v.T
+    a[:, 64:] = rng.standard_normal((m, d - 64))
+    r = host(ctx.qr_r(dev(a.copy())))
+    assert np.all(np.isfinite(r)) and np.all(np.diag(r) >= 0)
+    g = a.T @ a
+    err = np.abs(r.T @ r - g).max() / np.abs(g).max()
+    print(f"[qr kappa={kappa:.0e}] backward err {err:.2e}", flush=True)
+    assert err < 1e-13
+
+
+def test_qr_r_rank_deficient_panel_falls_back(slso, ctx):
+    """A zero column inside a 64-column panel makes its Cholesky fail; the
+    factorisation is redone column by column and stays a valid R."""
+    a = np.random.default_rng(2).standard_normal((2000, 150))
+    a[:, 70] = 0.0
+    a[:, 20] = a[:, 3]          # a repeated column as well
+    r = host(ctx.qr_r(dev(a.copy())))
+    assert np.all(np.isfinite(r))
+    g = a.T @ a
+    assert np.abs(r.T @ r - g).max() < 1e-12 * np.abs(g).max()
+    assert abs(r[70, 70]) < 1e-12 * np.abs(r).max()
+
+
 def test_qr_r_zero_column_is_finite(slso, ctx):
     a = np.random.default_rng(1).standard_normal((600, 40))
     a[:, 7] = 0.0

@@ -99,8 +99,13 @@ def test_mixed_job_matches_oracle(slso):
 
 
 def test_admission_by_hbm_footprint(slso):
-    jobs = _jobs(6, seed=3, n_max=30000)
-    need = max(slso.workspace_size(jb["x"], jb["r"], jb["k"]) for jb in jobs)
+    # six jobs of one shape (different data and seeds)
+    x64 = synth.lowrank_dense(30000, 128, 64, 2.0 ** (-np.arange(64) / 4.0),
+                              1e-3, 1.0, seed=77)
+    x = torch.from_numpy(x64.astype(np.float32)).cuda()
+    torch.cuda.synchronize()
+    jobs = [{"x": x, "seed": 100 + j, "r": 512, "k": 32} for j in range(6)]
+    need = slso.workspace_size(x, 512, 32)
     # room for one job's workspace only: the jobs run one at a time
     srv = slso.Server(0, slots=4, hbm_budget=need + (1 << 20))
     tickets = [srv.submit(jb["x"], jb["seed"], jb["r"], jb["k"]) for jb in jobs]
