@@ -51,6 +51,10 @@ def qr_node_flops(m: int, d: int, w: int = 16) -> float:
 
 # profiler name -> (kernel symbol in the PMC summary, source file)
 KERNEL_SRC = {
+    "cq_update": ("cq_update_kernel", "k_cqr.hip"),
+    "cq_z": ("cq_z_kernel", "k_cqr.hip"),
+    "cq_q1": ("cq_q1_kernel", "k_cqr.hip"),
+    "cq_gram": ("cq_gram_kernel", "k_cqr.hip"),
     "qr_node": ("qr_node_kernel", "k_qr.hip"),
     "qr_update": ("qr_update_kernel", "k_qr.hip"),
     "score": ("score_dense_kernel<float,float>", "k_score.hip"),
@@ -88,8 +92,38 @@ def roofline_for(name: str, ms_per_launch: float, launches_per_step: float):
     return r
 
 
+def cq_panels(m: int = R, d: int = D):
+    """(active rows, trailing columns) of each 64-column Cholesky-QR2 panel."""
+    return [(m - j0, d - j0 - 64) for j0 in range(0, d - 63, 64)]
+
+
+def _fp64(flops_per_launch: float, sec: float):
+    a = flops_per_launch / sec
+    return {"bound": "mfma", "achieved": a / 1e12, "peak": PEAK["fp64"] / 1e12,
+            "unit": "TFLOP/s", "frac": a / PEAK["fp64"], "traffic": None}
+
+
 def _roofline(name: str, ms_per_launch: float, launches_per_step: float):
     sec = ms_per_launch * 1e-3
+    if name in ("cq_update", "cq_z"):
+        # C -= Q1 K  /  Z = Q1^T C: 2 m' 64 n' flop per panel
+        f = sum(2.0 * mp * 64 * nc for mp, nc in cq_panels() if nc > 0)
+        return _fp64(f / launches_per_step, sec)
+    if name == "cq_q1":
+        # Q1 = P R1^{-1} and G2 = Q1^T Q1: 2 x 2 m' 64^2 flop per panel
+        return _fp64(sum(4.0 * mp * 64 * 64 for mp, _ in cq_panels())
+                     / launches_per_step, sec)
+    if name == "cq_gram":
+        return _fp64(sum(2.0 * mp * 64 * 64 for mp, _ in cq_panels())
+                     / launches_per_step, sec)
+    if name in ("cq_recon", "cq_chol"):
+        # one workgroup per panel: Cholesky (64^3 / 3), triangular inverses,
+        # the sign-choosing LU (2 64^3 / 3) and several 64^3 products
+        f = {"cq_chol": 64 ** 3, "cq_recon": 14 * 64 ** 3}[name]
+        a = f / sec
+        return {"bound": "alu", "achieved": a / 1e12,
+                "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
+                "frac": a / PEAK["fp64"], "traffic": None}
     if name == "qr_update":
         flops = qr_update_flops(R, D) / launches_per_step
         a = flops / sec
@@ -275,8 +309,20 @@ def main() -> int:
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    slso.profile_read()                      # drop warm-up launches
+    # per-kernel breakdown: a short pass with every launch bracketed by events
+    # (outside the timed region, since the events themselves cost time)
+    slso.profile_read()
+    slso.profile_only(None)
     slso.profile_enable(True)
+    nb = max(2, min(5, args.steps))
+    for _ in range(nb):
+        step()
+    prof = slso.profile_read()
+    kernels = {k: {"ms_per_step": v[0] / nb, "launches_per_step": v[1] / nb}
+               for k, v in prof.items() if v[1] > 0}
+    dname = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    # timed region: events around the dominant kernel's launches only
+    slso.profile_only(dname)
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -287,20 +333,16 @@ def main() -> int:
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
-    prof = slso.profile_read()
+    dprof = slso.profile_read()
     slso.profile_enable(False)
+    slso.profile_only(None)
 
     ms_step = 1e3 * total / args.steps
     rows_per_s = N * args.steps / total
     lat_ms = np.array(lat) * 1e3
 
-    # dominant kernel by total time inside the timed region
-    dom = max(prof.items(), key=lambda kv: kv[1][0])
-    dname, (dms, dcount) = dom
+    dms, dcount = dprof[dname]
     roof = roofline_for(dname, dms / max(dcount, 1), dcount / args.steps)
-    kernels = {k: {"ms_per_step": v[0] / args.steps,
-                   "launches_per_step": v[1] / args.steps}
-               for k, v in prof.items() if v[1] > 0}
 
     got = scores.cpu().numpy().astype(np.float64)
     perm_h = perm.cpu().numpy().astype(np.int64)
@@ -333,10 +375,12 @@ def main() -> int:
         "kernels": kernels,
         "roofline": dict(kernel=dname, **roof) if roof else None,
         "roofline_other": {
-            k: dict(kernel=k, **rr) for k in ("countsketch", "score", "colmax")
-            if k in prof and prof[k][1] > 0 and k != dname
-            for rr in [roofline_for(k, prof[k][0] / prof[k][1],
-                                    prof[k][1] / args.steps)] if rr},
+            k: dict(kernel=k, **rr)
+            for k in ("countsketch", "score", "colmax", "cq_update", "cq_z")
+            if k in kernels and k != dname
+            for rr in [roofline_for(
+                k, kernels[k]["ms_per_step"] / kernels[k]["launches_per_step"],
+                kernels[k]["launches_per_step"])] if rr},
     }
 
     if not args.no_cpu_baseline:

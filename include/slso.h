@@ -301,6 +301,10 @@ int slso_scores(slso_ctx* ctx, const slso_matrix* X, const double* m,
 int slso_profile_enable(int on);
 int slso_profile_read(double* ms, int64_t* launches, int n);
 const char* slso_profile_name(int id);
+/* Restrict recording to kernel id ``id`` (-1: every kernel, the default), so
+ * that timing one kernel adds two events per launch of that kernel only.
+ * EINVAL for an id out of range. */
+int slso_profile_only(int id);
 
 #ifdef __cplusplus
 }

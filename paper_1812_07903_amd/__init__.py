@@ -37,6 +37,7 @@ EXPORTED = (
     "slso_server_create", "slso_server_submit", "slso_server_poll",
     "slso_server_wait", "slso_server_stats", "slso_server_destroy",
     "slso_profile_enable", "slso_profile_read", "slso_profile_name",
+    "slso_profile_only",
 )
 # slso_info.flags bits
 INFO_REFINED, INFO_REFINE_FAILED = 1, 2
@@ -135,6 +136,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "slso_profile_enable": ([ctypes.c_int], ctypes.c_int),
         "slso_profile_read": ([vp, vp, ctypes.c_int], ctypes.c_int),
         "slso_profile_name": ([ctypes.c_int], ctypes.c_char_p),
+        "slso_profile_only": ([ctypes.c_int], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -437,6 +439,18 @@ class Server:
 def profile_enable(on: bool = True) -> None:
     """Record HIP events around every library kernel launch (process-wide)."""
     load_library().slso_profile_enable(1 if on else 0)
+
+
+def profile_only(name=None) -> None:
+    """Record only the kernel called ``name`` (None: every kernel)."""
+    lib = load_library()
+    kid = -1
+    if name is not None:
+        names = [lib.slso_profile_name(i).decode() for i in range(64)]
+        if name not in names:
+            raise ValueError(f"unknown kernel {name!r}")
+        kid = names.index(name)
+    _check(lib.slso_profile_only(kid))
 
 
 def profile_read() -> dict:

@@ -98,6 +98,15 @@ void launch_countsketch(const void* x, int dtype, int format, int64_t n,
                         const double* dscale, double* sx, hipStream_t s);
 
 // ---- QR (k_qr.hip) -----------------------------------------------------------
+// A second stream and two events that let the QR overlap one panel's
+// trailing update with the next panel's factorisation (side == nullptr:
+// everything on the calling stream).
+struct QrStreams {
+  hipStream_t side = nullptr;
+  hipEvent_t factored = nullptr;
+  hipEvent_t bulk_done = nullptr;
+};
+
 size_t qr_scratch_bytes(int64_t m, int64_t d);
 // Householder QR of a (m x d, lda = d) in place; r_out (d x d) receives R with
 // a non-negative diagonal and zeros below it. 64-column panels by Cholesky-QR2
@@ -106,15 +115,16 @@ size_t qr_scratch_bytes(int64_t m, int64_t d);
 // conditioned for Cholesky-QR: a and r_out are then unusable and the caller
 // reruns qr_factor_robust on the original matrix.
 void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
-               int* fail, hipStream_t s);
+               int* fail, const QrStreams& qs, hipStream_t s);
 // The same factorisation by the tree path alone (every column).
 void qr_factor_robust(double* a, int64_t m, int64_t d, double* r_out,
                       void* scratch, hipStream_t s);
 // 64-column panel path (k_cqr.hip)
 size_t cqr_scratch_bytes(int64_t m, int64_t d);
 int64_t cqr_panels(int64_t m, int64_t d);
-void cqr_panel(double* a, int64_t m, int64_t d, int64_t j0, void* scratch,
-               int* flag, hipStream_t s);
+// all 64-column panels (d / 64 of them), overlapped as described above
+void cqr_factor(double* a, int64_t m, int64_t d, void* scratch, int* flag,
+                const QrStreams& qs, hipStream_t s);
 // diag stats of upper-triangular r (d x d): out[0] = min |r_jj|, out[1] = max
 void launch_diag_stats(const double* r, int64_t d, double* out, hipStream_t s);
 

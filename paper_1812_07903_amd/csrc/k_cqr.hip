@@ -565,7 +565,8 @@ __global__ void __launch_bounds__(256)
 // ---- K4: partial Z = Q1^T C over row parts x 64-column blocks -------------------
 __global__ void __launch_bounds__(256)
     cq_z_kernel(const double* __restrict__ A, int64_t lda, int64_t m, int64_t j0,
-                int64_t ncols, double* __restrict__ zpart, int64_t ldz,
+                int64_t ncols, int64_t cb0, const double* __restrict__ q1top,
+                double* __restrict__ zpart, int64_t ldz,
                 const int* __restrict__ flag) {
   __shared__ double TQ[kTile];
   __shared__ double TC[kTile];
@@ -573,13 +574,17 @@ __global__ void __launch_bounds__(256)
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int p = lane & 15, q = lane >> 4;
   const int64_t r0 = j0 + static_cast<int64_t>(blockIdx.x) * kRZ;
-  const int64_t c0 = static_cast<int64_t>(blockIdx.y) * kP;  // trailing column
+  const int64_t c0 = (cb0 + blockIdx.y) * kP;  // trailing column
   const int64_t nc = ncols - c0 < kP ? ncols - c0 : kP;
   const int64_t cc = j0 + kP + c0;
   dbl4 acc[4];
   zero4(acc);
+  // the panel's top 64 rows hold its R by now: their Q1 comes from the copy
   double vq[16], vc[16];
-  load_regs(vq, A + r0 * lda + j0, lda, m - r0, kP, t);
+  if (r0 == j0)
+    load_regs(vq, q1top, kP, kP, kP, t);
+  else
+    load_regs(vq, A + r0 * lda + j0, lda, m - r0, kP, t);
   load_regs(vc, A + r0 * lda + cc, lda, m - r0, nc, t);
   for (int c = 0; c < kRZ / kP; ++c) {
     const int64_t rb = r0 + c * kP;
@@ -604,15 +609,16 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-// Z summed over the row parts (fixed order): zsum[i][c], c < ncols
+// Z summed over the row parts (fixed order): zsum[i][c], c_lo <= c < c_hi
 __global__ void __launch_bounds__(256)
     cq_zsum_kernel(const double* __restrict__ zpart, int64_t nz, int64_t ldz,
-                   int64_t ncols, double* __restrict__ zsum,
+                   int64_t c_lo, int64_t c_hi, double* __restrict__ zsum,
                    const int* __restrict__ flag) {
   if (*flag) return;
+  const int64_t w = c_hi - c_lo;
   const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (e >= kP * ncols) return;
-  const int64_t i = e / ncols, c = e % ncols;
+  if (e >= kP * w) return;
+  const int64_t i = e / w, c = c_lo + e % w;
   zsum[i * ldz + c] = sum_parts(zpart, nz, kP * ldz, i * ldz + c);
 }
 
@@ -902,7 +908,8 @@ __global__ void __launch_bounds__(256)
 // ---- K6: W' = T^T (L^T C_top + M2^T (Z - Q1_top^T C_top)), K = M2 W' ----------
 __global__ void __launch_bounds__(256)
     cq_w_kernel(const double* __restrict__ A, int64_t lda, int64_t j0,
-                int64_t ncols, const double* __restrict__ zsum, int64_t ldz,
+                int64_t ncols, int64_t cb0, const double* __restrict__ zsum,
+                int64_t ldz,
                 const double* __restrict__ q1top, const double* __restrict__ lbuf,
                 const double* __restrict__ tbuf, const double* __restrict__ m2buf,
                 double* __restrict__ wp, double* __restrict__ kb,
@@ -914,7 +921,7 @@ __global__ void __launch_bounds__(256)
   if (*flag) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int p = lane & 15, q = lane >> 4;
-  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kP;
+  const int64_t c0 = (cb0 + blockIdx.x) * kP;
   const int64_t nc = ncols - c0 < kP ? ncols - c0 : kP;
   load_tile(TZ, zsum + c0, ldz, kP, nc, t);
   load_tile(TC, A + j0 * lda + j0 + kP + c0, lda, kP, nc, t);
@@ -975,7 +982,7 @@ __global__ void __launch_bounds__(256)
 // ---- K7: C -= L W' (top 64 rows), C -= Q1 K (rows below) -----------------------
 __global__ void __launch_bounds__(256)
     cq_update_kernel(double* __restrict__ A, int64_t lda, int64_t m, int64_t j0,
-                     int64_t ncols, const double* __restrict__ lbuf,
+                     int64_t ncols, int64_t cb0, const double* __restrict__ lbuf,
                      const double* __restrict__ wp, const double* __restrict__ kb,
                      int64_t ldz, const int* __restrict__ flag) {
   __shared__ double TA[kTile];
@@ -984,7 +991,7 @@ __global__ void __launch_bounds__(256)
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int p = lane & 15, q = lane >> 4;
   const int64_t r0 = j0 + static_cast<int64_t>(blockIdx.x) * kRU;
-  const int64_t c0 = static_cast<int64_t>(blockIdx.y) * kP;
+  const int64_t c0 = (cb0 + blockIdx.y) * kP;
   const int64_t nc = ncols - c0 < kP ? ncols - c0 : kP;
   const int64_t ccol = j0 + kP + c0;  // first column of this block in A
   // A-operand rows of the first chunk: L for the panel's top rows, else Q1
@@ -1043,8 +1050,10 @@ inline unsigned cdiv(int64_t a, int64_t b) {
 }
 
 struct CqrScratch {
-  double *gpart, *g, *r1, *r1i, *q1top, *qtop, *r2, *r2i, *l, *t, *m2, *zpart,
-      *zsum, *wp, *kb;
+  double *gpart, *g, *r1, *r1i, *qtop, *r2, *r2i, *zpart, *zsum, *wp, *kb;
+  // read by a panel's trailing update while the next panel is factored:
+  // one set per panel parity
+  double *q1top[2], *l[2], *t[2], *m2[2];
   int* status;
 };
 
@@ -1057,13 +1066,15 @@ CqrScratch carve(void* base, int64_t m, int64_t d) {
   c.g = p;       p += kP * kP;
   c.r1 = p;      p += kP * kP;
   c.r1i = p;     p += kP * kP;
-  c.q1top = p;   p += kP * kP;
   c.qtop = p;    p += kP * kP;
   c.r2 = p;      p += kP * kP;
   c.r2i = p;     p += kP * kP;
-  c.l = p;       p += kP * kP;
-  c.t = p;       p += kP * kP;
-  c.m2 = p;      p += kP * kP;
+  for (int b = 0; b < 2; ++b) {
+    c.q1top[b] = p; p += kP * kP;
+    c.l[b] = p;     p += kP * kP;
+    c.t[b] = p;     p += kP * kP;
+    c.m2[b] = p;    p += kP * kP;
+  }
   c.zpart = p;   p += nz * kP * d;
   c.zsum = p;    p += kP * d;
   c.wp = p;      p += kP * d;
@@ -1072,28 +1083,40 @@ CqrScratch carve(void* base, int64_t m, int64_t d) {
   return c;
 }
 
-}  // namespace
-
-size_t cqr_scratch_bytes(int64_t m, int64_t d) {
-  const int64_t ng = (m + kRG - 1) / kRG;
-  const int64_t nz = (m + kRZ - 1) / kRZ;
-  return static_cast<size_t>(ng * kP * kP + 10 * kP * kP + nz * kP * d +
-                             3 * kP * d + 1) * sizeof(double);
-}
-
-int64_t cqr_panels(int64_t m, int64_t d) {
-  (void)m;
-  return d / kP;
-}
-
-void cqr_panel(double* a, int64_t m, int64_t d, int64_t j0, void* scratch,
-               int* flag, hipStream_t s) {
-  const CqrScratch c = carve(scratch, m, d);
+// Trailing update of panel j0 restricted to the 64-column blocks
+// [cb0, cb1) of its trailing columns, on stream s.
+void cqr_trailing(double* a, int64_t m, int64_t d, int64_t j0,
+                  const CqrScratch& c, int par, int64_t cb0, int64_t cb1,
+                  int* flag, hipStream_t s) {
   const int64_t mp = m - j0;
   const int64_t ncols = d - j0 - kP;
-  const unsigned ng = cdiv(mp, kRG);
-  const unsigned ncb = ncols > 0 ? cdiv(ncols, kP) : 0;
+  const int64_t c_hi = cb1 * kP < ncols ? cb1 * kP : ncols;
+  const unsigned nb = static_cast<unsigned>(cb1 - cb0);
   const unsigned nz = cdiv(mp, kRZ);
+  if (nb == 0) return;
+  prof_begin(kKCqZ, s);
+  cq_z_kernel<<<dim3(nz, nb), 256, 0, s>>>(a, d, m, j0, ncols, cb0,
+                                           c.q1top[par], c.zpart, d, flag);
+  prof_end(kKCqZ, s);
+  prof_begin(kKCqW, s);
+  cq_zsum_kernel<<<cdiv(kP * (c_hi - cb0 * kP), 256), 256, 0, s>>>(
+      c.zpart, nz, d, cb0 * kP, c_hi, c.zsum, flag);
+  cq_w_kernel<<<nb, 256, 0, s>>>(a, d, j0, ncols, cb0, c.zsum, d, c.q1top[par],
+                                 c.l[par], c.t[par], c.m2[par], c.wp, c.kb,
+                                 flag);
+  prof_end(kKCqW, s);
+  prof_begin(kKCqUpdate, s);
+  cq_update_kernel<<<dim3(cdiv(mp, kRU), nb), 256, 0, s>>>(
+      a, d, m, j0, ncols, cb0, c.l[par], c.wp, c.kb, d, flag);
+  prof_end(kKCqUpdate, s);
+}
+
+// Factorisation chain of panel j0 on stream s (ends with its Householder R,
+// Y and T in place / in the parity set).
+void cqr_chain(double* a, int64_t m, int64_t d, int64_t j0, const CqrScratch& c,
+               int par, int* flag, hipStream_t s) {
+  const int64_t mp = m - j0;
+  const unsigned ng = cdiv(mp, kRG);
   constexpr unsigned kSumGrid = kP * kP / 256;
   prof_begin(kKCqGram, s);
   cq_gram_kernel<<<ng, 256, 0, s>>>(a, d, m, j0, c.gpart, flag);
@@ -1110,31 +1133,57 @@ void cqr_panel(double* a, int64_t m, int64_t d, int64_t j0, void* scratch,
   prof_begin(kKCqSum, s);
   cq_sum_kernel<<<kSumGrid, 256, 0, s>>>(c.gpart, ng, c.g, flag);
   prof_end(kKCqSum, s);
-  if (ncols > 0) {
-    prof_begin(kKCqZ, s);
-    cq_z_kernel<<<dim3(nz, ncb), 256, 0, s>>>(a, d, m, j0, ncols, c.zpart, d,
-                                              flag);
-    prof_end(kKCqZ, s);
-  }
   prof_begin(kKCqRecon, s);
   cq_chol2_kernel<<<1, 256, 0, s>>>(c.g, c.r2, c.r2i, c.status, flag);
-  cq_recon_a_kernel<<<1, 256, 0, s>>>(a, d, j0, c.g, c.r1, c.q1top, c.qtop,
+  cq_recon_a_kernel<<<1, 256, 0, s>>>(a, d, j0, c.g, c.r1, c.q1top[par], c.qtop,
                                       c.r2, c.r2i, c.status, flag);
-  cq_recon_b_kernel<<<1, 256, 0, s>>>(a, d, j0, c.qtop, c.r2i, c.l, c.t, c.m2,
-                                      flag);
+  cq_recon_b_kernel<<<1, 256, 0, s>>>(a, d, j0, c.qtop, c.r2i, c.l[par],
+                                      c.t[par], c.m2[par], flag);
   prof_end(kKCqRecon, s);
-  if (ncols > 0) {
-    prof_begin(kKCqW, s);
-    cq_zsum_kernel<<<cdiv(kP * ncols, 256), 256, 0, s>>>(c.zpart, nz, d, ncols,
-                                                         c.zsum, flag);
-    cq_w_kernel<<<ncb, 256, 0, s>>>(a, d, j0, ncols, c.zsum, d, c.q1top, c.l,
-                                    c.t, c.m2, c.wp, c.kb, flag);
-    prof_end(kKCqW, s);
-    prof_begin(kKCqUpdate, s);
-    cq_update_kernel<<<dim3(cdiv(mp, kRU), ncb), 256, 0, s>>>(
-        a, d, m, j0, ncols, c.l, c.wp, c.kb, d, flag);
-    prof_end(kKCqUpdate, s);
+}
+
+}  // namespace
+
+size_t cqr_scratch_bytes(int64_t m, int64_t d) {
+  const int64_t ng = (m + kRG - 1) / kRG;
+  const int64_t nz = (m + kRZ - 1) / kRZ;
+  return static_cast<size_t>(ng * kP * kP + 14 * kP * kP + nz * kP * d +
+                             3 * kP * d + 1) * sizeof(double);
+}
+
+int64_t cqr_panels(int64_t m, int64_t d) {
+  (void)m;
+  return d / kP;
+}
+
+void cqr_factor(double* a, int64_t m, int64_t d, void* scratch, int* flag,
+                const QrStreams& qs, hipStream_t s) {
+  const int64_t np = d / kP;
+  if (np == 0) return;
+  const CqrScratch c = carve(scratch, m, d);
+  hipStream_t side = qs.side ? qs.side : s;
+  for (int64_t p = 0; p < np; ++p) {
+    const int64_t j0 = p * kP;
+    const int par = static_cast<int>(p & 1);
+    const int64_t nblk = (d - j0 - kP + kP - 1) / kP;  // trailing blocks
+    cqr_chain(a, m, d, j0, c, par, flag, s);
+    if (nblk == 0) continue;
+    // block 0 (the next panel's columns; all of them for the last panel)
+    // on the main stream, after the previous panel's bulk update
+    const int64_t next_end = p + 1 < np ? 1 : nblk;
+    if (qs.side && p > 0) (void)hipStreamWaitEvent(s, qs.bulk_done, 0);
+    if (qs.side && next_end < nblk)
+      (void)hipEventRecord(qs.factored, s);
+    cqr_trailing(a, m, d, j0, c, par, 0, next_end, flag, s);
+    // the remaining blocks on the side stream, overlapping the next panel's
+    // factorisation
+    if (next_end < nblk) {
+      if (qs.side) (void)hipStreamWaitEvent(side, qs.factored, 0);
+      cqr_trailing(a, m, d, j0, c, par, next_end, nblk, flag, side);
+      if (qs.side) (void)hipEventRecord(qs.bulk_done, side);
+    }
   }
+  if (qs.side) (void)hipStreamWaitEvent(s, qs.bulk_done, 0);
 }
 
 }  // namespace slso

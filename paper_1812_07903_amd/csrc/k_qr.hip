@@ -756,11 +756,11 @@ size_t qr_scratch_bytes(int64_t m, int64_t d) {
 }
 
 void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
-               int* fail, hipStream_t s) {
+               int* fail, const QrStreams& qs, hipStream_t s) {
   launch_fill_i32(fail, 1, 0, s);
   void* cws = static_cast<char*>(scratch) + tree_part(m);
   const int64_t np = cqr_panels(m, d);
-  for (int64_t p = 0; p < np; ++p) cqr_panel(a, m, d, 64 * p, cws, fail, s);
+  cqr_factor(a, m, d, cws, fail, qs, s);
   tree_panels(a, m, d, 64 * np, scratch, s);
   extract_r(a, d, r_out, s);
 }

@@ -18,6 +18,7 @@ struct slso_ctx {
   void* ws = nullptr;       // device workspace
   size_t ws_bytes = 0;
   hipEvent_t ws_done = nullptr;  // recorded after the last work using ws
+  slso::QrStreams qs;            // QR look-ahead stream and events
   void* host_buf = nullptr; // pinned host staging for small read-backs
   std::string err;
 };
@@ -32,6 +33,7 @@ struct ProfEntry {
 };
 struct Profiler {
   bool on = false;
+  int only = -1;  // record only this kernel id (-1: all)
   std::mutex mu;
   std::vector<hipEvent_t> pool;
   std::vector<ProfEntry> pending;
@@ -59,7 +61,7 @@ thread_local hipEvent_t open_ev = nullptr;
 
 void prof_begin(int kid, hipStream_t s) {
   Profiler& p = prof();
-  if (!p.on) return;
+  if (!p.on || (p.only >= 0 && p.only != kid)) return;
   std::lock_guard<std::mutex> g(p.mu);
   hipEvent_t e = p.get();
   if (!e) return;
@@ -363,7 +365,13 @@ int slso_create(slso_ctx** out, int device) {
   c->device = device;
   if (hipSetDevice(device) != hipSuccess ||
       hipHostMalloc(&c->host_buf, 4096, hipHostMallocDefault) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ws_done, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->ws_done, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->qs.side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->qs.factored, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->qs.bulk_done, hipEventDisableTiming) != hipSuccess) {
+    if (c->qs.factored) (void)hipEventDestroy(c->qs.factored);
+    if (c->qs.side) (void)hipStreamDestroy(c->qs.side);
+    if (c->ws_done) (void)hipEventDestroy(c->ws_done);
     if (c->host_buf) (void)hipHostFree(c->host_buf);
     delete c;
     return SLSO_EDEVICE;
@@ -378,6 +386,10 @@ int slso_destroy(slso_ctx* c) {
   (void)hipEventSynchronize(c->ws_done);
   if (c->ws) (void)hipFree(c->ws);
   (void)hipEventDestroy(c->ws_done);
+  (void)hipStreamSynchronize(c->qs.side);
+  (void)hipEventDestroy(c->qs.factored);
+  (void)hipEventDestroy(c->qs.bulk_done);
+  (void)hipStreamDestroy(c->qs.side);
   if (c->host_buf) (void)hipHostFree(c->host_buf);
   delete c;
   return SLSO_OK;
@@ -470,7 +482,7 @@ int slso_qr_r(slso_ctx* c, double* a, int64_t m, int64_t d, double* r_out,
   int* fail = ar.take<int>(64);
   const size_t bytes = static_cast<size_t>(m * d) * sizeof(double);
   SLSO_HIP(c, hipMemcpyAsync(copy, a, bytes, hipMemcpyDeviceToDevice, s));
-  qr_factor(a, m, d, r_out, qws, fail, s);
+  qr_factor(a, m, d, r_out, qws, fail, c->qs, s);
   if ((st = check_launch(c, "slso_qr_r"))) return st;
   int* hf = static_cast<int*>(c->host_buf);
   SLSO_HIP(c, hipMemcpyAsync(hf, fail, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -593,7 +605,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
     if (robust)
       qr_factor_robust(sx, r, d, RS, qws, s);
     else
-      qr_factor(sx, r, d, RS, qws, flags + 2, s);
+      qr_factor(sx, r, d, RS, qws, flags + 2, c->qs, s);
     launch_diag_stats(RS, d, dstat, s);
     if (refine) {
       launch_fill_i32(flags + 1, 1, 0, s);
@@ -723,6 +735,14 @@ int slso_profile_enable(int on) {
   slso::Profiler& p = slso::prof();
   std::lock_guard<std::mutex> g(p.mu);
   p.on = on != 0;
+  return SLSO_OK;
+}
+
+int slso_profile_only(int id) {
+  if (id < -1 || id >= slso::kKCount) return SLSO_EINVAL;
+  slso::Profiler& p = slso::prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  p.only = id;
   return SLSO_OK;
 }
 
