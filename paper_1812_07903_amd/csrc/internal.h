@@ -182,6 +182,7 @@ void launch_scores(const void* x, int dtype, int format, int64_t n, int64_t d,
                    const double* m64, const float* m32, int64_t k,
                    float* scores, hipStream_t s, double* partial);
 // bytes of the FP64 partial-sum buffer needed by launch_scores (0 if none)
-size_t scores_partial_bytes(int64_t n, int64_t k, int format);
+size_t scores_partial_bytes(int64_t n, int64_t d, int64_t k, int format,
+                            int dtype);
 
 }  // namespace slso

@@ -154,9 +154,260 @@ __global__ void __launch_bounds__(256)
   if (lane == 0) out[row] = static_cast<float>(tot);
 }
 
+// ---- MFMA scoring for k <= 64 ------------------------------------------------
+// A workgroup of four waves scores 128 rows; wave w owns rows 32w .. 32w + 31
+// and all 64 columns of M (two 32 x 32 accumulator tiles). The contraction
+// over d runs in chunks of 32: X (128 x 32) and M (32 x 64) are staged in
+// LDS, double-buffered, the chunk's products summed on MFMA in FP32 and added
+// to FP64 accumulators, so the error is that of 32-term FP32 sums.
+//   FP32 input: v_mfma_f32_32x32x2f32 on FP32 X and FP32 M.
+//   BF16 / FP8 input: v_mfma_f32_32x32x16_bf16 on X (exact in BF16) and three
+//   BF16 parts of M (M = Mh + Mm + Ml, |M - Mh - Mm - Ml| <= 2^-24 |M|).
+// Epilogue: l_i = sum over the 64 columns of the squared FP64 accumulators.
+// Accumulator register e of lane l holds row (e % 4) + 8 (e / 4) + 4 (l / 32)
+// and column l % 32 of its tile.
+constexpr int kMR = 128;     // rows per workgroup
+constexpr int kMC = 32;      // contraction chunk
+constexpr int kXS32 = 33;    // LDS row stride (floats) of the FP32 X tile
+constexpr int kXS16 = 40;    // LDS row stride (bf16) of the BF16 tiles
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+  return static_cast<uint16_t>(u);
+}
+
+template <int IT>
+struct XIn;
+template <>
+struct XIn<0> {
+  using T = float;
+};
+template <>
+struct XIn<1> {
+  using T = uint16_t;
+};
+template <>
+struct XIn<2> {
+  using T = uint8_t;
+};
+
+// BF16 bits of input element v (FP8 e4m3 values are exact in BF16)
+__device__ __forceinline__ uint16_t in_bf16(uint16_t v) { return v; }
+__device__ __forceinline__ uint16_t in_bf16(uint8_t q) {
+  return f32_to_bf16_bits(e4m3_to_f32(q));
+}
+
+// 32-lane butterfly sum (lanes l and l ^ 32 are kept apart)
+__device__ __forceinline__ double sum32(double v) {
+#pragma unroll
+  for (int o = 1; o < 32; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int IT>
+__global__ void __launch_bounds__(256)
+    score_mfma_kernel(const typename XIn<IT>::T* __restrict__ x, int64_t n,
+                      int64_t d, int64_t ld, const float* __restrict__ m32,
+                      int64_t k, const uint16_t* __restrict__ mh,
+                      const uint16_t* __restrict__ mm,
+                      const uint16_t* __restrict__ ml, int64_t ldm,
+                      float* __restrict__ out) {
+  // FP32: X[2][128][33] f32 + M[2][32][64] f32; BF16: X[2][128][40] bf16 +
+  // Mh, Mm, Ml[2][64][40] bf16 (M stored by column, k contiguous)
+  constexpr int kXBytes = IT == 0 ? kMR * kXS32 * 4 : kMR * kXS16 * 2;
+  constexpr int kMBytes = IT == 0 ? kMC * 64 * 4 : 3 * 64 * kXS16 * 2;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * (kXBytes + kMBytes)];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int l32 = lane & 31, h = lane >> 5;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kMR;
+  const int nch = static_cast<int>((d + kMC - 1) / kMC);
+
+  f16v acc[2];
+  double a64[2][16];
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      acc[tt][e] = 0.0f;
+      a64[tt][e] = 0.0;
+    }
+
+  // staging registers: X 16 elements per thread (row t/8 + 32 p, columns
+  // 4 (t%8) .. +3), M 8 elements per thread
+  using XT = typename XIn<IT>::T;
+  XT xr[16];
+  float mr[8];
+  uint16_t mhr[8], mmr[8], mlr[8];
+  auto load_chunk = [&](int ch) {
+    const int64_t c0 = static_cast<int64_t>(ch) * kMC;
+#pragma unroll
+    for (int pp = 0; pp < 4; ++pp) {
+      const int r = t / 8 + 32 * pp;
+      const int64_t gr = row0 + r;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t gc = c0 + 4 * (t % 8) + u;
+        xr[4 * pp + u] = (gr < n && gc < d) ? x[gr * ld + gc] : XT(0);
+      }
+    }
+    if constexpr (IT == 0) {
+      // M rows c0 .. c0 + 31, 64 columns: element e = t + 256 v
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int e = t + 256 * v;
+        const int kr = e / 64, cc = e % 64;
+        const int64_t gk = c0 + kr;
+        mr[v] = (gk < d && cc < k) ? m32[gk * k + cc] : 0.0f;
+      }
+    } else {
+      // Mh / Ml by column: 64 columns x 32 k, element e = t + 256 v
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int e = t + 256 * v;
+        const int cc = e / 32, kr = e % 32;
+        const int64_t gk = c0 + kr;
+        const bool ok = gk < d;
+        mhr[v] = ok ? mh[cc * ldm + gk] : uint16_t(0);
+        mmr[v] = ok ? mm[cc * ldm + gk] : uint16_t(0);
+        mlr[v] = ok ? ml[cc * ldm + gk] : uint16_t(0);
+      }
+    }
+  };
+  auto store_chunk = [&](int buf) {
+    unsigned char* xb = lds + buf * kXBytes;
+    unsigned char* mb = lds + 2 * kXBytes + buf * kMBytes;
+    if constexpr (IT == 0) {
+      float* X = reinterpret_cast<float*>(xb);
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          X[(t / 8 + 32 * pp) * kXS32 + 4 * (t % 8) + u] = xr[4 * pp + u];
+      float* M = reinterpret_cast<float*>(mb);
+#pragma unroll
+      for (int v = 0; v < 8; ++v) M[t + 256 * v] = mr[v];
+    } else {
+      uint16_t* X = reinterpret_cast<uint16_t*>(xb);
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          X[(t / 8 + 32 * pp) * kXS16 + 4 * (t % 8) + u] = in_bf16(xr[4 * pp + u]);
+      uint16_t* Mh = reinterpret_cast<uint16_t*>(mb);
+      uint16_t* Mm = Mh + 64 * kXS16;
+      uint16_t* Ml = Mm + 64 * kXS16;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int e = t + 256 * v;
+        Mh[(e / 32) * kXS16 + e % 32] = mhr[v];
+        Mm[(e / 32) * kXS16 + e % 32] = mmr[v];
+        Ml[(e / 32) * kXS16 + e % 32] = mlr[v];
+      }
+    }
+  };
+
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) load_chunk(ch + 1);
+    const unsigned char* xb = lds + buf * kXBytes;
+    const unsigned char* mb = lds + 2 * kXBytes + buf * kMBytes;
+    if constexpr (IT == 0) {
+      const float* X = reinterpret_cast<const float*>(xb);
+      const float* M = reinterpret_cast<const float*>(mb);
+#pragma unroll
+      for (int kk = 0; kk < kMC / 2; ++kk) {
+        const float av = X[(32 * w + l32) * kXS32 + 2 * kk + h];
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt)
+          acc[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+              av, M[(2 * kk + h) * 64 + 32 * tt + l32], acc[tt], 0, 0, 0);
+      }
+    } else {
+      const __bf16* X = reinterpret_cast<const __bf16*>(xb);
+      const __bf16* Mh = reinterpret_cast<const __bf16*>(mb);
+      const __bf16* Mm = Mh + 64 * kXS16;
+      const __bf16* Ml = Mm + 64 * kXS16;
+#pragma unroll
+      for (int kk = 0; kk < kMC / 16; ++kk) {
+        const bf16x8 av = *reinterpret_cast<const bf16x8*>(
+            &X[(32 * w + l32) * kXS16 + 16 * kk + 8 * h]);
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+          const int col = 32 * tt + l32;
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(
+              &Mh[col * kXS16 + 16 * kk + 8 * h]);
+          const bf16x8 bm = *reinterpret_cast<const bf16x8*>(
+              &Mm[col * kXS16 + 16 * kk + 8 * h]);
+          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(
+              &Ml[col * kXS16 + 16 * kk + 8 * h]);
+          // smallest part first
+          acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bl, acc[tt], 0, 0, 0);
+          acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bm, acc[tt], 0, 0, 0);
+          acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bh, acc[tt], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        a64[tt][e] += static_cast<double>(acc[tt][e]);
+        acc[tt][e] = 0.0f;
+      }
+    if (ch + 1 < nch) {
+      __syncthreads();  // every wave is done with the other buffer
+      store_chunk(buf ^ 1);
+      __syncthreads();
+    }
+  }
+  // l_i = sum_c y_ic^2: square and add the two tiles, then 32 lanes
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    double sq = a64[0][e] * a64[0][e] + a64[1][e] * a64[1][e];
+    sq = sum32(sq);
+    const int64_t row = row0 + 32 * w + (e % 4) + 8 * (e / 4) + 4 * h;
+    if (l32 == 0 && row < n) out[row] = static_cast<float>(sq);
+  }
+}
+
+__device__ __forceinline__ double bf16_bits_to_double(uint16_t b) {
+  return static_cast<double>(__uint_as_float(static_cast<uint32_t>(b) << 16));
+}
+
+// Mh, Mm, Ml (64 x ldm bf16, column c of M stored contiguously): the BF16
+// rounding of M, of the remainder, and of the remainder after that
+__global__ void split_m_kernel(const double* __restrict__ m64, int64_t d,
+                               int64_t k, int64_t ldm, uint16_t* __restrict__ mh,
+                               uint16_t* __restrict__ mm,
+                               uint16_t* __restrict__ ml) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= 64 * d) return;
+  const int64_t c = e / d, j = e % d;
+  double v = c < k ? m64[j * k + c] : 0.0;
+  const uint16_t hb = f32_to_bf16_bits(static_cast<float>(v));
+  v -= bf16_bits_to_double(hb);
+  const uint16_t mb = f32_to_bf16_bits(static_cast<float>(v));
+  v -= bf16_bits_to_double(mb);
+  mh[c * ldm + j] = hb;
+  mm[c * ldm + j] = mb;
+  ml[c * ldm + j] = f32_to_bf16_bits(static_cast<float>(v));
+}
+
 }  // namespace
 
-size_t scores_partial_bytes(int64_t n, int64_t k, int format) {
+size_t scores_partial_bytes(int64_t n, int64_t d, int64_t k, int format,
+                            int dtype) {
+  if (format == 0 && dtype != 0 && k <= 64) {
+    // the BF16 halves of M for reduced-precision input
+    return dtype == 1 ? 0 : static_cast<size_t>(3 * 64 * d) * sizeof(uint16_t);
+  }
   const int64_t tiles = (k + kCols - 1) / kCols;
   if (format == 1 || tiles <= 1) return 0;
   return static_cast<size_t>(tiles * n) * sizeof(double);
@@ -176,6 +427,33 @@ void launch_scores(const void* x, int dtype, int format, int64_t n, int64_t d,
     score_csr_kernel<<<static_cast<unsigned>((n + 3) / 4), 256, 0, s>>>(
         row_ptr, col_idx, static_cast<const float*>(x), n, m32, k, scores);
     prof_end(kKScore, s);
+    return;
+  }
+  if (dtype != 0 && k <= 64) {
+    const unsigned g = static_cast<unsigned>((n + kMR - 1) / kMR);
+    if (dtype == 1) {
+      prof_begin(kKScore, s);
+      score_mfma_kernel<0><<<g, 256, 0, s>>>(static_cast<const float*>(x), n, d,
+                                             ld, m32, k, nullptr, nullptr,
+                                             nullptr, 0, scores);
+      prof_end(kKScore, s);
+    } else {
+      uint16_t* mh = reinterpret_cast<uint16_t*>(partial);
+      uint16_t* mm = mh + 64 * d;
+      uint16_t* ml = mm + 64 * d;
+      split_m_kernel<<<static_cast<unsigned>((64 * d + 255) / 256), 256, 0, s>>>(
+          m64, d, k, d, mh, mm, ml);
+      prof_begin(kKScore, s);
+      if (dtype == 2)
+        score_mfma_kernel<1><<<g, 256, 0, s>>>(static_cast<const uint16_t*>(x), n,
+                                               d, ld, nullptr, k, mh, mm, ml, d,
+                                               scores);
+      else
+        score_mfma_kernel<2><<<g, 256, 0, s>>>(static_cast<const uint8_t*>(x), n,
+                                               d, ld, nullptr, k, mh, mm, ml, d,
+                                               scores);
+      prof_end(kKScore, s);
+    }
     return;
   }
   const int64_t tiles = (k + kCols - 1) / kCols;

@@ -303,7 +303,7 @@ size_t leverage_ws_bytes(const slso_matrix* X, int64_t r, int64_t k,
   z.take<double>(d * kk);          // Pi_2 -> M'
   z.take<double>(d * kk);          // M (FP64)
   z.take<float>(d * kk);           // M (FP32)
-  z.take<char>(scores_partial_bytes(n, kk, X->format));
+  z.take<char>(scores_partial_bytes(n, d, kk, X->format, X->dtype));
   return z.off;
 }
 
@@ -515,20 +515,23 @@ int slso_scores(slso_ctx* c, const slso_matrix* X, const double* m, int64_t k,
   hipStream_t s = static_cast<hipStream_t>(stream);
   Sizer z;
   z.take<double>(X->d);
+  z.take<double>(X->d * k);
   z.take<float>(X->d * k);
-  z.take<char>(scores_partial_bytes(X->n, k, X->format));
+  z.take<char>(scores_partial_bytes(X->n, X->d, k, X->format, X->dtype));
   if ((st = ensure_ws(c, z.off))) return st;
   WsMark mark_{c, s};
   Arena a{static_cast<char*>(c->ws)};
   double* cs = a.take<double>(X->d);
+  double* m64 = a.take<double>(X->d * k);
   float* m32 = a.take<float>(X->d * k);
-  double* part = a.take<double>(scores_partial_bytes(X->n, k, X->format) / 8);
+  double* part = a.take<double>(
+      scores_partial_bytes(X->n, X->d, k, X->format, X->dtype) / 8);
   // FP8 codes: the column scales are folded into the rows of M
   const bool fp8 = X->dtype == SLSO_FP8_E4M3;
   if (fp8) launch_mul_scale(nullptr, X->col_scale, X->d, cs, s);
-  launch_scale_rows(m, fp8 ? cs : nullptr, X->d, k, nullptr, m32, s);
+  launch_scale_rows(m, fp8 ? cs : nullptr, X->d, k, m64, m32, s);
   launch_scores(X->values, X->dtype, X->format, X->n, X->d, X->ld, X->row_ptr,
-                X->col_idx, X->col_scale, X->row_scale, m, m32, k, scores, s,
+                X->col_idx, X->col_scale, X->row_scale, m64, m32, k, scores, s,
                 part);
   return check_launch(c, "slso_scores");
 }
@@ -576,7 +579,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   double* pi = a.take<double>(d * kk);
   double* m64 = a.take<double>(d * kk);
   float* m32 = a.take<float>(d * kk);
-  double* part = a.take<double>(scores_partial_bytes(n, kk, X->format) / 8);
+  double* part = a.take<double>(scores_partial_bytes(n, d, kk, X->format, X->dtype) / 8);
 
   // 1. column equilibration D (power of two) from column max-abs of X
   launch_fill_u64(colmax, d, 0, s);
