@@ -129,8 +129,16 @@ void cqr_factor(double* a, int64_t m, int64_t d, void* scratch, int* flag,
 void launch_diag_stats(const double* r, int64_t d, double* out, hipStream_t s);
 
 // ---- triangular solve / Jacobi (k_solve.hip) --------------------------------------
+// Solve R X = B in place (R upper triangular d x d, B d x k row-major).
+// With scratch (trsm_blocked_scratch(d, k) bytes) the blocked solver with
+// 64 x 64 diagonal inverses on MFMA runs (k_cqr.hip); without it, 64-row
+// blocks with one wave per right-hand side.
 void solve_upper(const double* r, int64_t d, double* b, int64_t k,
-                 hipStream_t s);
+                 hipStream_t s, double* scratch = nullptr);
+size_t trsm_blocked_scratch(int64_t d, int64_t k);
+// R X = B (transposed = false) or R^T X = B (true), in place
+void trsm_blocked(const double* r, int64_t d, double* b, int64_t k,
+                  bool transposed, void* scratch, hipStream_t s);
 // pinv of the rank-`rank` truncation of r applied to b: out = V' S'^-1 U'^T b.
 // Works on copies; sigma (host) receives the d singular values, descending.
 size_t jacobi_scratch_bytes(int64_t d, int64_t k);
@@ -165,7 +173,7 @@ void launch_gauss_entries(uint64_t seed, int64_t r, int64_t n, int64_t row0,
 // ---- Cholesky refinement (k_chol.hip) ----------------------------------------
 // Solve R^T X = B in place (R upper triangular d x d, B d x k).
 void solve_upper_trans(const double* r, int64_t d, double* b, int64_t k,
-                       hipStream_t s);
+                       hipStream_t s, double* scratch = nullptr);
 void launch_transpose(const double* a, int64_t d, double* out, hipStream_t s);
 // Upper Cholesky factor of symmetric positive definite g (d x d, overwritten)
 // into r (zeros below the diagonal); *flag (device int) set to 1 on a

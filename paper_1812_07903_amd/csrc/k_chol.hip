@@ -179,8 +179,12 @@ inline unsigned grid1(int64_t n, int t) {
 }  // namespace
 
 void solve_upper_trans(const double* r, int64_t d, double* b, int64_t k,
-                       hipStream_t s) {
+                       hipStream_t s, double* scratch) {
   if (d <= 0 || k <= 0) return;
+  if (scratch) {
+    trsm_blocked(r, d, b, k, true, scratch, s);
+    return;
+  }
   const unsigned cgrid = static_cast<unsigned>((k + 63) / 64);
   const int64_t nb = (d + kB - 1) / kB;
   for (int64_t bi = 0; bi < nb; ++bi) {

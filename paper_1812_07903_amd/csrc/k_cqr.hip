@@ -1045,6 +1045,122 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// ---- blocked triangular solves with 64 x 64 diagonal inverses -----------------
+// Inverse of each 64 x 64 diagonal block of the upper-triangular R (d x d),
+// the block past d padded with the identity: wave w inverts the 16 x 16
+// diagonal block w by substitution, inv_offdiag fills the rest.
+__global__ void __launch_bounds__(256)
+    trinv_diag_kernel(const double* __restrict__ R, int64_t d,
+                      double* __restrict__ rinv) {
+  __shared__ double T[kTile];
+  __shared__ double X[kTile];
+  __shared__ double idg[kP];
+  __shared__ double tmp[4][16][17];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t o = static_cast<int64_t>(blockIdx.x) * kP;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = t + 256 * u;
+    const int i = e >> 6, j = e & 63;
+    double v;
+    if (o + i < d && o + j < d)
+      v = j >= i ? R[(o + i) * d + o + j] : 0.0;
+    else
+      v = i == j ? 1.0 : 0.0;
+    T[i * kS + j] = v;
+    X[i * kS + j] = 0.0;
+  }
+  __syncthreads();
+  if (t < kP) idg[t] = 1.0 / T[t * kS + t];
+  __syncthreads();
+  tri_inv16(&T[16 * w * kS + 16 * w], nullptr, &X[16 * w * kS + 16 * w],
+            idg + 16 * w, lane);
+  __syncthreads();
+  inv_offdiag(T, X, tmp, t);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = t + 256 * u;
+    rinv[blockIdx.x * kP * kP + e] = X[(e >> 6) * kS + (e & 63)];
+  }
+}
+
+// One block step of R X = B (back, blocks from the last) or R^T X = B
+// (forward, from the first): X_J = inv(J) B_J, with inv(J) = R_JJ^{-1} (back)
+// or R_JJ^{-T} (forward), written to X by the workgroups of block row J;
+// every other block row I still to be solved takes B_I -= C_IJ X_J with
+// C_IJ = R_IJ (back) or R_JI^T (forward), computing X_J itself. Grid:
+// (block rows, 64-column blocks of B).
+template <bool BACK>
+__global__ void __launch_bounds__(256)
+    trsm_step_kernel(const double* __restrict__ R, const double* __restrict__ rinv,
+                     int64_t d, double* __restrict__ B, double* __restrict__ X,
+                     int64_t k, int64_t J) {
+  __shared__ double TI[kTile];
+  __shared__ double TB[kTile];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int p = lane & 15, q = lane >> 4;
+  const int64_t I = BACK ? static_cast<int64_t>(blockIdx.x)
+                         : J + static_cast<int64_t>(blockIdx.x);
+  const int64_t c0 = static_cast<int64_t>(blockIdx.y) * kP;
+  const int64_t nc = k - c0 < kP ? k - c0 : kP;
+  const int64_t oJ = J * kP, oI = I * kP;
+  const int64_t nrJ = d - oJ < kP ? d - oJ : kP;
+  load_tile(TI, rinv + J * kP * kP, kP, kP, kP, t);
+  load_tile(TB, B + oJ * k + c0, k, nrJ, nc, t);
+  __syncthreads();
+  dbl4 acc[4];
+  zero4(acc);
+  if (BACK)
+    mm64<false>(TI, TB, acc, lane, w);
+  else
+    mm64<true>(TI, TB, acc, lane, w);
+  if (I == J) {
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = oJ + 16 * w + 4 * v + q;
+        const int64_t col = 16 * bj + p;
+        if (r < d && col < nc) X[r * k + c0 + col] = acc[bj][v];
+      }
+    return;
+  }
+  __syncthreads();
+  store_acc(TB, acc, 1.0, lane, w);  // X_J
+  // C_IJ: rows of block I, columns of block J of R (back), or the transpose
+  // of R_JI (forward); the block past d is zero
+  const int64_t nrI = d - oI < kP ? d - oI : kP;
+  if (BACK)
+    load_tile(TI, R + oI * d + oJ, d, nrI, nrJ, t);
+  else
+    load_tile(TI, R + oJ * d + oI, d, nrJ, nrI, t);
+  __syncthreads();
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = oI + 16 * w + 4 * v + q;
+      const int64_t col = 16 * bj + p;
+      acc[bj][v] = (r < d && col < nc) ? B[r * k + c0 + col] : 0.0;
+    }
+  // acc -= C_IJ X_J
+#pragma unroll 4
+  for (int kk = 0; kk < 16; ++kk) {
+    const int kx = 4 * kk + q;
+    const double a = BACK ? -TI[(16 * w + p) * kS + kx] : -TI[kx * kS + 16 * w + p];
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bj] = mfma(a, TB[kx * kS + 16 * bj + p], acc[bj]);
+  }
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = oI + 16 * w + 4 * v + q;
+      const int64_t col = 16 * bj + p;
+      if (r < d && col < nc) B[r * k + c0 + col] = acc[bj][v];
+    }
+}
+
 inline unsigned cdiv(int64_t a, int64_t b) {
   return static_cast<unsigned>((a + b - 1) / b);
 }
@@ -1184,6 +1300,34 @@ void cqr_factor(double* a, int64_t m, int64_t d, void* scratch, int* flag,
     }
   }
   if (qs.side) (void)hipStreamWaitEvent(s, qs.bulk_done, 0);
+}
+
+size_t trsm_blocked_scratch(int64_t d, int64_t k) {
+  const int64_t nb = (d + kP - 1) / kP;
+  return static_cast<size_t>(nb * kP * kP + d * k) * sizeof(double);
+}
+
+void trsm_blocked(const double* r, int64_t d, double* b, int64_t k,
+                  bool transposed, void* scratch, hipStream_t s) {
+  if (d <= 0 || k <= 0) return;
+  const int64_t nb = (d + kP - 1) / kP;
+  double* rinv = static_cast<double*>(scratch);
+  double* x = rinv + nb * kP * kP;
+  const unsigned ncb = cdiv(k, kP);
+  prof_begin(kKTrsm, s);
+  trinv_diag_kernel<<<static_cast<unsigned>(nb), 256, 0, s>>>(r, d, rinv);
+  for (int64_t i = 0; i < nb; ++i) {
+    const int64_t J = transposed ? i : nb - 1 - i;
+    if (transposed)
+      trsm_step_kernel<false><<<dim3(static_cast<unsigned>(nb - J), ncb), 256, 0,
+                                s>>>(r, rinv, d, b, x, k, J);
+    else
+      trsm_step_kernel<true><<<dim3(static_cast<unsigned>(J + 1), ncb), 256, 0,
+                               s>>>(r, rinv, d, b, x, k, J);
+  }
+  (void)hipMemcpyAsync(b, x, static_cast<size_t>(d * k) * sizeof(double),
+                       hipMemcpyDeviceToDevice, s);
+  prof_end(kKTrsm, s);
 }
 
 }  // namespace slso

@@ -208,11 +208,16 @@ __global__ void __launch_bounds__(64)
   UtB[static_cast<int64_t>(jj) * k + c] = s / sig[j];
 }
 
+
 }  // namespace
 
 void solve_upper(const double* r, int64_t d, double* b, int64_t k,
-                 hipStream_t s) {
+                 hipStream_t s, double* scratch) {
   if (d <= 0 || k <= 0) return;
+  if (scratch) {
+    trsm_blocked(r, d, b, k, false, scratch, s);
+    return;
+  }
   const unsigned cgrid = static_cast<unsigned>((k + 63) / 64);
   const int64_t nb = (d + kB - 1) / kB;
   for (int64_t bi = nb - 1; bi >= 0; --bi) {

@@ -304,6 +304,7 @@ size_t leverage_ws_bytes(const slso_matrix* X, int64_t r, int64_t k,
   z.take<double>(d * kk);          // M (FP64)
   z.take<float>(d * kk);           // M (FP32)
   z.take<char>(scores_partial_bytes(n, d, kk, X->format, X->dtype));
+  z.take<char>(trsm_blocked_scratch(d, refine ? d : kk));
   return z.off;
 }
 
@@ -500,7 +501,11 @@ int slso_solve_upper(slso_ctx* c, const double* r, int64_t d, double* b,
   if (!r || !b || d < 1 || k < 1)
     return set_err(c, SLSO_EINVAL, "need r, b, d >= 1, k >= 1");
   SLSO_HIP(c, hipSetDevice(c->device));
-  solve_upper(r, d, b, k, static_cast<hipStream_t>(stream));
+  int st = ensure_ws(c, trsm_blocked_scratch(d, k));
+  if (st) return st;
+  WsMark mark_{c, static_cast<hipStream_t>(stream)};
+  solve_upper(r, d, b, k, static_cast<hipStream_t>(stream),
+              static_cast<double*>(c->ws));
   return check_launch(c, "slso_solve_upper");
 }
 
@@ -580,6 +585,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   double* m64 = a.take<double>(d * kk);
   float* m32 = a.take<float>(d * kk);
   double* part = a.take<double>(scores_partial_bytes(n, d, kk, X->format, X->dtype) / 8);
+  double* tws = a.take<double>(trsm_blocked_scratch(d, refine ? d : kk) / 8);
 
   // 1. column equilibration D (power of two) from column max-abs of X
   launch_fill_u64(colmax, d, 0, s);
@@ -614,9 +620,9 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
       launch_fill_i32(flags + 1, 1, 0, s);
       launch_gram(X->values, X->dtype, n, d, X->ld, X->col_scale, dscale, gpart,
                   G, s);
-      solve_upper_trans(RS, d, G, d, s);     // W = R_S^-T G
+      solve_upper_trans(RS, d, G, d, s, tws);     // W = R_S^-T G
       launch_transpose(G, d, R1, s);         // W^T
-      solve_upper_trans(RS, d, R1, d, s);    // R_S^-T W^T = G'
+      solve_upper_trans(RS, d, R1, d, s, tws);    // R_S^-T W^T = G'
       cholesky(R1, d, G, flags + 1, s);      // G (reused) = R1
       launch_trmm_upper(G, RS, d, RR, s);    // R = R1 R_S
       launch_diag_stats(RR, d, dstat + 2, s);
@@ -670,7 +676,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
                     pi, s);
   int64_t rank = d;
   if (full) {
-    solve_upper(R, d, pi, kk, s);
+    solve_upper(R, d, pi, kk, s, tws);
     launch_scale_rows(pi, rowfac, d, kk, m64, m32, s);
   } else {
     Sizer jz;
