@@ -51,6 +51,8 @@ def qr_node_flops(m: int, d: int, w: int = 16) -> float:
 
 # profiler name -> (kernel symbol in the PMC summary, source file)
 KERNEL_SRC = {
+    "cq2_gram": ("gram_part_kernel", "k_cholqr.hip"),
+    "cq2_solve": ("stripe_solve_kernel", "k_cholqr.hip"),
     "cq_update": ("cq_update_kernel", "k_cqr.hip"),
     "cq_z": ("cq_z_kernel", "k_cqr.hip"),
     "cq_q1": ("cq_q1_kernel", "k_cqr.hip"),
@@ -105,6 +107,18 @@ def _fp64(flops_per_launch: float, sec: float):
 
 def _roofline(name: str, ms_per_launch: float, launches_per_step: float):
     sec = ms_per_launch * 1e-3
+    if name == "cq2_gram":
+        # upper triangle of A^T A (d (d + 1) / 2 entries, m products each)
+        return _fp64(float(R) * D * (D + 1), sec)
+    if name == "cq2_solve":
+        # Q1 = A R1^{-1}: m d^2 flop
+        return _fp64(float(R) * D * D, sec)
+    if name in ("cq2_chol", "cq2_r"):
+        # d^3 / 3 flop (Cholesky of G1; R = R2 R1 with triangular R2, R1)
+        a = D ** 3 / 3.0 / sec
+        return {"bound": "alu", "achieved": a / 1e12,
+                "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
+                "frac": a / PEAK["fp64"], "traffic": None}
     if name in ("cq_update", "cq_z"):
         # C -= Q1 K  /  Z = Q1^T C: 2 m' 64 n' flop per panel
         f = sum(2.0 * mp * 64 * nc for mp, nc in cq_panels() if nc > 0)

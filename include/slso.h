@@ -114,6 +114,13 @@ typedef struct {
                                   /* met a non-positive pivot (X D is, in    */
                                   /* working precision, rank deficient); the */
                                   /* sketch factor R_D was used instead      */
+#define SLSO_INFO_QR_SECOND_CHOLESKY 4 /* the sketch's Cholesky-QR2 needed   */
+                                  /* the blocked Cholesky in its second pass */
+#define SLSO_INFO_QR_HOUSEHOLDER 8 /* Cholesky-QR2 did not apply to the     */
+                                  /* sketch; its R came from the Householder */
+                                  /* panel path                              */
+#define SLSO_INFO_QR_TREE 16      /* ... and, that failing too, from the     */
+                                  /* column-by-column Householder path       */
 
 /* ---- context ------------------------------------------------------------ */
 
@@ -272,12 +279,32 @@ int slso_gaussian(uint64_t seed, int32_t stream_id, int64_t rows, int64_t cols,
 int slso_gaussian_sketch_entries(uint64_t seed, int64_t r, int64_t row0,
                                  int64_t n, float* out, void* stream);
 
-/* R factor of a Householder QR (Algorithm 2 step 2, QR form) of the m x d
+/* R factor of a QR factorisation (Algorithm 2 step 2, QR form) of the m x d
  * matrix a (device, row-major, lda = d, m >= d), which is overwritten.
  * r_out (device) d x d doubles: upper triangle of R with a non-negative
- * diagonal, zeros below. */
+ * diagonal, zeros below (R is unique up to the signs of its rows when a has
+ * full column rank; past a zero pivot any valid R may be returned).
+ * Path: Cholesky-QR2 over the whole matrix; when its checks fail (the first
+ * Gram matrix is not numerically positive definite, or the first pass leaves
+ * Q1 too far from orthonormal), Householder QR with 64-column panels; when a
+ * panel is too ill-conditioned for that, Householder QR column by column.
+ * The call synchronises the stream once per path tried. */
 int slso_qr_r(slso_ctx* ctx, double* a, int64_t m, int64_t d, double* r_out,
               void* stream);
+
+/* QR paths (slso_qr_r_path) */
+#define SLSO_QR_AUTO 0          /* the cascade of slso_qr_r                  */
+#define SLSO_QR_PANEL 1         /* Householder, 64-column panels (then tree) */
+#define SLSO_QR_TREE 2          /* Householder, column by column             */
+#define SLSO_QR_CHOLQR2 3       /* reported: Cholesky-QR2, one-launch R2     */
+#define SLSO_QR_CHOLQR2_FULL 4  /* reported: Cholesky-QR2, blocked R2        */
+
+/* slso_qr_r starting from a given path (SLSO_QR_AUTO, SLSO_QR_PANEL or
+ * SLSO_QR_TREE; EINVAL otherwise); *path_used (host, nullable) receives the
+ * path that produced r_out (SLSO_QR_CHOLQR2, SLSO_QR_CHOLQR2_FULL,
+ * SLSO_QR_PANEL or SLSO_QR_TREE). */
+int slso_qr_r_path(slso_ctx* ctx, double* a, int64_t m, int64_t d,
+                   double* r_out, int path, int32_t* path_used, void* stream);
 
 /* Solve R X = B in place for upper-triangular R (device, d x d, row-major)
  * and B (device, d x k, row-major) -- the R^{-1} Pi_2 of Algorithm 2 step 3. */

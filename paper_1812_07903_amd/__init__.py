@@ -32,7 +32,7 @@ STREAM_GAUSS_S, STREAM_PI2 = 3, 4
 EXPORTED = (
     "slso_create", "slso_destroy", "slso_status_string", "slso_last_error",
     "slso_sketch", "slso_leverage", "slso_order", "slso_hash",
-    "slso_gaussian", "slso_gaussian_sketch_entries", "slso_qr_r",
+    "slso_gaussian", "slso_gaussian_sketch_entries", "slso_qr_r", "slso_qr_r_path",
     "slso_solve_upper", "slso_scores", "slso_workspace_size",
     "slso_server_create", "slso_server_submit", "slso_server_poll",
     "slso_server_wait", "slso_server_stats", "slso_server_destroy",
@@ -41,6 +41,8 @@ EXPORTED = (
 )
 # slso_info.flags bits
 INFO_REFINED, INFO_REFINE_FAILED = 1, 2
+INFO_QR_SECOND_CHOLESKY, INFO_QR_HOUSEHOLDER, INFO_QR_TREE = 4, 8, 16
+QR_AUTO, QR_PANEL, QR_TREE, QR_CHOLQR2, QR_CHOLQR2_FULL = 0, 1, 2, 3, 4
 
 
 class SlsoError(RuntimeError):
@@ -119,6 +121,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "slso_gaussian_sketch_entries": ([u64, i64, i64, i64, vp, vp],
                                          ctypes.c_int),
         "slso_qr_r": ([vp, vp, i64, i64, vp, vp], ctypes.c_int),
+        "slso_qr_r_path": ([vp, vp, i64, i64, vp, ctypes.c_int, vp, vp],
+                           ctypes.c_int),
         "slso_solve_upper": ([vp, vp, i64, vp, i64, vp], ctypes.c_int),
         "slso_scores": ([vp, ctypes.POINTER(_Matrix), vp, i64, vp, vp],
                         ctypes.c_int),
@@ -312,13 +316,20 @@ class Context:
 
     # ---- stages ---------------------------------------------------------------
     def qr_r(self, a, stream=None):
-        """R (non-negative diagonal) of a Householder QR; ``a`` is overwritten."""
+        """R (non-negative diagonal) of a QR of ``a``, which is overwritten."""
+        return self.qr_r_path(a, QR_AUTO, stream)[0]
+
+    def qr_r_path(self, a, path=QR_AUTO, stream=None):
+        """(R, path used) starting from ``path`` (QR_AUTO, QR_PANEL or
+        QR_TREE); ``a`` is overwritten."""
         import torch
         m, d = a.shape
         r = torch.empty((d, d), dtype=torch.float64, device=a.device)
-        _check(load_library().slso_qr_r(self._h, _ptr(a), m, d, _ptr(r),
-                                        _stream(stream)), self._h)
-        return r
+        used = ctypes.c_int32(-1)
+        _check(load_library().slso_qr_r_path(self._h, _ptr(a), m, d, _ptr(r),
+                                             int(path), ctypes.byref(used),
+                                             _stream(stream)), self._h)
+        return r, used.value
 
     def solve_upper(self, r, b, stream=None):
         """Solve R X = B in place (B is d x k, float64)."""

@@ -40,6 +40,10 @@ enum KernelId : int {
   kKCqRecon,
   kKCqW,
   kKCqUpdate,
+  kKCq2Gram,
+  kKCq2Chol,
+  kKCq2Solve,
+  kKCq2R,
   kKCount
 };
 void prof_begin(int kid, hipStream_t s);
@@ -108,17 +112,35 @@ struct QrStreams {
 };
 
 size_t qr_scratch_bytes(int64_t m, int64_t d);
-// Householder QR of a (m x d, lda = d) in place; r_out (d x d) receives R with
-// a non-negative diagonal and zeros below it. 64-column panels by Cholesky-QR2
-// with Householder reconstruction (k_cqr.hip), the remaining columns by the
-// tree path. *fail (device int) is set to 1 when a panel is too ill-
-// conditioned for Cholesky-QR: a and r_out are then unusable and the caller
-// reruns qr_factor_robust on the original matrix.
+// R factor of a (m x d, lda = d, m >= d) into r_out (d x d, positive
+// diagonal, zeros below it) by Cholesky-QR2 (k_cholqr.hip); a is overwritten
+// by the first-pass Q1. *status (device int): 0 done; 2: r_out not yet
+// written, call qr_factor_finish; 1: Cholesky-QR2 does not apply (a too
+// ill-conditioned or rank deficient): a and r_out are unusable, the caller
+// factors the original matrix with qr_factor_panel.
 void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
-               int* fail, const QrStreams& qs, hipStream_t s);
+               int* status, hipStream_t s);
+// After status 2: the second pass's blocked Cholesky and R = R2 R1 (status
+// set again, 0 or 1).
+void qr_factor_finish(int64_t m, int64_t d, double* r_out, void* scratch,
+                      int* status, hipStream_t s);
+// Householder QR of a in place, r_out as above. 64-column panels by
+// Cholesky-QR2 with Householder reconstruction (k_cqr.hip), the remaining
+// columns by the tree path. *fail (device int) is set to 1 when a panel is
+// too ill-conditioned for Cholesky-QR: a and r_out are then unusable and the
+// caller reruns qr_factor_robust on the original matrix.
+void qr_factor_panel(double* a, int64_t m, int64_t d, double* r_out,
+                     void* scratch, int* fail, const QrStreams& qs,
+                     hipStream_t s);
 // The same factorisation by the tree path alone (every column).
 void qr_factor_robust(double* a, int64_t m, int64_t d, double* r_out,
                       void* scratch, hipStream_t s);
+// whole-matrix Cholesky-QR2 (k_cholqr.hip)
+size_t cholqr2_scratch_bytes(int64_t m, int64_t d);
+void cholqr2_factor(double* a, int64_t m, int64_t d, double* r_out,
+                    void* scratch, int* status, hipStream_t s);
+void cholqr2_finish(int64_t m, int64_t d, double* r_out, void* scratch,
+                    int* status, hipStream_t s);
 // 64-column panel path (k_cqr.hip)
 size_t cqr_scratch_bytes(int64_t m, int64_t d);
 int64_t cqr_panels(int64_t m, int64_t d);

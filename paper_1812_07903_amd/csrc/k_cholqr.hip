@@ -1,0 +1,470 @@
+// R factor of the sketch by Cholesky-QR2 over the whole matrix (Algorithm 2
+// step 2 in QR form; only R is kept):
+//   G1 = A^T A = R1^T R1,   Q1 = A R1^{-1} (in place over A),
+//   G2 = Q1^T Q1 = R2^T R2, R = R2 R1.
+// R has a positive diagonal and equals the R of a Householder QR of A up to
+// the signs of its rows (Fukaya, Nakatsukasa, Yanagisawa & Yamamoto,
+// "CholeskyQR2: a simple and communication-avoiding algorithm for computing a
+// tall-skinny QR factorization", 2014). All the O(m d^2) work is in three
+// passes over the rows on the FP64 MFMA: the two Gram matrices (upper 64 x 64
+// tiles, rows split into chunks, partial tiles summed in a fixed order) and
+// the blocked forward substitution that forms Q1.
+//
+// Validity. Cholesky-QR2 reaches the accuracy of Householder QR when the first
+// pass leaves Q1 well conditioned, i.e. when kappa(A)^2 u is well below one.
+// This is checked a posteriori: with E = G2 - I and e = max |E_ij|,
+//   e <= 1e-9      R2 = I + up(E) (strict upper part plus half the diagonal;
+//                  the neglected F^T F term is below d e^2 <= 1e-15 for
+//                  d <= 1000) and R = R1 + up(E) R1 in one launch;
+//   e <= 0.25 / d  status 2: the caller runs cholqr2_finish, the blocked
+//                  Cholesky of G2 and R = R2 R1;
+//   otherwise, or when a Cholesky pivot of G1 falls to 1e-13 of its diagonal
+//   entry, status 1: the caller factors the (re-formed) matrix with the
+//   Householder paths.
+//
+// Data layout. d x d matrices are kept as nb x nb tiles of 64 x 64 (tile
+// (I, J) at (I nb + J) 4096, row-major inside), padded past d with the
+// identity on the diagonal and zeros elsewhere; only tiles on and above the
+// diagonal are used. The Cholesky of a tiled matrix is right-looking by 64-row
+// block steps, one launch per step: the workgroup of tile (i, j) forms
+// X_i = R_kk^{-T} G_ki and X_j, updates G_ij -= X_i^T X_j, writes R_kj when
+// i = k + 1, and the workgroup of the next diagonal tile factors it at once
+// (Cholesky and inverse in one workgroup), so a step costs one launch.
+#include "internal.h"
+#include "tile64.h"
+
+namespace slso {
+namespace {
+
+constexpr int64_t kT2 = kP * kP;        // elements of a tile
+constexpr double kPivotTol = 1e-13;     // Cholesky pivot / diagonal entry
+constexpr double kNearId = 1e-9;        // max |G2 - I| for the one-launch R2
+
+inline unsigned cdivu(int64_t a, int64_t b) {
+  return static_cast<unsigned>((a + b - 1) / b);
+}
+
+__host__ __device__ inline int64_t tix(int64_t i, int64_t j, int64_t nb) {
+  return (i * nb + j) * kT2;
+}
+
+// t-th tile on or above the diagonal of an n x n tile grid, row by row
+__device__ __forceinline__ void upper_tile(int64_t t, int64_t n, int64_t& i,
+                                           int64_t& j) {
+  int64_t r = 0;
+  while (t >= n - r) {
+    t -= n - r;
+    ++r;
+  }
+  i = r;
+  j = r + t;
+}
+
+// acc -= A B (AT: A^T B) for LDS tiles, see mm64
+template <bool AT>
+__device__ __forceinline__ void mm64_sub(const double* A, const double* B,
+                                         dbl4 (&acc)[4], int lane, int w) {
+  const int p = lane & 15, q = lane >> 4;
+#pragma unroll 4
+  for (int kk = 0; kk < 16; ++kk) {
+    const int k = 4 * kk + q;
+    const double a = AT ? -A[k * kS + 16 * w + p] : -A[(16 * w + p) * kS + k];
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bj] = mfma(a, B[k * kS + 16 * bj + p], acc[bj]);
+  }
+}
+
+// 64 x 64 tile (row-major, ld 64) from global memory in result layout
+__device__ __forceinline__ void ld_acc(dbl4 (&acc)[4], const double* g, int lane,
+                                       int w) {
+  const int p = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[bj][v] = g[(16 * w + 4 * v + q) * kP + 16 * bj + p];
+}
+
+__device__ __forceinline__ void tile_to_global(double* g, const double* T,
+                                               int t) {
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = t + 256 * u;
+    g[e] = T[(e >> 6) * kS + (e & 63)];
+  }
+}
+
+// ---- Gram tiles: partial sums over row chunks ----------------------------------
+// Workgroup g: chunk s = g % S (consecutive workgroups, which the dispatcher
+// spreads over the XCDs, take different chunks), upper tile g / S.
+__global__ void __launch_bounds__(256)
+    gram_part_kernel(const double* __restrict__ A, int64_t lda, int64_t m,
+                     int64_t d, int64_t nb, int64_t S, int64_t chunk,
+                     double* __restrict__ part, unsigned long long* emax,
+                     const int* __restrict__ flag) {
+  __shared__ double TA[kTile];
+  __shared__ double TB[kTile];
+  if (*flag) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t g = blockIdx.x, s = g % S, tt = g / S;
+  const int64_t nt = nb * (nb + 1) / 2;
+  if (g == 0 && t == 0 && emax) *emax = 0ull;
+  int64_t I, J;
+  upper_tile(tt, nb, I, J);
+  const bool diag = I == J;
+  const int64_t ci = I * kP, cj = J * kP;
+  const int64_t ni = d - ci < kP ? d - ci : kP;
+  const int64_t nj = d - cj < kP ? d - cj : kP;
+  const int64_t r0 = s * chunk;
+  const int64_t r1 = m < r0 + chunk ? m : r0 + chunk;
+  dbl4 acc[4];
+  zero4(acc);
+  if (r0 < r1) {
+    double va[16], vb[16];
+    load_regs(va, A + r0 * lda + ci, lda, r1 - r0, ni, t);
+    if (!diag) load_regs(vb, A + r0 * lda + cj, lda, r1 - r0, nj, t);
+    for (int64_t r = r0; r < r1; r += kP) {
+      __syncthreads();
+      store_regs(TA, va, t);
+      if (!diag) store_regs(TB, vb, t);
+      __syncthreads();
+      if (r + kP < r1) {
+        load_regs(va, A + (r + kP) * lda + ci, lda, r1 - r - kP, ni, t);
+        if (!diag) load_regs(vb, A + (r + kP) * lda + cj, lda, r1 - r - kP, nj, t);
+      }
+      mm64<true>(TA, diag ? TA : TB, acc, lane, w);
+    }
+  }
+  store_acc_global(part + (s * nt + tt) * kT2, kP, acc, 1.0, lane, w);
+}
+
+// G tile = sum of its S partial tiles (fixed order); the padded diagonal is
+// set to 1; gdiag receives the diagonal; with emax, max |G - I| over the
+// valid entries (bit patterns of non-negative doubles order like the values,
+// a NaN above every number).
+__global__ void __launch_bounds__(256)
+    gram_reduce_kernel(const double* __restrict__ part, int64_t S, int64_t nb,
+                       int64_t d, double* __restrict__ G,
+                       double* __restrict__ gdiag, unsigned long long* emax,
+                       const int* __restrict__ flag) {
+  if (*flag) return;
+  const int64_t nt = nb * (nb + 1) / 2;
+  const int64_t tt = blockIdx.x >> 4;
+  const int e = static_cast<int>((blockIdx.x & 15) << 8) + threadIdx.x;
+  double v = sum_parts(part + tt * kT2, S, nt * kT2, e);
+  int64_t I, J;
+  upper_tile(tt, nb, I, J);
+  const int64_t gi = I * kP + (e >> 6), gj = J * kP + (e & 63);
+  if (gi == gj && gi >= d) v = 1.0;
+  G[tix(I, J, nb) + e] = v;
+  if (gi == gj) gdiag[gi] = v;
+  if (emax) {
+    double dev = 0.0;
+    if (gi < d && gj < d) dev = fabs(v - (gi == gj ? 1.0 : 0.0));
+    unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(dev));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long ob = __shfl_xor(b, o);
+      b = ob > b ? ob : b;
+    }
+    if ((threadIdx.x & 63) == 0 && b != 0ull) atomicMax(emax, b);
+  }
+}
+
+// ---- blocked Cholesky of a tiled SPD matrix ------------------------------------
+__global__ void __launch_bounds__(256)
+    bchol_first_kernel(const double* __restrict__ G, const double* __restrict__ gdiag,
+                       double tol, double* __restrict__ R,
+                       double* __restrict__ Dinv, int* __restrict__ flag) {
+  __shared__ double TC[kTile];
+  __shared__ double TX[kTile];
+  __shared__ double tmp[4][16][17];
+  __shared__ double lim[kP];
+  __shared__ int bad;
+  if (*flag) return;
+  const int t = threadIdx.x;
+  load_tile(TC, G, kP, kP, kP, t);
+  if (t < kP) lim[t] = tol * gdiag[t];
+  __syncthreads();
+  if (!chol64b(TC, TX, lim, &bad, tmp, t)) {
+    if (t == 0) *flag = 1;
+    return;
+  }
+  tile_to_global(R, TC, t);
+  tile_to_global(Dinv, TX, t);
+}
+
+// Step k: tiles (i, j), k < i <= j, one workgroup each (see the header).
+__global__ void __launch_bounds__(256)
+    bchol_step_kernel(double* __restrict__ G, int64_t nb, int64_t k,
+                      const double* __restrict__ gdiag, double tol,
+                      double* __restrict__ R, double* __restrict__ Dinv,
+                      int* __restrict__ flag) {
+  __shared__ double TI[kTile];
+  __shared__ double TA[kTile];
+  __shared__ double TB[kTile];
+  __shared__ double TC[kTile];
+  __shared__ double tmp[4][16][17];
+  __shared__ double lim[kP];
+  __shared__ int bad;
+  if (*flag) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int64_t i, j;
+  upper_tile(blockIdx.x, nb - k - 1, i, j);
+  i += k + 1;
+  j += k + 1;
+  const bool diag = i == j;
+  load_tile(TI, Dinv + k * kT2, kP, kP, kP, t);
+  load_tile(TA, G + tix(k, i, nb), kP, kP, kP, t);
+  if (!diag) load_tile(TB, G + tix(k, j, nb), kP, kP, kP, t);
+  dbl4 acc[4];
+  ld_acc(acc, G + tix(i, j, nb), lane, w);
+  __syncthreads();
+  dbl4 xa[4], xb[4];
+  zero4(xa);
+  mm64<true>(TI, TA, xa, lane, w);  // X_i = R_kk^{-T} G_ki = R_ki
+  if (!diag) {
+    zero4(xb);
+    mm64<true>(TI, TB, xb, lane, w);
+  }
+  __syncthreads();
+  store_acc(TA, xa, 1.0, lane, w);
+  if (!diag) store_acc(TB, xb, 1.0, lane, w);
+  if (i == k + 1) {
+    if (diag)
+      store_acc_global(R + tix(k, j, nb), kP, xa, 1.0, lane, w);
+    else
+      store_acc_global(R + tix(k, j, nb), kP, xb, 1.0, lane, w);
+  }
+  __syncthreads();
+  mm64_sub<true>(TA, diag ? TA : TB, acc, lane, w);  // G_ij -= X_i^T X_j
+  if (diag && i == k + 1) {
+    store_acc(TC, acc, 1.0, lane, w);
+    if (t < kP) lim[t] = tol * gdiag[i * kP + t];
+    __syncthreads();
+    if (!chol64b(TC, TI, lim, &bad, tmp, t)) {
+      if (t == 0) *flag = 1;
+      return;
+    }
+    tile_to_global(R + tix(i, i, nb), TC, t);
+    tile_to_global(Dinv + i * kT2, TI, t);
+  } else {
+    store_acc_global(G + tix(i, j, nb), kP, acc, 1.0, lane, w);
+  }
+}
+
+// ---- Q1 = A R^{-1} in place, by 64-row stripes ---------------------------------
+// Stripe rows are independent: column block J of the stripe becomes
+// (A_J - sum_{I<J} Q1_I R_IJ) R_JJ^{-1}, blocks in increasing J, each written
+// over A_J once A_J has been read.
+__global__ void __launch_bounds__(256)
+    stripe_solve_kernel(double* __restrict__ A, int64_t lda, int64_t m,
+                        int64_t d, int64_t nb, const double* __restrict__ R,
+                        const double* __restrict__ Dinv,
+                        const int* __restrict__ flag) {
+  __shared__ double TA[kTile];
+  __shared__ double TB[kTile];
+  if (*flag) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int p = lane & 15, q = lane >> 4;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kP;
+  const int64_t nr = m - r0 < kP ? m - r0 : kP;
+  double* As = A + r0 * lda;
+  for (int64_t J = 0; J < nb; ++J) {
+    const int64_t cJ = J * kP;
+    const int64_t nc = d - cJ < kP ? d - cJ : kP;
+    dbl4 acc[4];
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * w + 4 * v + q, col = 16 * bj + p;
+        acc[bj][v] = (row < nr && col < nc) ? As[row * lda + cJ + col] : 0.0;
+      }
+    // blocks I < J are complete (only the last block can be partial)
+    double va[16], vb[16];
+    if (J > 0) {
+      load_regs(va, As, lda, nr, kP, t);
+      load_regs(vb, R + tix(0, J, nb), kP, kP, kP, t);
+    }
+    for (int64_t I = 0; I < J; ++I) {
+      __syncthreads();
+      store_regs(TA, va, t);
+      store_regs(TB, vb, t);
+      __syncthreads();
+      if (I + 1 < J) {
+        load_regs(va, As + (I + 1) * kP, lda, nr, kP, t);
+        load_regs(vb, R + tix(I + 1, J, nb), kP, kP, kP, t);
+      }
+      mm64_sub<false>(TA, TB, acc, lane, w);
+    }
+    load_regs(vb, Dinv + J * kT2, kP, kP, kP, t);
+    __syncthreads();
+    store_acc(TA, acc, 1.0, lane, w);
+    store_regs(TB, vb, t);
+    __syncthreads();
+    dbl4 res[4];
+    zero4(res);
+    mm64<false>(TA, TB, res, lane, w);
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * w + 4 * v + q, col = 16 * bj + p;
+        if (row < nr && col < nc) As[row * lda + cJ + col] = res[bj][v];
+      }
+    // Q1_J is read back by other threads of the workgroup for later blocks
+    __syncthreads();
+  }
+}
+
+// ---- R = R2 R1 into r_out (d x d row-major) ------------------------------------
+// NEAR: F = G2 holds the second Gram matrix; after the checks of the header,
+// R_ij = R1_ij + sum_{i<=l<=j} up(E)_il R1_lj. Otherwise F holds R2 (tiled,
+// from the blocked Cholesky) and R_ij = sum_{i<=l<=j} R2_il R1_lj.
+template <bool NEAR>
+__global__ void __launch_bounds__(256)
+    r_final_kernel(const double* __restrict__ R1, const double* __restrict__ F,
+                   int64_t nb, int64_t d, const unsigned long long* __restrict__ emax,
+                   int* __restrict__ status, double* __restrict__ r_out) {
+  __shared__ double TA[kTile];
+  __shared__ double TB[kTile];
+  if (*status) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int p = lane & 15, q = lane >> 4;
+  const int64_t i = blockIdx.x / nb, j = blockIdx.x % nb;
+  if (NEAR) {
+    const double em = __longlong_as_double(static_cast<long long>(*emax));
+    const bool ok = em <= 0.25 / static_cast<double>(d);  // false for NaN
+    if (!ok || em > kNearId) {
+      if (blockIdx.x == 0 && t == 0) *status = ok ? 2 : 1;
+      return;
+    }
+  }
+  dbl4 acc[4];
+  zero4(acc);
+  if (i <= j) {
+    if (NEAR) ld_acc(acc, R1 + tix(i, j, nb), lane, w);
+    for (int64_t l = i; l <= j; ++l) {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = t + 256 * u;
+        const int a = e >> 6, b = e & 63;
+        double v = F[tix(i, l, nb) + e];
+        if (NEAR) {
+          // up(E): strict upper part of G2 - I and half its diagonal
+          const int64_t gi = i * kP + a, gl = l * kP + b;
+          v = gi < gl ? v : (gi == gl ? 0.5 * (v - 1.0) : 0.0);
+        }
+        TA[a * kS + b] = v;
+        TB[a * kS + b] = R1[tix(l, j, nb) + e];
+      }
+      __syncthreads();
+      mm64<false>(TA, TB, acc, lane, w);
+    }
+  }
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t gi = i * kP + 16 * w + 4 * v + q, gj = j * kP + 16 * bj + p;
+      if (gi < d && gj < d) r_out[gi * d + gj] = gi <= gj ? acc[bj][v] : 0.0;
+    }
+}
+
+struct Cq2 {
+  int64_t nb, nt, S, chunk;
+  double *part, *G, *R1, *R2, *Dinv, *gdiag;
+  unsigned long long* emax;
+};
+
+Cq2 cq2_shape(int64_t m, int64_t d) {
+  Cq2 c{};
+  c.nb = (d + kP - 1) / kP;
+  c.nt = c.nb * (c.nb + 1) / 2;
+  // row chunks: enough workgroups to fill the device twice over, a multiple
+  // of 8 (one chunk per XCD), chunks of at least 256 rows
+  int64_t S = (512 + c.nt - 1) / c.nt;
+  if (S > 1) S = (S + 7) / 8 * 8;
+  const int64_t smax = (m + 255) / 256;
+  if (S > smax) S = smax;
+  if (S < 1) S = 1;
+  const int64_t blocks = (m + kP - 1) / kP;
+  c.chunk = (blocks + S - 1) / S * kP;
+  c.S = S;
+  return c;
+}
+
+Cq2 cq2_carve(void* base, int64_t m, int64_t d) {
+  Cq2 c = cq2_shape(m, d);
+  double* p = static_cast<double*>(base);
+  c.part = p;  p += c.S * c.nt * kT2;
+  c.G = p;     p += c.nb * c.nb * kT2;
+  c.R1 = p;    p += c.nb * c.nb * kT2;
+  c.R2 = p;    p += c.nb * c.nb * kT2;
+  c.Dinv = p;  p += c.nb * kT2;
+  c.gdiag = p; p += c.nb * kP;
+  c.emax = reinterpret_cast<unsigned long long*>(p);
+  return c;
+}
+
+void gram_tiles(const double* a, int64_t m, int64_t d, const Cq2& c,
+                bool with_emax, int* flag, hipStream_t s) {
+  unsigned long long* em = with_emax ? c.emax : nullptr;
+  prof_begin(kKCq2Gram, s);
+  gram_part_kernel<<<static_cast<unsigned>(c.nt * c.S), 256, 0, s>>>(
+      a, d, m, d, c.nb, c.S, c.chunk, c.part, em, flag);
+  gram_reduce_kernel<<<static_cast<unsigned>(c.nt * 16), 256, 0, s>>>(
+      c.part, c.S, c.nb, d, c.G, c.gdiag, em, flag);
+  prof_end(kKCq2Gram, s);
+}
+
+void bchol(const Cq2& c, double* R, int* flag, hipStream_t s) {
+  prof_begin(kKCq2Chol, s);
+  bchol_first_kernel<<<1, 256, 0, s>>>(c.G, c.gdiag, kPivotTol, R, c.Dinv, flag);
+  for (int64_t k = 0; k + 1 < c.nb; ++k) {
+    const int64_t n = c.nb - k - 1;
+    bchol_step_kernel<<<static_cast<unsigned>(n * (n + 1) / 2), 256, 0, s>>>(
+        c.G, c.nb, k, c.gdiag, kPivotTol, R, c.Dinv, flag);
+  }
+  prof_end(kKCq2Chol, s);
+}
+
+}  // namespace
+
+size_t cholqr2_scratch_bytes(int64_t m, int64_t d) {
+  const Cq2 c = cq2_shape(m, d);
+  return static_cast<size_t>(c.S * c.nt * kT2 + 3 * c.nb * c.nb * kT2 +
+                             c.nb * kT2 + c.nb * kP + 8) *
+         sizeof(double);
+}
+
+void cholqr2_factor(double* a, int64_t m, int64_t d, double* r_out,
+                    void* scratch, int* status, hipStream_t s) {
+  const Cq2 c = cq2_carve(scratch, m, d);
+  launch_fill_i32(status, 1, 0, s);
+  gram_tiles(a, m, d, c, false, status, s);
+  bchol(c, c.R1, status, s);
+  prof_begin(kKCq2Solve, s);
+  stripe_solve_kernel<<<cdivu(m, kP), 256, 0, s>>>(a, d, m, d, c.nb, c.R1,
+                                                    c.Dinv, status);
+  prof_end(kKCq2Solve, s);
+  gram_tiles(a, m, d, c, true, status, s);
+  prof_begin(kKCq2R, s);
+  r_final_kernel<true><<<static_cast<unsigned>(c.nb * c.nb), 256, 0, s>>>(
+      c.R1, c.G, c.nb, d, c.emax, status, r_out);
+  prof_end(kKCq2R, s);
+}
+
+void cholqr2_finish(int64_t m, int64_t d, double* r_out, void* scratch,
+                    int* status, hipStream_t s) {
+  const Cq2 c = cq2_carve(scratch, m, d);
+  launch_fill_i32(status, 1, 0, s);
+  bchol(c, c.R2, status, s);
+  prof_begin(kKCq2R, s);
+  r_final_kernel<false><<<static_cast<unsigned>(c.nb * c.nb), 256, 0, s>>>(
+      c.R1, c.R2, c.nb, d, c.emax, status, r_out);
+  prof_end(kKCq2R, s);
+}
+
+}  // namespace slso

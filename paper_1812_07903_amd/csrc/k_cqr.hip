@@ -34,427 +34,16 @@
 // D[4v + l/16][l%16]. 64 x 64 tiles in LDS have a row stride of 65 doubles;
 // wave w of a 256-thread workgroup owns tile rows 16w .. 16w + 15.
 #include "internal.h"
+#include "tile64.h"
 
 namespace slso {
 namespace {
 
-constexpr int kP = 64;     // panel width
-constexpr int kS = 65;     // LDS row stride of a 64 x 64 tile
-constexpr int kTile = kP * kS;
 constexpr int kRG = 128;   // rows per workgroup: Gram and Q1 passes
 constexpr int kRZ = 512;   // rows per part: Q1^T C
 constexpr int kRU = 256;   // rows per workgroup: trailing update
 constexpr double kTol1 = 1e-10;  // pivot / column squared norm, first pass
 constexpr double kTol2 = 1e-10;  // pivot, second pass (G2 ~ I)
-
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ dbl4 mfma(double a, double b, dbl4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ void zero4(dbl4 (&acc)[4]) {
-#pragma unroll
-  for (int bj = 0; bj < 4; ++bj) acc[bj] = dbl4{0.0, 0.0, 0.0, 0.0};
-}
-
-// acc[bj] += A(16w + i, k) B(k, 16bj + j) over k < 64, both from LDS tiles;
-// A(i, k) = A[i][k], or A[k][i] when AT.
-template <bool AT>
-__device__ __forceinline__ void mm64(const double* A, const double* B,
-                                     dbl4 (&acc)[4], int lane, int w) {
-  const int p = lane & 15, q = lane >> 4;
-#pragma unroll 4
-  for (int kk = 0; kk < 16; ++kk) {
-    const int k = 4 * kk + q;
-    const double a = AT ? A[k * kS + 16 * w + p] : A[(16 * w + p) * kS + k];
-#pragma unroll
-    for (int bj = 0; bj < 4; ++bj) acc[bj] = mfma(a, B[k * kS + 16 * bj + p], acc[bj]);
-  }
-}
-
-// tile[16w + 4v + l/16][16bj + l%16] = sc * acc[bj][v]
-__device__ __forceinline__ void store_acc(double* tile, const dbl4 (&acc)[4],
-                                          double sc, int lane, int w) {
-  const int p = lane & 15, q = lane >> 4;
-#pragma unroll
-  for (int bj = 0; bj < 4; ++bj)
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      tile[(16 * w + 4 * v + q) * kS + 16 * bj + p] = sc * acc[bj][v];
-}
-
-__device__ __forceinline__ void store_acc_global(double* g, int64_t ldg,
-                                                 const dbl4 (&acc)[4], double sc,
-                                                 int lane, int w) {
-  const int p = lane & 15, q = lane >> 4;
-#pragma unroll
-  for (int bj = 0; bj < 4; ++bj)
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      g[(16 * w + 4 * v + q) * ldg + 16 * bj + p] = sc * acc[bj][v];
-}
-
-// 64 x 64 block of a row-major matrix: v[u] = a[i][j] for element
-// e = t + 256 u (i = e / 64, j = e % 64); rows >= nr and columns >= nc read as
-// zero. All sixteen loads are issued before any is used.
-__device__ __forceinline__ void load_regs(double (&v)[16], const double* a,
-                                          int64_t lda, int64_t nr, int64_t nc,
-                                          int t) {
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int e = t + 256 * u;
-    const int i = e >> 6, j = e & 63;
-    v[u] = (i < nr && j < nc) ? a[i * lda + j] : 0.0;
-  }
-}
-
-__device__ __forceinline__ void store_regs(double* tile, const double (&v)[16],
-                                           int t) {
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int e = t + 256 * u;
-    tile[(e >> 6) * kS + (e & 63)] = v[u];
-  }
-}
-
-__device__ __forceinline__ void load_tile(double* tile, const double* a,
-                                          int64_t lda, int64_t nr, int64_t nc,
-                                          int t) {
-  double v[16];
-  load_regs(v, a, lda, nr, nc, t);
-  store_regs(tile, v, t);
-}
-
-// 16 x 16 products on one wave, acc += A B with A(i, k) = A[i lda + k]
-// (mm16) or A[k lda + i] (mm16t), B(k, j) = B[k ldb + j].
-__device__ __forceinline__ dbl4 mm16(const double* A, int lda, const double* B,
-                                     int ldb, dbl4 acc, int lane) {
-  const int p = lane & 15, q = lane >> 4;
-#pragma unroll
-  for (int kk = 0; kk < 4; ++kk)
-    acc = mfma(A[p * lda + 4 * kk + q], B[(4 * kk + q) * ldb + p], acc);
-  return acc;
-}
-__device__ __forceinline__ dbl4 mm16t(const double* A, int lda, const double* B,
-                                      int ldb, dbl4 acc, int lane) {
-  const int p = lane & 15, q = lane >> 4;
-#pragma unroll
-  for (int kk = 0; kk < 4; ++kk)
-    acc = mfma(A[(4 * kk + q) * lda + p], B[(4 * kk + q) * ldb + p], acc);
-  return acc;
-}
-
-// 16 x 16 block in result layout: element (4v + l/16, l%16)
-__device__ __forceinline__ dbl4 ld16(const double* B, int lane) {
-  const int p = lane & 15, q = lane >> 4;
-  dbl4 r;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) r[v] = B[(4 * v + q) * kS + p];
-  return r;
-}
-__device__ __forceinline__ void st16(double* B, dbl4 x, int lane) {
-  const int p = lane & 15, q = lane >> 4;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) B[(4 * v + q) * kS + p] = x[v];
-}
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-__device__ __forceinline__ double readlane_d(double x, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
-                          __builtin_amdgcn_readlane(__double2loint(x), l));
-}
-
-// 1/x and 1/sqrt(x) from the hardware approximations refined by two Newton
-// steps (full double precision, shorter chains than the library sequences).
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return r;
-}
-__device__ __forceinline__ double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double hx = 0.5 * x;
-  y = y * fma(-hx * y, y, 1.5);
-  y = y * fma(-hx * y, y, 1.5);
-  return y;
-}
-
-// ---- 16 x 16 factorisations on one wave (lane l < 16 owns column l) ----------
-// Triangular inverses of a 16 x 16 block B by substitution: lanes 0..15
-// compute column l of L^{-1} for the unit lower triangle L held below B's
-// diagonal (when Li is given); lanes 16..31 compute column l - 16 of U^{-1}
-// for the upper triangle U on and above it (inv[i] = 1 / U_ii). The U lanes
-// hold their column reversed (b[r] = X[15 - r][c]), so both substitutions
-// advance together: step s finalises entry s and updates the entries after
-// it. One step's coefficients are loaded while the previous step computes.
-__device__ __forceinline__ void tri_inv16(const double* B, double* Li, double* Ui,
-                                          const double* inv, int l) {
-  const bool isL = l < 16 && Li != nullptr;
-  const bool isU = l >= 16 && l < 32;
-  const int c = l & 15;
-  // coefficient (r, s), r > s: L[r][s] = B[r][s] for the L lanes,
-  // U[15 - r][15 - s] = B[15 - r][15 - s] for the U lanes
-  const int base = l >= 16 ? 15 * kS + 15 : 0;
-  const int sgn = l >= 16 ? -1 : 1;
-  const double* Bb = B + base;
-  double b[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r)
-    b[r] = (isL && r == c) || (isU && 15 - r == c) ? 1.0 : 0.0;
-  double m[16];
-#pragma unroll
-  for (int r = 1; r < 16; ++r) m[r] = Bb[sgn * (r * kS)];
-#pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    const double x = isU ? b[s] * inv[15 - s] : b[s];
-    b[s] = x;
-    double mn[16];
-#pragma unroll
-    for (int r = s + 2; r < 16; ++r) mn[r] = Bb[sgn * (r * kS + s + 1)];
-#pragma unroll
-    for (int r = s + 1; r < 16; ++r) b[r] -= m[r] * x;
-#pragma unroll
-    for (int r = s + 2; r < 16; ++r) m[r] = mn[r];
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  if (isL) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) Li[r * kS + c] = b[r];
-  }
-  if (isU) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) Ui[(15 - r) * kS + c] = b[r];
-  }
-}
-
-// Cholesky of the symmetric block B (upper triangle read): B <- R (zeros
-// below), Xi <- R^{-1}; s16 (16 doubles of LDS) is scratch. False (the same
-// in every lane) when a pivot is not above lim[j].
-__device__ __forceinline__ bool chol16w(double* B, double* Xi, const double* lim,
-                                        double* s16, int lane) {
-  const int l = lane;
-  bool ok = true;
-  {
-    double gc[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i)
-      gc[i] = l < 16 ? (i <= l ? B[i * kS + l] : B[l * kS + i]) : 0.0;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const double piv = readlane_d(gc[j], j);
-      ok = ok && (piv > lim[j]);
-      const double pv = ok ? piv : 1.0;
-      const double ir = rsq_nr(pv);
-      if (l == 0) s16[j] = ir;
-      const double rjl = l > j ? gc[j] * ir : (l == j ? pv * ir : 0.0);
-      gc[j] = rjl;  // row j of R from here on
-#pragma unroll
-      for (int i = j + 1; i < 16; ++i) gc[i] -= readlane_d(rjl, i) * rjl;
-    }
-    wave_sync();
-    if (l < 16) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) B[i * kS + l] = gc[i];
-    }
-  }
-  wave_sync();
-  tri_inv16(B, nullptr, Xi, s16, l);
-  wave_sync();
-  return ok;
-}
-
-// Sign-choosing LU without pivoting of the block B: B - diag(sg) = L U with
-// sg_i = -sign(current pivot), so |U_ii| >= 1. B <- U on and above the
-// diagonal and the multipliers of L below; Li <- L^{-1}; Ui <- U^{-1}; s16
-// (16 doubles of LDS) is scratch.
-__device__ __forceinline__ void lu16w(double* B, double* Li, double* Ui,
-                                      double* sg, double* s16, int lane) {
-  const int l = lane;
-  {
-    double wc[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) wc[r] = l < 16 ? B[r * kS + l] : 0.0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const double pv = readlane_d(wc[i], i);
-      const double sgi = pv >= 0.0 ? -1.0 : 1.0;
-      const double piv = pv - sgi;
-      const double ip = rcp_nr(piv);
-      if (l == 0) {
-        sg[i] = sgi;
-        s16[i] = ip;
-      }
-      if (l == i) {
-        wc[i] = piv;
-#pragma unroll
-        for (int r = i + 1; r < 16; ++r) wc[r] *= ip;
-      }
-      const double uil = wc[i];
-#pragma unroll
-      for (int r = i + 1; r < 16; ++r) {
-        const double mr = readlane_d(wc[r], i);
-        if (l > i) wc[r] -= mr * uil;
-      }
-    }
-    // lane l: wc[r] = U[r][l] for r <= l, L[r][l] for r > l
-    wave_sync();
-    if (l < 16) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) B[r * kS + l] = wc[r];
-    }
-  }
-  wave_sync();
-  tri_inv16(B, Li, Ui, s16, l);
-  wave_sync();
-}
-
-// Off-diagonal blocks of X = R^{-1} for upper-triangular R, given X's
-// diagonal blocks (and zeros below them): X_ij = -X_ii sum_{k=i+1..j} R_ik X_kj.
-__device__ __forceinline__ void inv_offdiag(const double* R, double* X, double (*tmp)[16][17],
-                            int t) {
-  const int lane = t & 63, w = t >> 6, p = lane & 15, q = lane >> 4;
-#pragma unroll 1
-  for (int dist = 1; dist < 4; ++dist) {
-    const int i = w, j = w + dist;
-    if (j < 4) {
-      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-      for (int k = i + 1; k <= j; ++k)
-        acc = mm16(&R[16 * i * kS + 16 * k], kS, &X[16 * k * kS + 16 * j], kS,
-                   acc, lane);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) tmp[w][4 * v + q][p] = acc[v];
-      wave_sync();
-      dbl4 acc2 = {0.0, 0.0, 0.0, 0.0};
-      acc2 = mm16(&X[16 * i * kS + 16 * i], kS, &tmp[w][0][0], 17, acc2, lane);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) X[(16 * i + 4 * v + q) * kS + 16 * j + p] = -acc2[v];
-      wave_sync();
-    }
-    __syncthreads();
-  }
-}
-
-__device__ __forceinline__ void zero_tile(double* X, int t) {
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int e = t + 256 * u;
-    X[(e >> 6) * kS + (e & 63)] = 0.0;
-  }
-}
-
-// Blocked upper Cholesky of the symmetric tile G (upper triangle read) with
-// 16 x 16 diagonal factorisations on wave 0 and MFMA block updates. On
-// success G holds R (zeros below) and X holds R^{-1}. False, in every
-// thread, when a pivot is not above lim[j].
-__device__ __forceinline__ bool chol64b(double* G, double* X, const double* lim, int* bad,
-                        double (*tmp)[16][17], int t) {
-  const int lane = t & 63, w = t >> 6;
-  zero_tile(X, t);
-  if (t == 0) *bad = 0;
-  __syncthreads();
-#pragma unroll 1
-  for (int k = 0; k < 4; ++k) {
-    const int o = 16 * k;
-    if (w == 0) {
-      const bool ok = chol16w(&G[o * kS + o], &X[o * kS + o], lim + o,
-                              &tmp[0][0][0], lane);
-      if (!ok && lane == 0) *bad = 1;
-    }
-    __syncthreads();
-    if (*bad) return false;
-    // row block k: R_kj = R_kk^{-T} G_kj
-    if (w < 3 - k) {
-      const int j = k + 1 + w;
-      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-      acc = mm16t(&X[o * kS + o], kS, &G[o * kS + 16 * j], kS, acc, lane);
-      st16(&G[o * kS + 16 * j], acc, lane);
-    }
-    __syncthreads();
-    // trailing blocks G_ij -= R_ki^T R_kj, k < i <= j
-    int idx = 0;
-    for (int i = k + 1; i < 4; ++i)
-      for (int j = i; j < 4; ++j, ++idx) {
-        if ((idx & 3) != w) continue;
-        dbl4 acc = ld16(&G[16 * i * kS + 16 * j], lane);
-        dbl4 sub = {0.0, 0.0, 0.0, 0.0};
-        sub = mm16t(&G[o * kS + 16 * i], kS, &G[o * kS + 16 * j], kS, sub, lane);
-        st16(&G[16 * i * kS + 16 * j], acc - sub, lane);
-      }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int e = t + 256 * u;
-    const int i = e >> 6, c = e & 63;
-    if (i > c) G[i * kS + c] = 0.0;
-  }
-  __syncthreads();
-  inv_offdiag(G, X, tmp, t);
-  return true;
-}
-
-// Blocked sign-choosing LU of the tile Q (see lu16w): Q <- U on and above
-// the diagonal, L's multipliers below; Li and Ui receive the inverses of L's
-// and U's diagonal blocks (the caller zeroes them first); sg the signs.
-__device__ __forceinline__ void lu64b(double* Q, double* Li, double* Ui, double* sg, double* s16,
-                      int t) {
-  const int lane = t & 63, w = t >> 6;
-#pragma unroll 1
-  for (int k = 0; k < 4; ++k) {
-    const int o = 16 * k;
-    if (w == 0) lu16w(&Q[o * kS + o], &Li[o * kS + o], &Ui[o * kS + o], sg + o,
-                      s16, lane);
-    __syncthreads();
-    // U_kj = L_kk^{-1} Q_kj (j > k) and L_ik = Q_ik U_kk^{-1} (i > k)
-    const int nb = 3 - k;
-    for (int idx = w; idx < 2 * nb; idx += 4) {
-      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-      if (idx < nb) {
-        const int j = k + 1 + idx;
-        acc = mm16(&Li[o * kS + o], kS, &Q[o * kS + 16 * j], kS, acc, lane);
-        st16(&Q[o * kS + 16 * j], acc, lane);
-      } else {
-        const int i = k + 1 + idx - nb;
-        acc = mm16(&Q[16 * i * kS + o], kS, &Ui[o * kS + o], kS, acc, lane);
-        st16(&Q[16 * i * kS + o], acc, lane);
-      }
-    }
-    __syncthreads();
-    // trailing Q_ij -= L_ik U_kj, i, j > k
-    for (int idx = w; idx < nb * nb; idx += 4) {
-      const int i = k + 1 + idx / nb, j = k + 1 + idx % nb;
-      dbl4 acc = ld16(&Q[16 * i * kS + 16 * j], lane);
-      dbl4 sub = {0.0, 0.0, 0.0, 0.0};
-      sub = mm16(&Q[16 * i * kS + o], kS, &Q[o * kS + 16 * j], kS, sub, lane);
-      st16(&Q[16 * i * kS + 16 * j], acc - sub, lane);
-    }
-    __syncthreads();
-  }
-}
-
-// sum of nparts 64 x 64 matrices (fixed order), element e; sixteen loads in
-// flight
-__device__ __forceinline__ double sum_parts(const double* parts, int64_t nparts,
-                                            int64_t stride, int64_t e) {
-  double s = 0.0;
-  int64_t pp = 0;
-  for (; pp + 16 <= nparts; pp += 16) {
-    double v[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = parts[(pp + u) * stride + e];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) s += v[u];
-  }
-  for (; pp < nparts; ++pp) s += parts[pp * stride + e];
-  return s;
-}
 
 // ---- K1: partial Gram matrices P^T P of row blocks ----------------------------
 __global__ void __launch_bounds__(256)

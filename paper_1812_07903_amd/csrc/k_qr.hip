@@ -32,6 +32,8 @@
 // B[l/16][l%16], result register v of lane l = D[4v + l/16][l%16]). The result
 // layout of W1 = Y^T C is the B-operand layout of T^T W1 and of C - Y W2, so
 // the 16 x 16 intermediates never leave registers.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace slso {
@@ -752,11 +754,22 @@ size_t tree_part(int64_t m) {
 }  // namespace
 
 size_t qr_scratch_bytes(int64_t m, int64_t d) {
-  return tree_part(m) + cqr_scratch_bytes(m, d) + 512;
+  return tree_part(m) +
+         std::max(cqr_scratch_bytes(m, d), cholqr2_scratch_bytes(m, d)) + 512;
 }
-
 void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
-               int* fail, const QrStreams& qs, hipStream_t s) {
+               int* status, hipStream_t s) {
+  cholqr2_factor(a, m, d, r_out, static_cast<char*>(scratch) + tree_part(m),
+                 status, s);
+}
+void qr_factor_finish(int64_t m, int64_t d, double* r_out, void* scratch,
+                      int* status, hipStream_t s) {
+  cholqr2_finish(m, d, r_out, static_cast<char*>(scratch) + tree_part(m),
+                 status, s);
+}
+void qr_factor_panel(double* a, int64_t m, int64_t d, double* r_out,
+                     void* scratch, int* fail, const QrStreams& qs,
+                     hipStream_t s) {
   launch_fill_i32(fail, 1, 0, s);
   void* cws = static_cast<char*>(scratch) + tree_part(m);
   const int64_t np = cqr_panels(m, d);
@@ -764,7 +777,6 @@ void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
   tree_panels(a, m, d, 64 * np, scratch, s);
   extract_r(a, d, r_out, s);
 }
-
 void qr_factor_robust(double* a, int64_t m, int64_t d, double* r_out,
                       void* scratch, hipStream_t s) {
   tree_panels(a, m, d, 0, scratch, s);

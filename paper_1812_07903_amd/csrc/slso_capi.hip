@@ -463,16 +463,18 @@ int slso_sketch(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   return check_launch(c, "slso_sketch");
 }
 
-int slso_qr_r(slso_ctx* c, double* a, int64_t m, int64_t d, double* r_out,
-              void* stream) {
+int slso_qr_r_path(slso_ctx* c, double* a, int64_t m, int64_t d,
+                   double* r_out, int path, int32_t* path_used, void* stream) {
   if (!c) return SLSO_EINVAL;
   if (!a || !r_out || d < 1 || m < d)
     return set_err(c, SLSO_EINVAL, "need a, r_out and m >= d >= 1");
+  if (path < SLSO_QR_AUTO || path > SLSO_QR_TREE)
+    return set_err(c, SLSO_EINVAL, "unknown QR path");
   SLSO_HIP(c, hipSetDevice(c->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   Sizer z;
   z.take<char>(qr_scratch_bytes(m, d));
-  z.take<double>(m * d);  // copy of a for the fallback
+  z.take<double>(m * d);  // copy of a for the fallbacks
   z.take<int>(64);
   int st = ensure_ws(c, z.off);
   if (st) return st;
@@ -480,19 +482,53 @@ int slso_qr_r(slso_ctx* c, double* a, int64_t m, int64_t d, double* r_out,
   Arena ar{static_cast<char*>(c->ws)};
   void* qws = ar.take<char>(qr_scratch_bytes(m, d));
   double* copy = ar.take<double>(m * d);
-  int* fail = ar.take<int>(64);
+  int* status = ar.take<int>(64);
   const size_t bytes = static_cast<size_t>(m * d) * sizeof(double);
-  SLSO_HIP(c, hipMemcpyAsync(copy, a, bytes, hipMemcpyDeviceToDevice, s));
-  qr_factor(a, m, d, r_out, qws, fail, c->qs, s);
-  if ((st = check_launch(c, "slso_qr_r"))) return st;
   int* hf = static_cast<int*>(c->host_buf);
-  SLSO_HIP(c, hipMemcpyAsync(hf, fail, sizeof(int), hipMemcpyDeviceToHost, s));
-  SLSO_HIP(c, hipStreamSynchronize(s));
-  if (*hf) {
-    SLSO_HIP(c, hipMemcpyAsync(a, copy, bytes, hipMemcpyDeviceToDevice, s));
-    qr_factor_robust(a, m, d, r_out, qws, s);
+  auto read_status = [&]() -> int {
+    SLSO_HIP(c, hipMemcpyAsync(hf, status, sizeof(int), hipMemcpyDeviceToHost, s));
+    SLSO_HIP(c, hipStreamSynchronize(s));
+    return SLSO_OK;
+  };
+  if (path != SLSO_QR_TREE)
+    SLSO_HIP(c, hipMemcpyAsync(copy, a, bytes, hipMemcpyDeviceToDevice, s));
+  int used = path;
+  bool done = false;
+  if (path == SLSO_QR_AUTO) {
+    qr_factor(a, m, d, r_out, qws, status, s);
+    if ((st = check_launch(c, "slso_qr_r"))) return st;
+    if ((st = read_status())) return st;
+    if (*hf == 2) {
+      qr_factor_finish(m, d, r_out, qws, status, s);
+      if ((st = check_launch(c, "slso_qr_r"))) return st;
+      if ((st = read_status())) return st;
+      used = SLSO_QR_CHOLQR2_FULL;
+    } else {
+      used = SLSO_QR_CHOLQR2;
+    }
+    done = *hf == 0;
   }
+  if (!done && path != SLSO_QR_TREE) {
+    if (path == SLSO_QR_AUTO)
+      SLSO_HIP(c, hipMemcpyAsync(a, copy, bytes, hipMemcpyDeviceToDevice, s));
+    qr_factor_panel(a, m, d, r_out, qws, status, c->qs, s);
+    if ((st = check_launch(c, "slso_qr_r"))) return st;
+    if ((st = read_status())) return st;
+    used = SLSO_QR_PANEL;
+    done = *hf == 0;
+    if (!done) SLSO_HIP(c, hipMemcpyAsync(a, copy, bytes, hipMemcpyDeviceToDevice, s));
+  }
+  if (!done) {
+    qr_factor_robust(a, m, d, r_out, qws, s);
+    used = SLSO_QR_TREE;
+  }
+  if (path_used) *path_used = used;
   return check_launch(c, "slso_qr_r");
+}
+
+int slso_qr_r(slso_ctx* c, double* a, int64_t m, int64_t d, double* r_out,
+              void* stream) {
+  return slso_qr_r_path(c, a, m, d, r_out, SLSO_QR_AUTO, nullptr, stream);
 }
 
 int slso_solve_upper(slso_ctx* c, const double* r, int64_t d, double* b,
@@ -605,16 +641,14 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   // The QR's 64-column panels use Cholesky-QR2; when one is too ill-
   // conditioned for it (flags[2]), the sketch is formed again and factored
   // column by column.
-  auto factor = [&](bool robust) {
+  auto sketch = [&]() {
     if (gauss)
       launch_gauss_sketch(X->values, X->dtype, n, d, X->ld, X->col_scale, seed,
                           r, dscale, static_cast<float*>(gpart), sx, s);
     else
       enqueue_countsketch(X, seed, r, sb, rowfac, sx, s);
-    if (robust)
-      qr_factor_robust(sx, r, d, RS, qws, s);
-    else
-      qr_factor(sx, r, d, RS, qws, flags + 2, c->qs, s);
+  };
+  auto post = [&]() {
     launch_diag_stats(RS, d, dstat, s);
     if (refine) {
       launch_fill_i32(flags + 1, 1, 0, s);
@@ -640,19 +674,38 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
     SLSO_HIP(c, hipStreamSynchronize(s));
     std::memcpy(ds, hb, sizeof(ds));
     std::memcpy(fl, hb + 64, sizeof(fl));
-    return SLSO_OK;
+    return check_launch(c, "slso_leverage: sketch/QR");
   };
-  factor(false);
-  if ((st = check_launch(c, "slso_leverage: sketch/QR"))) return st;
+  // The sketch's R by Cholesky-QR2 (which overwrites the sketch); when that
+  // does not apply (flags[2] = 1: the sketch is too ill-conditioned), the
+  // sketch is formed again and factored by the Householder panel path, and
+  // should that fail too, column by column.
+  int32_t info_flags = 0;
+  sketch();
+  qr_factor(sx, r, d, RS, qws, flags + 2, s);
+  post();
   if ((st = readback())) return st;
   if (fl[0]) return set_err(c, SLSO_ENONFINITE, "X holds Inf or NaN");
-  const bool qr_fallback = fl[2] != 0;
-  if (qr_fallback) {
-    factor(true);
-    if ((st = check_launch(c, "slso_leverage: sketch/QR"))) return st;
+  if (fl[2] == 2) {
+    info_flags |= SLSO_INFO_QR_SECOND_CHOLESKY;
+    qr_factor_finish(r, d, RS, qws, flags + 2, s);
+    post();
     if ((st = readback())) return st;
   }
-  int32_t info_flags = 0;
+  if (fl[2] != 0) {
+    info_flags |= SLSO_INFO_QR_HOUSEHOLDER;
+    sketch();
+    qr_factor_panel(sx, r, d, RS, qws, flags + 2, c->qs, s);
+    post();
+    if ((st = readback())) return st;
+    if (fl[2] != 0) {
+      info_flags |= SLSO_INFO_QR_TREE;
+      sketch();
+      qr_factor_robust(sx, r, d, RS, qws, s);
+      post();
+      if ((st = readback())) return st;
+    }
+  }
   const double* R = RS;
   double dmin = ds[0], dmax = ds[1];
   if (refine) {
@@ -783,7 +836,8 @@ const char* slso_profile_name(int id) {
       "hash_pack", "sort_hist", "sort_scan", "sort_scatter", "bucket_offsets",
       "colmax", "countsketch", "qr_node", "qr_update", "qr_extract", "trsm",
       "score", "gaussian", "gauss_sketch", "gram", "cholesky", "cq_gram",
-      "cq_sum", "cq_chol", "cq_q1", "cq_z", "cq_recon", "cq_w", "cq_update"};
+      "cq_sum", "cq_chol", "cq_q1", "cq_z", "cq_recon", "cq_w", "cq_update", "cq2_gram",
+      "cq2_chol", "cq2_solve", "cq2_r"};
   if (id < 0 || id >= slso::kKCount) return "";
   return names[id];
 }

@@ -191,7 +191,10 @@ def test_refine_falls_back_on_rank_deficient_input(slso, ctx):
     xt = dev(x)
     got, info = ctx.leverage(xt, 2, 512, 16, sketch=slso.GAUSSIAN, refine=True)
     base, binfo = ctx.leverage(xt, 2, 512, 16, sketch=slso.GAUSSIAN)
-    assert info["flags"] == slso.INFO_REFINE_FAILED
+    assert info["flags"] & slso.INFO_REFINE_FAILED
+    # the zero column makes the sketch rank deficient as well: Cholesky-QR2
+    # does not apply and its R comes from a Householder path
+    assert info["flags"] & slso.INFO_QR_HOUSEHOLDER
     assert info["rank"] == binfo["rank"] == 39
     assert np.array_equal(host(got), host(base))
 

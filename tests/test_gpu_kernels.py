@@ -128,14 +128,20 @@ def test_countsketch_csr_bit_exact(slso, ctx, n, d, r):
 # ---- QR ------------------------------------------------------------------------
 @pytest.mark.parametrize("m,d", [(64, 64), (100, 37), (256, 32), (257, 33),
                                  (1000, 96), (3000, 200), (5000, 64),
-                                 (70000, 40), (2048, 512)])
+                                 (70000, 40), (2048, 512), (16384, 784),
+                                 (4099, 833)])
 def test_qr_r_matches_householder(slso, ctx, m, d):
+    """Cholesky-QR2 over the whole matrix (ragged row chunks and stripes,
+    d below, at and past a multiple of 64)."""
     rng = np.random.default_rng(m * 7 + d)
     a = rng.standard_normal((m, d)) * np.exp(rng.standard_normal(d))[None, :]
-    r = host(ctx.qr_r(dev(a.copy())))
+    r, used = ctx.qr_r_path(dev(a.copy()))
+    r = host(r)
     ref = olv.qr_r(a)
+    assert used == slso.QR_CHOLQR2
     assert np.all(np.diag(r) >= 0) and np.all(np.tril(r, -1) == 0)
     err = np.abs(r - ref).max() / np.abs(ref).max()
+    print(f"[qr cholqr2 {m}x{d}] rel err {err:.2e}", flush=True)
     assert err < 1e-12, err
 
 
@@ -143,48 +149,82 @@ def test_qr_r_matches_householder(slso, ctx, m, d):
                                  (16384, 784), (70001, 128), (256, 256),
                                  (4096, 192)])
 def test_qr_r_panel_path_matches_householder(slso, ctx, m, d):
-    """Shapes with d >= 64 go through the 64-column Cholesky-QR2 panels
-    (ragged row blocks, ragged trailing columns, d a multiple of 64, square)."""
+    """The Householder path with 64-column Cholesky-QR2 panels (ragged row
+    blocks, ragged trailing columns, d a multiple of 64, square)."""
     rng = np.random.default_rng(m + 3 * d)
     a = rng.standard_normal((m, d)) * np.exp(rng.standard_normal(d))[None, :]
-    r = host(ctx.qr_r(dev(a.copy())))
+    r, used = ctx.qr_r_path(dev(a.copy()), slso.QR_PANEL)
+    r = host(r)
     ref = olv.qr_r(a)
+    assert used == slso.QR_PANEL
     assert np.all(np.diag(r) >= 0) and np.all(np.tril(r, -1) == 0)
     err = np.abs(r - ref).max() / np.abs(ref).max()
     print(f"[qr panel {m}x{d}] rel err {err:.2e}", flush=True)
     assert err < 1e-12, err
 
 
-@pytest.mark.parametrize("kappa", [1e2, 5e4])
-def test_qr_r_ill_conditioned_panel(slso, ctx, kappa):
-    """First 64-column panel with condition number kappa: at 5e4 the Gram of
-    the first Cholesky-QR pass is still factorable, but the second pass is
-    not close enough to the identity for its near-identity form, so the
-    blocked Cholesky runs. R is compared through R^T R = A^T A (backward
-    error), the meaningful measure once kappa is large."""
-    rng = np.random.default_rng(int(kappa))
-    m, d = 3000, 160
-    u, _ = np.linalg.qr(rng.standard_normal((m, 64)))
-    v, _ = np.linalg.qr(rng.standard_normal((64, 64)))
-    s = np.logspace(0, -np.log10(kappa), 64)
+@pytest.mark.parametrize("m,d", [(300, 37), (5000, 200)])
+def test_qr_r_tree_path_matches_householder(slso, ctx, m, d):
+    rng = np.random.default_rng(m + d)
+    a = rng.standard_normal((m, d)) * np.exp(rng.standard_normal(d))[None, :]
+    r, used = ctx.qr_r_path(dev(a.copy()), slso.QR_TREE)
+    r = host(r)
+    assert used == slso.QR_TREE
+    ref = olv.qr_r(a)
+    assert np.abs(r - ref).max() / np.abs(ref).max() < 1e-12
+
+
+def _with_condition(kappa, m=3000, d=160, cols=None, seed=None):
+    """m x d with condition number kappa: all columns (cols None), or only
+    the first ``cols`` columns with the rest standard normal."""
+    rng = np.random.default_rng(int(kappa) if seed is None else seed)
+    c = d if cols is None else cols
+    u, _ = np.linalg.qr(rng.standard_normal((m, c)))
+    v, _ = np.linalg.qr(rng.standard_normal((c, c)))
+    s = np.logspace(0, -np.log10(kappa), c)
     a = np.empty((m, d))
-    a[:, :64] = (u * s) @ v.T
-    a[:, 64:] = rng.standard_normal((m, d - 64))
-    r = host(ctx.qr_r(dev(a.copy())))
+    a[:, :c] = (u * s) @ v.T
+    a[:, c:] = rng.standard_normal((m, d - c))
+    return a
+
+
+@pytest.mark.parametrize("kappa,cols,path,expect", [
+    (1e2, None, "auto", "cholqr2"), (1e5, None, "auto", "cholqr2_full"),
+    (1e8, None, "auto", "panel_or_tree"), (1e2, 64, "panel", "panel"),
+    (5e4, 64, "panel", "panel")])
+def test_qr_r_ill_conditioned(slso, ctx, kappa, cols, path, expect):
+    """Condition numbers that take each branch of the cascade: at 1e5 the
+    first Cholesky-QR pass leaves G2 too far from I for the one-launch R2 and
+    the blocked Cholesky runs; at 1e8 the whole-matrix Cholesky-QR2 does not
+    apply and a Householder path takes over. On the panel path, a first
+    panel with condition number 5e4 needs the blocked Cholesky in its second
+    pass. R is compared through R^T R = A^T A (backward error), the
+    meaningful measure once kappa is large."""
+    a = _with_condition(kappa, cols=cols)
+    start = slso.QR_AUTO if path == "auto" else slso.QR_PANEL
+    r, used = ctx.qr_r_path(dev(a.copy()), start)
+    r = host(r)
+    want = {"cholqr2": {slso.QR_CHOLQR2}, "cholqr2_full": {slso.QR_CHOLQR2_FULL},
+            "panel": {slso.QR_PANEL},
+            "panel_or_tree": {slso.QR_PANEL, slso.QR_TREE}}[expect]
+    assert used in want, used
     assert np.all(np.isfinite(r)) and np.all(np.diag(r) >= 0)
     g = a.T @ a
     err = np.abs(r.T @ r - g).max() / np.abs(g).max()
-    print(f"[qr kappa={kappa:.0e}] backward err {err:.2e}", flush=True)
+    print(f"[qr kappa={kappa:.0e} {path}] path {used} backward err {err:.2e}",
+          flush=True)
     assert err < 1e-13
 
 
-def test_qr_r_rank_deficient_panel_falls_back(slso, ctx):
-    """A zero column inside a 64-column panel makes its Cholesky fail; the
-    factorisation is redone column by column and stays a valid R."""
+def test_qr_r_rank_deficient_falls_back(slso, ctx):
+    """A zero column inside a 64-column panel makes both Cholesky-QR2 forms
+    fail; the factorisation is redone column by column and stays a valid R."""
     a = np.random.default_rng(2).standard_normal((2000, 150))
     a[:, 70] = 0.0
     a[:, 20] = a[:, 3]          # a repeated column as well
-    r = host(ctx.qr_r(dev(a.copy())))
+    r, used = ctx.qr_r_path(dev(a.copy()))
+    r = host(r)
+    assert used == slso.QR_TREE
     assert np.all(np.isfinite(r))
     g = a.T @ a
     assert np.abs(r.T @ r - g).max() < 1e-12 * np.abs(g).max()
@@ -200,6 +240,12 @@ def test_qr_r_zero_column_is_finite(slso, ctx):
     g = a.T @ a
     assert np.abs(r.T @ r - g).max() < 1e-12 * np.abs(g).max()
     assert r[7, 7] == 0.0
+
+
+def test_qr_r_path_rejects_unknown(slso, ctx):
+    with pytest.raises(slso.SlsoError) as e:
+        ctx.qr_r_path(dev(np.zeros((8, 4))), 7)
+    assert e.value.status == slso.EINVAL
 
 
 # ---- triangular solve ------------------------------------------------------------
