@@ -60,6 +60,11 @@ __device__ __forceinline__ void upper_tile(int64_t t, int64_t n, int64_t& i,
   j = r + t;
 }
 
+// index of tile (i, j), i <= j, in the enumeration of upper_tile
+__host__ __device__ inline int64_t upper_index(int64_t i, int64_t j, int64_t n) {
+  return i * n - i * (i - 1) / 2 + (j - i);
+}
+
 // acc -= A B (AT: A^T B) for LDS tiles, see mm64
 template <bool AT>
 __device__ __forceinline__ void mm64_sub(const double* A, const double* B,
@@ -94,68 +99,157 @@ __device__ __forceinline__ void tile_to_global(double* g, const double* T,
 }
 
 // ---- Gram tiles: partial sums over row chunks ----------------------------------
-// Workgroup g: chunk s = g % S (consecutive workgroups, which the dispatcher
-// spreads over the XCDs, take different chunks), upper tile g / S.
-__global__ void __launch_bounds__(256)
-    gram_part_kernel(const double* __restrict__ A, int64_t lda, int64_t m,
-                     int64_t d, int64_t nb, int64_t S, int64_t chunk,
-                     double* __restrict__ part, unsigned long long* emax,
-                     const int* __restrict__ flag) {
-  __shared__ double TA[kTile];
-  __shared__ double TB[kTile];
+// A workgroup forms one 128 x 128 block of the Gram matrix (a pair of
+// 128-column blocks I2 <= J2 of A) over one chunk of rows. Wave w owns the
+// 32-row strip 32 w .. 32 w + 31 of the block and all its columns, so the four
+// waves carry equal work (on diagonal blocks the lower half is formed too and
+// ignored). Rows advance in steps of 16 through two LDS buffers (one barrier
+// per step); the next step's rows are loaded into registers while the current
+// step multiplies. Blocks made of full 128-column blocks of A are formed by
+// one launch with about two workgroups per CU; the blocks that touch a last,
+// partial column block (little work) by a second launch with predicates.
+// Partial blocks are stored 128 x 128 row-major (edge blocks: only their
+// columns inside the matrix): full block t, chunk s at
+// part[(t S + s) 16384], edge block e, chunk s after all of those at
+// [(nfull S + e S_e + s) 16384].
+constexpr int kGK = 16;    // rows per step
+constexpr int kGS = 144;   // LDS row stride: rows 4 apart fall on the other
+                           // half of the banks
+constexpr int64_t kB2 = 128 * 128;
+
+template <bool EDGE>
+__global__ void __launch_bounds__(256, 2)
+    gram_block_kernel(const double* __restrict__ A, int64_t lda, int64_t m,
+                      int64_t d, int64_t S, int64_t chunk, int64_t part0,
+                      double* __restrict__ part, const int* __restrict__ flag) {
+  __shared__ double X[2][2][kGK * kGS];
   if (*flag) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int p = lane & 15, q = lane >> 4;
   const int64_t g = blockIdx.x, s = g % S, tt = g / S;
-  const int64_t nt = nb * (nb + 1) / 2;
-  if (g == 0 && t == 0 && emax) *emax = 0ull;
-  int64_t I, J;
-  upper_tile(tt, nb, I, J);
-  const bool diag = I == J;
-  const int64_t ci = I * kP, cj = J * kP;
-  const int64_t ni = d - ci < kP ? d - ci : kP;
-  const int64_t nj = d - cj < kP ? d - cj : kP;
+  const int64_t nf = d / 128;  // full 128-column blocks
+  int64_t I2, J2;
+  if (EDGE) {
+    I2 = tt;
+    J2 = nf;
+  } else {
+    upper_tile(tt, nf, I2, J2);
+  }
+  const bool diag = I2 == J2;
+  const int64_t cA = I2 * 128, cB = J2 * 128;
+  const int64_t nA = d - cA < 128 ? d - cA : 128;
+  const int64_t nB = d - cB < 128 ? d - cB : 128;
+  // 16-row / 16-column sub-blocks of this wave's strip inside the matrix
+  const int64_t rw = nA - 32 * w;
+  const int nrow = EDGE ? (rw <= 0 ? 0 : (rw >= 32 ? 2 : (rw > 16 ? 2 : 1))) : 2;
+  const int ncol = EDGE ? static_cast<int>((nB + 15) / 16) : 8;
   const int64_t r0 = s * chunk;
   const int64_t r1 = m < r0 + chunk ? m : r0 + chunk;
-  dbl4 acc[4];
-  zero4(acc);
-  if (r0 < r1) {
-    double va[16], vb[16];
-    load_regs(va, A + r0 * lda + ci, lda, r1 - r0, ni, t);
-    if (!diag) load_regs(vb, A + r0 * lda + cj, lda, r1 - r0, nj, t);
-    for (int64_t r = r0; r < r1; r += kP) {
-      __syncthreads();
-      store_regs(TA, va, t);
-      if (!diag) store_regs(TB, vb, t);
-      __syncthreads();
-      if (r + kP < r1) {
-        load_regs(va, A + (r + kP) * lda + ci, lda, r1 - r - kP, ni, t);
-        if (!diag) load_regs(vb, A + (r + kP) * lda + cj, lda, r1 - r - kP, nj, t);
+  dbl4 acc[2][8];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 8; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const int c = t & 127, rr = t >> 7;
+  double v[16];
+  // loads without branches (an entry outside the matrix reads A[0]); the
+  // zeros are put in when the values go to LDS
+  auto gload = [&](int64_t r) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t row = r + rr + 2 * u;
+      const bool oka = row < r1 && c < nA;
+      v[u] = A[oka ? row * lda + cA + c : 0];
+      if (!diag) {
+        const bool okb = row < r1 && c < nB;
+        v[8 + u] = A[okb ? row * lda + cB + c : 0];
       }
-      mm64<true>(TA, diag ? TA : TB, acc, lane, w);
+    }
+  };
+  auto lstore = [&](int buf, int64_t r) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t row = r + rr + 2 * u;
+      X[buf][0][(rr + 2 * u) * kGS + c] = (row < r1 && c < nA) ? v[u] : 0.0;
+      if (!diag)
+        X[buf][1][(rr + 2 * u) * kGS + c] = (row < r1 && c < nB) ? v[8 + u] : 0.0;
+    }
+  };
+  if (r0 < r1) {
+    gload(r0);
+    lstore(0, r0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t r = r0; r < r1; r += kGK) {
+      const bool more = r + kGK < r1;
+      if (more) gload(r + kGK);
+      const double* XA = X[buf][0];
+      const double* XB = diag ? X[buf][0] : X[buf][1];
+#pragma unroll
+      for (int kk = 0; kk < kGK / 4; ++kk) {
+        const int k = 4 * kk + q;
+        double a[2], b[8];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) a[x] = XA[k * kGS + 32 * w + 16 * x + p];
+#pragma unroll
+        for (int y = 0; y < 8; ++y) b[y] = XB[k * kGS + 16 * y + p];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 8; ++y)
+            if (!EDGE || (x < nrow && y < ncol))
+              acc[x][y] = mfma(a[x], b[y], acc[x][y]);
+      }
+      if (more) lstore(buf ^ 1, r + kGK);
+      __syncthreads();
+      buf ^= 1;
     }
   }
-  store_acc_global(part + (s * nt + tt) * kT2, kP, acc, 1.0, lane, w);
+  double* out = part + (part0 + g) * kB2;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 8; ++y)
+      if (!EDGE || y < ncol) {
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv)
+          out[(32 * w + 16 * x + 4 * vv + q) * 128 + 16 * y + p] = acc[x][y][vv];
+      }
 }
 
-// G tile = sum of its S partial tiles (fixed order); the padded diagonal is
-// set to 1; gdiag receives the diagonal; with emax, max |G - I| over the
-// valid entries (bit patterns of non-negative doubles order like the values,
-// a NaN above every number).
+// G tile = sum of its partial blocks (fixed order); the padding is the
+// identity; gdiag receives the diagonal. With emax, emax[workgroup] = max
+// |G - I| over the workgroup's valid entries (bit patterns of non-negative
+// doubles order like the values, a NaN above every number).
 __global__ void __launch_bounds__(256)
-    gram_reduce_kernel(const double* __restrict__ part, int64_t S, int64_t nb,
-                       int64_t d, double* __restrict__ G,
+    gram_reduce_kernel(const double* __restrict__ part, int64_t S, int64_t Se,
+                       int64_t nb, int64_t d, double* __restrict__ G,
                        double* __restrict__ gdiag, unsigned long long* emax,
                        const int* __restrict__ flag) {
+  __shared__ unsigned long long red[4];
   if (*flag) return;
-  const int64_t nt = nb * (nb + 1) / 2;
   const int64_t tt = blockIdx.x >> 4;
   const int e = static_cast<int>((blockIdx.x & 15) << 8) + threadIdx.x;
-  double v = sum_parts(part + tt * kT2, S, nt * kT2, e);
-  int64_t I, J;
-  upper_tile(tt, nb, I, J);
-  const int64_t gi = I * kP + (e >> 6), gj = J * kP + (e & 63);
-  if (gi == gj && gi >= d) v = 1.0;
-  G[tix(I, J, nb) + e] = v;
+  int64_t I0, J0;
+  upper_tile(tt, nb, I0, J0);
+  // the 128 x 128 partial block holding 64-tile (I0, J0), and the offset of
+  // this element inside it
+  const int64_t nf = d / 128;
+  const int64_t I2 = I0 >> 1, J2 = J0 >> 1;
+  const int64_t off = ((I0 & 1) * 64 + (e >> 6)) * 128 + (J0 & 1) * 64 + (e & 63);
+  const int64_t gi = I0 * kP + (e >> 6), gj = J0 * kP + (e & 63);
+  double v = 0.0;
+  if (gi >= d || gj >= d) {
+    // padding: the identity (partial edge blocks hold nothing there)
+    v = gi == gj ? 1.0 : 0.0;
+  } else if (J2 < nf) {
+    const int64_t blk = upper_index(I2, J2, nf) * S;
+    v = sum_parts(part + blk * kB2 + off, S, kB2, 0);
+  } else {
+    const int64_t blk = nf * (nf + 1) / 2 * S + I2 * Se;
+    v = sum_parts(part + blk * kB2 + off, Se, kB2, 0);
+  }
+  G[tix(I0, J0, nb) + e] = v;
   if (gi == gj) gdiag[gi] = v;
   if (emax) {
     double dev = 0.0;
@@ -166,7 +260,13 @@ __global__ void __launch_bounds__(256)
       const unsigned long long ob = __shfl_xor(b, o);
       b = ob > b ? ob : b;
     }
-    if ((threadIdx.x & 63) == 0 && b != 0ull) atomicMax(emax, b);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long m = red[0];
+      for (int k = 1; k < 4; ++k) m = red[k] > m ? red[k] : m;
+      emax[blockIdx.x] = m;
+    }
   }
 }
 
@@ -281,26 +381,26 @@ __global__ void __launch_bounds__(256)
         acc[bj][v] = (row < nr && col < nc) ? As[row * lda + cJ + col] : 0.0;
       }
     // blocks I < J are complete (only the last block can be partial)
-    double va[16], vb[16];
+    Stage va, vb;
     if (J > 0) {
-      load_regs(va, As, lda, nr, kP, t);
-      load_regs(vb, R + tix(0, J, nb), kP, kP, kP, t);
+      stage_load(va, As, lda, nr, kP, t);
+      stage_load(vb, R + tix(0, J, nb), kP, kP, kP, t);
     }
     for (int64_t I = 0; I < J; ++I) {
       __syncthreads();
-      store_regs(TA, va, t);
-      store_regs(TB, vb, t);
+      stage_store(TA, va, t);
+      stage_store(TB, vb, t);
       __syncthreads();
       if (I + 1 < J) {
-        load_regs(va, As + (I + 1) * kP, lda, nr, kP, t);
-        load_regs(vb, R + tix(I + 1, J, nb), kP, kP, kP, t);
+        stage_load(va, As + (I + 1) * kP, lda, nr, kP, t);
+        stage_load(vb, R + tix(I + 1, J, nb), kP, kP, kP, t);
       }
       mm64_sub<false>(TA, TB, acc, lane, w);
     }
-    load_regs(vb, Dinv + J * kT2, kP, kP, kP, t);
+    stage_load(vb, Dinv + J * kT2, kP, kP, kP, t);
     __syncthreads();
     store_acc(TA, acc, 1.0, lane, w);
-    store_regs(TB, vb, t);
+    stage_store(TB, vb, t);
     __syncthreads();
     dbl4 res[4];
     zero4(res);
@@ -333,7 +433,17 @@ __global__ void __launch_bounds__(256)
   const int p = lane & 15, q = lane >> 4;
   const int64_t i = blockIdx.x / nb, j = blockIdx.x % nb;
   if (NEAR) {
-    const double em = __longlong_as_double(static_cast<long long>(*emax));
+    __shared__ unsigned long long red[256];
+    const int64_t ne = nb * (nb + 1) / 2 * 16;
+    unsigned long long b = 0ull;
+    for (int64_t e = t; e < ne; e += 256) b = emax[e] > b ? emax[e] : b;
+    red[t] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) red[t] = red[t + o] > red[t] ? red[t + o] : red[t];
+      __syncthreads();
+    }
+    const double em = __longlong_as_double(static_cast<long long>(red[0]));
     const bool ok = em <= 0.25 / static_cast<double>(d);  // false for NaN
     if (!ok || em > kNearId) {
       if (blockIdx.x == 0 && t == 0) *status = ok ? 2 : 1;
@@ -373,7 +483,7 @@ __global__ void __launch_bounds__(256)
 }
 
 struct Cq2 {
-  int64_t nb, nt, S, chunk;
+  int64_t nb, nt, S, chunk, Se, chunk_e, nfull, nedge;
   double *part, *G, *R1, *R2, *Dinv, *gdiag;
   unsigned long long* emax;
 };
@@ -382,29 +492,36 @@ Cq2 cq2_shape(int64_t m, int64_t d) {
   Cq2 c{};
   c.nb = (d + kP - 1) / kP;
   c.nt = c.nb * (c.nb + 1) / 2;
-  // row chunks: enough workgroups to fill the device twice over, a multiple
-  // of 8 (one chunk per XCD), chunks of at least 256 rows
-  int64_t S = (512 + c.nt - 1) / c.nt;
-  if (S > 1) S = (S + 7) / 8 * 8;
-  const int64_t smax = (m + 255) / 256;
-  if (S > smax) S = smax;
-  if (S < 1) S = 1;
-  const int64_t blocks = (m + kP - 1) / kP;
-  c.chunk = (blocks + S - 1) / S * kP;
-  c.S = S;
+  // Gram row chunks: blocks of full 128-column blocks take at most 512
+  // workgroups in all (two per CU: one round), the edge blocks (thin: their
+  // time is load latency, so they get many short chunks) at most 512;
+  // chunks of at least 256 rows
+  const int64_t nf = d / 128;
+  c.nfull = nf * (nf + 1) / 2;
+  c.nedge = d % 128 ? nf + 1 : 0;
+  const int64_t steps = (m + kGK - 1) / kGK;
+  const int64_t smax = (m + 255) / 256 > 1 ? (m + 255) / 256 : 1;
+  auto pick = [&](int64_t slots, int64_t blocks, int64_t& S, int64_t& chunk) {
+    S = blocks > 0 ? slots / blocks : 1;
+    if (S > smax) S = smax;
+    if (S < 1) S = 1;
+    chunk = (steps + S - 1) / S * kGK;
+  };
+  pick(512, c.nfull, c.S, c.chunk);
+  pick(512, c.nedge, c.Se, c.chunk_e);
   return c;
 }
 
 Cq2 cq2_carve(void* base, int64_t m, int64_t d) {
   Cq2 c = cq2_shape(m, d);
   double* p = static_cast<double*>(base);
-  c.part = p;  p += c.S * c.nt * kT2;
+  c.part = p;  p += (c.nfull * c.S + c.nedge * c.Se) * kB2;
   c.G = p;     p += c.nb * c.nb * kT2;
   c.R1 = p;    p += c.nb * c.nb * kT2;
   c.R2 = p;    p += c.nb * c.nb * kT2;
   c.Dinv = p;  p += c.nb * kT2;
   c.gdiag = p; p += c.nb * kP;
-  c.emax = reinterpret_cast<unsigned long long*>(p);
+  c.emax = reinterpret_cast<unsigned long long*>(p);  // nt * 16 entries
   return c;
 }
 
@@ -412,10 +529,14 @@ void gram_tiles(const double* a, int64_t m, int64_t d, const Cq2& c,
                 bool with_emax, int* flag, hipStream_t s) {
   unsigned long long* em = with_emax ? c.emax : nullptr;
   prof_begin(kKCq2Gram, s);
-  gram_part_kernel<<<static_cast<unsigned>(c.nt * c.S), 256, 0, s>>>(
-      a, d, m, d, c.nb, c.S, c.chunk, c.part, em, flag);
+  if (c.nfull > 0)
+    gram_block_kernel<false><<<static_cast<unsigned>(c.nfull * c.S), 256, 0, s>>>(
+        a, d, m, d, c.S, c.chunk, 0, c.part, flag);
+  if (c.nedge > 0)
+    gram_block_kernel<true><<<static_cast<unsigned>(c.nedge * c.Se), 256, 0, s>>>(
+        a, d, m, d, c.Se, c.chunk_e, c.nfull * c.S, c.part, flag);
   gram_reduce_kernel<<<static_cast<unsigned>(c.nt * 16), 256, 0, s>>>(
-      c.part, c.S, c.nb, d, c.G, c.gdiag, em, flag);
+      c.part, c.S, c.Se, c.nb, d, c.G, c.gdiag, em, flag);
   prof_end(kKCq2Gram, s);
 }
 
@@ -434,8 +555,9 @@ void bchol(const Cq2& c, double* R, int* flag, hipStream_t s) {
 
 size_t cholqr2_scratch_bytes(int64_t m, int64_t d) {
   const Cq2 c = cq2_shape(m, d);
-  return static_cast<size_t>(c.S * c.nt * kT2 + 3 * c.nb * c.nb * kT2 +
-                             c.nb * kT2 + c.nb * kP + 8) *
+  return static_cast<size_t>((c.nfull * c.S + c.nedge * c.Se) * kB2 +
+                             3 * c.nb * c.nb * kT2 +
+                             c.nb * kT2 + c.nb * kP + c.nt * 16 + 8) *
          sizeof(double);
 }
 

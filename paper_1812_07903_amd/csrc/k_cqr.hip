@@ -56,16 +56,16 @@ __global__ void __launch_bounds__(256)
   const int64_t r0 = j0 + static_cast<int64_t>(blockIdx.x) * kRG;
   dbl4 acc[4];
   zero4(acc);
-  double v[16];
-  load_regs(v, A + r0 * lda + j0, lda, m - r0, kP, t);
+  Stage v;
+  stage_load(v, A + r0 * lda + j0, lda, m - r0, kP, t);
   for (int c = 0; c < kRG / kP; ++c) {
     const int64_t rb = r0 + c * kP;
     if (rb >= m) break;
     __syncthreads();
-    store_regs(T, v, t);
+    stage_store(T, v, t);
     __syncthreads();
     if (c + 1 < kRG / kP && rb + kP < m)
-      load_regs(v, A + (rb + kP) * lda + j0, lda, m - rb - kP, kP, t);
+      stage_load(v, A + (rb + kP) * lda + j0, lda, m - rb - kP, kP, t);
     mm64<true>(T, T, acc, lane, w);
   }
   store_acc_global(gpart + static_cast<int64_t>(blockIdx.x) * kP * kP, kP, acc,
@@ -119,8 +119,8 @@ __global__ void __launch_bounds__(256)
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int p = lane & 15, q = lane >> 4;
   const int64_t r0 = j0 + static_cast<int64_t>(blockIdx.x) * kRG;
-  double v[16];
-  load_regs(v, A + r0 * lda + j0, lda, m - r0, kP, t);
+  Stage v;
+  stage_load(v, A + r0 * lda + j0, lda, m - r0, kP, t);
   load_tile(Ri, r1i, kP, kP, kP, t);
   dbl4 g2[4];
   zero4(g2);
@@ -128,10 +128,10 @@ __global__ void __launch_bounds__(256)
     const int64_t rb = r0 + c * kP;
     if (rb >= m) break;
     __syncthreads();
-    store_regs(T, v, t);
+    stage_store(T, v, t);
     __syncthreads();
     if (c + 1 < kRG / kP && rb + kP < m)
-      load_regs(v, A + (rb + kP) * lda + j0, lda, m - rb - kP, kP, t);
+      stage_load(v, A + (rb + kP) * lda + j0, lda, m - rb - kP, kP, t);
     dbl4 acc[4];
     zero4(acc);
     mm64<false>(T, Ri, acc, lane, w);
@@ -169,22 +169,22 @@ __global__ void __launch_bounds__(256)
   dbl4 acc[4];
   zero4(acc);
   // the panel's top 64 rows hold its R by now: their Q1 comes from the copy
-  double vq[16], vc[16];
+  Stage vq, vc;
   if (r0 == j0)
-    load_regs(vq, q1top, kP, kP, kP, t);
+    stage_load(vq, q1top, kP, kP, kP, t);
   else
-    load_regs(vq, A + r0 * lda + j0, lda, m - r0, kP, t);
-  load_regs(vc, A + r0 * lda + cc, lda, m - r0, nc, t);
+    stage_load(vq, A + r0 * lda + j0, lda, m - r0, kP, t);
+  stage_load(vc, A + r0 * lda + cc, lda, m - r0, nc, t);
   for (int c = 0; c < kRZ / kP; ++c) {
     const int64_t rb = r0 + c * kP;
     if (rb >= m) break;
     __syncthreads();
-    store_regs(TQ, vq, t);
-    store_regs(TC, vc, t);
+    stage_store(TQ, vq, t);
+    stage_store(TC, vc, t);
     __syncthreads();
     if (c + 1 < kRZ / kP && rb + kP < m) {
-      load_regs(vq, A + (rb + kP) * lda + j0, lda, m - rb - kP, kP, t);
-      load_regs(vc, A + (rb + kP) * lda + cc, lda, m - rb - kP, nc, t);
+      stage_load(vq, A + (rb + kP) * lda + j0, lda, m - rb - kP, kP, t);
+      stage_load(vc, A + (rb + kP) * lda + cc, lda, m - rb - kP, nc, t);
     }
     mm64<true>(TQ, TC, acc, lane, w);
   }
@@ -584,18 +584,18 @@ __global__ void __launch_bounds__(256)
   const int64_t nc = ncols - c0 < kP ? ncols - c0 : kP;
   const int64_t ccol = j0 + kP + c0;  // first column of this block in A
   // A-operand rows of the first chunk: L for the panel's top rows, else Q1
-  double va[16];
+  Stage va;
   if (r0 == j0)
-    load_regs(va, lbuf, kP, kP, kP, t);
+    stage_load(va, lbuf, kP, kP, kP, t);
   else
-    load_regs(va, A + r0 * lda + j0, lda, m - r0, kP, t);
+    stage_load(va, A + r0 * lda + j0, lda, m - r0, kP, t);
   bool b_is_k = false;
   for (int c = 0; c < kRU / kP; ++c) {
     const int64_t rb = r0 + c * kP;
     if (rb >= m) break;
     const bool top = rb == j0;
     __syncthreads();
-    store_regs(TA, va, t);
+    stage_store(TA, va, t);
     if (top) {
       load_tile(TB, wp + c0, ldz, kP, nc, t);
     } else if (!b_is_k) {
@@ -613,7 +613,7 @@ __global__ void __launch_bounds__(256)
       }
     __syncthreads();
     if (c + 1 < kRU / kP && rb + kP < m)
-      load_regs(va, A + (rb + kP) * lda + j0, lda, m - rb - kP, kP, t);
+      stage_load(va, A + (rb + kP) * lda + j0, lda, m - rb - kP, kP, t);
     // acc -= A-tile B-tile (the A operand negated)
 #pragma unroll 4
     for (int kk = 0; kk < 16; ++kk) {

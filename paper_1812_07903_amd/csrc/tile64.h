@@ -69,32 +69,52 @@ __device__ __forceinline__ void store_acc_global(double* g, int64_t ldg,
 // 64 x 64 block of a row-major matrix: v[u] = a[i][j] for element
 // e = t + 256 u (i = e / 64, j = e % 64); rows >= nr and columns >= nc read as
 // zero. All sixteen loads are issued before any is used.
-__device__ __forceinline__ void load_regs(double (&v)[16], const double* a,
-                                          int64_t lda, int64_t nr, int64_t nc,
-                                          int t) {
+// A 64 x 64 tile staged in registers: thread t holds elements e = t + 256 u
+// (row e / 64, column e % 64). stage_load reads the rows < nr and columns
+// < nc of a (row stride lda) without branches -- an element outside reads a
+// clamped address inside that rectangle -- and records which elements are
+// inside; stage_store writes the tile to LDS with zeros outside. The loaded
+// values are not used before stage_store, so loads issued ahead of a
+// multiplication stay in flight during it.
+struct Stage {
+  double v[16];
+  uint32_t ok;
+};
+
+__device__ __forceinline__ void stage_load(Stage& s, const double* a,
+                                           int64_t lda, int64_t nr, int64_t nc,
+                                           int t) {
+  s.ok = 0u;
+  if (nr <= 0 || nc <= 0) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s.v[u] = 0.0;
+    return;
+  }
+  const int64_t r1 = nr - 1, c1 = nc - 1;
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = t + 256 * u;
-    const int i = e >> 6, j = e & 63;
-    v[u] = (i < nr && j < nc) ? a[i * lda + j] : 0.0;
+    const int64_t i = e >> 6, j = e & 63;
+    s.ok |= (i < nr && j < nc) ? (1u << u) : 0u;
+    s.v[u] = a[(i < r1 ? i : r1) * lda + (j < c1 ? j : c1)];
   }
 }
 
-__device__ __forceinline__ void store_regs(double* tile, const double (&v)[16],
-                                           int t) {
+__device__ __forceinline__ void stage_store(double* tile, const Stage& s,
+                                            int t) {
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = t + 256 * u;
-    tile[(e >> 6) * kS + (e & 63)] = v[u];
+    tile[(e >> 6) * kS + (e & 63)] = ((s.ok >> u) & 1u) ? s.v[u] : 0.0;
   }
 }
 
 __device__ __forceinline__ void load_tile(double* tile, const double* a,
                                           int64_t lda, int64_t nr, int64_t nc,
                                           int t) {
-  double v[16];
-  load_regs(v, a, lda, nr, nc, t);
-  store_regs(tile, v, t);
+  Stage v;
+  stage_load(v, a, lda, nr, nc, t);
+  stage_store(tile, v, t);
 }
 
 // 16 x 16 products on one wave, acc += A B with A(i, k) = A[i lda + k]
