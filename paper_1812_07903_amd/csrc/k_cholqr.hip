@@ -355,8 +355,53 @@ __global__ void __launch_bounds__(256)
 // ---- Q1 = A R^{-1} in place, by 64-row stripes ---------------------------------
 // Stripe rows are independent: column block J of the stripe becomes
 // (A_J - sum_{I<J} Q1_I R_IJ) R_JJ^{-1}, blocks in increasing J, each written
-// over A_J once A_J has been read.
-__global__ void __launch_bounds__(256)
+// over A_J once A_J has been read. Eight waves per stripe, two per SIMD:
+// wave w owns rows 16 (w & 3) .. + 15 and columns 32 (w >> 2) .. + 31 of each
+// 64 x 64 product, so one wave's LDS reads overlap the other's products.
+constexpr int kSW = 512;  // threads of a stripe workgroup
+
+struct Stage8 {
+  double v[8];
+  uint32_t ok;
+};
+// tile element e = t + 512 u (row e / 64, column e % 64), as stage_load
+__device__ __forceinline__ void stage8_load(Stage8& s, const double* a,
+                                            int64_t lda, int64_t nr, int64_t nc,
+                                            int t) {
+  s.ok = 0u;
+  const int64_t r1 = nr - 1, c1 = nc - 1;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int e = t + kSW * u;
+    const int64_t i = e >> 6, j = e & 63;
+    s.ok |= (i < nr && j < nc) ? (1u << u) : 0u;
+    s.v[u] = a[(i < r1 ? i : r1) * lda + (j < c1 ? j : c1)];
+  }
+}
+__device__ __forceinline__ void stage8_store(double* tile, const Stage8& s,
+                                             int t) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int e = t + kSW * u;
+    tile[(e >> 6) * kS + (e & 63)] = ((s.ok >> u) & 1u) ? s.v[u] : 0.0;
+  }
+}
+// acc (+)= A B on the wave's 16 x 32 part
+template <bool SUB>
+__device__ __forceinline__ void mm64x8(const double* A, const double* B,
+                                       dbl4 (&acc)[2], int lane, int w) {
+  const int p = lane & 15, q = lane >> 4, wr = w & 3, wc = w >> 2;
+#pragma unroll 4
+  for (int kk = 0; kk < 16; ++kk) {
+    const int k = 4 * kk + q;
+    const double a = SUB ? -A[(16 * wr + p) * kS + k] : A[(16 * wr + p) * kS + k];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+      acc[bj] = mfma(a, B[k * kS + 32 * wc + 16 * bj + p], acc[bj]);
+  }
+}
+
+__global__ void __launch_bounds__(kSW)
     stripe_solve_kernel(double* __restrict__ A, int64_t lda, int64_t m,
                         int64_t d, int64_t nb, const double* __restrict__ R,
                         const double* __restrict__ Dinv,
@@ -364,7 +409,7 @@ __global__ void __launch_bounds__(256)
   __shared__ double TA[kTile];
   __shared__ double TB[kTile];
   if (*flag) return;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w & 3, wc = w >> 2;
   const int p = lane & 15, q = lane >> 4;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kP;
   const int64_t nr = m - r0 < kP ? m - r0 : kP;
@@ -372,44 +417,48 @@ __global__ void __launch_bounds__(256)
   for (int64_t J = 0; J < nb; ++J) {
     const int64_t cJ = J * kP;
     const int64_t nc = d - cJ < kP ? d - cJ : kP;
-    dbl4 acc[4];
+    dbl4 acc[2];
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj)
+    for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = 16 * w + 4 * v + q, col = 16 * bj + p;
+        const int row = 16 * wr + 4 * v + q, col = 32 * wc + 16 * bj + p;
         acc[bj][v] = (row < nr && col < nc) ? As[row * lda + cJ + col] : 0.0;
       }
     // blocks I < J are complete (only the last block can be partial)
-    Stage va, vb;
+    Stage8 va, vb;
     if (J > 0) {
-      stage_load(va, As, lda, nr, kP, t);
-      stage_load(vb, R + tix(0, J, nb), kP, kP, kP, t);
+      stage8_load(va, As, lda, nr, kP, t);
+      stage8_load(vb, R + tix(0, J, nb), kP, kP, kP, t);
     }
     for (int64_t I = 0; I < J; ++I) {
       __syncthreads();
-      stage_store(TA, va, t);
-      stage_store(TB, vb, t);
+      stage8_store(TA, va, t);
+      stage8_store(TB, vb, t);
       __syncthreads();
       if (I + 1 < J) {
-        stage_load(va, As + (I + 1) * kP, lda, nr, kP, t);
-        stage_load(vb, R + tix(I + 1, J, nb), kP, kP, kP, t);
+        stage8_load(va, As + (I + 1) * kP, lda, nr, kP, t);
+        stage8_load(vb, R + tix(I + 1, J, nb), kP, kP, kP, t);
       }
-      mm64_sub<false>(TA, TB, acc, lane, w);
+      mm64x8<true>(TA, TB, acc, lane, w);
     }
-    stage_load(vb, Dinv + J * kT2, kP, kP, kP, t);
+    stage8_load(vb, Dinv + J * kT2, kP, kP, kP, t);
     __syncthreads();
-    store_acc(TA, acc, 1.0, lane, w);
-    stage_store(TB, vb, t);
-    __syncthreads();
-    dbl4 res[4];
-    zero4(res);
-    mm64<false>(TA, TB, res, lane, w);
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj)
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        TA[(16 * wr + 4 * v + q) * kS + 32 * wc + 16 * bj + p] = acc[bj][v];
+    stage8_store(TB, vb, t);
+    __syncthreads();
+    dbl4 res[2];
+    res[0] = res[1] = dbl4{0.0, 0.0, 0.0, 0.0};
+    mm64x8<false>(TA, TB, res, lane, w);
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = 16 * w + 4 * v + q, col = 16 * bj + p;
+        const int row = 16 * wr + 4 * v + q, col = 32 * wc + 16 * bj + p;
         if (row < nr && col < nc) As[row * lda + cJ + col] = res[bj][v];
       }
     // Q1_J is read back by other threads of the workgroup for later blocks
@@ -454,22 +503,30 @@ __global__ void __launch_bounds__(256)
   zero4(acc);
   if (i <= j) {
     if (NEAR) ld_acc(acc, R1 + tix(i, j, nb), lane, w);
+    // tiles of term l + 1 load while term l multiplies
+    Stage vf, vr;
+    auto issue = [&](int64_t l) {
+      stage_load(vf, F + tix(i, l, nb), kP, kP, kP, t);
+      stage_load(vr, R1 + tix(l, j, nb), kP, kP, kP, t);
+    };
+    issue(i);
     for (int64_t l = i; l <= j; ++l) {
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int e = t + 256 * u;
         const int a = e >> 6, b = e & 63;
-        double v = F[tix(i, l, nb) + e];
+        double v = vf.v[u];
         if (NEAR) {
           // up(E): strict upper part of G2 - I and half its diagonal
           const int64_t gi = i * kP + a, gl = l * kP + b;
           v = gi < gl ? v : (gi == gl ? 0.5 * (v - 1.0) : 0.0);
         }
         TA[a * kS + b] = v;
-        TB[a * kS + b] = R1[tix(l, j, nb) + e];
       }
+      stage_store(TB, vr, t);
       __syncthreads();
+      if (l < j) issue(l + 1);
       mm64<false>(TA, TB, acc, lane, w);
     }
   }
@@ -568,7 +625,7 @@ void cholqr2_factor(double* a, int64_t m, int64_t d, double* r_out,
   gram_tiles(a, m, d, c, false, status, s);
   bchol(c, c.R1, status, s);
   prof_begin(kKCq2Solve, s);
-  stripe_solve_kernel<<<cdivu(m, kP), 256, 0, s>>>(a, d, m, d, c.nb, c.R1,
+  stripe_solve_kernel<<<cdivu(m, kP), kSW, 0, s>>>(a, d, m, d, c.nb, c.R1,
                                                     c.Dinv, status);
   prof_end(kKCq2Solve, s);
   gram_tiles(a, m, d, c, true, status, s);
