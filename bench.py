@@ -51,7 +51,7 @@ def qr_node_flops(m: int, d: int, w: int = 16) -> float:
 
 # profiler name -> (kernel symbol in the PMC summary, source file)
 KERNEL_SRC = {
-    "cq2_gram": ("gram_part_kernel", "k_cholqr.hip"),
+    "cq2_gram": ("gram_block_kernel<false>", "k_cholqr.hip"),
     "cq2_solve": ("stripe_solve_kernel", "k_cholqr.hip"),
     "cq_update": ("cq_update_kernel", "k_cqr.hip"),
     "cq_z": ("cq_z_kernel", "k_cqr.hip"),
@@ -59,7 +59,7 @@ KERNEL_SRC = {
     "cq_gram": ("cq_gram_kernel", "k_cqr.hip"),
     "qr_node": ("qr_node_kernel", "k_qr.hip"),
     "qr_update": ("qr_update_kernel", "k_qr.hip"),
-    "score": ("score_dense_kernel<float,float>", "k_score.hip"),
+    "score": ("score_mfma_kernel<0>", "k_score.hip"),
     "countsketch": ("countsketch_dense_kernel<float>", "k_sketch.hip"),
     "colmax": ("colmax_dense_kernel<float>", "k_sketch.hip"),
 }
@@ -108,8 +108,15 @@ def _fp64(flops_per_launch: float, sec: float):
 def _roofline(name: str, ms_per_launch: float, launches_per_step: float):
     sec = ms_per_launch * 1e-3
     if name == "cq2_gram":
-        # upper triangle of A^T A (d (d + 1) / 2 entries, m products each)
-        return _fp64(float(R) * D * (D + 1), sec)
+        # the part of the upper triangle of A^T A inside full 128-column
+        # blocks: c (c + 1) / 2 entries (c = 128 floor(d / 128)), m products
+        c = 128 * (D // 128)
+        return _fp64(float(R) * c * (c + 1), sec)
+    if name == "cq2_gram_edge":
+        # the rest of the upper triangle (columns past c), plus the sum of
+        # the partial blocks
+        c = 128 * (D // 128)
+        return _fp64(float(R) * (D * (D + 1) - c * (c + 1)), sec)
     if name == "cq2_solve":
         # Q1 = A R1^{-1}: m d^2 flop
         return _fp64(float(R) * D * D, sec)
@@ -149,10 +156,11 @@ def _roofline(name: str, ms_per_launch: float, launches_per_step: float):
         return {"bound": "alu", "achieved": a / 1e12, "peak": PEAK["fp64"] / 1e12,
                 "unit": "TFLOP/s", "frac": a / PEAK["fp64"], "traffic": None}
     if name == "score":
-        flops = 2.0 * N * D * K / launches_per_step
-        a = flops / sec
-        return {"bound": "alu", "achieved": a / 1e12, "peak": PEAK["fp32"] / 1e12,
-                "unit": "TFLOP/s", "frac": a / PEAK["fp32"], "traffic": None}
+        # X read once (the products run on the MFMA, far below its peak)
+        byts = N * D * 4.0 / launches_per_step
+        a = byts / sec
+        return {"bound": "hbm", "achieved": a / 1e9, "peak": PEAK["hbm"] / 1e9,
+                "unit": "GB/s", "frac": a / PEAK["hbm"], "traffic": None}
     if name == "countsketch":
         # X once, the sketch written once, the sorted row list once
         byts = (N * D * 4 + R * D * 8 + N * 4) / launches_per_step

@@ -41,6 +41,7 @@ enum KernelId : int {
   kKCqW,
   kKCqUpdate,
   kKCq2Gram,
+  kKCq2GramEdge,
   kKCq2Chol,
   kKCq2Solve,
   kKCq2R,

@@ -589,12 +589,14 @@ void gram_tiles(const double* a, int64_t m, int64_t d, const Cq2& c,
   if (c.nfull > 0)
     gram_block_kernel<false><<<static_cast<unsigned>(c.nfull * c.S), 256, 0, s>>>(
         a, d, m, d, c.S, c.chunk, 0, c.part, flag);
+  prof_end(kKCq2Gram, s);
+  prof_begin(kKCq2GramEdge, s);
   if (c.nedge > 0)
     gram_block_kernel<true><<<static_cast<unsigned>(c.nedge * c.Se), 256, 0, s>>>(
         a, d, m, d, c.Se, c.chunk_e, c.nfull * c.S, c.part, flag);
   gram_reduce_kernel<<<static_cast<unsigned>(c.nt * 16), 256, 0, s>>>(
       c.part, c.S, c.Se, c.nb, d, c.G, c.gdiag, em, flag);
-  prof_end(kKCq2Gram, s);
+  prof_end(kKCq2GramEdge, s);
 }
 
 void bchol(const Cq2& c, double* R, int* flag, hipStream_t s) {

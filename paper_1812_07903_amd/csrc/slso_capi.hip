@@ -837,7 +837,7 @@ const char* slso_profile_name(int id) {
       "colmax", "countsketch", "qr_node", "qr_update", "qr_extract", "trsm",
       "score", "gaussian", "gauss_sketch", "gram", "cholesky", "cq_gram",
       "cq_sum", "cq_chol", "cq_q1", "cq_z", "cq_recon", "cq_w", "cq_update", "cq2_gram",
-      "cq2_chol", "cq2_solve", "cq2_r"};
+      "cq2_gram_edge", "cq2_chol", "cq2_solve", "cq2_r"};
   if (id < 0 || id >= slso::kKCount) return "";
   return names[id];
 }
