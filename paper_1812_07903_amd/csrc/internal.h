@@ -42,6 +42,7 @@ enum KernelId : int {
   kKCqUpdate,
   kKCq2Gram,
   kKCq2GramEdge,
+  kKCq2GramSum,
   kKCq2Chol,
   kKCq2Solve,
   kKCq2R,
@@ -120,11 +121,20 @@ size_t qr_scratch_bytes(int64_t m, int64_t d);
 // ill-conditioned or rank deficient): a and r_out are unusable, the caller
 // factors the original matrix with qr_factor_panel.
 void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
-               int* status, hipStream_t s);
+               int* status, const QrStreams& qs, hipStream_t s,
+               bool want_r = true, double* dstat = nullptr);
 // After status 2: the second pass's blocked Cholesky and R = R2 R1 (status
 // set again, 0 or 1).
 void qr_factor_finish(int64_t m, int64_t d, double* r_out, void* scratch,
-                      int* status, hipStream_t s);
+                      int* status, hipStream_t s, bool want_r = true,
+                      double* dstat = nullptr);
+// want_r = false: R is not formed; dstat[0..1] receive min and max |R_jj|, and
+// the scratch keeps R^{-1} in factored form for qr_apply_rinv (and the factors
+// for qr_write_r) until the scratch is reused. second: status 2 was met.
+void qr_apply_rinv(int64_t m, int64_t d, void* scratch, bool second, double* b,
+                   int64_t k, hipStream_t s);  // b (d x k) <- R^{-1} b
+void qr_write_r(int64_t m, int64_t d, double* r_out, void* scratch, bool second,
+                hipStream_t s);
 // Householder QR of a in place, r_out as above. 64-column panels by
 // Cholesky-QR2 with Householder reconstruction (k_cqr.hip), the remaining
 // columns by the tree path. *fail (device int) is set to 1 when a panel is
@@ -138,10 +148,16 @@ void qr_factor_robust(double* a, int64_t m, int64_t d, double* r_out,
                       void* scratch, hipStream_t s);
 // whole-matrix Cholesky-QR2 (k_cholqr.hip)
 size_t cholqr2_scratch_bytes(int64_t m, int64_t d);
+// (qs is reserved for overlapping parts of the factorisation)
 void cholqr2_factor(double* a, int64_t m, int64_t d, double* r_out,
-                    void* scratch, int* status, hipStream_t s);
+                    void* scratch, int* status, const QrStreams& qs,
+                    hipStream_t s, bool want_r, double* dstat);
 void cholqr2_finish(int64_t m, int64_t d, double* r_out, void* scratch,
-                    int* status, hipStream_t s);
+                    int* status, hipStream_t s, bool want_r, double* dstat);
+void cholqr2_write_r(int64_t m, int64_t d, double* r_out, void* scratch,
+                     bool second, hipStream_t s);
+void cholqr2_apply_rinv(int64_t m, int64_t d, void* scratch, bool second,
+                        double* b, int64_t k, hipStream_t s);
 // 64-column panel path (k_cqr.hip)
 size_t cqr_scratch_bytes(int64_t m, int64_t d);
 int64_t cqr_panels(int64_t m, int64_t d);

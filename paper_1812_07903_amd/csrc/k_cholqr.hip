@@ -274,7 +274,8 @@ __global__ void __launch_bounds__(256)
 __global__ void __launch_bounds__(256)
     bchol_first_kernel(const double* __restrict__ G, const double* __restrict__ gdiag,
                        double tol, double* __restrict__ R,
-                       double* __restrict__ Dinv, int* __restrict__ flag) {
+                       double* __restrict__ Dinv, double* __restrict__ X,
+                       int* __restrict__ flag) {
   __shared__ double TC[kTile];
   __shared__ double TX[kTile];
   __shared__ double tmp[4][16][17];
@@ -291,13 +292,89 @@ __global__ void __launch_bounds__(256)
   }
   tile_to_global(R, TC, t);
   tile_to_global(Dinv, TX, t);
+  if (X) tile_to_global(X, TX, t);
+}
+
+// X = R^{-1} block column by block column from X R = I:
+//   X_ik = -(sum_{l=i}^{k-1} X_il R_lk) R_kk^{-1},  i < k.
+// Each term needs block column l of X and block row l of R, which the step
+// launches produce at step l. So the terms are added as they become
+// available: at step k every pair (i, j), i < k < j, takes the term
+// l = k - 1 into a running sum P_ij (one product per workgroup), and block
+// column k is finished from P_ik and its last term (two products). No
+// workgroup of a step then does more than the diagonal one.
+__device__ __forceinline__ void two_tiles(double* TA, double* TB,
+                                          const double* a, const double* b,
+                                          int t) {
+  load_tile(TA, a, kP, kP, kP, t);
+  load_tile(TB, b, kP, kP, kP, t);
+}
+
+// X_ik = -(P_ik + X_{i,k-1} R_{k-1,k}) R_kk^{-1} (P_ik holds the terms
+// l <= k - 2 when i <= k - 2)
+__device__ __forceinline__ void xinv_finish(int64_t i, int64_t k, int64_t nb,
+                                            const double* __restrict__ R,
+                                            const double* __restrict__ Dinv,
+                                            double* __restrict__ X,
+                                            const double* __restrict__ P,
+                                            double* TA, double* TB, int t) {
+  const int lane = t & 63, w = t >> 6;
+  dbl4 acc[4];
+  if (i + 2 <= k)
+    ld_acc(acc, P + tix(i, k, nb), lane, w);
+  else
+    zero4(acc);
+  two_tiles(TA, TB, X + tix(i, k - 1, nb), R + tix(k - 1, k, nb), t);
+  __syncthreads();
+  mm64<false>(TA, TB, acc, lane, w);
+  __syncthreads();
+  store_acc(TA, acc, -1.0, lane, w);
+  load_tile(TB, Dinv + k * kT2, kP, kP, kP, t);
+  __syncthreads();
+  dbl4 res[4];
+  zero4(res);
+  mm64<false>(TA, TB, res, lane, w);
+  store_acc_global(X + tix(i, k, nb), kP, res, 1.0, lane, w);
+}
+
+// P_ij (+)= X_{i,k-1} R_{k-1,j}: the first term when i = k - 1
+__device__ __forceinline__ void xinv_term(int64_t i, int64_t j, int64_t k,
+                                          int64_t nb, const double* __restrict__ R,
+                                          const double* __restrict__ X,
+                                          double* __restrict__ P, double* TA,
+                                          double* TB, int t) {
+  const int lane = t & 63, w = t >> 6;
+  dbl4 acc[4];
+  if (i + 1 < k)
+    ld_acc(acc, P + tix(i, j, nb), lane, w);
+  else
+    zero4(acc);
+  two_tiles(TA, TB, X + tix(i, k - 1, nb), R + tix(k - 1, j, nb), t);
+  __syncthreads();
+  mm64<false>(TA, TB, acc, lane, w);
+  store_acc_global(P + tix(i, j, nb), kP, acc, 1.0, lane, w);
+}
+
+// Block column k of X (tiles i < k); used for the last block column, which
+// the step launches do not reach.
+__global__ void __launch_bounds__(256)
+    binv_col_kernel(int64_t nb, int64_t k, const double* __restrict__ R,
+                    const double* __restrict__ Dinv, double* __restrict__ X,
+                    const double* __restrict__ P, const int* __restrict__ flag) {
+  __shared__ double TA[kTile];
+  __shared__ double TB[kTile];
+  if (*flag) return;
+  xinv_finish(blockIdx.x, k, nb, R, Dinv, X, P, TA, TB, threadIdx.x);
 }
 
 // Step k: tiles (i, j), k < i <= j, one workgroup each (see the header).
+// With X, k more workgroups finish block column k of X = R^{-1}, and
+// k (nb - k - 1) more add the term l = k - 1 to the running sums P_ij.
 __global__ void __launch_bounds__(256)
     bchol_step_kernel(double* __restrict__ G, int64_t nb, int64_t k,
                       const double* __restrict__ gdiag, double tol,
                       double* __restrict__ R, double* __restrict__ Dinv,
+                      double* __restrict__ X, double* __restrict__ P,
                       int* __restrict__ flag) {
   __shared__ double TI[kTile];
   __shared__ double TA[kTile];
@@ -308,8 +385,18 @@ __global__ void __launch_bounds__(256)
   __shared__ int bad;
   if (*flag) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t n = nb - k - 1;
+  const int64_t ntile = n * (n + 1) / 2;
+  if (blockIdx.x >= ntile) {
+    const int64_t b = blockIdx.x - ntile;
+    if (b < k)
+      xinv_finish(b, k, nb, R, Dinv, X, P, TA, TB, t);
+    else
+      xinv_term((b - k) / n, k + 1 + (b - k) % n, k, nb, R, X, P, TA, TB, t);
+    return;
+  }
   int64_t i, j;
-  upper_tile(blockIdx.x, nb - k - 1, i, j);
+  upper_tile(blockIdx.x, n, i, j);
   i += k + 1;
   j += k + 1;
   const bool diag = i == j;
@@ -347,6 +434,7 @@ __global__ void __launch_bounds__(256)
     }
     tile_to_global(R + tix(i, i, nb), TC, t);
     tile_to_global(Dinv + i * kT2, TI, t);
+    if (X) tile_to_global(X + tix(i, i, nb), TI, t);
   } else {
     store_acc_global(G + tix(i, j, nb), kP, acc, 1.0, lane, w);
   }
@@ -477,7 +565,7 @@ __global__ void __launch_bounds__(256)
                    int* __restrict__ status, double* __restrict__ r_out) {
   __shared__ double TA[kTile];
   __shared__ double TB[kTile];
-  if (*status) return;
+  if (status && *status) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int p = lane & 15, q = lane >> 4;
   const int64_t i = blockIdx.x / nb, j = blockIdx.x % nb;
@@ -495,7 +583,7 @@ __global__ void __launch_bounds__(256)
     const double em = __longlong_as_double(static_cast<long long>(red[0]));
     const bool ok = em <= 0.25 / static_cast<double>(d);  // false for NaN
     if (!ok || em > kNearId) {
-      if (blockIdx.x == 0 && t == 0) *status = ok ? 2 : 1;
+      if (status && blockIdx.x == 0 && t == 0) *status = ok ? 2 : 1;
       return;
     }
   }
@@ -539,9 +627,143 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// ---- R^{-1} B through the tiled inverse ---------------------------------------
+// out = T B for an upper-triangular tiled T (d x d) and B (d x kk row-major):
+// row block I of out sums T_IJ B_J over J >= I; the sum is split into chunks
+// of kCH tile columns (one workgroup each, partial 64 x 64 blocks), then the
+// chunks are added in order. MODE 0 takes T's tiles as stored; MODE 1 forms
+// T = I - up(G - I) from the tiles of a Gram matrix G close to I (the first
+// two terms of (I + up(G - I))^{-1}; the next is below d max|G - I|^2).
+constexpr int64_t kCH = 3;
+
+__host__ __device__ inline int64_t tri_chunks(int64_t nb, int64_t I) {
+  return (nb - I + kCH - 1) / kCH;
+}
+__host__ __device__ inline int64_t tri_parts(int64_t nb) {
+  int64_t n = 0;
+  for (int64_t I = 0; I < nb; ++I) n += tri_chunks(nb, I);
+  return n;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256)
+    tri_part_kernel(const double* __restrict__ T, int64_t nb, int64_t d,
+                    const double* __restrict__ B, int64_t kk, int64_t cb0,
+                    int64_t ncb, double* __restrict__ part,
+                    const int* __restrict__ flag) {
+  __shared__ double TA[kTile];
+  __shared__ double TB[kTile];
+  if (flag && *flag) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int64_t pidx = blockIdx.x, I = 0, rest = blockIdx.x;
+  while (rest >= tri_chunks(nb, I)) {
+    rest -= tri_chunks(nb, I);
+    ++I;
+  }
+  const int64_t J0 = I + rest * kCH;
+  const int64_t J1 = J0 + kCH < nb ? J0 + kCH : nb;
+  const int64_t cb = cb0 + blockIdx.y;
+  const int64_t c0 = cb * kP;
+  dbl4 acc[4];
+  zero4(acc);
+  for (int64_t J = J0; J < J1; ++J) {
+    Stage vt, vb;
+    stage_load(vt, T + tix(I, J, nb), kP, kP, kP, t);
+    stage_load(vb, B + J * kP * kk + c0, kk, d - J * kP, kk - c0, t);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = t + 256 * u;
+      const int a = e >> 6, b = e & 63;
+      double v = vt.v[u];
+      if (MODE == 1) {
+        const int64_t gi = I * kP + a, gj = J * kP + b;
+        v = gi < gj ? -v : (gi == gj ? 1.0 - 0.5 * (v - 1.0) : 0.0);
+      }
+      TA[a * kS + b] = v;
+    }
+    stage_store(TB, vb, t);
+    __syncthreads();
+    mm64<false>(TA, TB, acc, lane, w);
+  }
+  store_acc_global(part + (pidx * ncb + blockIdx.y) * kT2, kP, acc, 1.0, lane,
+                   w);
+}
+
+__global__ void __launch_bounds__(256)
+    tri_sum_kernel(const double* __restrict__ part, int64_t nb, int64_t d,
+                   int64_t kk, int64_t cb0, int64_t ncb,
+                   double* __restrict__ out, const int* __restrict__ flag) {
+  if (flag && *flag) return;
+  const int64_t I = blockIdx.x, cbl = blockIdx.y;
+  const int e = static_cast<int>(blockIdx.z) * 256 + threadIdx.x;
+  int64_t p0 = 0;
+  for (int64_t i = 0; i < I; ++i) p0 += tri_chunks(nb, i);
+  double v = 0.0;
+  for (int64_t ch = 0; ch < tri_chunks(nb, I); ++ch)
+    v += part[((p0 + ch) * ncb + cbl) * kT2 + e];
+  const int64_t row = I * kP + (e >> 6), col = (cb0 + cbl) * kP + (e & 63);
+  if (row < d && col < kk) out[row * kk + col] = v;
+}
+
+// min and max |R_jj| without forming R: R_jj = (1 + F_jj) R1_jj with
+// F_jj = (G2_jj - 1) / 2 (NEAR, after the checks of r_final_kernel), or
+// R2_jj R1_jj.
+template <bool NEAR>
+__global__ void __launch_bounds__(256)
+    r_diag_kernel(const double* __restrict__ R1, const double* __restrict__ R2,
+                  const double* __restrict__ gdiag, int64_t nb, int64_t d,
+                  const unsigned long long* __restrict__ emax,
+                  int* __restrict__ status, double* __restrict__ dstat) {
+  __shared__ unsigned long long redu[256];
+  __shared__ double rmin[256], rmax[256];
+  if (*status) return;
+  const int t = threadIdx.x;
+  if (NEAR) {
+    const int64_t ne = nb * (nb + 1) / 2 * 16;
+    unsigned long long b = 0ull;
+    for (int64_t e = t; e < ne; e += 256) b = emax[e] > b ? emax[e] : b;
+    redu[t] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) redu[t] = redu[t + o] > redu[t] ? redu[t + o] : redu[t];
+      __syncthreads();
+    }
+    const double em = __longlong_as_double(static_cast<long long>(redu[0]));
+    const bool ok = em <= 0.25 / static_cast<double>(d);
+    if (!ok || em > kNearId) {
+      if (t == 0) *status = ok ? 2 : 1;
+      return;
+    }
+  }
+  double lo = 1.0 / 0.0, hi = 0.0;
+  for (int64_t j = t; j < d; j += 256) {
+    const int64_t I = j / kP, o = (j % kP) * kP + j % kP;
+    const double r1 = R1[tix(I, I, nb) + o];
+    const double f = NEAR ? 1.0 + 0.5 * (gdiag[j] - 1.0) : R2[tix(I, I, nb) + o];
+    const double v = fabs(f * r1);
+    lo = v < lo ? v : lo;
+    hi = v > hi ? v : hi;
+  }
+  rmin[t] = lo;
+  rmax[t] = hi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      rmin[t] = rmin[t + o] < rmin[t] ? rmin[t + o] : rmin[t];
+      rmax[t] = rmax[t + o] > rmax[t] ? rmax[t + o] : rmax[t];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    dstat[0] = rmin[0];
+    dstat[1] = rmax[0];
+  }
+}
+
 struct Cq2 {
   int64_t nb, nt, S, chunk, Se, chunk_e, nfull, nedge;
-  double *part, *G, *R1, *R2, *Dinv, *gdiag;
+  double *part, *G, *R1, *R2, *X1, *X2, *P, *Dinv, *gdiag, *apart;
   unsigned long long* emax;
 };
 
@@ -576,6 +798,10 @@ Cq2 cq2_carve(void* base, int64_t m, int64_t d) {
   c.G = p;     p += c.nb * c.nb * kT2;
   c.R1 = p;    p += c.nb * c.nb * kT2;
   c.R2 = p;    p += c.nb * c.nb * kT2;
+  c.X1 = p;    p += c.nb * c.nb * kT2;
+  c.X2 = p;    p += c.nb * c.nb * kT2;
+  c.P = p;     p += c.nb * c.nb * kT2;
+  c.apart = p; p += tri_parts(c.nb) * c.nb * kT2;
   c.Dinv = p;  p += c.nb * kT2;
   c.gdiag = p; p += c.nb * kP;
   c.emax = reinterpret_cast<unsigned long long*>(p);  // nt * 16 entries
@@ -585,6 +811,8 @@ Cq2 cq2_carve(void* base, int64_t m, int64_t d) {
 void gram_tiles(const double* a, int64_t m, int64_t d, const Cq2& c,
                 bool with_emax, int* flag, hipStream_t s) {
   unsigned long long* em = with_emax ? c.emax : nullptr;
+  // (the thin blocks gain nothing on a second stream: the main blocks hold
+  // every slot until their last round ends)
   prof_begin(kKCq2Gram, s);
   if (c.nfull > 0)
     gram_block_kernel<false><<<static_cast<unsigned>(c.nfull * c.S), 256, 0, s>>>(
@@ -594,19 +822,27 @@ void gram_tiles(const double* a, int64_t m, int64_t d, const Cq2& c,
   if (c.nedge > 0)
     gram_block_kernel<true><<<static_cast<unsigned>(c.nedge * c.Se), 256, 0, s>>>(
         a, d, m, d, c.Se, c.chunk_e, c.nfull * c.S, c.part, flag);
+  prof_end(kKCq2GramEdge, s);
+  prof_begin(kKCq2GramSum, s);
   gram_reduce_kernel<<<static_cast<unsigned>(c.nt * 16), 256, 0, s>>>(
       c.part, c.S, c.Se, c.nb, d, c.G, c.gdiag, em, flag);
-  prof_end(kKCq2GramEdge, s);
+  prof_end(kKCq2GramSum, s);
 }
 
-void bchol(const Cq2& c, double* R, int* flag, hipStream_t s) {
+// Blocked Cholesky of c.G into the tiles R (and, with X, R^{-1} into X)
+void bchol(const Cq2& c, double* R, double* X, int* flag, hipStream_t s) {
   prof_begin(kKCq2Chol, s);
-  bchol_first_kernel<<<1, 256, 0, s>>>(c.G, c.gdiag, kPivotTol, R, c.Dinv, flag);
+  bchol_first_kernel<<<1, 256, 0, s>>>(c.G, c.gdiag, kPivotTol, R, c.Dinv, X,
+                                       flag);
   for (int64_t k = 0; k + 1 < c.nb; ++k) {
     const int64_t n = c.nb - k - 1;
-    bchol_step_kernel<<<static_cast<unsigned>(n * (n + 1) / 2), 256, 0, s>>>(
-        c.G, c.nb, k, c.gdiag, kPivotTol, R, c.Dinv, flag);
+    const int64_t grid = n * (n + 1) / 2 + (X ? k + k * n : 0);
+    bchol_step_kernel<<<static_cast<unsigned>(grid), 256, 0, s>>>(
+        c.G, c.nb, k, c.gdiag, kPivotTol, R, c.Dinv, X, c.P, flag);
   }
+  if (X && c.nb > 1)
+    binv_col_kernel<<<static_cast<unsigned>(c.nb - 1), 256, 0, s>>>(
+        c.nb, c.nb - 1, R, c.Dinv, X, c.P, flag);
   prof_end(kKCq2Chol, s);
 }
 
@@ -615,37 +851,92 @@ void bchol(const Cq2& c, double* R, int* flag, hipStream_t s) {
 size_t cholqr2_scratch_bytes(int64_t m, int64_t d) {
   const Cq2 c = cq2_shape(m, d);
   return static_cast<size_t>((c.nfull * c.S + c.nedge * c.Se) * kB2 +
-                             3 * c.nb * c.nb * kT2 +
+                             6 * c.nb * c.nb * kT2 +
+                             tri_parts(c.nb) * c.nb * kT2 +
                              c.nb * kT2 + c.nb * kP + c.nt * 16 + 8) *
          sizeof(double);
 }
 
+namespace {
+// out = T B (see tri_part_kernel); out may be B
+template <int MODE>
+void tri_apply(const Cq2& c, const double* T, int64_t d, const double* B,
+               int64_t kk, double* out, const int* flag, hipStream_t s) {
+  const int64_t ncb_all = (kk + kP - 1) / kP;
+  const unsigned np = static_cast<unsigned>(tri_parts(c.nb));
+  for (int64_t cb0 = 0; cb0 < ncb_all; cb0 += c.nb) {
+    const int64_t ncb = ncb_all - cb0 < c.nb ? ncb_all - cb0 : c.nb;
+    tri_part_kernel<MODE><<<dim3(np, static_cast<unsigned>(ncb)), 256, 0, s>>>(
+        T, c.nb, d, B, kk, cb0, ncb, c.apart, flag);
+    tri_sum_kernel<<<dim3(static_cast<unsigned>(c.nb),
+                          static_cast<unsigned>(ncb), 16),
+                     256, 0, s>>>(c.apart, c.nb, d, kk, cb0, ncb, out, flag);
+  }
+}
+}  // namespace
+
 void cholqr2_factor(double* a, int64_t m, int64_t d, double* r_out,
-                    void* scratch, int* status, hipStream_t s) {
+                    void* scratch, int* status, const QrStreams& qs,
+                    hipStream_t s, bool want_r, double* dstat) {
+  (void)qs;
   const Cq2 c = cq2_carve(scratch, m, d);
   launch_fill_i32(status, 1, 0, s);
   gram_tiles(a, m, d, c, false, status, s);
-  bchol(c, c.R1, status, s);
+  bchol(c, c.R1, want_r ? nullptr : c.X1, status, s);
   prof_begin(kKCq2Solve, s);
   stripe_solve_kernel<<<cdivu(m, kP), kSW, 0, s>>>(a, d, m, d, c.nb, c.R1,
                                                     c.Dinv, status);
   prof_end(kKCq2Solve, s);
   gram_tiles(a, m, d, c, true, status, s);
   prof_begin(kKCq2R, s);
-  r_final_kernel<true><<<static_cast<unsigned>(c.nb * c.nb), 256, 0, s>>>(
-      c.R1, c.G, c.nb, d, c.emax, status, r_out);
+  if (want_r)
+    r_final_kernel<true><<<static_cast<unsigned>(c.nb * c.nb), 256, 0, s>>>(
+        c.R1, c.G, c.nb, d, c.emax, status, r_out);
+  else
+    r_diag_kernel<true><<<1, 256, 0, s>>>(c.R1, nullptr, c.gdiag, c.nb, d,
+                                          c.emax, status, dstat);
   prof_end(kKCq2R, s);
 }
 
 void cholqr2_finish(int64_t m, int64_t d, double* r_out, void* scratch,
-                    int* status, hipStream_t s) {
+                    int* status, hipStream_t s, bool want_r, double* dstat) {
   const Cq2 c = cq2_carve(scratch, m, d);
   launch_fill_i32(status, 1, 0, s);
-  bchol(c, c.R2, status, s);
+  bchol(c, c.R2, want_r ? nullptr : c.X2, status, s);
   prof_begin(kKCq2R, s);
-  r_final_kernel<false><<<static_cast<unsigned>(c.nb * c.nb), 256, 0, s>>>(
-      c.R1, c.R2, c.nb, d, c.emax, status, r_out);
+  if (want_r)
+    r_final_kernel<false><<<static_cast<unsigned>(c.nb * c.nb), 256, 0, s>>>(
+        c.R1, c.R2, c.nb, d, c.emax, status, r_out);
+  else
+    r_diag_kernel<false><<<1, 256, 0, s>>>(c.R1, c.R2, c.gdiag, c.nb, d,
+                                           c.emax, status, dstat);
   prof_end(kKCq2R, s);
+}
+
+void cholqr2_write_r(int64_t m, int64_t d, double* r_out, void* scratch,
+                     bool second, hipStream_t s) {
+  const Cq2 c = cq2_carve(scratch, m, d);
+  prof_begin(kKCq2R, s);
+  if (second)
+    r_final_kernel<false><<<static_cast<unsigned>(c.nb * c.nb), 256, 0, s>>>(
+        c.R1, c.R2, c.nb, d, c.emax, nullptr, r_out);
+  else
+    r_final_kernel<true><<<static_cast<unsigned>(c.nb * c.nb), 256, 0, s>>>(
+        c.R1, c.G, c.nb, d, c.emax, nullptr, r_out);
+  prof_end(kKCq2R, s);
+}
+
+void cholqr2_apply_rinv(int64_t m, int64_t d, void* scratch, bool second,
+                        double* b, int64_t kk, hipStream_t s) {
+  const Cq2 c = cq2_carve(scratch, m, d);
+  prof_begin(kKTrsm, s);
+  // R^{-1} = R1^{-1} (I + F)^{-1} = X1 (I - F) to rounding, or X1 R2^{-1}
+  if (second)
+    tri_apply<0>(c, c.X2, d, b, kk, b, nullptr, s);
+  else
+    tri_apply<1>(c, c.G, d, b, kk, b, nullptr, s);
+  tri_apply<0>(c, c.X1, d, b, kk, b, nullptr, s);
+  prof_end(kKTrsm, s);
 }
 
 }  // namespace slso

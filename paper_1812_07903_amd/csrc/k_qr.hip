@@ -758,14 +758,25 @@ size_t qr_scratch_bytes(int64_t m, int64_t d) {
          std::max(cqr_scratch_bytes(m, d), cholqr2_scratch_bytes(m, d)) + 512;
 }
 void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
-               int* status, hipStream_t s) {
+               int* status, const QrStreams& qs, hipStream_t s, bool want_r,
+               double* dstat) {
   cholqr2_factor(a, m, d, r_out, static_cast<char*>(scratch) + tree_part(m),
-                 status, s);
+                 status, qs, s, want_r, dstat);
 }
 void qr_factor_finish(int64_t m, int64_t d, double* r_out, void* scratch,
-                      int* status, hipStream_t s) {
+                      int* status, hipStream_t s, bool want_r, double* dstat) {
   cholqr2_finish(m, d, r_out, static_cast<char*>(scratch) + tree_part(m),
-                 status, s);
+                 status, s, want_r, dstat);
+}
+void qr_apply_rinv(int64_t m, int64_t d, void* scratch, bool second, double* b,
+                   int64_t k, hipStream_t s) {
+  cholqr2_apply_rinv(m, d, static_cast<char*>(scratch) + tree_part(m), second,
+                     b, k, s);
+}
+void qr_write_r(int64_t m, int64_t d, double* r_out, void* scratch, bool second,
+                hipStream_t s) {
+  cholqr2_write_r(m, d, r_out, static_cast<char*>(scratch) + tree_part(m),
+                  second, s);
 }
 void qr_factor_panel(double* a, int64_t m, int64_t d, double* r_out,
                      void* scratch, int* fail, const QrStreams& qs,

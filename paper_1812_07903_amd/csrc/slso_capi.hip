@@ -258,19 +258,29 @@ void size_sketch_bufs(Sizer& z, int64_t n, int64_t r) {
   z.take<char>(radix_sort_scratch_bytes(n));
 }
 
+// Bucket partition of the rows (hash, stable sort by bucket, offsets): it
+// reads no input values.
+void enqueue_partition(int64_t n, uint64_t seed, int64_t r,
+                       const SketchBufs& b, hipStream_t s) {
+  const HashCoeffs hb = make_hash_coeffs(seed, kStreamBucket);
+  const HashCoeffs hs = make_hash_coeffs(seed, kStreamSign);
+  launch_hash_pack(hb, hs, r, 0, n, b.keys, b.vals, s);
+  radix_sort_pairs(b.keys, b.vals, b.keys_s, b.vals_s, b.keys_t, b.vals_t, n,
+                   bits_for(r), b.sort_ws, s);
+  launch_bucket_offsets(b.keys_s, n, r, b.off, s);
+}
+void enqueue_gather(const slso_matrix* X, int64_t r, const SketchBufs& b,
+                    const double* dscale, double* sx, hipStream_t s) {
+  launch_countsketch(X->values, X->dtype, X->format, X->n, X->d, X->ld,
+                     X->row_ptr, X->col_idx, X->col_scale, X->row_scale,
+                     b.vals_s, b.off, r, dscale, sx, s);
+}
 // Bucket partition + CountSketch into sx (r x d), optionally column-scaled.
 void enqueue_countsketch(const slso_matrix* X, uint64_t seed, int64_t r,
                          const SketchBufs& b, const double* dscale, double* sx,
                          hipStream_t s) {
-  const HashCoeffs hb = make_hash_coeffs(seed, kStreamBucket);
-  const HashCoeffs hs = make_hash_coeffs(seed, kStreamSign);
-  launch_hash_pack(hb, hs, r, 0, X->n, b.keys, b.vals, s);
-  radix_sort_pairs(b.keys, b.vals, b.keys_s, b.vals_s, b.keys_t, b.vals_t, X->n,
-                   bits_for(r), b.sort_ws, s);
-  launch_bucket_offsets(b.keys_s, X->n, r, b.off, s);
-  launch_countsketch(X->values, X->dtype, X->format, X->n, X->d, X->ld,
-                     X->row_ptr, X->col_idx, X->col_scale, X->row_scale,
-                     b.vals_s, b.off, r, dscale, sx, s);
+  enqueue_partition(X->n, seed, r, b, s);
+  enqueue_gather(X, r, b, dscale, sx, s);
 }
 
 size_t gemm_partial_bytes(const slso_matrix* X, int64_t r, bool gauss,
@@ -495,7 +505,7 @@ int slso_qr_r_path(slso_ctx* c, double* a, int64_t m, int64_t d,
   int used = path;
   bool done = false;
   if (path == SLSO_QR_AUTO) {
-    qr_factor(a, m, d, r_out, qws, status, s);
+    qr_factor(a, m, d, r_out, qws, status, c->qs, s);
     if ((st = check_launch(c, "slso_qr_r"))) return st;
     if ((st = read_status())) return st;
     if (*hf == 2) {
@@ -623,6 +633,15 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   double* part = a.take<double>(scores_partial_bytes(n, d, kk, X->format, X->dtype) / 8);
   double* tws = a.take<double>(trsm_blocked_scratch(d, refine ? d : kk) / 8);
 
+  // 0. the bucket partition needs no input values: it runs on the context's
+  // second stream while the column maxima are taken
+  const bool side_partition = !gauss && c->qs.side;
+  if (side_partition) {
+    SLSO_HIP(c, hipEventRecord(c->qs.factored, s));
+    SLSO_HIP(c, hipStreamWaitEvent(c->qs.side, c->qs.factored, 0));
+    enqueue_partition(n, seed, r, sb, c->qs.side);
+    SLSO_HIP(c, hipEventRecord(c->qs.bulk_done, c->qs.side));
+  }
   // 1. column equilibration D (power of two) from column max-abs of X
   launch_fill_u64(colmax, d, 0, s);
   launch_fill_i32(flags, 64, 0, s);
@@ -641,15 +660,25 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   // The QR's 64-column panels use Cholesky-QR2; when one is too ill-
   // conditioned for it (flags[2]), the sketch is formed again and factored
   // column by column.
+  bool partitioned = false;
   auto sketch = [&]() {
-    if (gauss)
+    if (gauss) {
       launch_gauss_sketch(X->values, X->dtype, n, d, X->ld, X->col_scale, seed,
                           r, dscale, static_cast<float*>(gpart), sx, s);
-    else
+    } else if (side_partition) {
+      if (!partitioned)
+        (void)hipStreamWaitEvent(s, c->qs.bulk_done, 0);
+      partitioned = true;
+      enqueue_gather(X, r, sb, rowfac, sx, s);
+    } else {
       enqueue_countsketch(X, seed, r, sb, rowfac, sx, s);
+    }
   };
-  auto post = [&]() {
-    launch_diag_stats(RS, d, dstat, s);
+  // post(r_formed): rank-screen statistics of the R just formed (when
+  // Cholesky-QR2 ran without forming R it wrote them itself), then the
+  // refinement, which needs R_S
+  auto post = [&](bool r_formed) {
+    if (r_formed) launch_diag_stats(RS, d, dstat, s);
     if (refine) {
       launch_fill_i32(flags + 1, 1, 0, s);
       launch_gram(X->values, X->dtype, n, d, X->ld, X->col_scale, dscale, gpart,
@@ -680,29 +709,36 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   // does not apply (flags[2] = 1: the sketch is too ill-conditioned), the
   // sketch is formed again and factored by the Householder panel path, and
   // should that fail too, column by column.
+  // Without the refinement R itself is only needed if the rank screen trips:
+  // Cholesky-QR2 then keeps R^{-1} in factored form and applies it to Pi_2.
+  const bool want_r = refine;
+  bool cholqr2 = true, second = false, r_formed = want_r;
   int32_t info_flags = 0;
   sketch();
-  qr_factor(sx, r, d, RS, qws, flags + 2, s);
-  post();
+  qr_factor(sx, r, d, RS, qws, flags + 2, c->qs, s, want_r, dstat);
+  post(want_r);
   if ((st = readback())) return st;
   if (fl[0]) return set_err(c, SLSO_ENONFINITE, "X holds Inf or NaN");
   if (fl[2] == 2) {
     info_flags |= SLSO_INFO_QR_SECOND_CHOLESKY;
-    qr_factor_finish(r, d, RS, qws, flags + 2, s);
-    post();
+    second = true;
+    qr_factor_finish(r, d, RS, qws, flags + 2, s, want_r, dstat);
+    post(want_r);
     if ((st = readback())) return st;
   }
   if (fl[2] != 0) {
     info_flags |= SLSO_INFO_QR_HOUSEHOLDER;
+    cholqr2 = false;
+    r_formed = true;
     sketch();
     qr_factor_panel(sx, r, d, RS, qws, flags + 2, c->qs, s);
-    post();
+    post(true);
     if ((st = readback())) return st;
     if (fl[2] != 0) {
       info_flags |= SLSO_INFO_QR_TREE;
       sketch();
       qr_factor_robust(sx, r, d, RS, qws, s);
-      post();
+      post(true);
       if ((st = readback())) return st;
     }
   }
@@ -729,9 +765,13 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
                     pi, s);
   int64_t rank = d;
   if (full) {
-    solve_upper(R, d, pi, kk, s, tws);
+    if (cholqr2 && !refine)
+      qr_apply_rinv(r, d, qws, second, pi, kk, s);
+    else
+      solve_upper(R, d, pi, kk, s, tws);
     launch_scale_rows(pi, rowfac, d, kk, m64, m32, s);
   } else {
+    if (!r_formed) qr_write_r(r, d, RS, qws, second, s);
     Sizer jz;
     jz.take<char>(jacobi_scratch_bytes(d, kk));
     // the Jacobi scratch reuses the sketch area, which is no longer needed
@@ -837,7 +877,7 @@ const char* slso_profile_name(int id) {
       "colmax", "countsketch", "qr_node", "qr_update", "qr_extract", "trsm",
       "score", "gaussian", "gauss_sketch", "gram", "cholesky", "cq_gram",
       "cq_sum", "cq_chol", "cq_q1", "cq_z", "cq_recon", "cq_w", "cq_update", "cq2_gram",
-      "cq2_gram_edge", "cq2_chol", "cq2_solve", "cq2_r"};
+      "cq2_gram_edge", "cq2_gram_sum", "cq2_chol", "cq2_solve", "cq2_r"};
   if (id < 0 || id >= slso::kKCount) return "";
   return names[id];
 }
