@@ -14,8 +14,11 @@ namespace slso {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 16;
-constexpr int kTile = kThreads * kItems;
+// keys per thread of the histogram and scatter passes: 16 for large inputs,
+// 4 below kSmallSort keys (more workgroups: the passes are latency bound there)
+constexpr int kItemsLarge = 16;
+constexpr int kItemsSmall = 4;
+constexpr int64_t kSmallSort = int64_t{1} << 20;
 
 __global__ void hash_pack_kernel(HashCoeffs hb, HashCoeffs hs, uint64_t r,
                                  int64_t row0, int64_t n, uint32_t* keys,
@@ -60,9 +63,11 @@ __global__ void score_keys_kernel(const float* s, int64_t n, uint32_t* keys) {
   keys[i] = ~asc;  // ascending key order = descending score order
 }
 
+template <int kItems>
 __global__ void __launch_bounds__(kThreads)
     rs_hist_kernel(const uint32_t* __restrict__ keys, int64_t n, int shift,
                    uint32_t* __restrict__ hist, int nblocks) {
+  constexpr int kTile = kThreads * kItems;
   __shared__ uint32_t h[256];
   const int tid = threadIdx.x;
   h[tid] = 0;
@@ -77,7 +82,9 @@ __global__ void __launch_bounds__(kThreads)
   hist[static_cast<int64_t>(tid) * nblocks + blockIdx.x] = h[tid];
 }
 
-// Exclusive scan of len entries in place, one workgroup of 1024 threads.
+// Exclusive scan of len entries in place, one workgroup of 1024 threads:
+// thread t owns one contiguous segment; its entries are read 16 at a time
+// with all loads in flight together.
 __global__ void __launch_bounds__(1024)
     rs_scan_kernel(uint32_t* __restrict__ hist, int64_t len) {
   __shared__ uint32_t s[1024];
@@ -86,7 +93,13 @@ __global__ void __launch_bounds__(1024)
   const int64_t lo = tid * seg;
   const int64_t hi = lo + seg < len ? lo + seg : len;
   uint32_t sum = 0;
-  for (int64_t p = lo; p < hi; ++p) sum += hist[p];
+  for (int64_t c = lo; c < hi; c += 16) {
+    uint32_t v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = c + u < hi ? hist[c + u] : 0u;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sum += v[u];
+  }
   s[tid] = sum;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -96,19 +109,26 @@ __global__ void __launch_bounds__(1024)
     __syncthreads();
   }
   uint32_t run = s[tid] - sum;
-  for (int64_t p = lo; p < hi; ++p) {
-    const uint32_t v = hist[p];
-    hist[p] = run;
-    run += v;
+  for (int64_t c = lo; c < hi; c += 16) {
+    uint32_t v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = c + u < hi ? hist[c + u] : 0u;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if (c + u < hi) hist[c + u] = run;
+      run += v[u];
+    }
   }
 }
 
+template <int kItems>
 __global__ void __launch_bounds__(kThreads)
     rs_scatter_kernel(const uint32_t* __restrict__ keys_in,
                       const uint32_t* __restrict__ vals_in,
                       uint32_t* __restrict__ keys_out,
                       uint32_t* __restrict__ vals_out, int64_t n, int shift,
                       const uint32_t* __restrict__ hist, int nblocks) {
+  constexpr int kTile = kThreads * kItems;
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcount[4][256];
   __shared__ uint32_t wpref[4][256];
@@ -212,9 +232,14 @@ void launch_score_keys(const float* scores, int64_t n, uint32_t* keys,
   score_keys_kernel<<<grid1(n, 256), 256, 0, s>>>(scores, n, keys);
 }
 
+namespace {
+int sort_items(int64_t n) { return n < kSmallSort ? kItemsSmall : kItemsLarge; }
+}  // namespace
+
 size_t radix_sort_scratch_bytes(int64_t n) {
-  const int64_t nb = (n + kTile - 1) / kTile;
-  return static_cast<size_t>(256 * (nb > 0 ? nb : 1)) * sizeof(uint32_t);
+  const int64_t tile = static_cast<int64_t>(kThreads) * sort_items(n);
+  const int64_t nblocks = (n + tile - 1) / tile;
+  return static_cast<size_t>(256 * nblocks) * sizeof(uint32_t);
 }
 
 void radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in,
@@ -222,7 +247,9 @@ void radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in,
                       uint32_t* keys_tmp, uint32_t* vals_tmp, int64_t n,
                       int nbits, void* scratch, hipStream_t s) {
   if (n <= 0) return;
-  const int nblocks = static_cast<int>((n + kTile - 1) / kTile);
+  const int items = sort_items(n);
+  const int64_t tile = static_cast<int64_t>(kThreads) * items;
+  const int nblocks = static_cast<int>((n + tile - 1) / tile);
   uint32_t* hist = static_cast<uint32_t*>(scratch);
   const int passes = nbits <= 0 ? 1 : (nbits + 7) / 8;
   const uint32_t* ksrc = keys_in;
@@ -233,14 +260,23 @@ void radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in,
     uint32_t* vdst = to_out ? vals_out : vals_tmp;
     const int shift = 8 * p;
     prof_begin(kKSortHist, s);
-    rs_hist_kernel<<<nblocks, kThreads, 0, s>>>(ksrc, n, shift, hist, nblocks);
+    if (items == kItemsSmall)
+      rs_hist_kernel<kItemsSmall><<<nblocks, kThreads, 0, s>>>(ksrc, n, shift,
+                                                               hist, nblocks);
+    else
+      rs_hist_kernel<kItemsLarge><<<nblocks, kThreads, 0, s>>>(ksrc, n, shift,
+                                                               hist, nblocks);
     prof_end(kKSortHist, s);
     prof_begin(kKSortScan, s);
     rs_scan_kernel<<<1, 1024, 0, s>>>(hist, static_cast<int64_t>(256) * nblocks);
     prof_end(kKSortScan, s);
     prof_begin(kKSortScatter, s);
-    rs_scatter_kernel<<<nblocks, kThreads, 0, s>>>(ksrc, vsrc, kdst, vdst, n,
-                                                   shift, hist, nblocks);
+    if (items == kItemsSmall)
+      rs_scatter_kernel<kItemsSmall><<<nblocks, kThreads, 0, s>>>(
+          ksrc, vsrc, kdst, vdst, n, shift, hist, nblocks);
+    else
+      rs_scatter_kernel<kItemsLarge><<<nblocks, kThreads, 0, s>>>(
+          ksrc, vsrc, kdst, vdst, n, shift, hist, nblocks);
     prof_end(kKSortScatter, s);
     ksrc = kdst;
     vsrc = vdst;
