@@ -161,20 +161,13 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
                           __builtin_amdgcn_readlane(__double2loint(x), l));
 }
 
-// 1/x and 1/sqrt(x) from the hardware approximations refined by two Newton
-// steps (full double precision, shorter chains than the library sequences).
+// 1/x from the hardware approximation refined by two Newton steps (full
+// double precision, a shorter chain than the library sequence).
 __device__ __forceinline__ double rcp_nr(double x) {
   double r = __builtin_amdgcn_rcp(x);
   r = fma(r, fma(-x, r, 1.0), r);
   r = fma(r, fma(-x, r, 1.0), r);
   return r;
-}
-__device__ __forceinline__ double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double hx = 0.5 * x;
-  y = y * fma(-hx * y, y, 1.5);
-  y = y * fma(-hx * y, y, 1.5);
-  return y;
 }
 
 // ---- 16 x 16 factorisations on one wave (lane l < 16 owns column l) ----------
@@ -225,38 +218,49 @@ __device__ __forceinline__ void tri_inv16(const double* B, double* Li, double* U
   }
 }
 
-// Cholesky of the symmetric block B (upper triangle read): B <- R (zeros
-// below), Xi <- R^{-1}; s16 (16 doubles of LDS) is scratch. False (the same
-// in every lane) when a pivot is not above lim[j].
-__device__ __forceinline__ bool chol16w(double* B, double* Xi, const double* lim,
-                                        double* s16, int lane) {
-  const int l = lane;
+// Cholesky of the symmetric block B (upper triangle read) on one wave, with
+// R^{-1} from the same eliminations: lane l < 16 holds column l of B, lane
+// 16 + c column c of the identity. Pivot j scales row j by 1/sqrt(pivot) and
+// subtracts multiples of it from the rows below; on the identity columns
+// these steps are forward substitution with R^T, so lane 16 + c ends with
+// column c of R^{-T}, which is row c of R^{-1}. B <- R (zeros below),
+// Xi <- R^{-1}. False (the same in every lane) when a pivot is not above
+// lim[j]; the outputs are then meaningless.
+__device__ __forceinline__ bool chol16x(double* B, double* Xi, const double* lim,
+                                        int lane) {
+  const int l = lane, lc = lane & 15, c = lane - 16;
+  double gc[16], lm[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const double bv = B[i <= lc ? i * kS + lc : lc * kS + i];
+    gc[i] = l < 16 ? bv : (i == c ? 1.0 : 0.0);
+    lm[i] = lim[i];
+  }
   bool ok = true;
-  {
-    double gc[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-      gc[i] = l < 16 ? (i <= l ? B[i * kS + l] : B[l * kS + i]) : 0.0;
+  for (int j = 0; j < 16; ++j) {
+    const double piv = readlane_d(gc[j], j);
+    ok = ok && piv > lm[j];
+    // 1/sqrt(piv) = y0 (1 - e)^{-1/2} with e = 1 - piv y0^2 for the hardware
+    // estimate y0; |e| < 1e-7, so the series to e^2 leaves a remainder far
+    // below rounding. Row j of R (or of the substitution) is g (1 + e/2 +
+    // 3e^2/8) with g = gc[j] y0.
+    const double y0 = __builtin_amdgcn_rsq(piv);
+    const double e = fma(-piv * y0, y0, 1.0);
+    const double g = l < j ? 0.0 : gc[j] * y0;
+    const double rjl = fma(g * e, fma(e, 0.375, 0.5), g);
+    gc[j] = rjl;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const double piv = readlane_d(gc[j], j);
-      ok = ok && (piv > lim[j]);
-      const double pv = ok ? piv : 1.0;
-      const double ir = rsq_nr(pv);
-      if (l == 0) s16[j] = ir;
-      const double rjl = l > j ? gc[j] * ir : (l == j ? pv * ir : 0.0);
-      gc[j] = rjl;  // row j of R from here on
-#pragma unroll
-      for (int i = j + 1; i < 16; ++i) gc[i] -= readlane_d(rjl, i) * rjl;
-    }
-    wave_sync();
-    if (l < 16) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) B[i * kS + l] = gc[i];
-    }
+    for (int i = j + 1; i < 16; ++i) gc[i] -= readlane_d(rjl, i) * rjl;
   }
   wave_sync();
-  tri_inv16(B, nullptr, Xi, s16, l);
+  if (l < 16) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) B[i * kS + l] = gc[i];
+  } else if (l < 32) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Xi[c * kS + i] = gc[i];
+  }
   wave_sync();
   return ok;
 }
@@ -341,25 +345,53 @@ __device__ __forceinline__ void zero_tile(double* X, int t) {
 }
 
 // Blocked upper Cholesky of the symmetric tile G (upper triangle read) with
-// 16 x 16 diagonal factorisations on wave 0 and MFMA block updates. On
-// success G holds R (zeros below) and X holds R^{-1}. False, in every
-// thread, when a pivot is not above lim[j].
+// 16 x 16 diagonal factorisations (and their inverses) on wave 0 and MFMA
+// block updates. On success G holds R (zeros below) and X holds R^{-1}.
+// False, in every thread, when a pivot is not above lim[j].
+//
+// X's off-diagonal blocks follow from X R = I by block rows:
+// X_rj = -(sum_{m=r}^{j-1} X_rm R_mj) X_jj, r < j. Wave r + 1 keeps the
+// running sums P_rj in registers and, while wave 0 factors diagonal block k,
+// finishes X_r,k-1 and adds the terms m = k - 1 (block row k - 1 of R is
+// final by then), so the inverse costs no step of its own.
 __device__ __forceinline__ bool chol64b(double* G, double* X, const double* lim, int* bad,
                         double (*tmp)[16][17], int t) {
-  const int lane = t & 63, w = t >> 6;
+  const int lane = t & 63, w = t >> 6, p = lane & 15, q = lane >> 4;
+  const int r = w - 1;
   zero_tile(X, t);
   if (t == 0) *bad = 0;
   __syncthreads();
-#pragma unroll 1
+  dbl4 pacc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) pacc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  // X_rm = -P_rm X_mm, through the wave's LDS scratch
+  auto finish = [&](int m, const dbl4& pm) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) tmp[w][4 * v + q][p] = pm[v];
+    wave_sync();
+    dbl4 x = {0.0, 0.0, 0.0, 0.0};
+    x = mm16(&tmp[w][0][0], 17, &X[16 * m * kS + 16 * m], kS, x, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) X[(16 * r + 4 * v + q) * kS + 16 * m + p] = -x[v];
+    wave_sync();
+  };
+#pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int o = 16 * k;
     if (w == 0) {
-      const bool ok = chol16w(&G[o * kS + o], &X[o * kS + o], lim + o,
-                              &tmp[0][0][0], lane);
+      const bool ok = chol16x(&G[o * kS + o], &X[o * kS + o], lim + o, lane);
       if (!ok && lane == 0) *bad = 1;
+    } else if (k > 0 && r <= k - 1) {
+      const int m = k - 1;
+      if (r < m) finish(m, pacc[m]);
+#pragma unroll
+      for (int j = m + 1; j < 4; ++j)
+        pacc[j] = mm16(&X[16 * r * kS + 16 * m], kS, &G[16 * m * kS + 16 * j], kS,
+                       pacc[j], lane);
     }
     __syncthreads();
     if (*bad) return false;
+    if (k == 3) break;
     // row block k: R_kj = R_kk^{-T} G_kj
     if (w < 3 - k) {
       const int j = k + 1 + w;
@@ -370,7 +402,9 @@ __device__ __forceinline__ bool chol64b(double* G, double* X, const double* lim,
     __syncthreads();
     // trailing blocks G_ij -= R_ki^T R_kj, k < i <= j
     int idx = 0;
+#pragma unroll
     for (int i = k + 1; i < 4; ++i)
+#pragma unroll
       for (int j = i; j < 4; ++j, ++idx) {
         if ((idx & 3) != w) continue;
         dbl4 acc = ld16(&G[16 * i * kS + 16 * j], lane);
@@ -386,8 +420,8 @@ __device__ __forceinline__ bool chol64b(double* G, double* X, const double* lim,
     const int i = e >> 6, c = e & 63;
     if (i > c) G[i * kS + c] = 0.0;
   }
+  if (w > 0) finish(3, pacc[3]);
   __syncthreads();
-  inv_offdiag(G, X, tmp, t);
   return true;
 }
 
