@@ -60,7 +60,7 @@ KERNEL_SRC = {
     "qr_node": ("qr_node_kernel", "k_qr.hip"),
     "qr_update": ("qr_update_kernel", "k_qr.hip"),
     "score": ("score_mfma_kernel<0>", "k_score.hip"),
-    "countsketch": ("countsketch_dense_kernel<float>", "k_sketch.hip"),
+    "countsketch": ("countsketch_colmax_kernel<float>", "k_sketch.hip"),
     "colmax": ("colmax_dense_kernel<float>", "k_sketch.hip"),
 }
 PMC_SUMMARY = os.path.join(ROOT, "profiles",
@@ -162,8 +162,10 @@ def _roofline(name: str, ms_per_launch: float, launches_per_step: float):
         return {"bound": "hbm", "achieved": a / 1e9, "peak": PEAK["hbm"] / 1e9,
                 "unit": "GB/s", "frac": a / PEAK["hbm"], "traffic": None}
     if name == "countsketch":
-        # X once, the sketch written once, the sorted row list once
-        byts = (N * D * 4 + R * D * 8 + N * 4) / launches_per_step
+        # X once, the sketch written once, the sorted row list once, the
+        # per-workgroup column maxima (min(1024, R / 4) x D floats) once
+        byts = (N * D * 4 + R * D * 8 + N * 4 + min(1024, R // 4) * D * 4) \
+            / launches_per_step
         a = byts / sec
         return {"bound": "hbm", "achieved": a / 1e9, "peak": PEAK["hbm"] / 1e9,
                 "unit": "GB/s", "frac": a / PEAK["hbm"], "traffic": None}

@@ -103,6 +103,23 @@ void launch_countsketch(const void* x, int dtype, int format, int64_t n,
                         const int32_t* offsets, int64_t r,
                         const double* dscale, double* sx, hipStream_t s);
 
+// CountSketch and column equilibration in one pass over dense F32 / BF16 /
+// FP8 input (ld and the base address multiples of 4 elements): sx[b] = cs *
+// sum_{rows in bucket b, ascending} sign * x_row (cs: the FP8 column scales,
+// else 1) WITHOUT the equilibration D, which the consumer applies (qr_factor's
+// dsc), and dscale = D from the column max-abs values (times |cs|), as
+// launch_colmax + launch_colscale would give. parts: countsketch_colmax_groups(r)
+// * d floats of scratch. False, with nothing launched, when the input does
+// not qualify.
+int64_t countsketch_colmax_groups(int64_t r);
+bool countsketch_colmax_ok(const void* x, int dtype, int format, int64_t ld);
+bool launch_countsketch_colmax(const void* x, int dtype, int64_t d, int64_t ld,
+                               const float* col_scale,
+                               const uint32_t* sorted_vals,
+                               const int32_t* offsets, int64_t r, float* parts,
+                               int* nonfinite, double* dscale, double* sx,
+                               hipStream_t s);
+
 // ---- QR (k_qr.hip) -----------------------------------------------------------
 // A second stream and two events that let the QR overlap one panel's
 // trailing update with the next panel's factorisation (side == nullptr:
@@ -119,10 +136,13 @@ size_t qr_scratch_bytes(int64_t m, int64_t d);
 // by the first-pass Q1. *status (device int): 0 done; 2: r_out not yet
 // written, call qr_factor_finish; 1: Cholesky-QR2 does not apply (a too
 // ill-conditioned or rank deficient): a and r_out are unusable, the caller
-// factors the original matrix with qr_factor_panel.
+// factors the original matrix with qr_factor_panel. dsc (nullable): powers
+// of two that scale a's columns as they are read; the factorisation is then
+// that of a diag(dsc), with the same rounding as if a had been scaled first.
 void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
                int* status, const QrStreams& qs, hipStream_t s,
-               bool want_r = true, double* dstat = nullptr);
+               bool want_r = true, double* dstat = nullptr,
+               const double* dsc = nullptr);
 // After status 2: the second pass's blocked Cholesky and R = R2 R1 (status
 // set again, 0 or 1).
 void qr_factor_finish(int64_t m, int64_t d, double* r_out, void* scratch,
@@ -151,7 +171,8 @@ size_t cholqr2_scratch_bytes(int64_t m, int64_t d);
 // (qs is reserved for overlapping parts of the factorisation)
 void cholqr2_factor(double* a, int64_t m, int64_t d, double* r_out,
                     void* scratch, int* status, const QrStreams& qs,
-                    hipStream_t s, bool want_r, double* dstat);
+                    hipStream_t s, bool want_r, double* dstat,
+                    const double* dsc);
 void cholqr2_finish(int64_t m, int64_t d, double* r_out, void* scratch,
                     int* status, hipStream_t s, bool want_r, double* dstat);
 void cholqr2_write_r(int64_t m, int64_t d, double* r_out, void* scratch,

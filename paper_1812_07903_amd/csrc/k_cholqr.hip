@@ -223,7 +223,8 @@ __global__ void __launch_bounds__(256, 2)
 // doubles order like the values, a NaN above every number).
 __global__ void __launch_bounds__(256)
     gram_reduce_kernel(const double* __restrict__ part, int64_t S, int64_t Se,
-                       int64_t nb, int64_t d, double* __restrict__ G,
+                       int64_t nb, int64_t d, const double* __restrict__ dsc,
+                       double* __restrict__ G,
                        double* __restrict__ gdiag, unsigned long long* emax,
                        const int* __restrict__ flag) {
   __shared__ unsigned long long red[4];
@@ -249,6 +250,8 @@ __global__ void __launch_bounds__(256)
     const int64_t blk = nf * (nf + 1) / 2 * S + I2 * Se;
     v = sum_parts(part + blk * kB2 + off, Se, kB2, 0);
   }
+  // (A diag(dsc))^T (A diag(dsc)): exact scaling by powers of two
+  if (dsc && gi < d && gj < d) v *= dsc[gi] * dsc[gj];
   G[tix(I0, J0, nb) + e] = v;
   if (gi == gj) gdiag[gi] = v;
   if (emax) {
@@ -493,6 +496,7 @@ __global__ void __launch_bounds__(kSW)
     stripe_solve_kernel(double* __restrict__ A, int64_t lda, int64_t m,
                         int64_t d, int64_t nb, const double* __restrict__ R,
                         const double* __restrict__ Dinv,
+                        const double* __restrict__ dsc,
                         const int* __restrict__ flag) {
   __shared__ double TA[kTile];
   __shared__ double TB[kTile];
@@ -512,6 +516,7 @@ __global__ void __launch_bounds__(kSW)
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * wr + 4 * v + q, col = 32 * wc + 16 * bj + p;
         acc[bj][v] = (row < nr && col < nc) ? As[row * lda + cJ + col] : 0.0;
+        if (dsc && col < nc) acc[bj][v] *= dsc[cJ + col];
       }
     // blocks I < J are complete (only the last block can be partial)
     Stage8 va, vb;
@@ -809,7 +814,7 @@ Cq2 cq2_carve(void* base, int64_t m, int64_t d) {
 }
 
 void gram_tiles(const double* a, int64_t m, int64_t d, const Cq2& c,
-                bool with_emax, int* flag, hipStream_t s) {
+                bool with_emax, const double* dsc, int* flag, hipStream_t s) {
   unsigned long long* em = with_emax ? c.emax : nullptr;
   // (the thin blocks gain nothing on a second stream: the main blocks hold
   // every slot until their last round ends)
@@ -825,7 +830,7 @@ void gram_tiles(const double* a, int64_t m, int64_t d, const Cq2& c,
   prof_end(kKCq2GramEdge, s);
   prof_begin(kKCq2GramSum, s);
   gram_reduce_kernel<<<static_cast<unsigned>(c.nt * 16), 256, 0, s>>>(
-      c.part, c.S, c.Se, c.nb, d, c.G, c.gdiag, em, flag);
+      c.part, c.S, c.Se, c.nb, d, dsc, c.G, c.gdiag, em, flag);
   prof_end(kKCq2GramSum, s);
 }
 
@@ -877,17 +882,18 @@ void tri_apply(const Cq2& c, const double* T, int64_t d, const double* B,
 
 void cholqr2_factor(double* a, int64_t m, int64_t d, double* r_out,
                     void* scratch, int* status, const QrStreams& qs,
-                    hipStream_t s, bool want_r, double* dstat) {
+                    hipStream_t s, bool want_r, double* dstat,
+                    const double* dsc) {
   (void)qs;
   const Cq2 c = cq2_carve(scratch, m, d);
   launch_fill_i32(status, 1, 0, s);
-  gram_tiles(a, m, d, c, false, status, s);
+  gram_tiles(a, m, d, c, false, dsc, status, s);
   bchol(c, c.R1, want_r ? nullptr : c.X1, status, s);
   prof_begin(kKCq2Solve, s);
   stripe_solve_kernel<<<cdivu(m, kP), kSW, 0, s>>>(a, d, m, d, c.nb, c.R1,
-                                                    c.Dinv, status);
+                                                    c.Dinv, dsc, status);
   prof_end(kKCq2Solve, s);
-  gram_tiles(a, m, d, c, true, status, s);
+  gram_tiles(a, m, d, c, true, nullptr, status, s);
   prof_begin(kKCq2R, s);
   if (want_r)
     r_final_kernel<true><<<static_cast<unsigned>(c.nb * c.nb), 256, 0, s>>>(

@@ -759,9 +759,9 @@ size_t qr_scratch_bytes(int64_t m, int64_t d) {
 }
 void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
                int* status, const QrStreams& qs, hipStream_t s, bool want_r,
-               double* dstat) {
+               double* dstat, const double* dsc) {
   cholqr2_factor(a, m, d, r_out, static_cast<char*>(scratch) + tree_part(m),
-                 status, qs, s, want_r, dstat);
+                 status, qs, s, want_r, dstat, dsc);
 }
 void qr_factor_finish(int64_t m, int64_t d, double* r_out, void* scratch,
                       int* status, hipStream_t s, bool want_r, double* dstat) {

@@ -195,6 +195,174 @@ __global__ void mul_scale_kernel(const double* __restrict__ a,
   if (j < d) out[j] = (a ? a[j] : 1.0) * static_cast<double>(b[j]);
 }
 
+// ---- CountSketch with the column maxima in the same pass ----------------------
+// Dense F32 / BF16 / FP8 input whose rows start on 4-element boundaries. One
+// wave per bucket (waves stride over the buckets); lane l owns columns
+// 4 (l + 64 u) .. + 3, u < 4, of each 1024-column chunk and reads them as one
+// 4-element vector per row, so a row is one pass of coalesced loads. The
+// signed FP64 sums are those of countsketch_dense_kernel, in the same order,
+// times the FP8 column scale; the power-of-two equilibration D is left to the
+// consumer (scaling by a power of two is exact, so the consumer sees the same
+// numbers). Every row is read once, so the column max-abs values come from
+// the same loads: per workgroup into parts[blockIdx][col], reduced by
+// colmax_parts_kernel.
+constexpr int kSkChunk = 1024;
+constexpr int kSkMaxGroups = 1024;
+
+__device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  v[0] = q.x;
+  v[1] = q.y;
+  v[2] = q.z;
+  v[3] = q.w;
+}
+__device__ __forceinline__ void load4(const uint16_t* p, float (&v)[4]) {
+  const uint2 q = *reinterpret_cast<const uint2*>(p);
+  v[0] = bf16_to_f32(static_cast<uint16_t>(q.x & 0xffffu));
+  v[1] = bf16_to_f32(static_cast<uint16_t>(q.x >> 16));
+  v[2] = bf16_to_f32(static_cast<uint16_t>(q.y & 0xffffu));
+  v[3] = bf16_to_f32(static_cast<uint16_t>(q.y >> 16));
+}
+__device__ __forceinline__ void load4(const uint8_t* p, float (&v)[4]) {
+  const uint32_t q = *reinterpret_cast<const uint32_t*>(p);
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    v[e] = e4m3_to_f32(static_cast<uint8_t>((q >> (8 * e)) & 0xffu));
+}
+__device__ __forceinline__ float elem_f(const float* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float elem_f(const uint16_t* p, int64_t i) {
+  return bf16_to_f32(p[i]);
+}
+__device__ __forceinline__ float elem_f(const uint8_t* p, int64_t i) {
+  return e4m3_to_f32(p[i]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    countsketch_colmax_kernel(const T* __restrict__ x, int64_t d, int64_t ld,
+                              const float* __restrict__ col_scale,
+                              const uint32_t* __restrict__ sorted_vals,
+                              const int32_t* __restrict__ off, int64_t r,
+                              float* __restrict__ parts, int* nonfinite,
+                              double* __restrict__ sx) {
+  constexpr bool kFp8 = sizeof(T) == 1;  // codes times the column scale
+  __shared__ float wmax[4][kSkChunk];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * 4;
+  bool bad = false;
+  for (int64_t c0 = 0; c0 < d; c0 += kSkChunk) {
+    float cm[16];
+    double cs[16];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t c = c0 + 4 * (lane + 64 * u) + e;
+        cm[4 * u + e] = 0.0f;
+        cs[4 * u + e] = (kFp8 && c < d) ? static_cast<double>(col_scale[c]) : 1.0;
+      }
+    for (int64_t b = static_cast<int64_t>(blockIdx.x) * 4 + wv; b < r; b += nwaves) {
+      const int p0 = off[b], p1 = off[b + 1];
+      double acc[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+      for (int p = p0; p < p1; ++p) {
+        const uint32_t v = sorted_vals[p];
+        const int64_t row = static_cast<int64_t>(v & 0x7fffffffu);
+        const bool neg = (v >> 31) != 0;
+        const T* xr = x + row * ld;
+        float xv[16];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t c = c0 + 4 * (lane + 64 * u);
+          float q[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+          if (c + 4 <= d) {
+            load4(xr + c, q);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (c + e < d) q[e] = elem_f(xr, c + e);
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) xv[4 * u + e] = q[e];
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const float a = fabsf(xv[e]);
+          bad |= !(a <= 3.402823466e38f);
+          cm[e] = fmaxf(cm[e], a);
+          const double xd = static_cast<double>(xv[e]);
+          acc[e] += neg ? -xd : xd;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t c = c0 + 4 * (lane + 64 * u) + e;
+          if (c < d)
+            sx[b * d + c] = kFp8 ? acc[4 * u + e] * cs[4 * u + e] : acc[4 * u + e];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) wmax[wv][4 * (lane + 64 * u) + e] = cm[4 * u + e];
+    __syncthreads();
+    for (int j = threadIdx.x; j < kSkChunk; j += 256) {
+      const float m = fmaxf(fmaxf(wmax[0][j], wmax[1][j]), fmaxf(wmax[2][j], wmax[3][j]));
+      if (c0 + j < d) parts[static_cast<int64_t>(blockIdx.x) * d + c0 + j] = m;
+    }
+    __syncthreads();
+  }
+  if (bad) atomicExch(nonfinite, 1);
+}
+
+// dscale[col] = D_col from the largest of the groups' maxima (times |cs|, the
+// FP8 column scale), as colscale_kernel. Four columns per workgroup, 64
+// threads per column.
+__global__ void __launch_bounds__(256)
+    colmax_parts_kernel(const float* __restrict__ parts, int64_t groups,
+                        int64_t d, const float* __restrict__ col_scale,
+                        int* nonfinite, double* __restrict__ dscale) {
+  __shared__ float red[4][4];
+  const int t = threadIdx.x, cl = t & 3, g = t >> 2, lane = t & 63, wv = t >> 6;
+  const int64_t col = static_cast<int64_t>(blockIdx.x) * 4 + cl;
+  float m = 0.0f;
+  if (col < d) {
+    for (int64_t j0 = 0; j0 < groups; j0 += 64 * 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t j = j0 + g + 64 * u;
+        v[u] = j < groups ? parts[j * d + col] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) m = fmaxf(m, v[u]);
+    }
+  }
+#pragma unroll
+  for (int o = 4; o < 64; o <<= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if (lane < 4) red[wv][lane] = m;
+  __syncthreads();
+  if (t < 4) {
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 4 + t;
+    if (c < d) {
+      const float mx = fmaxf(fmaxf(red[0][t], red[1][t]), fmaxf(red[2][t], red[3][t]));
+      const double mm = static_cast<double>(mx) *
+                        (col_scale ? fabs(static_cast<double>(col_scale[c])) : 1.0);
+      if (!isfinite(mm)) atomicExch(nonfinite, 1);
+      double sc = 1.0;
+      if (mm > 0.0 && isfinite(mm)) {
+        int e;
+        frexp(mm, &e);
+        sc = ldexp(1.0, -(e - 1));
+      }
+      dscale[c] = sc;
+    }
+  }
+}
+
 inline unsigned grid1(int64_t n, int t) {
   return static_cast<unsigned>((n + t - 1) / t);
 }
@@ -320,6 +488,45 @@ void launch_countsketch(const void* x, int dtype, int format, int64_t n,
     default:
       break;
   }
+}
+
+int64_t countsketch_colmax_groups(int64_t r) {
+  const int64_t g = (r + 3) / 4;
+  return g < 1 ? 1 : (g < kSkMaxGroups ? g : kSkMaxGroups);
+}
+
+bool countsketch_colmax_ok(const void* x, int dtype, int format, int64_t ld) {
+  const int esz = dtype == 1 ? 4 : (dtype == 2 ? 2 : (dtype == 3 ? 1 : 0));
+  return format == 0 && esz != 0 && ld % 4 == 0 &&
+         reinterpret_cast<uintptr_t>(x) % (4 * esz) == 0;
+}
+
+bool launch_countsketch_colmax(const void* x, int dtype, int64_t d, int64_t ld,
+                               const float* col_scale,
+                               const uint32_t* sorted_vals,
+                               const int32_t* offsets, int64_t r, float* parts,
+                               int* nonfinite, double* dscale, double* sx,
+                               hipStream_t s) {
+  if (!countsketch_colmax_ok(x, dtype, 0, ld) || d <= 0 || r <= 0) return false;
+  const int64_t groups = countsketch_colmax_groups(r);
+  const unsigned g = static_cast<unsigned>(groups);
+  prof_begin(kKSketch, s);
+  if (dtype == 1)
+    countsketch_colmax_kernel<float><<<g, 256, 0, s>>>(
+        static_cast<const float*>(x), d, ld, nullptr, sorted_vals, offsets, r,
+        parts, nonfinite, sx);
+  else if (dtype == 2)
+    countsketch_colmax_kernel<uint16_t><<<g, 256, 0, s>>>(
+        static_cast<const uint16_t*>(x), d, ld, nullptr, sorted_vals, offsets,
+        r, parts, nonfinite, sx);
+  else
+    countsketch_colmax_kernel<uint8_t><<<g, 256, 0, s>>>(
+        static_cast<const uint8_t*>(x), d, ld, col_scale, sorted_vals, offsets,
+        r, parts, nonfinite, sx);
+  prof_end(kKSketch, s);
+  colmax_parts_kernel<<<grid1(d, 4), 256, 0, s>>>(
+      parts, groups, d, dtype == 3 ? col_scale : nullptr, nonfinite, dscale);
+  return true;
 }
 
 }  // namespace slso

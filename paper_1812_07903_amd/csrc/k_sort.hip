@@ -3,11 +3,15 @@
 // row within a bucket: the streaming order of Sec. 3.1.2) and the "dec"
 // ordering of Sec. 5.2 (scores decreasing, ties by ascending row).
 //
-// Radix sort: 8-bit digits, tiles of 4096 keys per 256-thread workgroup.
-// Per pass: (1) per-tile digit histogram in LDS, (2) one exclusive scan of
-// the digit-major histogram table, (3) a stable scatter in which each wave
-// ranks equal digits with eight ballots and the waves of a tile are ordered
-// through LDS prefix counts, so equal keys keep their input order.
+// Radix sort: 8-bit digits, tiles of 256 kItems keys per 256-thread
+// workgroup. Per pass: (1) per-tile digit histogram in LDS, (2) one exclusive
+// scan of the digit-major histogram table, (3) a stable scatter in which each
+// wave ranks equal digits with eight ballots and the waves of a tile are
+// ordered through LDS prefix counts, so equal keys keep their input order.
+// Up to kFusedTiles tiles, step (2) is folded into (3): the histogram is
+// stored tile-major and each scatter workgroup sums the few columns it needs
+// (its tile's predecessors and the digit totals), which saves a launch and a
+// single-workgroup pass per digit.
 #include "internal.h"
 
 namespace slso {
@@ -19,6 +23,7 @@ constexpr int kThreads = 256;
 constexpr int kItemsLarge = 16;
 constexpr int kItemsSmall = 4;
 constexpr int64_t kSmallSort = int64_t{1} << 20;
+constexpr int kFusedTiles = 128;
 
 __global__ void hash_pack_kernel(HashCoeffs hb, HashCoeffs hs, uint64_t r,
                                  int64_t row0, int64_t n, uint32_t* keys,
@@ -63,7 +68,8 @@ __global__ void score_keys_kernel(const float* s, int64_t n, uint32_t* keys) {
   keys[i] = ~asc;  // ascending key order = descending score order
 }
 
-template <int kItems>
+// tile-major (hist[tile][digit]) when kFused, else digit-major
+template <int kItems, bool kFused>
 __global__ void __launch_bounds__(kThreads)
     rs_hist_kernel(const uint32_t* __restrict__ keys, int64_t n, int shift,
                    uint32_t* __restrict__ hist, int nblocks) {
@@ -79,7 +85,10 @@ __global__ void __launch_bounds__(kThreads)
     if (p < n) atomicAdd(&h[(keys[p] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  hist[static_cast<int64_t>(tid) * nblocks + blockIdx.x] = h[tid];
+  if (kFused)
+    hist[static_cast<int64_t>(blockIdx.x) * 256 + tid] = h[tid];
+  else
+    hist[static_cast<int64_t>(tid) * nblocks + blockIdx.x] = h[tid];
 }
 
 // Exclusive scan of len entries in place, one workgroup of 1024 threads:
@@ -121,7 +130,7 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
-template <int kItems>
+template <int kItems, bool kFused>
 __global__ void __launch_bounds__(kThreads)
     rs_scatter_kernel(const uint32_t* __restrict__ keys_in,
                       const uint32_t* __restrict__ vals_in,
@@ -135,7 +144,37 @@ __global__ void __launch_bounds__(kThreads)
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  run[tid] = hist[static_cast<int64_t>(tid) * nblocks + blockIdx.x];
+  if (kFused) {
+    // start of digit tid in this tile's output: keys of smaller digits in
+    // all tiles, plus keys of digit tid in the tiles before this one
+    __shared__ uint32_t wsum[4];
+    uint32_t tot = 0, before = 0;
+    for (int b0 = 0; b0 < nblocks; b0 += 8) {
+      uint32_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = b0 + u < nblocks ? hist[static_cast<int64_t>(b0 + u) * 256 + tid] : 0u;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        tot += v[u];
+        before += b0 + u < static_cast<int>(blockIdx.x) ? v[u] : 0u;
+      }
+    }
+    uint32_t inc = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t off = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) off += w < wave ? wsum[w] : 0u;
+    run[tid] = off + inc - tot + before;
+  } else {
+    run[tid] = hist[static_cast<int64_t>(tid) * nblocks + blockIdx.x];
+  }
 #pragma unroll
   for (int w = 0; w < 4; ++w) wcount[w][tid] = 0;
   __syncthreads();
@@ -259,25 +298,36 @@ void radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in,
     uint32_t* kdst = to_out ? keys_out : keys_tmp;
     uint32_t* vdst = to_out ? vals_out : vals_tmp;
     const int shift = 8 * p;
-    prof_begin(kKSortHist, s);
-    if (items == kItemsSmall)
-      rs_hist_kernel<kItemsSmall><<<nblocks, kThreads, 0, s>>>(ksrc, n, shift,
-                                                               hist, nblocks);
-    else
-      rs_hist_kernel<kItemsLarge><<<nblocks, kThreads, 0, s>>>(ksrc, n, shift,
-                                                               hist, nblocks);
-    prof_end(kKSortHist, s);
-    prof_begin(kKSortScan, s);
-    rs_scan_kernel<<<1, 1024, 0, s>>>(hist, static_cast<int64_t>(256) * nblocks);
-    prof_end(kKSortScan, s);
-    prof_begin(kKSortScatter, s);
-    if (items == kItemsSmall)
-      rs_scatter_kernel<kItemsSmall><<<nblocks, kThreads, 0, s>>>(
+    if (nblocks <= kFusedTiles && items == kItemsSmall) {
+      prof_begin(kKSortHist, s);
+      rs_hist_kernel<kItemsSmall, true><<<nblocks, kThreads, 0, s>>>(
+          ksrc, n, shift, hist, nblocks);
+      prof_end(kKSortHist, s);
+      prof_begin(kKSortScatter, s);
+      rs_scatter_kernel<kItemsSmall, true><<<nblocks, kThreads, 0, s>>>(
           ksrc, vsrc, kdst, vdst, n, shift, hist, nblocks);
-    else
-      rs_scatter_kernel<kItemsLarge><<<nblocks, kThreads, 0, s>>>(
-          ksrc, vsrc, kdst, vdst, n, shift, hist, nblocks);
-    prof_end(kKSortScatter, s);
+      prof_end(kKSortScatter, s);
+    } else {
+      prof_begin(kKSortHist, s);
+      if (items == kItemsSmall)
+        rs_hist_kernel<kItemsSmall, false><<<nblocks, kThreads, 0, s>>>(
+            ksrc, n, shift, hist, nblocks);
+      else
+        rs_hist_kernel<kItemsLarge, false><<<nblocks, kThreads, 0, s>>>(
+            ksrc, n, shift, hist, nblocks);
+      prof_end(kKSortHist, s);
+      prof_begin(kKSortScan, s);
+      rs_scan_kernel<<<1, 1024, 0, s>>>(hist, static_cast<int64_t>(256) * nblocks);
+      prof_end(kKSortScan, s);
+      prof_begin(kKSortScatter, s);
+      if (items == kItemsSmall)
+        rs_scatter_kernel<kItemsSmall, false><<<nblocks, kThreads, 0, s>>>(
+            ksrc, vsrc, kdst, vdst, n, shift, hist, nblocks);
+      else
+        rs_scatter_kernel<kItemsLarge, false><<<nblocks, kThreads, 0, s>>>(
+            ksrc, vsrc, kdst, vdst, n, shift, hist, nblocks);
+      prof_end(kKSortScatter, s);
+    }
     ksrc = kdst;
     vsrc = vdst;
   }

@@ -298,7 +298,10 @@ size_t leverage_ws_bytes(const slso_matrix* X, int64_t r, int64_t k,
   const int64_t n = X->n, d = X->d;
   const int64_t kk = k == 0 ? d : k;
   Sizer z;
-  if (!gauss) size_sketch_bufs(z, n, r);
+  if (!gauss) {
+    size_sketch_bufs(z, n, r);
+    z.take<float>(countsketch_colmax_groups(r) * d);  // column maxima parts
+  }
   z.take<uint64_t>(d);             // colmax bits
   z.take<double>(d);               // dscale D
   z.take<double>(d);               // D * col_scale (FP8)
@@ -611,7 +614,11 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   WsMark mark_{c, s};
   Arena a{static_cast<char*>(c->ws)};
   SketchBufs sb{};
-  if (!gauss) sb = take_sketch_bufs(a, n, r);
+  float* cparts = nullptr;
+  if (!gauss) {
+    sb = take_sketch_bufs(a, n, r);
+    cparts = a.take<float>(countsketch_colmax_groups(r) * d);
+  }
   uint64_t* colmax = a.take<uint64_t>(d);
   double* dscale = a.take<double>(d);
   double* eff = a.take<double>(d);
@@ -633,9 +640,14 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   double* part = a.take<double>(scores_partial_bytes(n, d, kk, X->format, X->dtype) / 8);
   double* tws = a.take<double>(trsm_blocked_scratch(d, refine ? d : kk) / 8);
 
-  // 0. the bucket partition needs no input values: it runs on the context's
-  // second stream while the column maxima are taken
-  const bool side_partition = !gauss && c->qs.side;
+  // Dense F32 / BF16 / FP8 input: the column maxima are taken in the
+  // CountSketch's own pass over X, and D is applied by the QR as it reads the
+  // sketch (exact: powers of two). Otherwise a pass of its own comes first.
+  const bool fuse = !gauss && countsketch_colmax_ok(X->values, X->dtype,
+                                                    X->format, X->ld);
+  // 0. the bucket partition needs no input values: without the fused pass it
+  // runs on the context's second stream while the column maxima are taken
+  const bool side_partition = !gauss && !fuse && c->qs.side;
   if (side_partition) {
     SLSO_HIP(c, hipEventRecord(c->qs.factored, s));
     SLSO_HIP(c, hipStreamWaitEvent(c->qs.side, c->qs.factored, 0));
@@ -643,35 +655,47 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
     SLSO_HIP(c, hipEventRecord(c->qs.bulk_done, c->qs.side));
   }
   // 1. column equilibration D (power of two) from column max-abs of X
-  launch_fill_u64(colmax, d, 0, s);
   launch_fill_i32(flags, 64, 0, s);
-  launch_colmax(X->values, X->dtype, X->format, n, d, X->ld, X->row_ptr,
-                X->col_idx, X->nnz, X->col_scale, X->row_scale, colmax, flags, s);
-  launch_colscale(colmax, d, dscale, s);
-  // per-column factor applied to stored values: D, times the FP8 scales
-  const double* rowfac = dscale;
-  if (fp8) {
-    launch_mul_scale(dscale, X->col_scale, d, eff, s);
-    rowfac = eff;
+  if (!fuse) {
+    launch_fill_u64(colmax, d, 0, s);
+    launch_colmax(X->values, X->dtype, X->format, n, d, X->ld, X->row_ptr,
+                  X->col_idx, X->nnz, X->col_scale, X->row_scale, colmax, flags,
+                  s);
+    launch_colscale(colmax, d, dscale, s);
+    if (fp8) launch_mul_scale(dscale, X->col_scale, d, eff, s);
   }
+  // per-column factor applied to stored values: D, times the FP8 scales
+  const double* rowfac = fp8 ? eff : dscale;
   // 2. sketch of X D (Algorithm 2 step 1), 3. Householder QR of the sketch
   // (Algorithm 2 step 2, QR form), 3b. refinement: G = (X D)^T (X D);
   // G' = R_S^-T G R_S^-1 = R1^T R1; R = R1 R_S is the R factor of X D.
   // The QR's 64-column panels use Cholesky-QR2; when one is too ill-
   // conditioned for it (flags[2]), the sketch is formed again and factored
-  // column by column.
-  bool partitioned = false;
+  // column by column. unscaled: sx holds S X without D (the fused pass).
+  bool partitioned = false, fused_done = false, unscaled = false;
   auto sketch = [&]() {
+    unscaled = false;
     if (gauss) {
       launch_gauss_sketch(X->values, X->dtype, n, d, X->ld, X->col_scale, seed,
                           r, dscale, static_cast<float*>(gpart), sx, s);
-    } else if (side_partition) {
-      if (!partitioned)
+      return;
+    }
+    if (!partitioned) {
+      if (side_partition)
         (void)hipStreamWaitEvent(s, c->qs.bulk_done, 0);
+      else
+        enqueue_partition(n, seed, r, sb, s);
       partitioned = true;
-      enqueue_gather(X, r, sb, rowfac, sx, s);
+    }
+    if (fuse && !fused_done) {
+      (void)launch_countsketch_colmax(X->values, X->dtype, d, X->ld,
+                                      X->col_scale, sb.vals_s, sb.off, r,
+                                      cparts, flags, dscale, sx, s);
+      if (fp8) launch_mul_scale(dscale, X->col_scale, d, eff, s);
+      fused_done = true;
+      unscaled = true;
     } else {
-      enqueue_countsketch(X, seed, r, sb, rowfac, sx, s);
+      enqueue_gather(X, r, sb, rowfac, sx, s);
     }
   };
   // post(r_formed): rank-screen statistics of the R just formed (when
@@ -715,7 +739,8 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   bool cholqr2 = true, second = false, r_formed = want_r;
   int32_t info_flags = 0;
   sketch();
-  qr_factor(sx, r, d, RS, qws, flags + 2, c->qs, s, want_r, dstat);
+  qr_factor(sx, r, d, RS, qws, flags + 2, c->qs, s, want_r, dstat,
+            unscaled ? dscale : nullptr);
   post(want_r);
   if ((st = readback())) return st;
   if (fl[0]) return set_err(c, SLSO_ENONFINITE, "X holds Inf or NaN");

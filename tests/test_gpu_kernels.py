@@ -72,7 +72,7 @@ def test_gaussian_stream_matches(slso, stream_id):
 
 
 # ---- ordering ----------------------------------------------------------------
-@pytest.mark.parametrize("n", [1, 2, 4095, 4096, 4097, 100003])
+@pytest.mark.parametrize("n", [1, 2, 4095, 4096, 4097, 100003, 300001, 1100003])
 def test_order_is_stable_descending(slso, ctx, n):
     rng = np.random.default_rng(n)
     s = rng.integers(0, 50, n).astype(np.float32) * np.float32(0.125)

@@ -142,6 +142,16 @@ def test_nonfinite_input_rejected(slso, ctx):
     assert ei.value.status == slso.ENONFINITE
 
 
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_nonfinite_fp32_rejected(slso, ctx, bad):
+    """FP32 input: the column maxima come from the CountSketch's own pass."""
+    x = synth.image_like(500, 64, seed=2)
+    x[17, 3] = bad
+    with pytest.raises(slso.SlsoError) as ei:
+        ctx.leverage(dev(x), 1, 128, 4)
+    assert ei.value.status == slso.ENONFINITE
+
+
 def test_invalid_sizes_rejected(slso, ctx):
     x = synth.config0(n=500, d=8, seed=1)
     with pytest.raises(slso.SlsoError) as ei:
