@@ -51,7 +51,7 @@ def qr_node_flops(m: int, d: int, w: int = 16) -> float:
 
 # profiler name -> (kernel symbol in the PMC summary, source file)
 KERNEL_SRC = {
-    "cq2_gram": ("gram_block_kernel<false>", "k_cholqr.hip"),
+    "cq2_gram": ("gram_block_kernel<false, true>", "k_cholqr.hip"),
     "cq2_solve": ("stripe_solve_kernel", "k_cholqr.hip"),
     "cq_update": ("cq_update_kernel", "k_cqr.hip"),
     "cq_z": ("cq_z_kernel", "k_cqr.hip"),
@@ -108,9 +108,11 @@ def _fp64(flops_per_launch: float, sec: float):
 def _roofline(name: str, ms_per_launch: float, launches_per_step: float):
     sec = ms_per_launch * 1e-3
     if name == "cq2_gram":
-        # the part of the upper triangle of A^T A inside full 128-column
-        # blocks: c (c + 1) / 2 entries (c = 128 floor(d / 128)), m products
-        c = 128 * (D // 128)
+        # the upper triangle of A^T A: d (d + 1) / 2 entries of m products
+        # each when the last column block is at most 16 wide (its products
+        # are formed by the same launch), else the part inside full
+        # 128-column blocks (c = 128 floor(d / 128))
+        c = D if D % 128 <= 16 else 128 * (D // 128)
         return _fp64(float(R) * c * (c + 1), sec)
     if name == "cq2_gram_edge":
         # the rest of the upper triangle (columns past c), plus the sum of

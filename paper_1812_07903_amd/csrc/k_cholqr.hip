@@ -112,12 +112,17 @@ __device__ __forceinline__ void tile_to_global(double* g, const double* T,
 // columns inside the matrix): full block t, chunk s at
 // part[(t S + s) 16384], edge block e, chunk s after all of those at
 // [(nfull S + e S_e + s) 16384].
+// FE (a last column block of at most 16 columns): no second launch. On a
+// diagonal block the lower-left 64 x 64 quadrant is the transpose of the
+// upper-right one, so waves 2 and 3 skip it and form the edge products
+// A_I2^T A_e instead (8 + 4 MFMA blocks against the 16 of waves 0 and 1),
+// and wave 2 of block (0, 0) also the corner A_e^T A_e; S_e = S.
 constexpr int kGK = 16;    // rows per step
 constexpr int kGS = 144;   // LDS row stride: rows 4 apart fall on the other
                            // half of the banks
 constexpr int64_t kB2 = 128 * 128;
 
-template <bool EDGE>
+template <bool EDGE, bool FE>
 __global__ void __launch_bounds__(256, 2)
     gram_block_kernel(const double* __restrict__ A, int64_t lda, int64_t m,
                       int64_t d, int64_t S, int64_t chunk, int64_t part0,
@@ -136,6 +141,12 @@ __global__ void __launch_bounds__(256, 2)
     upper_tile(tt, nf, I2, J2);
   }
   const bool diag = I2 == J2;
+  // FE: edge products on this diagonal block (waves 2, 3), the corner on (0, 0)
+  const bool fe = FE && diag;
+  const bool fw = fe && w >= 2;
+  const bool corner = fe && I2 == 0 && w == 2;
+  const int64_t cE = nf * 128, nE = d - cE;
+  const int er = t >> 4, ec = t & 15;  // this thread's element of the edge rows
   const int64_t cA = I2 * 128, cB = J2 * 128;
   const int64_t nA = d - cA < 128 ? d - cA : 128;
   const int64_t nB = d - cB < 128 ? d - cB : 128;
@@ -165,6 +176,10 @@ __global__ void __launch_bounds__(256, 2)
         v[8 + u] = A[okb ? row * lda + cB + c : 0];
       }
     }
+    if (fe) {
+      const int64_t row = r + er;
+      v[8] = A[(row < r1 && ec < nE) ? row * lda + cE + ec : 0];
+    }
   };
   auto lstore = [&](int buf, int64_t r) {
 #pragma unroll
@@ -174,6 +189,8 @@ __global__ void __launch_bounds__(256, 2)
       if (!diag)
         X[buf][1][(rr + 2 * u) * kGS + c] = (row < r1 && c < nB) ? v[8 + u] : 0.0;
     }
+    if (fe)
+      X[buf][1][er * kGS + ec] = (r + er < r1 && ec < nE) ? v[8] : 0.0;
   };
   if (r0 < r1) {
     gload(r0);
@@ -185,20 +202,46 @@ __global__ void __launch_bounds__(256, 2)
       if (more) gload(r + kGK);
       const double* XA = X[buf][0];
       const double* XB = diag ? X[buf][0] : X[buf][1];
+      if (!fw) {
 #pragma unroll
-      for (int kk = 0; kk < kGK / 4; ++kk) {
-        const int k = 4 * kk + q;
-        double a[2], b[8];
+        for (int kk = 0; kk < kGK / 4; ++kk) {
+          const int k = 4 * kk + q;
+          double a[2], b[8];
 #pragma unroll
-        for (int x = 0; x < 2; ++x) a[x] = XA[k * kGS + 32 * w + 16 * x + p];
+          for (int x = 0; x < 2; ++x) a[x] = XA[k * kGS + 32 * w + 16 * x + p];
 #pragma unroll
-        for (int y = 0; y < 8; ++y) b[y] = XB[k * kGS + 16 * y + p];
+          for (int y = 0; y < 8; ++y) b[y] = XB[k * kGS + 16 * y + p];
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+          for (int x = 0; x < 2; ++x)
 #pragma unroll
-          for (int y = 0; y < 8; ++y)
-            if (!EDGE || (x < nrow && y < ncol))
-              acc[x][y] = mfma(a[x], b[y], acc[x][y]);
+            for (int y = 0; y < 8; ++y)
+              if (!EDGE || (x < nrow && y < ncol))
+                acc[x][y] = mfma(a[x], b[y], acc[x][y]);
+        }
+      } else if (FE) {
+        // acc[x][y], y >= 4: the upper-right quadrant as above; acc[0][y],
+        // y < 4: edge block rows 64 (w - 2) + 16 y ..; acc[1][0]: corner
+        const double* XE = X[buf][1];
+#pragma unroll
+        for (int kk = 0; kk < kGK / 4; ++kk) {
+          const int k = 4 * kk + q;
+          double a[2], b[4], ea[4];
+#pragma unroll
+          for (int x = 0; x < 2; ++x) a[x] = XA[k * kGS + 32 * w + 16 * x + p];
+#pragma unroll
+          for (int y = 0; y < 4; ++y) {
+            b[y] = XA[k * kGS + 64 + 16 * y + p];
+            ea[y] = XA[k * kGS + 64 * (w - 2) + 16 * y + p];
+          }
+          const double eb = XE[k * kGS + p];
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][4 + y] = mfma(a[x], b[y], acc[x][4 + y]);
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[0][y] = mfma(ea[y], eb, acc[0][y]);
+          if (corner) acc[1][0] = mfma(eb, eb, acc[1][0]);
+        }
       }
       if (more) lstore(buf ^ 1, r + kGK);
       __syncthreads();
@@ -210,11 +253,25 @@ __global__ void __launch_bounds__(256, 2)
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 8; ++y)
-      if (!EDGE || y < ncol) {
+      if ((!EDGE || y < ncol) && !(fw && y < 4)) {
 #pragma unroll
         for (int vv = 0; vv < 4; ++vv)
           out[(32 * w + 16 * x + 4 * vv + q) * 128 + 16 * y + p] = acc[x][y][vv];
       }
+  if (FE && fw) {
+    const int64_t nfull = nf * (nf + 1) / 2;
+    double* oe = part + ((nfull + I2) * S + s) * kB2;
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv)
+        oe[(64 * (w - 2) + 16 * y + 4 * vv + q) * 128 + p] = acc[0][y][vv];
+    if (corner) {
+      double* oc = part + ((nfull + nf) * S + s) * kB2;
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) oc[(4 * vv + q) * 128 + p] = acc[1][0][vv];
+    }
+  }
 }
 
 // G tile = sum of its partial blocks (fixed order); the padding is the
@@ -768,6 +825,7 @@ __global__ void __launch_bounds__(256)
 
 struct Cq2 {
   int64_t nb, nt, S, chunk, Se, chunk_e, nfull, nedge;
+  bool fe;  // edge products formed by the diagonal blocks (no edge launch)
   double *part, *G, *R1, *R2, *X1, *X2, *P, *Dinv, *gdiag, *apart;
   unsigned long long* emax;
 };
@@ -793,6 +851,11 @@ Cq2 cq2_shape(int64_t m, int64_t d) {
   };
   pick(512, c.nfull, c.S, c.chunk);
   pick(512, c.nedge, c.Se, c.chunk_e);
+  c.fe = nf > 0 && d % 128 != 0 && d % 128 <= 16;
+  if (c.fe) {
+    c.Se = c.S;
+    c.chunk_e = c.chunk;
+  }
   return c;
 }
 
@@ -819,13 +882,16 @@ void gram_tiles(const double* a, int64_t m, int64_t d, const Cq2& c,
   // (the thin blocks gain nothing on a second stream: the main blocks hold
   // every slot until their last round ends)
   prof_begin(kKCq2Gram, s);
-  if (c.nfull > 0)
-    gram_block_kernel<false><<<static_cast<unsigned>(c.nfull * c.S), 256, 0, s>>>(
+  if (c.fe)
+    gram_block_kernel<false, true><<<static_cast<unsigned>(c.nfull * c.S), 256, 0, s>>>(
+        a, d, m, d, c.S, c.chunk, 0, c.part, flag);
+  else if (c.nfull > 0)
+    gram_block_kernel<false, false><<<static_cast<unsigned>(c.nfull * c.S), 256, 0, s>>>(
         a, d, m, d, c.S, c.chunk, 0, c.part, flag);
   prof_end(kKCq2Gram, s);
   prof_begin(kKCq2GramEdge, s);
-  if (c.nedge > 0)
-    gram_block_kernel<true><<<static_cast<unsigned>(c.nedge * c.Se), 256, 0, s>>>(
+  if (c.nedge > 0 && !c.fe)
+    gram_block_kernel<true, false><<<static_cast<unsigned>(c.nedge * c.Se), 256, 0, s>>>(
         a, d, m, d, c.Se, c.chunk_e, c.nfull * c.S, c.part, flag);
   prof_end(kKCq2GramEdge, s);
   prof_begin(kKCq2GramSum, s);

@@ -129,10 +129,12 @@ def test_countsketch_csr_bit_exact(slso, ctx, n, d, r):
 @pytest.mark.parametrize("m,d", [(64, 64), (100, 37), (256, 32), (257, 33),
                                  (1000, 96), (3000, 200), (5000, 64),
                                  (70000, 40), (2048, 512), (16384, 784),
-                                 (4099, 833)])
+                                 (4099, 833), (1000, 140), (700, 257),
+                                 (5000, 400)])
 def test_qr_r_matches_householder(slso, ctx, m, d):
     """Cholesky-QR2 over the whole matrix (ragged row chunks and stripes,
-    d below, at and past a multiple of 64)."""
+    d below, at and past a multiple of 64; a last 128-column block of 1 to 16
+    columns, whose Gram products the diagonal blocks form, or of more)."""
     rng = np.random.default_rng(m * 7 + d)
     a = rng.standard_normal((m, d)) * np.exp(rng.standard_normal(d))[None, :]
     r, used = ctx.qr_r_path(dev(a.copy()))
