@@ -566,15 +566,28 @@ __global__ void __launch_bounds__(kSW)
   for (int64_t J = 0; J < nb; ++J) {
     const int64_t cJ = J * kP;
     const int64_t nc = d - cJ < kP ? d - cJ : kP;
+    // A_J (times dsc) without branches: an entry outside the matrix reads a
+    // clamped address and is replaced by zero, so the loads stay in flight
+    // together
     dbl4 acc[2];
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * wr + 4 * v + q, col = 32 * wc + 16 * bj + p;
-        acc[bj][v] = (row < nr && col < nc) ? As[row * lda + cJ + col] : 0.0;
-        if (dsc && col < nc) acc[bj][v] *= dsc[cJ + col];
+        const bool ok = row < nr && col < nc;
+        const double av = As[ok ? row * lda + cJ + col : 0];
+        acc[bj][v] = ok ? av : 0.0;
       }
+    if (dsc) {
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const int col = 32 * wc + 16 * bj + p;
+        const double sc = dsc[col < nc ? cJ + col : 0];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[bj][v] *= sc;
+      }
+    }
     // blocks I < J are complete (only the last block can be partial)
     Stage8 va, vb;
     if (J > 0) {

@@ -158,7 +158,9 @@ __global__ void __launch_bounds__(256)
 // A workgroup of four waves scores 128 rows; wave w owns rows 32w .. 32w + 31
 // and all 64 columns of M (two 32 x 32 accumulator tiles). The contraction
 // over d runs in chunks of 32: X (128 x 32) and M (32 x 64) are staged in
-// LDS, double-buffered, the chunk's products summed on MFMA in FP32 and added
+// LDS, double-buffered (FP32 input: loaded into registers two chunks ahead,
+// so a load has two chunks' products to arrive in), the chunk's products
+// summed on MFMA in FP32 and added
 // to FP64 accumulators, so the error is that of 32-term FP32 sums.
 //   FP32 input: v_mfma_f32_32x32x2f32 on FP32 X and FP32 M.
 //   BF16 / FP8 input: v_mfma_f32_32x32x16_bf16 on X (exact in BF16) and three
@@ -237,12 +239,16 @@ __global__ void __launch_bounds__(256)
     }
 
   // staging registers: X 16 elements per thread (row t/8 + 32 p, columns
-  // 4 (t%8) .. +3), M 8 elements per thread
+  // 4 (t%8) .. +3), M 8 elements per thread. Two sets: chunk c + 2 is loaded
+  // while chunk c is multiplied, so each load has two chunks' products to
+  // arrive in.
   using XT = typename XIn<IT>::T;
-  XT xr[16];
-  float mr[8];
-  uint16_t mhr[8], mmr[8], mlr[8];
-  auto load_chunk = [&](int ch) {
+  struct SStage {
+    XT xr[16];
+    float mr[8];
+    uint16_t mhr[8], mmr[8], mlr[8];
+  };
+  auto load_chunk = [&](int ch, SStage& st) {
     const int64_t c0 = static_cast<int64_t>(ch) * kMC;
 #pragma unroll
     for (int pp = 0; pp < 4; ++pp) {
@@ -250,8 +256,11 @@ __global__ void __launch_bounds__(256)
       const int64_t gr = row0 + r;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
+        // branch-free: an entry outside reads x[0] and becomes zero
         const int64_t gc = c0 + 4 * (t % 8) + u;
-        xr[4 * pp + u] = (gr < n && gc < d) ? x[gr * ld + gc] : XT(0);
+        const bool ok = gr < n && gc < d;
+        const XT xv = x[ok ? gr * ld + gc : 0];
+        st.xr[4 * pp + u] = ok ? xv : XT(0);
       }
     }
     if constexpr (IT == 0) {
@@ -261,7 +270,9 @@ __global__ void __launch_bounds__(256)
         const int e = t + 256 * v;
         const int kr = e / 64, cc = e % 64;
         const int64_t gk = c0 + kr;
-        mr[v] = (gk < d && cc < k) ? m32[gk * k + cc] : 0.0f;
+        const bool ok = gk < d && cc < k;
+        const float mv = m32[ok ? gk * k + cc : 0];
+        st.mr[v] = ok ? mv : 0.0f;
       }
     } else {
       // Mh / Ml by column: 64 columns x 32 k, element e = t + 256 v
@@ -271,13 +282,15 @@ __global__ void __launch_bounds__(256)
         const int cc = e / 32, kr = e % 32;
         const int64_t gk = c0 + kr;
         const bool ok = gk < d;
-        mhr[v] = ok ? mh[cc * ldm + gk] : uint16_t(0);
-        mmr[v] = ok ? mm[cc * ldm + gk] : uint16_t(0);
-        mlr[v] = ok ? ml[cc * ldm + gk] : uint16_t(0);
+        const int64_t i = ok ? cc * ldm + gk : 0;
+        const uint16_t hv = mh[i], mv = mm[i], lv = ml[i];
+        st.mhr[v] = ok ? hv : uint16_t(0);
+        st.mmr[v] = ok ? mv : uint16_t(0);
+        st.mlr[v] = ok ? lv : uint16_t(0);
       }
     }
   };
-  auto store_chunk = [&](int buf) {
+  auto store_chunk = [&](int buf, const SStage& st) {
     unsigned char* xb = lds + buf * kXBytes;
     unsigned char* mb = lds + 2 * kXBytes + buf * kMBytes;
     if constexpr (IT == 0) {
@@ -286,36 +299,31 @@ __global__ void __launch_bounds__(256)
       for (int pp = 0; pp < 4; ++pp)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          X[(t / 8 + 32 * pp) * kXS32 + 4 * (t % 8) + u] = xr[4 * pp + u];
+          X[(t / 8 + 32 * pp) * kXS32 + 4 * (t % 8) + u] = st.xr[4 * pp + u];
       float* M = reinterpret_cast<float*>(mb);
 #pragma unroll
-      for (int v = 0; v < 8; ++v) M[t + 256 * v] = mr[v];
+      for (int v = 0; v < 8; ++v) M[t + 256 * v] = st.mr[v];
     } else {
       uint16_t* X = reinterpret_cast<uint16_t*>(xb);
 #pragma unroll
       for (int pp = 0; pp < 4; ++pp)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          X[(t / 8 + 32 * pp) * kXS16 + 4 * (t % 8) + u] = in_bf16(xr[4 * pp + u]);
+          X[(t / 8 + 32 * pp) * kXS16 + 4 * (t % 8) + u] = in_bf16(st.xr[4 * pp + u]);
       uint16_t* Mh = reinterpret_cast<uint16_t*>(mb);
       uint16_t* Mm = Mh + 64 * kXS16;
       uint16_t* Ml = Mm + 64 * kXS16;
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
         const int e = t + 256 * v;
-        Mh[(e / 32) * kXS16 + e % 32] = mhr[v];
-        Mm[(e / 32) * kXS16 + e % 32] = mmr[v];
-        Ml[(e / 32) * kXS16 + e % 32] = mlr[v];
+        Mh[(e / 32) * kXS16 + e % 32] = st.mhr[v];
+        Mm[(e / 32) * kXS16 + e % 32] = st.mmr[v];
+        Ml[(e / 32) * kXS16 + e % 32] = st.mlr[v];
       }
     }
   };
-
-  load_chunk(0);
-  store_chunk(0);
-  __syncthreads();
-  for (int ch = 0; ch < nch; ++ch) {
-    const int buf = ch & 1;
-    if (ch + 1 < nch) load_chunk(ch + 1);
+  // products of the chunk in buffer buf, added to the FP64 accumulators
+  auto compute = [&](int buf) {
     const unsigned char* xb = lds + buf * kXBytes;
     const unsigned char* mb = lds + 2 * kXBytes + buf * kMBytes;
     if constexpr (IT == 0) {
@@ -361,10 +369,45 @@ __global__ void __launch_bounds__(256)
         a64[tt][e] += static_cast<double>(acc[tt][e]);
         acc[tt][e] = 0.0f;
       }
-    if (ch + 1 < nch) {
-      __syncthreads();  // every wave is done with the other buffer
-      store_chunk(buf ^ 1);
+  };
+
+  // every store to a buffer follows a barrier after its last reader
+  if constexpr (IT == 0) {
+    // buffer 0 holds chunk ch and stage s1 chunk ch + 1 at the top of the loop
+    SStage s0, s1;
+    load_chunk(0, s0);
+    if (nch > 1) load_chunk(1, s1);
+    store_chunk(0, s0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ch += 2) {
+      if (ch + 2 < nch) load_chunk(ch + 2, s0);
+      compute(0);
+      if (ch + 1 >= nch) break;
       __syncthreads();
+      store_chunk(1, s1);
+      __syncthreads();
+      if (ch + 3 < nch) load_chunk(ch + 3, s1);
+      compute(1);
+      if (ch + 2 >= nch) break;
+      __syncthreads();
+      store_chunk(0, s0);
+      __syncthreads();
+    }
+  } else {
+    // the BF16 parts of M take more staging registers: one chunk ahead
+    SStage s0;
+    load_chunk(0, s0);
+    store_chunk(0, s0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+      const int buf = ch & 1;
+      if (ch + 1 < nch) load_chunk(ch + 1, s0);
+      compute(buf);
+      if (ch + 1 < nch) {
+        __syncthreads();
+        store_chunk(buf ^ 1, s0);
+        __syncthreads();
+      }
     }
   }
   // l_i = sum_c y_ic^2: square and add the two tiles, then 32 lanes

@@ -237,7 +237,8 @@ __device__ __forceinline__ float elem_f(const uint8_t* p, int64_t i) {
   return e4m3_to_f32(p[i]);
 }
 
-template <typename T>
+// kTail: d % 4 != 0 (rows end in a partial vector)
+template <typename T, bool kTail>
 __global__ void __launch_bounds__(256)
     countsketch_colmax_kernel(const T* __restrict__ x, int64_t d, int64_t ld,
                               const float* __restrict__ col_scale,
@@ -266,33 +267,60 @@ __global__ void __launch_bounds__(256)
       double acc[16];
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[e] = 0.0;
-      for (int p = p0; p < p1; ++p) {
-        const uint32_t v = sorted_vals[p];
-        const int64_t row = static_cast<int64_t>(v & 0x7fffffffu);
-        const bool neg = (v >> 31) != 0;
-        const T* xr = x + row * ld;
-        float xv[16];
+      // rows four at a time: all their loads are issued before the sums,
+      // which still run row by row in ascending order
+      for (int p = p0; p < p1; p += 4) {
+        float xv[4][16];
+        bool neg[4];
+        // branch-free loads (a row past the bucket repeats its last row, a
+        // vector past the end reads the row start; both are masked): the row
+        // list entries first, then every vector, so all stay in flight
+        // together
+        const T* xr[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int64_t c = c0 + 4 * (lane + 64 * u);
-          float q[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-          if (c + 4 <= d) {
-            load4(xr + c, q);
-          } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (c + e < d) q[e] = elem_f(xr, c + e);
-          }
-#pragma unroll
-          for (int e = 0; e < 4; ++e) xv[4 * u + e] = q[e];
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t v = sorted_vals[p + j < p1 ? p + j : p1 - 1];
+          neg[j] = (v >> 31) != 0;
+          xr[j] = x + static_cast<int64_t>(v & 0x7fffffffu) * ld;
         }
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const float a = fabsf(xv[e]);
-          bad |= !(a <= 3.402823466e38f);
-          cm[e] = fmaxf(cm[e], a);
-          const double xd = static_cast<double>(xv[e]);
-          acc[e] += neg ? -xd : xd;
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int64_t c = c0 + 4 * (lane + 64 * u);
+            const bool full = c + 4 <= d;
+            float q[4];
+            load4(xr[j] + (full ? c : 0), q);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) xv[j][4 * u + e] = full ? q[e] : 0.0f;
+          }
+        if (kTail) {
+          // the partial last vector of each row, element by element
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int64_t c = c0 + 4 * (lane + 64 * u);
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const bool ok = c + 4 > d && c + e < d;
+                const float sv = elem_f(xr[j], ok ? c + e : 0);
+                xv[j][4 * u + e] = ok ? sv : xv[j][4 * u + e];
+              }
+            }
+        }
+        // sums in row order; a repeated row (past the bucket) is added with
+        // weight zero and changes no maximum
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double sg = p + j < p1 ? (neg[j] ? -1.0 : 1.0) : 0.0;
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            const float a = fabsf(xv[j][e]);
+            bad |= !(a <= 3.402823466e38f);
+            cm[e] = fmaxf(cm[e], a);
+            acc[e] = fma(sg, static_cast<double>(xv[j][e]), acc[e]);
+          }
         }
       }
 #pragma unroll
@@ -511,18 +539,25 @@ bool launch_countsketch_colmax(const void* x, int dtype, int64_t d, int64_t ld,
   const int64_t groups = countsketch_colmax_groups(r);
   const unsigned g = static_cast<unsigned>(groups);
   prof_begin(kKSketch, s);
+  const bool tail = d % 4 != 0;
+#define SLSO_CS_LAUNCH(T, CS)                                                   \
+  do {                                                                          \
+    if (tail)                                                                   \
+      countsketch_colmax_kernel<T, true><<<g, 256, 0, s>>>(                     \
+          static_cast<const T*>(x), d, ld, CS, sorted_vals, offsets, r, parts, \
+          nonfinite, sx);                                                       \
+    else                                                                        \
+      countsketch_colmax_kernel<T, false><<<g, 256, 0, s>>>(                    \
+          static_cast<const T*>(x), d, ld, CS, sorted_vals, offsets, r, parts, \
+          nonfinite, sx);                                                       \
+  } while (0)
   if (dtype == 1)
-    countsketch_colmax_kernel<float><<<g, 256, 0, s>>>(
-        static_cast<const float*>(x), d, ld, nullptr, sorted_vals, offsets, r,
-        parts, nonfinite, sx);
+    SLSO_CS_LAUNCH(float, nullptr);
   else if (dtype == 2)
-    countsketch_colmax_kernel<uint16_t><<<g, 256, 0, s>>>(
-        static_cast<const uint16_t*>(x), d, ld, nullptr, sorted_vals, offsets,
-        r, parts, nonfinite, sx);
+    SLSO_CS_LAUNCH(uint16_t, nullptr);
   else
-    countsketch_colmax_kernel<uint8_t><<<g, 256, 0, s>>>(
-        static_cast<const uint8_t*>(x), d, ld, col_scale, sorted_vals, offsets,
-        r, parts, nonfinite, sx);
+    SLSO_CS_LAUNCH(uint8_t, col_scale);
+#undef SLSO_CS_LAUNCH
   prof_end(kKSketch, s);
   colmax_parts_kernel<<<grid1(d, 4), 256, 0, s>>>(
       parts, groups, d, dtype == 3 ? col_scale : nullptr, nonfinite, dscale);
