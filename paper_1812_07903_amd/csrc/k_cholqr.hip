@@ -70,12 +70,21 @@ template <bool AT>
 __device__ __forceinline__ void mm64_sub(const double* A, const double* B,
                                          dbl4 (&acc)[4], int lane, int w) {
   const int p = lane & 15, q = lane >> 4;
-#pragma unroll 4
-  for (int kk = 0; kk < 16; ++kk) {
-    const int k = 4 * kk + q;
-    const double a = AT ? -A[k * kS + 16 * w + p] : -A[(16 * w + p) * kS + k];
+  // four steps' operands per LDS round trip (sixteen MFMAs)
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) acc[bj] = mfma(a, B[k * kS + 16 * bj + p], acc[bj]);
+  for (int k0 = 0; k0 < 16; k0 += 4) {
+    double a[4], b[4][4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * (k0 + kk) + q;
+      a[kk] = AT ? A[k * kS + 16 * w + p] : A[(16 * w + p) * kS + k];
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) b[kk][bj] = B[k * kS + 16 * bj + p];
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) acc[bj] = mfma(-a[kk], b[kk][bj], acc[bj]);
   }
 }
 
@@ -539,13 +548,23 @@ template <bool SUB>
 __device__ __forceinline__ void mm64x8(const double* A, const double* B,
                                        dbl4 (&acc)[2], int lane, int w) {
   const int p = lane & 15, q = lane >> 4, wr = w & 3, wc = w >> 2;
-#pragma unroll 4
-  for (int kk = 0; kk < 16; ++kk) {
-    const int k = 4 * kk + q;
-    const double a = SUB ? -A[(16 * wr + p) * kS + k] : A[(16 * wr + p) * kS + k];
+  // the operands of eight steps are read before their products: one LDS
+  // round trip per sixteen MFMAs
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-      acc[bj] = mfma(a, B[k * kS + 32 * wc + 16 * bj + p], acc[bj]);
+  for (int k0 = 0; k0 < 16; k0 += 8) {
+    double a[8], b[8][2];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const int k = 4 * (k0 + kk) + q;
+      a[kk] = A[(16 * wr + p) * kS + k];
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) b[kk][bj] = B[k * kS + 32 * wc + 16 * bj + p];
+    }
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+        acc[bj] = mfma(SUB ? -a[kk] : a[kk], b[kk][bj], acc[bj]);
   }
 }
 
@@ -566,9 +585,15 @@ __global__ void __launch_bounds__(kSW)
   for (int64_t J = 0; J < nb; ++J) {
     const int64_t cJ = J * kP;
     const int64_t nc = d - cJ < kP ? d - cJ : kP;
-    // A_J (times dsc) without branches: an entry outside the matrix reads a
-    // clamped address and is replaced by zero, so the loads stay in flight
-    // together
+    // blocks I < J are complete (only the last block can be partial)
+    Stage8 va, vb;
+    if (J > 0) {
+      stage8_load(va, As, lda, nr, kP, t);
+      stage8_load(vb, R + tix(0, J, nb), kP, kP, kP, t);
+    }
+    // A_J (times dsc), loaded after the staged blocks and without branches:
+    // an entry outside the matrix reads a clamped address and is replaced by
+    // zero, so all these loads are in flight together
     dbl4 acc[2];
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
@@ -587,12 +612,6 @@ __global__ void __launch_bounds__(kSW)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[bj][v] *= sc;
       }
-    }
-    // blocks I < J are complete (only the last block can be partial)
-    Stage8 va, vb;
-    if (J > 0) {
-      stage8_load(va, As, lda, nr, kP, t);
-      stage8_load(vb, R + tix(0, J, nb), kP, kP, kP, t);
     }
     for (int64_t I = 0; I < J; ++I) {
       __syncthreads();

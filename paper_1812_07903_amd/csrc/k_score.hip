@@ -158,9 +158,8 @@ __global__ void __launch_bounds__(256)
 // A workgroup of four waves scores 128 rows; wave w owns rows 32w .. 32w + 31
 // and all 64 columns of M (two 32 x 32 accumulator tiles). The contraction
 // over d runs in chunks of 32: X (128 x 32) and M (32 x 64) are staged in
-// LDS, double-buffered (FP32 input: loaded into registers two chunks ahead,
-// so a load has two chunks' products to arrive in), the chunk's products
-// summed on MFMA in FP32 and added
+// LDS, double-buffered (the next chunk is loaded into registers while this
+// one multiplies), the chunk's products summed on MFMA in FP32 and added
 // to FP64 accumulators, so the error is that of 32-term FP32 sums.
 //   FP32 input: v_mfma_f32_32x32x2f32 on FP32 X and FP32 M.
 //   BF16 / FP8 input: v_mfma_f32_32x32x16_bf16 on X (exact in BF16) and three
@@ -239,28 +238,31 @@ __global__ void __launch_bounds__(256)
     }
 
   // staging registers: X 16 elements per thread (row t/8 + 32 p, columns
-  // 4 (t%8) .. +3), M 8 elements per thread. Two sets: chunk c + 2 is loaded
-  // while chunk c is multiplied, so each load has two chunks' products to
-  // arrive in.
+  // 4 (t%8) .. +3), M 8 elements per thread
   using XT = typename XIn<IT>::T;
+  // raw loaded values and which of them lie inside the matrix: the zeros
+  // are put in when the stage goes to LDS, so no load is waited for early
   struct SStage {
     XT xr[16];
     float mr[8];
     uint16_t mhr[8], mmr[8], mlr[8];
+    uint32_t okx, okm;
   };
   auto load_chunk = [&](int ch, SStage& st) {
     const int64_t c0 = static_cast<int64_t>(ch) * kMC;
+    st.okx = 0u;
+    st.okm = 0u;
 #pragma unroll
     for (int pp = 0; pp < 4; ++pp) {
       const int r = t / 8 + 32 * pp;
       const int64_t gr = row0 + r;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        // branch-free: an entry outside reads x[0] and becomes zero
+        // an entry outside reads x[0] (zeroed at the store)
         const int64_t gc = c0 + 4 * (t % 8) + u;
         const bool ok = gr < n && gc < d;
-        const XT xv = x[ok ? gr * ld + gc : 0];
-        st.xr[4 * pp + u] = ok ? xv : XT(0);
+        st.xr[4 * pp + u] = x[ok ? gr * ld + gc : 0];
+        st.okx |= ok ? (1u << (4 * pp + u)) : 0u;
       }
     }
     if constexpr (IT == 0) {
@@ -271,8 +273,8 @@ __global__ void __launch_bounds__(256)
         const int kr = e / 64, cc = e % 64;
         const int64_t gk = c0 + kr;
         const bool ok = gk < d && cc < k;
-        const float mv = m32[ok ? gk * k + cc : 0];
-        st.mr[v] = ok ? mv : 0.0f;
+        st.mr[v] = m32[ok ? gk * k + cc : 0];
+        st.okm |= ok ? (1u << v) : 0u;
       }
     } else {
       // Mh / Ml by column: 64 columns x 32 k, element e = t + 256 v
@@ -283,10 +285,10 @@ __global__ void __launch_bounds__(256)
         const int64_t gk = c0 + kr;
         const bool ok = gk < d;
         const int64_t i = ok ? cc * ldm + gk : 0;
-        const uint16_t hv = mh[i], mv = mm[i], lv = ml[i];
-        st.mhr[v] = ok ? hv : uint16_t(0);
-        st.mmr[v] = ok ? mv : uint16_t(0);
-        st.mlr[v] = ok ? lv : uint16_t(0);
+        st.mhr[v] = mh[i];
+        st.mmr[v] = mm[i];
+        st.mlr[v] = ml[i];
+        st.okm |= ok ? (1u << v) : 0u;
       }
     }
   };
@@ -299,26 +301,30 @@ __global__ void __launch_bounds__(256)
       for (int pp = 0; pp < 4; ++pp)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          X[(t / 8 + 32 * pp) * kXS32 + 4 * (t % 8) + u] = st.xr[4 * pp + u];
+          X[(t / 8 + 32 * pp) * kXS32 + 4 * (t % 8) + u] =
+              ((st.okx >> (4 * pp + u)) & 1u) ? st.xr[4 * pp + u] : 0.0f;
       float* M = reinterpret_cast<float*>(mb);
 #pragma unroll
-      for (int v = 0; v < 8; ++v) M[t + 256 * v] = st.mr[v];
+      for (int v = 0; v < 8; ++v)
+        M[t + 256 * v] = ((st.okm >> v) & 1u) ? st.mr[v] : 0.0f;
     } else {
       uint16_t* X = reinterpret_cast<uint16_t*>(xb);
 #pragma unroll
       for (int pp = 0; pp < 4; ++pp)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          X[(t / 8 + 32 * pp) * kXS16 + 4 * (t % 8) + u] = in_bf16(st.xr[4 * pp + u]);
+          X[(t / 8 + 32 * pp) * kXS16 + 4 * (t % 8) + u] =
+              ((st.okx >> (4 * pp + u)) & 1u) ? in_bf16(st.xr[4 * pp + u]) : uint16_t(0);
       uint16_t* Mh = reinterpret_cast<uint16_t*>(mb);
       uint16_t* Mm = Mh + 64 * kXS16;
       uint16_t* Ml = Mm + 64 * kXS16;
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
         const int e = t + 256 * v;
-        Mh[(e / 32) * kXS16 + e % 32] = st.mhr[v];
-        Mm[(e / 32) * kXS16 + e % 32] = st.mmr[v];
-        Ml[(e / 32) * kXS16 + e % 32] = st.mlr[v];
+        const bool ok = (st.okm >> v) & 1u;
+        Mh[(e / 32) * kXS16 + e % 32] = ok ? st.mhr[v] : uint16_t(0);
+        Mm[(e / 32) * kXS16 + e % 32] = ok ? st.mmr[v] : uint16_t(0);
+        Ml[(e / 32) * kXS16 + e % 32] = ok ? st.mlr[v] : uint16_t(0);
       }
     }
   };
@@ -329,13 +335,24 @@ __global__ void __launch_bounds__(256)
     if constexpr (IT == 0) {
       const float* X = reinterpret_cast<const float*>(xb);
       const float* M = reinterpret_cast<const float*>(mb);
+      // operands of eight steps read before their products, so one LDS
+      // round trip serves sixteen MFMAs
 #pragma unroll
-      for (int kk = 0; kk < kMC / 2; ++kk) {
-        const float av = X[(32 * w + l32) * kXS32 + 2 * kk + h];
+      for (int k0 = 0; k0 < kMC / 2; k0 += 8) {
+        float av[8], bv[8][2];
 #pragma unroll
-        for (int tt = 0; tt < 2; ++tt)
-          acc[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-              av, M[(2 * kk + h) * 64 + 32 * tt + l32], acc[tt], 0, 0, 0);
+        for (int kk = 0; kk < 8; ++kk) {
+          av[kk] = X[(32 * w + l32) * kXS32 + 2 * (k0 + kk) + h];
+#pragma unroll
+          for (int tt = 0; tt < 2; ++tt)
+            bv[kk][tt] = M[(2 * (k0 + kk) + h) * 64 + 32 * tt + l32];
+        }
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+          for (int tt = 0; tt < 2; ++tt)
+            acc[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk], bv[kk][tt],
+                                                            acc[tt], 0, 0, 0);
       }
     } else {
       const __bf16* X = reinterpret_cast<const __bf16*>(xb);
@@ -372,42 +389,18 @@ __global__ void __launch_bounds__(256)
   };
 
   // every store to a buffer follows a barrier after its last reader
-  if constexpr (IT == 0) {
-    // buffer 0 holds chunk ch and stage s1 chunk ch + 1 at the top of the loop
-    SStage s0, s1;
-    load_chunk(0, s0);
-    if (nch > 1) load_chunk(1, s1);
-    store_chunk(0, s0);
-    __syncthreads();
-    for (int ch = 0; ch < nch; ch += 2) {
-      if (ch + 2 < nch) load_chunk(ch + 2, s0);
-      compute(0);
-      if (ch + 1 >= nch) break;
+  SStage s0;
+  load_chunk(0, s0);
+  store_chunk(0, s0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) load_chunk(ch + 1, s0);
+    compute(buf);
+    if (ch + 1 < nch) {
       __syncthreads();
-      store_chunk(1, s1);
+      store_chunk(buf ^ 1, s0);
       __syncthreads();
-      if (ch + 3 < nch) load_chunk(ch + 3, s1);
-      compute(1);
-      if (ch + 2 >= nch) break;
-      __syncthreads();
-      store_chunk(0, s0);
-      __syncthreads();
-    }
-  } else {
-    // the BF16 parts of M take more staging registers: one chunk ahead
-    SStage s0;
-    load_chunk(0, s0);
-    store_chunk(0, s0);
-    __syncthreads();
-    for (int ch = 0; ch < nch; ++ch) {
-      const int buf = ch & 1;
-      if (ch + 1 < nch) load_chunk(ch + 1, s0);
-      compute(buf);
-      if (ch + 1 < nch) {
-        __syncthreads();
-        store_chunk(buf ^ 1, s0);
-        __syncthreads();
-      }
     }
   }
   // l_i = sum_c y_ic^2: square and add the two tiles, then 32 lanes

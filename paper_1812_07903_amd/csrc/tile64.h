@@ -35,12 +35,21 @@ template <bool AT>
 __device__ __forceinline__ void mm64(const double* A, const double* B,
                                      dbl4 (&acc)[4], int lane, int w) {
   const int p = lane & 15, q = lane >> 4;
-#pragma unroll 4
-  for (int kk = 0; kk < 16; ++kk) {
-    const int k = 4 * kk + q;
-    const double a = AT ? A[k * kS + 16 * w + p] : A[(16 * w + p) * kS + k];
+  // four steps' operands per LDS round trip (sixteen MFMAs)
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) acc[bj] = mfma(a, B[k * kS + 16 * bj + p], acc[bj]);
+  for (int k0 = 0; k0 < 16; k0 += 4) {
+    double a[4], b[4][4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * (k0 + kk) + q;
+      a[kk] = AT ? A[k * kS + 16 * w + p] : A[(16 * w + p) * kS + k];
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) b[kk][bj] = B[k * kS + 16 * bj + p];
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) acc[bj] = mfma(a[kk], b[kk][bj], acc[bj]);
   }
 }
 
