@@ -52,7 +52,7 @@ def qr_node_flops(m: int, d: int, w: int = 16) -> float:
 # profiler name -> (kernel symbol in the PMC summary, source file)
 KERNEL_SRC = {
     "cq2_gram": ("gram_block_kernel<false, true>", "k_cholqr.hip"),
-    "cq2_solve": ("stripe_solve_kernel", "k_cholqr.hip"),
+    "cq2_solve": ("stripe_solve_kernel<64>", "k_cholqr.hip"),
     "cq_update": ("cq_update_kernel", "k_cqr.hip"),
     "cq_z": ("cq_z_kernel", "k_cqr.hip"),
     "cq_q1": ("cq_q1_kernel", "k_cqr.hip"),

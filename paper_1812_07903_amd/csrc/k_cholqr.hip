@@ -509,45 +509,51 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// ---- Q1 = A R^{-1} in place, by 64-row stripes ---------------------------------
+// ---- Q1 = A R^{-1} in place, by row stripes -------------------------------------
 // Stripe rows are independent: column block J of the stripe becomes
 // (A_J - sum_{I<J} Q1_I R_IJ) R_JJ^{-1}, blocks in increasing J, each written
-// over A_J once A_J has been read. Eight waves per stripe, two per SIMD:
-// wave w owns rows 16 (w & 3) .. + 15 and columns 32 (w >> 2) .. + 31 of each
-// 64 x 64 product, so one wave's LDS reads overlap the other's products.
-constexpr int kSW = 512;  // threads of a stripe workgroup
+// over A_J once A_J has been read. A stripe of kR rows has kR / 8 waves
+// (kR / 16 row groups x 2 column halves): wave w owns rows
+// 16 (w % (kR / 16)) .. + 15 and columns 32 (w / (kR / 16)) .. + 31 of each
+// kR x 64 product. 64-row stripes (eight waves, two per SIMD) measured
+// faster than 32-row ones (two workgroups of four waves per CU).
+constexpr int kStripeRows = 64;
 
-struct Stage8 {
-  double v[8];
+template <int N>
+struct StageN {
+  double v[N];
   uint32_t ok;
 };
-// tile element e = t + 512 u (row e / 64, column e % 64), as stage_load
-__device__ __forceinline__ void stage8_load(Stage8& s, const double* a,
+// element e = t + kT u (row e / 64, column e % 64) of a tile, loaded without
+// branches (clamped addresses, validity bits), as stage_load
+template <int N, int kT>
+__device__ __forceinline__ void stagen_load(StageN<N>& s, const double* a,
                                             int64_t lda, int64_t nr, int64_t nc,
                                             int t) {
   s.ok = 0u;
   const int64_t r1 = nr - 1, c1 = nc - 1;
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const int e = t + kSW * u;
+  for (int u = 0; u < N; ++u) {
+    const int e = t + kT * u;
     const int64_t i = e >> 6, j = e & 63;
     s.ok |= (i < nr && j < nc) ? (1u << u) : 0u;
     s.v[u] = a[(i < r1 ? i : r1) * lda + (j < c1 ? j : c1)];
   }
 }
-__device__ __forceinline__ void stage8_store(double* tile, const Stage8& s,
+template <int N, int kT>
+__device__ __forceinline__ void stagen_store(double* tile, const StageN<N>& s,
                                              int t) {
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const int e = t + kSW * u;
+  for (int u = 0; u < N; ++u) {
+    const int e = t + kT * u;
     tile[(e >> 6) * kS + (e & 63)] = ((s.ok >> u) & 1u) ? s.v[u] : 0.0;
   }
 }
-// acc (+)= A B on the wave's 16 x 32 part
-template <bool SUB>
-__device__ __forceinline__ void mm64x8(const double* A, const double* B,
-                                       dbl4 (&acc)[2], int lane, int w) {
-  const int p = lane & 15, q = lane >> 4, wr = w & 3, wc = w >> 2;
+// acc (+)= A B on the wave's 16 x 32 part (kWR row groups)
+template <bool SUB, int kWR>
+__device__ __forceinline__ void mm_stripe(const double* A, const double* B,
+                                          dbl4 (&acc)[2], int lane, int w) {
+  const int p = lane & 15, q = lane >> 4, wr = w % kWR, wc = w / kWR;
   // the operands of eight steps are read before their products: one LDS
   // round trip per sixteen MFMAs
 #pragma unroll
@@ -568,28 +574,32 @@ __device__ __forceinline__ void mm64x8(const double* A, const double* B,
   }
 }
 
-__global__ void __launch_bounds__(kSW)
+template <int kR>
+__global__ void __launch_bounds__(8 * kR)
     stripe_solve_kernel(double* __restrict__ A, int64_t lda, int64_t m,
                         int64_t d, int64_t nb, const double* __restrict__ R,
                         const double* __restrict__ Dinv,
                         const double* __restrict__ dsc,
                         const int* __restrict__ flag) {
-  __shared__ double TA[kTile];
+  constexpr int kT = 8 * kR, kWR = kR / 16;
+  constexpr int kNA = kR * 64 / kT, kNB = 4096 / kT;  // staged per thread
+  __shared__ double TA[kR * kS];
   __shared__ double TB[kTile];
   if (*flag) return;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w & 3, wc = w >> 2;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w % kWR, wc = w / kWR;
   const int p = lane & 15, q = lane >> 4;
-  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kP;
-  const int64_t nr = m - r0 < kP ? m - r0 : kP;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kR;
+  const int64_t nr = m - r0 < kR ? m - r0 : kR;
   double* As = A + r0 * lda;
   for (int64_t J = 0; J < nb; ++J) {
     const int64_t cJ = J * kP;
     const int64_t nc = d - cJ < kP ? d - cJ : kP;
     // blocks I < J are complete (only the last block can be partial)
-    Stage8 va, vb;
+    StageN<kNA> va;
+    StageN<kNB> vb;
     if (J > 0) {
-      stage8_load(va, As, lda, nr, kP, t);
-      stage8_load(vb, R + tix(0, J, nb), kP, kP, kP, t);
+      stagen_load<kNA, kT>(va, As, lda, nr, kP, t);
+      stagen_load<kNB, kT>(vb, R + tix(0, J, nb), kP, kP, kP, t);
     }
     // A_J (times dsc), loaded after the staged blocks and without branches:
     // an entry outside the matrix reads a clamped address and is replaced by
@@ -615,27 +625,27 @@ __global__ void __launch_bounds__(kSW)
     }
     for (int64_t I = 0; I < J; ++I) {
       __syncthreads();
-      stage8_store(TA, va, t);
-      stage8_store(TB, vb, t);
+      stagen_store<kNA, kT>(TA, va, t);
+      stagen_store<kNB, kT>(TB, vb, t);
       __syncthreads();
       if (I + 1 < J) {
-        stage8_load(va, As + (I + 1) * kP, lda, nr, kP, t);
-        stage8_load(vb, R + tix(I + 1, J, nb), kP, kP, kP, t);
+        stagen_load<kNA, kT>(va, As + (I + 1) * kP, lda, nr, kP, t);
+        stagen_load<kNB, kT>(vb, R + tix(I + 1, J, nb), kP, kP, kP, t);
       }
-      mm64x8<true>(TA, TB, acc, lane, w);
+      mm_stripe<true, kWR>(TA, TB, acc, lane, w);
     }
-    stage8_load(vb, Dinv + J * kT2, kP, kP, kP, t);
+    stagen_load<kNB, kT>(vb, Dinv + J * kT2, kP, kP, kP, t);
     __syncthreads();
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         TA[(16 * wr + 4 * v + q) * kS + 32 * wc + 16 * bj + p] = acc[bj][v];
-    stage8_store(TB, vb, t);
+    stagen_store<kNB, kT>(TB, vb, t);
     __syncthreads();
     dbl4 res[2];
     res[0] = res[1] = dbl4{0.0, 0.0, 0.0, 0.0};
-    mm64x8<false>(TA, TB, res, lane, w);
+    mm_stripe<false, kWR>(TA, TB, res, lane, w);
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
@@ -988,8 +998,8 @@ void cholqr2_factor(double* a, int64_t m, int64_t d, double* r_out,
   gram_tiles(a, m, d, c, false, dsc, status, s);
   bchol(c, c.R1, want_r ? nullptr : c.X1, status, s);
   prof_begin(kKCq2Solve, s);
-  stripe_solve_kernel<<<cdivu(m, kP), kSW, 0, s>>>(a, d, m, d, c.nb, c.R1,
-                                                    c.Dinv, dsc, status);
+  stripe_solve_kernel<kStripeRows><<<cdivu(m, kStripeRows), 8 * kStripeRows, 0, s>>>(
+      a, d, m, d, c.nb, c.R1, c.Dinv, dsc, status);
   prof_end(kKCq2Solve, s);
   gram_tiles(a, m, d, c, true, nullptr, status, s);
   prof_begin(kKCq2R, s);
