@@ -209,7 +209,10 @@ __device__ __forceinline__ double sum32(double v) {
   return v;
 }
 
-template <int IT>
+// kVec (FP32 input, ld and d multiples of 4, 16-byte aligned X, k = 64): the
+// staging loads are 4-float vectors, a quarter of the load instructions and
+// cache-line lookups of the element-wise form
+template <int IT, bool kVec = false>
 __global__ void __launch_bounds__(256)
     score_mfma_kernel(const typename XIn<IT>::T* __restrict__ x, int64_t n,
                       int64_t d, int64_t ld, const float* __restrict__ m32,
@@ -252,6 +255,36 @@ __global__ void __launch_bounds__(256)
     const int64_t c0 = static_cast<int64_t>(ch) * kMC;
     st.okx = 0u;
     st.okm = 0u;
+    if constexpr (kVec) {
+      // X: row t/8 + 32 pp, columns 4 (t%8) .. +3 as one vector; M: rows
+      // c0 + (t + 256 v) / 16, columns 4 ((t + 256 v) % 16) .. +3
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp) {
+        const int64_t gr = row0 + t / 8 + 32 * pp;
+        const int64_t gc = c0 + 4 * (t % 8);
+        const bool ok = gr < n && gc < d;
+        const float4 q = *reinterpret_cast<const float4*>(x + (ok ? gr * ld + gc : 0));
+        st.xr[4 * pp] = q.x;
+        st.xr[4 * pp + 1] = q.y;
+        st.xr[4 * pp + 2] = q.z;
+        st.xr[4 * pp + 3] = q.w;
+        st.okx |= ok ? (0xfu << (4 * pp)) : 0u;
+      }
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int e4 = t + 256 * v;
+        const int64_t gk = c0 + e4 / 16;
+        const bool ok = gk < d;
+        const float4 q = *reinterpret_cast<const float4*>(
+            m32 + (ok ? gk * 64 + 4 * (e4 % 16) : 0));
+        st.mr[4 * v] = q.x;
+        st.mr[4 * v + 1] = q.y;
+        st.mr[4 * v + 2] = q.z;
+        st.mr[4 * v + 3] = q.w;
+        st.okm |= ok ? (0xfu << (4 * v)) : 0u;
+      }
+      return;
+    }
 #pragma unroll
     for (int pp = 0; pp < 4; ++pp) {
       const int r = t / 8 + 32 * pp;
@@ -304,9 +337,18 @@ __global__ void __launch_bounds__(256)
           X[(t / 8 + 32 * pp) * kXS32 + 4 * (t % 8) + u] =
               ((st.okx >> (4 * pp + u)) & 1u) ? st.xr[4 * pp + u] : 0.0f;
       float* M = reinterpret_cast<float*>(mb);
+      if constexpr (kVec) {
 #pragma unroll
-      for (int v = 0; v < 8; ++v)
-        M[t + 256 * v] = ((st.okm >> v) & 1u) ? st.mr[v] : 0.0f;
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            M[4 * (t + 256 * v) + u] =
+                ((st.okm >> (4 * v + u)) & 1u) ? st.mr[4 * v + u] : 0.0f;
+      } else {
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+          M[t + 256 * v] = ((st.okm >> v) & 1u) ? st.mr[v] : 0.0f;
+      }
     } else {
       uint16_t* X = reinterpret_cast<uint16_t*>(xb);
 #pragma unroll
@@ -468,10 +510,18 @@ void launch_scores(const void* x, int dtype, int format, int64_t n, int64_t d,
   if (dtype != 0 && k <= 64) {
     const unsigned g = static_cast<unsigned>((n + kMR - 1) / kMR);
     if (dtype == 1) {
+      const bool vec = ld % 4 == 0 && d % 4 == 0 && k == 64 &&
+                       reinterpret_cast<uintptr_t>(x) % 16 == 0 &&
+                       reinterpret_cast<uintptr_t>(m32) % 16 == 0;
       prof_begin(kKScore, s);
-      score_mfma_kernel<0><<<g, 256, 0, s>>>(static_cast<const float*>(x), n, d,
-                                             ld, m32, k, nullptr, nullptr,
-                                             nullptr, 0, scores);
+      if (vec)
+        score_mfma_kernel<0, true><<<g, 256, 0, s>>>(
+            static_cast<const float*>(x), n, d, ld, m32, k, nullptr, nullptr,
+            nullptr, 0, scores);
+      else
+        score_mfma_kernel<0><<<g, 256, 0, s>>>(static_cast<const float*>(x), n,
+                                               d, ld, m32, k, nullptr, nullptr,
+                                               nullptr, 0, scores);
       prof_end(kKScore, s);
     } else {
       uint16_t* mh = reinterpret_cast<uint16_t*>(partial);
