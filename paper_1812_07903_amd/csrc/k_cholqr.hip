@@ -770,10 +770,11 @@ __global__ void __launch_bounds__(256)
   const int64_t c0 = cb * kP;
   dbl4 acc[4];
   zero4(acc);
+  // the next pair of tiles is loaded while this one multiplies
+  Stage vt, vb;
+  stage_load(vt, T + tix(I, J0, nb), kP, kP, kP, t);
+  stage_load(vb, B + J0 * kP * kk + c0, kk, d - J0 * kP, kk - c0, t);
   for (int64_t J = J0; J < J1; ++J) {
-    Stage vt, vb;
-    stage_load(vt, T + tix(I, J, nb), kP, kP, kP, t);
-    stage_load(vb, B + J * kP * kk + c0, kk, d - J * kP, kk - c0, t);
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -788,6 +789,10 @@ __global__ void __launch_bounds__(256)
     }
     stage_store(TB, vb, t);
     __syncthreads();
+    if (J + 1 < J1) {
+      stage_load(vt, T + tix(I, J + 1, nb), kP, kP, kP, t);
+      stage_load(vb, B + (J + 1) * kP * kk + c0, kk, d - (J + 1) * kP, kk - c0, t);
+    }
     mm64<false>(TA, TB, acc, lane, w);
   }
   store_acc_global(part + (pidx * ncb + blockIdx.y) * kT2, kP, acc, 1.0, lane,

@@ -148,16 +148,20 @@ __global__ void __launch_bounds__(kThreads)
     // start of digit tid in this tile's output: keys of smaller digits in
     // all tiles, plus keys of digit tid in the tiles before this one
     __shared__ uint32_t wsum[4];
+    // 32 entries per round trip (clamped addresses, masked after the load)
     uint32_t tot = 0, before = 0;
-    for (int b0 = 0; b0 < nblocks; b0 += 8) {
-      uint32_t v[8];
+    for (int b0 = 0; b0 < nblocks; b0 += 32) {
+      uint32_t v[32];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        v[u] = b0 + u < nblocks ? hist[static_cast<int64_t>(b0 + u) * 256 + tid] : 0u;
+      for (int u = 0; u < 32; ++u) {
+        const int b = b0 + u < nblocks ? b0 + u : nblocks - 1;
+        v[u] = hist[static_cast<int64_t>(b) * 256 + tid];
+      }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        tot += v[u];
-        before += b0 + u < static_cast<int>(blockIdx.x) ? v[u] : 0u;
+      for (int u = 0; u < 32; ++u) {
+        const uint32_t x = b0 + u < nblocks ? v[u] : 0u;
+        tot += x;
+        before += b0 + u < static_cast<int>(blockIdx.x) ? x : 0u;
       }
     }
     uint32_t inc = tot;
