@@ -51,7 +51,7 @@ def qr_node_flops(m: int, d: int, w: int = 16) -> float:
 
 # profiler name -> (kernel symbol in the PMC summary, source file)
 KERNEL_SRC = {
-    "cq2_gram": ("gram_block_kernel<false, true>", "k_cholqr.hip"),
+    "cq2_gram": ("gram_block_kernel<false,true>", "k_cholqr.hip"),
     "cq2_solve": ("stripe_solve_kernel<64>", "k_cholqr.hip"),
     "cq_update": ("cq_update_kernel", "k_cqr.hip"),
     "cq_z": ("cq_z_kernel", "k_cqr.hip"),
@@ -59,8 +59,8 @@ KERNEL_SRC = {
     "cq_gram": ("cq_gram_kernel", "k_cqr.hip"),
     "qr_node": ("qr_node_kernel", "k_qr.hip"),
     "qr_update": ("qr_update_kernel", "k_qr.hip"),
-    "score": ("score_mfma_kernel<0>", "k_score.hip"),
-    "countsketch": ("countsketch_colmax_kernel<float>", "k_sketch.hip"),
+    "score": ("score_mfma_kernel<0,true>", "k_score.hip"),
+    "countsketch": ("countsketch_colmax_kernel<float,false>", "k_sketch.hip"),
     "colmax": ("colmax_dense_kernel<float>", "k_sketch.hip"),
 }
 PMC_SUMMARY = os.path.join(ROOT, "profiles",
@@ -404,7 +404,8 @@ def main() -> int:
         "roofline": dict(kernel=dname, **roof) if roof else None,
         "roofline_other": {
             k: dict(kernel=k, **rr)
-            for k in ("countsketch", "score", "colmax", "cq_update", "cq_z")
+            for k in ("cq2_solve", "cq2_chol", "countsketch", "score", "colmax",
+                      "cq_update", "cq_z")
             if k in kernels and k != dname
             for rr in [roofline_for(
                 k, kernels[k]["ms_per_step"] / kernels[k]["launches_per_step"],
