@@ -135,14 +135,19 @@ def exact_leverage(x: np.ndarray, rank_tol: float = DEFAULT_RANK_TOL):
 
 
 def sketch_of(x, seed: int, r: int, kind: str = "countsketch",
-              precision: str = "bf16") -> np.ndarray:
+              precision: str = "bf16", nnz: int = 2) -> np.ndarray:
     """Unscaled sketch S X (FP64). For the Gaussian sketch, ``precision``
     names the entries of S ("bf16": reduced-precision inputs, "f32": the
-    plain FP32 path, "f64": the FP64 stream)."""
+    plain FP32 path, "f64": the FP64 stream); for OSNAP, ``nnz`` is the
+    number of nonzeros per column of S."""
     if kind == "countsketch":
         if isinstance(x, np.ndarray):
             return sk.countsketch_dense(x, seed, r)
         return sk.countsketch_csr(x, seed, r)
+    if kind == "osnap":
+        if isinstance(x, np.ndarray):
+            return sk.osnap_dense(x, seed, r, nnz)
+        return sk.osnap_csr(x, seed, r, nnz)
     if kind == "gaussian":
         if not isinstance(x, np.ndarray):
             x = x.to_dense()
@@ -152,7 +157,8 @@ def sketch_of(x, seed: int, r: int, kind: str = "countsketch",
 
 def sketched_leverage(x, seed: int, r: int, k: int, kind: str = "countsketch",
                       rank_tol: float = DEFAULT_RANK_TOL, sx=None,
-                      refine: bool = False, precision: str = "bf16"):
+                      refine: bool = False, precision: str = "bf16",
+                      nnz: int = 2):
     """Algorithm 3 in QR form with the second projection Pi_2.
 
     ``sx`` may carry a precomputed unscaled sketch. With ``refine`` the factor
@@ -168,7 +174,7 @@ def sketched_leverage(x, seed: int, r: int, k: int, kind: str = "countsketch",
         rd = qr_r(xd)
     else:
         if sx is None:
-            sx = sketch_of(x, seed, r, kind, precision)
+            sx = sketch_of(x, seed, r, kind, precision, nnz)
         rd = qr_r(sx * dsc[None, :])
     pi = np.eye(d) if k == 0 else streams.pi2_matrix(seed, d, k)
     mp, rank, info = truncated_apply(rd, pi, rank_tol)

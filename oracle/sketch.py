@@ -67,6 +67,36 @@ def countsketch_csr(csr, seed: int, r: int) -> np.ndarray:
     return sx
 
 
+def osnap_dense(x: np.ndarray, seed: int, r: int, s: int) -> np.ndarray:
+    """OSNAP sketch S X (r x d, FP64) with s nonzeros +-1/sqrt(s) per column
+    of S (block construction, streams.osnap_bucket_sign): for each hash j,
+    SX[h_j(i)] += s_j(i) x_i over i ascending; the sums are then multiplied
+    once by 1/sqrt(s). Block j's rows receive only hash j's rows, so every
+    sketch row is an ascending-row sum, as in the CountSketch."""
+    n, d = x.shape
+    bucket, sign = streams.osnap_bucket_sign(seed, r, s, np.arange(n))
+    sx = np.zeros((r, d), dtype=np.float64)
+    xf = np.asarray(x, dtype=np.float64)
+    for j in range(s):
+        for i in range(n):
+            sx[bucket[j, i]] += float(sign[j, i]) * xf[i]
+    return sx * (1.0 / math.sqrt(s))
+
+
+def osnap_csr(csr, seed: int, r: int, s: int) -> np.ndarray:
+    """OSNAP sketch of a CSR matrix, same order as the dense form."""
+    bucket, sign = streams.osnap_bucket_sign(seed, r, s, np.arange(csr.n))
+    sx = np.zeros((r, csr.d), dtype=np.float64)
+    rp = csr.row_ptr
+    for j in range(s):
+        for i in range(csr.n):
+            a, b = int(rp[i]), int(rp[i + 1])
+            if b > a:
+                sx[bucket[j, i], csr.col_idx[a:b]] += float(sign[j, i]) * \
+                    csr.val[a:b].astype(np.float64)
+    return sx * (1.0 / math.sqrt(s))
+
+
 def gaussian_sketch_dense(x: np.ndarray, seed: int, r: int,
                           g: np.ndarray | None = None,
                           precision: str = "f64") -> np.ndarray:

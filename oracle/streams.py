@@ -34,6 +34,14 @@ library) are:
   Reduced-precision inputs take it rounded to BF16 (ties to even).
 
 Stream ids: 1 bucket hash, 2 sign hash, 3 Gaussian sketch, 4 Pi_2.
+
+* OSNAP with s nonzeros per column (the sparse embedding the paper lists
+  beside CountSketch in Sec. 2.1 and implements, like CountSketch, as hash
+  functions in Sec. 3.1.2), block construction: the r sketch rows form s
+  blocks of b = r / s rows; hash j < s puts row i into block j at
+  j b + (P_1j(i) mod b) with sign from the parity of P_2j(i). Hash 0 uses
+  streams 1 and 2 (so s = 1 is CountSketch); hash j >= 1 uses streams
+  16 + 2j (bucket) and 17 + 2j (sign).
 """
 from __future__ import annotations
 
@@ -89,6 +97,31 @@ def bucket_sign(seed: int, r: int, idx) -> tuple[np.ndarray, np.ndarray]:
     bucket = np.array([int(v) % r for v in hb], dtype=np.int64)
     sign = np.array([1 - 2 * (int(v) & 1) for v in hs], dtype=np.int64)
     return bucket, sign
+
+
+def osnap_streams(j: int) -> tuple[int, int]:
+    """(bucket stream, sign stream) of OSNAP hash j."""
+    if j == 0:
+        return STREAM_BUCKET, STREAM_SIGN
+    return 16 + 2 * j, 17 + 2 * j
+
+
+def osnap_bucket_sign(seed: int, r: int, s: int, idx):
+    """OSNAP buckets and signs, each s x len(idx): hash j sends row i to
+    j (r // s) + (P_1j(i) mod (r // s)) with sign +1 if P_2j(i) is even."""
+    if s < 1 or r % s != 0:
+        raise ValueError("OSNAP needs s >= 1 dividing r")
+    b = r // s
+    idx = np.asarray(idx, dtype=np.int64)
+    buckets = np.empty((s, idx.shape[0]), dtype=np.int64)
+    signs = np.empty((s, idx.shape[0]), dtype=np.int64)
+    for j in range(s):
+        sb, ss = osnap_streams(j)
+        hb = poly_hash(hash_coeffs(seed, sb), idx)
+        hs = poly_hash(hash_coeffs(seed, ss), idx)
+        buckets[j] = [j * b + int(v) % b for v in hb]
+        signs[j] = [1 - 2 * (int(v) & 1) for v in hs]
+    return buckets, signs
 
 
 # --------------------------------------------------------------------------

@@ -107,6 +107,20 @@ def test_sketched_scores_within_realised_embedding_bound():
     assert eps_hat < 0.5
 
 
+def test_osnap_scores_within_realised_embedding_bound():
+    """The same bound with the OSNAP sketch (s = 2 nonzeros per column)."""
+    x = synth.config0(n=5000, d=12, seed=14)
+    lev, _ = lv.exact_leverage(x)
+    q, _ = np.linalg.qr(x)
+    out = lv.sketched_leverage(x, seed=10, r=512, k=0, kind="osnap", nnz=2)
+    sq = sk.osnap_dense(q, 10, 512, 2)
+    sv = np.linalg.svd(sq, compute_uv=False)
+    ratio = out["scores"] / lev
+    assert ratio.min() >= (1 - 1e-9) / sv[0] ** 2
+    assert ratio.max() <= (1 + 1e-9) / sv[-1] ** 2
+    assert max(sv[0] ** 2 - 1, 1 - sv[-1] ** 2) < 0.5
+
+
 def test_injective_sketch_gives_exact_scores():
     n, d, r = 60, 5, 1 << 16
     for seed in range(100):

@@ -84,3 +84,65 @@ def test_scaled_sketch_is_exact():
     a = sk.countsketch_dense(x * dsc, 8, 64)
     b = sk.countsketch_dense(x, 8, 64) * dsc
     assert np.array_equal(a, b)
+
+
+# ---- OSNAP -------------------------------------------------------------------
+def _explicit_osnap(seed, r, s, n):
+    """S as a dense r x n matrix, built entry by entry from the hashes."""
+    bucket, sign = streams.osnap_bucket_sign(seed, r, s, np.arange(n))
+    m = np.zeros((r, n))
+    for j in range(s):
+        for i in range(n):
+            m[bucket[j, i], i] += sign[j, i] / math.sqrt(s)
+    return m
+
+
+def test_osnap_with_one_nonzero_is_countsketch():
+    x = synth.config0(n=700, d=9, seed=4)
+    assert np.array_equal(sk.osnap_dense(x, 21, 96, 1),
+                          sk.countsketch_dense(x, 21, 96))
+
+
+def test_osnap_equals_explicit_product():
+    rng = np.random.default_rng(1)
+    # small integers and s = 4 (1/sqrt(s) = 0.5): every step is exact
+    x = rng.integers(-50, 50, (300, 7)).astype(np.float64)
+    assert np.array_equal(sk.osnap_dense(x, 13, 64, 4),
+                          _explicit_osnap(13, 64, 4, 300) @ x)
+    y = rng.standard_normal((257, 5))
+    np.testing.assert_allclose(sk.osnap_dense(y, 14, 90, 3),
+                               _explicit_osnap(14, 90, 3, 257) @ y,
+                               rtol=1e-13, atol=1e-13)
+
+
+def test_osnap_columns_have_one_entry_per_block():
+    r, s, n = 120, 3, 400
+    m = _explicit_osnap(7, r, s, n)
+    b = r // s
+    for i in range(n):
+        nz = np.nonzero(m[:, i])[0]
+        assert len(nz) == s
+        assert sorted(nz // b) == list(range(s))
+        np.testing.assert_allclose(np.abs(m[nz, i]), 1 / math.sqrt(s),
+                                   rtol=1e-15)
+        assert abs(np.dot(m[:, i], m[:, i]) - 1.0) < 1e-14
+
+
+def test_osnap_is_unbiased_embedding():
+    x = np.random.default_rng(3).standard_normal(64)
+    vals = [np.sum(sk.osnap_dense(x[:, None], seed, 32, 2) ** 2)
+            for seed in range(400)]
+    # ||S x||^2 is unbiased for ||x||^2; 400 draws, 5 standard errors
+    m, sd = np.mean(vals), np.std(vals) / math.sqrt(len(vals))
+    assert abs(m - np.dot(x, x)) < 5 * sd
+
+
+def test_osnap_csr_equals_dense():
+    c = synth.text_like_csr(400, 60, seed=2)
+    np.testing.assert_array_equal(sk.osnap_csr(c, 5, 48, 2),
+                                  sk.osnap_dense(c.to_dense(), 5, 48, 2))
+
+
+def test_osnap_rejects_s_not_dividing_r():
+    with pytest.raises(ValueError):
+        streams.osnap_bucket_sign(1, 10, 3, np.arange(5))
