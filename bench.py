@@ -288,6 +288,12 @@ def main() -> int:
                     default="image",
                     help="image: the image-like single-job workload (default); "
                          "serving: a Poisson stream of mixed jobs")
+    ap.add_argument("--sketch", choices=("countsketch", "osnap"),
+                    default="countsketch",
+                    help="image: the hashed sketch (OSNAP: --nnz nonzeros per "
+                         "column of S)")
+    ap.add_argument("--nnz", type=int, default=2,
+                    help="image, --sketch osnap: nonzeros per column of S")
     ap.add_argument("--rates", default="50,200,800",
                     help="serving: arrival rates in jobs/s")
     ap.add_argument("--jobs", type=int, default=1024,
@@ -329,8 +335,13 @@ def main() -> int:
     perm = torch.empty(N, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
 
+    osnap = args.sketch == "osnap"
+    kind = slso.OSNAP if osnap else slso.COUNTSKETCH
+    nnz = args.nnz if osnap else 0
+
     def step():
-        _, info = ctx.leverage(x, SEED, R, K, out=scores, stream=stream)
+        _, info = ctx.leverage(x, SEED, R, K, out=scores, stream=stream,
+                               sketch=kind, nnz=nnz)
         ctx.order(scores, out=perm, stream=stream)
         return info
 
@@ -395,8 +406,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "image-like dense FP32 X (n=60000, d=784, "
                                "values in [0,1], rank 50 + noise, 10 clusters); "
-                               "CountSketch r=16384, FP64 QR, k=64, scores + "
-                               "dec ordering",
+                               + (f"OSNAP (s={nnz}) " if osnap else "CountSketch ")
+                               + "r=16384, FP64 QR, k=64, scores + dec ordering",
                    "n": N, "d": D, "r": R, "k": K, "seed": SEED,
                    "rank": int(info["rank"])},
         "perm_matches_stable_sort": perm_ok,
@@ -425,7 +436,9 @@ def main() -> int:
         reps, t_cpu, ref = 0, 0.0, None
         while reps < 3 and t_cpu < 20.0:
             tc = time.perf_counter()
-            ref = olv.sketched_leverage(x_host, SEED, R, K)
+            ref = olv.sketched_leverage(x_host, SEED, R, K,
+                                        kind="osnap" if osnap else "countsketch",
+                                        nnz=max(nnz, 1))
             oorder.dec_order(ref["scores"].astype(np.float32))
             t_cpu += time.perf_counter() - tc
             reps += 1

@@ -65,7 +65,12 @@ typedef enum { SLSO_DENSE = 0, SLSO_CSR = 1 } slso_format;
 
 typedef enum {
   SLSO_COUNTSKETCH = 0, /* one signed nonzero per column of S (Sec. 2.1)     */
-  SLSO_GAUSSIAN = 1     /* S = G / sqrt(r), G i.i.d. N(0, 1) (Sec. 2.1)      */
+  SLSO_GAUSSIAN = 1,    /* S = G / sqrt(r), G i.i.d. N(0, 1) (Sec. 2.1)      */
+  SLSO_OSNAP = 2        /* s = nnz_per_col signed nonzeros +-1/sqrt(s) per   */
+                        /* column of S, one in each of s blocks of r / s     */
+                        /* rows (the sparse embedding of Sec. 2.1, hashed as */
+                        /* in Sec. 3.1.2); hash 0 is the CountSketch's, so   */
+                        /* s = 1 gives the CountSketch                       */
 } slso_sketch_kind;
 
 /* An n x d input matrix. Dense: ``values`` (device) holds n rows of ``ld``
@@ -97,6 +102,9 @@ typedef struct {
   double rank_tol;  /* relative threshold of Algorithm 3 step 3; 0 selects   */
                     /* the default 1e-10; a negative value disables          */
                     /* truncation (R^{-1} is used whatever its conditioning) */
+  int32_t nnz_per_col; /* OSNAP nonzeros per column of S, 1..16 dividing r;  */
+                       /* 0 selects 2; ignored by the other sketches         */
+  int32_t reserved;    /* must be 0                                          */
 } slso_options;
 
 /* Host-side report of one leverage computation. */
@@ -153,7 +161,11 @@ const char* slso_last_error(const slso_ctx* ctx);
  * BF16 and FP8 input); products on MFMA, sums in FP32 within chunks of at
  * most 65536 rows and in FP64 across chunks, in a fixed order
  * (deterministic); the 1/sqrt(r) (and for FP8 the column scale) is applied
- * once to the FP64 sum. EUNSUPPORTED: Gaussian with F64 or CSR input. */
+ * once to the FP64 sum. OSNAP (same inputs as CountSketch): for every hash
+ * j < s, sx[h_j(i)] += s_j(i) x_i in ascending i (each sketch row belongs to
+ * one hash's block), then every sum is multiplied once by 1/sqrt(s) in FP64.
+ * EUNSUPPORTED: Gaussian with F64 or CSR input. EINVAL: OSNAP with
+ * nnz_per_col outside 1..16 or not dividing r. */
 int slso_sketch(slso_ctx* ctx, const slso_matrix* X, uint64_t seed, int64_t r,
                 const slso_options* opt, double* sx, void* stream);
 

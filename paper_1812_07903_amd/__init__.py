@@ -26,7 +26,7 @@ EINVAL, ENOMEM, ENONFINITE, EDEVICE, EUNSUPPORTED = -1, -2, -3, -4, -5
 # slso_dtype / slso_format / slso_sketch_kind
 F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
 DENSE, CSR = 0, 1
-COUNTSKETCH, GAUSSIAN = 0, 1
+COUNTSKETCH, GAUSSIAN, OSNAP = 0, 1, 2
 STREAM_GAUSS_S, STREAM_PI2 = 3, 4
 
 EXPORTED = (
@@ -64,7 +64,8 @@ class _Matrix(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("sketch", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("rank_tol", ctypes.c_double)]
+                ("rank_tol", ctypes.c_double),
+                ("nnz_per_col", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -278,13 +279,13 @@ class Context:
 
     # ---- hot path ----------------------------------------------------------
     def sketch(self, x, seed: int, r: int, sketch: int = COUNTSKETCH, out=None,
-               stream=None):
+               stream=None, nnz: int = 0):
         import torch
         if out is None:
             out = torch.empty((r, _cols(x)), dtype=torch.float64,
                               device=_device(x))
         m = _matrix(x)
-        opt = _Options(sketch, 0, 0.0)
+        opt = _Options(sketch, 0, 0.0, nnz, 0)
         _check(load_library().slso_sketch(self._h, ctypes.byref(m), seed, r,
                                           ctypes.byref(opt), _ptr(out),
                                           _stream(stream)), self._h)
@@ -292,13 +293,14 @@ class Context:
 
     def leverage(self, x, seed: int, r: int, k: int, sketch: int = COUNTSKETCH,
                  refine: bool = False, rank_tol: float = 0.0, out=None,
-                 stream=None):
-        """Scores (float32 device tensor) and the rank-decision info dict."""
+                 stream=None, nnz: int = 0):
+        """Scores (float32 device tensor) and the rank-decision info dict.
+        ``nnz``: OSNAP nonzeros per column of S (0 selects 2)."""
         import torch
         if out is None:
             out = torch.empty(_rows(x), dtype=torch.float32, device=_device(x))
         m = _matrix(x)
-        opt = _Options(sketch, 1 if refine else 0, rank_tol)
+        opt = _Options(sketch, 1 if refine else 0, rank_tol, nnz, 0)
         info = _Info()
         st = _check(load_library().slso_leverage(
             self._h, ctypes.byref(m), seed, r, k, ctypes.byref(opt), _ptr(out),
@@ -357,10 +359,11 @@ def _info_dict(info, st):
 
 
 def workspace_size(x, r: int, k: int, sketch: int = COUNTSKETCH,
-                   refine: bool = False, rank_tol: float = 0.0) -> int:
+                   refine: bool = False, rank_tol: float = 0.0,
+                   nnz: int = 0) -> int:
     """Device workspace bytes a context allocates for leverage + order."""
     m = _matrix(x)
-    opt = _Options(sketch, 1 if refine else 0, rank_tol)
+    opt = _Options(sketch, 1 if refine else 0, rank_tol, nnz, 0)
     out = ctypes.c_size_t()
     _check(load_library().slso_workspace_size(ctypes.byref(m), r, k,
                                               ctypes.byref(opt),
@@ -391,7 +394,7 @@ class Server:
 
     def submit(self, x, seed: int, r: int, k: int, sketch: int = COUNTSKETCH,
                refine: bool = False, rank_tol: float = 0.0, order: bool = True,
-               scores=None, perm=None) -> Ticket:
+               scores=None, perm=None, nnz: int = 0) -> Ticket:
         """Queue a job; X must already hold its values (synchronise first)."""
         import torch
         n = _rows(x)
@@ -402,7 +405,7 @@ class Server:
         job = _Job()
         job.X = _matrix(x)
         job.seed, job.r, job.k = seed, r, k
-        job.opt = _Options(sketch, 1 if refine else 0, rank_tol)
+        job.opt = _Options(sketch, 1 if refine else 0, rank_tol, nnz, 0)
         job.scores = scores.data_ptr()
         job.perm = perm.data_ptr() if order else None
         tid = ctypes.c_int64()

@@ -29,6 +29,20 @@ struct HashCoeffs {
   uint64_t a[4];  // a0 + a1 i + a2 i^2 + a3 i^3 mod 2^61-1
 };
 
+// OSNAP hash j (block construction, at most kMaxOsnapNnz nonzeros per column
+// of S): hash 0 takes the CountSketch streams, hash j >= 1 streams 16 + 2j
+// (bucket) and 17 + 2j (sign).
+constexpr int kMaxOsnapNnz = 16;
+inline uint32_t osnap_bucket_stream(int j) {
+  return j == 0 ? kStreamBucket : static_cast<uint32_t>(16 + 2 * j);
+}
+inline uint32_t osnap_sign_stream(int j) {
+  return j == 0 ? kStreamSign : static_cast<uint32_t>(17 + 2 * j);
+}
+struct OsnapCoeffs {
+  HashCoeffs hb[kMaxOsnapNnz], hs[kMaxOsnapNnz];
+};
+
 // ---- host: coefficient derivation ----------------------------------------
 inline uint64_t sm64_mix(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;

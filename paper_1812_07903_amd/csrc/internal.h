@@ -60,6 +60,11 @@ int ctx_release_workspace(::slso_ctx* c);
 void launch_hash_pack(const HashCoeffs& hb, const HashCoeffs& hs, int64_t r,
                       int64_t row0, int64_t n, uint32_t* keys, uint32_t* vals,
                       hipStream_t s);
+// OSNAP entries, nnz per row: entry e = j n + i (hash j, row i) gets
+// keys[e] = j (r / nnz) + (P_1j(i) mod (r / nnz)), vals[e] = i | (sign << 31).
+void launch_hash_pack_osnap(const OsnapCoeffs& h, int nnz, int64_t r,
+                            int64_t n, uint32_t* keys, uint32_t* vals,
+                            hipStream_t s);
 void launch_hash_out(const HashCoeffs& hb, const HashCoeffs& hs, int64_t r,
                      int64_t row0, int64_t n, int32_t* bucket, int8_t* sign,
                      hipStream_t s);
@@ -94,19 +99,21 @@ void launch_colscale(const uint64_t* colmax_bits, int64_t d, double* dscale,
 // out[j] = a[j] * b[j] (a NULL: 1)
 void launch_mul_scale(const double* a, const float* b, int64_t d, double* out,
                       hipStream_t s);
-// sx[b] = dscale * sum_{rows in bucket b, ascending} sign * x_row (FP8: codes;
-// the caller folds the column scales into dscale)
+// sx[b] = (sum_{entries of bucket b, ascending row} sign * x_row) * sscale *
+// dscale (FP8: codes; the caller folds the column scales into dscale;
+// sscale: 1 for CountSketch, 1/sqrt(nnz) for OSNAP)
 void launch_countsketch(const void* x, int dtype, int format, int64_t n,
                         int64_t d, int64_t ld, const int64_t* row_ptr,
                         const int32_t* col_idx, const float* col_scale,
                         const float* row_scale, const uint32_t* sorted_vals,
                         const int32_t* offsets, int64_t r,
-                        const double* dscale, double* sx, hipStream_t s);
+                        const double* dscale, double* sx, hipStream_t s,
+                        double sscale = 1.0);
 
 // CountSketch and column equilibration in one pass over dense F32 / BF16 /
-// FP8 input (ld and the base address multiples of 4 elements): sx[b] = cs *
-// sum_{rows in bucket b, ascending} sign * x_row (cs: the FP8 column scales,
-// else 1) WITHOUT the equilibration D, which the consumer applies (qr_factor's
+// FP8 input (ld and the base address multiples of 4 elements): sx[b] =
+// (sum_{entries of bucket b, ascending row} sign * x_row) * sscale * cs (cs:
+// the FP8 column scales, else 1) WITHOUT the equilibration D, which the consumer applies (qr_factor's
 // dsc), and dscale = D from the column max-abs values (times |cs|), as
 // launch_colmax + launch_colscale would give. parts: countsketch_colmax_groups(r)
 // * d floats of scratch. False, with nothing launched, when the input does
@@ -118,7 +125,7 @@ bool launch_countsketch_colmax(const void* x, int dtype, int64_t d, int64_t ld,
                                const uint32_t* sorted_vals,
                                const int32_t* offsets, int64_t r, float* parts,
                                int* nonfinite, double* dscale, double* sx,
-                               hipStream_t s);
+                               hipStream_t s, double sscale = 1.0);
 
 // ---- QR (k_qr.hip) -----------------------------------------------------------
 // A second stream and two events that let the QR overlap one panel's

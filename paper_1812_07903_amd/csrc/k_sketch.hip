@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(256)
                              const uint32_t* __restrict__ sorted_vals,
                              const int32_t* __restrict__ off, int64_t r,
                              const double* __restrict__ dscale,
-                             double* __restrict__ sx) {
+                             double* __restrict__ sx, double sscale) {
   const int lane = threadIdx.x & 63;
   const int64_t b = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
   if (b >= r) return;
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t c = c0 + lane + 64 * u;
-      if (c < d) sx[b * d + c] = acc[u] * (dscale ? dscale[c] : 1.0);
+      if (c < d) sx[b * d + c] = acc[u] * sscale * (dscale ? dscale[c] : 1.0);
     }
   }
 }
@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(256)
                            const uint32_t* __restrict__ sorted_vals,
                            const int32_t* __restrict__ off, int64_t r,
                            const double* __restrict__ dscale,
-                           double* __restrict__ sx) {
+                           double* __restrict__ sx, double sscale) {
   __shared__ double acc_all[4][kCsrChunk];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(256)
       }
     }
     for (int64_t c = c0 + lane; c < c1; c += 64)
-      sx[b * d + c] = acc[c - c0] * (dscale ? dscale[c] : 1.0);
+      sx[b * d + c] = acc[c - c0] * sscale * (dscale ? dscale[c] : 1.0);
   }
 }
 
@@ -203,8 +203,8 @@ __global__ void mul_scale_kernel(const double* __restrict__ a,
 // signed FP64 sums are those of countsketch_dense_kernel, in the same order,
 // times the FP8 column scale; the power-of-two equilibration D is left to the
 // consumer (scaling by a power of two is exact, so the consumer sees the same
-// numbers). Every row is read once, so the column max-abs values come from
-// the same loads: per workgroup into parts[blockIdx][col], reduced by
+// numbers); OSNAP sums are multiplied once by 1/sqrt(nnz). Every row is read
+// (nnz times for OSNAP), so the column max-abs values come from the same loads: per workgroup into parts[blockIdx][col], reduced by
 // colmax_parts_kernel.
 constexpr int kSkChunk = 1024;
 constexpr int kSkMaxGroups = 1024;
@@ -245,7 +245,7 @@ __global__ void __launch_bounds__(256)
                               const uint32_t* __restrict__ sorted_vals,
                               const int32_t* __restrict__ off, int64_t r,
                               float* __restrict__ parts, int* nonfinite,
-                              double* __restrict__ sx) {
+                              double* __restrict__ sx, double sscale) {
   constexpr bool kFp8 = sizeof(T) == 1;  // codes times the column scale
   __shared__ float wmax[4][kSkChunk];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -329,7 +329,8 @@ __global__ void __launch_bounds__(256)
         for (int e = 0; e < 4; ++e) {
           const int64_t c = c0 + 4 * (lane + 64 * u) + e;
           if (c < d)
-            sx[b * d + c] = kFp8 ? acc[4 * u + e] * cs[4 * u + e] : acc[4 * u + e];
+            sx[b * d + c] = kFp8 ? acc[4 * u + e] * sscale * cs[4 * u + e]
+                                 : acc[4 * u + e] * sscale;
         }
     }
 #pragma unroll
@@ -471,7 +472,8 @@ void launch_countsketch(const void* x, int dtype, int format, int64_t n,
                         const int32_t* col_idx, const float* col_scale,
                         const float* row_scale, const uint32_t* sorted_vals,
                         const int32_t* offsets, int64_t r,
-                        const double* dscale, double* sx, hipStream_t s) {
+                        const double* dscale, double* sx, hipStream_t s,
+                        double sscale) {
   (void)n;
   (void)col_scale;
   (void)row_scale;
@@ -480,7 +482,7 @@ void launch_countsketch(const void* x, int dtype, int format, int64_t n,
     prof_begin(kKSketch, s);
     countsketch_csr_kernel<<<grid, 256, 0, s>>>(
         row_ptr, col_idx, static_cast<const float*>(x), d, sorted_vals, offsets,
-        r, dscale, sx);
+        r, dscale, sx, sscale);
     prof_end(kKSketch, s);
     return;
   }
@@ -489,28 +491,28 @@ void launch_countsketch(const void* x, int dtype, int format, int64_t n,
       prof_begin(kKSketch, s);
       countsketch_dense_kernel<double><<<grid, 256, 0, s>>>(
           static_cast<const double*>(x), d, ld, sorted_vals, offsets, r, dscale,
-          sx);
+          sx, sscale);
       prof_end(kKSketch, s);
       break;
     case 1:
       prof_begin(kKSketch, s);
       countsketch_dense_kernel<float><<<grid, 256, 0, s>>>(
           static_cast<const float*>(x), d, ld, sorted_vals, offsets, r, dscale,
-          sx);
+          sx, sscale);
       prof_end(kKSketch, s);
       break;
     case 2:
       prof_begin(kKSketch, s);
       countsketch_dense_kernel<uint16_t><<<grid, 256, 0, s>>>(
           static_cast<const uint16_t*>(x), d, ld, sorted_vals, offsets, r,
-          dscale, sx);
+          dscale, sx, sscale);
       prof_end(kKSketch, s);
       break;
     case 3:
       prof_begin(kKSketch, s);
       countsketch_dense_kernel<uint8_t><<<grid, 256, 0, s>>>(
           static_cast<const uint8_t*>(x), d, ld, sorted_vals, offsets, r,
-          dscale, sx);
+          dscale, sx, sscale);
       prof_end(kKSketch, s);
       break;
     default:
@@ -534,7 +536,7 @@ bool launch_countsketch_colmax(const void* x, int dtype, int64_t d, int64_t ld,
                                const uint32_t* sorted_vals,
                                const int32_t* offsets, int64_t r, float* parts,
                                int* nonfinite, double* dscale, double* sx,
-                               hipStream_t s) {
+                               hipStream_t s, double sscale) {
   if (!countsketch_colmax_ok(x, dtype, 0, ld) || d <= 0 || r <= 0) return false;
   const int64_t groups = countsketch_colmax_groups(r);
   const unsigned g = static_cast<unsigned>(groups);
@@ -545,11 +547,11 @@ bool launch_countsketch_colmax(const void* x, int dtype, int64_t d, int64_t ld,
     if (tail)                                                                   \
       countsketch_colmax_kernel<T, true><<<g, 256, 0, s>>>(                     \
           static_cast<const T*>(x), d, ld, CS, sorted_vals, offsets, r, parts, \
-          nonfinite, sx);                                                       \
+          nonfinite, sx, sscale);                                               \
     else                                                                        \
       countsketch_colmax_kernel<T, false><<<g, 256, 0, s>>>(                    \
           static_cast<const T*>(x), d, ld, CS, sorted_vals, offsets, r, parts, \
-          nonfinite, sx);                                                       \
+          nonfinite, sx, sscale);                                               \
   } while (0)
   if (dtype == 1)
     SLSO_CS_LAUNCH(float, nullptr);

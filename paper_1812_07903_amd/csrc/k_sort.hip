@@ -36,6 +36,18 @@ __global__ void hash_pack_kernel(HashCoeffs hb, HashCoeffs hs, uint64_t r,
   vals[i] = static_cast<uint32_t>(i) | (neg << 31);
 }
 
+__global__ void hash_pack_osnap_kernel(OsnapCoeffs h, int nnz, uint64_t b,
+                                       int64_t n, uint32_t* keys,
+                                       uint32_t* vals) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n * nnz) return;
+  const int j = static_cast<int>(e / n);
+  const uint64_t i = static_cast<uint64_t>(e - static_cast<int64_t>(j) * n);
+  keys[e] = static_cast<uint32_t>(static_cast<uint64_t>(j) * b + poly61(h.hb[j], i) % b);
+  const uint32_t neg = static_cast<uint32_t>(poly61(h.hs[j], i) & 1u);
+  vals[e] = static_cast<uint32_t>(i) | (neg << 31);
+}
+
 __global__ void hash_out_kernel(HashCoeffs hb, HashCoeffs hs, uint64_t r,
                                 int64_t row0, int64_t n, int32_t* bucket,
                                 int8_t* sign) {
@@ -244,6 +256,16 @@ void launch_hash_pack(const HashCoeffs& hb, const HashCoeffs& hs, int64_t r,
   prof_begin(kKHash, s);
   hash_pack_kernel<<<grid1(n, 256), 256, 0, s>>>(hb, hs, static_cast<uint64_t>(r),
                                                   row0, n, keys, vals);
+  prof_end(kKHash, s);
+}
+
+void launch_hash_pack_osnap(const OsnapCoeffs& h, int nnz, int64_t r,
+                            int64_t n, uint32_t* keys, uint32_t* vals,
+                            hipStream_t s) {
+  if (n <= 0 || nnz <= 0) return;
+  prof_begin(kKHash, s);
+  hash_pack_osnap_kernel<<<grid1(n * nnz, 256), 256, 0, s>>>(
+      h, nnz, static_cast<uint64_t>(r / nnz), n, keys, vals);
   prof_end(kKHash, s);
 }
 

@@ -258,29 +258,66 @@ void size_sketch_bufs(Sizer& z, int64_t n, int64_t r) {
   z.take<char>(radix_sort_scratch_bytes(n));
 }
 
-// Bucket partition of the rows (hash, stable sort by bucket, offsets): it
-// reads no input values.
-void enqueue_partition(int64_t n, uint64_t seed, int64_t r,
-                       const SketchBufs& b, hipStream_t s) {
-  const HashCoeffs hb = make_hash_coeffs(seed, kStreamBucket);
-  const HashCoeffs hs = make_hash_coeffs(seed, kStreamSign);
-  launch_hash_pack(hb, hs, r, 0, n, b.keys, b.vals, s);
-  radix_sort_pairs(b.keys, b.vals, b.keys_s, b.vals_s, b.keys_t, b.vals_t, n,
-                   bits_for(r), b.sort_ws, s);
-  launch_bucket_offsets(b.keys_s, n, r, b.off, s);
+// Nonzeros per column of S for the hashed sketches: 1 for CountSketch, the
+// option (default 2) for OSNAP, 0 for the Gaussian sketch.
+int sketch_nnz(const slso_options& o) {
+  if (o.sketch == SLSO_COUNTSKETCH) return 1;
+  if (o.sketch == SLSO_OSNAP) return o.nnz_per_col == 0 ? 2 : o.nnz_per_col;
+  return 0;
 }
-void enqueue_gather(const slso_matrix* X, int64_t r, const SketchBufs& b,
-                    const double* dscale, double* sx, hipStream_t s) {
+// 1 / sqrt(nnz), applied once to every FP64 sum of a hashed sketch
+double sketch_scale(int nnz) {
+  return nnz <= 1 ? 1.0 : 1.0 / std::sqrt(static_cast<double>(nnz));
+}
+int check_sketch_kind(slso_ctx* c, const slso_options& o, int64_t r) {
+  if (o.sketch != SLSO_COUNTSKETCH && o.sketch != SLSO_GAUSSIAN &&
+      o.sketch != SLSO_OSNAP)
+    return set_err(c, SLSO_EINVAL, "unknown sketch kind");
+  if (o.reserved != 0) return set_err(c, SLSO_EINVAL, "reserved must be 0");
+  if (o.sketch == SLSO_OSNAP) {
+    const int s = sketch_nnz(o);
+    if (s < 1 || s > kMaxOsnapNnz || r % s != 0)
+      return set_err(c, SLSO_EINVAL,
+                     "OSNAP needs 1 <= nnz_per_col <= 16 dividing r");
+  }
+  return SLSO_OK;
+}
+
+// Bucket partition of the rows (hash, stable sort by bucket, offsets) for
+// nnz entries per row (entry j n + i: hash j of row i): it reads no input
+// values. Entries of one bucket come from one hash, in ascending row order.
+void enqueue_partition(int64_t n, int nnz, uint64_t seed, int64_t r,
+                       const SketchBufs& b, hipStream_t s) {
+  if (nnz == 1) {
+    const HashCoeffs hb = make_hash_coeffs(seed, kStreamBucket);
+    const HashCoeffs hs = make_hash_coeffs(seed, kStreamSign);
+    launch_hash_pack(hb, hs, r, 0, n, b.keys, b.vals, s);
+  } else {
+    OsnapCoeffs h{};
+    for (int j = 0; j < nnz; ++j) {
+      h.hb[j] = make_hash_coeffs(seed, osnap_bucket_stream(j));
+      h.hs[j] = make_hash_coeffs(seed, osnap_sign_stream(j));
+    }
+    launch_hash_pack_osnap(h, nnz, r, n, b.keys, b.vals, s);
+  }
+  const int64_t ne = n * nnz;
+  radix_sort_pairs(b.keys, b.vals, b.keys_s, b.vals_s, b.keys_t, b.vals_t, ne,
+                   bits_for(r), b.sort_ws, s);
+  launch_bucket_offsets(b.keys_s, ne, r, b.off, s);
+}
+void enqueue_gather(const slso_matrix* X, int nnz, int64_t r,
+                    const SketchBufs& b, const double* dscale, double* sx,
+                    hipStream_t s) {
   launch_countsketch(X->values, X->dtype, X->format, X->n, X->d, X->ld,
                      X->row_ptr, X->col_idx, X->col_scale, X->row_scale,
-                     b.vals_s, b.off, r, dscale, sx, s);
+                     b.vals_s, b.off, r, dscale, sx, s, sketch_scale(nnz));
 }
-// Bucket partition + CountSketch into sx (r x d), optionally column-scaled.
-void enqueue_countsketch(const slso_matrix* X, uint64_t seed, int64_t r,
-                         const SketchBufs& b, const double* dscale, double* sx,
-                         hipStream_t s) {
-  enqueue_partition(X->n, seed, r, b, s);
-  enqueue_gather(X, r, b, dscale, sx, s);
+// Bucket partition + hashed sketch into sx (r x d), optionally column-scaled.
+void enqueue_countsketch(const slso_matrix* X, int nnz, uint64_t seed,
+                         int64_t r, const SketchBufs& b, const double* dscale,
+                         double* sx, hipStream_t s) {
+  enqueue_partition(X->n, nnz, seed, r, b, s);
+  enqueue_gather(X, nnz, r, b, dscale, sx, s);
 }
 
 size_t gemm_partial_bytes(const slso_matrix* X, int64_t r, bool gauss,
@@ -294,12 +331,13 @@ size_t gemm_partial_bytes(const slso_matrix* X, int64_t r, bool gauss,
 // Workspace of slso_leverage; the arena in slso_leverage takes the same
 // buffers in the same order.
 size_t leverage_ws_bytes(const slso_matrix* X, int64_t r, int64_t k,
-                         bool gauss, bool refine) {
+                         int nnz, bool refine) {
   const int64_t n = X->n, d = X->d;
   const int64_t kk = k == 0 ? d : k;
+  const bool gauss = nnz == 0;
   Sizer z;
   if (!gauss) {
-    size_sketch_bufs(z, n, r);
+    size_sketch_bufs(z, n * nnz, r);
     z.take<float>(countsketch_colmax_groups(r) * d);  // column maxima parts
   }
   z.take<uint64_t>(d);             // colmax bits
@@ -337,8 +375,7 @@ int check_leverage(slso_ctx* c, const slso_matrix* X, int64_t r, int64_t k,
   if (k < 0) return set_err(c, SLSO_EINVAL, "k must be >= 0");
   *o = slso_options{};
   if (opt) *o = *opt;
-  if (o->sketch != SLSO_COUNTSKETCH && o->sketch != SLSO_GAUSSIAN)
-    return set_err(c, SLSO_EINVAL, "unknown sketch kind");
+  if ((st = check_sketch_kind(c, *o, r))) return st;
   if (o->refine != 0 && o->refine != 1)
     return set_err(c, SLSO_EINVAL, "refine must be 0 or 1");
   if ((o->sketch == SLSO_GAUSSIAN || o->refine == 1) && !mfma_input(X))
@@ -443,17 +480,19 @@ int slso_sketch(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   if (r < X->d || r >= (static_cast<int64_t>(1) << 31))
     return set_err(c, SLSO_EINVAL, "need d <= r < 2^31");
   if (!sx) return set_err(c, SLSO_EINVAL, "sx is NULL");
-  const int kind = opt ? opt->sketch : SLSO_COUNTSKETCH;
-  if (kind != SLSO_COUNTSKETCH && kind != SLSO_GAUSSIAN)
-    return set_err(c, SLSO_EINVAL, "unknown sketch kind");
+  slso_options o{};
+  if (opt) o = *opt;
+  if ((st = check_sketch_kind(c, o, r))) return st;
+  const int kind = o.sketch;
+  const int nnz = sketch_nnz(o);
   if (kind == SLSO_GAUSSIAN && !mfma_input(X))
     return set_err(c, SLSO_EUNSUPPORTED,
                    "the Gaussian sketch takes dense F32, BF16 or FP8 input");
   SLSO_HIP(c, hipSetDevice(c->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   Sizer z;
-  if (kind == SLSO_COUNTSKETCH) {
-    size_sketch_bufs(z, X->n, r);
+  if (nnz > 0) {
+    size_sketch_bufs(z, X->n * nnz, r);
     z.take<double>(X->d);
   } else {
     z.take<char>(gauss_partial_bytes(X->n, r, X->d));
@@ -461,12 +500,12 @@ int slso_sketch(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   if ((st = ensure_ws(c, z.off))) return st;
   WsMark mark_{c, s};
   Arena a{static_cast<char*>(c->ws)};
-  if (kind == SLSO_COUNTSKETCH) {
-    SketchBufs b = take_sketch_bufs(a, X->n, r);
+  if (nnz > 0) {
+    SketchBufs b = take_sketch_bufs(a, X->n * nnz, r);
     double* cs = a.take<double>(X->d);
     if (X->dtype == SLSO_FP8_E4M3)
       launch_mul_scale(nullptr, X->col_scale, X->d, cs, s);
-    enqueue_countsketch(X, seed, r, b,
+    enqueue_countsketch(X, nnz, seed, r, b,
                         X->dtype == SLSO_FP8_E4M3 ? cs : nullptr, sx, s);
   } else {
     float* part = a.take<float>(gauss_partial_bytes(X->n, r, X->d) / 4);
@@ -599,6 +638,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   int st = check_leverage(c, X, r, k, opt, &o);
   if (st) return st;
   const bool gauss = o.sketch == SLSO_GAUSSIAN;
+  const int nnz = sketch_nnz(o);
   const bool refine = o.refine == 1;
   const bool fp8 = X->dtype == SLSO_FP8_E4M3;
   const double tol = o.rank_tol == 0.0 ? 1e-10 : o.rank_tol;
@@ -609,14 +649,14 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
 
   const size_t gemm_part = gemm_partial_bytes(X, r, gauss, refine);
   Sizer z;
-  z.off = leverage_ws_bytes(X, r, k, gauss, refine);
+  z.off = leverage_ws_bytes(X, r, k, nnz, refine);
   if ((st = ensure_ws(c, z.off))) return st;
   WsMark mark_{c, s};
   Arena a{static_cast<char*>(c->ws)};
   SketchBufs sb{};
   float* cparts = nullptr;
   if (!gauss) {
-    sb = take_sketch_bufs(a, n, r);
+    sb = take_sketch_bufs(a, n * nnz, r);
     cparts = a.take<float>(countsketch_colmax_groups(r) * d);
   }
   uint64_t* colmax = a.take<uint64_t>(d);
@@ -651,7 +691,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   if (side_partition) {
     SLSO_HIP(c, hipEventRecord(c->qs.factored, s));
     SLSO_HIP(c, hipStreamWaitEvent(c->qs.side, c->qs.factored, 0));
-    enqueue_partition(n, seed, r, sb, c->qs.side);
+    enqueue_partition(n, nnz, seed, r, sb, c->qs.side);
     SLSO_HIP(c, hipEventRecord(c->qs.bulk_done, c->qs.side));
   }
   // 1. column equilibration D (power of two) from column max-abs of X
@@ -684,18 +724,19 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
       if (side_partition)
         (void)hipStreamWaitEvent(s, c->qs.bulk_done, 0);
       else
-        enqueue_partition(n, seed, r, sb, s);
+        enqueue_partition(n, nnz, seed, r, sb, s);
       partitioned = true;
     }
     if (fuse && !fused_done) {
       (void)launch_countsketch_colmax(X->values, X->dtype, d, X->ld,
                                       X->col_scale, sb.vals_s, sb.off, r,
-                                      cparts, flags, dscale, sx, s);
+                                      cparts, flags, dscale, sx, s,
+                                      sketch_scale(nnz));
       if (fp8) launch_mul_scale(dscale, X->col_scale, d, eff, s);
       fused_done = true;
       unscaled = true;
     } else {
-      enqueue_gather(X, r, sb, rowfac, sx, s);
+      enqueue_gather(X, nnz, r, sb, rowfac, sx, s);
     }
   };
   // post(r_formed): rank-screen statistics of the R just formed (when
@@ -831,7 +872,7 @@ int slso_workspace_size(const slso_matrix* X, int64_t r, int64_t k,
   const int st = check_leverage(nullptr, X, r, k, opt, &o);
   if (st) return st;
   *bytes = ws_alloc_bytes(std::max(
-      leverage_ws_bytes(X, r, k, o.sketch == SLSO_GAUSSIAN, o.refine == 1),
+      leverage_ws_bytes(X, r, k, sketch_nnz(o), o.refine == 1),
       order_ws_bytes(X->n)));
   return SLSO_OK;
 }

@@ -73,8 +73,8 @@ def _mat(n, d, dtype=slso.F32, fmt=slso.DENSE, col_scale=None):
     return m
 
 
-def _ws(lib, m, r, k, sketch=slso.COUNTSKETCH, refine=0):
-    opt = slso._Options(sketch, refine, 0.0)
+def _ws(lib, m, r, k, sketch=slso.COUNTSKETCH, refine=0, nnz=0, reserved=0):
+    opt = slso._Options(sketch, refine, 0.0, nnz, reserved)
     out = ctypes.c_size_t()
     st = lib.slso_workspace_size(ctypes.byref(m), r, k, ctypes.byref(opt),
                                  ctypes.byref(out))
@@ -93,6 +93,26 @@ def test_workspace_size_is_a_host_computation(lib):
     st3, b3 = _ws(lib, _mat(4000, 512, slso.BF16), 2048, 64,
                   sketch=slso.GAUSSIAN, refine=1)
     assert st3 == slso.OK and b3 >= 2048 * 512 * 4  # split-K partial sums
+
+
+def test_workspace_size_osnap(lib):
+    n, d, r, k = 60000, 784, 16384, 64
+    _, b1 = _ws(lib, _mat(n, d), r, k)
+    st, b2 = _ws(lib, _mat(n, d), r, k, sketch=slso.OSNAP)       # 2 per column
+    assert st == slso.OK and b2 >= b1 + 6 * n * 4 - (2 << 20)
+    st, b4 = _ws(lib, _mat(n, d), r, k, sketch=slso.OSNAP, nnz=4)
+    assert st == slso.OK and b4 >= b2 + 12 * n * 4 - (2 << 20)
+    assert _ws(lib, _mat(n, d), r, k, sketch=slso.OSNAP, nnz=1)[1] >= b1
+
+
+def test_osnap_argument_errors(lib):
+    m = _mat(100, 10)
+    assert _ws(lib, m, 16, 4, sketch=slso.OSNAP, nnz=3)[0] == slso.EINVAL   # 3 does not divide 16
+    assert _ws(lib, m, 32, 4, sketch=slso.OSNAP, nnz=32)[0] == slso.EINVAL  # above 16
+    assert _ws(lib, m, 16, 4, sketch=slso.OSNAP, nnz=-1)[0] == slso.EINVAL
+    assert _ws(lib, m, 16, 4, reserved=1)[0] == slso.EINVAL
+    assert _ws(lib, m, 16, 4, sketch=3)[0] == slso.EINVAL
+    assert _ws(lib, m, 16, 4, sketch=slso.OSNAP, nnz=16)[0] == slso.OK
 
 
 def test_workspace_size_argument_errors(lib):

@@ -164,6 +164,16 @@ def test_countsketch_leverage_strided_rows(slso, ctx, kind, d, pad):
                    ref["scores"]) < 1e-5
 
 
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+def test_osnap_leverage_reduced_precision(slso, ctx, kind):
+    x64 = synth.config0(n=20000, d=64, seed=24)
+    xin, xval, _ = as_input(slso, x64, kind)
+    got, info = ctx.leverage(xin, 5, 4096, 32, sketch=slso.OSNAP, nnz=4)
+    ref = olv.sketched_leverage(xval, 5, 4096, 32, kind="osnap", nnz=4)
+    assert info["rank"] == ref["rank"]
+    assert _report(f"osnap lev {kind}", host(got), ref["scores"]) < 1e-5
+
+
 # ---- refinement ---------------------------------------------------------------------
 @pytest.fixture(scope="module")
 def precision_case():

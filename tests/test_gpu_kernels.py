@@ -125,6 +125,41 @@ def test_countsketch_csr_bit_exact(slso, ctx, n, d, r):
     assert np.array_equal(sx, osk.countsketch_csr(c, 8, r))
 
 
+# ---- OSNAP ---------------------------------------------------------------------
+@pytest.mark.parametrize("n,d,r,nnz", [(5000, 64, 512, 2), (3001, 33, 510, 3),
+                                       (2000, 70, 1024, 4), (1, 1, 16, 16),
+                                       (4000, 48, 256, 1)])
+def test_osnap_dense_f64_bit_exact(slso, ctx, n, d, r, nnz):
+    """S X with nnz signed nonzeros per column of S: FP64 sums in ascending
+    row order per sketch row, times 1/sqrt(nnz) once."""
+    x = synth.config0(n=n, d=d, seed=n + nnz) if n > 1 else np.ones((1, 1))
+    sx = host(ctx.sketch(dev(x), 17, r, sketch=slso.OSNAP, nnz=nnz))
+    assert np.array_equal(sx, osk.osnap_dense(x, 17, r, nnz))
+
+
+def test_osnap_one_nonzero_is_countsketch(slso, ctx):
+    x = synth.image_like(3000, 100, seed=3)
+    a = host(ctx.sketch(dev(x), 9, 1024, sketch=slso.OSNAP, nnz=1))
+    assert np.array_equal(a, host(ctx.sketch(dev(x), 9, 1024)))
+
+
+def test_osnap_f32_and_csr_bit_exact(slso, ctx):
+    x = synth.image_like(5000, 784, seed=5)
+    sx = host(ctx.sketch(dev(x), 6, 2048, sketch=slso.OSNAP, nnz=2))
+    assert np.array_equal(sx, osk.osnap_dense(x, 6, 2048, 2))
+    c = synth.text_like_csr(20000, 1500, density=0.01, seed=8)
+    sxc = host(ctx.sketch(csr_dev(slso, c), 8, 2048, sketch=slso.OSNAP, nnz=4))
+    assert np.array_equal(sxc, osk.osnap_csr(c, 8, 2048, 4))
+
+
+def test_osnap_rejects_bad_nnz(slso, ctx):
+    x = dev(synth.config0(n=500, d=8, seed=1))
+    for nnz, r in ((3, 64), (17, 68), (-2, 64)):
+        with pytest.raises(slso.SlsoError) as ei:
+            ctx.sketch(x, 1, r, sketch=slso.OSNAP, nnz=nnz)
+        assert ei.value.status == slso.EINVAL
+
+
 # ---- QR ------------------------------------------------------------------------
 @pytest.mark.parametrize("m,d", [(64, 64), (100, 37), (256, 32), (257, 33),
                                  (1000, 96), (3000, 200), (5000, 64),

@@ -100,6 +100,32 @@ def test_config1_ragged_small(slso, ctx):
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("d,nnz", [(128, 2), (130, 4), (784, 2)])
+def test_osnap_leverage(slso, ctx, d, nnz):
+    """OSNAP sketch (nnz nonzeros per column of S), FP32 input: d = 128 and
+    784 take the CountSketch pass with the column maxima, d = 130 (row stride
+    not a multiple of 4) the two-pass path."""
+    n, r = (60000, 16384) if d == 784 else (6000, 2048)
+    x = synth.image_like(n, d, seed=d + nnz)
+    got, info = ctx.leverage(dev(x), 31, r, 32, sketch=slso.OSNAP, nnz=nnz)
+    ref = olv.sketched_leverage(x, 31, r, 32, kind="osnap", nnz=nnz)
+    assert info["rank"] == ref["rank"]
+    err, tau = _report(f"osnap d={d} s={nnz}", host(got), ref["scores"])
+    assert err < 1e-5
+
+
+def test_osnap_csr_leverage(slso, ctx):
+    c = synth.text_like_csr(30000, 800, seed=7)
+    xc = slso.CsrMatrix(c.n, c.d, dev(c.row_ptr.astype(np.int64)),
+                        dev(c.col_idx.astype(np.int32)),
+                        dev(c.val.astype(np.float32)))
+    got, info = ctx.leverage(xc, 12, 4096, 64, sketch=slso.OSNAP, nnz=2)
+    ref = olv.sketched_leverage(c, 12, 4096, 64, kind="osnap", nnz=2)
+    assert info["rank"] == ref["rank"]
+    err, _ = _report("osnap csr", host(got), ref["scores"])
+    assert err < 1e-5
+
+
 def test_csr_small(slso, ctx):
     c = synth.text_like_csr(30000, 800, seed=6)
     xc = slso.CsrMatrix(c.n, c.d, dev(c.row_ptr.astype(np.int64)),
