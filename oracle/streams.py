@@ -33,7 +33,15 @@ library) are:
   quadrant's centre rotated by +-sqrt(1/2)); cos for even i, sin for odd i.
   Reduced-precision inputs take it rounded to BF16 (ties to even).
 
-Stream ids: 1 bucket hash, 2 sign hash, 3 Gaussian sketch, 4 Pi_2.
+Stream ids: 1 bucket hash, 2 sign hash, 3 Gaussian sketch, 4 Pi_2,
+5 dec-swr draws, 6 dec-swor keys.
+
+* Sampling draws (the dec-swr / dec-swor policies of Algorithm 4 step 4):
+  for item t and epoch, one Philox4x32-10 block with counter (lo32(t),
+  hi32(t), epoch, stream) and key (lo32(seed), hi32(seed)). dec-swr takes the
+  53-bit integer ((w0 << 32) | w1) >> 11; dec-swor the FP32 unit
+  u = ((w0 >> 8) + 1) 2^-24 and E = -ln u with the FP32 logarithm of the
+  Gaussian generator.
 
 * OSNAP with s nonzeros per column (the sparse embedding the paper lists
   beside CountSketch in Sec. 2.1 and implements, like CountSketch, as hash
@@ -55,6 +63,8 @@ STREAM_BUCKET = 1
 STREAM_SIGN = 2
 STREAM_GAUSS_S = 3
 STREAM_PI2 = 4
+STREAM_SWR = 5
+STREAM_SWOR = 6
 
 
 def splitmix64_mix(z: int) -> int:
@@ -196,6 +206,16 @@ def gaussian_sketch_matrix(seed: int, r: int, n: int) -> np.ndarray:
     return gaussian(seed, STREAM_GAUSS_S, i, j)
 
 
+def sample_words(seed: int, stream: int, epoch: int, t):
+    """Philox words (w0, w1) of sampling item t (uint64 arrays)."""
+    t = np.asarray(t, dtype=np.uint64)
+    w0, w1, _, _ = philox4x32_10(t & np.uint64(MASK32), t >> np.uint64(32),
+                                 np.full(t.shape, epoch, np.uint64),
+                                 np.full(t.shape, stream, np.uint64),
+                                 seed & MASK32, (seed >> 32) & MASK32)
+    return w0, w1
+
+
 # --------------------------------------------------------------------------
 # FP32 Gaussian entries of the sketch matrix S (the reduced-precision path)
 # --------------------------------------------------------------------------
@@ -229,14 +249,16 @@ _SIN_T = [F32(1.0 / 362880.0), F32(-1.0 / 5040.0), F32(1.0 / 120.0),
           F32(-1.0 / 6.0)]
 
 
-def _box_muller_f32(wa, wb):
-    """FP32 Box-Muller pair from two 32-bit words (arrays of uint64)."""
-    ua = (wa >> np.uint64(8)).astype(np.uint32)
-    ub = (wb >> np.uint64(8)).astype(np.uint32)
-    two_m24 = F32(2.0 ** -24)
-    u1 = (ua.astype(F32) + F32(1.0)) * two_m24
-    u2 = ub.astype(F32) * two_m24
-    # ln u1
+def unit_f32(w):
+    """u = ((w >> 8) + 1) 2^-24 in (0, 1] from 32-bit words (uint64 arrays)."""
+    ua = (np.asarray(w, dtype=np.uint64) >> np.uint64(8)).astype(np.uint32)
+    return (ua.astype(F32) + F32(1.0)) * F32(2.0 ** -24)
+
+
+def ln_f32(u1):
+    """ln u for FP32 u in (0, 1], separately rounded FP32 operations: u =
+    2^e m with m in [sqrt(1/2), sqrt(2)), ln u = e ln2 + t q(t), t = m - 1."""
+    u1 = np.asarray(u1, dtype=F32)
     bits = u1.view(np.uint32)
     e = (bits >> np.uint32(23)).astype(np.int32) - 127
     m = ((bits & np.uint32(0x7FFFFF)) | np.uint32(0x3F800000)).view(F32)
@@ -250,7 +272,16 @@ def _box_muller_f32(wa, wb):
         q = q + c
     lnm = t * q
     ln_u = e.astype(F32) * _LN2
-    ln_u = ln_u + lnm
+    return (ln_u + lnm).astype(F32)
+
+
+def _box_muller_f32(wa, wb):
+    """FP32 Box-Muller pair from two 32-bit words (arrays of uint64)."""
+    ub = (wb >> np.uint64(8)).astype(np.uint32)
+    two_m24 = F32(2.0 ** -24)
+    u1 = unit_f32(wa)
+    u2 = ub.astype(F32) * two_m24
+    ln_u = ln_f32(u1)
     L = F32(-2.0) * ln_u
     # sqrt(L) = L / sqrt(L) via Newton steps on 1/sqrt(L)
     li = L.view(np.uint32)
