@@ -198,6 +198,37 @@ int slso_leverage(slso_ctx* ctx, const slso_matrix* X, uint64_t seed,
 int slso_order(slso_ctx* ctx, const float* scores, int64_t n, int32_t* perm,
                void* stream);
 
+/* Orderings for one training epoch by a sampling policy of Algorithm 4
+ * step 4 (policies of Sec. 5.2), from P_i = L_i / sum_j L_j (step 3); a
+ * score that is not a positive finite number has P_i = 0.
+ *   scores  (device) n floats (1 <= n < 2^31).
+ *   policy  SLSO_ORDER_DEC: the "dec" order of slso_order (seed and epoch
+ *           unused). SLSO_ORDER_SWR ("dec, swr"): out[t], t < n, are n draws
+ *           with replacement, in draw order: with integer weights
+ *           w_i = floor(L_i 2^(30 - e)), 2^(e-1) <= max L < 2^e, cumulative
+ *           C_i and W = C_{n-1}, draw t is the smallest i with
+ *           C_i > floor(m_t W / 2^53). SLSO_ORDER_SWOR ("dec, swor"): the
+ *           permutation of weighted sampling without replacement, in draw
+ *           order: rows by ascending key E_i / L_i (FP32), E_i = 0 - ln u_i,
+ *           ties by ascending row, P_i = 0 rows last.
+ *   seed, epoch  the draws' stream: item t of an epoch takes one
+ *           Philox4x32-10 block, counter (lo32(t), hi32(t), epoch, 5 for swr
+ *           or 6 for swor), key (lo32(seed), hi32(seed)); swr uses
+ *           m_t = ((w0 << 32) | w1) >> 11, swor u_t = ((w0 >> 8) + 1) 2^-24
+ *           and ln u_t by the FP32 logarithm of the Gaussian sketch
+ *           generator (see slso_gaussian_sketch_entries).
+ *   out     (device) n int32 row indices.
+ * EINVAL: bad arguments, an unknown policy, or SLSO_ORDER_SWR without a
+ * positive score (the call then synchronises the stream to check W). */
+typedef enum {
+  SLSO_ORDER_DEC = 0,
+  SLSO_ORDER_SWR = 1,
+  SLSO_ORDER_SWOR = 2
+} slso_order_policy;
+int slso_order_sample(slso_ctx* ctx, const float* scores, int64_t n,
+                      int32_t policy, uint64_t seed, uint32_t epoch,
+                      int32_t* out, void* stream);
+
 /* Device workspace (bytes) a context allocates to run slso_leverage and then
  * slso_order on X with these arguments; nothing is enqueued. Same argument
  * checks and error codes as slso_leverage. */

@@ -27,11 +27,13 @@ EINVAL, ENOMEM, ENONFINITE, EDEVICE, EUNSUPPORTED = -1, -2, -3, -4, -5
 F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
 DENSE, CSR = 0, 1
 COUNTSKETCH, GAUSSIAN, OSNAP = 0, 1, 2
+ORDER_DEC, ORDER_SWR, ORDER_SWOR = 0, 1, 2
 STREAM_GAUSS_S, STREAM_PI2 = 3, 4
 
 EXPORTED = (
     "slso_create", "slso_destroy", "slso_status_string", "slso_last_error",
-    "slso_sketch", "slso_leverage", "slso_order", "slso_hash",
+    "slso_sketch", "slso_leverage", "slso_order", "slso_order_sample",
+    "slso_hash",
     "slso_gaussian", "slso_gaussian_sketch_entries", "slso_qr_r", "slso_qr_r_path",
     "slso_solve_upper", "slso_scores", "slso_workspace_size",
     "slso_server_create", "slso_server_submit", "slso_server_poll",
@@ -117,6 +119,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                            ctypes.POINTER(_Options), vp, ctypes.POINTER(_Info),
                            vp], ctypes.c_int),
         "slso_order": ([vp, vp, i64, vp, vp], ctypes.c_int),
+        "slso_order_sample": ([vp, vp, i64, i32, u64, ctypes.c_uint32, vp, vp],
+                              ctypes.c_int),
         "slso_hash": ([u64, i64, i64, i64, vp, vp, vp], ctypes.c_int),
         "slso_gaussian": ([u64, i32, i64, i64, vp, vp], ctypes.c_int),
         "slso_gaussian_sketch_entries": ([u64, i64, i64, i64, vp, vp],
@@ -314,6 +318,19 @@ class Context:
                               device=scores.device)
         _check(load_library().slso_order(self._h, _ptr(scores), scores.numel(),
                                          _ptr(out), _stream(stream)), self._h)
+        return out
+
+    def order_sample(self, scores, policy: int, seed: int, epoch: int = 0,
+                     out=None, stream=None):
+        """One epoch's order by a sampling policy (ORDER_DEC, ORDER_SWR with
+        replacement, ORDER_SWOR without): int32 row indices."""
+        import torch
+        if out is None:
+            out = torch.empty(scores.numel(), dtype=torch.int32,
+                              device=scores.device)
+        _check(load_library().slso_order_sample(
+            self._h, _ptr(scores), scores.numel(), policy, seed, epoch,
+            _ptr(out), _stream(stream)), self._h)
         return out
 
     # ---- stages ---------------------------------------------------------------

@@ -22,7 +22,9 @@ enum StreamId : uint32_t {
   kStreamBucket = 1,
   kStreamSign = 2,
   kStreamGaussS = 3,
-  kStreamPi2 = 4
+  kStreamPi2 = 4,
+  kStreamSwr = 5,
+  kStreamSwor = 6
 };
 
 struct HashCoeffs {

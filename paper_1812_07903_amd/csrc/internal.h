@@ -86,6 +86,19 @@ void radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in,
 void launch_bucket_offsets(const uint32_t* sorted_keys, int64_t n, int64_t r,
                            int32_t* offsets, hipStream_t s);
 
+// ---- sampling policies (k_sample.hip) ---------------------------------------
+// dec-swor: keys[i] = bits of E_i / L_i (FP32, +inf for probability 0), to be
+// sorted ascending with the row index as the value.
+void launch_swor_keys(const float* scores, int64_t n, uint64_t seed,
+                      uint32_t epoch, uint32_t* keys, hipStream_t s);
+// dec-swr: the exact cumulative integer weights (first n int64 of scratch,
+// swr_scratch_bytes(n) in all), then the n draws from them.
+size_t swr_scratch_bytes(int64_t n);
+void launch_swr_prefix(const float* scores, int64_t n, void* scratch,
+                       hipStream_t s);
+void launch_swr_draws(const void* scratch, int64_t n, uint64_t seed,
+                      uint32_t epoch, int32_t* out, hipStream_t s);
+
 // ---- sketch (k_sketch.hip) ---------------------------------------------------
 void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 // colmax_bits: d u64 (bit patterns of non-negative doubles), zero-filled by

@@ -899,6 +899,47 @@ int slso_order(slso_ctx* c, const float* scores, int64_t n, int32_t* perm,
   return check_launch(c, "slso_order");
 }
 
+int slso_order_sample(slso_ctx* c, const float* scores, int64_t n,
+                      int32_t policy, uint64_t seed, uint32_t epoch,
+                      int32_t* out, void* stream) {
+  if (!c) return SLSO_EINVAL;
+  if (policy == SLSO_ORDER_DEC) return slso_order(c, scores, n, out, stream);
+  if (!scores || !out || n < 1 || n >= (static_cast<int64_t>(1) << 31))
+    return set_err(c, SLSO_EINVAL, "need scores, out and 1 <= n < 2^31");
+  if (policy != SLSO_ORDER_SWR && policy != SLSO_ORDER_SWOR)
+    return set_err(c, SLSO_EINVAL, "unknown ordering policy");
+  SLSO_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t need = policy == SLSO_ORDER_SWR ? swr_scratch_bytes(n)
+                                               : order_ws_bytes(n);
+  int st = ensure_ws(c, need);
+  if (st) return st;
+  WsMark mark_{c, s};
+  Arena a{static_cast<char*>(c->ws)};
+  if (policy == SLSO_ORDER_SWOR) {
+    uint32_t* keys = a.take<uint32_t>(n);
+    uint32_t* keys_o = a.take<uint32_t>(n);
+    uint32_t* keys_t = a.take<uint32_t>(n);
+    uint32_t* vals_t = a.take<uint32_t>(n);
+    void* sws = a.take<char>(radix_sort_scratch_bytes(n));
+    launch_swor_keys(scores, n, seed, epoch, keys, s);
+    radix_sort_pairs(keys, nullptr, keys_o, reinterpret_cast<uint32_t*>(out),
+                     keys_t, vals_t, n, 32, sws, s);
+    return check_launch(c, "slso_order_sample");
+  }
+  void* scratch = a.take<char>(swr_scratch_bytes(n));
+  launch_swr_prefix(scores, n, scratch, s);
+  // W = 0 (no positive score) has no distribution to draw from
+  int64_t w = 0;
+  SLSO_HIP(c, hipMemcpyAsync(c->host_buf, static_cast<int64_t*>(scratch) + (n - 1),
+                             sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  SLSO_HIP(c, hipStreamSynchronize(s));
+  std::memcpy(&w, c->host_buf, sizeof(w));
+  if (w <= 0) return set_err(c, SLSO_EINVAL, "dec-swr needs a positive score");
+  launch_swr_draws(scratch, n, seed, epoch, out, s);
+  return check_launch(c, "slso_order_sample");
+}
+
 int slso_profile_enable(int on) {
   slso::Profiler& p = slso::prof();
   std::lock_guard<std::mutex> g(p.mu);

@@ -341,3 +341,61 @@ def test_scores_csr(slso, ctx):
     got = host(ctx.scores(csr_dev(slso, c), dev(m)))
     ref = olv.row_scores(c, m)
     assert omet.max_rel_err(got, ref) < 1e-6
+
+
+# ---- sampling policies (Algorithm 4 step 4) ---------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 3000, 65537])
+@pytest.mark.parametrize("epoch", [0, 7])
+def test_order_swr_swor_match_oracle(slso, ctx, n, epoch):
+    rng = np.random.default_rng(n + epoch)
+    s = rng.random(n).astype(np.float32) ** 3
+    if n > 10:
+        s[rng.integers(0, n, n // 20)] = 0.0      # probability 0
+        s[rng.integers(0, n, n // 50)] = -1.0     # probability 0
+        s[rng.integers(0, n, n // 20)] = np.float32(0.125)   # ties
+    sd = dev(s)
+    swr = host(ctx.order_sample(sd, slso.ORDER_SWR, 99, epoch)).astype(np.int64)
+    assert np.array_equal(swr, oorder.swr_order(s, 99, epoch))
+    swor = host(ctx.order_sample(sd, slso.ORDER_SWOR, 99, epoch)).astype(np.int64)
+    assert np.array_equal(swor, oorder.swor_order(s, 99, epoch))
+    dec = host(ctx.order_sample(sd, slso.ORDER_DEC, 99, epoch)).astype(np.int64)
+    assert np.array_equal(dec, np.argsort(-s, kind="stable"))
+
+
+def test_order_sampling_special_cases(slso, ctx):
+    z = dev(np.zeros(1000, np.float32))
+    with pytest.raises(slso.SlsoError) as ei:
+        ctx.order_sample(z, slso.ORDER_SWR, 1, 0)
+    assert ei.value.status == slso.EINVAL
+    # without replacement, all-zero scores keep the row order
+    assert np.array_equal(host(ctx.order_sample(z, slso.ORDER_SWOR, 1, 0)),
+                          np.arange(1000))
+    with pytest.raises(slso.SlsoError):
+        ctx.order_sample(z, 5, 1, 0)
+    one = np.zeros(5000, np.float32)
+    one[1234] = 3.0
+    assert np.all(host(ctx.order_sample(dev(one), slso.ORDER_SWR, 2, 3)) == 1234)
+
+
+def test_order_sampling_large_and_epochs_differ(slso, ctx):
+    """Bench-sized scores (n = 60000) and a larger n spanning many scan
+    blocks; successive epochs give different draws."""
+    for n in (60000, 300001):
+        s = (np.random.default_rng(n).random(n).astype(np.float32) + 0.01) ** 4
+        sd = dev(s)
+        a = host(ctx.order_sample(sd, slso.ORDER_SWR, 5, 0)).astype(np.int64)
+        b = host(ctx.order_sample(sd, slso.ORDER_SWR, 5, 1)).astype(np.int64)
+        assert not np.array_equal(a, b)
+        if n == 60000:
+            assert np.array_equal(a, oorder.swr_order(s, 5, 0))
+            assert np.array_equal(
+                host(ctx.order_sample(sd, slso.ORDER_SWOR, 5, 2)).astype(np.int64),
+                oorder.swor_order(s, 5, 2))
+        else:
+            # frequencies follow P (chi-square over 40 equal-mass bins)
+            cum = np.cumsum(s.astype(np.float64))
+            edges = np.searchsorted(cum, cum[-1] * np.arange(1, 40) / 40)
+            counts = np.bincount(np.searchsorted(edges, a, side="right"),
+                                 minlength=40)
+            from scipy import stats
+            assert stats.chisquare(counts).pvalue > 1e-4
