@@ -56,16 +56,19 @@ def qr_r(a: np.ndarray) -> np.ndarray:
     return positive_r(r)
 
 
-def rank_decision(r: np.ndarray, rank_tol: float = DEFAULT_RANK_TOL):
+def rank_decision(r: np.ndarray, rank_tol: float = DEFAULT_RANK_TOL,
+                  always_svd: bool = False):
     """Numerical rank of an upper-triangular R (Algorithm 3 step 3).
 
     Returns (rank, screened_full, diag_min, diag_max, svd) where svd is
-    (U, sigma, Vt) when the diagonal screen tripped, else None.
+    (U, sigma, Vt) when the diagonal screen tripped (or ``always_svd``: the
+    rank is always decided by the singular values, which a diagonal screen
+    can misjudge on Kahan-type R), else None.
     """
     dg = np.abs(np.diag(r))
     dmin, dmax = float(dg.min()), float(dg.max())
     d = r.shape[0]
-    if dmax > 0.0 and dmin > math.sqrt(rank_tol) * dmax:
+    if not always_svd and dmax > 0.0 and dmin > math.sqrt(rank_tol) * dmax:
         return d, True, dmin, dmax, None
     u, s, vt = np.linalg.svd(r)
     if s[0] == 0.0:
@@ -76,13 +79,14 @@ def rank_decision(r: np.ndarray, rank_tol: float = DEFAULT_RANK_TOL):
 
 
 def truncated_apply(r: np.ndarray, rhs: np.ndarray,
-                    rank_tol: float = DEFAULT_RANK_TOL):
+                    rank_tol: float = DEFAULT_RANK_TOL,
+                    always_svd: bool = False):
     """pinv_rank(R) @ rhs, with the rank from ``rank_decision``.
 
     Full rank: a triangular solve R M = rhs. Otherwise V' Sigma'^-1 U'^T rhs.
     Returns (M, rank, info-dict).
     """
-    rank, full, dmin, dmax, svd = rank_decision(r, rank_tol)
+    rank, full, dmin, dmax, svd = rank_decision(r, rank_tol, always_svd)
     info = {"rank": rank, "screen_full": full, "diag_min": dmin,
             "diag_max": dmax}
     if full:
@@ -155,10 +159,26 @@ def sketch_of(x, seed: int, r: int, kind: str = "countsketch",
     raise ValueError(kind)
 
 
+def sketched_svd(x, seed: int, r: int, kind: str = "countsketch",
+                 precision: str = "bf16", nnz: int = 2):
+    """Sketched SVD S X = U Sigma V^T (Algorithm 2 step 2): sigma
+    (descending) and V (d x d, column j the right singular vector of
+    sigma_j, its largest-magnitude entry made positive; the first such entry
+    when several tie)."""
+    sx = sketch_of(x, seed, r, kind, precision, nnz)
+    _, sig, vt = np.linalg.svd(sx, full_matrices=False)
+    v = vt.T.copy()
+    for j in range(v.shape[1]):
+        i = int(np.argmax(np.abs(v[:, j])))
+        if v[i, j] < 0:
+            v[:, j] = -v[:, j]
+    return sig, v
+
+
 def sketched_leverage(x, seed: int, r: int, k: int, kind: str = "countsketch",
                       rank_tol: float = DEFAULT_RANK_TOL, sx=None,
                       refine: bool = False, precision: str = "bf16",
-                      nnz: int = 2):
+                      nnz: int = 2, always_svd: bool = False):
     """Algorithm 3 in QR form with the second projection Pi_2.
 
     ``sx`` may carry a precomputed unscaled sketch. With ``refine`` the factor
@@ -177,7 +197,7 @@ def sketched_leverage(x, seed: int, r: int, k: int, kind: str = "countsketch",
             sx = sketch_of(x, seed, r, kind, precision, nnz)
         rd = qr_r(sx * dsc[None, :])
     pi = np.eye(d) if k == 0 else streams.pi2_matrix(seed, d, k)
-    mp, rank, info = truncated_apply(rd, pi, rank_tol)
+    mp, rank, info = truncated_apply(rd, pi, rank_tol, always_svd)
     m = dsc[:, None] * mp
     scores = row_scores(x, m)
     return {"scores": scores, "rank": rank, "R_D": rd, "D": dsc, "M": m,

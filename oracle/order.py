@@ -37,7 +37,7 @@ def dec_order(scores) -> np.ndarray:
 # dec-swor: a weighted random permutation without replacement, in draw order
 # (successive draws proportional to P among the rows not yet drawn), by the
 # exponential keys of Efraimidis and Spirakis: key_i = E_i / L_i with
-# E_i = -ln u_i exponential, rows in ascending key, ties by ascending row; a
+# E_i = 0 - ln u_i exponential, rows in ascending key, ties by ascending row; a
 # row of probability 0 has key +inf. All of it in FP32, each operation
 # rounded separately.
 from . import streams  # noqa: E402
@@ -78,7 +78,8 @@ def swor_keys(scores, seed: int, epoch: int) -> np.ndarray:
     s, ok = _positive(scores)
     n = s.shape[0]
     w0, _ = streams.sample_words(seed, streams.STREAM_SWOR, epoch, np.arange(n))
-    e = -streams.ln_f32(streams.unit_f32(w0))
+    # E = 0 - ln u (u = 1 gives +0, not -0)
+    e = (np.float32(0.0) - streams.ln_f32(streams.unit_f32(w0))).astype(np.float32)
     with np.errstate(divide="ignore", invalid="ignore"):
         k = (e / np.where(ok, s, np.float32(1.0))).astype(np.float32)
     return np.where(ok, k, np.float32(np.inf)).astype(np.float32)

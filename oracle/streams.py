@@ -40,7 +40,7 @@ Stream ids: 1 bucket hash, 2 sign hash, 3 Gaussian sketch, 4 Pi_2,
   for item t and epoch, one Philox4x32-10 block with counter (lo32(t),
   hi32(t), epoch, stream) and key (lo32(seed), hi32(seed)). dec-swr takes the
   53-bit integer ((w0 << 32) | w1) >> 11; dec-swor the FP32 unit
-  u = ((w0 >> 8) + 1) 2^-24 and E = -ln u with the FP32 logarithm of the
+  u = ((w0 >> 8) + 1) 2^-24 and E = 0 - ln u with the FP32 logarithm of the
   Gaussian generator.
 
 * OSNAP with s nonzeros per column (the sparse embedding the paper lists

@@ -200,3 +200,34 @@ def test_small_singular_values_truncated_by_threshold():
     assert lo["rank"] == d
     assert hi["rank"] == k
     assert abs(hi["scores"].sum() - k) < 0.5
+
+
+def test_sketched_svd_matches_r_factor_and_gram():
+    """Sigma of S X equals sigma of its QR factor R (Q is orthonormal), and
+    V Sigma^2 V^T is the Gram matrix (S X)^T (S X)."""
+    x = synth.config0(n=3000, d=20, seed=15)
+    sig, v = lv.sketched_svd(x, 4, 256)
+    sx = sk.countsketch_dense(x, 4, 256)
+    np.testing.assert_allclose(sig, np.linalg.svd(lv.qr_r(sx), compute_uv=False),
+                               rtol=1e-12)
+    np.testing.assert_allclose(v @ np.diag(sig ** 2) @ v.T, sx.T @ sx,
+                               rtol=1e-10, atol=1e-10 * sig[0] ** 2)
+    np.testing.assert_allclose(v.T @ v, np.eye(20), atol=1e-13)
+    assert np.all(np.diff(sig) <= 0)
+    assert np.all(v[np.argmax(np.abs(v), axis=0), np.arange(20)] > 0)
+
+
+def test_always_svd_rank_catches_kahan_matrix():
+    """A Kahan-type R has a benign diagonal but a tiny singular value: the
+    diagonal screen calls it full rank, the SVD decision does not."""
+    d, c = 60, 0.3
+    s_ = math.sqrt(1 - c * c)
+    kahan = np.triu(-c * np.ones((d, d)), 1) + np.eye(d)
+    kahan = np.diag(s_ ** np.arange(d)) @ kahan
+    sv = np.linalg.svd(kahan, compute_uv=False)
+    tol = (sv[-1] / sv[0]) * 10.0          # the smallest value falls below it
+    rank, full, dmin, dmax, _ = lv.rank_decision(kahan, tol)
+    assert full and rank == d               # the screen misses it
+    assert dmin > math.sqrt(tol) * dmax
+    rank2, full2, _, _, _ = lv.rank_decision(kahan, tol, always_svd=True)
+    assert not full2 and rank2 == d - 1
