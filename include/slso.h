@@ -104,8 +104,15 @@ typedef struct {
                     /* truncation (R^{-1} is used whatever its conditioning) */
   int32_t nnz_per_col; /* OSNAP nonzeros per column of S, 1..16 dividing r;  */
                        /* 0 selects 2; ignored by the other sketches         */
-  int32_t reserved;    /* must be 0                                          */
+  int32_t flags;       /* SLSO_OPT_* bits; other bits must be 0              */
 } slso_options;
+
+/* slso_options.flags bits */
+#define SLSO_OPT_SVD_RANK 1 /* decide the rank of Algorithm 3 step 3 by the */
+                            /* singular values of R every time (Jacobi SVD), */
+                            /* not by the diagonal screen, which can call a  */
+                            /* Kahan-type R full rank; with nothing cut the  */
+                            /* scores are those of R^{-1}                    */
 
 /* Host-side report of one leverage computation. */
 typedef struct {
@@ -168,6 +175,22 @@ const char* slso_last_error(const slso_ctx* ctx);
  * nnz_per_col outside 1..16 or not dividing r. */
 int slso_sketch(slso_ctx* ctx, const slso_matrix* X, uint64_t seed, int64_t r,
                 const slso_options* opt, double* sx, void* stream);
+
+/* The sketched SVD S X = U Sigma V^T of Algorithm 2 step 2 (the object the
+ * paper evaluates): S X by slso_sketch (same seed and options), R = the R of
+ * S X by slso_qr_r (Cholesky-QR2, else Householder), then the one-sided
+ * Jacobi SVD of R, whose singular values and right singular vectors are
+ * those of S X.
+ *   sx     (device) r x d doubles of caller scratch (overwritten).
+ *   sigma  (device) d doubles: the singular values, descending.
+ *   v      (device) d x d doubles, row-major: column j is the right singular
+ *          vector of sigma[j], its largest-magnitude entry made positive
+ *          (the first such entry when several tie).
+ * Errors as slso_sketch and slso_qr_r; the call synchronises the stream
+ * (the Jacobi sweeps stop when a sweep rotates nothing). */
+int slso_sketch_svd(slso_ctx* ctx, const slso_matrix* X, uint64_t seed,
+                    int64_t r, const slso_options* opt, double* sx,
+                    double* sigma, double* v, void* stream);
 
 /* Sketched leverage scores (Algorithms 2 and 3, QR form, with Pi_2).
  *   k       columns of Pi_2 (k >= 0; k = 0 means Pi_2 = I, exact sketched

@@ -27,12 +27,14 @@ EINVAL, ENOMEM, ENONFINITE, EDEVICE, EUNSUPPORTED = -1, -2, -3, -4, -5
 F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
 DENSE, CSR = 0, 1
 COUNTSKETCH, GAUSSIAN, OSNAP = 0, 1, 2
+OPT_SVD_RANK = 1
 ORDER_DEC, ORDER_SWR, ORDER_SWOR = 0, 1, 2
 STREAM_GAUSS_S, STREAM_PI2 = 3, 4
 
 EXPORTED = (
     "slso_create", "slso_destroy", "slso_status_string", "slso_last_error",
-    "slso_sketch", "slso_leverage", "slso_order", "slso_order_sample",
+    "slso_sketch", "slso_sketch_svd", "slso_leverage", "slso_order",
+    "slso_order_sample",
     "slso_hash",
     "slso_gaussian", "slso_gaussian_sketch_entries", "slso_qr_r", "slso_qr_r_path",
     "slso_solve_upper", "slso_scores", "slso_workspace_size",
@@ -67,7 +69,7 @@ class _Matrix(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("sketch", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("rank_tol", ctypes.c_double),
-                ("nnz_per_col", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("nnz_per_col", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -121,6 +123,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "slso_order": ([vp, vp, i64, vp, vp], ctypes.c_int),
         "slso_order_sample": ([vp, vp, i64, i32, u64, ctypes.c_uint32, vp, vp],
                               ctypes.c_int),
+        "slso_sketch_svd": ([vp, vp, u64, i64, vp, vp, vp, vp, vp], ctypes.c_int),
         "slso_hash": ([u64, i64, i64, i64, vp, vp, vp], ctypes.c_int),
         "slso_gaussian": ([u64, i32, i64, i64, vp, vp], ctypes.c_int),
         "slso_gaussian_sketch_entries": ([u64, i64, i64, i64, vp, vp],
@@ -297,14 +300,16 @@ class Context:
 
     def leverage(self, x, seed: int, r: int, k: int, sketch: int = COUNTSKETCH,
                  refine: bool = False, rank_tol: float = 0.0, out=None,
-                 stream=None, nnz: int = 0):
+                 stream=None, nnz: int = 0, svd_rank: bool = False):
         """Scores (float32 device tensor) and the rank-decision info dict.
-        ``nnz``: OSNAP nonzeros per column of S (0 selects 2)."""
+        ``nnz``: OSNAP nonzeros per column of S (0 selects 2); ``svd_rank``:
+        decide the rank by the SVD of R every time."""
         import torch
         if out is None:
             out = torch.empty(_rows(x), dtype=torch.float32, device=_device(x))
         m = _matrix(x)
-        opt = _Options(sketch, 1 if refine else 0, rank_tol, nnz, 0)
+        opt = _Options(sketch, 1 if refine else 0, rank_tol, nnz,
+                       OPT_SVD_RANK if svd_rank else 0)
         info = _Info()
         st = _check(load_library().slso_leverage(
             self._h, ctypes.byref(m), seed, r, k, ctypes.byref(opt), _ptr(out),
@@ -319,6 +324,22 @@ class Context:
         _check(load_library().slso_order(self._h, _ptr(scores), scores.numel(),
                                          _ptr(out), _stream(stream)), self._h)
         return out
+
+    def sketch_svd(self, x, seed: int, r: int, sketch: int = COUNTSKETCH,
+                   nnz: int = 0, stream=None):
+        """Sketched SVD of S X: (sigma descending, V with column j the right
+        singular vector of sigma[j]) as float64 device tensors."""
+        import torch
+        d = _cols(x)
+        sx = torch.empty((r, d), dtype=torch.float64, device=_device(x))
+        sigma = torch.empty(d, dtype=torch.float64, device=_device(x))
+        v = torch.empty((d, d), dtype=torch.float64, device=_device(x))
+        m = _matrix(x)
+        opt = _Options(sketch, 0, 0.0, nnz, 0)
+        _check(load_library().slso_sketch_svd(
+            self._h, ctypes.byref(m), seed, r, ctypes.byref(opt), _ptr(sx),
+            _ptr(sigma), _ptr(v), _stream(stream)), self._h)
+        return sigma, v
 
     def order_sample(self, scores, policy: int, seed: int, epoch: int = 0,
                      out=None, stream=None):

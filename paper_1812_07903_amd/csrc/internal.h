@@ -222,6 +222,13 @@ void trsm_blocked(const double* r, int64_t d, double* b, int64_t k,
 // pinv of the rank-`rank` truncation of r applied to b: out = V' S'^-1 U'^T b.
 // Works on copies; sigma (host) receives the d singular values, descending.
 size_t jacobi_scratch_bytes(int64_t d, int64_t k);
+// SVD of an upper-triangular d x d R (row-major) by one-sided Jacobi:
+// sigma (device, d, descending) and v (device, d x d row-major, column j the
+// right singular vector of sigma[j], largest-magnitude entry positive). r may
+// alias v. Synchronises the stream. 0 on success.
+size_t jacobi_svd_scratch_bytes(int64_t d);
+int jacobi_svd(const double* r, int64_t d, double* sigma, double* v,
+               void* scratch, hipStream_t s);
 int jacobi_truncated_apply(const double* r, int64_t d, const double* b,
                            int64_t k, double rank_tol, double* out,
                            int64_t* rank_out, void* scratch, hipStream_t s);

@@ -208,8 +208,89 @@ __global__ void __launch_bounds__(64)
   UtB[static_cast<int64_t>(jj) * k + c] = s / sig[j];
 }
 
+// out column k: the right singular vector V[:, idx[k]] with its
+// largest-magnitude entry (the first on ties) made positive; sigma_out[k]
+__global__ void __launch_bounds__(64)
+    svd_out_kernel(const double* __restrict__ V, const double* __restrict__ sig,
+                   const int* __restrict__ idx, int64_t d,
+                   double* __restrict__ sigma_out, double* __restrict__ v_out) {
+  const int64_t k = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int j = idx[k];
+  const double* vj = V + static_cast<int64_t>(j) * d;
+  double best = -1.0;
+  int64_t bi = d;
+  for (int64_t i = lane; i < d; i += 64) {
+    const double a = fabs(vj[i]);
+    if (a > best) {
+      best = a;
+      bi = i;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, 64);
+    const int64_t oi = __shfl_xor(bi, o, 64);
+    if (ob > best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  const double sg = vj[bi] < 0.0 ? -1.0 : 1.0;
+  for (int64_t i = lane; i < d; i += 64) v_out[i * d + k] = sg * vj[i];
+  if (lane == 0) sigma_out[k] = sig[j];
+}
 
 }  // namespace
+
+size_t jacobi_svd_scratch_bytes(int64_t d) {
+  return static_cast<size_t>(2 * d * d + d) * sizeof(double) +
+         static_cast<size_t>(d + 64) * sizeof(int);
+}
+
+int jacobi_svd(const double* r, int64_t d, double* sigma, double* v,
+               void* scratch, hipStream_t s) {
+  if (d <= 0) return 0;
+  double* A = static_cast<double*>(scratch);
+  double* V = A + d * d;
+  double* sig = V + d * d;
+  int* idx_d = reinterpret_cast<int*>(sig + d);
+  int* rotated = idx_d + d;
+  const int64_t dd = d * d;
+  transpose_init_kernel<<<static_cast<unsigned>((dd + 255) / 256), 256, 0, s>>>(
+      r, d, A, V);
+  const int64_t dpad = d + (d & 1);
+  const int64_t rounds = dpad - 1 > 0 ? dpad - 1 : 1;
+  const unsigned pgrid = static_cast<unsigned>((dpad / 2 + 3) / 4);
+  int host_rot = 1;
+  for (int sweep = 0; sweep < 40 && host_rot && d > 1; ++sweep) {
+    if (hipMemsetAsync(rotated, 0, sizeof(int), s) != hipSuccess) return -1;
+    for (int64_t rd = 0; rd < rounds; ++rd)
+      jacobi_round_kernel<<<pgrid, 256, 0, s>>>(A, V, d, dpad, rd, 1e-15, rotated);
+    if (hipMemcpyAsync(&host_rot, rotated, sizeof(int), hipMemcpyDeviceToHost,
+                       s) != hipSuccess)
+      return -1;
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+  }
+  col_norms_kernel<<<static_cast<unsigned>((d + 3) / 4), 256, 0, s>>>(A, d, sig);
+  std::vector<double> hs(static_cast<size_t>(d));
+  if (hipMemcpyAsync(hs.data(), sig, d * sizeof(double), hipMemcpyDeviceToHost,
+                     s) != hipSuccess)
+    return -1;
+  if (hipStreamSynchronize(s) != hipSuccess) return -1;
+  std::vector<int> idx(static_cast<size_t>(d));
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(),
+                   [&](int x, int y) { return hs[x] > hs[y]; });
+  if (hipMemcpyAsync(idx_d, idx.data(), d * sizeof(int), hipMemcpyHostToDevice,
+                     s) != hipSuccess)
+    return -1;
+  svd_out_kernel<<<static_cast<unsigned>(d), 64, 0, s>>>(V, sig, idx_d, d, sigma,
+                                                         v);
+  // keep the host index buffer alive until the copy has been consumed
+  if (hipStreamSynchronize(s) != hipSuccess) return -1;
+  return 0;
+}
 
 void solve_upper(const double* r, int64_t d, double* b, int64_t k,
                  hipStream_t s, double* scratch) {

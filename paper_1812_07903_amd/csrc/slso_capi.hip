@@ -273,7 +273,8 @@ int check_sketch_kind(slso_ctx* c, const slso_options& o, int64_t r) {
   if (o.sketch != SLSO_COUNTSKETCH && o.sketch != SLSO_GAUSSIAN &&
       o.sketch != SLSO_OSNAP)
     return set_err(c, SLSO_EINVAL, "unknown sketch kind");
-  if (o.reserved != 0) return set_err(c, SLSO_EINVAL, "reserved must be 0");
+  if ((o.flags & ~SLSO_OPT_SVD_RANK) != 0)
+    return set_err(c, SLSO_EINVAL, "unknown option flags");
   if (o.sketch == SLSO_OSNAP) {
     const int s = sketch_nnz(o);
     if (s < 1 || s > kMaxOsnapNnz || r % s != 0)
@@ -513,6 +514,24 @@ int slso_sketch(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
                         seed, r, nullptr, part, sx, s);
   }
   return check_launch(c, "slso_sketch");
+}
+
+int slso_sketch_svd(slso_ctx* c, const slso_matrix* X, uint64_t seed,
+                    int64_t r, const slso_options* opt, double* sx,
+                    double* sigma, double* v, void* stream) {
+  if (!c) return SLSO_EINVAL;
+  if (!sx || !sigma || !v) return set_err(c, SLSO_EINVAL, "sx, sigma or v is NULL");
+  int st = slso_sketch(c, X, seed, r, opt, sx, stream);
+  if (st) return st;
+  const int64_t d = X->d;
+  // R of S X into v, then its SVD (A and V of the sweeps in the workspace)
+  if ((st = slso_qr_r(c, sx, r, d, v, stream))) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = ensure_ws(c, jacobi_svd_scratch_bytes(d)))) return st;
+  WsMark mark_{c, s};
+  if (jacobi_svd(v, d, sigma, v, c->ws, s) != 0)
+    return set_err(c, SLSO_EDEVICE, "Jacobi SVD failed");
+  return check_launch(c, "slso_sketch_svd");
 }
 
 int slso_qr_r_path(slso_ctx* c, double* a, int64_t m, int64_t d,
@@ -822,7 +841,9 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
     }
   }
   bool full = true;
-  if (tol >= 0.0) full = dmax > 0.0 && dmin > std::sqrt(tol) * dmax;
+  if (tol >= 0.0)
+    full = (o.flags & SLSO_OPT_SVD_RANK) == 0 && dmax > 0.0 &&
+           dmin > std::sqrt(tol) * dmax;
   // 5. Pi_2 and M = D pinv(R_D) Pi_2 (Algorithm 2 step 3 / Algorithm 3 step 4)
   if (k == 0)
     launch_eye(pi, d, s);

@@ -73,8 +73,8 @@ def _mat(n, d, dtype=slso.F32, fmt=slso.DENSE, col_scale=None):
     return m
 
 
-def _ws(lib, m, r, k, sketch=slso.COUNTSKETCH, refine=0, nnz=0, reserved=0):
-    opt = slso._Options(sketch, refine, 0.0, nnz, reserved)
+def _ws(lib, m, r, k, sketch=slso.COUNTSKETCH, refine=0, nnz=0, flags=0):
+    opt = slso._Options(sketch, refine, 0.0, nnz, flags)
     out = ctypes.c_size_t()
     st = lib.slso_workspace_size(ctypes.byref(m), r, k, ctypes.byref(opt),
                                  ctypes.byref(out))
@@ -110,7 +110,8 @@ def test_osnap_argument_errors(lib):
     assert _ws(lib, m, 16, 4, sketch=slso.OSNAP, nnz=3)[0] == slso.EINVAL   # 3 does not divide 16
     assert _ws(lib, m, 32, 4, sketch=slso.OSNAP, nnz=32)[0] == slso.EINVAL  # above 16
     assert _ws(lib, m, 16, 4, sketch=slso.OSNAP, nnz=-1)[0] == slso.EINVAL
-    assert _ws(lib, m, 16, 4, reserved=1)[0] == slso.EINVAL
+    assert _ws(lib, m, 16, 4, flags=2)[0] == slso.EINVAL                  # unknown flag
+    assert _ws(lib, m, 16, 4, flags=slso.OPT_SVD_RANK)[0] == slso.OK
     assert _ws(lib, m, 16, 4, sketch=3)[0] == slso.EINVAL
     assert _ws(lib, m, 16, 4, sketch=slso.OSNAP, nnz=16)[0] == slso.OK
 

@@ -11,6 +11,7 @@ import pytest
 import synth
 from oracle import leverage as olv
 from oracle import metrics as omet
+from oracle import sketch as osk
 
 pytestmark = pytest.mark.gpu
 
@@ -185,3 +186,55 @@ def test_invalid_sizes_rejected(slso, ctx):
     assert ei.value.status == slso.EINVAL
     with pytest.raises(slso.SlsoError):
         ctx.leverage(dev(x), 1, 64, -1)    # k < 0
+
+
+# ---- sketched SVD and the SVD rank decision ----------------------------------------
+@pytest.mark.parametrize("kind,n,d,r", [("countsketch", 4000, 40, 512),
+                                        ("osnap", 3000, 64, 1024),
+                                        ("countsketch", 20000, 200, 2048)])
+def test_sketch_svd_matches_oracle(slso, ctx, kind, n, d, r):
+    x = synth.config0(n=n, d=d, seed=d)
+    sk = slso.OSNAP if kind == "osnap" else slso.COUNTSKETCH
+    sig, v = ctx.sketch_svd(dev(x), 3, r, sketch=sk, nnz=2)
+    sig, v = host(sig), host(v)
+    rs, rv = olv.sketched_svd(x, 3, r, kind=kind, nnz=2)
+    assert np.max(np.abs(sig - rs) / rs[0]) < 1e-12
+    # right singular vectors (distinct singular values: sigma_j = 2^(-j/4))
+    assert np.max(np.abs(v - rv)) < 1e-8
+    sx = osk.countsketch_dense(x, 3, r) if kind == "countsketch" else \
+        osk.osnap_dense(x, 3, r, 2)
+    g = sx.T @ sx
+    assert np.max(np.abs(v @ np.diag(sig ** 2) @ v.T - g)) < 1e-11 * sig[0] ** 2
+
+
+def test_svd_rank_mode(slso, ctx):
+    """A Kahan-type factor: X = Q K with Q orthonormal columns. The diagonal
+    screen calls the sketch's R full rank; the SVD decision cuts its smallest
+    singular value. Both modes match the oracle's."""
+    rng = np.random.default_rng(60)
+    d, c = 40, 0.3
+    s_ = np.sqrt(1 - c * c)
+    kahan = np.diag(s_ ** np.arange(d)) @ (np.triu(-c * np.ones((d, d)), 1) + np.eye(d))
+    x = synth.haar(rng, 8000, d) @ kahan
+    seed, r = 7, 1024
+    base = olv.sketched_leverage(x, seed, r, 0)
+    sv = np.linalg.svd(base["R_D"], compute_uv=False)
+    tol = float(np.sqrt(sv[-1] * sv[-2]) / sv[0])   # between the last two
+    dg = np.abs(np.diag(base["R_D"]))
+    if not dg.min() > np.sqrt(tol) * dg.max():
+        pytest.skip("this sketch's diagonal already trips the screen")
+    ref_screen = olv.sketched_leverage(x, seed, r, 0, rank_tol=tol)
+    ref_svd = olv.sketched_leverage(x, seed, r, 0, rank_tol=tol, always_svd=True)
+    assert ref_screen["rank"] == d and ref_svd["rank"] == d - 1
+    got, info = ctx.leverage(dev(x), seed, r, 0, rank_tol=tol)
+    assert info["rank"] == d
+    assert _report("kahan screen", host(got), ref_screen["scores"])[0] < 1e-5
+    got2, info2 = ctx.leverage(dev(x), seed, r, 0, rank_tol=tol, svd_rank=True)
+    assert info2["rank"] == d - 1 and not info2["screen_full"]
+    assert _report("kahan svd rank", host(got2), ref_svd["scores"])[0] < 1e-5
+    # full-rank input: the SVD decision keeps everything and gives R^{-1}'s scores
+    y = synth.config0(n=6000, d=32, seed=61)
+    a, ia = ctx.leverage(dev(y), 3, 1024, 16, svd_rank=True)
+    ref = olv.sketched_leverage(y, 3, 1024, 16)
+    assert ia["rank"] == 32
+    assert _report("full rank, svd decision", host(a), ref["scores"])[0] < 1e-5
