@@ -152,6 +152,10 @@ def sketch_of(x, seed: int, r: int, kind: str = "countsketch",
         if isinstance(x, np.ndarray):
             return sk.osnap_dense(x, seed, r, nnz)
         return sk.osnap_csr(x, seed, r, nnz)
+    if kind == "srht":
+        if not isinstance(x, np.ndarray):
+            x = x.to_dense()
+        return sk.srht_dense(x, seed, r)
     if kind == "gaussian":
         if not isinstance(x, np.ndarray):
             x = x.to_dense()

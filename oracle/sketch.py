@@ -97,6 +97,52 @@ def osnap_csr(csr, seed: int, r: int, s: int) -> np.ndarray:
     return sx * (1.0 / math.sqrt(s))
 
 
+def srht_plan(seed: int, n: int, r: int):
+    """(n', rows): the padded length n' = 2^ceil(log2 n) and the r sampled
+    Hadamard rows, in sketch-row order."""
+    n2 = 1 << max(0, (n - 1).bit_length())
+    if r > n2:
+        raise ValueError("SRHT needs r <= n' (the padded row count)")
+    w0, _ = streams.sample_words(seed, streams.STREAM_SRHT_ROWS, 0,
+                                 np.arange(n2))
+    return n2, np.argsort(w0.astype(np.uint64), kind="stable")[:r]
+
+
+def srht_signs(seed: int, n: int) -> np.ndarray:
+    h = streams.poly_hash(streams.hash_coeffs(seed, streams.STREAM_SRHT_SIGN),
+                          np.arange(n))
+    return np.array([1 - 2 * (int(v) & 1) for v in h], dtype=np.float64)
+
+
+def fwht_rows(y: np.ndarray) -> np.ndarray:
+    """Unnormalised Walsh-Hadamard transform along the rows (length a power
+    of two), Sylvester order: stage b = 0, 1, ... replaces rows a and
+    a + 2^b (bit b of a clear) by their sum and difference."""
+    n2, d = y.shape
+    y = y.copy()
+    h = 1
+    while h < n2:
+        v = y.reshape(n2 // (2 * h), 2, h, d)
+        a = v[:, 0].copy()
+        b = v[:, 1].copy()
+        v[:, 0] = a + b
+        v[:, 1] = a - b
+        h *= 2
+    return y
+
+
+def srht_dense(x: np.ndarray, seed: int, r: int) -> np.ndarray:
+    """SRHT sketch S X = (1/sqrt(r)) P H D X (r x d, FP64): D the random
+    signs, X padded with zero rows to n', H the unnormalised Hadamard
+    transform, P the r sampled rows; the 1/sqrt(r) is applied once at the end
+    (E[S^T S] = I)."""
+    n, d = x.shape
+    n2, rows = srht_plan(seed, n, r)
+    y = np.zeros((n2, d), dtype=np.float64)
+    y[:n] = srht_signs(seed, n)[:, None] * np.asarray(x, dtype=np.float64)
+    return fwht_rows(y)[rows] * (1.0 / math.sqrt(r))
+
+
 def gaussian_sketch_dense(x: np.ndarray, seed: int, r: int,
                           g: np.ndarray | None = None,
                           precision: str = "f64") -> np.ndarray:

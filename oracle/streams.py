@@ -34,7 +34,13 @@ library) are:
   Reduced-precision inputs take it rounded to BF16 (ties to even).
 
 Stream ids: 1 bucket hash, 2 sign hash, 3 Gaussian sketch, 4 Pi_2,
-5 dec-swr draws, 6 dec-swor keys.
+5 dec-swr draws, 6 dec-swor keys, 7 SRHT signs, 8 SRHT row choice.
+
+* SRHT (the randomized Hadamard transform of Sec. 2.1 / Table 1): row i's
+  sign is +1 if P(i) is even for the polynomial hash of stream 7; the r
+  sampled rows of the n' = 2^ceil(log2 n) Hadamard rows are those with the r
+  smallest 32-bit words w0 of the sampling block (counter (lo32(i), hi32(i),
+  0, 8)), ties by ascending row, in that order.
 
 * Sampling draws (the dec-swr / dec-swor policies of Algorithm 4 step 4):
   for item t and epoch, one Philox4x32-10 block with counter (lo32(t),
@@ -65,6 +71,8 @@ STREAM_GAUSS_S = 3
 STREAM_PI2 = 4
 STREAM_SWR = 5
 STREAM_SWOR = 6
+STREAM_SRHT_SIGN = 7
+STREAM_SRHT_ROWS = 8
 
 
 def splitmix64_mix(z: int) -> int:

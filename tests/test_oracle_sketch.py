@@ -146,3 +146,40 @@ def test_osnap_csr_equals_dense():
 def test_osnap_rejects_s_not_dividing_r():
     with pytest.raises(ValueError):
         streams.osnap_bucket_sign(1, 10, 3, np.arange(5))
+
+
+# ---- SRHT --------------------------------------------------------------------------
+def test_srht_equals_explicit_product():
+    """(1/sqrt(r)) P H D X against scipy's Hadamard matrix; integer X keeps
+    every sum exact, so the two agree exactly."""
+    import scipy.linalg
+    rng = np.random.default_rng(4)
+    x = rng.integers(-20, 20, (200, 6)).astype(np.float64)   # n' = 256
+    n2, rows = sk.srht_plan(3, 200, 64)
+    assert n2 == 256 and len(set(rows.tolist())) == 64
+    h = scipy.linalg.hadamard(256)
+    dx = np.zeros((256, 6))
+    dx[:200] = sk.srht_signs(3, 200)[:, None] * x
+    ref = (h @ dx)[rows] * (1.0 / math.sqrt(64))
+    assert np.array_equal(sk.srht_dense(x, 3, 64), ref)
+
+
+def test_srht_all_rows_is_orthogonal():
+    """With r = n' the sketch is (1/sqrt(n')) H D times a permutation:
+    orthogonal, so the Frobenius norm is kept."""
+    x = np.random.default_rng(5).standard_normal((128, 9))
+    sx = sk.srht_dense(x, 8, 128)
+    np.testing.assert_allclose(np.linalg.norm(sx), np.linalg.norm(x), rtol=1e-13)
+    np.testing.assert_allclose(sx.T @ sx, x.T @ x, rtol=1e-12, atol=1e-12)
+
+
+def test_srht_is_unbiased_embedding():
+    x = np.random.default_rng(6).standard_normal(100)
+    vals = [np.sum(sk.srht_dense(x[:, None], seed, 16) ** 2) for seed in range(400)]
+    m, sd = np.mean(vals), np.std(vals) / math.sqrt(len(vals))
+    assert abs(m - np.dot(x, x)) < 5 * sd
+
+
+def test_srht_rejects_r_above_padded_rows():
+    with pytest.raises(ValueError):
+        sk.srht_plan(1, 100, 200)
