@@ -66,11 +66,15 @@ typedef enum { SLSO_DENSE = 0, SLSO_CSR = 1 } slso_format;
 typedef enum {
   SLSO_COUNTSKETCH = 0, /* one signed nonzero per column of S (Sec. 2.1)     */
   SLSO_GAUSSIAN = 1,    /* S = G / sqrt(r), G i.i.d. N(0, 1) (Sec. 2.1)      */
-  SLSO_OSNAP = 2        /* s = nnz_per_col signed nonzeros +-1/sqrt(s) per   */
+  SLSO_OSNAP = 2,       /* s = nnz_per_col signed nonzeros +-1/sqrt(s) per   */
                         /* column of S, one in each of s blocks of r / s     */
                         /* rows (the sparse embedding of Sec. 2.1, hashed as */
                         /* in Sec. 3.1.2); hash 0 is the CountSketch's, so   */
                         /* s = 1 gives the CountSketch                       */
+  SLSO_SRHT = 3         /* S = (1/sqrt(r)) P H D: random signs D, the        */
+                        /* Walsh-Hadamard transform H over n' = 2^ceil(log2  */
+                        /* n) zero-padded rows, r sampled rows P (Sec. 2.1,  */
+                        /* Table 1); dense input, r <= n'                    */
 } slso_sketch_kind;
 
 /* An n x d input matrix. Dense: ``values`` (device) holds n rows of ``ld``
@@ -171,8 +175,15 @@ const char* slso_last_error(const slso_ctx* ctx);
  * once to the FP64 sum. OSNAP (same inputs as CountSketch): for every hash
  * j < s, sx[h_j(i)] += s_j(i) x_i in ascending i (each sketch row belongs to
  * one hash's block), then every sum is multiplied once by 1/sqrt(s) in FP64.
- * EUNSUPPORTED: Gaussian with F64 or CSR input. EINVAL: OSNAP with
- * nnz_per_col outside 1..16 or not dividing r. */
+ * SRHT (dense input): D_ii = +1 if the polynomial hash of stream 7 is even
+ * at i, else -1; rows past n are zero up to n' = 2^ceil(log2 n); H is applied
+ * as Sylvester-order stages t = 0, 1, ..., each replacing rows a and
+ * a + 2^t (bit t of a clear) by their FP64 sum and difference; P takes the r
+ * rows i < n' with the smallest words w0 of the Philox block with counter
+ * (lo32(i), hi32(i), 0, 8) and key (lo32(seed), hi32(seed)), ties by
+ * ascending i, in that order; the result is multiplied once by 1/sqrt(r).
+ * EUNSUPPORTED: Gaussian with F64 or CSR input, SRHT with CSR input. EINVAL:
+ * OSNAP with nnz_per_col outside 1..16 or not dividing r; SRHT with r > n'. */
 int slso_sketch(slso_ctx* ctx, const slso_matrix* X, uint64_t seed, int64_t r,
                 const slso_options* opt, double* sx, void* stream);
 

@@ -26,7 +26,7 @@ EINVAL, ENOMEM, ENONFINITE, EDEVICE, EUNSUPPORTED = -1, -2, -3, -4, -5
 # slso_dtype / slso_format / slso_sketch_kind
 F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
 DENSE, CSR = 0, 1
-COUNTSKETCH, GAUSSIAN, OSNAP = 0, 1, 2
+COUNTSKETCH, GAUSSIAN, OSNAP, SRHT = 0, 1, 2, 3
 OPT_SVD_RANK = 1
 ORDER_DEC, ORDER_SWR, ORDER_SWOR = 0, 1, 2
 STREAM_GAUSS_S, STREAM_PI2 = 3, 4

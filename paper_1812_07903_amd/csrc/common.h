@@ -24,7 +24,9 @@ enum StreamId : uint32_t {
   kStreamGaussS = 3,
   kStreamPi2 = 4,
   kStreamSwr = 5,
-  kStreamSwor = 6
+  kStreamSwor = 6,
+  kStreamSrhtSign = 7,
+  kStreamSrhtRows = 8
 };
 
 struct HashCoeffs {

@@ -86,6 +86,16 @@ void radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in,
 void launch_bucket_offsets(const uint32_t* sorted_keys, int64_t n, int64_t r,
                            int32_t* offsets, hipStream_t s);
 
+// ---- SRHT sketch (k_srht.hip) -------------------------------------------------
+// n' = the power of two >= n; scratch: srht_scratch_bytes(n, d).
+// sx = (1/sqrt(r)) P H D X times colfac[j] per column (nullable); dense input
+// (dtype 0 F64, 1 F32, 2 BF16, 3 FP8 codes). -1 when r > n'.
+int64_t srht_rows_padded(int64_t n);
+size_t srht_scratch_bytes(int64_t n, int64_t d);
+int launch_srht(const void* x, int dtype, int64_t n, int64_t d, int64_t ld,
+                uint64_t seed, int64_t r, const double* colfac, void* scratch,
+                double* sx, hipStream_t s);
+
 // ---- sampling policies (k_sample.hip) ---------------------------------------
 // dec-swor: keys[i] = bits of E_i / L_i (FP32, +inf for probability 0), to be
 // sorted ascending with the row index as the value.

@@ -269,10 +269,17 @@ int sketch_nnz(const slso_options& o) {
 double sketch_scale(int nnz) {
   return nnz <= 1 ? 1.0 : 1.0 / std::sqrt(static_cast<double>(nnz));
 }
-int check_sketch_kind(slso_ctx* c, const slso_options& o, int64_t r) {
+int check_sketch_kind(slso_ctx* c, const slso_options& o, int64_t r,
+                      const slso_matrix* X) {
   if (o.sketch != SLSO_COUNTSKETCH && o.sketch != SLSO_GAUSSIAN &&
-      o.sketch != SLSO_OSNAP)
+      o.sketch != SLSO_OSNAP && o.sketch != SLSO_SRHT)
     return set_err(c, SLSO_EINVAL, "unknown sketch kind");
+  if (o.sketch == SLSO_SRHT) {
+    if (X->format != SLSO_DENSE)
+      return set_err(c, SLSO_EUNSUPPORTED, "the SRHT takes dense input");
+    if (r > srht_rows_padded(X->n))
+      return set_err(c, SLSO_EINVAL, "SRHT needs r <= n rounded up to a power of two");
+  }
   if ((o.flags & ~SLSO_OPT_SVD_RANK) != 0)
     return set_err(c, SLSO_EINVAL, "unknown option flags");
   if (o.sketch == SLSO_OSNAP) {
@@ -332,15 +339,18 @@ size_t gemm_partial_bytes(const slso_matrix* X, int64_t r, bool gauss,
 // Workspace of slso_leverage; the arena in slso_leverage takes the same
 // buffers in the same order.
 size_t leverage_ws_bytes(const slso_matrix* X, int64_t r, int64_t k,
-                         int nnz, bool refine) {
+                         const slso_options& o) {
   const int64_t n = X->n, d = X->d;
   const int64_t kk = k == 0 ? d : k;
-  const bool gauss = nnz == 0;
+  const int nnz = sketch_nnz(o);
+  const bool gauss = o.sketch == SLSO_GAUSSIAN;
+  const bool refine = o.refine == 1;
   Sizer z;
-  if (!gauss) {
+  if (nnz > 0) {
     size_sketch_bufs(z, n * nnz, r);
     z.take<float>(countsketch_colmax_groups(r) * d);  // column maxima parts
   }
+  if (o.sketch == SLSO_SRHT) z.take<char>(srht_scratch_bytes(n, d));
   z.take<uint64_t>(d);             // colmax bits
   z.take<double>(d);               // dscale D
   z.take<double>(d);               // D * col_scale (FP8)
@@ -376,7 +386,7 @@ int check_leverage(slso_ctx* c, const slso_matrix* X, int64_t r, int64_t k,
   if (k < 0) return set_err(c, SLSO_EINVAL, "k must be >= 0");
   *o = slso_options{};
   if (opt) *o = *opt;
-  if ((st = check_sketch_kind(c, *o, r))) return st;
+  if ((st = check_sketch_kind(c, *o, r, X))) return st;
   if (o->refine != 0 && o->refine != 1)
     return set_err(c, SLSO_EINVAL, "refine must be 0 or 1");
   if ((o->sketch == SLSO_GAUSSIAN || o->refine == 1) && !mfma_input(X))
@@ -483,7 +493,7 @@ int slso_sketch(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   if (!sx) return set_err(c, SLSO_EINVAL, "sx is NULL");
   slso_options o{};
   if (opt) o = *opt;
-  if ((st = check_sketch_kind(c, o, r))) return st;
+  if ((st = check_sketch_kind(c, o, r, X))) return st;
   const int kind = o.sketch;
   const int nnz = sketch_nnz(o);
   if (kind == SLSO_GAUSSIAN && !mfma_input(X))
@@ -492,7 +502,10 @@ int slso_sketch(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   SLSO_HIP(c, hipSetDevice(c->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   Sizer z;
-  if (nnz > 0) {
+  if (kind == SLSO_SRHT) {
+    z.take<char>(srht_scratch_bytes(X->n, X->d));
+    z.take<double>(X->d);
+  } else if (nnz > 0) {
     size_sketch_bufs(z, X->n * nnz, r);
     z.take<double>(X->d);
   } else {
@@ -501,7 +514,15 @@ int slso_sketch(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   if ((st = ensure_ws(c, z.off))) return st;
   WsMark mark_{c, s};
   Arena a{static_cast<char*>(c->ws)};
-  if (nnz > 0) {
+  if (kind == SLSO_SRHT) {
+    void* ws = a.take<char>(srht_scratch_bytes(X->n, X->d));
+    double* cs = a.take<double>(X->d);
+    if (X->dtype == SLSO_FP8_E4M3)
+      launch_mul_scale(nullptr, X->col_scale, X->d, cs, s);
+    if (launch_srht(X->values, X->dtype, X->n, X->d, X->ld, seed, r,
+                    X->dtype == SLSO_FP8_E4M3 ? cs : nullptr, ws, sx, s) != 0)
+      return set_err(c, SLSO_EINVAL, "SRHT needs r <= n'");
+  } else if (nnz > 0) {
     SketchBufs b = take_sketch_bufs(a, X->n * nnz, r);
     double* cs = a.take<double>(X->d);
     if (X->dtype == SLSO_FP8_E4M3)
@@ -668,16 +689,18 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
 
   const size_t gemm_part = gemm_partial_bytes(X, r, gauss, refine);
   Sizer z;
-  z.off = leverage_ws_bytes(X, r, k, nnz, refine);
+  z.off = leverage_ws_bytes(X, r, k, o);
   if ((st = ensure_ws(c, z.off))) return st;
   WsMark mark_{c, s};
   Arena a{static_cast<char*>(c->ws)};
   SketchBufs sb{};
   float* cparts = nullptr;
-  if (!gauss) {
+  if (nnz > 0) {
     sb = take_sketch_bufs(a, n * nnz, r);
     cparts = a.take<float>(countsketch_colmax_groups(r) * d);
   }
+  const bool srht = o.sketch == SLSO_SRHT;
+  void* srht_ws = srht ? a.take<char>(srht_scratch_bytes(n, d)) : nullptr;
   uint64_t* colmax = a.take<uint64_t>(d);
   double* dscale = a.take<double>(d);
   double* eff = a.take<double>(d);
@@ -702,11 +725,11 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   // Dense F32 / BF16 / FP8 input: the column maxima are taken in the
   // CountSketch's own pass over X, and D is applied by the QR as it reads the
   // sketch (exact: powers of two). Otherwise a pass of its own comes first.
-  const bool fuse = !gauss && countsketch_colmax_ok(X->values, X->dtype,
-                                                    X->format, X->ld);
+  const bool fuse = nnz > 0 && countsketch_colmax_ok(X->values, X->dtype,
+                                                     X->format, X->ld);
   // 0. the bucket partition needs no input values: without the fused pass it
   // runs on the context's second stream while the column maxima are taken
-  const bool side_partition = !gauss && !fuse && c->qs.side;
+  const bool side_partition = nnz > 0 && !fuse && c->qs.side;
   if (side_partition) {
     SLSO_HIP(c, hipEventRecord(c->qs.factored, s));
     SLSO_HIP(c, hipStreamWaitEvent(c->qs.side, c->qs.factored, 0));
@@ -737,6 +760,11 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
     if (gauss) {
       launch_gauss_sketch(X->values, X->dtype, n, d, X->ld, X->col_scale, seed,
                           r, dscale, static_cast<float*>(gpart), sx, s);
+      return;
+    }
+    if (srht) {
+      (void)launch_srht(X->values, X->dtype, n, d, X->ld, seed, r, rowfac,
+                        srht_ws, sx, s);
       return;
     }
     if (!partitioned) {
@@ -893,7 +921,7 @@ int slso_workspace_size(const slso_matrix* X, int64_t r, int64_t k,
   const int st = check_leverage(nullptr, X, r, k, opt, &o);
   if (st) return st;
   *bytes = ws_alloc_bytes(std::max(
-      leverage_ws_bytes(X, r, k, sketch_nnz(o), o.refine == 1),
+      leverage_ws_bytes(X, r, k, o),
       order_ws_bytes(X->n)));
   return SLSO_OK;
 }

@@ -112,8 +112,21 @@ def test_osnap_argument_errors(lib):
     assert _ws(lib, m, 16, 4, sketch=slso.OSNAP, nnz=-1)[0] == slso.EINVAL
     assert _ws(lib, m, 16, 4, flags=2)[0] == slso.EINVAL                  # unknown flag
     assert _ws(lib, m, 16, 4, flags=slso.OPT_SVD_RANK)[0] == slso.OK
-    assert _ws(lib, m, 16, 4, sketch=3)[0] == slso.EINVAL
+    assert _ws(lib, m, 16, 4, sketch=4)[0] == slso.EINVAL                # unknown sketch
     assert _ws(lib, m, 16, 4, sketch=slso.OSNAP, nnz=16)[0] == slso.OK
+
+
+def test_srht_sizes_and_errors(lib):
+    m = _mat(100, 10)                                     # n' = 128
+    st, b = _ws(lib, m, 128, 4, sketch=slso.SRHT)
+    assert st == slso.OK and b >= 128 * 10 * 8 + 128 * 10 * 8
+    assert _ws(lib, m, 129, 4, sketch=slso.SRHT)[0] == slso.EINVAL      # r > n'
+    c = _mat(100, 10, fmt=slso.CSR)
+    c.row_ptr = ctypes.cast(0x3000, ctypes.c_void_p)     # never dereferenced
+    c.col_idx = ctypes.cast(0x4000, ctypes.c_void_p)
+    c.nnz = 10
+    assert _ws(lib, c, 64, 4)[0] == slso.OK
+    assert _ws(lib, c, 64, 4, sketch=slso.SRHT)[0] == slso.EUNSUPPORTED
 
 
 def test_workspace_size_argument_errors(lib):

@@ -174,6 +174,16 @@ def test_osnap_leverage_reduced_precision(slso, ctx, kind):
     assert _report(f"osnap lev {kind}", host(got), ref["scores"]) < 1e-5
 
 
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+def test_srht_leverage_reduced_precision(slso, ctx, kind):
+    x64 = synth.config0(n=20000, d=64, seed=25)
+    xin, xval, _ = as_input(slso, x64, kind)
+    got, info = ctx.leverage(xin, 6, 4096, 32, sketch=slso.SRHT)
+    ref = olv.sketched_leverage(xval, 6, 4096, 32, kind="srht")
+    assert info["rank"] == ref["rank"]
+    assert _report(f"srht lev {kind}", host(got), ref["scores"]) < 1e-5
+
+
 # ---- refinement ---------------------------------------------------------------------
 @pytest.fixture(scope="module")
 def precision_case():

@@ -160,6 +160,31 @@ def test_osnap_rejects_bad_nnz(slso, ctx):
         assert ei.value.status == slso.EINVAL
 
 
+# ---- SRHT ----------------------------------------------------------------------
+@pytest.mark.parametrize("n,d,r,f32", [(5000, 64, 512, False), (3000, 100, 1024, True),
+                                       (1, 1, 1, False), (257, 5, 512, False),
+                                       (70000, 64, 4096, True)])
+def test_srht_bit_exact(slso, ctx, n, d, r, f32):
+    """(1/sqrt(r)) P H D X: the same Sylvester stages in the same order as
+    the oracle, so every FP64 value agrees exactly (passes of 8 stages: one,
+    two and three passes here)."""
+    x = synth.image_like(n, d, seed=n) if f32 else \
+        (synth.config0(n=n, d=d, seed=n) if n > 1 else np.full((1, 1), 3.0))
+    sx = host(ctx.sketch(dev(x), 29, r, sketch=slso.SRHT))
+    assert np.array_equal(sx, osk.srht_dense(x, 29, r))
+
+
+def test_srht_rejects_bad_arguments(slso, ctx):
+    x = dev(synth.config0(n=500, d=8, seed=1))             # n' = 512
+    with pytest.raises(slso.SlsoError) as ei:
+        ctx.sketch(x, 1, 513, sketch=slso.SRHT)
+    assert ei.value.status == slso.EINVAL
+    c = synth.text_like_csr(1000, 50, seed=3)
+    with pytest.raises(slso.SlsoError) as ei:
+        ctx.sketch(csr_dev(slso, c), 1, 256, sketch=slso.SRHT)
+    assert ei.value.status == slso.EUNSUPPORTED
+
+
 # ---- QR ------------------------------------------------------------------------
 @pytest.mark.parametrize("m,d", [(64, 64), (100, 37), (256, 32), (257, 33),
                                  (1000, 96), (3000, 200), (5000, 64),

@@ -115,6 +115,16 @@ def test_osnap_leverage(slso, ctx, d, nnz):
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("n,d,r", [(6000, 128, 2048), (60000, 784, 16384)])
+def test_srht_leverage(slso, ctx, n, d, r):
+    x = synth.image_like(n, d, seed=d + 1)
+    got, info = ctx.leverage(dev(x), 33, r, 32, sketch=slso.SRHT)
+    ref = olv.sketched_leverage(x, 33, r, 32, kind="srht")
+    assert info["rank"] == ref["rank"]
+    err, _ = _report(f"srht n={n} d={d}", host(got), ref["scores"])
+    assert err < 1e-5
+
+
 def test_osnap_csr_leverage(slso, ctx):
     c = synth.text_like_csr(30000, 800, seed=7)
     xc = slso.CsrMatrix(c.n, c.d, dev(c.row_ptr.astype(np.int64)),
