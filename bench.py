@@ -288,10 +288,10 @@ def main() -> int:
                     default="image",
                     help="image: the image-like single-job workload (default); "
                          "serving: a Poisson stream of mixed jobs")
-    ap.add_argument("--sketch", choices=("countsketch", "osnap"),
+    ap.add_argument("--sketch", choices=("countsketch", "osnap", "srht"),
                     default="countsketch",
-                    help="image: the hashed sketch (OSNAP: --nnz nonzeros per "
-                         "column of S)")
+                    help="image: the sketch (OSNAP: --nnz nonzeros per column "
+                         "of S)")
     ap.add_argument("--nnz", type=int, default=2,
                     help="image, --sketch osnap: nonzeros per column of S")
     ap.add_argument("--rates", default="50,200,800",
@@ -336,7 +336,8 @@ def main() -> int:
     stream = torch.cuda.current_stream()
 
     osnap = args.sketch == "osnap"
-    kind = slso.OSNAP if osnap else slso.COUNTSKETCH
+    kind = {"countsketch": slso.COUNTSKETCH, "osnap": slso.OSNAP,
+            "srht": slso.SRHT}[args.sketch]
     nnz = args.nnz if osnap else 0
 
     def step():
@@ -406,7 +407,9 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "image-like dense FP32 X (n=60000, d=784, "
                                "values in [0,1], rank 50 + noise, 10 clusters); "
-                               + (f"OSNAP (s={nnz}) " if osnap else "CountSketch ")
+                               + {"countsketch": "CountSketch ",
+                                  "osnap": f"OSNAP (s={nnz}) ",
+                                  "srht": "SRHT "}[args.sketch]
                                + "r=16384, FP64 QR, k=64, scores + dec ordering",
                    "n": N, "d": D, "r": R, "k": K, "seed": SEED,
                    "rank": int(info["rank"])},
@@ -436,8 +439,7 @@ def main() -> int:
         reps, t_cpu, ref = 0, 0.0, None
         while reps < 3 and t_cpu < 20.0:
             tc = time.perf_counter()
-            ref = olv.sketched_leverage(x_host, SEED, R, K,
-                                        kind="osnap" if osnap else "countsketch",
+            ref = olv.sketched_leverage(x_host, SEED, R, K, kind=args.sketch,
                                         nnz=max(nnz, 1))
             oorder.dec_order(ref["scores"].astype(np.float32))
             t_cpu += time.perf_counter() - tc

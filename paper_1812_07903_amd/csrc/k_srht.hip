@@ -75,6 +75,7 @@ __global__ void __launch_bounds__(256)
                      int k, const int32_t* __restrict__ tmap, double cscale,
                      const double* __restrict__ colfac, double* __restrict__ sx) {
   __shared__ double Y[1 << kHB][kHC + 1];
+  __shared__ double sgn[1 << kHB];
   const int t = threadIdx.x, c = t % kHC, g = t / kHC;  // 8 row groups
   const int rows = 1 << k;
   const int64_t q = blockIdx.x;
@@ -82,21 +83,42 @@ __global__ void __launch_bounds__(256)
   const int64_t base = (hi << (s + k)) | lo;
   const int64_t col = static_cast<int64_t>(blockIdx.y) * kHC + c;
   const bool okc = col < d;
-  // load (branch-free: rows past n and columns past d read a clamped
-  // address and become zero)
-  for (int m = g; m < rows; m += 256 / kHC) {
-    const int64_t row = base + (static_cast<int64_t>(m) << s);
-    double v;
+  if (kFirst) {
+    // the rows' signs, once per row (zero past n)
+    for (int m = t; m < rows; m += 256) {
+      const int64_t row = base + (static_cast<int64_t>(m) << s);
+      sgn[m] = row >= n ? 0.0
+               : ((poly61(hs, static_cast<uint64_t>(row)) & 1u) ? -1.0 : 1.0);
+    }
+    __syncthreads();
+  }
+  // load without branches (a row past the set, past n or a column past d
+  // reads a clamped address and becomes zero), every load issued before any
+  // is stored, so they are in flight together
+  constexpr int kPer = (1 << kHB) / (256 / kHC);  // rows per thread
+  double v[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int m = g + (256 / kHC) * u;
+    const int mm = m < rows ? m : rows - 1;
+    const int64_t row = base + (static_cast<int64_t>(mm) << s);
     if (kFirst) {
       const bool ok = okc && row < n;
-      const double xv = SrhtIn<T>::get(x, ok ? row * ld + col : 0);
-      const double sg = (poly61(hs, static_cast<uint64_t>(row)) & 1u) ? -1.0 : 1.0;
-      v = ok ? sg * xv : 0.0;
+      v[u] = SrhtIn<T>::get(x, ok ? row * ld + col : 0);
     } else {
-      const double yv = yin[okc ? row * d + col : 0];
-      v = okc ? yv : 0.0;
+      v[u] = yin[okc ? row * d + col : 0];
     }
-    Y[m][c] = v;
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int m = g + (256 / kHC) * u;
+    if (m < rows) {
+      const int64_t row = base + (static_cast<int64_t>(m) << s);
+      if (kFirst)
+        Y[m][c] = (okc && row < n) ? sgn[m] * v[u] : 0.0;
+      else
+        Y[m][c] = okc ? v[u] : 0.0;
+    }
   }
   __syncthreads();
   for (int b = 0; b < k; ++b) {
@@ -122,6 +144,109 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// A full pass of 8 stages with few LDS trips: thread (g, c) first holds the
+// 32 consecutive rows 32 g .. 32 g + 31 of column c and applies stages 0-4 in
+// registers; through LDS, thread (l, cc) then holds rows l + 32 v (v < 8) of
+// columns cc + 8 w (w < 4) and applies stages 5-7; back through LDS for
+// coalesced stores. The stages still run in increasing order, on the same
+// pairs, so the values are those of fwht_pass_kernel.
+template <typename T, bool kFirst, bool kLast>
+__global__ void __launch_bounds__(256)
+    fwht8_kernel(const T* __restrict__ x, int64_t n, int64_t ld,
+                 HashCoeffs hs, const double* __restrict__ yin,
+                 double* __restrict__ yout, int64_t d, int s,
+                 const int32_t* __restrict__ tmap, double cscale,
+                 const double* __restrict__ colfac, double* __restrict__ sx) {
+  __shared__ double Y[256][kHC + 1];
+  __shared__ double sgn[256];
+  const int t = threadIdx.x;
+  const int g = t / kHC, c = t % kHC;      // layout A
+  const int l = t % 32, cc = t / 32;       // layout B
+  const int64_t q = blockIdx.x;
+  const int64_t lo = q & ((int64_t{1} << s) - 1), hi = q >> s;
+  const int64_t base = (hi << (s + 8)) | lo;
+  const int64_t col0 = static_cast<int64_t>(blockIdx.y) * kHC;
+  const int64_t col = col0 + c;
+  const bool okc = col < d;
+  if (kFirst) {
+    const int64_t row = base + (static_cast<int64_t>(t) << s);
+    sgn[t] = row >= n ? 0.0
+             : ((poly61(hs, static_cast<uint64_t>(row)) & 1u) ? -1.0 : 1.0);
+  }
+  double v[32];
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    const int64_t row = base + (static_cast<int64_t>(32 * g + u) << s);
+    if (kFirst) {
+      const bool ok = okc && row < n;
+      v[u] = SrhtIn<T>::get(x, ok ? row * ld + col : 0);
+    } else {
+      v[u] = yin[okc ? row * d + col : 0];
+    }
+  }
+  if (kFirst) __syncthreads();  // sgn
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    if (kFirst) {
+      const int64_t row = base + (static_cast<int64_t>(32 * g + u) << s);
+      v[u] = (okc && row < n) ? sgn[32 * g + u] * v[u] : 0.0;
+    } else {
+      v[u] = okc ? v[u] : 0.0;
+    }
+  }
+  // stages 0-4 (row bits 0-4: inside the thread)
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      if (u & (1 << b)) continue;
+      const double a = v[u], e = v[u + (1 << b)];
+      v[u] = a + e;
+      v[u + (1 << b)] = a - e;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 32; ++u) Y[32 * g + u][c] = v[u];
+  __syncthreads();
+  // stages 5-7 (row bits 5-7) in layout B
+  double z[8][4];
+#pragma unroll
+  for (int vv = 0; vv < 8; ++vv)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) z[vv][w] = Y[l + 32 * vv][cc + 8 * w];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+#pragma unroll
+    for (int vv = 0; vv < 8; ++vv) {
+      if (vv & (1 << b)) continue;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const double a = z[vv][w], e = z[vv + (1 << b)][w];
+        z[vv][w] = a + e;
+        z[vv + (1 << b)][w] = a - e;
+      }
+    }
+  }
+#pragma unroll
+  for (int vv = 0; vv < 8; ++vv)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) Y[l + 32 * vv][cc + 8 * w] = z[vv][w];
+  __syncthreads();
+  if (!okc) return;
+  const double cf = kLast && colfac ? colfac[col] : 1.0;
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    const int64_t row = base + (static_cast<int64_t>(32 * g + u) << s);
+    const double y = Y[32 * g + u][c];
+    if (kLast) {
+      const int32_t tt = tmap[row];
+      if (tt >= 0) sx[static_cast<int64_t>(tt) * d + col] = y * cscale * cf;
+    } else {
+      yout[row * d + col] = y;
+    }
+  }
+}
+
 inline unsigned grid1(int64_t n, int t) {
   return static_cast<unsigned>((n + t - 1) / t);
 }
@@ -138,6 +263,21 @@ void run_passes(const T* x, int64_t n, int64_t d, int64_t ld,
     const int k = L - s0 < kHB ? L - s0 : kHB;
     const dim3 grid(static_cast<unsigned>(n2 >> k), gy);
     const bool first = p == 0, last = p == passes - 1;
+    if (k == kHB) {
+      if (first && last)
+        fwht8_kernel<T, true, true><<<grid, 256, 0, s>>>(
+            x, n, ld, hs, nullptr, nullptr, d, s0, tmap, cscale, colfac, sx);
+      else if (first)
+        fwht8_kernel<T, true, false><<<grid, 256, 0, s>>>(
+            x, n, ld, hs, nullptr, y, d, s0, nullptr, 1.0, nullptr, nullptr);
+      else if (last)
+        fwht8_kernel<double, false, true><<<grid, 256, 0, s>>>(
+            nullptr, n, ld, hs, y, nullptr, d, s0, tmap, cscale, colfac, sx);
+      else
+        fwht8_kernel<double, false, false><<<grid, 256, 0, s>>>(
+            nullptr, n, ld, hs, y, y, d, s0, nullptr, 1.0, nullptr, nullptr);
+      continue;
+    }
     if (first && last)
       fwht_pass_kernel<T, true, true><<<grid, 256, 0, s>>>(
           x, n, ld, hs, nullptr, nullptr, n2, d, s0, k, tmap, cscale, colfac, sx);
@@ -189,11 +329,12 @@ int launch_srht(const void* x, int dtype, int64_t n, int64_t d, int64_t ld,
   uint32_t* vals_t = reinterpret_cast<uint32_t*>(take(n2 * 4));
   int32_t* tmap = reinterpret_cast<int32_t*>(take(n2 * 4));
   void* sws = take(radix_sort_scratch_bytes(n2));
-  prof_begin(kKSketch, s);
+  // the row choice (its sort is profiled as the sort's own groups)
   srht_keys_kernel<<<grid1(n2, 256), 256, 0, s>>>(seed, n2, keys);
   radix_sort_pairs(keys, nullptr, keys_o, order, keys_t, vals_t, n2, 32, sws, s);
   launch_fill_i32(tmap, n2, -1, s);
   srht_tmap_kernel<<<grid1(r, 256), 256, 0, s>>>(order, r, tmap);
+  prof_begin(kKSketch, s);
   const HashCoeffs hs = make_hash_coeffs(seed, kStreamSrhtSign);
   const double cscale = 1.0 / std::sqrt(static_cast<double>(r));
   switch (dtype) {

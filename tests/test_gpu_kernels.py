@@ -163,11 +163,12 @@ def test_osnap_rejects_bad_nnz(slso, ctx):
 # ---- SRHT ----------------------------------------------------------------------
 @pytest.mark.parametrize("n,d,r,f32", [(5000, 64, 512, False), (3000, 100, 1024, True),
                                        (1, 1, 1, False), (257, 5, 512, False),
-                                       (70000, 64, 4096, True)])
+                                       (70000, 64, 4096, True),
+                                       (200, 7, 128, False), (40000, 96, 2048, True)])
 def test_srht_bit_exact(slso, ctx, n, d, r, f32):
     """(1/sqrt(r)) P H D X: the same Sylvester stages in the same order as
-    the oracle, so every FP64 value agrees exactly (passes of 8 stages: one,
-    two and three passes here)."""
+    the oracle, so every FP64 value agrees exactly (passes of up to 8 stages:
+    one, two and three passes, full and partial, here)."""
     x = synth.image_like(n, d, seed=n) if f32 else \
         (synth.config0(n=n, d=d, seed=n) if n > 1 else np.full((1, 1), 3.0))
     sx = host(ctx.sketch(dev(x), 29, r, sketch=slso.SRHT))
