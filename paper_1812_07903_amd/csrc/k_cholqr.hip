@@ -738,7 +738,8 @@ __global__ void __launch_bounds__(256)
 // chunks are added in order. MODE 0 takes T's tiles as stored; MODE 1 forms
 // T = I - up(G - I) from the tiles of a Gram matrix G close to I (the first
 // two terms of (I + up(G - I))^{-1}; the next is below d max|G - I|^2).
-constexpr int64_t kCH = 3;
+constexpr int64_t kCH = 1;  // one tile product per workgroup: the products
+                            // are latency bound, so more workgroups win
 
 __host__ __device__ inline int64_t tri_chunks(int64_t nb, int64_t I) {
   return (nb - I + kCH - 1) / kCH;
