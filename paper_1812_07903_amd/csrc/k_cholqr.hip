@@ -549,8 +549,9 @@ __device__ __forceinline__ void stagen_store(double* tile, const StageN<N>& s,
     tile[(e >> 6) * kS + (e & 63)] = ((s.ok >> u) & 1u) ? s.v[u] : 0.0;
   }
 }
-// acc (+)= A B on the wave's 16 x 32 part (kWR row groups)
-template <bool SUB, int kWR>
+// acc (+)= A B on the wave's 16 x 32 part (kWR row groups); NBJ < 2: only
+// its first NBJ 16-column blocks (the others lie past the matrix)
+template <bool SUB, int kWR, int NBJ = 2>
 __device__ __forceinline__ void mm_stripe(const double* A, const double* B,
                                           dbl4 (&acc)[2], int lane, int w) {
   const int p = lane & 15, q = lane >> 4, wr = w % kWR, wc = w / kWR;
@@ -564,14 +565,25 @@ __device__ __forceinline__ void mm_stripe(const double* A, const double* B,
       const int k = 4 * (k0 + kk) + q;
       a[kk] = A[(16 * wr + p) * kS + k];
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) b[kk][bj] = B[k * kS + 32 * wc + 16 * bj + p];
+      for (int bj = 0; bj < NBJ; ++bj) b[kk][bj] = B[k * kS + 32 * wc + 16 * bj + p];
     }
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
+      for (int bj = 0; bj < NBJ; ++bj)
         acc[bj] = mfma(SUB ? -a[kk] : a[kk], b[kk][bj], acc[bj]);
   }
+}
+// the product on the columns below nc only (whole-wave choice)
+template <bool SUB, int kWR>
+__device__ __forceinline__ void mm_stripe_nc(const double* A, const double* B,
+                                             dbl4 (&acc)[2], int lane, int w,
+                                             int64_t nc) {
+  const int wc = w / kWR;
+  if (32 * wc + 16 < nc)
+    mm_stripe<SUB, kWR, 2>(A, B, acc, lane, w);
+  else if (32 * wc < nc)
+    mm_stripe<SUB, kWR, 1>(A, B, acc, lane, w);
 }
 
 template <int kR>
@@ -632,7 +644,7 @@ __global__ void __launch_bounds__(8 * kR)
         stagen_load<kNA, kT>(va, As + (I + 1) * kP, lda, nr, kP, t);
         stagen_load<kNB, kT>(vb, R + tix(I + 1, J, nb), kP, kP, kP, t);
       }
-      mm_stripe<true, kWR>(TA, TB, acc, lane, w);
+      mm_stripe_nc<true, kWR>(TA, TB, acc, lane, w, nc);
     }
     stagen_load<kNB, kT>(vb, Dinv + J * kT2, kP, kP, kP, t);
     __syncthreads();
@@ -645,7 +657,7 @@ __global__ void __launch_bounds__(8 * kR)
     __syncthreads();
     dbl4 res[2];
     res[0] = res[1] = dbl4{0.0, 0.0, 0.0, 0.0};
-    mm_stripe<false, kWR>(TA, TB, res, lane, w);
+    mm_stripe_nc<false, kWR>(TA, TB, res, lane, w, nc);
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
