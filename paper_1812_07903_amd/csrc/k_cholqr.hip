@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(256)
 // With X, k more workgroups finish block column k of X = R^{-1}, and
 // k (nb - k - 1) more add the term l = k - 1 to the running sums P_ij.
 __global__ void __launch_bounds__(256)
-    bchol_step_kernel(double* __restrict__ G, int64_t nb, int64_t k,
+    bchol_step_kernel(double* __restrict__ G, int64_t nb, int64_t k, int64_t d,
                       const double* __restrict__ gdiag, double tol,
                       double* __restrict__ R, double* __restrict__ Dinv,
                       double* __restrict__ X, double* __restrict__ P,
@@ -497,7 +497,9 @@ __global__ void __launch_bounds__(256)
     store_acc(TC, acc, 1.0, lane, w);
     if (t < kP) lim[t] = tol * gdiag[i * kP + t];
     __syncthreads();
-    if (!chol64b(TC, TI, lim, &bad, tmp, t)) {
+    const int64_t nv = d - i * kP;  // columns of the tile inside the matrix
+    const int nblk = nv >= kP ? 4 : static_cast<int>((nv + 15) / 16);
+    if (!chol64b(TC, TI, lim, &bad, tmp, t, nblk)) {
       if (t == 0) *flag = 1;
       return;
     }
@@ -884,7 +886,7 @@ __global__ void __launch_bounds__(256)
 }
 
 struct Cq2 {
-  int64_t nb, nt, S, chunk, Se, chunk_e, nfull, nedge;
+  int64_t d, nb, nt, S, chunk, Se, chunk_e, nfull, nedge;
   bool fe;  // edge products formed by the diagonal blocks (no edge launch)
   double *part, *G, *R1, *R2, *X1, *X2, *P, *Dinv, *gdiag, *apart;
   unsigned long long* emax;
@@ -892,6 +894,7 @@ struct Cq2 {
 
 Cq2 cq2_shape(int64_t m, int64_t d) {
   Cq2 c{};
+  c.d = d;
   c.nb = (d + kP - 1) / kP;
   c.nt = c.nb * (c.nb + 1) / 2;
   // Gram row chunks: blocks of full 128-column blocks take at most 512
@@ -969,7 +972,7 @@ void bchol(const Cq2& c, double* R, double* X, int* flag, hipStream_t s) {
     const int64_t n = c.nb - k - 1;
     const int64_t grid = n * (n + 1) / 2 + (X ? k + k * n : 0);
     bchol_step_kernel<<<static_cast<unsigned>(grid), 256, 0, s>>>(
-        c.G, c.nb, k, c.gdiag, kPivotTol, R, c.Dinv, X, c.P, flag);
+        c.G, c.nb, k, c.d, c.gdiag, kPivotTol, R, c.Dinv, X, c.P, flag);
   }
   if (X && c.nb > 1)
     binv_col_kernel<<<static_cast<unsigned>(c.nb - 1), 256, 0, s>>>(

@@ -363,8 +363,11 @@ __device__ __forceinline__ void zero_tile(double* X, int t) {
 // running sums P_rj in registers and, while wave 0 factors diagonal block k,
 // finishes X_r,k-1 and adds the terms m = k - 1 (block row k - 1 of R is
 // final by then), so the inverse costs no step of its own.
+// nblk < 4: the diagonal blocks from nblk on are padding (identity in G,
+// untouched by the updates, since the rows above them are zero there), so
+// their Cholesky is the identity and is written, not computed.
 __device__ __forceinline__ bool chol64b(double* G, double* X, const double* lim, int* bad,
-                        double (*tmp)[16][17], int t) {
+                        double (*tmp)[16][17], int t, int nblk = 4) {
   const int lane = t & 63, w = t >> 6, p = lane & 15, q = lane >> 4;
   const int r = w - 1;
   zero_tile(X, t);
@@ -388,8 +391,12 @@ __device__ __forceinline__ bool chol64b(double* G, double* X, const double* lim,
   for (int k = 0; k < 4; ++k) {
     const int o = 16 * k;
     if (w == 0) {
-      const bool ok = chol16x(&G[o * kS + o], &X[o * kS + o], lim + o, lane);
-      if (!ok && lane == 0) *bad = 1;
+      if (k < nblk) {
+        const bool ok = chol16x(&G[o * kS + o], &X[o * kS + o], lim + o, lane);
+        if (!ok && lane == 0) *bad = 1;
+      } else if (lane < 16) {
+        X[(o + lane) * kS + o + lane] = 1.0;
+      }
     } else if (k > 0 && r <= k - 1) {
       const int m = k - 1;
       if (r < m) finish(m, pacc[m]);
