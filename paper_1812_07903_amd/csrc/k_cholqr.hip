@@ -588,6 +588,14 @@ __device__ __forceinline__ void mm_stripe_nc(const double* A, const double* B,
     mm_stripe<SUB, kWR, 1>(A, B, acc, lane, w);
 }
 
+// The products of a stripe form one sequence of phases: for each J the terms
+// I = 0 .. J - 1 (operands Q1_I and R_IJ), then the diagonal one (the
+// accumulated block times R_JJ^{-1}). The phase operands go through two LDS
+// buffers, so one barrier per phase separates the stores into one buffer from
+// the products on the other, and each phase's loads (the next block's A_J
+// included) are issued before the previous phase multiplies. The one load that
+// would read a block stored by the phase before it (Q1_0, right after the
+// diagonal phase of J = 0) is issued after that store and a barrier instead.
 template <int kR>
 __global__ void __launch_bounds__(8 * kR)
     stripe_solve_kernel(double* __restrict__ A, int64_t lda, int64_t m,
@@ -597,28 +605,19 @@ __global__ void __launch_bounds__(8 * kR)
                         const int* __restrict__ flag) {
   constexpr int kT = 8 * kR, kWR = kR / 16;
   constexpr int kNA = kR * 64 / kT, kNB = 4096 / kT;  // staged per thread
-  __shared__ double TA[kR * kS];
-  __shared__ double TB[kTile];
+  __shared__ double TA[2][kR * kS];
+  __shared__ double TB[2][kTile];
   if (*flag) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w % kWR, wc = w / kWR;
   const int p = lane & 15, q = lane >> 4;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kR;
   const int64_t nr = m - r0 < kR ? m - r0 : kR;
   double* As = A + r0 * lda;
-  for (int64_t J = 0; J < nb; ++J) {
+  // A_J (times dsc) in this thread's accumulator layout; branch-free loads
+  // (an entry outside the matrix reads a clamped address and becomes zero)
+  auto load_aj = [&](dbl4 (&x)[2], int64_t J) {
     const int64_t cJ = J * kP;
     const int64_t nc = d - cJ < kP ? d - cJ : kP;
-    // blocks I < J are complete (only the last block can be partial)
-    StageN<kNA> va;
-    StageN<kNB> vb;
-    if (J > 0) {
-      stagen_load<kNA, kT>(va, As, lda, nr, kP, t);
-      stagen_load<kNB, kT>(vb, R + tix(0, J, nb), kP, kP, kP, t);
-    }
-    // A_J (times dsc), loaded after the staged blocks and without branches:
-    // an entry outside the matrix reads a clamped address and is replaced by
-    // zero, so all these loads are in flight together
-    dbl4 acc[2];
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
@@ -626,7 +625,7 @@ __global__ void __launch_bounds__(8 * kR)
         const int row = 16 * wr + 4 * v + q, col = 32 * wc + 16 * bj + p;
         const bool ok = row < nr && col < nc;
         const double av = As[ok ? row * lda + cJ + col : 0];
-        acc[bj][v] = ok ? av : 0.0;
+        x[bj][v] = ok ? av : 0.0;
       }
     if (dsc) {
 #pragma unroll
@@ -634,41 +633,71 @@ __global__ void __launch_bounds__(8 * kR)
         const int col = 32 * wc + 16 * bj + p;
         const double sc = dsc[col < nc ? cJ + col : 0];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[bj][v] *= sc;
+        for (int v = 0; v < 4; ++v) x[bj][v] *= sc;
       }
     }
-    for (int64_t I = 0; I < J; ++I) {
-      __syncthreads();
-      stagen_store<kNA, kT>(TA, va, t);
-      stagen_store<kNB, kT>(TB, vb, t);
-      __syncthreads();
-      if (I + 1 < J) {
-        stagen_load<kNA, kT>(va, As + (I + 1) * kP, lda, nr, kP, t);
-        stagen_load<kNB, kT>(vb, R + tix(I + 1, J, nb), kP, kP, kP, t);
-      }
-      mm_stripe_nc<true, kWR>(TA, TB, acc, lane, w, nc);
+  };
+  StageN<kNA> va;
+  StageN<kNB> vb;
+  // phase (I, J): I < J a term, I == J the diagonal phase
+  auto issue = [&](int64_t I, int64_t J) {
+    if (I < J) {
+      stagen_load<kNA, kT>(va, As + I * kP, lda, nr, kP, t);
+      stagen_load<kNB, kT>(vb, R + tix(I, J, nb), kP, kP, kP, t);
+    } else {
+      stagen_load<kNB, kT>(vb, Dinv + J * kT2, kP, kP, kP, t);
     }
-    stagen_load<kNB, kT>(vb, Dinv + J * kT2, kP, kP, kP, t);
+  };
+  dbl4 acc[2], nacc[2];
+  load_aj(acc, 0);
+  issue(0, 0);
+  int buf = 0;
+  int64_t I = 0, J = 0;
+  while (J < nb) {
+    const int64_t nc = d - J * kP < kP ? d - J * kP : kP;
+    const bool dg = I == J;
+    if (dg) {
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          TA[buf][(16 * wr + 4 * v + q) * kS + 32 * wc + 16 * bj + p] = acc[bj][v];
+    } else {
+      stagen_store<kNA, kT>(TA[buf], va, t);
+    }
+    stagen_store<kNB, kT>(TB[buf], vb, t);
     __syncthreads();
+    // the next phase
+    const int64_t nI = dg ? 0 : I + 1, nJ = dg ? J + 1 : J;
+    const bool more = nJ < nb;
+    const bool late = dg && J == 0 && more && nI < nJ;  // reads Q1_0
+    if (more && !late) issue(nI, nJ);
+    if (dg && more) load_aj(nacc, nJ);
+    if (dg) {
+      dbl4 res[2];
+      res[0] = res[1] = dbl4{0.0, 0.0, 0.0, 0.0};
+      mm_stripe_nc<false, kWR>(TA[buf], TB[buf], res, lane, w, nc);
+      const int64_t cJ = J * kP;
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+      for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        TA[(16 * wr + 4 * v + q) * kS + 32 * wc + 16 * bj + p] = acc[bj][v];
-    stagen_store<kNB, kT>(TB, vb, t);
-    __syncthreads();
-    dbl4 res[2];
-    res[0] = res[1] = dbl4{0.0, 0.0, 0.0, 0.0};
-    mm_stripe_nc<false, kWR>(TA, TB, res, lane, w, nc);
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 16 * wr + 4 * v + q, col = 32 * wc + 16 * bj + p;
-        if (row < nr && col < nc) As[row * lda + cJ + col] = res[bj][v];
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * wr + 4 * v + q, col = 32 * wc + 16 * bj + p;
+          if (row < nr && col < nc) As[row * lda + cJ + col] = res[bj][v];
+        }
+      if (late) {
+        // Q1_0 is read back by other threads of the workgroup
+        __syncthreads();
+        issue(nI, nJ);
       }
-    // Q1_J is read back by other threads of the workgroup for later blocks
-    __syncthreads();
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc[bj] = nacc[bj];
+    } else {
+      mm_stripe_nc<true, kWR>(TA[buf], TB[buf], acc, lane, w, nc);
+    }
+    buf ^= 1;
+    I = nI;
+    J = nJ;
   }
 }
 
