@@ -436,6 +436,79 @@ __global__ void __launch_bounds__(256)
   xinv_finish(blockIdx.x, k, nb, R, Dinv, X, P, TA, TB, threadIdx.x);
 }
 
+// The step's diagonal workgroup (tile (k + 1, k + 1)), which the next step
+// waits for: X = R_kk^{-T} G_k,k+1 by column strips (wave w forms columns
+// 16 w .. 16 w + 15; row block rb of R_kk^{-T} is zero past column block rb,
+// so each wave does 40 of the 64 MFMA blocks), then G_k+1,k+1 - X^T X on the
+// upper 16 x 16 blocks only (the factorisation reads no others): three or
+// two blocks per wave. TI holds R_kk^{-1}, TA G_k,k+1; TC receives the
+// updated tile (lower blocks undefined).
+__device__ __forceinline__ void bchol_lead(const double* TI, double* TA, double* TC,
+                                           const double* __restrict__ Gd,
+                                           double* __restrict__ Rg, int lane, int w) {
+  const int p = lane & 15, q = lane >> 4;
+  // the tile's own blocks, (rb, cb) = kUp[w + 4 u]
+  constexpr int kUpR[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+  constexpr int kUpC[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+  dbl4 g[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int b = w + 4 * u < 10 ? w + 4 * u : 9;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      g[u][v] = Gd[(16 * kUpR[b] + 4 * v + q) * kP + 16 * kUpC[b] + p];
+  }
+  dbl4 x[4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) x[rb] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k0 = 0; k0 < 4; ++k0) {
+    // column block k0 of R_kk^{-T} feeds row blocks rb >= k0
+    double b[4], a[4][4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 16 * k0 + 4 * kk + q;
+      b[kk] = TA[k * kS + 16 * w + p];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+        if (rb >= k0) a[kk][rb] = TI[k * kS + 16 * rb + p];
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+        if (rb >= k0) x[rb] = mfma(a[kk][rb], b[kk], x[rb]);
+  }
+  __syncthreads();  // every wave is done reading TA
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      TA[(16 * rb + 4 * v + q) * kS + 16 * w + p] = x[rb][v];
+      Rg[(16 * rb + 4 * v + q) * kP + 16 * w + p] = x[rb][v];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    if (w + 4 * u >= 10) break;
+    const int rb = kUpR[w + 4 * u], cb = kUpC[w + 4 * u];
+#pragma unroll
+    for (int k0 = 0; k0 < 16; k0 += 8) {
+      double a[8], b[8];
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const int k = 4 * (k0 + kk) + q;
+        a[kk] = TA[k * kS + 16 * rb + p];
+        b[kk] = TA[k * kS + 16 * cb + p];
+      }
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) g[u] = mfma(-a[kk], b[kk], g[u]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) TC[(16 * rb + 4 * v + q) * kS + 16 * cb + p] = g[u][v];
+  }
+}
+
 // Step k: tiles (i, j), k < i <= j, one workgroup each (see the header).
 // With X, k more workgroups finish block column k of X = R^{-1}, and
 // k (nb - k - 1) more add the term l = k - 1 to the running sums P_ij.
@@ -469,6 +542,24 @@ __global__ void __launch_bounds__(256)
   i += k + 1;
   j += k + 1;
   const bool diag = i == j;
+  if (diag && i == k + 1) {
+    load_tile(TI, Dinv + k * kT2, kP, kP, kP, t);
+    load_tile(TA, G + tix(k, i, nb), kP, kP, kP, t);
+    if (t < kP) lim[t] = tol * gdiag[i * kP + t];
+    __syncthreads();
+    bchol_lead(TI, TA, TC, G + tix(i, i, nb), R + tix(k, i, nb), lane, w);
+    __syncthreads();
+    const int64_t nv = d - i * kP;  // columns of the tile inside the matrix
+    const int nblk = nv >= kP ? 4 : static_cast<int>((nv + 15) / 16);
+    if (!chol64b(TC, TI, lim, &bad, tmp, t, nblk)) {
+      if (t == 0) *flag = 1;
+      return;
+    }
+    tile_to_global(R + tix(i, i, nb), TC, t);
+    tile_to_global(Dinv + i * kT2, TI, t);
+    if (X) tile_to_global(X + tix(i, i, nb), TI, t);
+    return;
+  }
   load_tile(TI, Dinv + k * kT2, kP, kP, kP, t);
   load_tile(TA, G + tix(k, i, nb), kP, kP, kP, t);
   if (!diag) load_tile(TB, G + tix(k, j, nb), kP, kP, kP, t);
@@ -493,22 +584,7 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   mm64_sub<true>(TA, diag ? TA : TB, acc, lane, w);  // G_ij -= X_i^T X_j
-  if (diag && i == k + 1) {
-    store_acc(TC, acc, 1.0, lane, w);
-    if (t < kP) lim[t] = tol * gdiag[i * kP + t];
-    __syncthreads();
-    const int64_t nv = d - i * kP;  // columns of the tile inside the matrix
-    const int nblk = nv >= kP ? 4 : static_cast<int>((nv + 15) / 16);
-    if (!chol64b(TC, TI, lim, &bad, tmp, t, nblk)) {
-      if (t == 0) *flag = 1;
-      return;
-    }
-    tile_to_global(R + tix(i, i, nb), TC, t);
-    tile_to_global(Dinv + i * kT2, TI, t);
-    if (X) tile_to_global(X + tix(i, i, nb), TI, t);
-  } else {
-    store_acc_global(G + tix(i, j, nb), kP, acc, 1.0, lane, w);
-  }
+  store_acc_global(G + tix(i, j, nb), kP, acc, 1.0, lane, w);
 }
 
 // ---- Q1 = A R^{-1} in place, by row stripes -------------------------------------

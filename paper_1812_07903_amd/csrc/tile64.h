@@ -259,8 +259,15 @@ __device__ __forceinline__ bool chol16x(double* B, double* Xi, const double* lim
     const double g = l < j ? 0.0 : gc[j] * y0;
     const double rjl = fma(g * e, fma(e, 0.375, 0.5), g);
     gc[j] = rjl;
+    // row j of R: all its lane reads first (each into registers of its own),
+    // then the updates; read and use interleaved, the reads queue behind one
+    // another on a shared scalar register pair
+    double rb[16];
 #pragma unroll
-    for (int i = j + 1; i < 16; ++i) gc[i] -= readlane_d(rjl, i) * rjl;
+    for (int i = j + 1; i < 16; ++i) rb[i] = readlane_d(rjl, i);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = j + 1; i < 16; ++i) gc[i] -= rb[i] * rjl;
   }
   wave_sync();
   if (l < 16) {
