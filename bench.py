@@ -59,7 +59,7 @@ KERNEL_SRC = {
     "cq_gram": ("cq_gram_kernel", "k_cqr.hip"),
     "qr_node": ("qr_node_kernel", "k_qr.hip"),
     "qr_update": ("qr_update_kernel", "k_qr.hip"),
-    "score": ("score_mfma_kernel<0,true>", "k_score.hip"),
+    "score": ("score_mfma_kernel<3,true>", "k_score.hip"),
     "countsketch": ("countsketch_colmax_kernel<float,false>", "k_sketch.hip"),
     "colmax": ("colmax_dense_kernel<float>", "k_sketch.hip"),
 }
@@ -158,13 +158,14 @@ def _roofline(name: str, ms_per_launch: float, launches_per_step: float):
         return {"bound": "alu", "achieved": a / 1e12, "peak": PEAK["fp64"] / 1e12,
                 "unit": "TFLOP/s", "frac": a / PEAK["fp64"], "traffic": None}
     if name == "score":
-        # X M on the FP32 MFMA: 2 n d k flop (X read once is 4 n d bytes,
-        # which at the HBM peak takes less time than the products at theirs)
-        flops = 2.0 * N * D * K / launches_per_step
-        a = flops / sec
-        return {"bound": "mfma", "achieved": a / 1e12,
-                "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
-                "frac": a / PEAK["fp32"], "traffic": None}
+        # X M as six split-BF16 products: 12 n d k flop on the BF16 MFMA take
+        # less time at its peak than reading X once, so the pass is priced
+        # against HBM: X once (4 n d), M's three BF16 parts (6 d k) and the
+        # scores (4 n)
+        byts = (N * D * 4 + 6 * D * K + N * 4) / launches_per_step
+        a = byts / sec
+        return {"bound": "hbm", "achieved": a / 1e9, "peak": PEAK["hbm"] / 1e9,
+                "unit": "GB/s", "frac": a / PEAK["hbm"], "traffic": None}
     if name == "countsketch":
         # X once, the sketch written once, the sorted row list once, the
         # per-workgroup column maxima (min(1024, R / 4) x D floats) once

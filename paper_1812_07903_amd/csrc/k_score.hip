@@ -9,6 +9,8 @@
 // throughout. CSR rows gather the FP32 rows of M and accumulate in FP64.
 #include "internal.h"
 
+#include <type_traits>
+
 namespace slso {
 namespace {
 
@@ -164,12 +166,21 @@ __global__ void __launch_bounds__(256)
 //   FP32 input: v_mfma_f32_32x32x2f32 on FP32 X and FP32 M.
 //   BF16 / FP8 input: v_mfma_f32_32x32x16_bf16 on X (exact in BF16) and three
 //   BF16 parts of M (M = Mh + Mm + Ml, |M - Mh - Mm - Ml| <= 2^-24 |M|).
+//   FP32 input, split form (IT 3): split-BF16 emulation of the FP32 product
+//   (Henry, Tang and Heinecke 2019). Each X operand is cut, as it leaves LDS,
+//   into X1 = bf16(X), X2 = bf16(X - X1), X3 = bf16(X - X1 - X2), which sum to
+//   X exactly for normal FP32 values; with M's three parts, the six products
+//   Xi Mj with i + j <= 4 are taken (smallest first) on the BF16 MFMA, each
+//   exact in the FP32 accumulation; the three dropped ones are below 2^-23
+//   |X| |M| together. It needs a sixth of the FP32 MFMA's cycles per flop
+//   times six products: the pass is then bound by reading X.
 // Epilogue: l_i = sum over the 64 columns of the squared FP64 accumulators.
 // Accumulator register e of lane l holds row (e % 4) + 8 (e / 4) + 4 (l / 32)
 // and column l % 32 of its tile.
 constexpr int kMR = 128;     // rows per workgroup
 constexpr int kMC = 32;      // contraction chunk
 constexpr int kXS32 = 33;    // LDS row stride (floats) of the FP32 X tile
+constexpr int kXS36 = 36;    // the same for the split form (16-byte rows)
 constexpr int kXS16 = 40;    // LDS row stride (bf16) of the BF16 tiles
 
 typedef float f16v __attribute__((ext_vector_type(16)));
@@ -194,6 +205,11 @@ struct XIn<1> {
 template <>
 struct XIn<2> {
   using T = uint8_t;
+};
+// FP32 input multiplied as three BF16 parts (see the kernel header)
+template <>
+struct XIn<3> {
+  using T = float;
 };
 
 // BF16 bits of input element v (FP8 e4m3 values are exact in BF16)
@@ -222,7 +238,9 @@ __global__ void __launch_bounds__(256)
                       float* __restrict__ out) {
   // FP32: X[2][128][33] f32 + M[2][32][64] f32; BF16: X[2][128][40] bf16 +
   // Mh, Mm, Ml[2][64][40] bf16 (M stored by column, k contiguous)
-  constexpr int kXBytes = IT == 0 ? kMR * kXS32 * 4 : kMR * kXS16 * 2;
+  constexpr int kXBytes = IT == 0   ? kMR * kXS32 * 4
+                          : IT == 3 ? kMR * kXS36 * 4
+                                    : kMR * kXS16 * 2;
   constexpr int kMBytes = IT == 0 ? kMC * 64 * 4 : 3 * 64 * kXS16 * 2;
   __shared__ __attribute__((aligned(16))) unsigned char lds[2 * (kXBytes + kMBytes)];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -249,6 +267,7 @@ __global__ void __launch_bounds__(256)
     XT xr[16];
     float mr[8];
     uint16_t mhr[8], mmr[8], mlr[8];
+    uint4 mq[3];  // split form: 8 k of one column of Mh, Mm, Ml
     uint32_t okx, okm;
   };
   auto load_chunk = [&](int ch, SStage& st) {
@@ -270,21 +289,36 @@ __global__ void __launch_bounds__(256)
         st.xr[4 * pp + 3] = q.w;
         st.okx |= ok ? (0xfu << (4 * pp)) : 0u;
       }
-#pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        const int e4 = t + 256 * v;
-        const int64_t gk = c0 + e4 / 16;
+      if constexpr (IT == 3) {
+        // column t / 4 of each part, k = c0 + 8 (t % 4) .. + 7 (d is a
+        // multiple of 8, so the eight are all inside or all outside)
+        const int64_t gk = c0 + 8 * (t % 4);
         const bool ok = gk < d;
-        const float4 q = *reinterpret_cast<const float4*>(
-            m32 + (ok ? gk * 64 + 4 * (e4 % 16) : 0));
-        st.mr[4 * v] = q.x;
-        st.mr[4 * v + 1] = q.y;
-        st.mr[4 * v + 2] = q.z;
-        st.mr[4 * v + 3] = q.w;
-        st.okm |= ok ? (0xfu << (4 * v)) : 0u;
+        const int64_t i = ok ? (t / 4) * ldm + gk : 0;
+        st.mq[0] = *reinterpret_cast<const uint4*>(mh + i);
+        st.mq[1] = *reinterpret_cast<const uint4*>(mm + i);
+        st.mq[2] = *reinterpret_cast<const uint4*>(ml + i);
+        st.okm = ok ? 1u : 0u;
+        return;
       }
-      return;
+      if constexpr (IT == 0) {
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          const int e4 = t + 256 * v;
+          const int64_t gk = c0 + e4 / 16;
+          const bool ok = gk < d;
+          const float4 q = *reinterpret_cast<const float4*>(
+              m32 + (ok ? gk * 64 + 4 * (e4 % 16) : 0));
+          st.mr[4 * v] = q.x;
+          st.mr[4 * v + 1] = q.y;
+          st.mr[4 * v + 2] = q.z;
+          st.mr[4 * v + 3] = q.w;
+          st.okm |= ok ? (0xfu << (4 * v)) : 0u;
+        }
+        return;
+      }
     }
+    if constexpr (!kVec) {
 #pragma unroll
     for (int pp = 0; pp < 4; ++pp) {
       const int r = t / 8 + 32 * pp;
@@ -297,6 +331,7 @@ __global__ void __launch_bounds__(256)
         st.xr[4 * pp + u] = x[ok ? gr * ld + gc : 0];
         st.okx |= ok ? (1u << (4 * pp + u)) : 0u;
       }
+    }
     }
     if constexpr (IT == 0) {
       // M rows c0 .. c0 + 31, 64 columns: element e = t + 256 v
@@ -328,6 +363,18 @@ __global__ void __launch_bounds__(256)
   auto store_chunk = [&](int buf, const SStage& st) {
     unsigned char* xb = lds + buf * kXBytes;
     unsigned char* mb = lds + 2 * kXBytes + buf * kMBytes;
+    if constexpr (IT == 3) {
+      float* X = reinterpret_cast<float*>(xb);
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp) {
+        float4 q;
+        q.x = ((st.okx >> (4 * pp)) & 1u) ? st.xr[4 * pp] : 0.0f;
+        q.y = ((st.okx >> (4 * pp + 1)) & 1u) ? st.xr[4 * pp + 1] : 0.0f;
+        q.z = ((st.okx >> (4 * pp + 2)) & 1u) ? st.xr[4 * pp + 2] : 0.0f;
+        q.w = ((st.okx >> (4 * pp + 3)) & 1u) ? st.xr[4 * pp + 3] : 0.0f;
+        *reinterpret_cast<float4*>(&X[(t / 8 + 32 * pp) * kXS36 + 4 * (t % 8)]) = q;
+      }
+    }
     if constexpr (IT == 0) {
       float* X = reinterpret_cast<float*>(xb);
 #pragma unroll
@@ -350,16 +397,34 @@ __global__ void __launch_bounds__(256)
           M[t + 256 * v] = ((st.okm >> v) & 1u) ? st.mr[v] : 0.0f;
       }
     } else {
-      uint16_t* X = reinterpret_cast<uint16_t*>(xb);
+      if constexpr (IT != 3) {
+        uint16_t* X = reinterpret_cast<uint16_t*>(xb);
 #pragma unroll
-      for (int pp = 0; pp < 4; ++pp)
+        for (int pp = 0; pp < 4; ++pp)
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          X[(t / 8 + 32 * pp) * kXS16 + 4 * (t % 8) + u] =
-              ((st.okx >> (4 * pp + u)) & 1u) ? in_bf16(st.xr[4 * pp + u]) : uint16_t(0);
+          for (int u = 0; u < 4; ++u)
+            X[(t / 8 + 32 * pp) * kXS16 + 4 * (t % 8) + u] =
+                ((st.okx >> (4 * pp + u)) & 1u) ? in_bf16(st.xr[4 * pp + u]) : uint16_t(0);
+      }
       uint16_t* Mh = reinterpret_cast<uint16_t*>(mb);
       uint16_t* Mm = Mh + 64 * kXS16;
       uint16_t* Ml = Mm + 64 * kXS16;
+      if constexpr (IT == 3 && kVec) {
+        const uint32_t mk = st.okm ? 0xffffffffu : 0u;
+        const int o = (t / 4) * kXS16 + 8 * (t % 4);
+        uint4* dst[3] = {reinterpret_cast<uint4*>(Mh + o), reinterpret_cast<uint4*>(Mm + o),
+                         reinterpret_cast<uint4*>(Ml + o)};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          uint4 v;
+          v.x = st.mq[j].x & mk;
+          v.y = st.mq[j].y & mk;
+          v.z = st.mq[j].z & mk;
+          v.w = st.mq[j].w & mk;
+          *dst[j] = v;
+        }
+        return;
+      }
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
         const int e = t + 256 * v;
@@ -396,6 +461,46 @@ __global__ void __launch_bounds__(256)
             acc[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk], bv[kk][tt],
                                                             acc[tt], 0, 0, 0);
       }
+    } else if constexpr (IT == 3) {
+      const float* X = reinterpret_cast<const float*>(xb);
+      const __bf16* Mh = reinterpret_cast<const __bf16*>(mb);
+      const __bf16* Mm = Mh + 64 * kXS16;
+      const __bf16* Ml = Mm + 64 * kXS16;
+#pragma unroll
+      for (int kk = 0; kk < kMC / 16; ++kk) {
+        const float* xp = &X[(32 * w + l32) * kXS36 + 16 * kk + 8 * h];
+        const float4 q0 = *reinterpret_cast<const float4*>(xp);
+        const float4 q1 = *reinterpret_cast<const float4*>(xp + 4);
+        const float xv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+        bf16x8 a1, a2, a3;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const __bf16 p1 = static_cast<__bf16>(xv[j]);
+          const float r1 = xv[j] - static_cast<float>(p1);  // exact
+          const __bf16 p2 = static_cast<__bf16>(r1);
+          const float r2 = r1 - static_cast<float>(p2);     // exact
+          a1[j] = p1;
+          a2[j] = p2;
+          a3[j] = static_cast<__bf16>(r2);
+        }
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+          const int col = 32 * tt + l32;
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(
+              &Mh[col * kXS16 + 16 * kk + 8 * h]);
+          const bf16x8 bm = *reinterpret_cast<const bf16x8*>(
+              &Mm[col * kXS16 + 16 * kk + 8 * h]);
+          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(
+              &Ml[col * kXS16 + 16 * kk + 8 * h]);
+          // i + j = 4, then 3, then 2
+          acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3, bh, acc[tt], 0, 0, 0);
+          acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, bm, acc[tt], 0, 0, 0);
+          acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bl, acc[tt], 0, 0, 0);
+          acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, bh, acc[tt], 0, 0, 0);
+          acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bm, acc[tt], 0, 0, 0);
+          acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bh, acc[tt], 0, 0, 0);
+        }
+      }
     } else {
       const __bf16* X = reinterpret_cast<const __bf16*>(xb);
       const __bf16* Mh = reinterpret_cast<const __bf16*>(mb);
@@ -430,20 +535,35 @@ __global__ void __launch_bounds__(256)
       }
   };
 
-  // every store to a buffer follows a barrier after its last reader
-  SStage s0;
-  load_chunk(0, s0);
-  store_chunk(0, s0);
+  // Chunk ch is read from buffer ch % 2 after the barrier that follows its
+  // store; the store of chunk ch + 1 goes to the other buffer, whose last
+  // reader (chunk ch - 1) finished before that same barrier, so one barrier
+  // per chunk suffices. kVec: two register stages, and chunk ch + 2 is
+  // loaded into the stage chunk ch has left (already in LDS) before chunk ch
+  // multiplies, so two chunks of X are in flight while one multiplies; the
+  // other forms load chunk ch + 1 there (one stage, fewer registers).
+  SStage st[kVec ? 2 : 1];
+  load_chunk(0, st[0]);
+  store_chunk(0, st[0]);
+  if (kVec && nch > 1) load_chunk(1, st[kVec ? 1 : 0]);
   __syncthreads();
-  for (int ch = 0; ch < nch; ++ch) {
-    const int buf = ch & 1;
-    if (ch + 1 < nch) load_chunk(ch + 1, s0);
-    compute(buf);
+  auto step = [&](int ch, auto stage) {
+    constexpr int S = decltype(stage)::value;
+    constexpr int kIn = kVec ? S : 0, kNext = kVec ? 1 - S : 0;
+    if (kVec) {
+      if (ch + 2 < nch) load_chunk(ch + 2, st[kIn]);
+    } else {
+      if (ch + 1 < nch) load_chunk(ch + 1, st[0]);
+    }
+    compute(ch & 1);
     if (ch + 1 < nch) {
-      __syncthreads();
-      store_chunk(buf ^ 1, s0);
+      store_chunk((ch + 1) & 1, st[kNext]);
       __syncthreads();
     }
+  };
+  for (int ch = 0; ch < nch; ch += 2) {
+    step(ch, std::integral_constant<int, 0>{});
+    if (ch + 1 < nch) step(ch + 1, std::integral_constant<int, 1>{});
   }
   // l_i = sum_c y_ic^2: square and add the two tiles, then 32 lanes
 #pragma unroll
@@ -483,8 +603,9 @@ __global__ void split_m_kernel(const double* __restrict__ m64, int64_t d,
 size_t scores_partial_bytes(int64_t n, int64_t d, int64_t k, int format,
                             int dtype) {
   if (format == 0 && dtype != 0 && k <= 64) {
-    // the BF16 halves of M for reduced-precision input
-    return dtype == 1 ? 0 : static_cast<size_t>(3 * 64 * d) * sizeof(uint16_t);
+    // the three BF16 parts of M (reduced-precision input, and FP32 input in
+    // the split form)
+    return static_cast<size_t>(3 * 64 * d) * sizeof(uint16_t);
   }
   const int64_t tiles = (k + kCols - 1) / kCols;
   if (format == 1 || tiles <= 1) return 0;
@@ -510,18 +631,27 @@ void launch_scores(const void* x, int dtype, int format, int64_t n, int64_t d,
   if (dtype != 0 && k <= 64) {
     const unsigned g = static_cast<unsigned>((n + kMR - 1) / kMR);
     if (dtype == 1) {
-      const bool vec = ld % 4 == 0 && d % 4 == 0 && k == 64 &&
+      // the split form: 4-float X loads and 8-element loads of M's parts
+      const bool vec = ld % 4 == 0 && d % 8 == 0 && k == 64 &&
                        reinterpret_cast<uintptr_t>(x) % 16 == 0 &&
-                       reinterpret_cast<uintptr_t>(m32) % 16 == 0;
+                       reinterpret_cast<uintptr_t>(partial) % 16 == 0;
+      if (vec) {
+        uint16_t* mh = reinterpret_cast<uint16_t*>(partial);
+        uint16_t* mm = mh + 64 * d;
+        uint16_t* ml = mm + 64 * d;
+        split_m_kernel<<<static_cast<unsigned>((64 * d + 255) / 256), 256, 0, s>>>(
+            m64, d, k, d, mh, mm, ml);
+        prof_begin(kKScore, s);
+        score_mfma_kernel<3, true><<<g, 256, 0, s>>>(
+            static_cast<const float*>(x), n, d, ld, nullptr, k, mh, mm, ml, d,
+            scores);
+        prof_end(kKScore, s);
+        return;
+      }
       prof_begin(kKScore, s);
-      if (vec)
-        score_mfma_kernel<0, true><<<g, 256, 0, s>>>(
-            static_cast<const float*>(x), n, d, ld, m32, k, nullptr, nullptr,
-            nullptr, 0, scores);
-      else
-        score_mfma_kernel<0><<<g, 256, 0, s>>>(static_cast<const float*>(x), n,
-                                               d, ld, m32, k, nullptr, nullptr,
-                                               nullptr, 0, scores);
+      score_mfma_kernel<0><<<g, 256, 0, s>>>(static_cast<const float*>(x), n, d,
+                                             ld, m32, k, nullptr, nullptr,
+                                             nullptr, 0, scores);
       prof_end(kKScore, s);
     } else {
       uint16_t* mh = reinterpret_cast<uint16_t*>(partial);
