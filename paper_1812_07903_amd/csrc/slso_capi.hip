@@ -807,14 +807,16 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   char* hb = static_cast<char*>(c->host_buf);
   double ds[4];
   int fl[3];
+  // flags and dstat are consecutive arena blocks: one copy brings both (the
+  // GPU idles while it runs, so a second copy would add its whole latency)
+  const size_t ds_off = static_cast<size_t>(reinterpret_cast<char*>(dstat) -
+                                            reinterpret_cast<char*>(flags));
   auto readback = [&]() -> int {
-    SLSO_HIP(c, hipMemcpyAsync(hb, dstat, 4 * sizeof(double),
-                               hipMemcpyDeviceToHost, s));
-    SLSO_HIP(c, hipMemcpyAsync(hb + 64, flags, 3 * sizeof(int),
+    SLSO_HIP(c, hipMemcpyAsync(hb, flags, ds_off + 4 * sizeof(double),
                                hipMemcpyDeviceToHost, s));
     SLSO_HIP(c, hipStreamSynchronize(s));
-    std::memcpy(ds, hb, sizeof(ds));
-    std::memcpy(fl, hb + 64, sizeof(fl));
+    std::memcpy(fl, hb, sizeof(fl));
+    std::memcpy(ds, hb + ds_off, sizeof(ds));
     return check_launch(c, "slso_leverage: sketch/QR");
   };
   // The sketch's R by Cholesky-QR2 (which overwrites the sketch); when that
