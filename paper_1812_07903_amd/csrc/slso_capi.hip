@@ -738,6 +738,14 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   }
   // 1. column equilibration D (power of two) from column max-abs of X
   launch_fill_i32(flags, 64, 0, s);
+  // Pi_2 depends only on the seed, d and k: it is formed here, ahead of the
+  // sketch, rather than after the rank-screen read-back, where the GPU would
+  // wait for its launch
+  if (k == 0)
+    launch_eye(pi, d, s);
+  else
+    launch_gaussian(seed, kStreamPi2, d, k, std::sqrt(static_cast<double>(k)),
+                    pi, s);
   if (!fuse) {
     launch_fill_u64(colmax, d, 0, s);
     launch_colmax(X->values, X->dtype, X->format, n, d, X->ld, X->row_ptr,
@@ -874,12 +882,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   if (tol >= 0.0)
     full = (o.flags & SLSO_OPT_SVD_RANK) == 0 && dmax > 0.0 &&
            dmin > std::sqrt(tol) * dmax;
-  // 5. Pi_2 and M = D pinv(R_D) Pi_2 (Algorithm 2 step 3 / Algorithm 3 step 4)
-  if (k == 0)
-    launch_eye(pi, d, s);
-  else
-    launch_gaussian(seed, kStreamPi2, d, k, std::sqrt(static_cast<double>(k)),
-                    pi, s);
+  // 5. M = D pinv(R_D) Pi_2 (Algorithm 2 step 3 / Algorithm 3 step 4)
   int64_t rank = d;
   if (full) {
     if (cholqr2 && !refine)
