@@ -101,6 +101,21 @@ def test_config1_ragged_small(slso, ctx):
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("n,d", [(5000, 200), (4097, 196)])
+def test_fp32_k64_scoring_forms(slso, ctx, n, d):
+    """FP32 input with k = 64: d = 200 takes the split-BF16 scoring (d a
+    multiple of 8; its last 32-column chunk is partial), d = 196 the FP32
+    MFMA; both within the FP32 gate of the oracle."""
+    x = synth.image_like(n, d, seed=60 + d)
+    assert x.dtype == np.float32
+    got, info = ctx.leverage(dev(x), 21, 2048, 64)
+    ref = olv.sketched_leverage(x, 21, 2048, 64)
+    assert info["rank"] == d
+    err, tau = _report(f"fp32 k64 d={d}", host(got), ref["scores"])
+    assert err < 1e-5
+    assert tau > 0.999
+
+
 @pytest.mark.parametrize("d,nnz", [(128, 2), (130, 4), (784, 2)])
 def test_osnap_leverage(slso, ctx, d, nnz):
     """OSNAP sketch (nnz nonzeros per column of S), FP32 input: d = 128 and
