@@ -632,7 +632,8 @@ void launch_scores(const void* x, int dtype, int format, int64_t n, int64_t d,
     const unsigned g = static_cast<unsigned>((n + kMR - 1) / kMR);
     if (dtype == 1) {
       // the split form: 4-float X loads and 8-element loads of M's parts
-      const bool vec = ld % 4 == 0 && d % 8 == 0 && k == 64 &&
+      // (the parts hold 64 columns, zero past k, so any k <= 64)
+      const bool vec = ld % 4 == 0 && d % 8 == 0 &&
                        reinterpret_cast<uintptr_t>(x) % 16 == 0 &&
                        reinterpret_cast<uintptr_t>(partial) % 16 == 0;
       if (vec) {
