@@ -389,7 +389,15 @@ int slso_solve_upper(slso_ctx* ctx, const double* r, int64_t d, double* b,
                      int64_t k, void* stream);
 
 /* Row scores l_i = ||x_i M||^2 for a given M (device, d x k doubles,
- * row-major), Algorithm 2 step 4; scores (device) n floats. */
+ * row-major), Algorithm 2 step 4; scores (device) n floats. The same pass
+ * scores rows in slso_leverage. Dense input with k <= 64 runs on the MFMA:
+ * M is cut into three BF16 parts (Mh + Mm + Ml within 2^-24 |M|); BF16 and
+ * FP8 X multiply all three; FP32 X (d a multiple of 8, 16-byte aligned) is
+ * cut the same way as it is read and the six products of parts whose orders
+ * add to at most four are taken (split-BF16 emulation of the FP32 product),
+ * else the FP32 MFMA multiplies X and M rounded to FP32. Every product is
+ * summed in FP32 over 32-column chunks and the chunks in FP64. FP64 input,
+ * CSR input and k > 64 use FP64 or FP32 vector arithmetic. */
 int slso_scores(slso_ctx* ctx, const slso_matrix* X, const double* m,
                 int64_t k, float* scores, void* stream);
 
