@@ -428,7 +428,8 @@ def main() -> int:
     }
 
     if not args.no_cpu_baseline:
-        # the oracle, untouched, on one full job of the same workload
+        # the oracle, untouched, on whole jobs of the same workload until
+        # about 10 s of CPU work has been timed (a bounded sample)
         from oracle import leverage as olv
         from oracle import metrics as omet
         from oracle import order as oorder
@@ -438,7 +439,7 @@ def main() -> int:
         except Exception:
             cores = os.cpu_count() or 1
         reps, t_cpu, ref = 0, 0.0, None
-        while reps < 3 and t_cpu < 20.0:
+        while reps < 40 and t_cpu < 10.0:
             tc = time.perf_counter()
             ref = olv.sketched_leverage(x_host, SEED, R, K, kind=args.sketch,
                                         nnz=max(nnz, 1))
