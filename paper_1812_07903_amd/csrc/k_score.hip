@@ -225,9 +225,10 @@ __device__ __forceinline__ double sum32(double v) {
   return v;
 }
 
-// kVec (FP32 input, ld and d multiples of 4, 16-byte aligned X, k = 64): the
-// staging loads are 4-float vectors, a quarter of the load instructions and
-// cache-line lookups of the element-wise form
+// kVec (the split form, IT 3: ld a multiple of 4, d of 8, 16-byte aligned X
+// and parts of M): the staging loads are 4-float vectors of X and 8-element
+// vectors of M's parts, a fraction of the load instructions and cache-line
+// lookups of the element-wise form
 template <int IT, bool kVec = false>
 __global__ void __launch_bounds__(256)
     score_mfma_kernel(const typename XIn<IT>::T* __restrict__ x, int64_t n,
@@ -238,6 +239,7 @@ __global__ void __launch_bounds__(256)
                       float* __restrict__ out) {
   // FP32: X[2][128][33] f32 + M[2][32][64] f32; BF16: X[2][128][40] bf16 +
   // Mh, Mm, Ml[2][64][40] bf16 (M stored by column, k contiguous)
+  static_assert(!kVec || IT == 3, "vector staging is the split form's");
   constexpr int kXBytes = IT == 0   ? kMR * kXS32 * 4
                           : IT == 3 ? kMR * kXS36 * 4
                                     : kMR * kXS16 * 2;
@@ -275,8 +277,7 @@ __global__ void __launch_bounds__(256)
     st.okx = 0u;
     st.okm = 0u;
     if constexpr (kVec) {
-      // X: row t/8 + 32 pp, columns 4 (t%8) .. +3 as one vector; M: rows
-      // c0 + (t + 256 v) / 16, columns 4 ((t + 256 v) % 16) .. +3
+      // X: row t/8 + 32 pp, columns 4 (t%8) .. +3 as one vector
 #pragma unroll
       for (int pp = 0; pp < 4; ++pp) {
         const int64_t gr = row0 + t / 8 + 32 * pp;
@@ -289,34 +290,16 @@ __global__ void __launch_bounds__(256)
         st.xr[4 * pp + 3] = q.w;
         st.okx |= ok ? (0xfu << (4 * pp)) : 0u;
       }
-      if constexpr (IT == 3) {
-        // column t / 4 of each part, k = c0 + 8 (t % 4) .. + 7 (d is a
-        // multiple of 8, so the eight are all inside or all outside)
-        const int64_t gk = c0 + 8 * (t % 4);
-        const bool ok = gk < d;
-        const int64_t i = ok ? (t / 4) * ldm + gk : 0;
-        st.mq[0] = *reinterpret_cast<const uint4*>(mh + i);
-        st.mq[1] = *reinterpret_cast<const uint4*>(mm + i);
-        st.mq[2] = *reinterpret_cast<const uint4*>(ml + i);
-        st.okm = ok ? 1u : 0u;
-        return;
-      }
-      if constexpr (IT == 0) {
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-          const int e4 = t + 256 * v;
-          const int64_t gk = c0 + e4 / 16;
-          const bool ok = gk < d;
-          const float4 q = *reinterpret_cast<const float4*>(
-              m32 + (ok ? gk * 64 + 4 * (e4 % 16) : 0));
-          st.mr[4 * v] = q.x;
-          st.mr[4 * v + 1] = q.y;
-          st.mr[4 * v + 2] = q.z;
-          st.mr[4 * v + 3] = q.w;
-          st.okm |= ok ? (0xfu << (4 * v)) : 0u;
-        }
-        return;
-      }
+      // M: column t / 4 of each part, k = c0 + 8 (t % 4) .. + 7 (d is a
+      // multiple of 8, so the eight are all inside or all outside)
+      const int64_t gk = c0 + 8 * (t % 4);
+      const bool ok = gk < d;
+      const int64_t i = ok ? (t / 4) * ldm + gk : 0;
+      st.mq[0] = *reinterpret_cast<const uint4*>(mh + i);
+      st.mq[1] = *reinterpret_cast<const uint4*>(mm + i);
+      st.mq[2] = *reinterpret_cast<const uint4*>(ml + i);
+      st.okm = ok ? 1u : 0u;
+      return;
     }
     if constexpr (!kVec) {
 #pragma unroll
@@ -384,18 +367,9 @@ __global__ void __launch_bounds__(256)
           X[(t / 8 + 32 * pp) * kXS32 + 4 * (t % 8) + u] =
               ((st.okx >> (4 * pp + u)) & 1u) ? st.xr[4 * pp + u] : 0.0f;
       float* M = reinterpret_cast<float*>(mb);
-      if constexpr (kVec) {
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            M[4 * (t + 256 * v) + u] =
-                ((st.okm >> (4 * v + u)) & 1u) ? st.mr[4 * v + u] : 0.0f;
-      } else {
-#pragma unroll
-        for (int v = 0; v < 8; ++v)
-          M[t + 256 * v] = ((st.okm >> v) & 1u) ? st.mr[v] : 0.0f;
-      }
+      for (int v = 0; v < 8; ++v)
+        M[t + 256 * v] = ((st.okm >> v) & 1u) ? st.mr[v] : 0.0f;
     } else {
       if constexpr (IT != 3) {
         uint16_t* X = reinterpret_cast<uint16_t*>(xb);
