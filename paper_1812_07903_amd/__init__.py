@@ -108,6 +108,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(
             f"{path} is missing: build it with paper_1812_07903_amd.build.build()")
+    # torch first: it carries its own copy of the HIP runtime, and the library
+    # must bind to that one (same soname) so that one runtime owns the device
+    # and the library shares torch's memory and streams; loaded first, the
+    # library would pull in the system runtime and torch a second one
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
     sig = {
@@ -206,10 +211,50 @@ def _device(x):
     return x.val.device if isinstance(x, CsrMatrix) else x.device
 
 
+def _on_gpu(t, what: str):
+    """Raise unless ``t`` is a torch tensor in device memory: the library
+    reads and writes through device pointers only."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{what} must be on a GPU device, not {t.device}")
+
+
+def _same_device(ts, what: str):
+    devs = {t.device for t in ts if t is not None}
+    if len(devs) > 1:
+        raise ValueError(f"{what}: tensors on different devices {sorted(map(str, devs))}")
+
+
+def _out(t, dtype, numel, device, what: str):
+    """An output tensor: the given one after checks, or a new one of
+    ``numel`` elements (an int, or a shape tuple)."""
+    import math
+    import torch
+    shape = tuple(numel) if isinstance(numel, (tuple, list)) else (numel,)
+    numel = math.prod(shape)
+    if t is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    _on_gpu(t, what)
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, not {t.dtype}")
+    if t.numel() != numel:
+        raise ValueError(f"{what} must hold {numel} elements, not {t.numel()}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if torch.device(device) != t.device:
+        raise ValueError(f"{what} is on {t.device}, the input on {device}")
+    return t
+
+
 def _matrix(x) -> _Matrix:
     import torch
     m = _Matrix()
     if isinstance(x, Fp8Matrix):
+        _on_gpu(x.codes, "FP8 codes")
+        _on_gpu(x.col_scale, "col_scale")
+        _same_device((x.codes, x.col_scale), "FP8 matrix")
         c = x.codes
         if c.dtype not in (torch.uint8, torch.float8_e4m3fn):
             raise TypeError("FP8 codes must be uint8 or float8_e4m3fn")
@@ -226,6 +271,15 @@ def _matrix(x) -> _Matrix:
         m.col_scale = cs.data_ptr()
         return m
     if isinstance(x, CsrMatrix):
+        for t, w in ((x.row_ptr, "row_ptr"), (x.col_idx, "col_idx"),
+                     (x.val, "CSR values")):
+            _on_gpu(t, w)
+            if not t.is_contiguous():
+                raise ValueError(f"{w} must be contiguous")
+        _same_device((x.row_ptr, x.col_idx, x.val), "CSR matrix")
+        if x.row_ptr.numel() != x.n + 1 or x.col_idx.numel() != x.val.numel():
+            raise ValueError("CSR needs n + 1 row pointers and one column "
+                             "index per value")
         if x.val.dtype != torch.float32:
             raise TypeError("CSR values must be float32")
         if x.row_ptr.dtype != torch.int64 or x.col_idx.dtype != torch.int32:
@@ -237,6 +291,7 @@ def _matrix(x) -> _Matrix:
         m.col_idx = x.col_idx.data_ptr()
         m.nnz = int(x.col_idx.numel())
         return m
+    _on_gpu(x, "X")
     if x.dim() != 2 or x.stride(1) != 1:
         raise ValueError("dense X must be 2-D with unit column stride")
     code = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}.get(x.dtype)
@@ -273,6 +328,12 @@ class Context:
     def handle(self):
         return self._h
 
+    def _here(self, dev):
+        """Raise unless ``dev`` is this context's device."""
+        idx = dev.index if dev.index is not None else 0
+        if dev.type != "cuda" or idx != self.device:
+            raise ValueError(f"tensor on {dev}, context on cuda:{self.device}")
+
     def close(self):
         if self._h:
             load_library().slso_destroy(self._h)
@@ -288,10 +349,9 @@ class Context:
     def sketch(self, x, seed: int, r: int, sketch: int = COUNTSKETCH, out=None,
                stream=None, nnz: int = 0):
         import torch
-        if out is None:
-            out = torch.empty((r, _cols(x)), dtype=torch.float64,
-                              device=_device(x))
         m = _matrix(x)
+        self._here(_device(x))
+        out = _out(out, torch.float64, (r, _cols(x)), _device(x), "out")
         opt = _Options(sketch, 0, 0.0, nnz, 0)
         _check(load_library().slso_sketch(self._h, ctypes.byref(m), seed, r,
                                           ctypes.byref(opt), _ptr(out),
@@ -305,9 +365,9 @@ class Context:
         ``nnz``: OSNAP nonzeros per column of S (0 selects 2); ``svd_rank``:
         decide the rank by the SVD of R every time."""
         import torch
-        if out is None:
-            out = torch.empty(_rows(x), dtype=torch.float32, device=_device(x))
         m = _matrix(x)
+        self._here(_device(x))
+        out = _out(out, torch.float32, _rows(x), _device(x), "out")
         opt = _Options(sketch, 1 if refine else 0, rank_tol, nnz,
                        OPT_SVD_RANK if svd_rank else 0)
         info = _Info()
@@ -318,9 +378,9 @@ class Context:
 
     def order(self, scores, out=None, stream=None):
         import torch
-        if out is None:
-            out = torch.empty(scores.numel(), dtype=torch.int32,
-                              device=scores.device)
+        _scores_in(scores)
+        self._here(scores.device)
+        out = _out(out, torch.int32, scores.numel(), scores.device, "out")
         _check(load_library().slso_order(self._h, _ptr(scores), scores.numel(),
                                          _ptr(out), _stream(stream)), self._h)
         return out
@@ -331,10 +391,11 @@ class Context:
         singular vector of sigma[j]) as float64 device tensors."""
         import torch
         d = _cols(x)
+        m = _matrix(x)
+        self._here(_device(x))
         sx = torch.empty((r, d), dtype=torch.float64, device=_device(x))
         sigma = torch.empty(d, dtype=torch.float64, device=_device(x))
         v = torch.empty((d, d), dtype=torch.float64, device=_device(x))
-        m = _matrix(x)
         opt = _Options(sketch, 0, 0.0, nnz, 0)
         _check(load_library().slso_sketch_svd(
             self._h, ctypes.byref(m), seed, r, ctypes.byref(opt), _ptr(sx),
@@ -346,9 +407,9 @@ class Context:
         """One epoch's order by a sampling policy (ORDER_DEC, ORDER_SWR with
         replacement, ORDER_SWOR without): int32 row indices."""
         import torch
-        if out is None:
-            out = torch.empty(scores.numel(), dtype=torch.int32,
-                              device=scores.device)
+        _scores_in(scores)
+        self._here(scores.device)
+        out = _out(out, torch.int32, scores.numel(), scores.device, "out")
         _check(load_library().slso_order_sample(
             self._h, _ptr(scores), scores.numel(), policy, seed, epoch,
             _ptr(out), _stream(stream)), self._h)
@@ -363,6 +424,8 @@ class Context:
         """(R, path used) starting from ``path`` (QR_AUTO, QR_PANEL or
         QR_TREE); ``a`` is overwritten."""
         import torch
+        _f64_matrix(a, "a")
+        self._here(a.device)
         m, d = a.shape
         r = torch.empty((d, d), dtype=torch.float64, device=a.device)
         used = ctypes.c_int32(-1)
@@ -373,6 +436,12 @@ class Context:
 
     def solve_upper(self, r, b, stream=None):
         """Solve R X = B in place (B is d x k, float64)."""
+        _f64_matrix(r, "R")
+        _f64_matrix(b, "B")
+        self._here(r.device)
+        self._here(b.device)
+        if r.shape[0] != r.shape[1] or r.shape[0] != b.shape[0]:
+            raise ValueError("R must be d x d and B d x k")
         d, k = b.shape
         _check(load_library().slso_solve_upper(self._h, _ptr(r), d, _ptr(b), k,
                                                _stream(stream)), self._h)
@@ -380,13 +449,32 @@ class Context:
 
     def scores(self, x, m, out=None, stream=None):
         import torch
-        if out is None:
-            out = torch.empty(_rows(x), dtype=torch.float32, device=_device(x))
         mm = _matrix(x)
+        self._here(_device(x))
+        _on_gpu(m, "M")
+        if m.dtype != torch.float64 or m.dim() != 2 or not m.is_contiguous() \
+                or m.shape[0] != _cols(x):
+            raise ValueError("M must be a contiguous float64 d x k tensor")
+        self._here(m.device)
+        out = _out(out, torch.float32, _rows(x), _device(x), "out")
         _check(load_library().slso_scores(self._h, ctypes.byref(mm), _ptr(m),
                                           m.shape[1], _ptr(out),
                                           _stream(stream)), self._h)
         return out
+
+
+def _f64_matrix(a, what: str):
+    import torch
+    _on_gpu(a, what)
+    if a.dtype != torch.float64 or a.dim() != 2 or not a.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous 2-D float64 tensor")
+
+
+def _scores_in(scores):
+    import torch
+    _on_gpu(scores, "scores")
+    if scores.dtype != torch.float32 or not scores.is_contiguous():
+        raise TypeError("scores must be a contiguous float32 tensor")
 
 
 def _info_dict(info, st):
@@ -436,12 +524,12 @@ class Server:
         """Queue a job; X must already hold its values (synchronise first)."""
         import torch
         n = _rows(x)
-        if scores is None:
-            scores = torch.empty(n, dtype=torch.float32, device=_device(x))
-        if order and perm is None:
-            perm = torch.empty(n, dtype=torch.int32, device=_device(x))
+        jx = _matrix(x)
+        scores = _out(scores, torch.float32, n, _device(x), "scores")
+        if order:
+            perm = _out(perm, torch.int32, n, _device(x), "perm")
         job = _Job()
-        job.X = _matrix(x)
+        job.X = jx
         job.seed, job.r, job.k = seed, r, k
         job.opt = _Options(sketch, 1 if refine else 0, rank_tol, nnz, 0)
         job.scores = scores.data_ptr()

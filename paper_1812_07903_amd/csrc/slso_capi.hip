@@ -18,6 +18,7 @@ struct slso_ctx {
   void* ws = nullptr;       // device workspace
   size_t ws_bytes = 0;
   hipEvent_t ws_done = nullptr;  // recorded after the last work using ws
+  hipEvent_t side_done = nullptr;  // joins the side stream into a call's stream
   slso::QrStreams qs;            // QR look-ahead stream and events
   void* host_buf = nullptr; // pinned host staging for small read-backs
   std::string err;
@@ -149,12 +150,24 @@ size_t ws_alloc_bytes(size_t need) {
   return (need + g - 1) / g * g;
 }
 
-// Records ws_done on the call's stream when the call returns, after all of
-// its work on the workspace has been enqueued.
+// Orders a call's use of the context's workspace after every earlier call's,
+// whatever streams the two were made on: the call's stream first waits for
+// ws_done (recorded by the previous call), and when the call returns, after
+// all of its work has been enqueued, whatever it left on the side stream is
+// joined into its stream and ws_done is recorded there.
 struct WsMark {
   slso_ctx* c;
   hipStream_t s;
-  ~WsMark() { (void)hipEventRecord(c->ws_done, s); }
+  WsMark(slso_ctx* ctx, hipStream_t stream) : c(ctx), s(stream) {
+    (void)hipStreamWaitEvent(s, c->ws_done, 0);
+  }
+  ~WsMark() {
+    if (c->qs.side && hipEventRecord(c->side_done, c->qs.side) == hipSuccess)
+      (void)hipStreamWaitEvent(s, c->side_done, 0);
+    (void)hipEventRecord(c->ws_done, s);
+  }
+  WsMark(const WsMark&) = delete;
+  WsMark& operator=(const WsMark&) = delete;
 };
 
 int ensure_ws(slso_ctx* c, size_t bytes) {
@@ -428,11 +441,13 @@ int slso_create(slso_ctx** out, int device) {
   if (hipSetDevice(device) != hipSuccess ||
       hipHostMalloc(&c->host_buf, 4096, hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&c->ws_done, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->side_done, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&c->qs.side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->qs.factored, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->qs.bulk_done, hipEventDisableTiming) != hipSuccess) {
     if (c->qs.factored) (void)hipEventDestroy(c->qs.factored);
     if (c->qs.side) (void)hipStreamDestroy(c->qs.side);
+    if (c->side_done) (void)hipEventDestroy(c->side_done);
     if (c->ws_done) (void)hipEventDestroy(c->ws_done);
     if (c->host_buf) (void)hipHostFree(c->host_buf);
     delete c;
@@ -448,6 +463,7 @@ int slso_destroy(slso_ctx* c) {
   (void)hipEventSynchronize(c->ws_done);
   if (c->ws) (void)hipFree(c->ws);
   (void)hipEventDestroy(c->ws_done);
+  (void)hipEventDestroy(c->side_done);
   (void)hipStreamSynchronize(c->qs.side);
   (void)hipEventDestroy(c->qs.factored);
   (void)hipEventDestroy(c->qs.bulk_done);

@@ -151,3 +151,37 @@ def test_server_rejects_invalid_arguments(lib):
     assert lib.slso_server_wait(None, 1, None) == slso.EINVAL
     assert lib.slso_server_stats(None, None) == slso.EINVAL
     assert lib.slso_server_destroy(None) == slso.EINVAL
+
+
+# ---- binding checks: host tensors and wrong outputs never reach the kernels --
+torch = pytest.importorskip("torch")
+
+
+def test_binding_rejects_host_tensors():
+    x = torch.zeros((10, 4), dtype=torch.float32)
+    with pytest.raises(ValueError, match="GPU"):
+        slso._matrix(x)
+    with pytest.raises(ValueError, match="GPU"):
+        slso._matrix(slso.Fp8Matrix(torch.zeros((10, 4), dtype=torch.uint8),
+                                    torch.ones(4)))
+    csr = slso.CsrMatrix(2, 3, torch.tensor([0, 1, 2]),
+                         torch.tensor([0, 2], dtype=torch.int32),
+                         torch.ones(2))
+    with pytest.raises(ValueError, match="GPU"):
+        slso._matrix(csr)
+    with pytest.raises(TypeError):
+        slso._matrix(x.numpy())
+
+
+def test_binding_checks_outputs():
+    # outputs are checked for device first, then dtype, size and layout
+    with pytest.raises(ValueError, match="GPU"):
+        slso._out(torch.empty(5, dtype=torch.float32), torch.float32, 5,
+                  "cuda:0", "out")
+    with pytest.raises(ValueError, match="GPU"):
+        slso._out(torch.empty(5, dtype=torch.float64), torch.float32, 5,
+                  "cuda:0", "out")
+    with pytest.raises(ValueError, match="GPU"):
+        slso._scores_in(torch.empty(5, dtype=torch.float32))
+    with pytest.raises(ValueError):
+        slso._f64_matrix(torch.empty((3, 3), dtype=torch.float64), "R")

@@ -263,3 +263,34 @@ def test_svd_rank_mode(slso, ctx):
     ref = olv.sketched_leverage(y, 3, 1024, 16)
     assert ia["rank"] == 32
     assert _report("full rank, svd decision", host(a), ref["scores"])[0] < 1e-5
+
+
+def test_calls_on_two_streams_share_the_workspace_in_order(slso, ctx):
+    """Two leverage calls and their orderings issued back to back on two
+    streams, with no synchronisation between them, use one context's
+    workspace: the second call's sketch must not overwrite what the first
+    call's scoring pass still reads. Each result must equal, bit for bit,
+    the same call made alone."""
+    n, d, r, k = 200003, 256, 2048, 64
+    xs = [dev(synth.lowrank_dense(n, d, d // 2,
+                                  2.0 ** (-np.arange(d // 2) / 4.0), 1e-3, 1.0,
+                                  seed=300 + i).astype(np.float32))
+          for i in range(2)]
+    alone = []
+    for i, x in enumerate(xs):
+        sc, _ = ctx.leverage(x, 40 + i, r, k)
+        pm = ctx.order(sc)
+        alone.append((host(sc).copy(), host(pm).copy()))
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in xs]
+    perms = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in xs]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for i, x in enumerate(xs):
+            ctx.leverage(x, 40 + i, r, k, out=outs[i], stream=streams[i])
+            ctx.order(outs[i], out=perms[i], stream=streams[i])
+        torch.cuda.synchronize()
+        for i in range(2):
+            assert np.array_equal(host(outs[i]).view(np.uint32),
+                                  alone[i][0].view(np.uint32)), (rep, i)
+            assert np.array_equal(host(perms[i]), alone[i][1]), (rep, i)
