@@ -13,9 +13,12 @@
 // Validity. Cholesky-QR2 reaches the accuracy of Householder QR when the first
 // pass leaves Q1 well conditioned, i.e. when kappa(A)^2 u is well below one.
 // This is checked a posteriori: with E = G2 - I and e = max |E_ij|,
-//   e <= 1e-9      R2 = I + up(E) (strict upper part plus half the diagonal;
-//                  the neglected F^T F term is below d e^2 <= 1e-15 for
-//                  d <= 1000) and R = R1 + up(E) R1 in one launch;
+//   e <= e_near(d) R2 = I + up(E) (strict upper part plus half the diagonal)
+//                  and R = R1 + up(E) R1 in one launch. With R2 = I + F,
+//                  F + F^T = E - F^T F, so the neglected term is at most
+//                  d e^2 per entry; e_near(d) = min(1e-9, sqrt(1e-15 / d))
+//                  keeps it below 1e-15 (about 9 units of FP64 rounding) at
+//                  every d: 1e-9 up to d = 1000, 4.9e-10 at d = 4096;
 //   e <= 0.25 / d  status 2: the caller runs cholqr2_finish, the blocked
 //                  Cholesky of G2 and R = R2 R1;
 //   otherwise, or when a Cholesky pivot of G1 falls to 1e-13 of its diagonal
@@ -38,7 +41,11 @@ namespace {
 
 constexpr int64_t kT2 = kP * kP;        // elements of a tile
 constexpr double kPivotTol = 1e-13;     // Cholesky pivot / diagonal entry
-constexpr double kNearId = 1e-9;        // max |G2 - I| for the one-launch R2
+// max |G2 - I| for the one-launch R2 (see above)
+__host__ __device__ inline double near_id(int64_t d) {
+  const double b = sqrt(1e-15 / static_cast<double>(d));
+  return b < 1e-9 ? b : 1e-9;
+}
 
 inline unsigned cdivu(int64_t a, int64_t b) {
   return static_cast<unsigned>((a + b - 1) / b);
@@ -805,7 +812,7 @@ __global__ void __launch_bounds__(256)
     }
     const double em = __longlong_as_double(static_cast<long long>(red[0]));
     const bool ok = em <= 0.25 / static_cast<double>(d);  // false for NaN
-    if (!ok || em > kNearId) {
+    if (!ok || em > near_id(d)) {
       if (status && blockIdx.x == 0 && t == 0) *status = ok ? 2 : 1;
       return;
     }
@@ -960,7 +967,7 @@ __global__ void __launch_bounds__(256)
     }
     const double em = __longlong_as_double(static_cast<long long>(redu[0]));
     const bool ok = em <= 0.25 / static_cast<double>(d);
-    if (!ok || em > kNearId) {
+    if (!ok || em > near_id(d)) {
       if (t == 0) *status = ok ? 2 : 1;
       return;
     }
