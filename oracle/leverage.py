@@ -141,8 +141,9 @@ def exact_leverage(x: np.ndarray, rank_tol: float = DEFAULT_RANK_TOL):
 def sketch_of(x, seed: int, r: int, kind: str = "countsketch",
               precision: str = "bf16", nnz: int = 2) -> np.ndarray:
     """Unscaled sketch S X (FP64). For the Gaussian sketch, ``precision``
-    names the entries of S ("bf16": reduced-precision inputs, "f32": the
-    plain FP32 path, "f64": the FP64 stream); for OSNAP, ``nnz`` is the
+    names the entries of S ("bf16" / "fp8": the quantile form for BF16 / FP8
+    inputs, "f32": the plain FP32 path, "f64": the FP64 stream); for OSNAP,
+    ``nnz`` is the
     number of nonzeros per column of S."""
     if kind == "countsketch":
         if isinstance(x, np.ndarray):

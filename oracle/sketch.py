@@ -149,8 +149,8 @@ def gaussian_sketch_dense(x: np.ndarray, seed: int, r: int,
     """SX = G X / sqrt(r) in FP64.
 
     ``precision`` selects the entries of G: "f64" the FP64 Box-Muller stream,
-    "f32" the FP32 generator (plain FP32 path), "bf16" the FP32 generator
-    rounded to bfloat16 (reduced-precision inputs). The product is FP64.
+    "f32" the FP32 generator (plain FP32 path), "bf16" and "fp8" the quantile
+    form rounded to BF16 or e4m3 (BF16 and FP8 inputs). The product is FP64.
     """
     n = x.shape[0]
     if g is None:
@@ -158,8 +158,8 @@ def gaussian_sketch_dense(x: np.ndarray, seed: int, r: int,
             g = streams.gaussian_sketch_matrix(seed, r, n)
         elif precision == "f32":
             g = streams.gaussian_sketch_matrix_f32(seed, r, n)
-        elif precision == "bf16":
-            g = streams.gaussian_sketch_matrix_bf16(seed, r, n)
+        elif precision in ("bf16", "fp8"):
+            g = streams.gaussian_sketch_matrix_q(seed, r, n, precision)
         else:
             raise ValueError(precision)
     return (np.asarray(g, dtype=np.float64) @ np.asarray(x, dtype=np.float64)) \

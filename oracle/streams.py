@@ -31,10 +31,23 @@ library) are:
   sqrt(2) range split, sqrt(L) = L rsqrt(L) with the 0x5F3759DF seed and three
   Newton steps, cos/sin of 2 pi u2 by quadrant: Taylor polynomials at the
   quadrant's centre rotated by +-sqrt(1/2)); cos for even i, sin for odd i.
-  Reduced-precision inputs take it rounded to BF16 (ties to even).
+  This is the plain FP32 path's generator.
 
-Stream ids: 1 bucket hash, 2 sign hash, 3 Gaussian sketch, 4 Pi_2,
-5 dec-swr draws, 6 dec-swor keys, 7 SRHT signs, 8 SRHT row choice.
+* Quantile form of the Gaussian sketch entries (``gaussian_q``; stream 9),
+  used for BF16 and FP8 inputs, whose sketch entries are BF16 or e4m3
+  values: one Philox block per eight consecutive data rows, counter
+  (lo32(q), hi32(q), j, 9) with q = i >> 3; data row i takes the 16-bit half
+  (i & 1: high, else low) of word (i >> 1) & 3. Its top bit is the sign and
+  its low 15 bits a cell m of 2^15 equiprobable cells of |Z|, Z standard
+  normal; the magnitude is the cell's midpoint quantile
+  t_m = sqrt(2) erfinv((2 m + 1) / 65536) rounded to BF16 (ties to even) for
+  BF16 input, to e4m3 (ties to even) for FP8 input. Every t_m lies more than
+  1e-9 of itself from a rounding boundary of either format, so any FP64
+  evaluation of erfinv good to 1e-12 gives the same two tables.
+
+Stream ids: 1 bucket hash, 2 sign hash, 3 Gaussian sketch (FP32 entries),
+4 Pi_2, 5 dec-swr draws, 6 dec-swor keys, 7 SRHT signs, 8 SRHT row choice,
+9 Gaussian sketch (quantile form).
 
 * SRHT (the randomized Hadamard transform of Sec. 2.1 / Table 1): row i's
   sign is +1 if P(i) is even for the polynomial hash of stream 7; the r
@@ -73,6 +86,7 @@ STREAM_SWR = 5
 STREAM_SWOR = 6
 STREAM_SRHT_SIGN = 7
 STREAM_SRHT_ROWS = 8
+STREAM_GAUSS_Q = 9
 
 
 def splitmix64_mix(z: int) -> int:
@@ -342,14 +356,6 @@ def gaussian_f32(seed: int, stream: int, i, j) -> np.ndarray:
     return np.select([r == 0, r == 1, r == 2], [z0, z1, z2], z3).astype(F32)
 
 
-def bf16_round(x) -> np.ndarray:
-    """Round FP32 values to the nearest bfloat16 (ties to even), as FP32."""
-    u = np.asarray(x, dtype=F32).view(np.uint32).astype(np.uint64)
-    u = ((u + np.uint64(0x7FFF) + ((u >> np.uint64(16)) & np.uint64(1)))
-         >> np.uint64(16)) << np.uint64(16)
-    return u.astype(np.uint32).view(F32)
-
-
 def gaussian_sketch_matrix_f32(seed: int, r: int, n: int, row0: int = 0):
     """Sketch G (r x n) with FP32 entries (the plain FP32 path), generated a
     few sketch rows at a time to bound the temporaries."""
@@ -362,7 +368,99 @@ def gaussian_sketch_matrix_f32(seed: int, r: int, n: int, row0: int = 0):
     return out
 
 
-def gaussian_sketch_matrix_bf16(seed: int, r: int, n: int, row0: int = 0):
-    """Sketch G (r x n) with entries bf16(gaussian_f32): the reduced-precision
-    path's S = G / sqrt(r)."""
-    return bf16_round(gaussian_sketch_matrix_f32(seed, r, n, row0))
+
+
+# --------------------------------------------------------------------------
+# Quantile form of the Gaussian sketch entries (BF16 and FP8 inputs)
+# --------------------------------------------------------------------------
+QCELLS = 1 << 15
+
+
+def half_normal_quantiles() -> np.ndarray:
+    """t_m = sqrt(2) erfinv((2 m + 1) / 65536), m = 0 .. 2^15 - 1 (FP64): the
+    quantile of |Z| at the midpoint of the m-th of 2^15 equiprobable cells,
+    since P(|Z| <= t) = erf(t / sqrt(2))."""
+    from scipy.special import erfinv
+    m = np.arange(QCELLS, dtype=np.float64)
+    return np.sqrt(2.0) * erfinv((2.0 * m + 1.0) / 65536.0)
+
+
+def round_to_format(v, fmt: str) -> np.ndarray:
+    """Round non-negative FP64 values to the nearest BF16 ("bf16": 8
+    significant bits) or OCP e4m3fn ("fp8": 4 significant bits, subnormal
+    spacing 2^-9, largest finite 448) value, ties to even, as FP64."""
+    v = np.asarray(v, dtype=np.float64)
+    _, ex = np.frexp(v)                      # v = f 2^ex, f in [0.5, 1)
+    e = ex - 1                               # v in [2^e, 2^(e+1))
+    if fmt == "bf16":
+        spacing = np.ldexp(1.0, e - 7)
+    elif fmt == "fp8":
+        spacing = np.ldexp(1.0, np.maximum(e, -6) - 3)
+    else:
+        raise ValueError(fmt)
+    out = np.round(v / spacing) * spacing    # exact quotient; half to even
+    out = np.where(v == 0.0, 0.0, out)
+    if fmt == "fp8":
+        out = np.minimum(out, 448.0)
+    return out
+
+
+def quantile_table(fmt: str) -> np.ndarray:
+    """Magnitudes of the quantile-form entries: t_m rounded to ``fmt``."""
+    return round_to_format(half_normal_quantiles(), fmt)
+
+
+def gaussian_q_halfwords(seed: int, i, j) -> np.ndarray:
+    """The 16-bit value behind the quantile-form entry (data row i, sketch
+    row j), broadcast, as int64."""
+    i = np.asarray(i, dtype=np.uint64)
+    j = np.asarray(j, dtype=np.uint64)
+    i, j = np.broadcast_arrays(i, j)
+    q = i >> np.uint64(3)
+    w = philox4x32_10(q & np.uint64(MASK32), q >> np.uint64(32), j,
+                      np.full(i.shape, STREAM_GAUSS_Q, np.uint64),
+                      seed & MASK32, (seed >> 32) & MASK32)
+    widx = ((i >> np.uint64(1)) & np.uint64(3)).astype(np.int64)
+    word = np.select([widx == 0, widx == 1, widx == 2], list(w[:3]), w[3])
+    half = (i & np.uint64(1)).astype(bool)
+    return np.where(half, word >> np.uint64(16),
+                    word & np.uint64(0xFFFF)).astype(np.int64)
+
+
+def gaussian_q(seed: int, i, j, fmt: str, table=None) -> np.ndarray:
+    """Quantile-form Gaussian entry for data row i and sketch row j (FP64
+    value of a BF16 or e4m3 number)."""
+    t = quantile_table(fmt) if table is None else table
+    v = gaussian_q_halfwords(seed, i, j)
+    mag = t[v & (QCELLS - 1)]
+    return np.where(v >> 15, -mag, mag)
+
+
+def gaussian_sketch_matrix_q(seed: int, r: int, n: int, fmt: str,
+                             row0: int = 0) -> np.ndarray:
+    """Sketch G (r x n) with quantile-form entries (FP64 values). Each
+    Philox block is evaluated once and split into its eight 16-bit halves
+    (data rows 8q .. 8q + 7 in order), a few sketch rows at a time."""
+    t = quantile_table(fmt)
+    out = np.empty((r, n), dtype=np.float64)
+    if n == 0:
+        return out
+    q0, q1 = row0 >> 3, (row0 + n - 1) >> 3
+    q = np.arange(q0, q1 + 1, dtype=np.uint64)[None, :]
+    lo = row0 - 8 * q0
+    step = max(1, (1 << 18) // q.shape[1])
+    for j0 in range(0, r, step):
+        j = np.arange(j0, min(r, j0 + step), dtype=np.uint64)[:, None]
+        jq, qq = np.broadcast_arrays(j, q)
+        w = philox4x32_10(qq & np.uint64(MASK32), qq >> np.uint64(32), jq,
+                          np.full(qq.shape, STREAM_GAUSS_Q, np.uint64),
+                          seed & MASK32, (seed >> 32) & MASK32)
+        halves = []
+        for word in w:
+            halves.append(word & np.uint64(0xFFFF))
+            halves.append(word >> np.uint64(16))
+        v = np.stack(halves, axis=-1).reshape(jq.shape[0], -1).astype(np.int64)
+        v = v[:, lo:lo + n]
+        mag = t[v & (QCELLS - 1)]
+        out[j0:j0 + jq.shape[0]] = np.where(v >> 15, -mag, mag)
+    return out

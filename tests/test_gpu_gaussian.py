@@ -71,7 +71,7 @@ def as_input(slso, x64, kind):
     if kind == "fp8":
         codes, cs = synth.to_fp8_e4m3(x64)
         return (slso.Fp8Matrix(dev(codes), dev(cs)),
-                synth.fp8_e4m3_to_f64(codes, cs), "bf16")
+                synth.fp8_e4m3_to_f64(codes, cs), "fp8")
     raise ValueError(kind)
 
 
@@ -96,7 +96,7 @@ def test_gaussian_sketch_matches_oracle(slso, ctx, kind, n, d, r):
     xin, xval, prec = as_input(slso, x64, kind)
     sx = host(ctx.sketch(xin, 99, r, sketch=slso.GAUSSIAN))
     g = (ost.gaussian_sketch_matrix_f32(99, r, n) if prec == "f32"
-         else ost.gaussian_sketch_matrix_bf16(99, r, n)).astype(np.float64)
+         else ost.gaussian_sketch_matrix_q(99, r, n, prec)).astype(np.float64)
     ref = osk.gaussian_sketch_dense(xval, 99, r, g=g)
     bound = 1e-4 * (np.abs(g) @ np.abs(xval)) / math.sqrt(r)
     err = np.abs(sx - ref)
@@ -116,9 +116,15 @@ def test_fp8_countsketch_matches_oracle(slso, ctx):
 
 
 # ---- leverage with the Gaussian sketch (no refinement) -------------------------
-@pytest.mark.parametrize("kind", ["f32", "bf16"])
-def test_gaussian_leverage_matches_sketched_oracle(slso, ctx, kind):
-    x64 = synth.config0(n=20000, d=64, seed=21)
+@pytest.mark.parametrize("kind,n", [("f32", 20000), ("bf16", 20000),
+                                    ("f32", 140001)])
+def test_gaussian_leverage_matches_sketched_oracle(slso, ctx, kind, n):
+    """Unrefined Gaussian-sketch leverage. FP32 input is the plain FP32 path
+    (FP32 entries of S on the FP32 MFMA): the FP32 gate, <= 1e-5 against
+    the FP64 oracle of the same sketch, at one row split (n = 20000) and at
+    three (n = 140001: FP32 sums within splits of at most 65536 rows, FP64
+    across them). BF16 input: the reduced-precision gate."""
+    x64 = synth.config0(n=n, d=64, seed=21)
     xin, xval, prec = as_input(slso, x64, kind)
     got, info = ctx.leverage(xin, 8, 512, 32, sketch=slso.GAUSSIAN)
     got = host(got)
@@ -126,10 +132,11 @@ def test_gaussian_leverage_matches_sketched_oracle(slso, ctx, kind):
                                 precision=prec)
     assert info["rank"] == ref["rank"] == 64
     assert not info["refined"]
-    err = _report(f"gauss lev {kind}", got, ref["scores"])
-    # sketch entries differ from the FP64 sums by ~1e-6 relative; R and the
-    # scores inherit that times the conditioning of the equilibrated sketch
-    assert err < 1e-3
+    err = _report(f"gauss lev {kind} n={n}", got, ref["scores"])
+    if kind == "f32":
+        assert err <= 1e-5
+    else:
+        assert err <= 1e-2 and omet.kendall_tau(got, ref["scores"]) >= 0.99
 
 
 def test_fp8_countsketch_leverage(slso, ctx):

@@ -105,7 +105,109 @@ def test_gaussian_f32_distribution():
     assert stats.kstest(z, "norm").pvalue > 1e-4
 
 
-def test_bf16_round_ties_to_even():
-    x = np.array([1.0, 1.00390625, 1.01171875, -3.3, 0.0], np.float32)
-    want = np.array([1.0, 1.0, 1.015625, -3.296875, 0.0], np.float32)
-    assert np.array_equal(streams.bf16_round(x), want)
+# ---- quantile form of the sketch entries (BF16 / FP8 inputs) ----------------
+def test_half_normal_quantiles_against_library_halfnorm():
+    """t_m against scipy's half-normal quantile function (a separate routine
+    from erfinv), and the first cells against erfinv's leading term
+    sqrt(pi)/2 p: t_m ~ sqrt(pi/2) (2m + 1) / 65536."""
+    t = streams.half_normal_quantiles()
+    m = np.arange(streams.QCELLS)
+    assert np.all(np.diff(t) > 0)
+    ref = stats.halfnorm.ppf((m + 0.5) / streams.QCELLS)
+    assert np.max(np.abs(t - ref) / t) < 1e-12
+    lead = np.sqrt(np.pi / 2) * (2 * m[:4] + 1) / 65536.0
+    assert np.max(np.abs(t[:4] - lead) / lead) < 1e-8
+
+
+def _rounding_margin(t, fmt):
+    """Relative distance of each t to the nearest rounding boundary (midpoint
+    of two neighbours) of the format."""
+    _, ex = np.frexp(t)
+    e = ex - 1
+    sp = np.ldexp(1.0, e - 7) if fmt == "bf16" else \
+        np.ldexp(1.0, np.maximum(e, -6) - 3)
+    fr = t / sp - np.floor(t / sp)
+    return np.abs(fr - 0.5) * sp / t
+
+
+def test_quantile_tables_well_defined_and_rounded():
+    """No t_m lies within 1e-9 (relative) of a rounding boundary, so the
+    tables do not depend on how erfinv is evaluated; the roundings agree with
+    independent implementations: torch's FP64 -> bfloat16 conversion, and the
+    e4m3 quantiser of the input generators (nearest representable value by
+    search, a column with maximum 448 so that its scale is 1)."""
+    import synth
+    torch = pytest.importorskip("torch")
+    t = streams.half_normal_quantiles()
+    for fmt in ("bf16", "fp8"):
+        assert _rounding_margin(t, fmt).min() > 1e-9
+    tb = streams.quantile_table("bf16")
+    assert np.array_equal(
+        tb, torch.from_numpy(t).to(torch.bfloat16).to(torch.float64).numpy())
+    codes, cs = synth.to_fp8_e4m3(np.concatenate([t, [448.0]])[:, None])
+    assert cs[0] == 1.0
+    t8 = streams.quantile_table("fp8")
+    assert np.array_equal(t8, synth.fp8_e4m3_to_f64(codes, cs)[:-1, 0])
+    # e4m3: the cells below 2^-10 round to zero, the largest to 4.5
+    assert t8[0] == 0.0 and t8[-1] == 4.5
+    # rounding ties go to the even neighbour
+    assert np.array_equal(streams.round_to_format(
+        np.array([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 0.0]), "bf16"),
+        [1.0, 1.0 + 2.0 ** -6, 0.0])
+    assert np.array_equal(streams.round_to_format(
+        np.array([1.0625, 1.1875, 2.0 ** -10, 3 * 2.0 ** -10, 500.0]), "fp8"),
+        [1.0, 1.25, 0.0, 2.0 ** -8, 448.0])
+
+
+def test_gaussian_q_block_layout_and_counter():
+    """Entry (i, j) from its own Philox block equals the block-split matrix
+    at any row offset; the eight data rows of one block are its eight 16-bit
+    halves, low half first, words in order."""
+    j = np.arange(37)[:, None]
+    for row0, n in ((0, 64), (5, 1001), (2 ** 33 + 3, 29)):
+        i = np.arange(row0, row0 + n, dtype=np.uint64)[None, :]
+        for fmt in ("bf16", "fp8"):
+            a = streams.gaussian_q(11, i, j, fmt)
+            b = streams.gaussian_sketch_matrix_q(11, 37, n, fmt, row0=row0)
+            assert np.array_equal(a, b)
+    w = streams.philox4x32_10(np.uint64(3), np.uint64(0), np.uint64(5),
+                              np.uint64(streams.STREAM_GAUSS_Q), 77, 0)
+    halves = [int(x) & 0xFFFF if h == 0 else int(x) >> 16
+              for x in w for h in (0, 1)]
+    got = streams.gaussian_q_halfwords(77, np.arange(24, 32), 5)
+    assert list(got) == halves
+
+
+def test_gaussian_q_distribution():
+    """Sample of 400000 entries: halves uniform over 2^16 values (chi^2 on
+    256 bins of the top byte and on the low byte), signs balanced, mean 0,
+    variance that of the table, neighbouring entries uncorrelated. The law
+    of a BF16 entry (2^16 equiprobable signed cells) is within 2^-9 of
+    N(0,1) in Kolmogorov distance (BF16 rounding moves a quantile z by at
+    most 2^-8 |z|, and z phi(z) <= 0.25), and the sample's KS statistic
+    within that plus sampling noise."""
+    i = np.arange(100000)[None, :]
+    j = np.arange(4)[:, None]
+    v = streams.gaussian_q_halfwords(2024, i, j).ravel()
+    for byte in (v >> 8, v & 0xFF):
+        c = np.bincount(byte, minlength=256)
+        chi2 = ((c - v.size / 256) ** 2 / (v.size / 256)).sum()
+        assert stats.chi2.sf(chi2, 255) > 1e-4
+    for fmt in ("bf16", "fp8"):
+        z = streams.gaussian_sketch_matrix_q(2024, 4, 100000, fmt).ravel()
+        tab = streams.quantile_table(fmt)
+        assert abs(z.mean()) < 5 / np.sqrt(z.size)
+        assert abs(z.var() - (tab ** 2).mean()) < 6 * np.sqrt(2 / z.size)
+        assert abs((tab ** 2).mean() - 1) < (2e-5 if fmt == "bf16" else 1e-3)
+        if fmt == "bf16":
+            # exact Kolmogorov distance of the table's law: the CDF jumps by
+            # 2^-16 at each signed value; compare both sides of every jump
+            vals = np.sort(np.concatenate([-tab, tab]))
+            cdf_hi = np.arange(1, vals.size + 1) / vals.size
+            phi = stats.norm.cdf(vals)
+            law_ks = max(np.abs(cdf_hi - phi).max(),
+                         np.abs(cdf_hi - 2.0 ** -16 - phi).max())
+            assert law_ks < 2.0 ** -9
+            ks = stats.kstest(z, "norm").statistic
+            assert ks < law_ks + 1.63 / np.sqrt(z.size)
+        assert abs(np.corrcoef(z[:-1], z[1:])[0, 1]) < 5 / np.sqrt(z.size)
