@@ -1,78 +1,85 @@
 #!/usr/bin/env python3
 """Throughput of the sketched leverage-score path on one MI355X.
 
-One step = slso_leverage (column equilibration, CountSketch, FP64 Householder
-QR of the sketch, rank screen, Pi_2 and triangular solve, scores) followed by
-slso_order (dec ordering), on the image-like workload: dense FP32 X with
-n = 60000, d = 784 (entries in [0, 1], rank 50 + noise, 10 clusters),
-CountSketch r = 16384, k = 64. X is resident in HBM before the clock starts.
+One step = slso_leverage (sketch, QR of the sketch, rank screen, refinement
+where asked, Pi_2 and the triangular factor, scores) followed by slso_order
+(dec ordering) on one synthetic job whose input is resident in HBM before
+the clock starts.
+
+Workloads (``--workload``):
+* ``precision`` (default): dense X with n = 4e6, d = 512 (rank 256 with
+  sigma_j = j^-1.5, noise 1e-4, row scales e^N(0, 1.5^2)); Gaussian sketch
+  r = 2048, Cholesky-QR refinement, k = 64. The headline runs BF16 input; the
+  FP8-e4m3 input (per-column scales) and the plain FP32 path (FP32 input,
+  FP32 MFMA sketch, no refinement) are timed beside it. The text-like CSR
+  and serving workloads follow as extra keys unless ``--headline-only``.
+* ``image``: dense FP32 image-like X (n = 60000, d = 784), CountSketch
+  r = 16384, k = 64.
+* ``text``: CSR X (n = 5e5, d = 4096, 0.5 % dense, tf-idf-like), CountSketch
+  on CSR r = 32768, k = 64.
+* ``serving``: a Poisson stream of mixed jobs through the library's server.
 
 Prints one JSON line: rows/s over the timed steps, p50/p99 step latency, the
-max relative score error and Kendall tau of the last step against the FP64
-oracle, the roofline of the dominant kernel (HIP events recorded live around
-every launch in the timed region) and the oracle's own CPU throughput.
+max relative score error and Kendall tau against the FP64 oracle on a
+bounded sample job of the same workload, the roofline of the dominant kernel
+(HIP events recorded live around its launches in the timed region) and the
+oracle's own CPU throughput.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
 import time
+from dataclasses import dataclass
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {"hbm": 8.0e12, "fp64": 78.6e12, "fp32": 157.3e12}
-
-N, D, R, K, SEED = 60000, 784, 16384, 64, 2001
-
-
-def qr_update_flops(m: int, d: int, w: int = 16) -> float:
-    """Algorithmic flops of the blocked Householder trailing updates
-    (Y^T C and C - Y W: 4 m' w n' per panel)."""
-    f = 0.0
-    for j0 in range(0, d, w):
-        wj = min(w, d - j0)
-        f += 4.0 * (m - j0) * wj * (d - j0 - wj)
-    return f
+PEAK = {"hbm": 8.0e12, "fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15,
+        "fp8": 5.0e15}
+METRIC = ("rows/sec leverage-scored at stated rel err vs FP64; "
+          "p50/p99 job latency")
 
 
-def qr_node_flops(m: int, d: int, w: int = 16) -> float:
-    """Algorithmic flops of the panel factorisations (unblocked Householder
-    on (m - j0) x w panels: 2 m' w^2 - 2/3 w^3)."""
-    f = 0.0
-    for j0 in range(0, d, w):
-        wj = min(w, d - j0)
-        f += 2.0 * (m - j0) * wj * wj - (2.0 / 3.0) * wj ** 3
-    return f
+@dataclass
+class Shape:
+    """A job's sizes, as the roofline formulas need them."""
+    n: int
+    d: int
+    r: int
+    k: int
+    xbytes: int          # bytes per stored element of X (CSR: per nonzero)
+    dtype: str           # "f32", "bf16", "fp8", "f64", "csr"
+    nnz: int = 0
 
 
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---- rooflines ----------------------------------------------------------------
 # profiler name -> (kernel symbol in the PMC summary, source file)
 KERNEL_SRC = {
     "cq2_gram": ("gram_block_kernel<false,true>", "k_cholqr.hip"),
     "cq2_solve": ("stripe_solve_kernel<64>", "k_cholqr.hip"),
-    "cq_update": ("cq_update_kernel", "k_cqr.hip"),
-    "cq_z": ("cq_z_kernel", "k_cqr.hip"),
-    "cq_q1": ("cq_q1_kernel", "k_cqr.hip"),
-    "cq_gram": ("cq_gram_kernel", "k_cqr.hip"),
-    "qr_node": ("qr_node_kernel", "k_qr.hip"),
-    "qr_update": ("qr_update_kernel", "k_qr.hip"),
     "score": ("score_mfma_kernel<3,true>", "k_score.hip"),
     "countsketch": ("countsketch_colmax_kernel<float,false>", "k_sketch.hip"),
-    "colmax": ("colmax_dense_kernel<float>", "k_sketch.hip"),
 }
 PMC_SUMMARY = os.path.join(ROOT, "profiles",
                            "pmc_traffic_image_like_n60000_d784.txt")
 
 
-def measured_traffic(name: str):
+def measured_traffic(name: str, workload: str):
     """Calibrated HBM bytes per launch from the committed rocprofv3 PMC
-    summary, or None when there is none or the kernel's source has changed
-    since the counters were taken."""
-    import hashlib
-    if name not in KERNEL_SRC or not os.path.exists(PMC_SUMMARY):
+    summary of the image-like workload, or None for other workloads, when
+    there is none, or when the kernel's source has changed since the
+    counters were taken."""
+    if workload != "image" or name not in KERNEL_SRC or \
+            not os.path.exists(PMC_SUMMARY):
         return None
     sym, src = KERNEL_SRC[name]
     path = os.path.join(ROOT, "paper_1812_07903_amd", "csrc", src)
@@ -86,100 +93,510 @@ def measured_traffic(name: str):
     return None
 
 
-def roofline_for(name: str, ms_per_launch: float, launches_per_step: float):
-    """Algorithmic work per launch of a kernel at this workload."""
-    r = _roofline(name, ms_per_launch, launches_per_step)
-    if r is not None:
-        r["traffic"] = measured_traffic(name)
-    return r
+def _rate(bound: str, work: float, sec: float, peak_key: str):
+    a = work / sec
+    p = PEAK[peak_key]
+    if bound == "hbm":
+        return {"bound": "hbm", "achieved": a / 1e9, "peak": p / 1e9,
+                "unit": "GB/s", "frac": a / p, "traffic": None}
+    return {"bound": bound, "achieved": a / 1e12, "peak": p / 1e12,
+            "unit": "TFLOP/s", "frac": a / p, "traffic": None}
 
 
-def cq_panels(m: int = R, d: int = D):
-    """(active rows, trailing columns) of each 64-column Cholesky-QR2 panel."""
-    return [(m - j0, d - j0 - 64) for j0 in range(0, d - 63, 64)]
-
-
-def _fp64(flops_per_launch: float, sec: float):
-    a = flops_per_launch / sec
-    return {"bound": "mfma", "achieved": a / 1e12, "peak": PEAK["fp64"] / 1e12,
-            "unit": "TFLOP/s", "frac": a / PEAK["fp64"], "traffic": None}
-
-
-def _roofline(name: str, ms_per_launch: float, launches_per_step: float):
-    sec = ms_per_launch * 1e-3
-    if name == "cq2_gram":
-        # the upper triangle of A^T A: d (d + 1) / 2 entries of m products
-        # each when the last column block is at most 16 wide (its products
-        # are formed by the same launch), else the part inside full
-        # 128-column blocks (c = 128 floor(d / 128))
-        c = D if D % 128 <= 16 else 128 * (D // 128)
-        return _fp64(float(R) * c * (c + 1), sec)
-    if name == "cq2_gram_edge":
-        # the rest of the upper triangle (columns past c), plus the sum of
-        # the partial blocks
-        c = 128 * (D // 128)
-        return _fp64(float(R) * (D * (D + 1) - c * (c + 1)), sec)
-    if name == "cq2_solve":
-        # Q1 = A R1^{-1}: m d^2 flop
-        return _fp64(float(R) * D * D, sec)
-    if name in ("cq2_chol", "cq2_r"):
-        # d^3 / 3 flop (Cholesky of G1; R = R2 R1 with triangular R2, R1)
-        a = D ** 3 / 3.0 / sec
-        return {"bound": "alu", "achieved": a / 1e12,
-                "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
-                "frac": a / PEAK["fp64"], "traffic": None}
-    if name in ("cq_update", "cq_z"):
-        # C -= Q1 K  /  Z = Q1^T C: 2 m' 64 n' flop per panel
-        f = sum(2.0 * mp * 64 * nc for mp, nc in cq_panels() if nc > 0)
-        return _fp64(f / launches_per_step, sec)
-    if name == "cq_q1":
-        # Q1 = P R1^{-1} and G2 = Q1^T Q1: 2 x 2 m' 64^2 flop per panel
-        return _fp64(sum(4.0 * mp * 64 * 64 for mp, _ in cq_panels())
-                     / launches_per_step, sec)
-    if name == "cq_gram":
-        return _fp64(sum(2.0 * mp * 64 * 64 for mp, _ in cq_panels())
-                     / launches_per_step, sec)
-    if name in ("cq_recon", "cq_chol"):
-        # one workgroup per panel: Cholesky (64^3 / 3), triangular inverses,
-        # the sign-choosing LU (2 64^3 / 3) and several 64^3 products
-        f = {"cq_chol": 64 ** 3, "cq_recon": 14 * 64 ** 3}[name]
-        a = f / sec
-        return {"bound": "alu", "achieved": a / 1e12,
-                "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
-                "frac": a / PEAK["fp64"], "traffic": None}
-    if name == "qr_update":
-        flops = qr_update_flops(R, D) / launches_per_step
-        a = flops / sec
-        return {"bound": "alu", "achieved": a / 1e12, "peak": PEAK["fp64"] / 1e12,
-                "unit": "TFLOP/s", "frac": a / PEAK["fp64"], "traffic": None}
-    if name == "qr_node":
-        flops = qr_node_flops(R, D) / launches_per_step
-        a = flops / sec
-        return {"bound": "alu", "achieved": a / 1e12, "peak": PEAK["fp64"] / 1e12,
-                "unit": "TFLOP/s", "frac": a / PEAK["fp64"], "traffic": None}
+def _roofline(name: str, sh: Shape, sec: float, launches: float):
+    """Algorithmic work of one launch of a kernel at this job's shape."""
+    n, d, r, k = sh.n, sh.d, sh.r, sh.k
+    if name == "gauss_sketch":
+        # S X: 2 r n d flop on the MFMA of the input's precision (BF16 for
+        # BF16 and FP8 input, FP32 for FP32 input)
+        key = "fp32" if sh.dtype == "f32" else "bf16"
+        return _rate("mfma", 2.0 * r * n * d / launches, sec, key)
+    if name == "gram":
+        # refinement Gram (X D)^T (X D): X read once (n d xbytes); the
+        # d (d + 1) n flop of its upper triangle take less time on the MFMA
+        return _rate("hbm", float(n) * d * sh.xbytes / launches, sec, "hbm")
     if name == "score":
-        # X M as six split-BF16 products: 12 n d k flop on the BF16 MFMA take
-        # less time at its peak than reading X once, so the pass is priced
-        # against HBM: X once (4 n d), M's three BF16 parts (6 d k) and the
-        # scores (4 n)
-        byts = (N * D * 4 + 6 * D * K + N * 4) / launches_per_step
-        a = byts / sec
-        return {"bound": "hbm", "achieved": a / 1e9, "peak": PEAK["hbm"] / 1e9,
-                "unit": "GB/s", "frac": a / PEAK["hbm"], "traffic": None}
+        # X once, M's parts (three BF16 parts of d x 64 for FP32 input, one
+        # FP32 copy otherwise), the scores
+        if sh.dtype == "csr":
+            b = sh.nnz * 8.0 + (n + 1) * 8.0 + d * k * 4.0 + n * 4.0
+        else:
+            mb = 6.0 * d * 64 if sh.dtype == "f32" else 4.0 * d * k
+            b = float(n) * d * sh.xbytes + mb + n * 4.0
+        return _rate("hbm", b / launches, sec, "hbm")
     if name == "countsketch":
-        # X once, the sketch written once, the sorted row list once, the
-        # per-workgroup column maxima (min(1024, R / 4) x D floats) once
-        byts = (N * D * 4 + R * D * 8 + N * 4 + min(1024, R // 4) * D * 4) \
-            / launches_per_step
-        a = byts / sec
-        return {"bound": "hbm", "achieved": a / 1e9, "peak": PEAK["hbm"] / 1e9,
-                "unit": "GB/s", "frac": a / PEAK["hbm"], "traffic": None}
-    if name == "colmax":
-        byts = N * D * 4 / launches_per_step
-        a = byts / sec
-        return {"bound": "hbm", "achieved": a / 1e9, "peak": PEAK["hbm"] / 1e9,
-                "unit": "GB/s", "frac": a / PEAK["hbm"], "traffic": None}
+        if sh.dtype == "csr":
+            # CSR once (values, column indices, row pointers), the sorted
+            # row list, the sketch written once
+            b = sh.nnz * 8.0 + (n + 1) * 8.0 + n * 4.0 + r * d * 8.0
+        else:
+            # X once, the sketch written once, the sorted row list, the
+            # per-workgroup column maxima (min(1024, r / 4) x d floats)
+            b = (float(n) * d * sh.xbytes + r * d * 8.0 + n * 4.0
+                 + min(1024, r // 4) * d * 4.0)
+        return _rate("hbm", b / launches, sec, "hbm")
+    if name == "cq2_gram":
+        # the upper triangle of A^T A over the r x d sketch: d (d + 1) / 2
+        # entries of r products each when the last column block is at most
+        # 16 wide (formed by the same launch), else the part inside full
+        # 128-column blocks (c = 128 floor(d / 128))
+        c = d if d % 128 <= 16 else 128 * (d // 128)
+        return _rate("mfma", float(r) * c * (c + 1), sec, "fp64")
+    if name == "cq2_solve":
+        # Q1 = A R1^{-1}: r d^2 flop
+        return _rate("mfma", float(r) * d * d, sec, "fp64")
+    if name in ("cq2_chol", "cq2_r"):
+        # d^3 / 3 flop
+        out = _rate("alu", d ** 3 / 3.0, sec, "fp64")
+        return out
     return None
+
+
+def roofline_for(name, sh, ms_per_launch, launches_per_step, workload):
+    rr = _roofline(name, sh, ms_per_launch * 1e-3, launches_per_step)
+    if rr is not None:
+        rr["traffic"] = measured_traffic(name, workload)
+    return rr
+
+
+# ---- host facts ------------------------------------------------------------------
+def host_facts() -> dict:
+    model, mem = "unknown", None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for ln in f:
+                if ln.startswith("MemTotal"):
+                    mem = int(ln.split()[1]) * 1024
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "usable_cpus": usable,
+            "host_ram_gib": None if mem is None else round(mem / 2 ** 30, 1)}
+
+
+def blas_threads() -> int:
+    try:
+        from threadpoolctl import threadpool_info
+        return max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
+# ---- one job, timed --------------------------------------------------------------
+def time_job(slso, ctx, x, n, seed, r, k, steps, warmup, sketch, refine=False,
+             nnz=0, label=""):
+    """Warm-up, a per-kernel breakdown pass, then ``steps`` timed steps with
+    HIP events around the dominant kernel's launches only."""
+    import numpy as np
+    import torch
+    scores = torch.empty(n, dtype=torch.float32, device="cuda")
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        _, info = ctx.leverage(x, seed, r, k, out=scores, stream=stream,
+                               sketch=sketch, refine=refine, nnz=nnz)
+        ctx.order(scores, out=perm, stream=stream)
+        return info
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    slso.profile_read()
+    slso.profile_only(None)
+    slso.profile_enable(True)
+    nb = max(2, min(3, steps))
+    for _ in range(nb):
+        step()
+    prof = slso.profile_read()
+    kernels = {kk: {"ms_per_step": v[0] / nb, "launches_per_step": v[1] / nb}
+               for kk, v in prof.items() if v[1] > 0}
+    dname = max(kernels, key=lambda kk: kernels[kk]["ms_per_step"])
+    slso.profile_only(dname)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        info = step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    dprof = slso.profile_read()
+    slso.profile_enable(False)
+    slso.profile_only(None)
+    got = scores.cpu().numpy()
+    perm_h = perm.cpu().numpy().astype(np.int64)
+    perm_ok = bool(np.array_equal(perm_h, np.argsort(-got, kind="stable")))
+    lat_ms = np.array(lat) * 1e3
+    dms, dcount = dprof[dname]
+    log(f"{label}: {1e3 * total / steps:.3f} ms/step, dominant {dname} "
+        f"{dms / max(dcount, 1):.3f} ms/launch")
+    return {"ms_per_step": 1e3 * total / steps, "rows_per_s": n * steps / total,
+            "p50_ms": float(np.percentile(lat_ms, 50)),
+            "p99_ms": float(np.percentile(lat_ms, 99)),
+            "kernels": kernels, "dominant": dname,
+            "dominant_ms_per_launch": dms / max(dcount, 1),
+            "dominant_launches_per_step": dcount / steps,
+            "rank": int(info["rank"]), "flags": int(info["flags"]),
+            "perm_matches_stable_sort": perm_ok, "scores": got}
+
+
+def rooflines(res, sh, workload, others=()):
+    dname = res["dominant"]
+    roof = roofline_for(dname, sh, res["dominant_ms_per_launch"],
+                        res["dominant_launches_per_step"], workload)
+    other = {}
+    for kk in others:
+        if kk in res["kernels"] and kk != dname:
+            kv = res["kernels"][kk]
+            rr = roofline_for(kk, sh, kv["ms_per_step"] / kv["launches_per_step"],
+                              kv["launches_per_step"], workload)
+            if rr:
+                other[kk] = dict(kernel=kk, **rr)
+    return (dict(kernel=dname, **roof) if roof else None), other
+
+
+def gpu_scores(slso, ctx, x, seed, r, k, sketch, refine=False, nnz=0):
+    import torch
+    sc, info = ctx.leverage(x, seed, r, k, sketch=sketch, refine=refine,
+                            nnz=nnz)
+    torch.cuda.synchronize()
+    return sc.cpu().numpy(), info
+
+
+# ---- workloads ---------------------------------------------------------------------
+PREC = dict(n=4_000_000, d=512, r=2048, k=64, seed=2003, data_seed=1003)
+IMAGE = dict(n=60000, d=784, r=16384, k=64, seed=2001, data_seed=1001)
+TEXT = dict(n=500000, d=4096, r=32768, k=64, seed=2002, data_seed=1002)
+
+
+def precision_bench(args, slso, ctx) -> dict:
+    """The precision form: BF16 (headline), FP8 and plain FP32 paths."""
+    import numpy as np
+    import torch
+
+    import synth
+    P = PREC
+    n, d, r, k, seed = P["n"], P["d"], P["r"], P["k"], P["seed"]
+    t0 = time.perf_counter()
+    x64 = synth.precision_dense_device(n, d, 256, P["data_seed"])
+    xb = x64.to(torch.bfloat16)
+    codes, cs = synth.to_fp8_e4m3_device(x64)
+    x8 = slso.Fp8Matrix(codes, cs)
+    xf = x64.to(torch.float32)
+    del x64
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log(f"precision inputs ready in {time.perf_counter() - t0:.1f} s")
+
+    bf = time_job(slso, ctx, xb, n, seed, r, k, args.steps, args.warmup,
+                  slso.GAUSSIAN, refine=True, label="precision bf16")
+    sh_b = Shape(n, d, r, k, 2, "bf16")
+    roof, roof_other = rooflines(bf, sh_b, "precision",
+                                 ("gauss_sketch", "gram", "score"))
+    side_steps = max(2, min(5, args.steps))
+    f8 = time_job(slso, ctx, x8, n, seed, r, k, side_steps, 1, slso.GAUSSIAN,
+                  refine=True, label="precision fp8")
+    f32 = time_job(slso, ctx, xf, n, seed, r, k, side_steps, 1, slso.GAUSSIAN,
+                   refine=False, label="precision f32 plain")
+    paths = {}
+    for name, res, sh in (("fp8", f8, Shape(n, d, r, k, 1, "fp8")),
+                          ("f32_plain", f32, Shape(n, d, r, k, 4, "f32"))):
+        rf, ro = rooflines(res, sh, "precision", ("gauss_sketch", "gram", "score"))
+        paths[name] = {"rows_per_s": res["rows_per_s"],
+                       "ms_per_step": res["ms_per_step"],
+                       "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"],
+                       "steps": side_steps, "rank": res["rank"],
+                       "kernels": res["kernels"], "roofline": rf,
+                       "roofline_other": ro,
+                       "perm_matches_stable_sort":
+                           res["perm_matches_stable_sort"]}
+    # property that holds at any size: with the refinement R is the R factor
+    # of X D, so X R^-1 has orthonormal columns and the scores sum to
+    # ||Pi_2||_F^2 (checked against the oracle's Pi_2 in the CPU leg)
+    out = {
+        "metric": METRIC, "value": bf["rows_per_s"], "unit": "rows/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": bf["ms_per_step"], "p50_ms": bf["p50_ms"],
+        "p99_ms": bf["p99_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "precision form: dense BF16 X (n=4e6, d=512, "
+                               "rank 256, sigma_j=j^-1.5, noise 1e-4, row "
+                               "scales e^N(0,1.5^2)); Gaussian sketch r=2048 "
+                               "on MFMA, Cholesky-QR refinement, FP64 QR/rank/"
+                               "R^-1, k=64, scores + dec ordering",
+                   "n": n, "d": d, "r": r, "k": k, "seed": seed,
+                   "refine": True, "rank": bf["rank"]},
+        "perm_matches_stable_sort": bf["perm_matches_stable_sort"],
+        "kernels": bf["kernels"], "roofline": roof,
+        "roofline_other": roof_other, "paths": paths,
+    }
+    if not args.no_cpu_baseline:
+        out.update(precision_check(args, slso, ctx, xb, x8, xf, bf, f8))
+    del xb, x8, xf, codes, cs
+    torch.cuda.empty_cache()
+    return out
+
+
+def precision_check(args, slso, ctx, xb, x8, xf, bf, f8) -> dict:
+    """The oracle leg: timed on a bounded sample job (the first rows of the
+    same X as a job of their own), which also gives the error figures; the
+    full-size scores are checked by the sum identity."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import leverage as olv
+    from oracle import metrics as omet
+    from oracle import order as oorder
+    from oracle import streams as ost
+    from threadpoolctl import threadpool_limits
+    P = PREC
+    d, r, k, seed = P["d"], P["r"], P["k"], P["seed"]
+    ns = args.sample_rows
+    res = {}
+    # BF16: oracle timed on the sample (all BLAS threads)
+    xb_s = xb[:ns].contiguous()
+    got_b, _ = gpu_scores(slso, ctx, xb_s, seed, r, k, slso.GAUSSIAN, True)
+    xv = synth.bf16_bits_to_f64(xb_s.view(torch.int16).cpu().numpy()
+                                .view(np.uint16))
+    threads = blas_threads()
+    tc = time.perf_counter()
+    ref = olv.sketched_leverage(xv, seed, r, k, refine=True)
+    oorder.dec_order(ref["scores"].astype(np.float32))
+    t_all = time.perf_counter() - tc
+    res["rel_err_vs_fp64"] = omet.max_rel_err(got_b, ref["scores"])
+    res["kendall_tau_vs_fp64"] = omet.kendall_tau(got_b, ref["scores"])
+    log(f"bf16 sample: err {res['rel_err_vs_fp64']:.3e} "
+        f"tau {res['kendall_tau_vs_fp64']:.6f}, oracle {t_all:.1f} s")
+    # one BLAS thread on a quarter of the sample
+    n1 = max(d + 1, ns // 4)
+    with threadpool_limits(limits=1):
+        tc = time.perf_counter()
+        r1 = olv.sketched_leverage(xv[:n1], seed, r, k, refine=True)
+        oorder.dec_order(r1["scores"].astype(np.float32))
+        t_one = time.perf_counter() - tc
+    facts = host_facts()
+    res["cpu_baseline"] = {
+        "value": ns / t_all, "unit": "rows/s", "cores": threads,
+        "kind": "oracle",
+        "sample": f"one job of the first {ns} rows of the BF16 input (same "
+                  "seed, r, k; refined): oracle sketched leverage (numpy "
+                  "FP64, Householder QR of X D) + dec ordering",
+        "one_thread": {"value": n1 / t_one, "unit": "rows/s", "cores": 1,
+                       "sample": f"the first {n1} rows as a job"},
+        **facts}
+    # FP8 on the same sample
+    x8_s = slso.Fp8Matrix(x8.codes[:ns].contiguous(), x8.col_scale)
+    got_8, _ = gpu_scores(slso, ctx, x8_s, seed, r, k, slso.GAUSSIAN, True)
+    xv8 = synth.fp8_e4m3_to_f64(x8_s.codes.cpu().numpy(),
+                                x8.col_scale.cpu().numpy())
+    ref8 = olv.sketched_leverage(xv8, seed, r, k, refine=True)
+    res["paths_err"] = {"fp8": {
+        "rel_err_vs_fp64": omet.max_rel_err(got_8, ref8["scores"]),
+        "kendall_tau_vs_fp64": omet.kendall_tau(got_8, ref8["scores"])}}
+    # plain FP32: the sketched (unrefined) oracle generates every entry of
+    # the Gaussian sketch, so its sample is smaller
+    nf = args.sample_rows_f32
+    xf_s = xf[:nf].contiguous()
+    got_f, _ = gpu_scores(slso, ctx, xf_s, seed, r, k, slso.GAUSSIAN, False)
+    reff = olv.sketched_leverage(xf_s.cpu().numpy().astype(np.float64), seed,
+                                 r, k, kind="gaussian", precision="f32")
+    res["paths_err"]["f32_plain"] = {
+        "rel_err_vs_fp64": omet.max_rel_err(got_f, reff["scores"]),
+        "kendall_tau_vs_fp64": omet.kendall_tau(got_f, reff["scores"]),
+        "sample_rows": nf}
+    # full size: sum of the refined scores = ||Pi_2||_F^2
+    pi_f2 = float((ost.pi2_matrix(seed, d, k) ** 2).sum())
+    res["full_size_check"] = {
+        "bf16_sum_over_pi2_frob2": float(bf["scores"].astype(np.float64).sum())
+        / pi_f2,
+        "fp8_sum_over_pi2_frob2": float(f8["scores"].astype(np.float64).sum())
+        / pi_f2}
+    res["err_sample"] = (f"a job of the first {ns} rows (BF16, FP8) and "
+                         f"{nf} rows (plain FP32) of the same inputs")
+    return res
+
+
+def text_bench(args, slso, ctx, steps=None, warmup=None) -> dict:
+    import numpy as np
+    import torch
+
+    import synth
+    T = TEXT
+    n, d, r, k, seed = T["n"], T["d"], T["r"], T["k"], T["seed"]
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    t0 = time.perf_counter()
+    c = synth.config2(n, d, T["data_seed"])
+    x = slso.CsrMatrix(n, d, torch.from_numpy(c.row_ptr).cuda(),
+                       torch.from_numpy(c.col_idx).cuda(),
+                       torch.from_numpy(c.val).cuda())
+    torch.cuda.synchronize()
+    log(f"text-like CSR ready in {time.perf_counter() - t0:.1f} s "
+        f"(nnz {c.nnz})")
+    res = time_job(slso, ctx, x, n, seed, r, k, steps, warmup,
+                   slso.COUNTSKETCH, label="text-like csr")
+    sh = Shape(n, d, r, k, 8, "csr", nnz=c.nnz)
+    roof, other = rooflines(res, sh, "text", ("cq2_gram", "cq2_solve",
+                                              "cq2_chol", "countsketch",
+                                              "score"))
+    out = {"rows_per_s": res["rows_per_s"], "ms_per_step": res["ms_per_step"],
+           "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"], "steps": steps,
+           "config": {"workload": "text-like CSR X (n=5e5, d=4096, 0.5% "
+                                  "dense, Zipf(1.1) columns, tf-idf values); "
+                                  "CountSketch on CSR r=32768, FP64 QR, k=64, "
+                                  "scores + dec ordering",
+                      "n": n, "d": d, "r": r, "k": k, "seed": seed,
+                      "nnz": c.nnz, "rank": res["rank"]},
+           "flags": res["flags"],
+           "perm_matches_stable_sort": res["perm_matches_stable_sort"],
+           "kernels": res["kernels"], "roofline": roof,
+           "roofline_other": other}
+    return out, res, c
+
+
+def image_bench(args, slso, ctx) -> dict:
+    import numpy as np
+    import torch
+
+    import synth
+    I = IMAGE
+    n, d, r, k, seed = I["n"], I["d"], I["r"], I["k"], I["seed"]
+    x_host = synth.config1(n, d)
+    x = torch.from_numpy(x_host).cuda()
+    kind = {"countsketch": slso.COUNTSKETCH, "osnap": slso.OSNAP,
+            "srht": slso.SRHT}[args.sketch]
+    nnz = args.nnz if args.sketch == "osnap" else 0
+    res = time_job(slso, ctx, x, n, seed, r, k, args.steps, args.warmup, kind,
+                   nnz=nnz, label="image-like")
+    sh = Shape(n, d, r, k, 4, "f32")
+    roof, other = rooflines(res, sh, "image",
+                            ("cq2_solve", "cq2_chol", "countsketch", "score"))
+    out = {
+        "metric": METRIC, "value": res["rows_per_s"], "unit": "rows/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"], "p50_ms": res["p50_ms"],
+        "p99_ms": res["p99_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "image-like dense FP32 X (n=60000, d=784, "
+                               "values in [0,1], rank 50 + noise, 10 clusters); "
+                               + {"countsketch": "CountSketch ",
+                                  "osnap": f"OSNAP (s={nnz}) ",
+                                  "srht": "SRHT "}[args.sketch]
+                               + "r=16384, FP64 QR, k=64, scores + dec ordering",
+                   "n": n, "d": d, "r": r, "k": k, "seed": seed,
+                   "rank": res["rank"]},
+        "perm_matches_stable_sort": res["perm_matches_stable_sort"],
+        "kernels": res["kernels"], "roofline": roof, "roofline_other": other,
+    }
+    if not args.no_cpu_baseline:
+        import numpy as np
+        from oracle import leverage as olv
+        from oracle import metrics as omet
+        from oracle import order as oorder
+        got = res["scores"].astype(np.float64)
+        reps, t_cpu, ref = 0, 0.0, None
+        while reps < 40 and t_cpu < 10.0:
+            tc = time.perf_counter()
+            ref = olv.sketched_leverage(x_host, seed, r, k, kind=args.sketch,
+                                        nnz=max(nnz, 1))
+            oorder.dec_order(ref["scores"].astype(np.float32))
+            t_cpu += time.perf_counter() - tc
+            reps += 1
+        out["cpu_baseline"] = {
+            "value": n * reps / t_cpu, "unit": "rows/s",
+            "cores": blas_threads(), "kind": "oracle",
+            "sample": f"{reps} full job(s) of the same workload (n={n}): "
+                      "oracle sketched leverage (numpy FP64) + dec ordering",
+            **host_facts()}
+        out["rel_err_vs_fp64"] = omet.max_rel_err(got, ref["scores"])
+        out["kendall_tau_vs_fp64"] = omet.kendall_tau(got, ref["scores"])
+    return out
+
+
+def serving_run(args, slso) -> dict:
+    """Continuous serving: jobs arrive as a Poisson stream and are admitted
+    by the library's server (slots under an HBM budget); aggregate rows/s and
+    p50/p99 latency from arrival to resident outputs, per arrival rate."""
+    import numpy as np
+    import torch
+
+    import synth
+
+    rates = [float(v) for v in args.rates.split(",") if v]
+    t_gen = time.perf_counter()
+    pool = synth.serving_pool(n=args.pool_n)
+    torch.cuda.synchronize()
+    log(f"serving pool of {len(pool)} base matrices ready in "
+        f"{time.perf_counter() - t_gen:.1f} s")
+    per_rate = {}
+    checked = None
+    for rate in rates:
+        jobs = synth.serving_jobs(args.jobs, rate, pool_n=args.pool_n)
+        srv = slso.Server(0, slots=args.slots, hbm_budget=96 << 30)
+        tickets = []
+        t0 = time.perf_counter()
+        for jb in jobs:
+            delay = t0 + jb["arrival_s"] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            x = pool[(jb["d"], jb["dtype"])][jb["row0"]:jb["row0"] + jb["n"]]
+            tickets.append(srv.submit(x, jb["seed"], jb["r"], jb["k"]))
+        res = [srv.wait(t) for t in tickets]
+        stats = srv.stats()
+        srv.close()
+        bad = [q for q in res if q["status"] < 0]
+        lat = np.array([q["latency_ms"] for q in res])
+        span_ms = max(q["end_ms"] for q in res) - min(q["submit_ms"] for q in res)
+        rows = sum(jb["n"] for jb in jobs)
+        per_rate[str(int(rate))] = {
+            "rows_per_s": rows / (span_ms * 1e-3), "jobs": len(jobs),
+            "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)),
+            "max_running": stats["max_running"], "failed": len(bad)}
+        log(f"serving rate {rate:g}/s: {per_rate[str(int(rate))]}")
+        if checked is None and not args.no_cpu_baseline:
+            # accuracy of a stratified sample of jobs (one per d, the
+            # smallest n of each) against the FP64 oracle
+            from oracle import leverage as olv
+            from oracle import metrics as omet
+            errs, taus, picked = [], [], []
+            for dv in sorted({jb["d"] for jb in jobs}):
+                cand = [i for i in range(len(jobs)) if jobs[i]["d"] == dv]
+                picked.append(min(cand, key=lambda i: jobs[i]["n"]))
+            for i in picked:
+                jb, t = jobs[i], tickets[i]
+                xv = t.x.double().cpu().numpy()
+                ref = olv.sketched_leverage(xv, jb["seed"], jb["r"], jb["k"])
+                got = t.scores.cpu().numpy()
+                errs.append(omet.max_rel_err(got, ref["scores"]))
+                taus.append(omet.kendall_tau(got, ref["scores"]))
+            checked = (max(errs), min(taus), len(picked))
+        del tickets, res
+    out = {"per_rate": per_rate, "jobs_per_rate": args.jobs,
+           "slots": args.slots, "pool_rows": args.pool_n,
+           "config": {"workload": "serving: Poisson stream of leverage jobs, "
+                                  "n log-uniform [1e4, 2e6], d in {64..1024}, "
+                                  "FP32/BF16, CountSketch r=4d..8d, k=32, "
+                                  "scores + dec ordering"}}
+    if checked is not None:
+        out["rel_err_vs_fp64"], out["kendall_tau_vs_fp64"] = checked[:2]
+        out["jobs_checked"] = checked[2]
+    del pool
+    torch.cuda.empty_cache()
+    return out
 
 
 def copy_calibration(mib: int) -> int:
@@ -198,86 +615,6 @@ def copy_calibration(mib: int) -> int:
     return 0
 
 
-def serving_bench(args) -> int:
-    """Continuous serving: jobs arrive as a Poisson stream and are admitted
-    by the library's server (slots under an HBM budget); reports aggregate
-    rows/s and p50/p99 latency from arrival to resident outputs per rate."""
-    import numpy as np
-    import torch
-
-    import synth
-    import paper_1812_07903_amd as slso
-
-    rates = [float(v) for v in args.rates.split(",") if v]
-    t_gen = time.perf_counter()
-    pool = synth.serving_pool(n=args.pool_n)
-    torch.cuda.synchronize()
-    print(f"[serving] pool of {len(pool)} base matrices ready in "
-          f"{time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
-    per_rate = {}
-    checked = None
-    for rate in rates:
-        jobs = synth.serving_jobs(args.jobs, rate, pool_n=args.pool_n)
-        srv = slso.Server(0, slots=args.slots, hbm_budget=96 << 30)
-        tickets = []
-        t0 = time.perf_counter()
-        for jb in jobs:
-            delay = t0 + jb["arrival_s"] - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            x = pool[(jb["d"], jb["dtype"])][jb["row0"]:jb["row0"] + jb["n"]]
-            tickets.append(srv.submit(x, jb["seed"], jb["r"], jb["k"]))
-        res = [srv.wait(t) for t in tickets]
-        stats = srv.stats()
-        srv.close()
-        bad = [r for r in res if r["status"] < 0]
-        lat = np.array([r["latency_ms"] for r in res])
-        span_ms = max(r["end_ms"] for r in res) - min(r["submit_ms"] for r in res)
-        rows = sum(jb["n"] for jb in jobs)
-        per_rate[str(int(rate))] = {
-            "rows_per_s": rows / (span_ms * 1e-3), "jobs": len(jobs),
-            "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)),
-            "max_running": stats["max_running"], "failed": len(bad)}
-        print(f"[serving] rate {rate:g}/s: {per_rate[str(int(rate))]}",
-              file=sys.stderr, flush=True)
-        if checked is None and not args.no_cpu_baseline:
-            # accuracy of the three smallest jobs against the FP64 oracle
-            from oracle import leverage as olv
-            from oracle import metrics as omet
-            errs, taus = [], []
-            for i in sorted(range(len(jobs)), key=lambda i: jobs[i]["n"])[:3]:
-                jb, t = jobs[i], tickets[i]
-                xv = t.x.double().cpu().numpy()
-                ref = olv.sketched_leverage(xv, jb["seed"], jb["r"], jb["k"])
-                got = t.scores.cpu().numpy()
-                errs.append(omet.max_rel_err(got, ref["scores"]))
-                taus.append(omet.kendall_tau(got, ref["scores"]))
-            checked = (max(errs), min(taus))
-        del tickets, res
-    top = per_rate[str(int(rates[-1]))]
-    out = {
-        "metric": "rows/sec leverage-scored at stated rel err vs FP64; "
-                  "p50/p99 job latency",
-        "value": top["rows_per_s"], "unit": "rows/s", "n_gpus": 1,
-        "steps": args.jobs, "warmup": 0,
-        "ms_per_step": None,
-        "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64+f32+bf16", "data": "synthetic",
-        "config": {"workload": "serving: Poisson stream of leverage jobs, n "
-                               "log-uniform [1e4, 2e6], d in {64..1024}, "
-                               "FP32/BF16, CountSketch r=4d..8d, k=32, "
-                               "scores + dec ordering",
-                   "jobs_per_rate": args.jobs, "slots": args.slots,
-                   "pool_rows": args.pool_n},
-        "per_rate": per_rate,
-    }
-    if checked is not None:
-        out["rel_err_vs_fp64"], out["kendall_tau_vs_fp64"] = checked
-    print(json.dumps(out), flush=True)
-    return 0
-
 
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -285,14 +622,17 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("image", "serving"),
-                    default="image",
-                    help="image: the image-like single-job workload (default); "
-                         "serving: a Poisson stream of mixed jobs")
+    ap.add_argument("--workload",
+                    choices=("precision", "image", "text", "serving"),
+                    default="precision")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="precision: skip the text-like and serving keys")
+    ap.add_argument("--sample-rows", type=int, default=262147,
+                    help="precision: rows of the oracle's sample job")
+    ap.add_argument("--sample-rows-f32", type=int, default=16411,
+                    help="precision: rows of the plain FP32 path's sample job")
     ap.add_argument("--sketch", choices=("countsketch", "osnap", "srht"),
-                    default="countsketch",
-                    help="image: the sketch (OSNAP: --nnz nonzeros per column "
-                         "of S)")
+                    default="countsketch", help="image: the sketch")
     ap.add_argument("--nnz", type=int, default=2,
                     help="image, --sketch osnap: nonzeros per column of S")
     ap.add_argument("--rates", default="50,200,800",
@@ -310,12 +650,6 @@ def main() -> int:
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
-    if args.workload == "serving":
-        if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-            print("bench.py measures one GPU only; run with --gpus 1",
-                  file=sys.stderr)
-            return 2
-        return serving_bench(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the leverage path runs on a "
@@ -323,138 +657,44 @@ def main() -> int:
               "of the sketch); run with --gpus 1", file=sys.stderr)
         return 2
 
-    import numpy as np
-    import torch
-
-    import synth
     import paper_1812_07903_amd as slso
+    slso.load_library()
 
-    x_host = synth.config1(N, D)
-    x = torch.from_numpy(x_host).cuda()
+    if args.workload == "serving":
+        srv = serving_run(args, slso)
+        top = srv["per_rate"][args.rates.split(",")[-1].split(".")[0]]
+        out = {"metric": METRIC, "value": top["rows_per_s"], "unit": "rows/s",
+               "n_gpus": 1, "steps": args.jobs, "warmup": 0,
+               "ms_per_step": None, "p50_ms": top["p50_ms"],
+               "p99_ms": top["p99_ms"], "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None,
+               "dtype": "f64+f32+bf16", "data": "synthetic", **srv}
+        print(json.dumps(out), flush=True)
+        return 0
+
     ctx = slso.Context(0)
-    scores = torch.empty(N, dtype=torch.float32, device="cuda")
-    perm = torch.empty(N, dtype=torch.int32, device="cuda")
-    stream = torch.cuda.current_stream()
-
-    osnap = args.sketch == "osnap"
-    kind = {"countsketch": slso.COUNTSKETCH, "osnap": slso.OSNAP,
-            "srht": slso.SRHT}[args.sketch]
-    nnz = args.nnz if osnap else 0
-
-    def step():
-        _, info = ctx.leverage(x, SEED, R, K, out=scores, stream=stream,
-                               sketch=kind, nnz=nnz)
-        ctx.order(scores, out=perm, stream=stream)
-        return info
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    # per-kernel breakdown: a short pass with every launch bracketed by events
-    # (outside the timed region, since the events themselves cost time)
-    slso.profile_read()
-    slso.profile_only(None)
-    slso.profile_enable(True)
-    nb = max(2, min(5, args.steps))
-    for _ in range(nb):
-        step()
-    prof = slso.profile_read()
-    kernels = {k: {"ms_per_step": v[0] / nb, "launches_per_step": v[1] / nb}
-               for k, v in prof.items() if v[1] > 0}
-    dname = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-    # timed region: events around the dominant kernel's launches only
-    slso.profile_only(dname)
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        info = step()
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - ts)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    dprof = slso.profile_read()
-    slso.profile_enable(False)
-    slso.profile_only(None)
-
-    ms_step = 1e3 * total / args.steps
-    rows_per_s = N * args.steps / total
-    lat_ms = np.array(lat) * 1e3
-
-    dms, dcount = dprof[dname]
-    roof = roofline_for(dname, dms / max(dcount, 1), dcount / args.steps)
-
-    got = scores.cpu().numpy().astype(np.float64)
-    perm_h = perm.cpu().numpy().astype(np.int64)
-    perm_ok = bool(np.array_equal(perm_h, np.argsort(-got.astype(np.float32),
-                                                      kind="stable")))
-
-    out = {
-        "metric": "rows/sec leverage-scored at stated rel err vs FP64; "
-                  "p50/p99 job latency",
-        "value": rows_per_s,
-        "unit": "rows/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "p50_ms": float(np.percentile(lat_ms, 50)),
-        "p99_ms": float(np.percentile(lat_ms, 99)),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64+f32",
-        "data": "synthetic",
-        "config": {"workload": "image-like dense FP32 X (n=60000, d=784, "
-                               "values in [0,1], rank 50 + noise, 10 clusters); "
-                               + {"countsketch": "CountSketch ",
-                                  "osnap": f"OSNAP (s={nnz}) ",
-                                  "srht": "SRHT "}[args.sketch]
-                               + "r=16384, FP64 QR, k=64, scores + dec ordering",
-                   "n": N, "d": D, "r": R, "k": K, "seed": SEED,
-                   "rank": int(info["rank"])},
-        "perm_matches_stable_sort": perm_ok,
-        "kernels": kernels,
-        "roofline": dict(kernel=dname, **roof) if roof else None,
-        "roofline_other": {
-            k: dict(kernel=k, **rr)
-            for k in ("cq2_solve", "cq2_chol", "countsketch", "score", "colmax",
-                      "cq_update", "cq_z")
-            if k in kernels and k != dname
-            for rr in [roofline_for(
-                k, kernels[k]["ms_per_step"] / kernels[k]["launches_per_step"],
-                kernels[k]["launches_per_step"])] if rr},
-    }
-
-    if not args.no_cpu_baseline:
-        # the oracle, untouched, on whole jobs of the same workload until
-        # about 10 s of CPU work has been timed (a bounded sample)
-        from oracle import leverage as olv
-        from oracle import metrics as omet
-        from oracle import order as oorder
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-        except Exception:
-            cores = os.cpu_count() or 1
-        reps, t_cpu, ref = 0, 0.0, None
-        while reps < 40 and t_cpu < 10.0:
-            tc = time.perf_counter()
-            ref = olv.sketched_leverage(x_host, SEED, R, K, kind=args.sketch,
-                                        nnz=max(nnz, 1))
-            oorder.dec_order(ref["scores"].astype(np.float32))
-            t_cpu += time.perf_counter() - tc
-            reps += 1
-        out["cpu_baseline"] = {
-            "value": N * reps / t_cpu, "unit": "rows/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": f"{reps} full job(s) of the same workload (n={N}): "
-                      "oracle sketched leverage (numpy FP64) + dec ordering"}
-        out["rel_err_vs_fp64"] = omet.max_rel_err(got, ref["scores"])
-        out["kendall_tau_vs_fp64"] = omet.kendall_tau(got, ref["scores"])
+    if args.workload == "image":
+        out = image_bench(args, slso, ctx)
+    elif args.workload == "text":
+        txt, res, _ = text_bench(args, slso, ctx)
+        out = {"metric": METRIC, "value": txt["rows_per_s"], "unit": "rows/s",
+               "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": txt["ms_per_step"], "p50_ms": txt["p50_ms"],
+               "p99_ms": txt["p99_ms"], "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+               "data": "synthetic", **txt}
+    else:
+        out = precision_bench(args, slso, ctx)
+        if not args.headline_only:
+            txt, _, _ = text_bench(args, slso, ctx, steps=max(3, args.steps // 4),
+                                   warmup=1)
+            out["text_like"] = txt
+            ctx.close()
+            ctx = None
+            out["serving"] = serving_run(args, slso)
+    if ctx is not None:
+        ctx.close()
     print(json.dumps(out), flush=True)
-    ctx.close()
     return 0
 
 

@@ -40,6 +40,7 @@ __all__ = [
     "text_like_csr", "config2", "precision_dense", "to_bf16_bits",
     "bf16_bits_to_f64", "to_fp8_e4m3", "fp8_e4m3_to_f64", "Csr",
     "lowrank_dense_device", "serving_pool", "serving_jobs",
+    "precision_dense_device", "to_fp8_e4m3_device",
 ]
 
 
@@ -291,3 +292,29 @@ def serving_jobs(n_jobs: int = 1024, rate: float = 200.0, seed: int = 1005,
                      "row0": row0, "r": r, "k": 32,
                      "seed": 3_000_000 + j})
     return jobs
+
+
+def precision_dense_device(n: int = 4_000_000, d: int = 512, rank: int = 256,
+                           seed: int = 1003, device="cuda"):
+    """``precision_dense`` drawn on a torch device (FP64 tensor): the same
+    recipe (sigma_j = j^-1.5, noise 1e-4, rho = e^N(0, 1.5^2)) from a seeded
+    torch generator, for the full-size precision workload (4e6 x 512 FP64 is
+    16 GB, slow to draw and to move from the host)."""
+    sigma = np.arange(1, rank + 1, dtype=np.float64) ** -1.5
+    return lowrank_dense_device(n, d, rank, sigma, 1e-4, 1.5, seed, device)
+
+
+def to_fp8_e4m3_device(x):
+    """``to_fp8_e4m3`` of a torch tensor on its own device: per-column FP32
+    scales max |x_j| / 448 (1 for a zero column) and e4m3fn codes of x / scale
+    rounded to nearest even (torch's float8_e4m3fn conversion, which the
+    host quantiser matches). Returns (codes uint8, col_scale float32)."""
+    import torch
+    cm = x.abs().amax(dim=0).to(torch.float64)
+    cs = torch.where(cm > 0, cm / 448.0, torch.ones_like(cm)).to(torch.float32)
+    codes = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+    step = max(1, (1 << 26) // max(1, x.shape[1]))
+    for a in range(0, x.shape[0], step):
+        v = x[a:a + step].to(torch.float64) / cs.to(torch.float64)[None, :]
+        codes[a:a + step] = v.to(torch.float8_e4m3fn).view(torch.uint8)
+    return codes, cs
