@@ -168,11 +168,12 @@ const char* slso_last_error(const slso_ctx* ctx);
  *          column equilibration).
  * CountSketch: sx[h(i)] += s(i) x_i, summed in FP64 in ascending i within
  * each bucket (deterministic). Gaussian: S = G/sqrt(r) with G[j][i] the
- * FP32 generator value of slso_gaussian_sketch_entries (rounded to BF16 for
- * BF16 and FP8 input); products on MFMA, sums in FP32 within chunks of at
- * most 65536 rows and in FP64 across chunks, in a fixed order
- * (deterministic); the 1/sqrt(r) (and for FP8 the column scale) is applied
- * once to the FP64 sum. OSNAP (same inputs as CountSketch): for every hash
+ * FP32 generator value of slso_gaussian_sketch_entries for F32 input, the
+ * quantile-form value of slso_gaussian_sketch_entries_q (BF16 or e4m3
+ * table) for BF16 and FP8 input; products on MFMA, sums in FP32 within
+ * slices of rows (at most 65536 rows for F32 input, 2^18 for BF16 and FP8)
+ * and in FP64 across slices, in a fixed order (deterministic); the
+ * 1/sqrt(r) (and for FP8 the column scale) is applied once to the FP64 sum. OSNAP (same inputs as CountSketch): for every hash
  * j < s, sx[h_j(i)] += s_j(i) x_i in ascending i (each sketch row belongs to
  * one hash's block), then every sum is multiplied once by 1/sqrt(s) in FP64.
  * SRHT (dense input): D_ii = +1 if the polynomial hash of stream 7 is even
@@ -355,6 +356,23 @@ int slso_gaussian(uint64_t seed, int32_t stream_id, int64_t rows, int64_t cols,
  * EINVAL for negative sizes. */
 int slso_gaussian_sketch_entries(uint64_t seed, int64_t r, int64_t row0,
                                  int64_t n, float* out, void* stream);
+
+/* Quantile-form Gaussian sketch entries G[j][row0 + i] of the BF16
+ * (dtype SLSO_BF16) or FP8 (dtype SLSO_FP8_E4M3) input path, j in [0, r),
+ * i in [0, n): out (device) r x n floats, row-major (each value a BF16 or
+ * e4m3 number). Definition (Sec. 2.1 asks for i.i.d. N(0,1) entries; these
+ * are N(0,1) quantiles on 2^16 equiprobable signed cells, rounded to the
+ * input's format): with (w0, w1, w2, w3) = Philox4x32-10(counter (lo32(q),
+ * hi32(q), j, 9), key (lo32(seed), hi32(seed))), q = floor(c / 8) for
+ * column c = row0 + i, v = the 16-bit half (c & 1 ? high : low) of word
+ * w[(c >> 1) & 3]; the value is (-1)^(v >> 15) T[v & 0x7FFF] with
+ * T[m] = sqrt(2) erfinv((2 m + 1) / 65536) rounded to nearest even in BF16
+ * (SLSO_BF16) or e4m3 (SLSO_FP8_E4M3). The tables are computed once per
+ * device. EINVAL for negative sizes or another dtype; EDEVICE when the
+ * tables cannot be copied to the current device. */
+int slso_gaussian_sketch_entries_q(uint64_t seed, int32_t dtype, int64_t r,
+                                   int64_t row0, int64_t n, float* out,
+                                   void* stream);
 
 /* R factor of a QR factorisation (Algorithm 2 step 2, QR form) of the m x d
  * matrix a (device, row-major, lda = d, m >= d), which is overwritten.

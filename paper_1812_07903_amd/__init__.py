@@ -36,7 +36,8 @@ EXPORTED = (
     "slso_sketch", "slso_sketch_svd", "slso_leverage", "slso_order",
     "slso_order_sample",
     "slso_hash",
-    "slso_gaussian", "slso_gaussian_sketch_entries", "slso_qr_r", "slso_qr_r_path",
+    "slso_gaussian", "slso_gaussian_sketch_entries",
+    "slso_gaussian_sketch_entries_q", "slso_qr_r", "slso_qr_r_path",
     "slso_solve_upper", "slso_scores", "slso_workspace_size",
     "slso_server_create", "slso_server_submit", "slso_server_poll",
     "slso_server_wait", "slso_server_stats", "slso_server_destroy",
@@ -133,6 +134,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "slso_gaussian": ([u64, i32, i64, i64, vp, vp], ctypes.c_int),
         "slso_gaussian_sketch_entries": ([u64, i64, i64, i64, vp, vp],
                                          ctypes.c_int),
+        "slso_gaussian_sketch_entries_q": ([u64, i32, i64, i64, i64, vp, vp],
+                                           ctypes.c_int),
         "slso_qr_r": ([vp, vp, i64, i64, vp, vp], ctypes.c_int),
         "slso_qr_r_path": ([vp, vp, i64, i64, vp, ctypes.c_int, vp, vp],
                            ctypes.c_int),
@@ -633,4 +636,16 @@ def gaussian_sketch_entries(seed: int, r: int, n: int, row0: int = 0,
     _check(load_library().slso_gaussian_sketch_entries(seed, r, row0, n,
                                                        _ptr(out),
                                                        _stream(stream)))
+    return out
+
+
+def gaussian_sketch_entries_q(seed: int, dtype: int, r: int, n: int,
+                              row0: int = 0, device="cuda", stream=None):
+    """Quantile-form Gaussian sketch entries G[j][row0 + i] of the BF16
+    (``dtype=BF16``) or FP8 (``dtype=FP8_E4M3``) input path, as an r x n
+    float32 tensor."""
+    import torch
+    out = torch.empty((r, n), dtype=torch.float32, device=device)
+    _check(load_library().slso_gaussian_sketch_entries_q(
+        seed, dtype, r, row0, n, _ptr(out), _stream(stream)))
     return out

@@ -26,7 +26,8 @@ enum StreamId : uint32_t {
   kStreamSwr = 5,
   kStreamSwor = 6,
   kStreamSrhtSign = 7,
-  kStreamSrhtRows = 8
+  kStreamSrhtRows = 8,
+  kStreamGaussQ = 9
 };
 
 struct HashCoeffs {
@@ -97,15 +98,15 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t p0lo = c.x * 0xD2511F53u;
-    const uint32_t p0hi = __umulhi(c.x, 0xD2511F53u);
-    const uint32_t p1lo = c.z * 0xCD9E8D57u;
-    const uint32_t p1hi = __umulhi(c.z, 0xCD9E8D57u);
+    // one 32 x 32 -> 64-bit product per multiplier (v_mad_u64_u32): faster
+    // here than separate low and high halves
+    const uint64_t p0 = static_cast<uint64_t>(c.x) * 0xD2511F53u;
+    const uint64_t p1 = static_cast<uint64_t>(c.z) * 0xCD9E8D57u;
     U4 n;
-    n.x = p1hi ^ c.y ^ k0;
-    n.y = p1lo;
-    n.z = p0hi ^ c.w ^ k1;
-    n.w = p0lo;
+    n.x = static_cast<uint32_t>(p1 >> 32) ^ c.y ^ k0;
+    n.y = static_cast<uint32_t>(p1);
+    n.z = static_cast<uint32_t>(p0 >> 32) ^ c.w ^ k1;
+    n.w = static_cast<uint32_t>(p0);
     c = n;
   }
   return c;

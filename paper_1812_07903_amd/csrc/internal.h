@@ -248,14 +248,51 @@ void launch_eye(double* out, int64_t d, hipStream_t s);
 void launch_scale_rows(const double* m, const double* scale_row, int64_t d,
                        int64_t k, double* out64, float* out32, hipStream_t s);
 
+// ---- Gaussian sketch, quantile form (k_gauss_q.hip) ----------------------------
+// Copy the quantile tables (BF16 and e4m3 magnitudes) to the current device;
+// 0 on success. Idempotent per device.
+int init_quantile_tables(int device);
+bool gauss_q_dtype(int dtype);
+size_t gauss_q_partial_bytes(int64_t n, int64_t r, int64_t d);
+// partial[s][j][c] = FP32 sums of G[j][i] x[i][c] over slice s of the rows
+// (BF16 input: dtype 2; FP8 codes: dtype 3, without their column scales);
+// *splits = the number of slices. With colmax (zero-filled by the caller),
+// the column max-abs values (times |col_scale| for FP8) are folded into it
+// as FP64 bit patterns and *nonfinite is set on Inf / NaN.
+void launch_gauss_q_sketch(const void* x, int dtype, int64_t n, int64_t d,
+                           int64_t ld, uint64_t seed, int64_t r,
+                           float* partial, int64_t* splits,
+                           const float* col_scale, uint64_t* colmax,
+                           int* nonfinite, hipStream_t s);
+// partial[s][i][j] = FP32 sums of x[.][i] x[.][j] over slice s of the rows,
+// for i, j in 256-column blocks A <= B (BF16 / FP8 input, as above)
+size_t gram_q_partial_bytes(int64_t n, int64_t d);
+void launch_gram_q(const void* x, int dtype, int64_t n, int64_t d, int64_t ld,
+                   float* partial, int64_t* splits, hipStream_t s);
+// out[j * n + i] = quantile-form entry G[j][row0 + i] (fmt 0: BF16, 1: e4m3)
+void launch_gauss_q_entries(uint64_t seed, int64_t r, int64_t n, int64_t row0,
+                            int fmt, float* out, hipStream_t s);
+
 // ---- Gaussian sketch and Gram matrix (k_gauss.hip) -------------------------
 // dtype: slso_dtype of a dense X (F32, BF16 or FP8-e4m3 with col_scale)
-size_t gauss_partial_bytes(int64_t n, int64_t r, int64_t d);
-// sx = G X / sqrt(r) (times col_scale for FP8 and dscale when given)
+size_t gauss_partial_bytes(int64_t n, int64_t r, int64_t d, int dtype);
+// sx = G X / sqrt(r) (times col_scale for FP8 and dscale when given); BF16
+// and FP8 input take the quantile form of the entries (k_gauss_q.hip), F32
+// input the FP32 Box-Muller generator
 void launch_gauss_sketch(const void* x, int dtype, int64_t n, int64_t d,
                          int64_t ld, const float* col_scale, uint64_t seed,
                          int64_t r, const double* dscale, float* partial,
                          double* sx, hipStream_t s);
+// BF16 / FP8 input: the sketch and the column equilibration in one pass over
+// X. colmax_bits (d u64) is zero-filled here, dscale_out = D from the column
+// max-abs values (times |col_scale| for FP8, as launch_colmax +
+// launch_colscale give), sx = G X D / sqrt(r) (times col_scale for FP8);
+// *nonfinite is set on Inf / NaN.
+void launch_gauss_sketch_eq(const void* x, int dtype, int64_t n, int64_t d,
+                            int64_t ld, const float* col_scale, uint64_t seed,
+                            int64_t r, uint64_t* colmax_bits, int* nonfinite,
+                            double* dscale_out, float* partial, double* sx,
+                            hipStream_t s);
 size_t gram_partial_bytes(int64_t n, int64_t d, int dtype);
 // g (d x d) = Dc X^T X Dc with Dc = diag(col_scale (FP8) * dscale); FP32
 // input on the FP64 MFMA (exact products, FP64 sums), BF16/FP8 on the BF16
@@ -279,6 +316,18 @@ void cholesky(double* g, int64_t d, double* r, int* flag, hipStream_t s);
 // c = a b for upper-triangular a, b (d x d)
 void launch_trmm_upper(const double* a, const double* b, int64_t d, double* c,
                        hipStream_t s);
+
+// ---- scoring, BF16 / FP8 input with M resident in LDS (k_score_q.hip) ---------
+// applies to dense BF16 (dtype 2) / FP8 (3) input with d % 16 == 0,
+// d <= 512, k <= 64, rows on 16-byte (BF16) or 8-byte (FP8) boundaries
+bool score_q_ok(const void* x, int dtype, int format, int64_t d, int64_t ld,
+                int64_t k);
+size_t score_q_scratch_bytes(int64_t d);
+// scores[i] = ||x_i M||^2 with M = m64 (d x k FP64, row-major; FP8: the
+// column scales already folded into its rows); scratch: score_q_scratch_bytes
+void launch_score_q(const void* x, int dtype, int64_t n, int64_t d, int64_t ld,
+                    const double* m64, int64_t k, void* scratch, float* scores,
+                    hipStream_t s);
 
 // ---- scoring (k_score.hip) ---------------------------------------------------
 void launch_scores(const void* x, int dtype, int format, int64_t n, int64_t d,

@@ -1,31 +1,28 @@
-// Gaussian sketch S X (Sec. 2.1; Algorithm 2 step 1) and the Gram matrix X^T X
-// of the refinement pass, as MFMA GEMMs.
+// Gaussian sketch S X of FP32 input (Sec. 2.1; Algorithm 2 step 1, the plain
+// FP32 path) and the Gram matrix X^T X of the refinement pass; the BF16 and
+// FP8 paths of both live in k_gauss_q.hip, whose partial sums the reduction
+// kernels here also finish.
 //
 // Entries of S = G / sqrt(r): G[j][i] is produced on the fly from the seed
 // (one Philox4x32-10 block per four consecutive data rows i of one sketch
 // row j, FP32 Box-Muller with polynomial logarithm, Newton square root and
 // Taylor sine/cosine, every operation separately rounded so the value is
-// reproducible exactly). Reduced-precision inputs (BF16, FP8-e4m3 decoded to
-// BF16 exactly) use BF16 MFMA (v_mfma_f32_32x32x16_bf16) with G rounded to
-// BF16; the plain FP32 path uses v_mfma_f32_32x32x2_f32 with FP32 G.
-// Products of BF16 values are exact in FP32; sums are FP32 within one
-// workgroup's slice of rows (split-K) and FP64 across slices, in a fixed
-// order, so the result is deterministic.
+// reproducible exactly), multiplied on v_mfma_f32_32x32x2_f32. Sums are FP32
+// within one workgroup's slice of rows (split-K) and FP64 across slices, in a
+// fixed order, so the result is deterministic.
 //
 // Tiling: a workgroup of eight waves owns 256 sketch rows x 256 columns;
 // wave w owns rows 32 w .. 32 w + 31 (8 accumulator tiles of 32 x 32). Per
-// step of 16 data rows, the X tile (16 x 256) is staged in LDS, transposed so
-// that the 8 consecutive rows of one MFMA operand are one 16-byte read; each
-// lane generates its own 8 entries of G (two Philox blocks). The MFMA
-// K-slots are permuted (slot 2s + h <-> data row 8h + s for the FP32 variant)
-// so that each lane's 8 entries of G are 8 consecutive data rows.
+// step of 16 data rows, the X tile (16 x 256) is staged in LDS and each lane
+// generates its own 8 entries of G (two Philox blocks). The MFMA K-slots are
+// permuted (slot 2s + h <-> data row 8h + s) so that each lane's 8 entries of
+// G are 8 consecutive data rows.
 #include "internal.h"
 
 namespace slso {
 namespace {
 
 typedef float f16v __attribute__((ext_vector_type(16)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // ---- the FP32 Gaussian generator -------------------------------------------
 #pragma clang fp contract(off)
@@ -118,49 +115,16 @@ __device__ __forceinline__ void gauss4(uint64_t seed, uint64_t g, uint32_t j,
 }
 #pragma clang fp contract(on)
 
-__device__ __forceinline__ __bf16 f32_to_bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-  return __builtin_bit_cast(__bf16, static_cast<uint16_t>(u));
-}
-
-// input element types: 0 F32, 1 BF16, 2 FP8-e4m3 (decoded to BF16 exactly)
-template <int IT>
-struct In;
-template <>
-struct In<0> {
-  using T = float;
-};
-template <>
-struct In<1> {
-  using T = uint16_t;
-};
-template <>
-struct In<2> {
-  using T = uint8_t;
-};
-
-__device__ __forceinline__ __bf16 to_bf16(uint16_t b) {
-  return __builtin_bit_cast(__bf16, b);
-}
-__device__ __forceinline__ __bf16 to_bf16(uint8_t q) {
-  // e4m3 values are exactly representable in BF16
-  return f32_to_bf16_rne(e4m3_to_f32(q));
-}
-
 constexpr int kTR = 256;  // sketch rows per workgroup
 constexpr int kTD = 256;  // columns per workgroup
 constexpr int kKS = 16;   // data rows per step
-constexpr int kXP = 24;   // padded LDS row (elements) of the transposed tile
 
-template <int IT>
 __global__ void __launch_bounds__(512)
-    gauss_sketch_kernel(const typename In<IT>::T* __restrict__ x, int64_t n,
-                        int64_t d, int64_t ld, uint64_t seed, int64_t r,
+    gauss_sketch_kernel(const float* __restrict__ x, int64_t n, int64_t d,
+                        int64_t ld, uint64_t seed, int64_t r,
                         int64_t rows_per_split, float* __restrict__ partial) {
-  // BF16 tiles: XT[col][row]; FP32 tiles: XS[row][col]
-  __shared__ __attribute__((aligned(16))) unsigned char lds_raw[
-      IT == 0 ? kKS * kTD * 4 : kTD * kXP * 2];
+  // XS[row][col]
+  __shared__ float XS[kKS * kTD];
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = t >> 6;
@@ -189,23 +153,10 @@ __global__ void __launch_bounds__(512)
     {
       const int64_t gi = k0 + srow;
       const int64_t gc = col0 + scol;
-      if constexpr (IT == 0) {
-        float* XS = reinterpret_cast<float*>(lds_raw);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const bool ok = gi < i_end && gc + u < d;
-          XS[srow * kTD + scol + u] =
-              ok ? reinterpret_cast<const float*>(x)[gi * ld + gc + u] : 0.0f;
-        }
-      } else {
-        __bf16* XT = reinterpret_cast<__bf16*>(lds_raw);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const bool ok = gi < i_end && gc + u < d;
-          __bf16 v = __builtin_bit_cast(__bf16, static_cast<uint16_t>(0));
-          if (ok) v = to_bf16(x[gi * ld + gc + u]);
-          XT[(scol + u) * kXP + srow] = v;
-        }
+      for (int u = 0; u < 8; ++u) {
+        const bool ok = gi < i_end && gc + u < d;
+        XS[srow * kTD + scol + u] = ok ? x[gi * ld + gc + u] : 0.0f;
       }
     }
     __syncthreads();
@@ -221,26 +172,12 @@ __global__ void __launch_bounds__(512)
 #pragma unroll
       for (int s = 0; s < 4; ++s) gz[4 + s] = z4[s];
     }
-    if constexpr (IT == 0) {
-      const float* XS = reinterpret_cast<const float*>(lds_raw);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-#pragma unroll
-        for (int ct = 0; ct < 8; ++ct) {
-          const float b = XS[(8 * h + s) * kTD + ct * 32 + l32];
-          acc[ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(gz[s], b, acc[ct], 0, 0, 0);
-        }
-      }
-    } else {
-      bf16x8 a;
-#pragma unroll
-      for (int s = 0; s < 8; ++s) a[s] = f32_to_bf16_rne(gz[s]);
-      const __bf16* XT = reinterpret_cast<const __bf16*>(lds_raw);
+    for (int s = 0; s < 8; ++s) {
 #pragma unroll
       for (int ct = 0; ct < 8; ++ct) {
-        const bf16x8 b =
-            *reinterpret_cast<const bf16x8*>(&XT[(ct * 32 + l32) * kXP + 8 * h]);
-        acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[ct], 0, 0, 0);
+        const float b = XS[(8 * h + s) * kTD + ct * 32 + l32];
+        acc[ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(gz[s], b, acc[ct], 0, 0, 0);
       }
     }
   }
@@ -274,87 +211,6 @@ __global__ void gauss_reduce_kernel(const float* __restrict__ partial,
   s = s * f;
   if (dscale) s *= dscale[c];
   sx[e] = s;
-}
-
-// ---- Gram matrix X^T X of BF16 / FP8 input ----------------------------------
-// Output tile (256 x 256) of column blocks (a, b), a <= b; eight waves, wave w
-// owns rows 32 w .. 32 w + 31 of the tile. Both operands come from the same
-// transposed LDS staging as the sketch (A = X^T block a, B = X block b).
-template <int IT>
-__global__ void __launch_bounds__(512)
-    gram_kernel(const typename In<IT>::T* __restrict__ x, int64_t n, int64_t d,
-                int64_t ld, int nb, int64_t rows_per_split,
-                float* __restrict__ partial) {
-  static_assert(IT != 0, "FP32 input uses gram_f64_kernel");
-  __shared__ __attribute__((aligned(16))) unsigned char lds_a[kTD * kXP * 2];
-  __shared__ __attribute__((aligned(16))) unsigned char lds_b[kTD * kXP * 2];
-  const int t = threadIdx.x;
-  const int lane = t & 63;
-  const int wave = t >> 6;
-  const int l32 = lane & 31;
-  const int h = lane >> 5;
-  // blockIdx.x enumerates the column-block pairs a <= b row by row
-  int ta = 0, rem = static_cast<int>(blockIdx.x);
-  while (rem >= nb - ta) {
-    rem -= nb - ta;
-    ++ta;
-  }
-  const int tb = ta + rem;
-  const bool diag = ta == tb;
-  const int64_t a0 = static_cast<int64_t>(ta) * kTD;
-  const int64_t b0 = static_cast<int64_t>(tb) * kTD;
-  const int64_t i_begin = static_cast<int64_t>(blockIdx.z) * rows_per_split;
-  int64_t i_end = i_begin + rows_per_split;
-  if (i_end > n) i_end = n;
-
-  f16v acc[8];
-#pragma unroll
-  for (int ct = 0; ct < 8; ++ct)
-#pragma unroll
-    for (int e = 0; e < 16; ++e) acc[ct][e] = 0.0f;
-  const int srow = t >> 5;
-  const int scol = (t & 31) * 8;
-
-  for (int64_t k0 = i_begin; k0 < i_end; k0 += kKS) {
-    __syncthreads();
-    const int64_t gi = k0 + srow;
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      if (side == 1 && diag) break;
-      unsigned char* buf = side == 0 ? lds_a : lds_b;
-      const int64_t gc = (side == 0 ? a0 : b0) + scol;
-      __bf16* XT = reinterpret_cast<__bf16*>(buf);
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const bool ok = gi < i_end && gc + u < d;
-        __bf16 v = __builtin_bit_cast(__bf16, static_cast<uint16_t>(0));
-        if (ok) v = to_bf16(x[gi * ld + gc + u]);
-        XT[(scol + u) * kXP + srow] = v;
-      }
-    }
-    __syncthreads();
-    const unsigned char* bb = diag ? lds_a : lds_b;
-    const __bf16* XA = reinterpret_cast<const __bf16*>(lds_a);
-    const __bf16* XB = reinterpret_cast<const __bf16*>(bb);
-    const bf16x8 av =
-        *reinterpret_cast<const bf16x8*>(&XA[(wave * 32 + l32) * kXP + 8 * h]);
-#pragma unroll
-    for (int ct = 0; ct < 8; ++ct) {
-      const bf16x8 bv =
-          *reinterpret_cast<const bf16x8*>(&XB[(ct * 32 + l32) * kXP + 8 * h]);
-      acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[ct], 0, 0, 0);
-    }
-  }
-  float* P = partial + static_cast<int64_t>(blockIdx.z) * d * d;
-#pragma unroll
-  for (int ct = 0; ct < 8; ++ct) {
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int64_t i = a0 + wave * 32 + (e % 4) + 8 * (e / 4) + 4 * h;
-      const int64_t j = b0 + ct * 32 + l32;
-      if (i < d && j < d) P[i * d + j] = acc[ct][e];
-    }
-  }
 }
 
 // G[i][j] = D_i D_j cs_i cs_j sum_s partial[s][min][max] (symmetric fill)
@@ -516,7 +372,8 @@ constexpr int64_t kMaxRowsPerSplit = 65536;
 
 }  // namespace
 
-size_t gauss_partial_bytes(int64_t n, int64_t r, int64_t d) {
+size_t gauss_partial_bytes(int64_t n, int64_t r, int64_t d, int dtype) {
+  if (gauss_q_dtype(dtype)) return gauss_q_partial_bytes(n, r, d);
   int64_t splits;
   split_rows(n, kMaxRowsPerSplit, &splits);
   return static_cast<size_t>(splits * r * d) * sizeof(float);
@@ -527,24 +384,38 @@ void launch_gauss_sketch(const void* x, int dtype, int64_t n, int64_t d,
                          int64_t r, const double* dscale, float* partial,
                          double* sx, hipStream_t s) {
   int64_t splits;
-  const int64_t per = split_rows(n, kMaxRowsPerSplit, &splits);
-  dim3 grid(static_cast<unsigned>((r + kTR - 1) / kTR),
-            static_cast<unsigned>((d + kTD - 1) / kTD),
-            static_cast<unsigned>(splits));
-  prof_begin(kKGaussSketch, s);
-  if (dtype == 1)
-    gauss_sketch_kernel<0><<<grid, 512, 0, s>>>(static_cast<const float*>(x), n,
-                                                d, ld, seed, r, per, partial);
-  else if (dtype == 2)
-    gauss_sketch_kernel<1><<<grid, 512, 0, s>>>(
-        static_cast<const uint16_t*>(x), n, d, ld, seed, r, per, partial);
-  else
-    gauss_sketch_kernel<2><<<grid, 512, 0, s>>>(
-        static_cast<const uint8_t*>(x), n, d, ld, seed, r, per, partial);
-  prof_end(kKGaussSketch, s);
+  if (gauss_q_dtype(dtype)) {
+    launch_gauss_q_sketch(x, dtype, n, d, ld, seed, r, partial, &splits,
+                          col_scale, nullptr, nullptr, s);
+  } else {
+    const int64_t per = split_rows(n, kMaxRowsPerSplit, &splits);
+    dim3 grid(static_cast<unsigned>((r + kTR - 1) / kTR),
+              static_cast<unsigned>((d + kTD - 1) / kTD),
+              static_cast<unsigned>(splits));
+    prof_begin(kKGaussSketch, s);
+    gauss_sketch_kernel<<<grid, 512, 0, s>>>(static_cast<const float*>(x), n, d,
+                                             ld, seed, r, per, partial);
+    prof_end(kKGaussSketch, s);
+  }
   const int64_t tot = r * d;
   gauss_reduce_kernel<<<static_cast<unsigned>((tot + 255) / 256), 256, 0, s>>>(
       partial, splits, r, d, dtype == 3 ? col_scale : nullptr, dscale,
+      1.0 / sqrt(static_cast<double>(r)), sx);
+}
+
+void launch_gauss_sketch_eq(const void* x, int dtype, int64_t n, int64_t d,
+                            int64_t ld, const float* col_scale, uint64_t seed,
+                            int64_t r, uint64_t* colmax_bits, int* nonfinite,
+                            double* dscale_out, float* partial, double* sx,
+                            hipStream_t s) {
+  launch_fill_u64(colmax_bits, d, 0, s);
+  int64_t splits;
+  launch_gauss_q_sketch(x, dtype, n, d, ld, seed, r, partial, &splits,
+                        col_scale, colmax_bits, nonfinite, s);
+  launch_colscale(colmax_bits, d, dscale_out, s);
+  const int64_t tot = r * d;
+  gauss_reduce_kernel<<<static_cast<unsigned>((tot + 255) / 256), 256, 0, s>>>(
+      partial, splits, r, d, dtype == 3 ? col_scale : nullptr, dscale_out,
       1.0 / sqrt(static_cast<double>(r)), sx);
 }
 
@@ -564,6 +435,7 @@ inline int64_t gram_f64_split(int64_t n, int64_t d, int64_t* splits) {
 }
 
 size_t gram_partial_bytes(int64_t n, int64_t d, int dtype) {
+  if (gauss_q_dtype(dtype)) return gram_q_partial_bytes(n, d);
   int64_t splits;
   if (dtype == 1) {
     gram_f64_split(n, d, &splits);
@@ -591,19 +463,8 @@ void launch_gram(const void* x, int dtype, int64_t n, int64_t d, int64_t ld,
                              s>>>(partial, splits, d, dscale, g);
     return;
   }
-  const int64_t per = split_rows(n, kMaxRowsPerSplit, &splits);
-  const int nb = static_cast<int>((d + kTD - 1) / kTD);
   float* partial = static_cast<float*>(scratch);
-  const int ntiles = nb * (nb + 1) / 2;
-  dim3 grid(static_cast<unsigned>(ntiles), 1, static_cast<unsigned>(splits));
-  prof_begin(kKGram, s);
-  if (dtype == 2)
-    gram_kernel<1><<<grid, 512, 0, s>>>(static_cast<const uint16_t*>(x), n, d,
-                                        ld, nb, per, partial);
-  else
-    gram_kernel<2><<<grid, 512, 0, s>>>(static_cast<const uint8_t*>(x), n, d, ld,
-                                        nb, per, partial);
-  prof_end(kKGram, s);
+  launch_gram_q(x, dtype, n, d, ld, partial, &splits, s);
   gram_reduce_kernel<<<static_cast<unsigned>((d * d + 255) / 256), 256, 0, s>>>(
       partial, splits, d, dtype == 3 ? col_scale : nullptr, dscale, g);
 }

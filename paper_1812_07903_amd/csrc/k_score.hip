@@ -602,6 +602,11 @@ void launch_scores(const void* x, int dtype, int format, int64_t n, int64_t d,
     prof_end(kKScore, s);
     return;
   }
+  if (score_q_ok(x, dtype, format, d, ld, k) &&
+      reinterpret_cast<uintptr_t>(partial) % 16 == 0) {
+    launch_score_q(x, dtype, n, d, ld, m64, k, partial, scores, s);
+    return;
+  }
   if (dtype != 0 && k <= 64) {
     const unsigned g = static_cast<unsigned>((n + kMR - 1) / kMR);
     if (dtype == 1) {

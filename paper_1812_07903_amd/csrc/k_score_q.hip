@@ -1,0 +1,253 @@
+// Scores l_i = ||x_i M||^2 (Algorithm 2 step 4) for BF16 and FP8 input with
+// d a multiple of 16 up to 512 and k <= 64: the pass that reads X once per
+// job, so it is priced against HBM.
+//
+// M (d x 64, zero past k) enters the BF16 MFMA as two BF16 parts,
+// Mh = bf16(M) and Ml = bf16(M - Mh) (M to 2^-17 of each entry), held in LDS
+// for the whole kernel (2 x 64 x (d + 8) BF16, 133 KB at d = 512), so a
+// workgroup reads M once. X goes from HBM straight into MFMA operand
+// registers: for v_mfma_f32_32x32x16_bf16 lane l takes row l % 32 and 8
+// consecutive columns, which are 16 contiguous bytes of a row-major BF16 row
+// (8 bytes of FP8 codes, decoded through a 256-entry LDS table). A wave
+// owns blocks of 32 rows (persistent: blocks wave, wave + W, ...), each
+// taken in two halves of at most 16 K-steps whose loads are issued one half
+// ahead. Sums are FP32 (products exact); the epilogue squares and adds the
+// 64 columns in FP32.
+#include "internal.h"
+
+namespace slso {
+namespace {
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kSQThreads = 512;  // eight waves
+constexpr int kSQHalf = 16;      // K-steps per half block
+constexpr int kSQMaxD = 512;     // largest d (two halves of 16 K-steps)
+
+__device__ __forceinline__ uint16_t bf16_bits_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+  return static_cast<uint16_t>(u);
+}
+
+// Mh, Ml by column (k contiguous, ldm = d), 64 columns, zero past k
+__global__ void split_m2_kernel(const double* __restrict__ m64, int64_t d,
+                                int64_t k, uint16_t* __restrict__ mh,
+                                uint16_t* __restrict__ ml) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= 64 * d) return;
+  const int64_t c = e / d, j = e % d;
+  const double v = c < k ? m64[j * k + c] : 0.0;
+  const uint16_t hb = bf16_bits_rne(static_cast<float>(v));
+  const double rest = v - static_cast<double>(__uint_as_float(
+                              static_cast<uint32_t>(hb) << 16));
+  mh[c * d + j] = hb;
+  ml[c * d + j] = bf16_bits_rne(static_cast<float>(rest));
+}
+
+template <int IT>
+struct SQIn;
+template <>
+struct SQIn<1> {
+  using T = uint16_t;
+};
+template <>
+struct SQIn<2> {
+  using T = uint8_t;
+};
+
+__device__ __forceinline__ uint32_t e4m3_to_bf16(uint32_t q) {
+  return __float_as_uint(e4m3_to_f32(static_cast<uint8_t>(q))) >> 16;
+}
+
+// A operand (8 BF16) of K-step s for this lane: row `row`, columns
+// 16 s + 8 h .. + 7 (raw: 16 bytes of BF16, or 8 bytes of FP8 codes)
+template <int IT>
+struct Raw;
+template <>
+struct Raw<1> {
+  uint4 v;
+};
+template <>
+struct Raw<2> {
+  uint2 v;
+};
+
+template <int IT>
+__device__ __forceinline__ Raw<IT> load_raw(const typename SQIn<IT>::T* p) {
+  Raw<IT> r;
+  if constexpr (IT == 1)
+    r.v = *reinterpret_cast<const uint4*>(p);
+  else
+    r.v = *reinterpret_cast<const uint2*>(p);
+  return r;
+}
+
+template <int IT>
+__device__ __forceinline__ bf16x8 operand(const Raw<IT>& r,
+                                          const uint16_t* dec8) {
+  if constexpr (IT == 1) {
+    return __builtin_bit_cast(bf16x8, r.v);
+  } else {
+    uint4 o;
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t src = q < 2 ? r.v.x : r.v.y;
+      const int sh = 16 * (q & 1);
+      w[q] = static_cast<uint32_t>(dec8[(src >> sh) & 0xFFu]) |
+             (static_cast<uint32_t>(dec8[(src >> (sh + 8)) & 0xFFu]) << 16);
+    }
+    o.x = w[0];
+    o.y = w[1];
+    o.z = w[2];
+    o.w = w[3];
+    return __builtin_bit_cast(bf16x8, o);
+  }
+}
+
+template <int IT>
+__global__ void __launch_bounds__(kSQThreads)
+    score_q_kernel(const typename SQIn<IT>::T* __restrict__ x, int64_t n,
+                   int64_t d, int64_t ld, const uint16_t* __restrict__ mh,
+                   const uint16_t* __restrict__ ml, float* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) uint16_t sm[128 * (kSQMaxD + 8) + 256];
+  const int pm = static_cast<int>(d) + 8;  // LDS pitch of M (elements)
+  uint16_t* Mh = sm;
+  uint16_t* Ml = sm + 64 * pm;
+  uint16_t* dec8 = sm + 128 * pm;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int l32 = lane & 31, h = lane >> 5;
+  const int steps = static_cast<int>(d / 16);
+  // M into LDS, 8 elements per access (d is a multiple of 16)
+  for (int64_t e = t; e < 8 * d; e += kSQThreads) {
+    const int64_t c = e / (d / 8), j = 8 * (e % (d / 8));
+    *reinterpret_cast<uint4*>(&Mh[c * pm + j]) =
+        *reinterpret_cast<const uint4*>(&mh[c * d + j]);
+    *reinterpret_cast<uint4*>(&Ml[c * pm + j]) =
+        *reinterpret_cast<const uint4*>(&ml[c * d + j]);
+  }
+  if (IT == 2 && t < 256) dec8[t] = static_cast<uint16_t>(e4m3_to_bf16(t));
+  __syncthreads();
+
+  const int64_t nblk = (n + 31) / 32;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 8;
+  int64_t blk = static_cast<int64_t>(blockIdx.x) * 8 + w;
+  using T = typename SQIn<IT>::T;
+  auto rowptr = [&](int64_t b) -> const T* {
+    int64_t row = b * 32 + l32;
+    if (row >= n) row = n - 1;  // in bounds; the score is not written
+    return x + row * ld + 8 * h;
+  };
+  // two halves of K-steps; loads run one half ahead of the products
+  Raw<IT> A0[kSQHalf], A1[kSQHalf];
+  if (blk < nblk) {
+    const T* p = rowptr(blk);
+#pragma unroll
+    for (int s = 0; s < kSQHalf; ++s)
+      if (s < steps) A0[s] = load_raw<IT>(p + 16 * s);
+  }
+  for (; blk < nblk; blk += stride) {
+    const T* p = rowptr(blk);
+    const int64_t nxt = blk + stride;
+    const T* pn = rowptr(nxt < nblk ? nxt : blk);
+    f16v acc[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[ct][e] = 0.0f;
+    // second half of this block in flight while the first multiplies
+#pragma unroll
+    for (int s = 0; s < kSQHalf; ++s)
+      if (kSQHalf + s < steps) A1[s] = load_raw<IT>(p + 16 * (kSQHalf + s));
+#pragma unroll
+    for (int s = 0; s < kSQHalf; ++s) {
+      if (s < steps) {
+        const bf16x8 a = operand<IT>(A0[s], dec8);
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          const int o = (32 * ct + l32) * pm + 16 * s + 8 * h;
+          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Ml[o]);
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Mh[o]);
+          acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, acc[ct], 0, 0, 0);
+          acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, acc[ct], 0, 0, 0);
+        }
+      }
+    }
+    // the next block's first half in flight while the second multiplies
+    if (nxt < nblk) {
+#pragma unroll
+      for (int s = 0; s < kSQHalf; ++s)
+        if (s < steps) A0[s] = load_raw<IT>(pn + 16 * s);
+    }
+#pragma unroll
+    for (int s = 0; s < kSQHalf; ++s) {
+      if (kSQHalf + s < steps) {
+        const bf16x8 a = operand<IT>(A1[s], dec8);
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          const int o = (32 * ct + l32) * pm + 16 * (kSQHalf + s) + 8 * h;
+          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Ml[o]);
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Mh[o]);
+          acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, acc[ct], 0, 0, 0);
+          acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, acc[ct], 0, 0, 0);
+        }
+      }
+    }
+    // l_i = sum over the 64 columns of the squares: register e of lane l
+    // holds row (e % 4) + 8 (e / 4) + 4 h, column l % 32 (+ 32 ct)
+    float v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      v[e] = acc[0][e] * acc[0][e] + acc[1][e] * acc[1][e];
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] += __shfl_xor(v[e], o, 64);
+    if (l32 < 16) {
+      const int e = l32;
+      const int64_t row = blk * 32 + (e % 4) + 8 * (e / 4) + 4 * h;
+      float val = v[0];
+#pragma unroll
+      for (int q = 1; q < 16; ++q) val = e == q ? v[q] : val;
+      if (row < n) out[row] = val;
+    }
+  }
+}
+
+}  // namespace
+
+bool score_q_ok(const void* x, int dtype, int format, int64_t d, int64_t ld,
+                int64_t k) {
+  if (format != 0 || (dtype != 2 && dtype != 3) || k > 64 || k < 1) return false;
+  if (d % 16 != 0 || d > kSQMaxD || ld % 8 != 0) return false;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(x);
+  return a % (dtype == 2 ? 16 : 8) == 0;
+}
+
+size_t score_q_scratch_bytes(int64_t d) {
+  return static_cast<size_t>(2 * 64 * d) * sizeof(uint16_t);
+}
+
+void launch_score_q(const void* x, int dtype, int64_t n, int64_t d, int64_t ld,
+                    const double* m64, int64_t k, void* scratch, float* scores,
+                    hipStream_t s) {
+  uint16_t* mh = static_cast<uint16_t*>(scratch);
+  uint16_t* ml = mh + 64 * d;
+  split_m2_kernel<<<static_cast<unsigned>((64 * d + 255) / 256), 256, 0, s>>>(
+      m64, d, k, mh, ml);
+  const int64_t nblk = (n + 31) / 32;
+  int64_t grid = (nblk + 7) / 8;
+  if (grid > 256) grid = 256;
+  prof_begin(kKScore, s);
+  if (dtype == 2)
+    score_q_kernel<1><<<static_cast<unsigned>(grid), kSQThreads, 0, s>>>(
+        static_cast<const uint16_t*>(x), n, d, ld, mh, ml, scores);
+  else
+    score_q_kernel<2><<<static_cast<unsigned>(grid), kSQThreads, 0, s>>>(
+        static_cast<const uint8_t*>(x), n, d, ld, mh, ml, scores);
+  prof_end(kKScore, s);
+}
+
+}  // namespace slso

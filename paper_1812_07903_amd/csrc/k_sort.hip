@@ -142,6 +142,77 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
+// Exclusive scan of len entries in place by chunks of kScanChunk: the
+// chunk sums (one workgroup per chunk), their exclusive scan (one
+// workgroup, up to 1024 chunks), and each chunk's scan from its offset.
+constexpr int kScanChunk = 2048;
+
+__global__ void __launch_bounds__(256)
+    rs_chunk_sum_kernel(const uint32_t* __restrict__ hist, int64_t len,
+                        uint32_t* __restrict__ sums) {
+  __shared__ uint32_t ws[4];
+  const int tid = threadIdx.x;
+  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kScanChunk;
+  uint32_t v = 0;
+#pragma unroll
+  for (int u = 0; u < kScanChunk / 256; ++u) {
+    const int64_t i = c0 + u * 256 + tid;
+    v += i < len ? hist[i] : 0u;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((tid & 63) == 0) ws[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) sums[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ void __launch_bounds__(1024)
+    rs_sums_scan_kernel(uint32_t* __restrict__ sums, int nchunks) {
+  __shared__ uint32_t s[1024];
+  const int tid = threadIdx.x;
+  const uint32_t v = tid < nchunks ? sums[tid] : 0u;
+  s[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint32_t y = tid >= o ? s[tid - o] : 0u;
+    __syncthreads();
+    s[tid] += y;
+    __syncthreads();
+  }
+  if (tid < nchunks) sums[tid] = s[tid] - v;
+}
+
+__global__ void __launch_bounds__(256)
+    rs_chunk_scan_kernel(uint32_t* __restrict__ hist, int64_t len,
+                         const uint32_t* __restrict__ sums) {
+  // thread tid scans entries c0 + 8 tid .. + 7, then the 256 thread sums
+  __shared__ uint32_t ws[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kScanChunk + 8 * tid;
+  uint32_t v[8], tot = 0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    v[u] = c0 + u < len ? hist[c0 + u] : 0u;
+    tot += v[u];
+  }
+  uint32_t inc = tot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) ws[wave] = inc;
+  __syncthreads();
+  uint32_t run = sums[blockIdx.x] + inc - tot;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) run += w < wave ? ws[w] : 0u;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    if (c0 + u < len) hist[c0 + u] = run;
+    run += v[u];
+  }
+}
+
 template <int kItems, bool kFused>
 __global__ void __launch_bounds__(kThreads)
     rs_scatter_kernel(const uint32_t* __restrict__ keys_in,
@@ -304,7 +375,9 @@ int sort_items(int64_t n) { return n < kSmallSort ? kItemsSmall : kItemsLarge; }
 size_t radix_sort_scratch_bytes(int64_t n) {
   const int64_t tile = static_cast<int64_t>(kThreads) * sort_items(n);
   const int64_t nblocks = (n + tile - 1) / tile;
-  return static_cast<size_t>(256 * nblocks) * sizeof(uint32_t);
+  const int64_t len = 256 * nblocks;
+  const int64_t nchunks = (len + kScanChunk - 1) / kScanChunk;
+  return static_cast<size_t>(len + nchunks) * sizeof(uint32_t);
 }
 
 void radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in,
@@ -343,7 +416,18 @@ void radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in,
             ksrc, n, shift, hist, nblocks);
       prof_end(kKSortHist, s);
       prof_begin(kKSortScan, s);
-      rs_scan_kernel<<<1, 1024, 0, s>>>(hist, static_cast<int64_t>(256) * nblocks);
+      const int64_t len = static_cast<int64_t>(256) * nblocks;
+      const int64_t nchunks = (len + kScanChunk - 1) / kScanChunk;
+      if (nchunks <= 1024) {
+        uint32_t* sums = hist + len;
+        rs_chunk_sum_kernel<<<static_cast<unsigned>(nchunks), 256, 0, s>>>(
+            hist, len, sums);
+        rs_sums_scan_kernel<<<1, 1024, 0, s>>>(sums, static_cast<int>(nchunks));
+        rs_chunk_scan_kernel<<<static_cast<unsigned>(nchunks), 256, 0, s>>>(
+            hist, len, sums);
+      } else {
+        rs_scan_kernel<<<1, 1024, 0, s>>>(hist, len);
+      }
       prof_end(kKSortScan, s);
       prof_begin(kKSortScatter, s);
       if (items == kItemsSmall)

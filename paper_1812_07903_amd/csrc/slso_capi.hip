@@ -344,7 +344,7 @@ void enqueue_countsketch(const slso_matrix* X, int nnz, uint64_t seed,
 size_t gemm_partial_bytes(const slso_matrix* X, int64_t r, bool gauss,
                           bool refine) {
   const int64_t n = X->n, d = X->d;
-  const size_t g = gauss ? gauss_partial_bytes(n, r, d) : size_t{0};
+  const size_t g = gauss ? gauss_partial_bytes(n, r, d, X->dtype) : size_t{0};
   const size_t m = refine ? gram_partial_bytes(n, d, X->dtype) : size_t{0};
   return std::max(g, m);
 }
@@ -439,6 +439,7 @@ int slso_create(slso_ctx** out, int device) {
   slso_ctx* c = new slso_ctx();
   c->device = device;
   if (hipSetDevice(device) != hipSuccess ||
+      init_quantile_tables(device) != 0 ||
       hipHostMalloc(&c->host_buf, 4096, hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&c->ws_done, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->side_done, hipEventDisableTiming) != hipSuccess ||
@@ -499,6 +500,19 @@ int slso_gaussian_sketch_entries(uint64_t seed, int64_t r, int64_t row0,
   return hipGetLastError() == hipSuccess ? SLSO_OK : SLSO_EDEVICE;
 }
 
+int slso_gaussian_sketch_entries_q(uint64_t seed, int32_t dtype, int64_t r,
+                                   int64_t row0, int64_t n, float* out,
+                                   void* stream) {
+  if (r < 0 || n < 0 || row0 < 0 || (r * n > 0 && !out)) return SLSO_EINVAL;
+  if (dtype != SLSO_BF16 && dtype != SLSO_FP8_E4M3) return SLSO_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || init_quantile_tables(dev) != 0)
+    return SLSO_EDEVICE;
+  launch_gauss_q_entries(seed, r, n, row0, dtype == SLSO_BF16 ? 0 : 1, out,
+                         static_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? SLSO_OK : SLSO_EDEVICE;
+}
+
 int slso_sketch(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
                 const slso_options* opt, double* sx, void* stream) {
   if (!c) return SLSO_EINVAL;
@@ -525,7 +539,7 @@ int slso_sketch(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
     size_sketch_bufs(z, X->n * nnz, r);
     z.take<double>(X->d);
   } else {
-    z.take<char>(gauss_partial_bytes(X->n, r, X->d));
+    z.take<char>(gauss_partial_bytes(X->n, r, X->d, X->dtype));
   }
   if ((st = ensure_ws(c, z.off))) return st;
   WsMark mark_{c, s};
@@ -546,7 +560,7 @@ int slso_sketch(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
     enqueue_countsketch(X, nnz, seed, r, b,
                         X->dtype == SLSO_FP8_E4M3 ? cs : nullptr, sx, s);
   } else {
-    float* part = a.take<float>(gauss_partial_bytes(X->n, r, X->d) / 4);
+    float* part = a.take<float>(gauss_partial_bytes(X->n, r, X->d, X->dtype) / 4);
     launch_gauss_sketch(X->values, X->dtype, X->n, X->d, X->ld, X->col_scale,
                         seed, r, nullptr, part, sx, s);
   }
@@ -743,6 +757,9 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   // sketch (exact: powers of two). Otherwise a pass of its own comes first.
   const bool fuse = nnz > 0 && countsketch_colmax_ok(X->values, X->dtype,
                                                      X->format, X->ld);
+  // BF16 / FP8 input to the Gaussian sketch: the column maxima are taken in
+  // the sketch's own pass, and D is applied when its slices are summed
+  const bool gauss_eq = gauss && gauss_q_dtype(X->dtype);
   // 0. the bucket partition needs no input values: without the fused pass it
   // runs on the context's second stream while the column maxima are taken
   const bool side_partition = nnz > 0 && !fuse && c->qs.side;
@@ -762,7 +779,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   else
     launch_gaussian(seed, kStreamPi2, d, k, std::sqrt(static_cast<double>(k)),
                     pi, s);
-  if (!fuse) {
+  if (!fuse && !gauss_eq) {
     launch_fill_u64(colmax, d, 0, s);
     launch_colmax(X->values, X->dtype, X->format, n, d, X->ld, X->row_ptr,
                   X->col_idx, X->nnz, X->col_scale, X->row_scale, colmax, flags,
@@ -781,6 +798,13 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   bool partitioned = false, fused_done = false, unscaled = false;
   auto sketch = [&]() {
     unscaled = false;
+    if (gauss_eq) {
+      launch_gauss_sketch_eq(X->values, X->dtype, n, d, X->ld, X->col_scale,
+                             seed, r, colmax, flags, dscale,
+                             static_cast<float*>(gpart), sx, s);
+      if (fp8) launch_mul_scale(dscale, X->col_scale, d, eff, s);
+      return;
+    }
     if (gauss) {
       launch_gauss_sketch(X->values, X->dtype, n, d, X->ld, X->col_scale, seed,
                           r, dscale, static_cast<float*>(gpart), sx, s);

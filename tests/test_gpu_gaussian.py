@@ -2,12 +2,14 @@
 refinement against the CPU oracle, through the C ABI (gfx950).
 
 Tolerances:
-* generator entries: bit-exact (both sides evaluate the same sequence of
-  separately rounded FP32 operations);
+* generator entries: bit-exact (the FP32 generator: both sides evaluate the
+  same sequence of separately rounded FP32 operations; the quantile form:
+  the same Philox halves and the same tables);
 * Gaussian sketch: the GPU sums exact BF16 (or FP32) products in FP32 within
-  row chunks of at most 65536 rows and in FP64 across chunks; the oracle sums
-  in FP64. The error bound used is 1e-4 of sum_i |g_ji x_ic| / sqrt(r), about
-  25x the random-walk estimate sqrt(n / 16) 2^-24 at n = 66000;
+  slices of at most 65536 rows (FP32 input) or 2^18 rows (BF16, FP8) and in
+  FP64 across slices; the oracle sums in FP64. The error bound used is 1e-4
+  of sum_i |g_ji x_ic| / sqrt(r), about 13x the random-walk estimate
+  sqrt(m / 16) 2^-24 for slices of m = 2^18 rows;
 * refined scores: the spec bar for the reduced-precision path, max
   relative error <= 1e-2 and Kendall tau >= 0.99 against the FP64 oracle;
   observed errors are far smaller and are printed.
@@ -86,10 +88,24 @@ def test_gaussian_sketch_entries_bit_exact(slso, seed, r, row0, n):
     assert np.array_equal(g.view(np.uint32), ref.view(np.uint32))
 
 
+@pytest.mark.parametrize("seed,r,row0,n", [
+    (0, 1, 0, 1), (11, 7, 0, 4099), (2025, 300, 3, 1001),
+    (2**63 + 5, 33, 2**33 + 13, 517), (1003, 2048, 123457, 64)])
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_gaussian_sketch_entries_q_bit_exact(slso, seed, r, row0, n, fmt):
+    """Quantile-form entries (BF16 and e4m3 tables, Philox halves) against
+    the oracle's, bit for bit."""
+    dt = slso.BF16 if fmt == "bf16" else slso.FP8_E4M3
+    g = host(slso.gaussian_sketch_entries_q(seed, dt, r, n, row0=row0))
+    ref = ost.gaussian_sketch_matrix_q(seed, r, n, fmt, row0=row0)
+    assert np.array_equal(g.astype(np.float64), ref)
+
+
 # ---- sketch ----------------------------------------------------------------------
 @pytest.mark.parametrize("kind,n,d,r", [
     ("f32", 3001, 40, 300), ("bf16", 3001, 40, 300), ("fp8", 2999, 37, 257),
-    ("bf16", 66000, 33, 257), ("f32", 520, 300, 520)])
+    ("bf16", 66000, 33, 257), ("f32", 520, 300, 520), ("bf16", 300007, 72, 257),
+    ("fp8", 70001, 520, 600), ("bf16", 5003, 1030, 1100)])
 def test_gaussian_sketch_matches_oracle(slso, ctx, kind, n, d, r):
     rng = np.random.default_rng(n + d)
     x64 = rng.standard_normal((n, d)) * np.exp(rng.standard_normal(n))[:, None]
@@ -256,3 +272,45 @@ def test_gaussian_rejects_unsupported_inputs(slso, ctx):
     with pytest.raises(slso.SlsoError) as e:
         ctx.leverage(x, 1, 16, 4, refine=True)
     assert e.value.status == slso.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("kind,bad,row,n", [
+    ("bf16", np.nan, 17, 5000), ("bf16", np.inf, 4999, 5000),
+    ("bf16", -np.inf, 70000, 100003), ("fp8", np.nan, 33, 5000)])
+def test_gaussian_nonfinite_rejected(slso, ctx, kind, bad, row, n):
+    """BF16 / FP8 input: the column maxima (and the Inf / NaN check) come from
+    the Gaussian sketch's own pass, shared by its row-tile workgroups; a bad
+    value in any row of any slice must be caught."""
+    x64 = synth.config0(n=n, d=40, seed=3)
+    xin, _, _ = as_input(slso, x64, kind)
+    if kind == "fp8":
+        xin.codes[row, 5] = 0x7F          # the e4m3fn NaN code
+    else:
+        xin[row, 5] = float(bad)
+    with pytest.raises(slso.SlsoError) as ei:
+        ctx.leverage(xin, 1, 512, 8, sketch=slso.GAUSSIAN)
+    assert ei.value.status == slso.ENONFINITE
+
+
+@pytest.mark.parametrize("kind,d,pad", [("bf16", 72, 0), ("bf16", 70, 3),
+                                        ("fp8", 520, 0), ("fp8", 33, 5)])
+def test_gaussian_equilibration_matches_oracle(slso, ctx, kind, d, pad):
+    """Column scales D from the sketch pass (BF16, FP8; aligned rows and not)
+    give the oracle's leverage: the unrefined Gaussian path against the
+    sketched oracle of the same entries."""
+    x64 = synth.config0(n=30011, d=d, seed=4)
+    x64 *= np.exp(np.linspace(-6, 6, d))[None, :]   # columns over 2^17
+    xin, xval, prec = as_input(slso, np.pad(x64, ((0, 0), (0, pad))), kind)
+    xval = xval[:, :d]
+    if kind == "fp8":
+        xin = slso.Fp8Matrix(xin.codes[:, :d], xin.col_scale[:d])
+    else:
+        xin = xin[:, :d]
+    r = 2 * d + 64
+    got, info = ctx.leverage(xin, 12, r, 16, sketch=slso.GAUSSIAN)
+    got = host(got)
+    ref = olv.sketched_leverage(xval, 12, r, 16, kind="gaussian",
+                                precision=prec)
+    assert info["rank"] == ref["rank"]
+    err = _report(f"gauss eq {kind} d={d} ld={d + pad}", got, ref["scores"])
+    assert err <= 1e-2 and omet.kendall_tau(got, ref["scores"]) >= 0.99

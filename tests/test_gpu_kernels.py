@@ -361,6 +361,35 @@ def test_scores_dense(slso, ctx, dtype, k):
         assert np.all(np.abs(got - ref) <= tol * bound)
 
 
+@pytest.mark.parametrize("dtype,n,d,k", [
+    ("bf16", 4099, 512, 64), ("bf16", 31, 16, 1), ("bf16", 70001, 496, 37),
+    ("fp8", 5003, 512, 64), ("fp8", 1000, 272, 64), ("bf16", 300, 64, 64)])
+def test_scores_m_in_lds(slso, ctx, dtype, n, d, k):
+    """BF16 / FP8 input with d a multiple of 16 up to 512 and k <= 64: M
+    enters the MFMA as two BF16 parts held in LDS, X straight from HBM into
+    the operands (ragged n, more blocks than waves). Bound: M to 2^-17 per
+    entry and FP32 sums of d exact products, so |l - l_ref| <= 1e-4
+    sum_c (sum_j |x_ij M_jc|)^2."""
+    rng = np.random.default_rng(n + d)
+    x64 = rng.standard_normal((n, d)) * np.exp(rng.standard_normal(n))[:, None]
+    m = rng.standard_normal((d, k)) / np.sqrt(d)
+    if dtype == "bf16":
+        bits = synth.to_bf16_bits(x64)
+        xt = dev(bits.view(np.int16)).view(torch.bfloat16)
+        xref = synth.bf16_bits_to_f64(bits)
+    else:
+        codes, cs = synth.to_fp8_e4m3(x64)
+        xt = slso.Fp8Matrix(dev(codes), dev(cs))
+        xref = synth.fp8_e4m3_to_f64(codes, cs)
+    got = host(ctx.scores(xt, dev(m)))
+    ref = olv.row_scores(xref, m)
+    bound = ((np.abs(xref) @ np.abs(m)) ** 2).sum(axis=1)
+    print(f"[scores lds {dtype} n={n} d={d} k={k}] max_rel="
+          f"{omet.max_rel_err(got, ref):.2e} max err/bound="
+          f"{(np.abs(got - ref) / bound).max():.2e}", flush=True)
+    assert np.all(np.abs(got - ref) <= 1e-4 * bound)
+
+
 def test_scores_csr(slso, ctx):
     c = synth.text_like_csr(20000, 700, density=0.02, seed=4)
     m = np.random.default_rng(2).standard_normal((700, 64)) / 8
