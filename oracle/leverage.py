@@ -207,3 +207,22 @@ def sketched_leverage(x, seed: int, r: int, k: int, kind: str = "countsketch",
     scores = row_scores(x, m)
     return {"scores": scores, "rank": rank, "R_D": rd, "D": dsc, "M": m,
             "SX": sx, "info": info}
+
+
+def realised_distortion(x, seed: int, r: int, kind: str = "countsketch",
+                        precision: str = "bf16", nnz: int = 2) -> float:
+    """Realised distortion of the sketch on the column space of X (Def. 1 and
+    Thm. 1, Sec. 2.1): with U an orthonormal basis of range(X) (the Q of a
+    Householder QR of X D; X of full column rank),
+        eps_hat = max(sigma_max(S U)^2 - 1, 1 - sigma_min(S U)^2),
+    the smallest eps for which S is a (1 +- eps) subspace embedding of X,
+    ||S X v||^2 in [(1 - eps), (1 + eps)] ||X v||^2 for every v. S is the
+    sketch of ``sketch_of`` with the same seed (its entries do not depend on
+    the matrix they multiply)."""
+    xd = x.to_dense() if not isinstance(x, np.ndarray) else \
+        np.asarray(x, dtype=np.float64)
+    dsc = sk.column_scale(_colmax(x))
+    q, _ = np.linalg.qr(xd * dsc[None, :])
+    su = sketch_of(q, seed, r, kind, precision, nnz)
+    sv = np.linalg.svd(su, compute_uv=False)
+    return float(max(sv[0] ** 2 - 1.0, 1.0 - sv[-1] ** 2))

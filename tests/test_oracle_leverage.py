@@ -231,3 +231,53 @@ def test_always_svd_rank_catches_kahan_matrix():
     assert dmin > math.sqrt(tol) * dmax
     rank2, full2, _, _, _ = lv.rank_decision(kahan, tol, always_svd=True)
     assert not full2 and rank2 == d - 1
+
+
+# ---- realised distortion (Def. 1 / Thm. 1) -------------------------------------
+def test_realised_distortion_zero_for_injective_sketch():
+    """An injective CountSketch maps U to a signed row permutation of U:
+    S U has orthonormal columns, eps_hat = 0 (to rounding)."""
+    n, d, r = 60, 5, 1 << 16
+    for seed in range(100):
+        b, _ = streams.bucket_sign(seed, r, np.arange(n))
+        if len(set(b.tolist())) == n:
+            break
+    x = np.random.default_rng(6).standard_normal((n, d))
+    assert lv.realised_distortion(x, seed, r) < 1e-13
+
+
+def test_realised_distortion_brackets_the_scores():
+    """Thm. 1 with Def. 1: every sketched score (k = 0) lies in
+    [l_i / (1 + eps_hat), l_i / (1 - eps_hat)]."""
+    x = synth.config0(n=4000, d=10, seed=31)
+    eps = lv.realised_distortion(x, 7, 512)
+    lev, _ = lv.exact_leverage(x)
+    got = lv.sketched_leverage(x, seed=7, r=512, k=0)["scores"]
+    ratio = got / lev
+    assert 0.0 < eps < 1.0
+    assert ratio.min() >= (1 - 1e-9) / (1 + eps)
+    assert ratio.max() <= (1 + 1e-9) / (1 - eps)
+
+
+def test_realised_distortion_gaussian_matches_marchenko_pastur():
+    """FP64 Gaussian S (N(0, 1/r) entries) on a d-dimensional subspace: the
+    squared singular values of S U fill [(1 - sqrt(d/r))^2, (1 + sqrt(d/r))^2]
+    as r grows, so eps_hat ~ 2 sqrt(d/r) + d/r; checked within 25 % over
+    four seeds at d = 20, r = 2000."""
+    x = np.random.default_rng(3).standard_normal((3000, 20))
+    edge = 2 * np.sqrt(20 / 2000) + 20 / 2000
+    vals = [lv.realised_distortion(x, s, 2000, kind="gaussian",
+                                   precision="f64") for s in range(4)]
+    assert 0.75 * edge < np.mean(vals) < 1.25 * edge
+
+
+def test_realised_distortion_equals_sketch_r_over_exact_r():
+    """sigma(S U) = sigma(R_S R^-1) with R_S the R of S X D and R the R of
+    X D (S X D = Q_S R_S and X D = Q R give S Q = Q_S R_S R^-1): the route a
+    factor-only implementation takes."""
+    x = synth.config0(n=3000, d=16, seed=33)
+    out = lv.sketched_leverage(x, seed=5, r=256, k=0)
+    rd = lv.qr_r(x * out["D"][None, :])
+    sv = np.linalg.svd(out["R_D"] @ np.linalg.inv(rd), compute_uv=False)
+    eps = max(sv[0] ** 2 - 1, 1 - sv[-1] ** 2)
+    assert abs(eps - lv.realised_distortion(x, 5, 256)) < 1e-12
