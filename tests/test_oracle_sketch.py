@@ -183,3 +183,17 @@ def test_srht_is_unbiased_embedding():
 def test_srht_rejects_r_above_padded_rows():
     with pytest.raises(ValueError):
         sk.srht_plan(1, 100, 200)
+
+
+def test_colmax_csr_equals_colmax_of_dense():
+    """Column max-abs of a CSR matrix equals that of its dense form (with
+    negative values, empty columns and a column holding one entry)."""
+    c = synth.text_like_csr(3000, 300, density=0.01, seed=21)
+    c.val = (c.val * np.where(np.arange(c.nnz) % 3 == 0, -1.0, 1.0)).astype(
+        np.float32)
+    got = sk.colmax_csr(c)
+    want = sk.colmax_dense(c.to_dense())
+    assert np.array_equal(got, want)
+    assert (want == 0).any()             # some column is empty
+    # the equilibration derived from it is the same power of two
+    assert np.array_equal(sk.column_scale(got), sk.column_scale(want))
