@@ -117,6 +117,16 @@ typedef struct {
                             /* not by the diagonal screen, which can call a  */
                             /* Kahan-type R full rank; with nothing cut the  */
                             /* scores are those of R^{-1}                    */
+#define SLSO_OPT_EPS_HAT 2  /* report the realised distortion eps_hat of the */
+                            /* sketch on range(X) (Def. 1 / Thm. 1, Sec.     */
+                            /* 2.1) in slso_info.eps_hat: with R1 the        */
+                            /* refinement's Cholesky factor, R = R1 R_S is   */
+                            /* the R of X D, so sigma(S U) = sigma(R_S R^-1) */
+                            /* = 1 / sigma(R1), from a Jacobi SVD of R1. The */
+                            /* refinement's Gram pass and Cholesky run even  */
+                            /* without refine (dense F32 / BF16 / FP8 input  */
+                            /* only: EUNSUPPORTED otherwise); the call then  */
+                            /* synchronises its stream a few more times      */
 
 /* Host-side report of one leverage computation. */
 typedef struct {
@@ -125,6 +135,10 @@ typedef struct {
   int32_t flags;       /* SLSO_INFO_* bits                                   */
   double diag_min;     /* min |R[j][j]| of the factor used (the refined one  */
   double diag_max;     /* when SLSO_INFO_REFINED is set, else R_D's)         */
+  double eps_hat;      /* with SLSO_OPT_EPS_HAT: max(sigma_max(S U)^2 - 1,   */
+                       /* 1 - sigma_min(S U)^2), U an orthonormal basis of   */
+                       /* range(X); NaN when not asked for or when X D is    */
+                       /* numerically rank deficient                         */
 } slso_info;
 
 /* slso_info.flags bits */

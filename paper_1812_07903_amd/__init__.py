@@ -27,7 +27,7 @@ EINVAL, ENOMEM, ENONFINITE, EDEVICE, EUNSUPPORTED = -1, -2, -3, -4, -5
 F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
 DENSE, CSR = 0, 1
 COUNTSKETCH, GAUSSIAN, OSNAP, SRHT = 0, 1, 2, 3
-OPT_SVD_RANK = 1
+OPT_SVD_RANK, OPT_EPS_HAT = 1, 2
 ORDER_DEC, ORDER_SWR, ORDER_SWOR = 0, 1, 2
 STREAM_GAUSS_S, STREAM_PI2 = 3, 4
 
@@ -76,7 +76,7 @@ class _Options(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("rank", ctypes.c_int64), ("screen_full", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("diag_min", ctypes.c_double),
-                ("diag_max", ctypes.c_double)]
+                ("diag_max", ctypes.c_double), ("eps_hat", ctypes.c_double)]
 
 
 class _Job(ctypes.Structure):
@@ -363,16 +363,19 @@ class Context:
 
     def leverage(self, x, seed: int, r: int, k: int, sketch: int = COUNTSKETCH,
                  refine: bool = False, rank_tol: float = 0.0, out=None,
-                 stream=None, nnz: int = 0, svd_rank: bool = False):
+                 stream=None, nnz: int = 0, svd_rank: bool = False,
+                 eps_hat: bool = False):
         """Scores (float32 device tensor) and the rank-decision info dict.
         ``nnz``: OSNAP nonzeros per column of S (0 selects 2); ``svd_rank``:
-        decide the rank by the SVD of R every time."""
+        decide the rank by the SVD of R every time; ``eps_hat``: report the
+        sketch's realised distortion on range(X) as info["eps_hat"]."""
         import torch
         m = _matrix(x)
         self._here(_device(x))
         out = _out(out, torch.float32, _rows(x), _device(x), "out")
         opt = _Options(sketch, 1 if refine else 0, rank_tol, nnz,
-                       OPT_SVD_RANK if svd_rank else 0)
+                       (OPT_SVD_RANK if svd_rank else 0) |
+                       (OPT_EPS_HAT if eps_hat else 0))
         info = _Info()
         st = _check(load_library().slso_leverage(
             self._h, ctypes.byref(m), seed, r, k, ctypes.byref(opt), _ptr(out),
@@ -484,7 +487,8 @@ def _info_dict(info, st):
     return {"status": st, "rank": info.rank,
             "screen_full": bool(info.screen_full), "flags": info.flags,
             "refined": bool(info.flags & INFO_REFINED),
-            "diag_min": info.diag_min, "diag_max": info.diag_max}
+            "diag_min": info.diag_min, "diag_max": info.diag_max,
+            "eps_hat": info.eps_hat}
 
 
 def workspace_size(x, r: int, k: int, sketch: int = COUNTSKETCH,

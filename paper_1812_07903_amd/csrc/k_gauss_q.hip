@@ -23,8 +23,9 @@
 // registers so that each column's 4 rows are one 8-byte LDS write. Wave w
 // owns sketch rows 64 (w & 1) .. + 63 and columns 128 (w >> 1) .. + 127 as
 // 2 x 4 MFMA blocks of 32 x 32 (v_mfma_f32_32x32x16_bf16). The next step's
-// entries are drawn and its rows loaded while the current step's products
-// run, so the generator's VALU work overlaps the matrix unit.
+// entries are drawn while the current step's products run, so the
+// generator's VALU work overlaps the matrix unit, and rows are loaded two
+// steps ahead.
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -141,62 +142,80 @@ __device__ __forceinline__ uint32_t e4m3_bf16_bits(uint32_t q) {
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 // ---- staging of X blocks (shared by the sketch and the Gram pass) ------------
-// A thread stages rows row .. row + 3 and columns gcol .. gcol + 7 of X as
-// BF16 pairs: xr[u][v] = row + u, columns 2 v (low half) and 2 v + 1; rows
-// at or past i_end are zero (full: none of the four is). FP8 codes are
-// decoded through the 256-entry table dec8 (exact in BF16).
+// A thread stages rows row .. row + 3 and columns gcol .. gcol + 7 of X. The
+// loads are issued unconditionally (rows past i_end read row i_end - 1) into
+// raw registers and only used a step or two later, so nothing waits for
+// them at the issue point; rows at or past i_end are zeroed when the block
+// is unpacked (stage_unpack) into BF16 pairs xr[u][v] = row + u, columns
+// 2 v (low half) and 2 v + 1. FP8 codes are decoded through the 256-entry
+// table dec8 (exact in BF16).
+template <int IT>
+struct RawBlock;
+template <>
+struct RawBlock<1> {  // BF16: 8 elements per row, 16 bytes
+  uint4 q[4];
+};
+template <>
+struct RawBlock<2> {  // FP8 codes: 8 per row, 8 bytes
+  uint2 q[4];
+};
+
 template <int IT, bool VEC>
-__device__ __forceinline__ void stage_load(
+__device__ __forceinline__ void stage_issue(
     const typename QIn<IT>::T* __restrict__ x, int64_t ld, int64_t d,
-    int64_t gcol, int64_t row, int64_t i_end, bool full, const uint16_t* dec8,
-    uint32_t (&xr)[4][4]) {
+    int64_t gcol, int64_t row, int64_t i_end, RawBlock<IT>& raw) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    int64_t gi = row + u;
-    const bool ok = full || gi < i_end;
-    if (!ok) gi = i_end - 1;
+    const int64_t gi = row + u < i_end ? row + u : i_end - 1;
     const typename QIn<IT>::T* p = x + gi * ld + gcol;
+    if constexpr (VEC) {
+      if constexpr (IT == 1)
+        raw.q[u] = *reinterpret_cast<const uint4*>(p);
+      else
+        raw.q[u] = *reinterpret_cast<const uint2*>(p);
+    } else {
+      uint32_t e8[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t c = gcol + e < d ? e : 0;
+        e8[e] = p[c];
+      }
+      if constexpr (IT == 1) {
+        raw.q[u] = make_uint4(e8[0] | (e8[1] << 16), e8[2] | (e8[3] << 16),
+                              e8[4] | (e8[5] << 16), e8[6] | (e8[7] << 16));
+      } else {
+        raw.q[u] = make_uint2(e8[0] | (e8[1] << 8) | (e8[2] << 16) | (e8[3] << 24),
+                              e8[4] | (e8[5] << 8) | (e8[6] << 16) | (e8[7] << 24));
+      }
+    }
+  }
+}
+
+// nvalid = rows of the block inside the slice (i_end - row, clamped to 0..4)
+template <int IT>
+__device__ __forceinline__ void stage_unpack(const RawBlock<IT>& raw,
+                                             int64_t nvalid,
+                                             const uint16_t* dec8,
+                                             uint32_t (&xr)[4][4]) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
     uint32_t v4[4];
     if constexpr (IT == 1) {
-      if constexpr (VEC) {
-        const uint4 q = *reinterpret_cast<const uint4*>(p);
-        v4[0] = q.x;
-        v4[1] = q.y;
-        v4[2] = q.z;
-        v4[3] = q.w;
-      } else {
-        uint32_t e8[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int64_t c = gcol + e < d ? e : 0;
-          e8[e] = p[c];
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) v4[v] = e8[2 * v] | (e8[2 * v + 1] << 16);
-      }
+      v4[0] = raw.q[u].x;
+      v4[1] = raw.q[u].y;
+      v4[2] = raw.q[u].z;
+      v4[3] = raw.q[u].w;
     } else {
-      uint32_t b8[8];
-      if constexpr (VEC) {
-        const uint2 q = *reinterpret_cast<const uint2*>(p);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          b8[e] = (q.x >> (8 * e)) & 0xFFu;
-          b8[4 + e] = (q.y >> (8 * e)) & 0xFFu;
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int64_t c = gcol + e < d ? e : 0;
-          b8[e] = p[c];
-        }
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t w = v < 2 ? raw.q[u].x : raw.q[u].y;
+        const int sh = 16 * (v & 1);
+        v4[v] = static_cast<uint32_t>(dec8[(w >> sh) & 0xFFu]) |
+                (static_cast<uint32_t>(dec8[(w >> (sh + 8)) & 0xFFu]) << 16);
       }
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        v4[v] = static_cast<uint32_t>(dec8[b8[2 * v]]) |
-                (static_cast<uint32_t>(dec8[b8[2 * v + 1]]) << 16);
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) xr[u][v] = ok ? v4[v] : 0u;
+    for (int v = 0; v < 4; ++v) xr[u][v] = u < nvalid ? v4[v] : 0u;
   }
 }
 
@@ -337,25 +356,26 @@ __global__ void __launch_bounds__(kQThreads)
   // column maxima (when colmax is given): the nrt row-tile workgroups of a
   // slice take turns, step s by the workgroup with s mod nrt = rt
   uint32_t mx[4] = {0u, 0u, 0u, 0u};
-  uint32_t xr[4][4];
+  // rows are loaded two steps ahead (two raw buffers, steps taken in pairs
+  // so that each buffer keeps its registers)
+  RawBlock<IT> ra, rb;
   uint32_t gw[4];
   __syncthreads();  // tables in LDS
-  stage_load<IT, VEC>(x, ld, d, gcol, i_begin + 4 * rg, i_end,
-                      i_begin + kQK <= i_end, dec8, xr);
+  stage_issue<IT, VEC>(x, ld, d, gcol, i_begin + 4 * rg, i_end, ra);
+  stage_issue<IT, VEC>(x, ld, d, gcol, i_begin + kQK + 4 * rg, i_end, rb);
   draw8(static_cast<uint64_t>(i_begin >> 3) + gq, jctr, sk0, sk1, tab, gw);
 
-  int step = 0;
-  for (int64_t k0 = i_begin; k0 < i_end; k0 += kQK, ++step) {
-    if (colmax && step % nrt == rt) stage_max(xr, mx);
+  auto step = [&](int64_t k0, int st, RawBlock<IT>& raw) {
+    uint32_t xr[4][4];
+    stage_unpack<IT>(raw, i_end - (k0 + 4 * rg), dec8, xr);
+    if (colmax && st % nrt == rt) stage_max(xr, mx);
     __syncthreads();  // the previous step's operands have been read
     stage_store(XT, 8 * cc, 4 * rg, xr);
     *reinterpret_cast<uint4*>(&GT[jr * kQP + 8 * gq]) =
         make_uint4(gw[0], gw[1], gw[2], gw[3]);
     __syncthreads();
-    const bool more = k0 + kQK < i_end;
-    if (more)
-      stage_load<IT, VEC>(x, ld, d, gcol, k0 + kQK + 4 * rg, i_end,
-                          k0 + 2 * kQK <= i_end, dec8, xr);
+    // two steps ahead (past the slice: rows clamped, never used)
+    stage_issue<IT, VEC>(x, ld, d, gcol, k0 + 2 * kQK + 4 * rg, i_end, raw);
 #pragma unroll
     for (int kh = 0; kh < 2; ++kh) {
       bf16x8 av[2], bv[4];
@@ -374,9 +394,13 @@ __global__ void __launch_bounds__(kQThreads)
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b],
                                                               acc[a][b], 0, 0, 0);
     }
-    if (more)
-      draw8(static_cast<uint64_t>((k0 + kQK) >> 3) + gq, jctr, sk0, sk1, tab,
-            gw);
+    draw8(static_cast<uint64_t>((k0 + kQK) >> 3) + gq, jctr, sk0, sk1, tab,
+          gw);
+  };
+  int st = 0;
+  for (int64_t k0 = i_begin; k0 < i_end; k0 += 2 * kQK, st += 2) {
+    step(k0, st, ra);
+    if (k0 + kQK < i_end) step(k0 + kQK, st + 1, rb);
   }
   if (colmax) flush_max(mx, rg, col0 + 8 * cc, d, cs, colmax, nonfinite);
 
@@ -445,18 +469,20 @@ __global__ void __launch_bounds__(kQThreads)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.0f;
 
-  uint32_t xr[4][4];
+  RawBlock<IT> ra, rb;
   __syncthreads();  // dec8
-  if (stager)
-    stage_load<IT, VEC>(x, ld, d, gcol, i_begin + 4 * rg, i_end,
-                        i_begin + kQK <= i_end, dec8, xr);
-  for (int64_t k0 = i_begin; k0 < i_end; k0 += kQK) {
+  if (stager) {
+    stage_issue<IT, VEC>(x, ld, d, gcol, i_begin + 4 * rg, i_end, ra);
+    stage_issue<IT, VEC>(x, ld, d, gcol, i_begin + kQK + 4 * rg, i_end, rb);
+  }
+  auto step = [&](int64_t k0, RawBlock<IT>& raw) {
+    uint32_t xr[4][4];
+    if (stager) stage_unpack<IT>(raw, i_end - (k0 + 4 * rg), dec8, xr);
     __syncthreads();
     if (stager) stage_store(T, 8 * cc, 4 * rg, xr);
     __syncthreads();
-    if (stager && k0 + kQK < i_end)
-      stage_load<IT, VEC>(x, ld, d, gcol, k0 + kQK + 4 * rg, i_end,
-                          k0 + 2 * kQK <= i_end, dec8, xr);
+    if (stager)
+      stage_issue<IT, VEC>(x, ld, d, gcol, k0 + 2 * kQK + 4 * rg, i_end, raw);
 #pragma unroll
     for (int kh = 0; kh < 2; ++kh) {
       bf16x8 av[2], bv[4];
@@ -475,6 +501,10 @@ __global__ void __launch_bounds__(kQThreads)
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b],
                                                               acc[a][b], 0, 0, 0);
     }
+  };
+  for (int64_t k0 = i_begin; k0 < i_end; k0 += 2 * kQK) {
+    step(k0, ra);
+    if (k0 + kQK < i_end) step(k0 + kQK, rb);
   }
   float* P = partial + sp * d * d;
   const int64_t a0 = static_cast<int64_t>(ta) * kGB, b0 = static_cast<int64_t>(tb) * kGB;

@@ -2,10 +2,11 @@
 // d a multiple of 16 up to 512 and k <= 64: the pass that reads X once per
 // job, so it is priced against HBM.
 //
-// M (d x 64, zero past k) enters the BF16 MFMA as two BF16 parts,
-// Mh = bf16(M) and Ml = bf16(M - Mh) (M to 2^-17 of each entry), held in LDS
-// for the whole kernel (2 x 64 x (d + 8) BF16, 133 KB at d = 512), so a
-// workgroup reads M once. X goes from HBM straight into MFMA operand
+// M (d x 64, zero past k) enters the BF16 MFMA as BF16 parts held in LDS
+// for the whole kernel, so a workgroup reads M once: three parts
+// Mh = bf16(M), Mm = bf16(M - Mh), Ml = bf16(M - Mh - Mm) (M to FP32
+// precision) while they fit, d <= 352 (138 KB); two, Mh and bf16(M - Mh)
+// (M to 2^-17 of each entry), for 352 < d <= 512 (133 KB at d = 512). X goes from HBM straight into MFMA operand
 // registers: for v_mfma_f32_32x32x16_bf16 lane l takes row l % 32 and 8
 // consecutive columns, which are 16 contiguous bytes of a row-major BF16 row
 // (8 bytes of FP8 codes, decoded through a 256-entry LDS table). A wave
@@ -24,6 +25,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kSQThreads = 512;  // eight waves
 constexpr int kSQHalf = 16;      // K-steps per half block
 constexpr int kSQMaxD = 512;     // largest d (two halves of 16 K-steps)
+constexpr int kSQMaxD3 = 352;    // largest d with three parts of M
+constexpr int kSQLds = 3 * 64 * (kSQMaxD3 + 8) > 2 * 64 * (kSQMaxD + 8)
+                           ? 3 * 64 * (kSQMaxD3 + 8)
+                           : 2 * 64 * (kSQMaxD + 8);
 
 __device__ __forceinline__ uint16_t bf16_bits_rne(float f) {
   uint32_t u = __float_as_uint(f);
@@ -44,6 +49,24 @@ __global__ void split_m2_kernel(const double* __restrict__ m64, int64_t d,
                               static_cast<uint32_t>(hb) << 16));
   mh[c * d + j] = hb;
   ml[c * d + j] = bf16_bits_rne(static_cast<float>(rest));
+}
+
+// Mh, Mm, Ml by column: Mh = bf16(M), Mm = bf16(M - Mh), Ml = bf16(M - Mh - Mm)
+__global__ void split_m3_kernel(const double* __restrict__ m64, int64_t d,
+                                int64_t k, uint16_t* __restrict__ mh,
+                                uint16_t* __restrict__ mm,
+                                uint16_t* __restrict__ ml) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= 64 * d) return;
+  const int64_t c = e / d, j = e % d;
+  double v = c < k ? m64[j * k + c] : 0.0;
+  const uint16_t hb = bf16_bits_rne(static_cast<float>(v));
+  v -= static_cast<double>(__uint_as_float(static_cast<uint32_t>(hb) << 16));
+  const uint16_t mb = bf16_bits_rne(static_cast<float>(v));
+  v -= static_cast<double>(__uint_as_float(static_cast<uint32_t>(mb) << 16));
+  mh[c * d + j] = hb;
+  mm[c * d + j] = mb;
+  ml[c * d + j] = bf16_bits_rne(static_cast<float>(v));
 }
 
 template <int IT>
@@ -107,16 +130,19 @@ __device__ __forceinline__ bf16x8 operand(const Raw<IT>& r,
   }
 }
 
-template <int IT>
+// NP parts of M: mp[0] = Mh, mp[NP - 1] = the smallest part
+template <int IT, int NP>
 __global__ void __launch_bounds__(kSQThreads)
     score_q_kernel(const typename SQIn<IT>::T* __restrict__ x, int64_t n,
                    int64_t d, int64_t ld, const uint16_t* __restrict__ mh,
+                   const uint16_t* __restrict__ mm,
                    const uint16_t* __restrict__ ml, float* __restrict__ out) {
-  __shared__ __attribute__((aligned(16))) uint16_t sm[128 * (kSQMaxD + 8) + 256];
+  __shared__ __attribute__((aligned(16))) uint16_t sm[kSQLds + 256];
   const int pm = static_cast<int>(d) + 8;  // LDS pitch of M (elements)
   uint16_t* Mh = sm;
-  uint16_t* Ml = sm + 64 * pm;
-  uint16_t* dec8 = sm + 128 * pm;
+  uint16_t* Mm = sm + 64 * pm;             // NP == 3 only
+  uint16_t* Ml = sm + (NP - 1) * 64 * pm;
+  uint16_t* dec8 = sm + NP * 64 * pm;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int l32 = lane & 31, h = lane >> 5;
   const int steps = static_cast<int>(d / 16);
@@ -127,6 +153,9 @@ __global__ void __launch_bounds__(kSQThreads)
         *reinterpret_cast<const uint4*>(&mh[c * d + j]);
     *reinterpret_cast<uint4*>(&Ml[c * pm + j]) =
         *reinterpret_cast<const uint4*>(&ml[c * d + j]);
+    if (NP == 3)
+      *reinterpret_cast<uint4*>(&Mm[c * pm + j]) =
+          *reinterpret_cast<const uint4*>(&mm[c * d + j]);
   }
   if (IT == 2 && t < 256) dec8[t] = static_cast<uint16_t>(e4m3_to_bf16(t));
   __syncthreads();
@@ -169,8 +198,12 @@ __global__ void __launch_bounds__(kSQThreads)
         for (int ct = 0; ct < 2; ++ct) {
           const int o = (32 * ct + l32) * pm + 16 * s + 8 * h;
           const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Ml[o]);
-          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Mh[o]);
           acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, acc[ct], 0, 0, 0);
+          if constexpr (NP == 3) {
+            const bf16x8 bm = *reinterpret_cast<const bf16x8*>(&Mm[o]);
+            acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bm, acc[ct], 0, 0, 0);
+          }
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Mh[o]);
           acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, acc[ct], 0, 0, 0);
         }
       }
@@ -189,8 +222,12 @@ __global__ void __launch_bounds__(kSQThreads)
         for (int ct = 0; ct < 2; ++ct) {
           const int o = (32 * ct + l32) * pm + 16 * (kSQHalf + s) + 8 * h;
           const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Ml[o]);
-          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Mh[o]);
           acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, acc[ct], 0, 0, 0);
+          if constexpr (NP == 3) {
+            const bf16x8 bm = *reinterpret_cast<const bf16x8*>(&Mm[o]);
+            acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bm, acc[ct], 0, 0, 0);
+          }
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Mh[o]);
           acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, acc[ct], 0, 0, 0);
         }
       }
@@ -227,26 +264,39 @@ bool score_q_ok(const void* x, int dtype, int format, int64_t d, int64_t ld,
 }
 
 size_t score_q_scratch_bytes(int64_t d) {
-  return static_cast<size_t>(2 * 64 * d) * sizeof(uint16_t);
+  return static_cast<size_t>(3 * 64 * d) * sizeof(uint16_t);
 }
 
 void launch_score_q(const void* x, int dtype, int64_t n, int64_t d, int64_t ld,
                     const double* m64, int64_t k, void* scratch, float* scores,
                     hipStream_t s) {
   uint16_t* mh = static_cast<uint16_t*>(scratch);
-  uint16_t* ml = mh + 64 * d;
-  split_m2_kernel<<<static_cast<unsigned>((64 * d + 255) / 256), 256, 0, s>>>(
-      m64, d, k, mh, ml);
+  uint16_t* mm = mh + 64 * d;
+  uint16_t* ml = mm + 64 * d;
+  const bool three = d <= kSQMaxD3;
+  const unsigned gs = static_cast<unsigned>((64 * d + 255) / 256);
+  if (three)
+    split_m3_kernel<<<gs, 256, 0, s>>>(m64, d, k, mh, mm, ml);
+  else
+    split_m2_kernel<<<gs, 256, 0, s>>>(m64, d, k, mh, ml);
   const int64_t nblk = (n + 31) / 32;
   int64_t grid = (nblk + 7) / 8;
   if (grid > 256) grid = 256;
+  const unsigned g = static_cast<unsigned>(grid);
   prof_begin(kKScore, s);
-  if (dtype == 2)
-    score_q_kernel<1><<<static_cast<unsigned>(grid), kSQThreads, 0, s>>>(
-        static_cast<const uint16_t*>(x), n, d, ld, mh, ml, scores);
-  else
-    score_q_kernel<2><<<static_cast<unsigned>(grid), kSQThreads, 0, s>>>(
-        static_cast<const uint8_t*>(x), n, d, ld, mh, ml, scores);
+  if (dtype == 2) {
+    const uint16_t* xp = static_cast<const uint16_t*>(x);
+    if (three)
+      score_q_kernel<1, 3><<<g, kSQThreads, 0, s>>>(xp, n, d, ld, mh, mm, ml, scores);
+    else
+      score_q_kernel<1, 2><<<g, kSQThreads, 0, s>>>(xp, n, d, ld, mh, mm, ml, scores);
+  } else {
+    const uint8_t* xp = static_cast<const uint8_t*>(x);
+    if (three)
+      score_q_kernel<2, 3><<<g, kSQThreads, 0, s>>>(xp, n, d, ld, mh, mm, ml, scores);
+    else
+      score_q_kernel<2, 2><<<g, kSQThreads, 0, s>>>(xp, n, d, ld, mh, mm, ml, scores);
+  }
   prof_end(kKScore, s);
 }
 

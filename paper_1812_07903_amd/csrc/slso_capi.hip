@@ -293,7 +293,7 @@ int check_sketch_kind(slso_ctx* c, const slso_options& o, int64_t r,
     if (r > srht_rows_padded(X->n))
       return set_err(c, SLSO_EINVAL, "SRHT needs r <= n rounded up to a power of two");
   }
-  if ((o.flags & ~SLSO_OPT_SVD_RANK) != 0)
+  if ((o.flags & ~(SLSO_OPT_SVD_RANK | SLSO_OPT_EPS_HAT)) != 0)
     return set_err(c, SLSO_EINVAL, "unknown option flags");
   if (o.sketch == SLSO_OSNAP) {
     const int s = sketch_nnz(o);
@@ -358,6 +358,8 @@ size_t leverage_ws_bytes(const slso_matrix* X, int64_t r, int64_t k,
   const int nnz = sketch_nnz(o);
   const bool gauss = o.sketch == SLSO_GAUSSIAN;
   const bool refine = o.refine == 1;
+  // the refinement's Gram and Cholesky also run for the distortion report
+  const bool gram = refine || (o.flags & SLSO_OPT_EPS_HAT) != 0;
   Sizer z;
   if (nnz > 0) {
     size_sketch_bufs(z, n * nnz, r);
@@ -370,16 +372,21 @@ size_t leverage_ws_bytes(const slso_matrix* X, int64_t r, int64_t k,
   z.take<int>(64);                 // flags
   z.take<double>(8);               // diag stats
   z.take<double>(r * d);           // sketch
-  z.take<char>(gemm_partial_bytes(X, r, gauss, refine));
+  z.take<char>(gemm_partial_bytes(X, r, gauss, gram));
   z.take<char>(qr_scratch_bytes(r, d));
   z.take<double>(d * d);           // R_D of the sketch
-  if (refine)
+  if (gram)
     for (int i = 0; i < 3; ++i) z.take<double>(d * d);  // G, R1, refined R
   z.take<double>(d * kk);          // Pi_2 -> M'
   z.take<double>(d * kk);          // M (FP64)
   z.take<float>(d * kk);           // M (FP32)
   z.take<char>(scores_partial_bytes(n, d, kk, X->format, X->dtype));
-  z.take<char>(trsm_blocked_scratch(d, refine ? d : kk));
+  z.take<char>(trsm_blocked_scratch(d, gram ? d : kk));
+  if (o.flags & SLSO_OPT_EPS_HAT) {  // Jacobi SVD of R1
+    z.take<char>(jacobi_svd_scratch_bytes(d));
+    z.take<double>(d * d);
+    z.take<double>(d);
+  }
   return z.off;
 }
 
@@ -402,10 +409,12 @@ int check_leverage(slso_ctx* c, const slso_matrix* X, int64_t r, int64_t k,
   if ((st = check_sketch_kind(c, *o, r, X))) return st;
   if (o->refine != 0 && o->refine != 1)
     return set_err(c, SLSO_EINVAL, "refine must be 0 or 1");
-  if ((o->sketch == SLSO_GAUSSIAN || o->refine == 1) && !mfma_input(X))
+  if ((o->sketch == SLSO_GAUSSIAN || o->refine == 1 ||
+       (o->flags & SLSO_OPT_EPS_HAT) != 0) &&
+      !mfma_input(X))
     return set_err(c, SLSO_EUNSUPPORTED,
-                   "the Gaussian sketch and the refinement take dense F32, "
-                   "BF16 or FP8 input");
+                   "the Gaussian sketch, the refinement and the distortion "
+                   "report take dense F32, BF16 or FP8 input");
   return SLSO_OK;
 }
 
@@ -710,6 +719,10 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   const bool gauss = o.sketch == SLSO_GAUSSIAN;
   const int nnz = sketch_nnz(o);
   const bool refine = o.refine == 1;
+  const bool want_eps = (o.flags & SLSO_OPT_EPS_HAT) != 0;
+  // the refinement's Gram and Cholesky run for the refinement and for the
+  // distortion report
+  const bool gram = refine || want_eps;
   const bool fp8 = X->dtype == SLSO_FP8_E4M3;
   const double tol = o.rank_tol == 0.0 ? 1e-10 : o.rank_tol;
   const int64_t n = X->n, d = X->d;
@@ -717,7 +730,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   SLSO_HIP(c, hipSetDevice(c->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
 
-  const size_t gemm_part = gemm_partial_bytes(X, r, gauss, refine);
+  const size_t gemm_part = gemm_partial_bytes(X, r, gauss, gram);
   Sizer z;
   z.off = leverage_ws_bytes(X, r, k, o);
   if ((st = ensure_ws(c, z.off))) return st;
@@ -741,7 +754,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   void* qws = a.take<char>(qr_scratch_bytes(r, d));
   double* RS = a.take<double>(d * d);
   double *G = nullptr, *R1 = nullptr, *RR = nullptr;
-  if (refine) {
+  if (gram) {
     G = a.take<double>(d * d);
     R1 = a.take<double>(d * d);
     RR = a.take<double>(d * d);
@@ -750,7 +763,14 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   double* m64 = a.take<double>(d * kk);
   float* m32 = a.take<float>(d * kk);
   double* part = a.take<double>(scores_partial_bytes(n, d, kk, X->format, X->dtype) / 8);
-  double* tws = a.take<double>(trsm_blocked_scratch(d, refine ? d : kk) / 8);
+  double* tws = a.take<double>(trsm_blocked_scratch(d, gram ? d : kk) / 8);
+  void* jws = nullptr;
+  double *jv = nullptr, *jsig = nullptr;
+  if (want_eps) {
+    jws = a.take<char>(jacobi_svd_scratch_bytes(d));
+    jv = a.take<double>(d * d);
+    jsig = a.take<double>(d);
+  }
 
   // Dense F32 / BF16 / FP8 input: the column maxima are taken in the
   // CountSketch's own pass over X, and D is applied by the QR as it reads the
@@ -839,7 +859,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   // refinement, which needs R_S
   auto post = [&](bool r_formed) {
     if (r_formed) launch_diag_stats(RS, d, dstat, s);
-    if (refine) {
+    if (gram) {
       launch_fill_i32(flags + 1, 1, 0, s);
       launch_gram(X->values, X->dtype, n, d, X->ld, X->col_scale, dscale, gpart,
                   G, s);
@@ -873,7 +893,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   // should that fail too, column by column.
   // Without the refinement R itself is only needed if the rank screen trips:
   // Cholesky-QR2 then keeps R^{-1} in factored form and applies it to Pi_2.
-  const bool want_r = refine;
+  const bool want_r = gram;
   bool cholqr2 = true, second = false, r_formed = want_r;
   int32_t info_flags = 0;
   sketch();
@@ -925,7 +945,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   // 5. M = D pinv(R_D) Pi_2 (Algorithm 2 step 3 / Algorithm 3 step 4)
   int64_t rank = d;
   if (full) {
-    if (cholqr2 && !refine)
+    if (cholqr2 && !want_r)
       qr_apply_rinv(r, d, qws, second, pi, kk, s);
     else
       solve_upper(R, d, pi, kk, s, tws);
@@ -949,12 +969,29 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
                 X->col_idx, X->col_scale, X->row_scale, m64, m32, kk, scores, s,
                 part);
   if ((st = check_launch(c, "slso_leverage: scores"))) return st;
+  // 7. realised distortion (Def. 1 / Thm. 1): R = R1 R_S is the R of X D, so
+  // S U = Q_S R_S R^-1 = Q_S R1^-1 and sigma(S U) = 1 / sigma(R1)
+  double eps_hat = std::nan("");
+  if (want_eps && fl[1] == 0) {
+    if (jacobi_svd(G, d, jsig, jv, jws, s) != 0)
+      return set_err(c, SLSO_EDEVICE, "Jacobi SVD of R1 failed");
+    double* hs = reinterpret_cast<double*>(hb + 2048);
+    SLSO_HIP(c, hipMemcpyAsync(hs, jsig, sizeof(double), hipMemcpyDeviceToHost, s));
+    SLSO_HIP(c, hipMemcpyAsync(hs + 1, jsig + d - 1, sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    SLSO_HIP(c, hipStreamSynchronize(s));
+    if (hs[1] > 0.0) {
+      const double su_max = 1.0 / hs[1], su_min = 1.0 / hs[0];
+      eps_hat = std::max(su_max * su_max - 1.0, 1.0 - su_min * su_min);
+    }
+  }
   if (info) {
     info->rank = rank;
     info->screen_full = full ? 1 : 0;
     info->flags = info_flags;
     info->diag_min = dmin;
     info->diag_max = dmax;
+    info->eps_hat = eps_hat;
   }
   return rank < d ? SLSO_RANK_DEFICIENT : SLSO_OK;
 }

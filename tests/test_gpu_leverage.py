@@ -294,3 +294,34 @@ def test_calls_on_two_streams_share_the_workspace_in_order(slso, ctx):
             assert np.array_equal(host(outs[i]).view(np.uint32),
                                   alone[i][0].view(np.uint32)), (rep, i)
             assert np.array_equal(host(perms[i]), alone[i][1]), (rep, i)
+
+
+@pytest.mark.parametrize("kind,sketch,refine,r,tol", [
+    ("f32", "countsketch", False, 1024, 1e-8),
+    ("f32", "countsketch", True, 1024, 1e-8),
+    ("f32", "gaussian", False, 256, 1e-5),
+    ("bf16", "gaussian", True, 512, 1e-4)])
+def test_eps_hat_matches_oracle(slso, ctx, kind, sketch, refine, r, tol):
+    """Realised distortion of the sketch on range(X) (Def. 1 / Thm. 1): the
+    library's 1 / sigma(R1) route against the oracle's sigma(S U). FP32
+    input: the Gram is exact (FP64 MFMA), and so is the CountSketch; the
+    FP32 Gaussian sketch carries FP32 sums (about 1e-7 of each entry); BF16:
+    FP32 sums of the Gram as well."""
+    x64 = synth.config0(n=20011, d=48, seed=41)
+    if kind == "f32":
+        x32 = x64.astype(np.float32)
+        xin, xval, prec = dev(x32), x32.astype(np.float64), "f32"
+    else:
+        b = synth.to_bf16_bits(x64)
+        xin = dev(b.view(np.int16)).view(torch.bfloat16)
+        xval, prec = synth.bf16_bits_to_f64(b), "bf16"
+    sk = slso.GAUSSIAN if sketch == "gaussian" else slso.COUNTSKETCH
+    got, info = ctx.leverage(xin, 17, r, 16, sketch=sk, refine=refine,
+                             eps_hat=True)
+    ref = olv.realised_distortion(xval, 17, r, kind=sketch, precision=prec)
+    print(f"[eps_hat {kind} {sketch} refine={refine}] gpu={info['eps_hat']:.10f}"
+          f" oracle={ref:.10f}", flush=True)
+    assert abs(info["eps_hat"] - ref) <= tol * max(1.0, ref)
+    # the report changes nothing else: same scores as without it
+    base, _ = ctx.leverage(xin, 17, r, 16, sketch=sk, refine=refine)
+    np.testing.assert_allclose(host(got), host(base), rtol=1e-6)
