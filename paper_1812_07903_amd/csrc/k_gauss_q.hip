@@ -18,14 +18,15 @@
 // Tiling: one workgroup of eight waves owns 128 sketch rows x 512 columns of
 // one slice of data rows, so each entry of G is generated once per column
 // chunk of 512 (once in all for d <= 512) and feeds 2 x 512 flops. A step
-// takes 32 data rows: each thread draws one Philox block (8 entries of one
-// sketch row) and stages a 4-row x 8-column block of X, transposed in
-// registers so that each column's 4 rows are one 8-byte LDS write. Wave w
-// owns sketch rows 64 (w & 1) .. + 63 and columns 128 (w >> 1) .. + 127 as
-// 2 x 4 MFMA blocks of 32 x 32 (v_mfma_f32_32x32x16_bf16). The next step's
-// entries are drawn while the current step's products run, so the
-// generator's VALU work overlaps the matrix unit, and rows are loaded two
-// steps ahead.
+// takes 16 data rows through one of two LDS buffers: every thread stages a
+// 2-row x 8-column block of X (one 4-byte LDS write per column), half the
+// threads draw one Philox block each (8 entries of one sketch row), and wave
+// w multiplies sketch rows 64 (w & 1) .. + 63 by columns 128 (w >> 1) ..
+// + 127 as 2 x 4 MFMA blocks of 32 x 32 (v_mfma_f32_32x32x16_bf16). While a
+// step's products run, the next step is written into the other buffer, rows
+// three steps ahead are loaded and the entries two steps ahead drawn, so the
+// generator's VALU work, the loads and the matrix unit overlap, with one
+// barrier per step.
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -47,9 +48,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kQR = 128;        // sketch rows per workgroup
 constexpr int kQD = 512;        // columns per workgroup
-constexpr int kQK = 32;         // data rows per step
-constexpr int kQP = 40;         // LDS pitch (elements) along the data rows
+constexpr int kQK = 16;         // data rows per step of the Gram pass
+constexpr int kQP = 24;         // LDS pitch (elements) of its 16-row tiles
 constexpr int kQThreads = 512;  // eight waves
+constexpr int kSK = 32;         // data rows per step of the sketch
 
 // ---- host: the quantile tables ---------------------------------------------
 // erfinv(p) for 0 < p < 1: the Winitzki estimate refined by Newton steps on
@@ -116,18 +118,25 @@ struct QIn<2> {  // FP8-e4m3 codes
   using T = uint8_t;
 };
 
-// 8 entries of sketch row j for data rows 8 q .. 8 q + 7, as 4 words of
-// BF16 pairs (lower data row in the low half)
-__device__ __forceinline__ void draw8(uint64_t q, uint32_t j, uint32_t k0,
-                                      uint32_t k1, const uint16_t* tab,
-                                      uint32_t (&gw)[4]) {
+// The Philox block of sketch row j for data rows 8 q .. 8 q + 7
+__device__ __forceinline__ void draw_raw(uint64_t q, uint32_t j, uint32_t k0,
+                                         uint32_t k1, uint32_t (&o4)[4]) {
   U4 c{static_cast<uint32_t>(q), static_cast<uint32_t>(q >> 32), j,
        static_cast<uint32_t>(kStreamGaussQ)};
   const U4 o = philox10(c, k0, k1);
-  const uint32_t w4[4] = {o.x, o.y, o.z, o.w};
+  o4[0] = o.x;
+  o4[1] = o.y;
+  o4[2] = o.z;
+  o4[3] = o.w;
+}
+
+// its 8 entries as 4 words of BF16 pairs (lower data row in the low half)
+__device__ __forceinline__ void entries8(const uint32_t (&o4)[4],
+                                         const uint16_t* tab,
+                                         uint32_t (&gw)[4]) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const uint32_t v = w4[u];
+    const uint32_t v = o4[u];
     const uint32_t lo = tab[v & 0x7FFFu];
     const uint32_t hi = tab[(v >> 16) & 0x7FFFu];
     gw[u] = (lo | (hi << 16)) | (v & 0x80008000u);
@@ -140,113 +149,6 @@ __device__ __forceinline__ uint32_t e4m3_bf16_bits(uint32_t q) {
 }
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
-// ---- staging of X blocks (shared by the sketch and the Gram pass) ------------
-// A thread stages rows row .. row + 3 and columns gcol .. gcol + 7 of X. The
-// loads are issued unconditionally (rows past i_end read row i_end - 1) into
-// raw registers and only used a step or two later, so nothing waits for
-// them at the issue point; rows at or past i_end are zeroed when the block
-// is unpacked (stage_unpack) into BF16 pairs xr[u][v] = row + u, columns
-// 2 v (low half) and 2 v + 1. FP8 codes are decoded through the 256-entry
-// table dec8 (exact in BF16).
-template <int IT>
-struct RawBlock;
-template <>
-struct RawBlock<1> {  // BF16: 8 elements per row, 16 bytes
-  uint4 q[4];
-};
-template <>
-struct RawBlock<2> {  // FP8 codes: 8 per row, 8 bytes
-  uint2 q[4];
-};
-
-template <int IT, bool VEC>
-__device__ __forceinline__ void stage_issue(
-    const typename QIn<IT>::T* __restrict__ x, int64_t ld, int64_t d,
-    int64_t gcol, int64_t row, int64_t i_end, RawBlock<IT>& raw) {
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int64_t gi = row + u < i_end ? row + u : i_end - 1;
-    const typename QIn<IT>::T* p = x + gi * ld + gcol;
-    if constexpr (VEC) {
-      if constexpr (IT == 1)
-        raw.q[u] = *reinterpret_cast<const uint4*>(p);
-      else
-        raw.q[u] = *reinterpret_cast<const uint2*>(p);
-    } else {
-      uint32_t e8[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t c = gcol + e < d ? e : 0;
-        e8[e] = p[c];
-      }
-      if constexpr (IT == 1) {
-        raw.q[u] = make_uint4(e8[0] | (e8[1] << 16), e8[2] | (e8[3] << 16),
-                              e8[4] | (e8[5] << 16), e8[6] | (e8[7] << 16));
-      } else {
-        raw.q[u] = make_uint2(e8[0] | (e8[1] << 8) | (e8[2] << 16) | (e8[3] << 24),
-                              e8[4] | (e8[5] << 8) | (e8[6] << 16) | (e8[7] << 24));
-      }
-    }
-  }
-}
-
-// nvalid = rows of the block inside the slice (i_end - row, clamped to 0..4)
-template <int IT>
-__device__ __forceinline__ void stage_unpack(const RawBlock<IT>& raw,
-                                             int64_t nvalid,
-                                             const uint16_t* dec8,
-                                             uint32_t (&xr)[4][4]) {
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    uint32_t v4[4];
-    if constexpr (IT == 1) {
-      v4[0] = raw.q[u].x;
-      v4[1] = raw.q[u].y;
-      v4[2] = raw.q[u].z;
-      v4[3] = raw.q[u].w;
-    } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const uint32_t w = v < 2 ? raw.q[u].x : raw.q[u].y;
-        const int sh = 16 * (v & 1);
-        v4[v] = static_cast<uint32_t>(dec8[(w >> sh) & 0xFFu]) |
-                (static_cast<uint32_t>(dec8[(w >> (sh + 8)) & 0xFFu]) << 16);
-      }
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) xr[u][v] = u < nvalid ? v4[v] : 0u;
-  }
-}
-
-// The staged block into a K-contiguous LDS tile (pitch kQP): column col + e
-// gets its four rows at k .. k + 3 as one 8-byte write.
-__device__ __forceinline__ void stage_store(uint16_t* T, int col, int k,
-                                            const uint32_t (&xr)[4][4]) {
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const uint32_t sel = (e & 1) ? 0x07060302u : 0x05040100u;
-    uint2 v;
-    v.x = __builtin_amdgcn_perm(xr[1][e >> 1], xr[0][e >> 1], sel);
-    v.y = __builtin_amdgcn_perm(xr[3][e >> 1], xr[2][e >> 1], sel);
-    *reinterpret_cast<uint2*>(&T[(col + e) * kQP + k]) = v;
-  }
-}
-
-// |x| of the block folded into per-column maxima of BF16 bit patterns
-// (packed pairs like xr): for non-negative values the pattern order is the
-// numeric order, and Inf / NaN patterns (>= 0x7F80) exceed every finite one
-__device__ __forceinline__ void stage_max(const uint32_t (&xr)[4][4],
-                                          uint32_t (&mx)[4]) {
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const u16x2 a = __builtin_bit_cast(u16x2, mx[v]);
-      const u16x2 b = __builtin_bit_cast(u16x2, xr[u][v] & 0x7FFF7FFFu);
-      mx[v] = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(a, b));
-    }
-}
 
 // Column maxima of the eight row groups of a column chunk (lanes 8 c ..
 // 8 c + 7 of a wave) into colmax (FP64 bit patterns, times |cs| for FP8
@@ -299,6 +201,198 @@ __device__ __forceinline__ void load_dec8(uint16_t* dec8, int t) {
   if (IT == 2 && t < 256) dec8[t] = static_cast<uint16_t>(e4m3_bf16_bits(t));
 }
 
+// ---- staging of X (shared by the sketch and the Gram pass) ------------------
+// A step takes 16 data rows; a thread stages rows row, row + 1 and columns
+// gcol .. gcol + 7 of X. The loads are issued unconditionally (rows past
+// i_end read row i_end - 1, in bounds) into raw registers and only used a
+// step or two later, so nothing waits for them at the issue point; rows at or
+// past i_end are zeroed when the block is unpacked (pair_unpack) into BF16
+// pairs xr[u][v] = row + u, columns 2 v (low half) and 2 v + 1. FP8 codes
+// are decoded through the 256-entry table dec8 (exact in BF16).
+template <int IT>
+struct RawPair;
+template <>
+struct RawPair<1> {
+  uint4 q[2];
+};
+template <>
+struct RawPair<2> {
+  uint2 q[2];
+};
+
+template <int IT, bool VEC>
+__device__ __forceinline__ void pair_issue(
+    const typename QIn<IT>::T* __restrict__ x, int64_t ld, int64_t d,
+    int64_t gcol, int64_t row, int64_t i_end, RawPair<IT>& raw) {
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int64_t gi = row + u < i_end ? row + u : i_end - 1;
+    const typename QIn<IT>::T* p = x + gi * ld + gcol;
+    if constexpr (VEC) {
+      if constexpr (IT == 1)
+        raw.q[u] = *reinterpret_cast<const uint4*>(p);
+      else
+        raw.q[u] = *reinterpret_cast<const uint2*>(p);
+    } else {
+      uint32_t e8[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t c = gcol + e < d ? e : 0;
+        e8[e] = p[c];
+      }
+      if constexpr (IT == 1) {
+        raw.q[u] = make_uint4(e8[0] | (e8[1] << 16), e8[2] | (e8[3] << 16),
+                              e8[4] | (e8[5] << 16), e8[6] | (e8[7] << 16));
+      } else {
+        raw.q[u] = make_uint2(e8[0] | (e8[1] << 8) | (e8[2] << 16) | (e8[3] << 24),
+                              e8[4] | (e8[5] << 8) | (e8[6] << 16) | (e8[7] << 24));
+      }
+    }
+  }
+}
+
+template <int IT>
+__device__ __forceinline__ void pair_unpack(const RawPair<IT>& raw,
+                                            int64_t nvalid,
+                                            const uint16_t* dec8,
+                                            uint32_t (&xr)[2][4]) {
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    uint32_t v4[4];
+    if constexpr (IT == 1) {
+      v4[0] = raw.q[u].x;
+      v4[1] = raw.q[u].y;
+      v4[2] = raw.q[u].z;
+      v4[3] = raw.q[u].w;
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t w = v < 2 ? raw.q[u].x : raw.q[u].y;
+        const int sh = 16 * (v & 1);
+        v4[v] = static_cast<uint32_t>(dec8[(w >> sh) & 0xFFu]) |
+                (static_cast<uint32_t>(dec8[(w >> (sh + 8)) & 0xFFu]) << 16);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xr[u][v] = u < nvalid ? v4[v] : 0u;
+  }
+}
+
+// |x| of the block folded into per-column maxima of BF16 bit patterns
+// (packed pairs like xr): for non-negative values the pattern order is the
+// numeric order, and Inf / NaN patterns (>= 0x7F80) exceed every finite one
+__device__ __forceinline__ void pair_max(const uint32_t (&xr)[2][4],
+                                         uint32_t (&mx)[4]) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const u16x2 a = __builtin_bit_cast(u16x2, mx[v]);
+      const u16x2 b = __builtin_bit_cast(u16x2, xr[u][v] & 0x7FFF7FFFu);
+      mx[v] = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(a, b));
+    }
+}
+
+// Rows k, k + 1 of a tile's columns 8 cc + e (e = 0..7, cc < NC) into a
+// K-contiguous tile of 8 NC slots (pitch kQP): column 8 cc + e goes to
+// slot NC e + cc, so that the 64 lanes of one store (eight chunks cc, eight
+// row pairs) fall on the banks two lanes per bank, where a slot per column
+// in order would put the eight chunks of a wave on the same banks
+template <int NC>
+__device__ __forceinline__ int q_slot_col(int slot) {
+  return 8 * (slot % NC) + slot / NC;
+}
+
+template <int NC>
+__device__ __forceinline__ void pair_store(uint16_t* T, int cc, int k,
+                                           const uint32_t (&xr)[2][4]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const uint32_t sel = (e & 1) ? 0x07060302u : 0x05040100u;
+    *reinterpret_cast<uint32_t*>(&T[(NC * e + cc) * kQP + k]) =
+        __builtin_amdgcn_perm(xr[1][e >> 1], xr[0][e >> 1], sel);
+  }
+}
+
+// ---- the sketch's 32-row tiles ------------------------------------------------
+// A slot (an X column or a sketch row) holds its 32 data rows contiguously as
+// four 8-element groups, group q stored at position q ^ ((slot >> 1) & 3):
+// the MFMA operand reads (16 bytes per lane, 32 consecutive slots, one group)
+// and the staging writes below then spread over all banks, without padding.
+__device__ __forceinline__ int qsw(int slot, int grp) {
+  return slot * kSK + 8 * (grp ^ ((slot >> 1) & 3));
+}
+
+// Four-row blocks: a thread stages rows row .. row + 3 and columns gcol ..
+// gcol + 7, loaded and masked as the two-row blocks above.
+template <int IT>
+struct RawQuad;
+template <>
+struct RawQuad<1> {
+  uint4 q[4];
+};
+template <>
+struct RawQuad<2> {
+  uint2 q[4];
+};
+
+template <int IT, bool VEC>
+__device__ __forceinline__ void quad_issue(
+    const typename QIn<IT>::T* __restrict__ x, int64_t ld, int64_t d,
+    int64_t gcol, int64_t row, int64_t i_end, RawQuad<IT>& raw) {
+  RawPair<IT> lo, hi;
+  pair_issue<IT, VEC>(x, ld, d, gcol, row, i_end, lo);
+  pair_issue<IT, VEC>(x, ld, d, gcol, row + 2, i_end, hi);
+  raw.q[0] = lo.q[0];
+  raw.q[1] = lo.q[1];
+  raw.q[2] = hi.q[0];
+  raw.q[3] = hi.q[1];
+}
+
+template <int IT>
+__device__ __forceinline__ void quad_unpack(const RawQuad<IT>& raw,
+                                            int64_t nvalid,
+                                            const uint16_t* dec8,
+                                            uint32_t (&xr)[4][4]) {
+  RawPair<IT> lo, hi;
+  lo.q[0] = raw.q[0];
+  lo.q[1] = raw.q[1];
+  hi.q[0] = raw.q[2];
+  hi.q[1] = raw.q[3];
+  uint32_t a[2][4], b[2][4];
+  pair_unpack<IT>(lo, nvalid, dec8, a);
+  pair_unpack<IT>(hi, nvalid - 2, dec8, b);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    xr[0][v] = a[0][v];
+    xr[1][v] = a[1][v];
+    xr[2][v] = b[0][v];
+    xr[3][v] = b[1][v];
+  }
+}
+
+// rows 4 rg .. 4 rg + 3 of columns 8 cc + e into slot NC e + cc of a 32-row
+// tile (one 8-byte write per column)
+template <int NC>
+__device__ __forceinline__ void quad_store(uint16_t* T, int cc, int rg,
+                                           const uint32_t (&xr)[4][4]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const uint32_t sel = (e & 1) ? 0x07060302u : 0x05040100u;
+    uint2 v;
+    v.x = __builtin_amdgcn_perm(xr[1][e >> 1], xr[0][e >> 1], sel);
+    v.y = __builtin_amdgcn_perm(xr[3][e >> 1], xr[2][e >> 1], sel);
+    *reinterpret_cast<uint2*>(&T[qsw(NC * e + cc, rg >> 1) + 4 * (rg & 1)]) = v;
+  }
+}
+
+// Steps of 32 data rows through two LDS buffers, every thread doing the same
+// work in every step: it writes the next step's block of X (four rows x
+// eight columns, transposed) and its Philox block of the next step's entries
+// (sketch row jr, data rows 8 g .. 8 g + 7) into the other buffer, issues the
+// loads for three steps ahead, draws its block for two steps ahead and
+// multiplies the current buffer; one barrier per step. With no branch in the
+// step, the generator's VALU work can issue between the MFMAs.
 template <int IT, bool VEC>
 __global__ void __launch_bounds__(kQThreads)
     gauss_q_kernel(const typename QIn<IT>::T* __restrict__ x, int64_t n,
@@ -308,8 +402,8 @@ __global__ void __launch_bounds__(kQThreads)
                    unsigned long long* __restrict__ colmax,
                    int* __restrict__ nonfinite) {
   __shared__ __attribute__((aligned(16))) uint16_t tab[kQCells];
-  __shared__ __attribute__((aligned(16))) uint16_t XT[kQD * kQP];
-  __shared__ __attribute__((aligned(16))) uint16_t GT[kQR * kQP];
+  __shared__ __attribute__((aligned(16))) uint16_t XT[2][kQD * kSK];
+  __shared__ __attribute__((aligned(16))) uint16_t GT[2][kQR * kSK];
   __shared__ uint16_t dec8[256];
   const int t = threadIdx.x;
   // consecutive logical ids share a slice of rows
@@ -323,6 +417,7 @@ __global__ void __launch_bounds__(kQThreads)
   const int64_t i_begin = sp * rows_per_split;
   int64_t i_end = i_begin + rows_per_split;
   if (i_end > n) i_end = n;
+  const int nsteps = static_cast<int>((i_end - i_begin + kSK - 1) / kSK);
 
   {
     const uint4* src = reinterpret_cast<const uint4*>(g_qtab[IT == 2 ? 1 : 0]);
@@ -336,8 +431,8 @@ __global__ void __launch_bounds__(kQThreads)
   // that are never stored)
   const int rg = t & 7, cc = t >> 3;
   const int64_t gcol = col0 + 8 * cc < d ? col0 + 8 * cc : 0;
-  // generation role: sketch row row0 + jr, data rows 8 gq .. 8 gq + 7
-  const int jr = t >> 2, gq = t & 3;
+  // generation role: sketch row row0 + jr, data rows 8 g .. 8 g + 7
+  const int jr = t >> 2, g = t & 3;
   const uint32_t jctr = static_cast<uint32_t>(row0 + jr);
   const uint32_t sk0 = static_cast<uint32_t>(seed);
   const uint32_t sk1 = static_cast<uint32_t>(seed >> 32);
@@ -356,75 +451,107 @@ __global__ void __launch_bounds__(kQThreads)
   // column maxima (when colmax is given): the nrt row-tile workgroups of a
   // slice take turns, step s by the workgroup with s mod nrt = rt
   uint32_t mx[4] = {0u, 0u, 0u, 0u};
-  // rows are loaded two steps ahead (two raw buffers, steps taken in pairs
-  // so that each buffer keeps its registers)
-  RawBlock<IT> ra, rb;
-  uint32_t gw[4];
-  __syncthreads();  // tables in LDS
-  stage_issue<IT, VEC>(x, ld, d, gcol, i_begin + 4 * rg, i_end, ra);
-  stage_issue<IT, VEC>(x, ld, d, gcol, i_begin + kQK + 4 * rg, i_end, rb);
-  draw8(static_cast<uint64_t>(i_begin >> 3) + gq, jctr, sk0, sk1, tab, gw);
-
-  auto step = [&](int64_t k0, int st, RawBlock<IT>& raw) {
+  auto krow = [&](int st) { return i_begin + static_cast<int64_t>(st) * kSK; };
+  auto write_step = [&](int st, const RawQuad<IT>& raw, const uint32_t (&o4)[4]) {
+    const int b = st & 1;
+    uint32_t gw[4];
+    entries8(o4, tab, gw);
     uint32_t xr[4][4];
-    stage_unpack<IT>(raw, i_end - (k0 + 4 * rg), dec8, xr);
-    if (colmax && st % nrt == rt) stage_max(xr, mx);
-    __syncthreads();  // the previous step's operands have been read
-    stage_store(XT, 8 * cc, 4 * rg, xr);
-    *reinterpret_cast<uint4*>(&GT[jr * kQP + 8 * gq]) =
+    quad_unpack<IT>(raw, i_end - (krow(st) + 4 * rg), dec8, xr);
+    if (colmax && st % nrt == rt) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const u16x2 a = __builtin_bit_cast(u16x2, mx[v]);
+          const u16x2 c = __builtin_bit_cast(u16x2, xr[u][v] & 0x7FFF7FFFu);
+          mx[v] = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(a, c));
+        }
+    }
+    quad_store<kQD / 8>(XT[b], cc, rg, xr);
+    *reinterpret_cast<uint4*>(&GT[b][qsw(jr, g)]) =
         make_uint4(gw[0], gw[1], gw[2], gw[3]);
-    __syncthreads();
-    // two steps ahead (past the slice: rows clamped, never used)
-    stage_issue<IT, VEC>(x, ld, d, gcol, k0 + 2 * kQK + 4 * rg, i_end, raw);
+  };
+  auto draw_step = [&](int st, uint32_t (&o4)[4]) {
+    draw_raw(static_cast<uint64_t>(krow(st) >> 3) + g, jctr, sk0, sk1, o4);
+  };
+  auto mma = [&](int st) {
+    const int b = st & 1;
 #pragma unroll
     for (int kh = 0; kh < 2; ++kh) {
       bf16x8 av[2], bv[4];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
         av[a] = *reinterpret_cast<const bf16x8*>(
-            &GT[(64 * wr + 32 * a + l32) * kQP + 16 * kh + 8 * h]);
+            &GT[b][qsw(64 * wr + 32 * a + l32, 2 * kh + h)]);
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-        bv[b] = *reinterpret_cast<const bf16x8*>(
-            &XT[(128 * wc + 32 * b + l32) * kQP + 16 * kh + 8 * h]);
+      for (int c4 = 0; c4 < 4; ++c4)
+        bv[c4] = *reinterpret_cast<const bf16x8*>(
+            &XT[b][qsw(128 * wc + 32 * c4 + l32, 2 * kh + h)]);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b],
-                                                              acc[a][b], 0, 0, 0);
+        for (int c4 = 0; c4 < 4; ++c4)
+          acc[a][c4] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              av[a], bv[c4], acc[a][c4], 0, 0, 0);
     }
-    draw8(static_cast<uint64_t>((k0 + kQK) >> 3) + gq, jctr, sk0, sk1, tab,
-          gw);
   };
-  int st = 0;
-  for (int64_t k0 = i_begin; k0 < i_end; k0 += 2 * kQK, st += 2) {
-    step(k0, st, ra);
-    if (k0 + kQK < i_end) step(k0 + kQK, st + 1, rb);
+
+  RawQuad<IT> ra, rb;  // steps of even / odd index
+  uint32_t o4[4];       // Philox words of the next step's block
+  __syncthreads();  // tables in LDS
+  quad_issue<IT, VEC>(x, ld, d, gcol, krow(0) + 4 * rg, i_end, ra);
+  quad_issue<IT, VEC>(x, ld, d, gcol, krow(1) + 4 * rg, i_end, rb);
+  draw_step(0, o4);
+  write_step(0, ra, o4);
+  quad_issue<IT, VEC>(x, ld, d, gcol, krow(2) + 4 * rg, i_end, ra);
+  draw_step(1, o4);
+  __syncthreads();
+  // iteration st: buffer st & 1 holds step st. Steps past the slice's end
+  // read its last row (in bounds) and stage zeros, so the loop body has no
+  // conditional memory operations and runs in pairs (an odd count gets one
+  // all-zero step).
+  auto iter = [&](int st, RawQuad<IT>& rnext) {
+    write_step(st + 1, rnext, o4);
+    quad_issue<IT, VEC>(x, ld, d, gcol, krow(st + 3) + 4 * rg, i_end, rnext);
+    draw_step(st + 2, o4);
+    mma(st);
+    __syncthreads();
+    // keeps the next step's unpacking (and its wait for the loads) after
+    // the barrier
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  for (int st = 0; st < nsteps; st += 2) {
+    iter(st, rb);
+    iter(st + 1, ra);
   }
   if (colmax) flush_max(mx, rg, col0 + 8 * cc, d, cs, colmax, nonfinite);
 
   // partial[slice][j][c]; accumulator register e of lane l holds
-  // D[(e % 4) + 8 (e / 4) + 4 (l / 32)][l % 32]
+  // D[(e % 4) + 8 (e / 4) + 4 (l / 32)][l % 32], the column of slot l % 32
+  // of the block
   float* P = partial + sp * r * d;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 4; ++b) {
+      const int64_t c = col0 + q_slot_col<kQD / 8>(128 * wc + 32 * b + l32);
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int64_t j = row0 + 64 * wr + 32 * a + (e % 4) + 8 * (e / 4) + 4 * h;
-        const int64_t c = col0 + 128 * wc + 32 * b + l32;
         if (j < r && c < d) P[j * d + c] = acc[a][b][e];
       }
+    }
 }
 
 // ---- Gram matrix X^T X of BF16 / FP8 input (the refinement pass) -------------
 // Output tile 256 x 256 of column blocks (A, B), A <= B, over one slice of
 // rows; eight waves, wave w owns rows 64 (w & 3) .. + 63 and columns
 // 128 (w >> 2) .. + 127 of the tile as 2 x 4 MFMA blocks. Threads 0-255
-// stage block A and 256-511 block B (the diagonal tiles stage A only) into
-// K-contiguous tiles, which serve both as the A^T and the B operand.
+// stage block A and 256-511 block B (on the diagonal both stage the same
+// block) into K-contiguous tiles, which serve both as the A^T and the B
+// operand. Steps of 16 rows through two buffers with one barrier per step,
+// loads three steps ahead, as in the sketch.
 constexpr int kGB = 256;
 
 template <int IT, bool VEC>
@@ -432,8 +559,8 @@ __global__ void __launch_bounds__(kQThreads)
     gram_q_kernel(const typename QIn<IT>::T* __restrict__ x, int64_t n,
                   int64_t d, int64_t ld, int nb, int ntiles,
                   int64_t rows_per_split, float* __restrict__ partial) {
-  __shared__ __attribute__((aligned(16))) uint16_t TA[kGB * kQP];
-  __shared__ __attribute__((aligned(16))) uint16_t TB[kGB * kQP];
+  __shared__ __attribute__((aligned(16))) uint16_t TA[2][kGB * kQP];
+  __shared__ __attribute__((aligned(16))) uint16_t TB[2][kGB * kQP];
   __shared__ uint16_t dec8[256];
   const int t = threadIdx.x;
   const unsigned L = xcd_logical();
@@ -445,19 +572,17 @@ __global__ void __launch_bounds__(kQThreads)
     ++ta;
   }
   const int tb = ta + rem;
-  const bool diag = ta == tb;
   const int64_t i_begin = sp * rows_per_split;
   int64_t i_end = i_begin + rows_per_split;
   if (i_end > n) i_end = n;
+  const int nsteps = static_cast<int>((i_end - i_begin + kQK - 1) / kQK);
   load_dec8<IT>(dec8, t);
 
+  constexpr int kNC = kGB / 8;  // 32 chunks of 8 columns
   const int side = t >> 8, ts = t & 255;
-  const int rg = ts & 7, cc = ts >> 3;  // 32 chunks of 8 columns
+  const int rp = ts & 7, cc = ts >> 3;
   const int64_t c0 = static_cast<int64_t>(side ? tb : ta) * kGB + 8 * cc;
   const int64_t gcol = c0 < d ? c0 : 0;
-  const bool stager = side == 0 || !diag;
-  uint16_t* T = side ? TB : TA;
-  const uint16_t* TBr = diag ? TA : TB;
   const int lane = t & 63, w = t >> 6, l32 = lane & 31, h = lane >> 5;
   const int wr = w & 3, wc = w >> 2;
 
@@ -469,55 +594,65 @@ __global__ void __launch_bounds__(kQThreads)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.0f;
 
-  RawBlock<IT> ra, rb;
-  __syncthreads();  // dec8
-  if (stager) {
-    stage_issue<IT, VEC>(x, ld, d, gcol, i_begin + 4 * rg, i_end, ra);
-    stage_issue<IT, VEC>(x, ld, d, gcol, i_begin + kQK + 4 * rg, i_end, rb);
-  }
-  auto step = [&](int64_t k0, RawBlock<IT>& raw) {
-    uint32_t xr[4][4];
-    if (stager) stage_unpack<IT>(raw, i_end - (k0 + 4 * rg), dec8, xr);
-    __syncthreads();
-    if (stager) stage_store(T, 8 * cc, 4 * rg, xr);
-    __syncthreads();
-    if (stager)
-      stage_issue<IT, VEC>(x, ld, d, gcol, k0 + 2 * kQK + 4 * rg, i_end, raw);
+  auto krow = [&](int st) { return i_begin + static_cast<int64_t>(st) * kQK; };
+  auto write_step = [&](int st, const RawPair<IT>& raw) {
+    uint32_t xr[2][4];
+    pair_unpack<IT>(raw, i_end - (krow(st) + 2 * rp), dec8, xr);
+    pair_store<kNC>(side ? TB[st & 1] : TA[st & 1], cc, 2 * rp, xr);
+  };
+  auto mma = [&](int st) {
+    const uint16_t* A = TA[st & 1];
+    const uint16_t* B = TB[st & 1];
+    bf16x8 av[2], bv[4];
 #pragma unroll
-    for (int kh = 0; kh < 2; ++kh) {
-      bf16x8 av[2], bv[4];
+    for (int a = 0; a < 2; ++a)
+      av[a] = *reinterpret_cast<const bf16x8*>(
+          &A[(64 * wr + 32 * a + l32) * kQP + 8 * h]);
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-        av[a] = *reinterpret_cast<const bf16x8*>(
-            &TA[(64 * wr + 32 * a + l32) * kQP + 16 * kh + 8 * h]);
+    for (int b = 0; b < 4; ++b)
+      bv[b] = *reinterpret_cast<const bf16x8*>(
+          &B[(128 * wc + 32 * b + l32) * kQP + 8 * h]);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b)
-        bv[b] = *reinterpret_cast<const bf16x8*>(
-            &TBr[(128 * wc + 32 * b + l32) * kQP + 16 * kh + 8 * h]);
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b],
-                                                              acc[a][b], 0, 0, 0);
-    }
+        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b],
+                                                            acc[a][b], 0, 0, 0);
   };
-  for (int64_t k0 = i_begin; k0 < i_end; k0 += 2 * kQK) {
-    step(k0, ra);
-    if (k0 + kQK < i_end) step(k0 + kQK, rb);
+
+  RawPair<IT> ra, rb;
+  __syncthreads();  // dec8
+  pair_issue<IT, VEC>(x, ld, d, gcol, krow(0) + 2 * rp, i_end, ra);
+  pair_issue<IT, VEC>(x, ld, d, gcol, krow(1) + 2 * rp, i_end, rb);
+  write_step(0, ra);
+  pair_issue<IT, VEC>(x, ld, d, gcol, krow(2) + 2 * rp, i_end, ra);
+  __syncthreads();
+  auto iter = [&](int st, RawPair<IT>& rnext) {
+    write_step(st + 1, rnext);
+    pair_issue<IT, VEC>(x, ld, d, gcol, krow(st + 3) + 2 * rp, i_end, rnext);
+    mma(st);
+    __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  for (int st = 0; st < nsteps; st += 2) {
+    iter(st, rb);
+    iter(st + 1, ra);
   }
+
   float* P = partial + sp * d * d;
   const int64_t a0 = static_cast<int64_t>(ta) * kGB, b0 = static_cast<int64_t>(tb) * kGB;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 4; ++b) {
+      const int64_t j = b0 + q_slot_col<kNC>(128 * wc + 32 * b + l32);
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int64_t i = a0 + 64 * wr + 32 * a + (e % 4) + 8 * (e / 4) + 4 * h;
-        const int64_t j = b0 + 128 * wc + 32 * b + l32;
+        const int64_t i =
+            a0 + q_slot_col<kNC>(64 * wr + 32 * a + (e % 4) + 8 * (e / 4) + 4 * h);
         if (i < d && j < d) P[i * d + j] = acc[a][b][e];
       }
+    }
 }
 
 __global__ void gauss_q_entries_kernel(uint64_t seed, int64_t r, int64_t n,
@@ -539,16 +674,17 @@ __global__ void gauss_q_entries_kernel(uint64_t seed, int64_t r, int64_t n,
 }
 
 // Slices of rows for a grid of `tiles` workgroups per slice: slices of at
-// most 2^18 rows (multiples of kQK), as many as fit the 256 CUs in one round
-// of one workgroup each (at least one slice, at least one step per slice)
+// most 2^18 rows (multiples of 32, whole steps of both kernels), as many as
+// fit the 256 CUs in one round of one workgroup each (at least one slice, at
+// least one step per slice)
 int64_t q_split(int64_t n, int64_t tiles, int64_t* splits) {
-  const int64_t steps = (n + kQK - 1) / kQK;
+  const int64_t steps = (n + kSK - 1) / kSK;
   int64_t s = 256 / tiles;
   const int64_t need = (n + (int64_t{1} << 18) - 1) >> 18;
   if (s < need) s = need;
   if (s > steps) s = steps;
   if (s < 1) s = 1;
-  int64_t per = (steps + s - 1) / s * kQK;
+  int64_t per = (steps + s - 1) / s * kSK;
   *splits = (n + per - 1) / per;
   return per;
 }

@@ -110,7 +110,8 @@ def test_osnap_argument_errors(lib):
     assert _ws(lib, m, 16, 4, sketch=slso.OSNAP, nnz=3)[0] == slso.EINVAL   # 3 does not divide 16
     assert _ws(lib, m, 32, 4, sketch=slso.OSNAP, nnz=32)[0] == slso.EINVAL  # above 16
     assert _ws(lib, m, 16, 4, sketch=slso.OSNAP, nnz=-1)[0] == slso.EINVAL
-    assert _ws(lib, m, 16, 4, flags=2)[0] == slso.EINVAL                  # unknown flag
+    assert _ws(lib, m, 16, 4, flags=4)[0] == slso.EINVAL                  # unknown flag
+    assert _ws(lib, m, 16, 4, flags=slso.OPT_EPS_HAT)[0] == slso.OK
     assert _ws(lib, m, 16, 4, flags=slso.OPT_SVD_RANK)[0] == slso.OK
     assert _ws(lib, m, 16, 4, sketch=4)[0] == slso.EINVAL                # unknown sketch
     assert _ws(lib, m, 16, 4, sketch=slso.OSNAP, nnz=16)[0] == slso.OK
