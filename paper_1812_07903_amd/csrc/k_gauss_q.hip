@@ -30,6 +30,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -118,16 +119,40 @@ struct QIn<2> {  // FP8-e4m3 codes
   using T = uint8_t;
 };
 
-// The Philox block of sketch row j for data rows 8 q .. 8 q + 7
+// a ^ b ^ k in one instruction (k uniform): gfx950's three-input logic op
+// with the truth table of a three-way xor (0x96); the compiler forms two
+// two-input xors here, and the generator's VALU work bounds the sketch
+__device__ __forceinline__ uint32_t xor3k(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "s"(k), "v"(a), "v"(b));
+  return r;
+}
+
+// The Philox4x32-10 block of sketch row j for data rows 8 q .. 8 q + 7 (the
+// same rounds as philox10, with the key folded in by xor3k)
 __device__ __forceinline__ void draw_raw(uint64_t q, uint32_t j, uint32_t k0,
                                          uint32_t k1, uint32_t (&o4)[4]) {
-  U4 c{static_cast<uint32_t>(q), static_cast<uint32_t>(q >> 32), j,
-       static_cast<uint32_t>(kStreamGaussQ)};
-  const U4 o = philox10(c, k0, k1);
-  o4[0] = o.x;
-  o4[1] = o.y;
-  o4[2] = o.z;
-  o4[3] = o.w;
+  uint32_t c0 = static_cast<uint32_t>(q), c1 = static_cast<uint32_t>(q >> 32);
+  uint32_t c2 = j, c3 = static_cast<uint32_t>(kStreamGaussQ);
+#pragma unroll
+  for (int rd = 0; rd < 10; ++rd) {
+    if (rd > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = static_cast<uint64_t>(c0) * 0xD2511F53u;
+    const uint64_t p1 = static_cast<uint64_t>(c2) * 0xCD9E8D57u;
+    const uint32_t n0 = xor3k(static_cast<uint32_t>(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3k(static_cast<uint32_t>(p0 >> 32), c3, k1);
+    c1 = static_cast<uint32_t>(p1);
+    c3 = static_cast<uint32_t>(p0);
+    c0 = n0;
+    c2 = n2;
+  }
+  o4[0] = c0;
+  o4[1] = c1;
+  o4[2] = c2;
+  o4[3] = c3;
 }
 
 // its 8 entries as 4 words of BF16 pairs (lower data row in the low half)
@@ -371,6 +396,58 @@ __device__ __forceinline__ void quad_unpack(const RawQuad<IT>& raw,
   }
 }
 
+// The same four rows where every row read is inside X and inside the slice:
+// p points at row `row`, column gcol; no clamping and no masking.
+template <int IT, bool VEC>
+__device__ __forceinline__ void quad_issue_fast(
+    const typename QIn<IT>::T* __restrict__ p, int64_t ld, int64_t d,
+    int64_t gcol, RawQuad<IT>& raw) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const typename QIn<IT>::T* q = p + u * ld;
+    if constexpr (VEC) {
+      if constexpr (IT == 1)
+        raw.q[u] = *reinterpret_cast<const uint4*>(q);
+      else
+        raw.q[u] = *reinterpret_cast<const uint2*>(q);
+    } else {
+      uint32_t e8[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) e8[e] = q[gcol + e < d ? e : 0];
+      if constexpr (IT == 1) {
+        raw.q[u] = make_uint4(e8[0] | (e8[1] << 16), e8[2] | (e8[3] << 16),
+                              e8[4] | (e8[5] << 16), e8[6] | (e8[7] << 16));
+      } else {
+        raw.q[u] = make_uint2(e8[0] | (e8[1] << 8) | (e8[2] << 16) | (e8[3] << 24),
+                              e8[4] | (e8[5] << 8) | (e8[6] << 16) | (e8[7] << 24));
+      }
+    }
+  }
+}
+
+template <int IT>
+__device__ __forceinline__ void quad_unpack_fast(const RawQuad<IT>& raw,
+                                                 const uint16_t* dec8,
+                                                 uint32_t (&xr)[4][4]) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if constexpr (IT == 1) {
+      xr[u][0] = raw.q[u].x;
+      xr[u][1] = raw.q[u].y;
+      xr[u][2] = raw.q[u].z;
+      xr[u][3] = raw.q[u].w;
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t w = v < 2 ? raw.q[u].x : raw.q[u].y;
+        const int sh = 16 * (v & 1);
+        xr[u][v] = static_cast<uint32_t>(dec8[(w >> sh) & 0xFFu]) |
+                   (static_cast<uint32_t>(dec8[(w >> (sh + 8)) & 0xFFu]) << 16);
+      }
+    }
+  }
+}
+
 // rows 4 rg .. 4 rg + 3 of columns 8 cc + e into slot NC e + cc of a 32-row
 // tile (one 8-byte write per column)
 template <int NC>
@@ -452,26 +529,6 @@ __global__ void __launch_bounds__(kQThreads)
   // slice take turns, step s by the workgroup with s mod nrt = rt
   uint32_t mx[4] = {0u, 0u, 0u, 0u};
   auto krow = [&](int st) { return i_begin + static_cast<int64_t>(st) * kSK; };
-  auto write_step = [&](int st, const RawQuad<IT>& raw, const uint32_t (&o4)[4]) {
-    const int b = st & 1;
-    uint32_t gw[4];
-    entries8(o4, tab, gw);
-    uint32_t xr[4][4];
-    quad_unpack<IT>(raw, i_end - (krow(st) + 4 * rg), dec8, xr);
-    if (colmax && st % nrt == rt) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const u16x2 a = __builtin_bit_cast(u16x2, mx[v]);
-          const u16x2 c = __builtin_bit_cast(u16x2, xr[u][v] & 0x7FFF7FFFu);
-          mx[v] = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(a, c));
-        }
-    }
-    quad_store<kQD / 8>(XT[b], cc, rg, xr);
-    *reinterpret_cast<uint4*>(&GT[b][qsw(jr, g)]) =
-        make_uint4(gw[0], gw[1], gw[2], gw[3]);
-  };
   auto draw_step = [&](int st, uint32_t (&o4)[4]) {
     draw_raw(static_cast<uint64_t>(krow(st) >> 3) + g, jctr, sk0, sk1, o4);
   };
@@ -497,33 +554,85 @@ __global__ void __launch_bounds__(kQThreads)
     }
   };
 
-  RawQuad<IT> ra, rb;  // steps of even / odd index
-  uint32_t o4[4];       // Philox words of the next step's block
-  __syncthreads();  // tables in LDS
-  quad_issue<IT, VEC>(x, ld, d, gcol, krow(0) + 4 * rg, i_end, ra);
-  quad_issue<IT, VEC>(x, ld, d, gcol, krow(1) + 4 * rg, i_end, rb);
-  draw_step(0, o4);
-  write_step(0, ra, o4);
-  quad_issue<IT, VEC>(x, ld, d, gcol, krow(2) + 4 * rg, i_end, ra);
-  draw_step(1, o4);
-  __syncthreads();
-  // iteration st: buffer st & 1 holds step st. Steps past the slice's end
-  // read its last row (in bounds) and stage zeros, so the loop body has no
-  // conditional memory operations and runs in pairs (an odd count gets one
-  // all-zero step).
-  auto iter = [&](int st, RawQuad<IT>& rnext) {
-    write_step(st + 1, rnext, o4);
-    quad_issue<IT, VEC>(x, ld, d, gcol, krow(st + 3) + 4 * rg, i_end, rnext);
-    draw_step(st + 2, o4);
-    mma(st);
+  // SAFE: rows are clamped into the slice and masked past its end (the last
+  // slices). Otherwise every step lies inside the slice, whose row count is
+  // even in steps, and the three steps of look-ahead past its end are still
+  // rows of X, so rows are read and staged as they are.
+  auto run = [&](auto safe_tag) {
+    constexpr bool SAFE = decltype(safe_tag)::value;
+    const int64_t stride = kSK * ld;
+    const typename QIn<IT>::T* pnext = x + (i_begin + 4 * rg) * ld + gcol;
+    auto issue = [&](int st, RawQuad<IT>& raw) {
+      if constexpr (SAFE) {
+        quad_issue<IT, VEC>(x, ld, d, gcol, krow(st) + 4 * rg, i_end, raw);
+      } else {
+        quad_issue_fast<IT, VEC>(pnext, ld, d, gcol, raw);
+        pnext += stride;
+      }
+    };
+    auto write_step = [&](int st, const RawQuad<IT>& raw,
+                          const uint32_t (&o4)[4]) {
+      const int b = st & 1;
+      uint32_t gw[4];
+      entries8(o4, tab, gw);
+      uint32_t xr[4][4];
+      if constexpr (SAFE)
+        quad_unpack<IT>(raw, i_end - (krow(st) + 4 * rg), dec8, xr);
+      else
+        quad_unpack_fast<IT>(raw, dec8, xr);
+      if (colmax && st % nrt == rt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const u16x2 a = __builtin_bit_cast(u16x2, mx[v]);
+            const u16x2 c = __builtin_bit_cast(u16x2, xr[u][v] & 0x7FFF7FFFu);
+            mx[v] = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(a, c));
+          }
+      }
+      quad_store<kQD / 8>(XT[b], cc, rg, xr);
+      *reinterpret_cast<uint4*>(&GT[b][qsw(jr, g)]) =
+          make_uint4(gw[0], gw[1], gw[2], gw[3]);
+    };
+
+    RawQuad<IT> ra, rb;  // steps of even / odd index
+    uint32_t o4[4];       // Philox words of the next step's block
+    issue(0, ra);
+    issue(1, rb);
+    draw_step(0, o4);
+    write_step(0, ra, o4);
+    issue(2, ra);
+    draw_step(1, o4);
     __syncthreads();
-    // keeps the next step's unpacking (and its wait for the loads) after
-    // the barrier
-    __builtin_amdgcn_sched_barrier(0);
+    // iteration st: buffer st & 1 holds step st. Steps past the slice's end
+    // (SAFE) read its last row and stage zeros, so the loop body has no
+    // conditional memory operations and runs in pairs (an odd count gets
+    // one all-zero step).
+    auto iter = [&](int st, RawQuad<IT>& rnext) {
+      write_step(st + 1, rnext, o4);
+      issue(st + 3, rnext);
+      draw_step(st + 2, o4);
+      mma(st);
+      __syncthreads();
+      // keeps the next step's unpacking (and its wait for the loads) after
+      // the barrier
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    for (int st = 0; st < nsteps; st += 2) {
+      iter(st, rb);
+      iter(st + 1, ra);
+    }
   };
-  for (int st = 0; st < nsteps; st += 2) {
-    iter(st, rb);
-    iter(st + 1, ra);
+  __syncthreads();  // tables in LDS
+  // (element-wise loads of unaligned input always take the SAFE form)
+  if constexpr (VEC) {
+    if ((i_end - i_begin) % (2 * kSK) == 0 && i_end + 3 * kSK <= n) {
+      run(std::false_type{});
+    } else {
+      run(std::true_type{});
+    }
+  } else {
+    run(std::true_type{});
   }
   if (colmax) flush_max(mx, rg, col0 + 8 * cc, d, cs, colmax, nonfinite);
 
@@ -674,17 +783,17 @@ __global__ void gauss_q_entries_kernel(uint64_t seed, int64_t r, int64_t n,
 }
 
 // Slices of rows for a grid of `tiles` workgroups per slice: slices of at
-// most 2^18 rows (multiples of 32, whole steps of both kernels), as many as
+// most 2^18 rows (multiples of 64, pairs of steps of both kernels), as many as
 // fit the 256 CUs in one round of one workgroup each (at least one slice, at
 // least one step per slice)
 int64_t q_split(int64_t n, int64_t tiles, int64_t* splits) {
-  const int64_t steps = (n + kSK - 1) / kSK;
+  const int64_t steps = (n + 2 * kSK - 1) / (2 * kSK);
   int64_t s = 256 / tiles;
   const int64_t need = (n + (int64_t{1} << 18) - 1) >> 18;
   if (s < need) s = need;
   if (s > steps) s = steps;
   if (s < 1) s = 1;
-  int64_t per = (steps + s - 1) / s * kSK;
+  int64_t per = (steps + s - 1) / s * (2 * kSK);
   *splits = (n + per - 1) / per;
   return per;
 }
