@@ -433,6 +433,25 @@ int slso_solve_upper(slso_ctx* ctx, const double* r, int64_t d, double* b,
 int slso_scores(slso_ctx* ctx, const slso_matrix* X, const double* m,
                 int64_t k, float* scores, void* stream);
 
+/* slso_scores without any device allocation, for callers that cannot
+ * allocate: work under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. Same arguments, kernels and results (bit-identical to
+ * slso_scores on the same input). Instead of the context's workspace it uses
+ * one fixed device array per GPU of 16 MiB (SLSO_NOALLOC_SCRATCH_BYTES),
+ * which holds, 256-byte aligned, d FP64 column factors, M as d x k FP64 and
+ * FP32, and for dense non-FP64 input with k <= 64 the three BF16 parts of M
+ * (3 x 64 x d x 2 bytes), or for dense input with k > 64 ceil(k / 64) x n
+ * FP64 partial sums: dense FP32 / BF16 / FP8 input with k <= 64 fits up to
+ * d of about 14000. A call whose buffers exceed the array returns
+ * SLSO_EINVAL (nothing is enqueued). The array is set up by slso_create
+ * (once per device) and kept until the process ends; it keeps the last
+ * call's contents, and every call on one GPU shares it, so calls that
+ * overlap on one GPU (other streams, other contexts, other threads) race:
+ * order them on one stream or with events. */
+#define SLSO_NOALLOC_SCRATCH_BYTES (16ll << 20)
+int slso_scores_noalloc(slso_ctx* ctx, const slso_matrix* X, const double* m,
+                        int64_t k, float* scores, void* stream);
+
 /* ---- measurement ---------------------------------------------------------- */
 
 /* Process-wide launch profiler. While enabled, HIP events are recorded on

@@ -38,7 +38,8 @@ EXPORTED = (
     "slso_hash",
     "slso_gaussian", "slso_gaussian_sketch_entries",
     "slso_gaussian_sketch_entries_q", "slso_qr_r", "slso_qr_r_path",
-    "slso_solve_upper", "slso_scores", "slso_workspace_size",
+    "slso_solve_upper", "slso_scores", "slso_scores_noalloc",
+    "slso_workspace_size",
     "slso_server_create", "slso_server_submit", "slso_server_poll",
     "slso_server_wait", "slso_server_stats", "slso_server_destroy",
     "slso_profile_enable", "slso_profile_read", "slso_profile_name",
@@ -142,6 +143,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "slso_solve_upper": ([vp, vp, i64, vp, i64, vp], ctypes.c_int),
         "slso_scores": ([vp, ctypes.POINTER(_Matrix), vp, i64, vp, vp],
                         ctypes.c_int),
+        "slso_scores_noalloc": ([vp, ctypes.POINTER(_Matrix), vp, i64, vp, vp],
+                                ctypes.c_int),
         "slso_workspace_size": ([ctypes.POINTER(_Matrix), i64, i64,
                                  ctypes.POINTER(_Options),
                                  ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -453,7 +456,11 @@ class Context:
                                                _stream(stream)), self._h)
         return b
 
-    def scores(self, x, m, out=None, stream=None):
+    def scores(self, x, m, out=None, stream=None, noalloc=False):
+        """l_i = ||x_i M||^2 (slso_scores). noalloc=True calls
+        slso_scores_noalloc: no device allocation, the library's fixed
+        per-device scratch instead of the context workspace (calls that
+        overlap on one GPU race on it)."""
         import torch
         mm = _matrix(x)
         self._here(_device(x))
@@ -463,9 +470,10 @@ class Context:
             raise ValueError("M must be a contiguous float64 d x k tensor")
         self._here(m.device)
         out = _out(out, torch.float32, _rows(x), _device(x), "out")
-        _check(load_library().slso_scores(self._h, ctypes.byref(mm), _ptr(m),
-                                          m.shape[1], _ptr(out),
-                                          _stream(stream)), self._h)
+        lib = load_library()
+        fn = lib.slso_scores_noalloc if noalloc else lib.slso_scores
+        _check(fn(self._h, ctypes.byref(mm), _ptr(m), m.shape[1], _ptr(out),
+                  _stream(stream)), self._h)
         return out
 
 

@@ -15,6 +15,7 @@
 
 struct slso_ctx {
   int device = 0;
+  void* scratch = nullptr;  // this device's address of the scoring scratch
   void* ws = nullptr;       // device workspace
   size_t ws_bytes = 0;
   hipEvent_t ws_done = nullptr;  // recorded after the last work using ws
@@ -101,6 +102,15 @@ int ctx_release_workspace(slso_ctx* c) {
   return SLSO_OK;
 }
 }  // namespace slso
+
+// ---- the scratch of the allocation-free scoring call ------------------------
+// One array per device, alive until the process ends, shared by every
+// slso_scores_noalloc call on that device. Host code never uses the array's
+// name as an address: slso_create looks up this device's address once
+// (hipGetSymbolAddress, with the device current) and every launch takes that
+// pointer.
+constexpr size_t kNoAllocScratchBytes = SLSO_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace {
 
@@ -190,6 +200,25 @@ int ensure_ws(slso_ctx* c, size_t bytes) {
   }
   c->ws_bytes = want;
   return SLSO_OK;
+}
+
+// this device's address of the scratch array (see its definition)
+std::mutex g_scratch_mu;
+void* g_scratch_addr[64] = {};
+
+// the array's address on `device` (current); nullptr when it cannot be had
+void* scratch_address(int device) {
+  if (device < 0 || device >= 64) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_addr[device] = p;
+  }
+  return g_scratch_addr[device];
 }
 
 int check_launch(slso_ctx* c, const char* what) {
@@ -454,7 +483,9 @@ int slso_create(slso_ctx** out, int device) {
       hipEventCreateWithFlags(&c->side_done, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&c->qs.side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->qs.factored, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->qs.bulk_done, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->qs.bulk_done, hipEventDisableTiming) != hipSuccess ||
+      (c->scratch = scratch_address(device)) == nullptr) {
+    if (c->qs.bulk_done) (void)hipEventDestroy(c->qs.bulk_done);
     if (c->qs.factored) (void)hipEventDestroy(c->qs.factored);
     if (c->qs.side) (void)hipStreamDestroy(c->qs.side);
     if (c->side_done) (void)hipEventDestroy(c->side_done);
@@ -676,6 +707,46 @@ int slso_solve_upper(slso_ctx* c, const double* r, int64_t d, double* b,
   return check_launch(c, "slso_solve_upper");
 }
 
+}  // extern "C"
+
+namespace {
+// Layout of the scoring call's buffers, from `base` (workspace or scratch)
+template <typename A>
+void score_layout(A& a, const slso_matrix* X, int64_t k, double** cs,
+                  double** m64, float** m32, double** part) {
+  *cs = a.template take<double>(X->d);
+  *m64 = a.template take<double>(X->d * k);
+  *m32 = a.template take<float>(X->d * k);
+  *part = a.template take<double>(
+      scores_partial_bytes(X->n, X->d, k, X->format, X->dtype) / 8);
+}
+
+size_t score_bytes(const slso_matrix* X, int64_t k) {
+  Sizer z;
+  double *cs, *m64, *part;
+  float* m32;
+  score_layout(z, X, k, &cs, &m64, &m32, &part);
+  return z.off;
+}
+
+void score_enqueue(const slso_matrix* X, const double* m, int64_t k,
+                   float* scores, char* base, hipStream_t s) {
+  Arena a{base};
+  double *cs, *m64, *part;
+  float* m32;
+  score_layout(a, X, k, &cs, &m64, &m32, &part);
+  // FP8 codes: the column scales are folded into the rows of M
+  const bool fp8 = X->dtype == SLSO_FP8_E4M3;
+  if (fp8) launch_mul_scale(nullptr, X->col_scale, X->d, cs, s);
+  launch_scale_rows(m, fp8 ? cs : nullptr, X->d, k, m64, m32, s);
+  launch_scores(X->values, X->dtype, X->format, X->n, X->d, X->ld, X->row_ptr,
+                X->col_idx, X->col_scale, X->row_scale, m64, m32, k, scores, s,
+                part);
+}
+}  // namespace
+
+extern "C" {
+
 int slso_scores(slso_ctx* c, const slso_matrix* X, const double* m, int64_t k,
                 float* scores, void* stream) {
   if (!c) return SLSO_EINVAL;
@@ -685,27 +756,31 @@ int slso_scores(slso_ctx* c, const slso_matrix* X, const double* m, int64_t k,
     return set_err(c, SLSO_EINVAL, "need m, scores and k >= 1");
   SLSO_HIP(c, hipSetDevice(c->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  Sizer z;
-  z.take<double>(X->d);
-  z.take<double>(X->d * k);
-  z.take<float>(X->d * k);
-  z.take<char>(scores_partial_bytes(X->n, X->d, k, X->format, X->dtype));
-  if ((st = ensure_ws(c, z.off))) return st;
+  if ((st = ensure_ws(c, score_bytes(X, k)))) return st;
   WsMark mark_{c, s};
-  Arena a{static_cast<char*>(c->ws)};
-  double* cs = a.take<double>(X->d);
-  double* m64 = a.take<double>(X->d * k);
-  float* m32 = a.take<float>(X->d * k);
-  double* part = a.take<double>(
-      scores_partial_bytes(X->n, X->d, k, X->format, X->dtype) / 8);
-  // FP8 codes: the column scales are folded into the rows of M
-  const bool fp8 = X->dtype == SLSO_FP8_E4M3;
-  if (fp8) launch_mul_scale(nullptr, X->col_scale, X->d, cs, s);
-  launch_scale_rows(m, fp8 ? cs : nullptr, X->d, k, m64, m32, s);
-  launch_scores(X->values, X->dtype, X->format, X->n, X->d, X->ld, X->row_ptr,
-                X->col_idx, X->col_scale, X->row_scale, m64, m32, k, scores, s,
-                part);
+  score_enqueue(X, m, k, scores, static_cast<char*>(c->ws), s);
   return check_launch(c, "slso_scores");
+}
+
+int slso_scores_noalloc(slso_ctx* c, const slso_matrix* X, const double* m,
+                        int64_t k, float* scores, void* stream) {
+  if (!c) return SLSO_EINVAL;
+  int st = validate_matrix(c, X);
+  if (st) return st;
+  if (!m || !scores || k < 1)
+    return set_err(c, SLSO_EINVAL, "need m, scores and k >= 1");
+  const size_t need = score_bytes(X, k);
+  if (need > kNoAllocScratchBytes)
+    return set_err(c, SLSO_EINVAL,
+                   "slso_scores_noalloc needs " + std::to_string(need) +
+                       " bytes of scratch; the limit is " +
+                       std::to_string(kNoAllocScratchBytes));
+  if (!c->scratch)
+    return set_err(c, SLSO_EDEVICE, "no scratch address on this device");
+  SLSO_HIP(c, hipSetDevice(c->device));
+  score_enqueue(X, m, k, scores, static_cast<char*>(c->scratch),
+                static_cast<hipStream_t>(stream));
+  return check_launch(c, "slso_scores_noalloc");
 }
 
 int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
