@@ -729,23 +729,31 @@ __global__ void __launch_bounds__(kQThreads)
                                                             acc[a][b], 0, 0, 0);
   };
 
-  RawPair<IT> ra, rb;
+  RawPair<IT> ra, rb, rc, rd;
   __syncthreads();  // dec8
+  // four register buffers: step s is loaded into buffer s mod 4, five steps
+  // (80 rows) ahead of its products
   pair_issue<IT, VEC>(x, ld, d, gcol, krow(0) + 2 * rp, i_end, ra);
   pair_issue<IT, VEC>(x, ld, d, gcol, krow(1) + 2 * rp, i_end, rb);
+  pair_issue<IT, VEC>(x, ld, d, gcol, krow(2) + 2 * rp, i_end, rc);
+  pair_issue<IT, VEC>(x, ld, d, gcol, krow(3) + 2 * rp, i_end, rd);
   write_step(0, ra);
-  pair_issue<IT, VEC>(x, ld, d, gcol, krow(2) + 2 * rp, i_end, ra);
+  pair_issue<IT, VEC>(x, ld, d, gcol, krow(4) + 2 * rp, i_end, ra);
   __syncthreads();
   auto iter = [&](int st, RawPair<IT>& rnext) {
     write_step(st + 1, rnext);
-    pair_issue<IT, VEC>(x, ld, d, gcol, krow(st + 3) + 2 * rp, i_end, rnext);
+    pair_issue<IT, VEC>(x, ld, d, gcol, krow(st + 5) + 2 * rp, i_end, rnext);
     mma(st);
     __syncthreads();
     __builtin_amdgcn_sched_barrier(0);
   };
-  for (int st = 0; st < nsteps; st += 2) {
+  // steps past the slice's end read its last row and stage zeros (slices
+  // hold whole groups of four steps except the last)
+  for (int st = 0; st < nsteps; st += 4) {
     iter(st, rb);
-    iter(st + 1, ra);
+    iter(st + 1, rc);
+    iter(st + 2, rd);
+    iter(st + 3, ra);
   }
 
   float* P = partial + sp * d * d;
