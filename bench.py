@@ -62,34 +62,52 @@ def log(msg: str) -> None:
 
 
 # ---- rooflines ----------------------------------------------------------------
-# profiler name -> (kernel symbol in the PMC summary, source file)
-KERNEL_SRC = {
-    "cq2_gram": ("gram_block_kernel<false,true>", "k_cholqr.hip"),
-    "cq2_solve": ("stripe_solve_kernel<64>", "k_cholqr.hip"),
-    "score": ("score_mfma_kernel<3,true>", "k_score.hip"),
-    "countsketch": ("countsketch_colmax_kernel<float,false>", "k_sketch.hip"),
+# per workload: the committed PMC summary and, per profiler name, the kernel
+# symbol in it (the BF16 / FP32 form that the bench line's roofline times)
+PMC_SUMMARIES = {
+    "image": ("pmc_traffic_image_like_n60000_d784.txt", {
+        "cq2_gram": "gram_block_kernel<false,true>",
+        "cq2_solve": "stripe_solve_kernel<64>",
+        "score": "score_mfma_kernel<3,true>",
+        "countsketch": "countsketch_colmax_kernel<float,false>"}),
+    "precision_bf16": ("pmc_traffic_precision_n4000000_d512.txt", {
+        "gauss_sketch": "gauss_q_kernel<1,true>",
+        "gram": "gram_q_kernel<1,true>",
+        "score": "score_q_kernel<1,2>"}),
+    "precision_fp8": ("pmc_traffic_precision_n4000000_d512.txt", {
+        "gauss_sketch": "gauss_q_kernel<2,true>",
+        "gram": "gram_q_kernel<2,true>",
+        "score": "score_q_kernel<2,2>"}),
+    "precision_f32": ("pmc_traffic_precision_n4000000_d512.txt", {
+        "gauss_sketch": "gauss_sketch_kernel",
+        "score": "score_mfma_kernel<3,true>"}),
+    "text": ("pmc_traffic_text_like_n500000_d4096.txt", {
+        "countsketch": "countsketch_csr_kernel",
+        "cq2_solve": "stripe_solve_kernel<64>",
+        "score": "score_csr_kernel"}),
 }
-PMC_SUMMARY = os.path.join(ROOT, "profiles",
-                           "pmc_traffic_image_like_n60000_d784.txt")
 
 
 def measured_traffic(name: str, workload: str):
-    """Calibrated HBM bytes per launch from the committed rocprofv3 PMC
-    summary of the image-like workload, or None for other workloads, when
-    there is none, or when the kernel's source has changed since the
-    counters were taken."""
-    if workload != "image" or name not in KERNEL_SRC or \
-            not os.path.exists(PMC_SUMMARY):
+    """Calibrated HBM bytes per launch from the workload's committed
+    rocprofv3 PMC summary, or None when there is none, when the kernel is
+    not in it, or when the kernel's source has changed since the counters
+    were taken."""
+    if workload not in PMC_SUMMARIES:
         return None
-    sym, src = KERNEL_SRC[name]
-    path = os.path.join(ROOT, "paper_1812_07903_amd", "csrc", src)
-    with open(path, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    with open(PMC_SUMMARY) as f:
+    fname, syms = PMC_SUMMARIES[workload]
+    path = os.path.join(ROOT, "profiles", fname)
+    if name not in syms or not os.path.exists(path):
+        return None
+    want = syms[name]
+    with open(path) as f:
         for line in f:
             t = line.split()
-            if len(t) == 8 and t[0] == "traffic" and t[1] == sym:
-                return float(t[7]) if t[2] == src and t[3] == sha else None
+            if len(t) == 8 and t[0] == "traffic" and t[1] == want:
+                src = os.path.join(ROOT, "paper_1812_07903_amd", "csrc", t[2])
+                with open(src, "rb") as g:
+                    sha = hashlib.sha256(g.read()).hexdigest()[:16]
+                return float(t[7]) if t[3] == sha else None
     return None
 
 
@@ -303,7 +321,7 @@ def precision_bench(args, slso, ctx) -> dict:
     bf = time_job(slso, ctx, xb, n, seed, r, k, args.steps, args.warmup,
                   slso.GAUSSIAN, refine=True, label="precision bf16")
     sh_b = Shape(n, d, r, k, 2, "bf16")
-    roof, roof_other = rooflines(bf, sh_b, "precision",
+    roof, roof_other = rooflines(bf, sh_b, "precision_bf16",
                                  ("gauss_sketch", "gram", "score"))
     side_steps = max(2, min(5, args.steps))
     f8 = time_job(slso, ctx, x8, n, seed, r, k, side_steps, 1, slso.GAUSSIAN,
@@ -311,9 +329,10 @@ def precision_bench(args, slso, ctx) -> dict:
     f32 = time_job(slso, ctx, xf, n, seed, r, k, side_steps, 1, slso.GAUSSIAN,
                    refine=False, label="precision f32 plain")
     paths = {}
-    for name, res, sh in (("fp8", f8, Shape(n, d, r, k, 1, "fp8")),
-                          ("f32_plain", f32, Shape(n, d, r, k, 4, "f32"))):
-        rf, ro = rooflines(res, sh, "precision", ("gauss_sketch", "gram", "score"))
+    for name, res, sh, wl in (
+            ("fp8", f8, Shape(n, d, r, k, 1, "fp8"), "precision_fp8"),
+            ("f32_plain", f32, Shape(n, d, r, k, 4, "f32"), "precision_f32")):
+        rf, ro = rooflines(res, sh, wl, ("gauss_sketch", "gram", "score"))
         paths[name] = {"rows_per_s": res["rows_per_s"],
                        "ms_per_step": res["ms_per_step"],
                        "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"],
@@ -599,6 +618,120 @@ def serving_run(args, slso) -> dict:
     return out
 
 
+# ---- rocprofv3 summaries ------------------------------------------------------
+def _kernel_sources() -> dict:
+    """kernel function name -> csrc file that defines it"""
+    import re
+    out = {}
+    csrc = os.path.join(ROOT, "paper_1812_07903_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if not f.endswith(".hip"):
+            continue
+        with open(os.path.join(csrc, f)) as fh:
+            text = fh.read()
+        for m in re.finditer(r"__global__([^;{]*)", text):
+            # the first called-looking name that is not an attribute
+            for nm in re.findall(r"\b(\w+)\s*\(", m.group(1)):
+                if not nm.startswith("__"):
+                    out.setdefault(nm, f)
+                    break
+    return out
+
+
+def _short_name(name: str) -> str:
+    """'void slso::(anonymous namespace)::k<1, true>(args)' -> 'k<1,true>'"""
+    name = name.replace("void ", "").replace("slso::(anonymous namespace)::", "")
+    name = name.replace("slso::", "")
+    depth, cut = 0, len(name)
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            cut = i
+            break
+    return name[:cut].replace(" ", "")
+
+
+def _rocprof_csv(d: str, pattern: str) -> list:
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", pattern), recursive=True)
+    if not files:
+        raise SystemExit(f"no {pattern} under {d}")
+    with open(files[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _field(row: dict, *names):
+    low = {k.lower(): v for k, v in row.items()}
+    for n in names:
+        if n.lower() in low:
+            return low[n.lower()]
+    raise KeyError(names)
+
+
+def rocprof_stats(d: str, top: int = 40) -> int:
+    """Kernel-trace statistics (rocprofv3 --kernel-trace --stats, CSV) as a
+    table: calls, total and average duration per kernel."""
+    rows = _rocprof_csv(d, "*kernel_stats.csv")
+    print(f"{'kernel':58s} {'calls':>6s} {'total_us':>11s} {'avg_us':>10s} {'pct':>6s}")
+    for r in rows[:top]:
+        print(f"{_short_name(_field(r, 'Name', 'KernelName'))[:58]:58s} "
+              f"{int(_field(r, 'Calls')):6d} "
+              f"{float(_field(r, 'TotalDurationNs')) / 1e3:11.1f} "
+              f"{float(_field(r, 'AverageNs')) / 1e3:10.3f} "
+              f"{float(_field(r, 'Percentage')):6.2f}")
+    return 0
+
+
+def _counter_means(d: str, counter: str) -> dict:
+    """kernel short name -> (dispatches, mean per dispatch of the counter)"""
+    from collections import defaultdict
+    per = defaultdict(lambda: defaultdict(float))
+    for r in _rocprof_csv(d, "*counter_collection.csv"):
+        if _field(r, "Counter_Name", "CounterName") != counter:
+            continue
+        k = _short_name(_field(r, "Kernel_Name", "KernelName"))
+        per[k][_field(r, "Dispatch_Id", "DispatchId")] += float(
+            _field(r, "Counter_Value", "CounterValue"))
+    return {k: (len(v), sum(v.values()) / len(v)) for k, v in per.items()}
+
+
+def rocprof_traffic(fetch_dir: str, write_dir: str, cfetch_dir: str,
+                    cwrite_dir: str, copy_mib: int) -> int:
+    """HBM bytes per dispatch of every library kernel from a FETCH_SIZE and a
+    WRITE_SIZE run (KiB per dispatch), each scaled by what the counter reads
+    for a plain copy of copy_mib MiB (the --copy-calibration kernel): one
+    'traffic' line per kernel with its source file and that file's hash."""
+    cf = _counter_means(cfetch_dir, "FETCH_SIZE")
+    cw = _counter_means(cwrite_dir, "WRITE_SIZE")
+    kib = copy_mib * 1024.0
+    copy_f = max(cf.values(), key=lambda t: t[1])[1]
+    copy_w = max(cw.values(), key=lambda t: t[1])[1]
+    ff, wf = kib / copy_f, kib / copy_w
+    print(f"# copy kernel: FETCH_SIZE {copy_f:.2f} KiB and WRITE_SIZE "
+          f"{copy_w:.2f} KiB per launch for {kib:.0f} KiB read and written")
+    fetch = _counter_means(fetch_dir, "FETCH_SIZE")
+    write = _counter_means(write_dir, "WRITE_SIZE")
+    srcs = _kernel_sources()
+    rows = []
+    for k, (nd, fv) in fetch.items():
+        base = k.split("<")[0]
+        if base not in srcs:
+            continue
+        src = srcs[base]
+        with open(os.path.join(ROOT, "paper_1812_07903_amd", "csrc", src), "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+        wv = write.get(k, (0, 0.0))[1]
+        rows.append((fv * 1024 * ff + wv * 1024 * wf, k, src, sha, nd, fv, wv))
+    for b, k, src, sha, nd, fv, wv in sorted(rows, reverse=True):
+        print(f"traffic {k} {src} {sha} {nd} {fv:.2f} {wv:.2f} {b:.0f}")
+    print(f"calibration fetch_factor {ff:.6f} write_factor {wf:.6f}")
+    return 0
+
+
 def copy_calibration(mib: int) -> int:
     """A plain elementwise copy y = 1.0 * x of known size, five launches."""
     import torch
@@ -647,7 +780,20 @@ def main() -> int:
                     help="only run a plain device copy of MIB MiB five times "
                          "(reads MIB, writes MIB per launch): the reference "
                          "kernel for scaling HBM byte counters")
+    ap.add_argument("--rocprof-stats", metavar="DIR",
+                    help="only print the kernel statistics of a rocprofv3 "
+                         "--kernel-trace --stats CSV output folder")
+    ap.add_argument("--rocprof-traffic", nargs=5,
+                    metavar=("FETCH", "WRITE", "CFETCH", "CWRITE", "MIB"),
+                    help="only print HBM bytes per dispatch from rocprofv3 "
+                         "--pmc FETCH_SIZE / WRITE_SIZE CSV folders of a run "
+                         "and of --copy-calibration MIB")
     args = ap.parse_args()
+    if args.rocprof_stats:
+        return rocprof_stats(args.rocprof_stats)
+    if args.rocprof_traffic:
+        f, w, cf, cw, mib = args.rocprof_traffic
+        return rocprof_traffic(f, w, cf, cw, int(mib))
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -290,14 +290,121 @@ __global__ void __launch_bounds__(256, 2)
   }
 }
 
+// Stream-K form of the full blocks (used when the last column block is not
+// folded into the diagonal blocks): the work is cut into units of one block
+// over one chunk of rows, C units per block in row order, blocks in
+// upper_tile order, and workgroup g takes units g Q .. g Q + Q - 1, so every
+// workgroup carries the same work whatever the number of blocks (528 blocks
+// at d = 4096 would otherwise take two rounds of 512 slots, the second
+// nearly empty). A run of a workgroup's units inside one block (a segment)
+// is summed into partial block s of that block, s = the number of workgroup
+// boundaries inside the block before the run, at part[(blk NS + s) 16384].
+// one segment: block (I2, J2) over rows r0 .. r1 - 1 into out
+__device__ __attribute__((noinline)) void gram_segment(
+    const double* __restrict__ A, int64_t lda, int64_t I2, int64_t J2,
+    int64_t r0, int64_t r1, double (*X)[2][kGK * kGS],
+    double* __restrict__ out) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int p = lane & 15, q = lane >> 4;
+  const bool diag = I2 == J2;
+  const int c = t & 127, rr = t >> 7;
+  const double* pa = A + I2 * 128 + c;
+  const double* pb = A + J2 * 128 + c;
+  dbl4 acc[2][8];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 8; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+  double v[16];
+  // loads without branches (rows past r1 read row r0); zeros put in when
+  // the values go to LDS
+  auto gload = [&](int64_t r) {
+#pragma unroll
+    for (int uu = 0; uu < 8; ++uu) {
+      const int64_t row = r + rr + 2 * uu;
+      const int64_t ro = (row < r1 ? row : r0) * lda;
+      v[uu] = pa[ro];
+      if (!diag) v[8 + uu] = pb[ro];
+    }
+  };
+  auto lstore = [&](int buf, int64_t r) {
+#pragma unroll
+    for (int uu = 0; uu < 8; ++uu) {
+      const int64_t row = r + rr + 2 * uu;
+      X[buf][0][(rr + 2 * uu) * kGS + c] = row < r1 ? v[uu] : 0.0;
+      if (!diag) X[buf][1][(rr + 2 * uu) * kGS + c] = row < r1 ? v[8 + uu] : 0.0;
+    }
+  };
+  __syncthreads();  // the previous segment's last reads of X
+  gload(r0);
+  lstore(0, r0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t r = r0; r < r1; r += kGK) {
+    const bool more = r + kGK < r1;
+    if (more) gload(r + kGK);
+    const double* XA = X[buf][0];
+    const double* XB = diag ? X[buf][0] : X[buf][1];
+#pragma unroll
+    for (int kk = 0; kk < kGK / 4; ++kk) {
+      const int k = 4 * kk + q;
+      double a[2], b[8];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) a[x] = XA[k * kGS + 32 * w + 16 * x + p];
+#pragma unroll
+      for (int y = 0; y < 8; ++y) b[y] = XB[k * kGS + 16 * y + p];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 8; ++y) acc[x][y] = mfma(a[x], b[y], acc[x][y]);
+    }
+    if (more) lstore(buf ^ 1, r + kGK);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 8; ++y)
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv)
+        out[(32 * w + 16 * x + 4 * vv + q) * 128 + 16 * y + p] = acc[x][y][vv];
+}
+
+__global__ void __launch_bounds__(256, 2)
+    gram_sk_kernel(const double* __restrict__ A, int64_t lda, int64_t m,
+                   int64_t d, int64_t C, int64_t chunk, int64_t Q, int64_t NS,
+                   double* __restrict__ part, const int* __restrict__ flag) {
+  __shared__ double X[2][2][kGK * kGS];
+  if (*flag) return;
+  const int64_t nf = d / 128;
+  const int64_t U = nf * (nf + 1) / 2 * C;
+  int64_t u = static_cast<int64_t>(blockIdx.x) * Q;
+  const int64_t uend = u + Q < U ? u + Q : U;
+  while (u < uend) {
+    const int64_t blk = u / C, c0 = u % C;
+    const int64_t c1 = C < c0 + (uend - u) ? C : c0 + (uend - u);
+    const int64_t seg = c0 == 0 ? 0 : u / Q - (blk * C) / Q;
+    int64_t I2, J2;
+    upper_tile(blk, nf, I2, J2);
+    const int64_t r0 = c0 * chunk;
+    const int64_t r1 = m < c1 * chunk ? m : c1 * chunk;
+    // (r0 < m always: units past the last row are never made)
+    gram_segment(A, lda, I2, J2, r0, r1, X, part + (blk * NS + seg) * kB2);
+    u += c1 - c0;
+  }
+}
+
 // G tile = sum of its partial blocks (fixed order); the padding is the
 // identity; gdiag receives the diagonal. With emax, emax[workgroup] = max
 // |G - I| over the workgroup's valid entries (bit patterns of non-negative
 // doubles order like the values, a NaN above every number).
+// Q > 0: the full blocks are in the stream-K form (C units per block, Q per
+// workgroup, NS = S partial slots per block, the first nseg of them used).
 __global__ void __launch_bounds__(256)
     gram_reduce_kernel(const double* __restrict__ part, int64_t S, int64_t Se,
-                       int64_t nb, int64_t d, const double* __restrict__ dsc,
-                       double* __restrict__ G,
+                       int64_t C, int64_t Q, int64_t nb, int64_t d,
+                       const double* __restrict__ dsc, double* __restrict__ G,
                        double* __restrict__ gdiag, unsigned long long* emax,
                        const int* __restrict__ flag) {
   __shared__ unsigned long long red[4];
@@ -317,8 +424,11 @@ __global__ void __launch_bounds__(256)
     // padding: the identity (partial edge blocks hold nothing there)
     v = gi == gj ? 1.0 : 0.0;
   } else if (J2 < nf) {
-    const int64_t blk = upper_index(I2, J2, nf) * S;
-    v = sum_parts(part + blk * kB2 + off, S, kB2, 0);
+    const int64_t b = upper_index(I2, J2, nf);
+    // partial blocks of this block: S of them, or in the stream-K form one
+    // per workgroup boundary inside its units plus one
+    const int64_t np = Q > 0 ? 1 + (b * C + C - 1) / Q - (b * C) / Q : S;
+    v = sum_parts(part + b * S * kB2 + off, np, kB2, 0);
   } else {
     const int64_t blk = nf * (nf + 1) / 2 * S + I2 * Se;
     v = sum_parts(part + blk * kB2 + off, Se, kB2, 0);
@@ -999,6 +1109,8 @@ __global__ void __launch_bounds__(256)
 
 struct Cq2 {
   int64_t d, nb, nt, S, chunk, Se, chunk_e, nfull, nedge;
+  int64_t C, Q, nwg;  // stream-K full blocks (Q > 0): units per block and
+                      // per workgroup, workgroups; S: slots per block
   bool fe;  // edge products formed by the diagonal blocks (no edge launch)
   double *part, *G, *R1, *R2, *X1, *X2, *P, *Dinv, *gdiag, *apart;
   unsigned long long* emax;
@@ -1030,6 +1142,21 @@ Cq2 cq2_shape(int64_t m, int64_t d) {
   if (c.fe) {
     c.Se = c.S;
     c.chunk_e = c.chunk;
+  } else if (c.nfull > 0 &&
+             8 * c.nfull * c.S < 7 * 512 * ((c.nfull * c.S + 511) / 512)) {
+    // the rounds of the 512 slots less than seven eighths busy (528 blocks
+    // at d = 4096: two rounds, the second nearly empty): the stream-K form,
+    // with at least 256 rows per unit and 32 units per block where the rows
+    // allow, one round of at most 512 equal workgroups
+    c.C = 32;
+    const int64_t rows = (m + c.C - 1) / c.C;
+    if (rows < 256) c.C = (m + 255) / 256 > 1 ? (m + 255) / 256 : 1;
+    c.chunk = ((m + c.C - 1) / c.C + kGK - 1) / kGK * kGK;
+    c.C = (m + c.chunk - 1) / c.chunk;
+    const int64_t U = c.nfull * c.C;
+    c.Q = (U + 511) / 512;
+    c.nwg = (U + c.Q - 1) / c.Q;
+    c.S = (c.C - 1) / c.Q + 2;
   }
   return c;
 }
@@ -1057,7 +1184,10 @@ void gram_tiles(const double* a, int64_t m, int64_t d, const Cq2& c,
   // (the thin blocks gain nothing on a second stream: the main blocks hold
   // every slot until their last round ends)
   prof_begin(kKCq2Gram, s);
-  if (c.fe)
+  if (c.Q > 0)
+    gram_sk_kernel<<<static_cast<unsigned>(c.nwg), 256, 0, s>>>(
+        a, d, m, d, c.C, c.chunk, c.Q, c.S, c.part, flag);
+  else if (c.fe)
     gram_block_kernel<false, true><<<static_cast<unsigned>(c.nfull * c.S), 256, 0, s>>>(
         a, d, m, d, c.S, c.chunk, 0, c.part, flag);
   else if (c.nfull > 0)
@@ -1071,7 +1201,7 @@ void gram_tiles(const double* a, int64_t m, int64_t d, const Cq2& c,
   prof_end(kKCq2GramEdge, s);
   prof_begin(kKCq2GramSum, s);
   gram_reduce_kernel<<<static_cast<unsigned>(c.nt * 16), 256, 0, s>>>(
-      c.part, c.S, c.Se, c.nb, d, dsc, c.G, c.gdiag, em, flag);
+      c.part, c.S, c.Se, c.C, c.Q, c.nb, d, dsc, c.G, c.gdiag, em, flag);
   prof_end(kKCq2GramSum, s);
 }
 

@@ -212,13 +212,14 @@ __device__ __forceinline__ void flush_max(uint32_t (&mx)[4], int rg,
   if (bad) atomicExch(nonfinite, 1);
 }
 
-// logical workgroup id: with a grid that is a multiple of 8 each XCD
-// (blockIdx mod 8) gets a contiguous range of ids, so workgroups that share
-// a slice of rows of X share that XCD's L2
+// logical workgroup id: workgroups are dealt to the eight XCDs in turn
+// (XCD = blockIdx mod 8), so numbering each XCD's workgroups consecutively
+// (the XCDs before it hold q + 1 or q of the nb = 8 q + rem workgroups)
+// gives workgroups that share a slice of rows of X the same XCD and L2
 __device__ __forceinline__ unsigned xcd_logical() {
-  const unsigned nb = gridDim.x;
-  if ((nb & 7u) != 0u) return blockIdx.x;
-  return (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3);
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned xcd = b & 7u, q = nb >> 3, rem = nb & 7u;
+  return xcd * q + (xcd < rem ? xcd : rem) + (b >> 3);
 }
 
 template <int IT>

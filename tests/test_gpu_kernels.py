@@ -191,11 +191,13 @@ def test_srht_rejects_bad_arguments(slso, ctx):
                                  (1000, 96), (3000, 200), (5000, 64),
                                  (70000, 40), (2048, 512), (16384, 784),
                                  (4099, 833), (1000, 140), (700, 257),
-                                 (5000, 400)])
+                                 (5000, 400), (12000, 2048), (4500, 4096)])
 def test_qr_r_matches_householder(slso, ctx, m, d):
     """Cholesky-QR2 over the whole matrix (ragged row chunks and stripes,
     d below, at and past a multiple of 64; a last 128-column block of 1 to 16
-    columns, whose Gram products the diagonal blocks form, or of more)."""
+    columns, whose Gram products the diagonal blocks form, or of more; Gram
+    passes in the stream-K form: few blocks over few rows, 136 blocks at
+    d = 2048, 528 at d = 4096 with ragged units)."""
     rng = np.random.default_rng(m * 7 + d)
     a = rng.standard_normal((m, d)) * np.exp(rng.standard_normal(d))[None, :]
     r, used = ctx.qr_r_path(dev(a.copy()))
