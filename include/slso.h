@@ -154,6 +154,13 @@ typedef struct {
                                   /* panel path                              */
 #define SLSO_INFO_QR_TREE 16      /* ... and, that failing too, from the     */
                                   /* column-by-column Householder path       */
+#define SLSO_INFO_QR_ONE_PASS 32  /* the sketch's R is the first Cholesky-QR */
+                                  /* pass's R1: R1's condition estimate      */
+                                  /* kappa bounds the scores' relative error */
+                                  /* 4 kappa^2 sqrt(r d) 2^-53 by 1e-7 (by   */
+                                  /* 1e-2 with the refinement, where R only  */
+                                  /* preconditions); Algorithm 2 step 2      */
+                                  /* needs only R^T R of the sketch          */
 
 /* ---- context ------------------------------------------------------------ */
 

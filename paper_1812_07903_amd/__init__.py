@@ -48,6 +48,7 @@ EXPORTED = (
 # slso_info.flags bits
 INFO_REFINED, INFO_REFINE_FAILED = 1, 2
 INFO_QR_SECOND_CHOLESKY, INFO_QR_HOUSEHOLDER, INFO_QR_TREE = 4, 8, 16
+INFO_QR_ONE_PASS = 32
 QR_AUTO, QR_PANEL, QR_TREE, QR_CHOLQR2, QR_CHOLQR2_FULL = 0, 1, 2, 3, 4
 
 

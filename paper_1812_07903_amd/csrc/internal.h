@@ -166,13 +166,16 @@ size_t qr_scratch_bytes(int64_t m, int64_t d);
 // by the first-pass Q1. *status (device int): 0 done; 2: r_out not yet
 // written, call qr_factor_finish; 1: Cholesky-QR2 does not apply (a too
 // ill-conditioned or rank deficient): a and r_out are unusable, the caller
-// factors the original matrix with qr_factor_panel. dsc (nullable): powers
-// of two that scale a's columns as they are read; the factorisation is then
-// that of a diag(dsc), with the same rounding as if a had been scaled first.
+// factors the original matrix with qr_factor_panel; 3: one pass taken (R =
+// R1, see one_pass). dsc (nullable): powers of two that scale a's columns
+// as they are read; the factorisation is then that of a diag(dsc), with the
+// same rounding as if a had been scaled first. one_pass: 0 two passes; 2
+// one when the condition estimate of R1 bounds the score error far below
+// the gate; 1 the same with the looser bound of a preconditioner.
 void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
                int* status, const QrStreams& qs, hipStream_t s,
                bool want_r = true, double* dstat = nullptr,
-               const double* dsc = nullptr);
+               const double* dsc = nullptr, int one_pass = 0);
 // After status 2: the second pass's blocked Cholesky and R = R2 R1 (status
 // set again, 0 or 1).
 void qr_factor_finish(int64_t m, int64_t d, double* r_out, void* scratch,
@@ -180,10 +183,11 @@ void qr_factor_finish(int64_t m, int64_t d, double* r_out, void* scratch,
                       double* dstat = nullptr);
 // want_r = false: R is not formed; dstat[0..1] receive min and max |R_jj|, and
 // the scratch keeps R^{-1} in factored form for qr_apply_rinv (and the factors
-// for qr_write_r) until the scratch is reused. second: status 2 was met.
-void qr_apply_rinv(int64_t m, int64_t d, void* scratch, bool second, double* b,
+// for qr_write_r) until the scratch is reused. form: 0 two passes ending in
+// status 0, 1 two passes through status 2, 2 one pass (status 3).
+void qr_apply_rinv(int64_t m, int64_t d, void* scratch, int form, double* b,
                    int64_t k, hipStream_t s);  // b (d x k) <- R^{-1} b
-void qr_write_r(int64_t m, int64_t d, double* r_out, void* scratch, bool second,
+void qr_write_r(int64_t m, int64_t d, double* r_out, void* scratch, int form,
                 hipStream_t s);
 // Householder QR of a in place, r_out as above. 64-column panels by
 // Cholesky-QR2 with Householder reconstruction (k_cqr.hip), the remaining
@@ -202,12 +206,12 @@ size_t cholqr2_scratch_bytes(int64_t m, int64_t d);
 void cholqr2_factor(double* a, int64_t m, int64_t d, double* r_out,
                     void* scratch, int* status, const QrStreams& qs,
                     hipStream_t s, bool want_r, double* dstat,
-                    const double* dsc);
+                    const double* dsc, int one_pass);
 void cholqr2_finish(int64_t m, int64_t d, double* r_out, void* scratch,
                     int* status, hipStream_t s, bool want_r, double* dstat);
 void cholqr2_write_r(int64_t m, int64_t d, double* r_out, void* scratch,
-                     bool second, hipStream_t s);
-void cholqr2_apply_rinv(int64_t m, int64_t d, void* scratch, bool second,
+                     int form, hipStream_t s);
+void cholqr2_apply_rinv(int64_t m, int64_t d, void* scratch, int form,
                         double* b, int64_t k, hipStream_t s);
 // 64-column panel path (k_cqr.hip)
 size_t cqr_scratch_bytes(int64_t m, int64_t d);

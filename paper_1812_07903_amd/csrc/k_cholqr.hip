@@ -25,6 +25,18 @@
 //   entry, status 1: the caller factors the (re-formed) matrix with the
 //   Householder paths.
 //
+// One pass (CholeskyQR). For the scores only R^T R matters: the first
+// pass's R1 has R1^T R1 = A^T A + E with |E| about sqrt(m d) u |A|^2 under
+// the usual model of rounding errors that add like random ones, which moves
+// every score by a relative amount up to |E| / sigma_min(A)^2 =
+// sqrt(m d) u kappa(A)^2. With one_pass = 2 the passes stop after R1 when
+// 4 kappa_est^2 sqrt(m d) u <= 1e-7 (two orders below the FP32 gate of
+// the scores), kappa_est = |R1 x| |R1^{-1} y| from six power iterations on
+// R1 and on R1^{-1} (a lower bound of kappa, hence the factor 4 = 2^2):
+// status 3, R = R1. With one_pass = 1 (the sketch factor only preconditions
+// the refinement, which needs R^{-T} A^T A R^{-1} near I, not R itself) the
+// bound is 1e-2.
+//
 // Data layout. d x d matrices are kept as nb x nb tiles of 64 x 64 (tile
 // (I, J) at (I nb + J) 4096, row-major inside), padded past d with the
 // identity on the diagonal and zeros elsewhere; only tiles on and above the
@@ -1107,12 +1119,261 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// ---- condition estimate of R1 (one-pass acceptance) -------------------------
+// Power iteration on R1 and X1 = R1^{-1} together (blockIdx.y = 0, 1): the
+// vectors live in v[mat][nb 64] (zero past d, where the tiles hold the
+// identity). Every workgroup forms the norm of its input vector itself, in
+// the same order, so the iteration is deterministic.
+constexpr int kPowIters = 6;
+
+// Cheap lower bounds of kappa(R1) = sigma_max(R1) sigma_max(X1): for a
+// triangular matrix max |R1_jj| / min |R1_jj|, and the largest column norm
+// of R1 (that of A: sqrt(G_jj)) times the largest row norm of X1. When one
+// of them already breaks the one-pass bound, *skip = 1 and the power
+// iterations do not run. xrow[I] receives the largest squared row norm of
+// row block I of X1 (one workgroup each).
+__global__ void __launch_bounds__(256)
+    x_rownorm_kernel(const double* __restrict__ X1, int64_t nb,
+                     const int* __restrict__ status, double* __restrict__ xrow) {
+  __shared__ double red[256];
+  if (*status) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t I = blockIdx.x;
+  // lane b, rows w + 4 u: row sums of squares over the tiles J >= I
+  double acc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+  for (int64_t J = I; J < nb; ++J) {
+    const double* tile = X1 + tix(I, J, nb);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const double e = tile[(w + 4 * u) * kP + lane];
+      acc[u] += e * e;
+    }
+  }
+  double mx = 0.0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    double a = acc[u];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    mx = a > mx ? a : mx;
+  }
+  red[t] = mx;
+  __syncthreads();
+  if (t == 0) {
+    const double m01 = red[0] > red[64] ? red[0] : red[64];
+    const double m23 = red[128] > red[192] ? red[128] : red[192];
+    xrow[I] = m01 > m23 ? m01 : m23;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    cq1_precheck_kernel(const double* __restrict__ R1,
+                        const double* __restrict__ gdiag,
+                        const double* __restrict__ xrow, int64_t nb, int64_t m,
+                        int64_t d, double bound, const int* __restrict__ status,
+                        int* __restrict__ skip) {
+  __shared__ double red[3][256];
+  const int t = threadIdx.x;
+  if (*status) {
+    if (t == 0) *skip = 1;
+    return;
+  }
+  // red[0]: min |R1_jj|, red[1]: max |R1_jj|, red[2]: max G_jj, and then
+  // max of xrow
+  double lo = 1.0 / 0.0, hi = 0.0, gm = 0.0, xm = 0.0;
+  for (int64_t j = t; j < d; j += 256) {
+    const int64_t I = j / kP, o = (j % kP) * kP + j % kP;
+    const double r = fabs(R1[tix(I, I, nb) + o]);
+    lo = r < lo ? r : lo;
+    hi = r > hi ? r : hi;
+    gm = gdiag[j] > gm ? gdiag[j] : gm;
+  }
+  for (int64_t I = t; I < nb; I += 256) xm = xrow[I] > xm ? xrow[I] : xm;
+  red[0][t] = lo;
+  red[1][t] = hi;
+  red[2][t] = gm;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      red[0][t] = red[0][t + o] < red[0][t] ? red[0][t + o] : red[0][t];
+      red[1][t] = red[1][t + o] > red[1][t] ? red[1][t + o] : red[1][t];
+      red[2][t] = red[2][t + o] > red[2][t] ? red[2][t + o] : red[2][t];
+    }
+    __syncthreads();
+  }
+  const double rlo = red[0][0], rhi = red[1][0], gmax = red[2][0];
+  __syncthreads();
+  red[0][t] = xm;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[0][t] = red[0][t + o] > red[0][t] ? red[0][t + o] : red[0][t];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double k1 = rhi / rlo;
+    const double k2 = sqrt(gmax * red[0][0]);
+    const double kl = k1 > k2 ? k1 : k2;
+    const bool ok = 4.0 * kl * kl * sqrt(static_cast<double>(m) * d) *
+                        0x1p-53 <= bound;  // false for NaN
+    *skip = ok ? 0 : 1;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    pow_init_kernel(int64_t nb, int64_t d, double* __restrict__ v,
+                    const int* __restrict__ skip) {
+  if (*skip) return;
+  const int64_t n = nb * kP;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < 2 * n; i += gridDim.x * 256) {
+    const int64_t j = i % n;
+    // signs and sizes from a multiplicative hash of the index
+    const uint32_t hsh = static_cast<uint32_t>(j) * 0x9E3779B9u;
+    const double val = (1.0 + static_cast<double>(hsh >> 22) / 1024.0) *
+                       ((hsh >> 21) & 1u ? -1.0 : 1.0);
+    v[i] = j < d ? val : 0.0;
+  }
+}
+
+// 1 / |x| of x[0 .. n), the same value in every workgroup
+__device__ double inv_norm(const double* __restrict__ x, int64_t n,
+                           double* red) {
+  const int t = threadIdx.x;
+  double acc = 0.0;
+  for (int64_t i = t; i < n; i += 256) acc += x[i] * x[i];
+  red[t] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r > 0.0 ? 1.0 / sqrt(r) : 0.0;
+}
+
+// y = T (x / |x|) (TRANS: T^T (x / |x|)) for T = R1 (y 0) or X1 (y 1);
+// workgroup blockIdx.x forms the 64 entries of row block I (TRANS: column
+// block J)
+template <bool TRANS>
+__global__ void __launch_bounds__(256)
+    pow_step_kernel(const double* __restrict__ R1, const double* __restrict__ X1,
+                    int64_t nb, const double* __restrict__ xin,
+                    double* __restrict__ yout, const int* __restrict__ skip) {
+  __shared__ double red[256];
+  __shared__ double xs[kP];
+  if (*skip) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t n = nb * kP;
+  const int mat = blockIdx.y;
+  const double* T = mat ? X1 : R1;
+  const double* x = xin + mat * n;
+  double* y = yout + mat * n;
+  const double inv = inv_norm(x, n, red);
+  const int64_t B = blockIdx.x;
+  if (!TRANS) {
+    // y_B[a] = sum_{J >= B} sum_b T_BJ[a][b] x_J[b]; lane b, rows w + 4 u
+    double acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+    for (int64_t J = B; J < nb; ++J) {
+      const double* tile = T + tix(B, J, nb);
+      const double xb = x[J * kP + lane];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[u] += tile[(w + 4 * u) * kP + lane] * xb;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      double a = acc[u];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+      if (lane == 0) y[B * kP + w + 4 * u] = a * inv;
+    }
+  } else {
+    // y_B[b] = sum_{I <= B} sum_a T_IB[a][b] x_I[a]; lane b, rows w + 4 u
+    double acc = 0.0;
+    for (int64_t I = 0; I <= B; ++I) {
+      const double* tile = T + tix(I, B, nb);
+      __syncthreads();
+      if (t < kP) xs[t] = x[I * kP + t];
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        acc += tile[(w + 4 * u) * kP + lane] * xs[w + 4 * u];
+    }
+    red[t] = acc;
+    __syncthreads();
+    if (t < kP) y[B * kP + t] = (red[t] + red[t + 64] + red[t + 128] + red[t + 192]) * inv;
+  }
+}
+
+// one workgroup: kappa_est = |R1 x^| |X1 y^| from the last forward products
+// (v holds R1 x^ and X1 y^ for unit x^, y^); when the one-pass bound holds,
+// min and max |R1_jj| into dstat and status 3
+__global__ void __launch_bounds__(256)
+    cq1_decide_kernel(const double* __restrict__ R1, int64_t nb, int64_t m,
+                      int64_t d, const double* __restrict__ v, double bound,
+                      const int* __restrict__ skip, double* __restrict__ dstat,
+                      double* __restrict__ kest, int* __restrict__ status) {
+  __shared__ double red[256];
+  __shared__ double rmin[256], rmax[256];
+  if (*status || *skip) return;
+  const int t = threadIdx.x;
+  const int64_t n = nb * kP;
+  const double sr = 1.0 / inv_norm(v, n, red);
+  const double sx = 1.0 / inv_norm(v + n, n, red);
+  const double kap = sr * sx;
+  if (kest && t == 0) *kest = kap;
+  const double u = 0x1p-53;
+  const bool ok = 4.0 * kap * kap * sqrt(static_cast<double>(m) * d) * u <= bound;
+  if (!ok) return;  // (false for NaN too)
+  double lo = 1.0 / 0.0, hi = 0.0;
+  for (int64_t j = t; j < d; j += 256) {
+    const int64_t I = j / kP, o = (j % kP) * kP + j % kP;
+    const double r = fabs(R1[tix(I, I, nb) + o]);
+    lo = r < lo ? r : lo;
+    hi = r > hi ? r : hi;
+  }
+  rmin[t] = lo;
+  rmax[t] = hi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      rmin[t] = rmin[t + o] < rmin[t] ? rmin[t + o] : rmin[t];
+      rmax[t] = rmax[t + o] > rmax[t] ? rmax[t + o] : rmax[t];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (dstat) {
+      dstat[0] = rmin[0];
+      dstat[1] = rmax[0];
+    }
+    *status = 3;
+  }
+}
+
+// R1 (tiled) into r_out (d x d row-major, zeros below the diagonal); with
+// status, only when *status = 3
+__global__ void __launch_bounds__(256)
+    r_copy_kernel(const double* __restrict__ R1, int64_t nb, int64_t d,
+                  const int* __restrict__ status, double* __restrict__ r_out) {
+  if (status && *status != 3) return;
+  const int64_t i = blockIdx.x / nb, j = blockIdx.x % nb;
+  const double* tile = R1 + tix(i, j, nb);
+  for (int e = threadIdx.x; e < kP * kP; e += 256) {
+    const int64_t gi = i * kP + e / kP, gj = j * kP + e % kP;
+    if (gi < d && gj < d) r_out[gi * d + gj] = gi <= gj && i <= j ? tile[e] : 0.0;
+  }
+}
+
 struct Cq2 {
   int64_t d, nb, nt, S, chunk, Se, chunk_e, nfull, nedge;
   int64_t C, Q, nwg;  // stream-K full blocks (Q > 0): units per block and
                       // per workgroup, workgroups; S: slots per block
   bool fe;  // edge products formed by the diagonal blocks (no edge launch)
-  double *part, *G, *R1, *R2, *X1, *X2, *P, *Dinv, *gdiag, *apart;
+  double *part, *G, *R1, *R2, *X1, *X2, *P, *Dinv, *gdiag, *apart, *pv, *kest;
   unsigned long long* emax;
 };
 
@@ -1175,6 +1436,9 @@ Cq2 cq2_carve(void* base, int64_t m, int64_t d) {
   c.Dinv = p;  p += c.nb * kT2;
   c.gdiag = p; p += c.nb * kP;
   c.emax = reinterpret_cast<unsigned long long*>(p);  // nt * 16 entries
+  p += c.nt * 16;
+  c.pv = p;    p += 4 * c.nb * kP;  // power-iteration vectors, two per matrix
+  c.kest = p;
   return c;
 }
 
@@ -1229,7 +1493,8 @@ size_t cholqr2_scratch_bytes(int64_t m, int64_t d) {
   return static_cast<size_t>((c.nfull * c.S + c.nedge * c.Se) * kB2 +
                              6 * c.nb * c.nb * kT2 +
                              tri_parts(c.nb) * c.nb * kT2 +
-                             c.nb * kT2 + c.nb * kP + c.nt * 16 + 8) *
+                             c.nb * kT2 + c.nb * kP + c.nt * 16 +
+                             4 * c.nb * kP + 8) *
          sizeof(double);
 }
 
@@ -1254,12 +1519,40 @@ void tri_apply(const Cq2& c, const double* T, int64_t d, const double* B,
 void cholqr2_factor(double* a, int64_t m, int64_t d, double* r_out,
                     void* scratch, int* status, const QrStreams& qs,
                     hipStream_t s, bool want_r, double* dstat,
-                    const double* dsc) {
+                    const double* dsc, int one_pass) {
   (void)qs;
   const Cq2 c = cq2_carve(scratch, m, d);
   launch_fill_i32(status, 1, 0, s);
   gram_tiles(a, m, d, c, false, dsc, status, s);
-  bchol(c, c.R1, want_r ? nullptr : c.X1, status, s);
+  bchol(c, c.R1, want_r && one_pass == 0 ? nullptr : c.X1, status, s);
+  // the one-pass forms (status 3 stops every later launch of this pass)
+  if (one_pass != 0) {
+    prof_begin(kKCq2R, s);
+    const unsigned nb = static_cast<unsigned>(c.nb);
+    const double bound = one_pass == 1 ? 1e-2 : 1e-7;
+    double* va = c.pv;
+    double* vb = c.pv + 2 * c.nb * kP;
+    int* skip = reinterpret_cast<int*>(c.kest + 1);
+    x_rownorm_kernel<<<nb, 256, 0, s>>>(c.X1, c.nb, status, va);
+    cq1_precheck_kernel<<<1, 256, 0, s>>>(c.R1, c.gdiag, va, c.nb, m, d, bound,
+                                          status, skip);
+    pow_init_kernel<<<8, 256, 0, s>>>(c.nb, d, va, skip);
+    for (int it = 0; it < kPowIters; ++it) {
+      pow_step_kernel<false><<<dim3(nb, 2), 256, 0, s>>>(c.R1, c.X1, c.nb, va,
+                                                         vb, skip);
+      pow_step_kernel<true><<<dim3(nb, 2), 256, 0, s>>>(c.R1, c.X1, c.nb, vb,
+                                                        va, skip);
+    }
+    pow_step_kernel<false><<<dim3(nb, 2), 256, 0, s>>>(c.R1, c.X1, c.nb, va, vb,
+                                                       skip);
+    cq1_decide_kernel<<<1, 256, 0, s>>>(c.R1, c.nb, m, d, vb, bound, skip,
+                                        want_r ? nullptr : dstat, c.kest,
+                                        status);
+    if (want_r)
+      r_copy_kernel<<<static_cast<unsigned>(c.nb * c.nb), 256, 0, s>>>(
+          c.R1, c.nb, d, status, r_out);
+    prof_end(kKCq2R, s);
+  }
   prof_begin(kKCq2Solve, s);
   stripe_solve_kernel<kStripeRows><<<cdivu(m, kStripeRows), 8 * kStripeRows, 0, s>>>(
       a, d, m, d, c.nb, c.R1, c.Dinv, dsc, status);
@@ -1291,10 +1584,13 @@ void cholqr2_finish(int64_t m, int64_t d, double* r_out, void* scratch,
 }
 
 void cholqr2_write_r(int64_t m, int64_t d, double* r_out, void* scratch,
-                     bool second, hipStream_t s) {
+                     int form, hipStream_t s) {
   const Cq2 c = cq2_carve(scratch, m, d);
   prof_begin(kKCq2R, s);
-  if (second)
+  if (form == 2)
+    r_copy_kernel<<<static_cast<unsigned>(c.nb * c.nb), 256, 0, s>>>(
+        c.R1, c.nb, d, nullptr, r_out);
+  else if (form == 1)
     r_final_kernel<false><<<static_cast<unsigned>(c.nb * c.nb), 256, 0, s>>>(
         c.R1, c.R2, c.nb, d, c.emax, nullptr, r_out);
   else
@@ -1303,14 +1599,15 @@ void cholqr2_write_r(int64_t m, int64_t d, double* r_out, void* scratch,
   prof_end(kKCq2R, s);
 }
 
-void cholqr2_apply_rinv(int64_t m, int64_t d, void* scratch, bool second,
+void cholqr2_apply_rinv(int64_t m, int64_t d, void* scratch, int form,
                         double* b, int64_t kk, hipStream_t s) {
   const Cq2 c = cq2_carve(scratch, m, d);
   prof_begin(kKTrsm, s);
-  // R^{-1} = R1^{-1} (I + F)^{-1} = X1 (I - F) to rounding, or X1 R2^{-1}
-  if (second)
+  // R^{-1} = R1^{-1} (I + F)^{-1} = X1 (I - F) to rounding (form 0), or
+  // X1 R2^{-1} (form 1), or X1 (form 2: one pass)
+  if (form == 1)
     tri_apply<0>(c, c.X2, d, b, kk, b, nullptr, s);
-  else
+  else if (form == 0)
     tri_apply<1>(c, c.G, d, b, kk, b, nullptr, s);
   tri_apply<0>(c, c.X1, d, b, kk, b, nullptr, s);
   prof_end(kKTrsm, s);

@@ -759,24 +759,24 @@ size_t qr_scratch_bytes(int64_t m, int64_t d) {
 }
 void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
                int* status, const QrStreams& qs, hipStream_t s, bool want_r,
-               double* dstat, const double* dsc) {
+               double* dstat, const double* dsc, int one_pass) {
   cholqr2_factor(a, m, d, r_out, static_cast<char*>(scratch) + tree_part(m),
-                 status, qs, s, want_r, dstat, dsc);
+                 status, qs, s, want_r, dstat, dsc, one_pass);
 }
 void qr_factor_finish(int64_t m, int64_t d, double* r_out, void* scratch,
                       int* status, hipStream_t s, bool want_r, double* dstat) {
   cholqr2_finish(m, d, r_out, static_cast<char*>(scratch) + tree_part(m),
                  status, s, want_r, dstat);
 }
-void qr_apply_rinv(int64_t m, int64_t d, void* scratch, bool second, double* b,
+void qr_apply_rinv(int64_t m, int64_t d, void* scratch, int form, double* b,
                    int64_t k, hipStream_t s) {
-  cholqr2_apply_rinv(m, d, static_cast<char*>(scratch) + tree_part(m), second,
+  cholqr2_apply_rinv(m, d, static_cast<char*>(scratch) + tree_part(m), form,
                      b, k, s);
 }
-void qr_write_r(int64_t m, int64_t d, double* r_out, void* scratch, bool second,
+void qr_write_r(int64_t m, int64_t d, double* r_out, void* scratch, int form,
                 hipStream_t s) {
   cholqr2_write_r(m, d, r_out, static_cast<char*>(scratch) + tree_part(m),
-                  second, s);
+                  form, s);
 }
 void qr_factor_panel(double* a, int64_t m, int64_t d, double* r_out,
                      void* scratch, int* fail, const QrStreams& qs,

@@ -968,15 +968,23 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   // should that fail too, column by column.
   // Without the refinement R itself is only needed if the rank screen trips:
   // Cholesky-QR2 then keeps R^{-1} in factored form and applies it to Pi_2.
+  // One pass of Cholesky-QR is taken (flags[2] = 3) when R1's condition
+  // estimate bounds the scores' error far below the gate, or, with the
+  // refinement (R only preconditions it), R^T R close enough to X's Gram.
   const bool want_r = gram;
-  bool cholqr2 = true, second = false, r_formed = want_r;
+  bool cholqr2 = true, second = false, one = false, r_formed = want_r;
   int32_t info_flags = 0;
   sketch();
   qr_factor(sx, r, d, RS, qws, flags + 2, c->qs, s, want_r, dstat,
-            unscaled ? dscale : nullptr);
+            unscaled ? dscale : nullptr, refine ? 1 : (want_r ? 0 : 2));
   post(want_r);
   if ((st = readback())) return st;
   if (fl[0]) return set_err(c, SLSO_ENONFINITE, "X holds Inf or NaN");
+  if (fl[2] == 3) {
+    info_flags |= SLSO_INFO_QR_ONE_PASS;
+    one = true;
+    fl[2] = 0;
+  }
   if (fl[2] == 2) {
     info_flags |= SLSO_INFO_QR_SECOND_CHOLESKY;
     second = true;
@@ -1021,12 +1029,12 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   int64_t rank = d;
   if (full) {
     if (cholqr2 && !want_r)
-      qr_apply_rinv(r, d, qws, second, pi, kk, s);
+      qr_apply_rinv(r, d, qws, one ? 2 : (second ? 1 : 0), pi, kk, s);
     else
       solve_upper(R, d, pi, kk, s, tws);
     launch_scale_rows(pi, rowfac, d, kk, m64, m32, s);
   } else {
-    if (!r_formed) qr_write_r(r, d, RS, qws, second, s);
+    if (!r_formed) qr_write_r(r, d, RS, qws, one ? 2 : (second ? 1 : 0), s);
     Sizer jz;
     jz.take<char>(jacobi_scratch_bytes(d, kk));
     // the Jacobi scratch reuses the sketch area, which is no longer needed
