@@ -83,6 +83,7 @@ PMC_SUMMARIES = {
         "score": "score_mfma_kernel<3,true>"}),
     "text": ("pmc_traffic_text_like_n500000_d4096.txt", {
         "countsketch": "countsketch_csr_kernel",
+        "cq2_gram": "gram_sk_kernel",
         "cq2_solve": "stripe_solve_kernel<64>",
         "score": "score_csr_kernel"}),
 }
@@ -699,6 +700,27 @@ def _counter_means(d: str, counter: str) -> dict:
     return {k: (len(v), sum(v.values()) / len(v)) for k, v in per.items()}
 
 
+def rocprof_counters(d: str) -> int:
+    """Mean per dispatch of every counter of a rocprofv3 --pmc CSV output
+    folder, for the library's kernels (one line per kernel)."""
+    from collections import defaultdict
+    per = defaultdict(lambda: defaultdict(lambda: defaultdict(float)))
+    for r in _rocprof_csv(d, "*counter_collection.csv"):
+        k = _short_name(_field(r, "Kernel_Name", "KernelName"))
+        c = _field(r, "Counter_Name", "CounterName")
+        per[k][c][_field(r, "Dispatch_Id", "DispatchId")] += float(
+            _field(r, "Counter_Value", "CounterValue"))
+    srcs = _kernel_sources()
+    for k in sorted(per):
+        if k.split("<")[0] not in srcs:
+            continue
+        cs = per[k]
+        nd = max(len(v) for v in cs.values())
+        print(f"counters {k} dispatches {nd} " + " ".join(
+            f"{c}={sum(v.values()) / len(v):.4g}" for c, v in sorted(cs.items())))
+    return 0
+
+
 def rocprof_traffic(fetch_dir: str, write_dir: str, cfetch_dir: str,
                     cwrite_dir: str, copy_mib: int) -> int:
     """HBM bytes per dispatch of every library kernel from a FETCH_SIZE and a
@@ -783,6 +805,9 @@ def main() -> int:
     ap.add_argument("--rocprof-stats", metavar="DIR",
                     help="only print the kernel statistics of a rocprofv3 "
                          "--kernel-trace --stats CSV output folder")
+    ap.add_argument("--rocprof-counters", metavar="DIR",
+                    help="only print mean counter values per dispatch of the "
+                         "library's kernels from a rocprofv3 --pmc CSV folder")
     ap.add_argument("--rocprof-traffic", nargs=5,
                     metavar=("FETCH", "WRITE", "CFETCH", "CWRITE", "MIB"),
                     help="only print HBM bytes per dispatch from rocprofv3 "
@@ -791,6 +816,8 @@ def main() -> int:
     args = ap.parse_args()
     if args.rocprof_stats:
         return rocprof_stats(args.rocprof_stats)
+    if args.rocprof_counters:
+        return rocprof_counters(args.rocprof_counters)
     if args.rocprof_traffic:
         f, w, cf, cw, mib = args.rocprof_traffic
         return rocprof_traffic(f, w, cf, cw, int(mib))
