@@ -55,6 +55,7 @@ class Shape:
     xbytes: int          # bytes per stored element of X (CSR: per nonzero)
     dtype: str           # "f32", "bf16", "fp8", "f64", "csr"
     nnz: int = 0
+    qr_passes: int = 2   # Cholesky-QR passes of the sketch (1: one pass)
 
 
 def log(msg: str) -> None:
@@ -159,10 +160,16 @@ def _roofline(name: str, sh: Shape, sec: float, launches: float):
         # entries of r products each when the last column block is at most
         # 16 wide (formed by the same launch), else the part inside full
         # 128-column blocks (c = 128 floor(d / 128))
+        # Each job launches both passes; after one pass the second launch
+        # exits at once, so the work of a launch is the passes' work over the
+        # launches
         c = d if d % 128 <= 16 else 128 * (d // 128)
-        return _rate("mfma", float(r) * c * (c + 1), sec, "fp64")
+        return _rate("mfma", sh.qr_passes * float(r) * c * (c + 1) / launches,
+                     sec, "fp64")
     if name == "cq2_solve":
-        # Q1 = A R1^{-1}: r d^2 flop
+        # Q1 = A R1^{-1}: r d^2 flop (not run after one pass)
+        if sh.qr_passes == 1:
+            return None
         return _rate("mfma", float(r) * d * d, sec, "fp64")
     if name in ("cq2_chol", "cq2_r"):
         # d^3 / 3 flop
@@ -468,7 +475,8 @@ def text_bench(args, slso, ctx, steps=None, warmup=None) -> dict:
         f"(nnz {c.nnz})")
     res = time_job(slso, ctx, x, n, seed, r, k, steps, warmup,
                    slso.COUNTSKETCH, label="text-like csr")
-    sh = Shape(n, d, r, k, 8, "csr", nnz=c.nnz)
+    sh = Shape(n, d, r, k, 8, "csr", nnz=c.nnz,
+               qr_passes=1 if res["flags"] & 32 else 2)
     roof, other = rooflines(res, sh, "text", ("cq2_gram", "cq2_solve",
                                               "cq2_chol", "countsketch",
                                               "score"))
@@ -501,7 +509,7 @@ def image_bench(args, slso, ctx) -> dict:
     nnz = args.nnz if args.sketch == "osnap" else 0
     res = time_job(slso, ctx, x, n, seed, r, k, args.steps, args.warmup, kind,
                    nnz=nnz, label="image-like")
-    sh = Shape(n, d, r, k, 4, "f32")
+    sh = Shape(n, d, r, k, 4, "f32", qr_passes=1 if res["flags"] & 32 else 2)
     roof, other = rooflines(res, sh, "image",
                             ("cq2_solve", "cq2_chol", "countsketch", "score"))
     out = {

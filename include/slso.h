@@ -8,7 +8,9 @@
  *   - leverage of row i of an n x d matrix A: the i-th diagonal entry of the
  *     hat matrix A (A^T A)^+ A^T, equal to ||U_i||^2 for A = U S V^T (Sec. 2.2);
  *   - the sketched approximation of Algorithm 2, in QR form: sketch S*X
- *     (Sec. 2.1), R from a Householder QR of the small sketch, scores
+ *     (Sec. 2.1), R of the small sketch (Cholesky-QR on the FP64 matrix
+ *     cores: one pass when a condition estimate allows it, two passes
+ *     otherwise, Householder QR when neither applies), scores
  *     ||x_i R^{-1} Pi_2||^2 with a second Gaussian projection Pi_2 (d x k),
  *     with the truncation of small singular values of Algorithm 3;
  *   - the "dec" ordering of Sec. 5.2: rows by decreasing score.
