@@ -130,6 +130,24 @@ typedef struct {
                             /* only: EUNSUPPORTED otherwise); the call then  */
                             /* synchronises its stream a few more times      */
 
+#define SLSO_OPT_NO_SYNC 4   /* slso_leverage enqueues the whole job and    */
+                             /* returns at once: the QR's passes, the form  */
+                             /* of R^{-1} and the rank screen are decided  */
+                             /* on the device, no host wait and no other   */
+                             /* stream (the call can be captured in a HIP  */
+                             /* graph once a call of its size has grown    */
+                             /* the workspace). info is filled by          */
+                             /* slso_leverage_finish, which the caller     */
+                             /* makes before the context's next            */
+                             /* slso_leverage call; cases the device path  */
+                             /* does not take (a Householder fallback, a   */
+                             /* truncation) are rerun there on the         */
+                             /* synchronous path. Not with the refinement, */
+                             /* SLSO_OPT_EPS_HAT or SLSO_OPT_SVD_RANK      */
+                             /* (EUNSUPPORTED). Calls on other streams     */
+                             /* that share the context are not ordered     */
+                             /* after it: the caller orders them.          */
+
 /* Host-side report of one leverage computation. */
 typedef struct {
   int64_t rank;        /* numerical rank used (d when nothing is truncated) */
@@ -156,6 +174,8 @@ typedef struct {
                                   /* panel path                              */
 #define SLSO_INFO_QR_TREE 16      /* ... and, that failing too, from the     */
                                   /* column-by-column Householder path       */
+#define SLSO_INFO_RERUN 64        /* slso_leverage_finish reran the job on   */
+                                  /* the synchronous path                    */
 #define SLSO_INFO_QR_ONE_PASS 32  /* the sketch's R is the first Cholesky-QR */
                                   /* pass's R1: R1's condition estimate      */
                                   /* kappa bounds the scores' relative error */
@@ -249,6 +269,16 @@ int slso_sketch_svd(slso_ctx* ctx, const slso_matrix* X, uint64_t seed,
 int slso_leverage(slso_ctx* ctx, const slso_matrix* X, uint64_t seed,
                   int64_t r, int64_t k, const slso_options* opt,
                   float* scores, slso_info* info, void* stream);
+
+/* Completes the context's last call made with SLSO_OPT_NO_SYNC (Algorithm
+ * 2 steps 2-4 on the device), or the last execution of a graph that
+ * captured it (the caller has waited for it): waits for that call's stream,
+ * fills info (host, may be NULL) and returns its status; when the device
+ * path did not apply (see SLSO_OPT_NO_SYNC) the job is rerun on the
+ * synchronous path into the same scores, info->flags then has
+ * SLSO_INFO_RERUN and the call's stream holds the rerun's work. EINVAL when
+ * the context made no such call. */
+int slso_leverage_finish(slso_ctx* ctx, slso_info* info);
 
 /* "dec" ordering (Sec. 5.2): perm[0] is the row of the largest score; equal
  * scores keep ascending row index (stable). scores (device) n floats,

@@ -27,13 +27,14 @@ EINVAL, ENOMEM, ENONFINITE, EDEVICE, EUNSUPPORTED = -1, -2, -3, -4, -5
 F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
 DENSE, CSR = 0, 1
 COUNTSKETCH, GAUSSIAN, OSNAP, SRHT = 0, 1, 2, 3
-OPT_SVD_RANK, OPT_EPS_HAT = 1, 2
+OPT_SVD_RANK, OPT_EPS_HAT, OPT_NO_SYNC = 1, 2, 4
 ORDER_DEC, ORDER_SWR, ORDER_SWOR = 0, 1, 2
 STREAM_GAUSS_S, STREAM_PI2 = 3, 4
 
 EXPORTED = (
     "slso_create", "slso_destroy", "slso_status_string", "slso_last_error",
-    "slso_sketch", "slso_sketch_svd", "slso_leverage", "slso_order",
+    "slso_sketch", "slso_sketch_svd", "slso_leverage", "slso_leverage_finish",
+    "slso_order",
     "slso_order_sample",
     "slso_hash",
     "slso_gaussian", "slso_gaussian_sketch_entries",
@@ -48,7 +49,7 @@ EXPORTED = (
 # slso_info.flags bits
 INFO_REFINED, INFO_REFINE_FAILED = 1, 2
 INFO_QR_SECOND_CHOLESKY, INFO_QR_HOUSEHOLDER, INFO_QR_TREE = 4, 8, 16
-INFO_QR_ONE_PASS = 32
+INFO_QR_ONE_PASS, INFO_RERUN = 32, 64
 QR_AUTO, QR_PANEL, QR_TREE, QR_CHOLQR2, QR_CHOLQR2_FULL = 0, 1, 2, 3, 4
 
 
@@ -128,6 +129,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "slso_leverage": ([vp, ctypes.POINTER(_Matrix), u64, i64, i64,
                            ctypes.POINTER(_Options), vp, ctypes.POINTER(_Info),
                            vp], ctypes.c_int),
+        "slso_leverage_finish": ([vp, ctypes.POINTER(_Info)], ctypes.c_int),
         "slso_order": ([vp, vp, i64, vp, vp], ctypes.c_int),
         "slso_order_sample": ([vp, vp, i64, i32, u64, ctypes.c_uint32, vp, vp],
                               ctypes.c_int),
@@ -368,23 +370,39 @@ class Context:
     def leverage(self, x, seed: int, r: int, k: int, sketch: int = COUNTSKETCH,
                  refine: bool = False, rank_tol: float = 0.0, out=None,
                  stream=None, nnz: int = 0, svd_rank: bool = False,
-                 eps_hat: bool = False):
+                 eps_hat: bool = False, no_sync: bool = False):
         """Scores (float32 device tensor) and the rank-decision info dict.
         ``nnz``: OSNAP nonzeros per column of S (0 selects 2); ``svd_rank``:
         decide the rank by the SVD of R every time; ``eps_hat``: report the
-        sketch's realised distortion on range(X) as info["eps_hat"]."""
+        sketch's realised distortion on range(X) as info["eps_hat"];
+        ``no_sync``: enqueue the whole job (capturable) and return (out,
+        None); leverage_finish() then gives the info dict."""
         import torch
         m = _matrix(x)
         self._here(_device(x))
         out = _out(out, torch.float32, _rows(x), _device(x), "out")
         opt = _Options(sketch, 1 if refine else 0, rank_tol, nnz,
                        (OPT_SVD_RANK if svd_rank else 0) |
-                       (OPT_EPS_HAT if eps_hat else 0))
+                       (OPT_EPS_HAT if eps_hat else 0) |
+                       (OPT_NO_SYNC if no_sync else 0))
         info = _Info()
         st = _check(load_library().slso_leverage(
             self._h, ctypes.byref(m), seed, r, k, ctypes.byref(opt), _ptr(out),
             ctypes.byref(info), _stream(stream)), self._h)
+        if no_sync:
+            self._keep = (x, m, out)  # the pending call's buffers
+            return out, None
         return out, _info_dict(info, st)
+
+    def leverage_finish(self):
+        """Info dict of the pending no-sync leverage call (waits for its
+        stream; a case the device path does not take is rerun there)."""
+        info = _Info()
+        st = _check(load_library().slso_leverage_finish(self._h,
+                                                        ctypes.byref(info)),
+                    self._h)
+        self._keep = None
+        return _info_dict(info, st)
 
     def order(self, scores, out=None, stream=None):
         import torch

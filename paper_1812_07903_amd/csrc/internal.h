@@ -54,6 +54,7 @@ void prof_end(int kid, hipStream_t s);
 // ---- context internals used by the serving loop (slso_capi.hip) -------------
 // Wait for the context's last use of its workspace and free it.
 int ctx_release_workspace(::slso_ctx* c);
+int ctx_reserve_workspace(::slso_ctx* c, size_t bytes);
 
 // ---- streams / ordering (k_sort.hip) ----------------------------------------
 // keys[i] = bucket h(row0+i), vals[i] = i | (sign bit << 31).
@@ -189,6 +190,11 @@ void qr_apply_rinv(int64_t m, int64_t d, void* scratch, int form, double* b,
                    int64_t k, hipStream_t s);  // b (d x k) <- R^{-1} b
 void qr_write_r(int64_t m, int64_t d, double* r_out, void* scratch, int form,
                 hipStream_t s);
+// no-sync forms of qr_factor_finish and qr_apply_rinv (see cholqr2_*_dev)
+void qr_finish_dev(int64_t m, int64_t d, void* scratch, const int* status,
+                   int* p2, double* dstat, hipStream_t s);
+void qr_apply_rinv_dev(int64_t m, int64_t d, void* scratch, const int* f,
+                       double* b, int64_t k, hipStream_t s);
 // Householder QR of a in place, r_out as above. 64-column panels by
 // Cholesky-QR2 with Householder reconstruction (k_cqr.hip), the remaining
 // columns by the tree path. *fail (device int) is set to 1 when a panel is
@@ -211,6 +217,17 @@ void cholqr2_finish(int64_t m, int64_t d, double* r_out, void* scratch,
                     int* status, hipStream_t s, bool want_r, double* dstat);
 void cholqr2_write_r(int64_t m, int64_t d, double* r_out, void* scratch,
                      int form, hipStream_t s);
+// The no-sync forms (every decision on the device): the second pass's
+// Cholesky when *status = 2 (p2 receives its exit flag, set on failure), the
+// choice of R^{-1}'s form and of the synchronous fallback (f[0..3]), and
+// the conditional product b <- R^{-1} b.
+void cholqr2_finish_dev(int64_t m, int64_t d, void* scratch, const int* status,
+                        int* p2, double* dstat, hipStream_t s);
+void cholqr2_decide_dev(const int* status, const int* p2, const double* dstat,
+                        double tol, const int* nonfinite, int* f,
+                        hipStream_t s);
+void cholqr2_apply_rinv_dev(int64_t m, int64_t d, void* scratch, const int* f,
+                            double* b, int64_t kk, hipStream_t s);
 void cholqr2_apply_rinv(int64_t m, int64_t d, void* scratch, int form,
                         double* b, int64_t k, hipStream_t s);
 // 64-column panel path (k_cqr.hip)

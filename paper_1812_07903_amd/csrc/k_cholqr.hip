@@ -1368,6 +1368,39 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// ---- a job without host decisions (the no-sync leverage path) --------------
+// out = 0 when *status == value, else 1 (the exit flag of a conditional pass)
+__global__ void status_select_kernel(const int* __restrict__ status, int value,
+                                     int* __restrict__ out) {
+  if (threadIdx.x == 0) *out = *status == value ? 0 : 1;
+}
+
+// After the first pass (status 0, 2, 3 or 1) and the conditional second
+// Cholesky (p2 = 0 when it ran and succeeded): which factored form of R^{-1}
+// applies, and whether the rank screen calls R full rank (min |R_jj| >
+// sqrt(tol) max |R_jj|, dstat of the path taken). f[0]: exit flag of the
+// (I - F) correction, f[1]: of R2^{-1}, f[2]: of R1^{-1} (0: apply);
+// f[3] = 1 when the job needs the synchronous path (a Householder fallback,
+// a failed second pass, a truncation, or non-finite input: nonfinite).
+__global__ void nosync_decide_kernel(const int* __restrict__ status,
+                                     const int* __restrict__ p2,
+                                     const double* __restrict__ dstat,
+                                     double tol,
+                                     const int* __restrict__ nonfinite,
+                                     int* __restrict__ f) {
+  if (threadIdx.x != 0) return;
+  const int st = *status;
+  const bool second = st == 2 && *p2 == 0;
+  const bool ok = st == 0 || st == 3 || second;
+  const double lo = dstat[0], hi = dstat[1];
+  const bool full = tol < 0.0 || (hi > 0.0 && lo > sqrt(tol) * hi);
+  const bool run = ok && full && *nonfinite == 0;
+  f[0] = run && st == 0 ? 0 : 1;
+  f[1] = run && second ? 0 : 1;
+  f[2] = run ? 0 : 1;
+  f[3] = run ? 0 : 1;
+}
+
 struct Cq2 {
   int64_t d, nb, nt, S, chunk, Se, chunk_e, nfull, nedge;
   int64_t C, Q, nwg;  // stream-K full blocks (Q > 0): units per block and
@@ -1610,6 +1643,33 @@ void cholqr2_apply_rinv(int64_t m, int64_t d, void* scratch, int form,
   else if (form == 0)
     tri_apply<1>(c, c.G, d, b, kk, b, nullptr, s);
   tri_apply<0>(c, c.X1, d, b, kk, b, nullptr, s);
+  prof_end(kKTrsm, s);
+}
+
+void cholqr2_finish_dev(int64_t m, int64_t d, void* scratch, const int* status,
+                        int* p2, double* dstat, hipStream_t s) {
+  const Cq2 c = cq2_carve(scratch, m, d);
+  status_select_kernel<<<1, 64, 0, s>>>(status, 2, p2);
+  bchol(c, c.R2, c.X2, p2, s);
+  prof_begin(kKCq2R, s);
+  r_diag_kernel<false><<<1, 256, 0, s>>>(c.R1, c.R2, c.gdiag, c.nb, d, c.emax,
+                                         p2, dstat);
+  prof_end(kKCq2R, s);
+}
+
+void cholqr2_decide_dev(const int* status, const int* p2, const double* dstat,
+                        double tol, const int* nonfinite, int* f,
+                        hipStream_t s) {
+  nosync_decide_kernel<<<1, 64, 0, s>>>(status, p2, dstat, tol, nonfinite, f);
+}
+
+void cholqr2_apply_rinv_dev(int64_t m, int64_t d, void* scratch, const int* f,
+                            double* b, int64_t kk, hipStream_t s) {
+  const Cq2 c = cq2_carve(scratch, m, d);
+  prof_begin(kKTrsm, s);
+  tri_apply<1>(c, c.G, d, b, kk, b, f + 0, s);
+  tri_apply<0>(c, c.X2, d, b, kk, b, f + 1, s);
+  tri_apply<0>(c, c.X1, d, b, kk, b, f + 2, s);
   prof_end(kKTrsm, s);
 }
 

@@ -773,6 +773,16 @@ void qr_apply_rinv(int64_t m, int64_t d, void* scratch, int form, double* b,
   cholqr2_apply_rinv(m, d, static_cast<char*>(scratch) + tree_part(m), form,
                      b, k, s);
 }
+void qr_finish_dev(int64_t m, int64_t d, void* scratch, const int* status,
+                   int* p2, double* dstat, hipStream_t s) {
+  cholqr2_finish_dev(m, d, static_cast<char*>(scratch) + tree_part(m), status,
+                     p2, dstat, s);
+}
+void qr_apply_rinv_dev(int64_t m, int64_t d, void* scratch, const int* f,
+                       double* b, int64_t k, hipStream_t s) {
+  cholqr2_apply_rinv_dev(m, d, static_cast<char*>(scratch) + tree_part(m), f,
+                         b, k, s);
+}
 void qr_write_r(int64_t m, int64_t d, double* r_out, void* scratch, int form,
                 hipStream_t s) {
   cholqr2_write_r(m, d, r_out, static_cast<char*>(scratch) + tree_part(m),

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <optional>
 #include <string>
 #include <vector>
 
@@ -14,6 +15,19 @@
 #include "slso.h"
 
 struct slso_ctx {
+  // the arguments of a no-sync slso_leverage call awaiting
+  // slso_leverage_finish
+  struct Pending {
+    bool valid = false;   // the arguments of the last no-sync call
+    bool active = false;  // its work may still be in flight
+    slso_matrix X{};
+    uint64_t seed = 0;
+    int64_t r = 0, k = 0;
+    slso_options o{};
+    float* scores = nullptr;
+    hipStream_t s = nullptr;
+    size_t ds_off = 0;
+  } pend;
   int device = 0;
   void* scratch = nullptr;  // this device's address of the scoring scratch
   void* ws = nullptr;       // device workspace
@@ -90,6 +104,7 @@ void prof_end(int kid, hipStream_t s) {
   open_kid = -1;
   open_ev = nullptr;
 }
+int ctx_reserve_workspace(slso_ctx* c, size_t bytes);
 int ctx_release_workspace(slso_ctx* c) {
   if (!c) return SLSO_EINVAL;
   if (!c->ws) return SLSO_OK;
@@ -185,7 +200,9 @@ int ensure_ws(slso_ctx* c, size_t bytes) {
   SLSO_HIP(c, hipSetDevice(c->device));
   if (c->ws) {
     // only this context's own earlier work can still be using the buffer
+    // (a pending no-sync call recorded no event: its stream is waited for)
     SLSO_HIP(c, hipEventSynchronize(c->ws_done));
+    if (c->pend.active) SLSO_HIP(c, hipStreamSynchronize(c->pend.s));
     SLSO_HIP(c, hipFree(c->ws));
     c->ws = nullptr;
     c->ws_bytes = 0;
@@ -322,7 +339,7 @@ int check_sketch_kind(slso_ctx* c, const slso_options& o, int64_t r,
     if (r > srht_rows_padded(X->n))
       return set_err(c, SLSO_EINVAL, "SRHT needs r <= n rounded up to a power of two");
   }
-  if ((o.flags & ~(SLSO_OPT_SVD_RANK | SLSO_OPT_EPS_HAT)) != 0)
+  if ((o.flags & ~(SLSO_OPT_SVD_RANK | SLSO_OPT_EPS_HAT | SLSO_OPT_NO_SYNC)) != 0)
     return set_err(c, SLSO_EINVAL, "unknown option flags");
   if (o.sketch == SLSO_OSNAP) {
     const int s = sketch_nnz(o);
@@ -438,6 +455,11 @@ int check_leverage(slso_ctx* c, const slso_matrix* X, int64_t r, int64_t k,
   if ((st = check_sketch_kind(c, *o, r, X))) return st;
   if (o->refine != 0 && o->refine != 1)
     return set_err(c, SLSO_EINVAL, "refine must be 0 or 1");
+  if ((o->flags & SLSO_OPT_NO_SYNC) != 0 &&
+      (o->refine != 0 || (o->flags & (SLSO_OPT_EPS_HAT | SLSO_OPT_SVD_RANK)) != 0))
+    return set_err(c, SLSO_EUNSUPPORTED,
+                   "SLSO_OPT_NO_SYNC takes neither the refinement, the "
+                   "distortion report nor the SVD rank mode");
   if ((o->sketch == SLSO_GAUSSIAN || o->refine == 1 ||
        (o->flags & SLSO_OPT_EPS_HAT) != 0) &&
       !mfma_input(X))
@@ -502,6 +524,7 @@ int slso_destroy(slso_ctx* c) {
   if (!c) return SLSO_EINVAL;
   (void)hipSetDevice(c->device);
   (void)hipEventSynchronize(c->ws_done);
+  if (c->pend.active) (void)hipStreamSynchronize(c->pend.s);
   if (c->ws) (void)hipFree(c->ws);
   (void)hipEventDestroy(c->ws_done);
   (void)hipEventDestroy(c->side_done);
@@ -805,11 +828,17 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   SLSO_HIP(c, hipSetDevice(c->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
 
+  // no-sync: every decision on the device, nothing waited for on the host
+  // and no other stream involved (the call can be captured in a graph); the
+  // caller orders calls that share the context and calls
+  // slso_leverage_finish
+  const bool nosync = (o.flags & SLSO_OPT_NO_SYNC) != 0;
   const size_t gemm_part = gemm_partial_bytes(X, r, gauss, gram);
   Sizer z;
   z.off = leverage_ws_bytes(X, r, k, o);
   if ((st = ensure_ws(c, z.off))) return st;
-  WsMark mark_{c, s};
+  std::optional<WsMark> mark_;
+  if (!nosync) mark_.emplace(c, s);
   Arena a{static_cast<char*>(c->ws)};
   SketchBufs sb{};
   float* cparts = nullptr;
@@ -857,7 +886,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   const bool gauss_eq = gauss && gauss_q_dtype(X->dtype);
   // 0. the bucket partition needs no input values: without the fused pass it
   // runs on the context's second stream while the column maxima are taken
-  const bool side_partition = nnz > 0 && !fuse && c->qs.side;
+  const bool side_partition = nnz > 0 && !fuse && c->qs.side && !nosync;
   if (side_partition) {
     SLSO_HIP(c, hipEventRecord(c->qs.factored, s));
     SLSO_HIP(c, hipStreamWaitEvent(c->qs.side, c->qs.factored, 0));
@@ -974,6 +1003,38 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   const bool want_r = gram;
   bool cholqr2 = true, second = false, one = false, r_formed = want_r;
   int32_t info_flags = 0;
+  if (nosync) {
+    // the common path with its branches taken on the device: the second
+    // pass runs only after status 2, the factored R^{-1} applies the form
+    // the passes left; a Householder fallback, a failed second pass, a
+    // truncation or non-finite input leave flags[15] set, and
+    // slso_leverage_finish then reruns the job on the synchronous path
+    sketch();
+    qr_factor(sx, r, d, RS, qws, flags + 2, c->qs, s, false, dstat,
+              unscaled ? dscale : nullptr, 2);
+    qr_finish_dev(r, d, qws, flags + 2, flags + 8, dstat, s);
+    cholqr2_decide_dev(flags + 2, flags + 8, dstat, tol, flags, flags + 12, s);
+    qr_apply_rinv_dev(r, d, qws, flags + 12, pi, kk, s);
+    launch_scale_rows(pi, rowfac, d, kk, m64, m32, s);
+    launch_scores(X->values, X->dtype, X->format, n, d, X->ld, X->row_ptr,
+                  X->col_idx, X->col_scale, X->row_scale, m64, m32, kk, scores,
+                  s, part);
+    SLSO_HIP(c, hipMemcpyAsync(c->host_buf, flags, ds_off + 4 * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    if ((st = check_launch(c, "slso_leverage (no-sync)"))) return st;
+    c->pend.valid = true;
+    c->pend.active = true;
+    c->pend.X = *X;
+    c->pend.seed = seed;
+    c->pend.r = r;
+    c->pend.k = k;
+    c->pend.o = o;
+    c->pend.scores = scores;
+    c->pend.s = s;
+    c->pend.ds_off = ds_off;
+    if (info) *info = slso_info{};
+    return SLSO_OK;
+  }
   sketch();
   qr_factor(sx, r, d, RS, qws, flags + 2, c->qs, s, want_r, dstat,
             unscaled ? dscale : nullptr, refine ? 1 : (want_r ? 0 : 2));
@@ -1077,6 +1138,40 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
     info->eps_hat = eps_hat;
   }
   return rank < d ? SLSO_RANK_DEFICIENT : SLSO_OK;
+}
+
+int slso_leverage_finish(slso_ctx* c, slso_info* info) {
+  if (!c) return SLSO_EINVAL;
+  if (!c->pend.valid)
+    return set_err(c, SLSO_EINVAL, "no no-sync slso_leverage call was made");
+  const slso_ctx::Pending p = c->pend;
+  SLSO_HIP(c, hipSetDevice(c->device));
+  SLSO_HIP(c, hipStreamSynchronize(p.s));
+  c->pend.active = false;
+  int fl[16];
+  double ds[4];
+  const char* hb = static_cast<const char*>(c->host_buf);
+  std::memcpy(fl, hb, sizeof(fl));
+  std::memcpy(ds, hb + p.ds_off, sizeof(ds));
+  if (fl[0]) return set_err(c, SLSO_ENONFINITE, "X holds Inf or NaN");
+  if (fl[15]) {
+    slso_options o = p.o;
+    o.flags &= ~SLSO_OPT_NO_SYNC;
+    const int st = slso_leverage(c, &p.X, p.seed, p.r, p.k, &o, p.scores, info,
+                                 p.s);
+    if (st >= 0 && info) info->flags |= SLSO_INFO_RERUN;
+    return st;
+  }
+  if (info) {
+    info->rank = p.X.d;
+    info->screen_full = 1;
+    info->flags = (fl[2] == 3 ? SLSO_INFO_QR_ONE_PASS : 0) |
+                  (fl[2] == 2 ? SLSO_INFO_QR_SECOND_CHOLESKY : 0);
+    info->diag_min = ds[0];
+    info->diag_max = ds[1];
+    info->eps_hat = std::nan("");
+  }
+  return SLSO_OK;
 }
 
 int slso_workspace_size(const slso_matrix* X, int64_t r, int64_t k,
@@ -1204,3 +1299,13 @@ const char* slso_profile_name(int id) {
 }
 
 }  // extern "C"
+
+namespace slso {
+// grow the context's workspace to at least `bytes` now (the serving loop's
+// headroom); nothing happens when it is that large already
+int ctx_reserve_workspace(slso_ctx* c, size_t bytes) {
+  if (!c) return SLSO_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return SLSO_EDEVICE;
+  return ensure_ws(c, bytes);
+}
+}  // namespace slso

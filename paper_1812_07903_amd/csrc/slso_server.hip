@@ -19,6 +19,7 @@
 // Each job's result equals the result of the same slso_leverage (+ slso_order)
 // call made alone: every kernel sums in a fixed order, so the result does not
 // depend on what else runs on the device.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -131,9 +132,20 @@ void worker(slso_server* S, int i) {
       continue;
     }
     Slot& sl = S->slots[i];
-    if (j->need > sl.cap) {  // reserve before the context grows
-      S->allocated += j->need - sl.cap;
-      sl.cap = j->need;
+    size_t grow = 0;
+    if (j->need > sl.cap) {
+      // reserve before the context grows, with headroom (up to twice the
+      // job's need, within the slot's share of the budget and the budget
+      // left) so that later jobs rarely make it grow again: a workspace
+      // that grows frees its old buffer, which waits for the whole device
+      size_t want = j->need;
+      const size_t share = S->budget / S->slots.size();
+      // (whole 2 MiB units: the granularity the context allocates in)
+      const size_t head = std::min(2 * j->need, share) >> 21 << 21;
+      if (head > want && S->allocated - sl.cap + head <= S->budget) want = head;
+      S->allocated += want - sl.cap;
+      sl.cap = want;
+      grow = want;
     }
     sl.cur = j;
     j->slot = i;
@@ -143,14 +155,34 @@ void worker(slso_server* S, int i) {
     lk.unlock();
 
     const slso_job& d = j->desc;
-    int st = slso_leverage(sl.ctx, &d.X, d.seed, d.r, d.k, &d.opt, d.scores,
-                           &j->info, sl.stream);
+    int st = grow ? slso::ctx_reserve_workspace(sl.ctx, grow) : SLSO_OK;
+    // the job as one enqueue (no host wait between its stages) when its
+    // options allow; the rare cases the device path leaves to the host are
+    // rerun by slso_leverage_finish
+    slso_options o = d.opt;
+    const bool ns = o.refine == 0 &&
+                    (o.flags & (SLSO_OPT_EPS_HAT | SLSO_OPT_SVD_RANK)) == 0;
+    if (ns) o.flags |= SLSO_OPT_NO_SYNC;
+    if (st >= 0)
+      st = slso_leverage(sl.ctx, &d.X, d.seed, d.r, d.k, &o, d.scores, &j->info,
+                         sl.stream);
+    const bool pending = ns && st >= 0;
     if (st >= 0 && d.perm) {
       const int so = slso_order(sl.ctx, d.scores, d.X.n, d.perm, sl.stream);
       if (so < 0) st = so;
     }
     if (hipStreamSynchronize(sl.stream) != hipSuccess && st >= 0)
       st = SLSO_EDEVICE;
+    if (pending) {
+      const int fs = slso_leverage_finish(sl.ctx, &j->info);
+      if (st >= 0) st = fs;
+      if (st >= 0 && (j->info.flags & SLSO_INFO_RERUN) && d.perm) {
+        const int so = slso_order(sl.ctx, d.scores, d.X.n, d.perm, sl.stream);
+        if (so < 0) st = so;
+        if (hipStreamSynchronize(sl.stream) != hipSuccess && st >= 0)
+          st = SLSO_EDEVICE;
+      }
+    }
 
     lk.lock();
     j->status = st;

@@ -110,9 +110,22 @@ def test_osnap_argument_errors(lib):
     assert _ws(lib, m, 16, 4, sketch=slso.OSNAP, nnz=3)[0] == slso.EINVAL   # 3 does not divide 16
     assert _ws(lib, m, 32, 4, sketch=slso.OSNAP, nnz=32)[0] == slso.EINVAL  # above 16
     assert _ws(lib, m, 16, 4, sketch=slso.OSNAP, nnz=-1)[0] == slso.EINVAL
-    assert _ws(lib, m, 16, 4, flags=4)[0] == slso.EINVAL                  # unknown flag
+    assert _ws(lib, m, 16, 4, flags=8)[0] == slso.EINVAL                  # unknown flag
     assert _ws(lib, m, 16, 4, flags=slso.OPT_EPS_HAT)[0] == slso.OK
     assert _ws(lib, m, 16, 4, flags=slso.OPT_SVD_RANK)[0] == slso.OK
+    assert _ws(lib, m, 16, 4, flags=slso.OPT_NO_SYNC)[0] == slso.OK
+
+
+def test_no_sync_option_combinations(lib):
+    """The device-decided path takes neither the refinement, the distortion
+    report nor the SVD rank mode (each needs a host decision or read-back)."""
+    m = _mat(1000, 16, slso.F32)
+    ns = slso.OPT_NO_SYNC
+    assert _ws(lib, m, 64, 4, flags=ns)[0] == slso.OK
+    assert _ws(lib, m, 64, 4, sketch=slso.GAUSSIAN, flags=ns)[0] == slso.OK
+    assert _ws(lib, m, 64, 4, refine=1, flags=ns)[0] == slso.EUNSUPPORTED
+    assert _ws(lib, m, 64, 4, flags=ns | slso.OPT_EPS_HAT)[0] == slso.EUNSUPPORTED
+    assert _ws(lib, m, 64, 4, flags=ns | slso.OPT_SVD_RANK)[0] == slso.EUNSUPPORTED
     assert _ws(lib, m, 16, 4, sketch=4)[0] == slso.EINVAL                # unknown sketch
     assert _ws(lib, m, 16, 4, sketch=slso.OSNAP, nnz=16)[0] == slso.OK
 

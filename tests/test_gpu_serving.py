@@ -27,18 +27,18 @@ def slso():
     return m
 
 
-def _jobs(n_jobs, seed=7, n_max=60000):
-    """Serving-shaped jobs: n log-uniform, d from {64, 128, 256},
-    FP32/BF16 half and half, r = d * U{4..8}, k = 32, data like the plain
-    small workload with a per-job seed."""
+def _jobs(n_jobs, seed=7, n_max=60000, d_values=(64, 128, 256), n_min=2000):
+    """Serving-shaped jobs: n log-uniform, d from d_values, FP32/BF16 half
+    and half, r = d * U{4..8}, k = 32, data like the plain small workload
+    with a per-job seed."""
     rng = np.random.default_rng(seed)
     out = []
     for j in range(n_jobs):
-        n = int(np.exp(rng.uniform(np.log(2000), np.log(n_max))))
-        d = int(rng.choice([64, 128, 256]))
+        n = int(np.exp(rng.uniform(np.log(n_min), np.log(n_max))))
+        d = int(rng.choice(d_values))
         x64 = synth.lowrank_dense(n, d, d // 2,
-                                  2.0 ** (-np.arange(d // 2) / 4.0), 1e-3, 1.0,
-                                  seed=5000 + j)
+                                  2.0 ** (-np.arange(d // 2) / 4.0), 1e-3,
+                                  1.0, seed=5000 + j)
         if j % 2 == 0:
             x = torch.from_numpy(x64.astype(np.float32)).cuda()
         else:
@@ -60,6 +60,45 @@ def _alone(slso, jobs):
         res.append((sc.cpu().numpy(), pm.cpu().numpy(), info["rank"]))
     ctx.close()
     return res
+
+
+def _check_mix(slso, jobs, slots, budget):
+    alone = _alone(slso, jobs)
+    srv = slso.Server(0, slots=slots, hbm_budget=budget)
+    tickets = [srv.submit(jb["x"], jb["seed"], jb["r"], jb["k"]) for jb in jobs]
+    results = [srv.wait(t) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    print(f"[serving mix d<={max(jb['d'] for jb in jobs)}] "
+          f"max_running={stats['max_running']} completed={stats['completed']} "
+          f"allocated={stats['allocated_bytes'] >> 20} MiB", flush=True)
+    assert stats["completed"] == len(jobs)
+    assert stats["max_running"] >= 2          # jobs overlapped on the device
+    for jb, t, res, (sc, pm, rank) in zip(jobs, tickets, results, alone):
+        assert res["status"] >= 0, res
+        assert res["info"]["rank"] == rank
+        assert np.array_equal(t.scores.cpu().numpy().view(np.uint32),
+                              sc.view(np.uint32))
+        assert np.array_equal(t.perm.cpu().numpy(), pm)
+    return results
+
+
+def test_mixed_jobs_wide_equal_alone(slso):
+    """Jobs of d up to 1024 (the serving pool's widest), n 20000..60000,
+    with one noise-free rank-deficient job among them: the server runs
+    its jobs with the decisions on the device, the truncated one is rerun
+    on the host path, and every result equals the synchronous call made
+    alone, bit for bit."""
+    jobs = _jobs(6, seed=19, n_min=20000, d_values=(512, 768, 1024))
+    # rank <= 64 in d = 128: each column twice
+    half = synth.lowrank_dense(6007, 64, 32, 2.0 ** (-np.arange(32) / 4.0),
+                               1e-3, 1.0, seed=23).astype(np.float32)
+    x = torch.from_numpy(np.hstack([half, half])).cuda()
+    jobs.insert(3, {"x": x, "seed": 77, "r": 512, "k": 32, "n": 6007,
+                    "d": 128})
+    results = _check_mix(slso, jobs, slots=4, budget=48 << 30)
+    assert results[3]["info"]["rank"] <= 64
+    assert results[3]["info"]["flags"] & slso.INFO_RERUN
 
 
 def test_mixed_jobs_equal_alone(slso):
