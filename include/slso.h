@@ -182,7 +182,9 @@ typedef struct {
                                   /* 4 kappa^2 sqrt(r d) 2^-53 by 1e-7 (by   */
                                   /* 1e-2 with the refinement, where R only  */
                                   /* preconditions); Algorithm 2 step 2      */
-                                  /* needs only R^T R of the sketch          */
+                                  /* needs only R^T R of the sketch. Tried   */
+                                  /* only when 2 r d^2 >= 2^31, where the    */
+                                  /* second pass costs more than the estimate*/
 
 /* ---- context ------------------------------------------------------------ */
 

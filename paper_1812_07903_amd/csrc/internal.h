@@ -172,7 +172,8 @@ size_t qr_scratch_bytes(int64_t m, int64_t d);
 // as they are read; the factorisation is then that of a diag(dsc), with the
 // same rounding as if a had been scaled first. one_pass: 0 two passes; 2
 // one when the condition estimate of R1 bounds the score error far below
-// the gate; 1 the same with the looser bound of a preconditioner.
+// the gate; 1 the same with the looser bound of a preconditioner (both only
+// where 2 m d^2 >= 2^31: smaller factorisations always take two passes).
 void qr_factor(double* a, int64_t m, int64_t d, double* r_out, void* scratch,
                int* status, const QrStreams& qs, hipStream_t s,
                bool want_r = true, double* dstat = nullptr,

@@ -35,7 +35,10 @@
 // R1 and on R1^{-1} (a lower bound of kappa, hence the factor 4 = 2^2):
 // status 3, R = R1. With one_pass = 1 (the sketch factor only preconditions
 // the refinement, which needs R^{-T} A^T A R^{-1} near I, not R itself) the
-// bound is 1e-2.
+// bound is 1e-2. The estimate is a chain of about 17 small launches (about
+// 0.1 ms at d = 256 to 512); it is only tried when the second pass's two
+// m d^2 products (its Gram and Q1 = A R1^{-1}) reach 2^31 flop each, where
+// they take longer than the estimate: below that both passes always run.
 //
 // Data layout. d x d matrices are kept as nb x nb tiles of 64 x 64 (tile
 // (I, J) at (I nb + J) 4096, row-major inside), padded past d with the
@@ -146,6 +149,7 @@ __device__ __forceinline__ void tile_to_global(double* g, const double* T,
 // A_I2^T A_e instead (8 + 4 MFMA blocks against the 16 of waves 0 and 1),
 // and wave 2 of block (0, 0) also the corner A_e^T A_e; S_e = S.
 constexpr int kGK = 16;    // rows per step
+constexpr int64_t kGMin = 64;  // fewest rows of a workgroup's chunk
 constexpr int kGS = 144;   // LDS row stride: rows 4 apart fall on the other
                            // half of the banks
 constexpr int64_t kB2 = 128 * 128;
@@ -1418,12 +1422,13 @@ Cq2 cq2_shape(int64_t m, int64_t d) {
   // Gram row chunks: blocks of full 128-column blocks take at most 512
   // workgroups in all (two per CU: one round), the edge blocks (thin: their
   // time is load latency, so they get many short chunks) at most 512;
-  // chunks of at least 256 rows
+  // chunks of at least kGMin rows (a workgroup's chain of 16-row steps is
+  // latency bound: a short matrix is split into short chains)
   const int64_t nf = d / 128;
   c.nfull = nf * (nf + 1) / 2;
   c.nedge = d % 128 ? nf + 1 : 0;
   const int64_t steps = (m + kGK - 1) / kGK;
-  const int64_t smax = (m + 255) / 256 > 1 ? (m + 255) / 256 : 1;
+  const int64_t smax = (m + kGMin - 1) / kGMin > 1 ? (m + kGMin - 1) / kGMin : 1;
   auto pick = [&](int64_t slots, int64_t blocks, int64_t& S, int64_t& chunk) {
     S = blocks > 0 ? slots / blocks : 1;
     if (S > smax) S = smax;
@@ -1440,11 +1445,11 @@ Cq2 cq2_shape(int64_t m, int64_t d) {
              8 * c.nfull * c.S < 7 * 512 * ((c.nfull * c.S + 511) / 512)) {
     // the rounds of the 512 slots less than seven eighths busy (528 blocks
     // at d = 4096: two rounds, the second nearly empty): the stream-K form,
-    // with at least 256 rows per unit and 32 units per block where the rows
-    // allow, one round of at most 512 equal workgroups
+    // with at least kGMin rows per unit and 32 units per block where the
+    // rows allow, one round of at most 512 equal workgroups
     c.C = 32;
     const int64_t rows = (m + c.C - 1) / c.C;
-    if (rows < 256) c.C = (m + 255) / 256 > 1 ? (m + 255) / 256 : 1;
+    if (rows < kGMin) c.C = smax;
     c.chunk = ((m + c.C - 1) / c.C + kGK - 1) / kGK * kGK;
     c.C = (m + c.chunk - 1) / c.chunk;
     const int64_t U = c.nfull * c.C;
@@ -1554,6 +1559,8 @@ void cholqr2_factor(double* a, int64_t m, int64_t d, double* r_out,
                     hipStream_t s, bool want_r, double* dstat,
                     const double* dsc, int one_pass) {
   (void)qs;
+  if (2.0 * static_cast<double>(m) * static_cast<double>(d) * d < 0x1p31)
+    one_pass = 0;
   const Cq2 c = cq2_carve(scratch, m, d);
   launch_fill_i32(status, 1, 0, s);
   gram_tiles(a, m, d, c, false, dsc, status, s);

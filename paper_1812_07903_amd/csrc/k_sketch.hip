@@ -198,15 +198,18 @@ __global__ void mul_scale_kernel(const double* __restrict__ a,
 // ---- CountSketch with the column maxima in the same pass ----------------------
 // Dense F32 / BF16 / FP8 input whose rows start on 4-element boundaries. One
 // wave per bucket (waves stride over the buckets); lane l owns columns
-// 4 (l + 64 u) .. + 3, u < 4, of each 1024-column chunk and reads them as one
-// 4-element vector per row, so a row is one pass of coalesced loads. The
-// signed FP64 sums are those of countsketch_dense_kernel, in the same order,
-// times the FP8 column scale; the power-of-two equilibration D is left to the
-// consumer (scaling by a power of two is exact, so the consumer sees the same
-// numbers); OSNAP sums are multiplied once by 1/sqrt(nnz). Every row is read
-// (nnz times for OSNAP), so the column max-abs values come from the same loads: per workgroup into parts[blockIdx][col], reduced by
-// colmax_parts_kernel.
-constexpr int kSkChunk = 1024;
+// 4 (l + 64 u) .. + 3, u < U, of each 256 U-column chunk (U = 1, 2 or 4, the
+// fewest that cover d up to 1024) and reads them as one 4-element vector per
+// row, so a row is one pass of coalesced loads. NR rows of the bucket are
+// loaded at a time (16, 8 or 4: narrower rows leave registers for more
+// loads in flight), and the next NR row-list entries are read while they
+// are summed. The signed FP64 sums are those of countsketch_dense_kernel,
+// in the same order, times the FP8 column scale; the power-of-two
+// equilibration D is left to the consumer (scaling by a power of two is
+// exact, so the consumer sees the same numbers); OSNAP sums are multiplied
+// once by 1/sqrt(nnz). Every row is read (nnz times for OSNAP), so the
+// column max-abs values come from the same loads: per workgroup into
+// parts[blockIdx][col], reduced by colmax_parts_kernel.
 constexpr int kSkMaxGroups = 1024;
 
 __device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
@@ -238,7 +241,7 @@ __device__ __forceinline__ float elem_f(const uint8_t* p, int64_t i) {
 }
 
 // kTail: d % 4 != 0 (rows end in a partial vector)
-template <typename T, bool kTail>
+template <typename T, bool kTail, int U, int NR>
 __global__ void __launch_bounds__(256)
     countsketch_colmax_kernel(const T* __restrict__ x, int64_t d, int64_t ld,
                               const float* __restrict__ col_scale,
@@ -247,15 +250,17 @@ __global__ void __launch_bounds__(256)
                               float* __restrict__ parts, int* nonfinite,
                               double* __restrict__ sx, double sscale) {
   constexpr bool kFp8 = sizeof(T) == 1;  // codes times the column scale
-  __shared__ float wmax[4][kSkChunk];
+  constexpr int kW = 256 * U;            // columns per chunk
+  constexpr int kE = 4 * U;              // columns per lane
+  __shared__ float wmax[4][kW];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * 4;
   bool bad = false;
-  for (int64_t c0 = 0; c0 < d; c0 += kSkChunk) {
-    float cm[16];
-    double cs[16];
+  for (int64_t c0 = 0; c0 < d; c0 += kW) {
+    float cm[kE];
+    double cs[kE];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t c = c0 + 4 * (lane + 64 * u) + e;
@@ -264,29 +269,30 @@ __global__ void __launch_bounds__(256)
       }
     for (int64_t b = static_cast<int64_t>(blockIdx.x) * 4 + wv; b < r; b += nwaves) {
       const int p0 = off[b], p1 = off[b + 1];
-      double acc[16];
+      double acc[kE];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[e] = 0.0;
-      // rows four at a time: all their loads are issued before the sums,
-      // which still run row by row in ascending order
-      for (int p = p0; p < p1; p += 4) {
-        float xv[4][16];
-        bool neg[4];
-        // branch-free loads (a row past the bucket repeats its last row, a
-        // vector past the end reads the row start; both are masked): the row
-        // list entries first, then every vector, so all stay in flight
-        // together
-        const T* xr[4];
+      for (int e = 0; e < kE; ++e) acc[e] = 0.0;
+      // the row-list entries of the first NR rows (a row past the bucket
+      // repeats its last row and is masked below)
+      uint32_t vn[NR];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const uint32_t v = sorted_vals[p + j < p1 ? p + j : p1 - 1];
-          neg[j] = (v >> 31) != 0;
-          xr[j] = x + static_cast<int64_t>(v & 0x7fffffffu) * ld;
+      for (int j = 0; j < NR; ++j)
+        vn[j] = p0 < p1 ? sorted_vals[p0 + j < p1 ? p0 + j : p1 - 1] : 0u;
+      for (int p = p0; p < p1; p += NR) {
+        bool neg[NR];
+        const T* xr[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+          neg[j] = (vn[j] >> 31) != 0;
+          xr[j] = x + static_cast<int64_t>(vn[j] & 0x7fffffffu) * ld;
         }
+        // branch-free loads (a vector past the end reads the row start and
+        // is masked), all in flight together, then the next entries
+        float xv[NR][kE];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < NR; ++j)
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < U; ++u) {
             const int64_t c = c0 + 4 * (lane + 64 * u);
             const bool full = c + 4 <= d;
             float q[4];
@@ -294,12 +300,16 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int e = 0; e < 4; ++e) xv[j][4 * u + e] = full ? q[e] : 0.0f;
           }
+        const int pn = p + NR;
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+          vn[j] = sorted_vals[pn + j < p1 ? pn + j : p1 - 1];
         if (kTail) {
           // the partial last vector of each row, element by element
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < NR; ++j)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < U; ++u) {
               const int64_t c = c0 + 4 * (lane + 64 * u);
 #pragma unroll
               for (int e = 0; e < 4; ++e) {
@@ -312,10 +322,10 @@ __global__ void __launch_bounds__(256)
         // sums in row order; a repeated row (past the bucket) is added with
         // weight zero and changes no maximum
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NR; ++j) {
           const double sg = p + j < p1 ? (neg[j] ? -1.0 : 1.0) : 0.0;
 #pragma unroll
-          for (int e = 0; e < 16; ++e) {
+          for (int e = 0; e < kE; ++e) {
             const float a = fabsf(xv[j][e]);
             bad |= !(a <= 3.402823466e38f);
             cm[e] = fmaxf(cm[e], a);
@@ -324,7 +334,7 @@ __global__ void __launch_bounds__(256)
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int64_t c = c0 + 4 * (lane + 64 * u) + e;
@@ -334,11 +344,11 @@ __global__ void __launch_bounds__(256)
         }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int e = 0; e < 4; ++e) wmax[wv][4 * (lane + 64 * u) + e] = cm[4 * u + e];
     __syncthreads();
-    for (int j = threadIdx.x; j < kSkChunk; j += 256) {
+    for (int j = threadIdx.x; j < kW; j += 256) {
       const float m = fmaxf(fmaxf(wmax[0][j], wmax[1][j]), fmaxf(wmax[2][j], wmax[3][j]));
       if (c0 + j < d) parts[static_cast<int64_t>(blockIdx.x) * d + c0 + j] = m;
     }
@@ -542,16 +552,23 @@ bool launch_countsketch_colmax(const void* x, int dtype, int64_t d, int64_t ld,
   const unsigned g = static_cast<unsigned>(groups);
   prof_begin(kKSketch, s);
   const bool tail = d % 4 != 0;
+  // chunk width 256 U: one chunk for d up to 1024
+  const int U = d <= 256 ? 1 : (d <= 512 ? 2 : 4);
+#define SLSO_CS_GO(T, CS, TL, UU, NR)                                           \
+  countsketch_colmax_kernel<T, TL, UU, NR><<<g, 256, 0, s>>>(                   \
+      static_cast<const T*>(x), d, ld, CS, sorted_vals, offsets, r, parts,     \
+      nonfinite, sx, sscale)
 #define SLSO_CS_LAUNCH(T, CS)                                                   \
   do {                                                                          \
-    if (tail)                                                                   \
-      countsketch_colmax_kernel<T, true><<<g, 256, 0, s>>>(                     \
-          static_cast<const T*>(x), d, ld, CS, sorted_vals, offsets, r, parts, \
-          nonfinite, sx, sscale);                                               \
-    else                                                                        \
-      countsketch_colmax_kernel<T, false><<<g, 256, 0, s>>>(                    \
-          static_cast<const T*>(x), d, ld, CS, sorted_vals, offsets, r, parts, \
-          nonfinite, sx, sscale);                                               \
+    if (tail) {                                                                 \
+      if (U == 1) SLSO_CS_GO(T, CS, true, 1, 16);                               \
+      else if (U == 2) SLSO_CS_GO(T, CS, true, 2, 8);                           \
+      else SLSO_CS_GO(T, CS, true, 4, 4);                                       \
+    } else {                                                                    \
+      if (U == 1) SLSO_CS_GO(T, CS, false, 1, 16);                              \
+      else if (U == 2) SLSO_CS_GO(T, CS, false, 2, 8);                          \
+      else SLSO_CS_GO(T, CS, false, 4, 4);                                      \
+    }                                                                           \
   } while (0)
   if (dtype == 1)
     SLSO_CS_LAUNCH(float, nullptr);
@@ -560,6 +577,7 @@ bool launch_countsketch_colmax(const void* x, int dtype, int64_t d, int64_t ld,
   else
     SLSO_CS_LAUNCH(uint8_t, col_scale);
 #undef SLSO_CS_LAUNCH
+#undef SLSO_CS_GO
   prof_end(kKSketch, s);
   colmax_parts_kernel<<<grid1(d, 4), 256, 0, s>>>(
       parts, groups, d, dtype == 3 ? col_scale : nullptr, nonfinite, dscale);

@@ -167,11 +167,12 @@ def test_fp8_countsketch_leverage(slso, ctx):
 
 @pytest.mark.parametrize("kind,d,pad", [
     ("f32", 70, 2), ("bf16", 70, 2), ("fp8", 70, 2), ("f32", 64, 0),
-    ("f32", 33, 3), ("fp8", 33, 0)])
+    ("f32", 33, 3), ("fp8", 33, 0), ("f32", 514, 2), ("bf16", 1030, 2)])
 def test_countsketch_leverage_strided_rows(slso, ctx, kind, d, pad):
     """Row stride d + pad: the CountSketch that takes the column maxima in the
     same pass (rows starting on 4-element boundaries, a partial last vector
-    when d % 4 != 0) and, for a row stride of 33, the two-pass path."""
+    when d % 4 != 0, in each of its width forms: d = 70, 514 and 1030) and,
+    for a row stride of 33, the two-pass path."""
     x64 = synth.config0(n=3001, d=d, seed=23)
     xin, xval, _ = as_input(slso, np.pad(x64, ((0, 0), (0, pad))), kind)
     xval = xval[:, :d]
@@ -179,9 +180,10 @@ def test_countsketch_leverage_strided_rows(slso, ctx, kind, d, pad):
         xin = slso.Fp8Matrix(xin.codes[:, :d], xin.col_scale[:d])
     else:
         xin = xin[:, :d]
-    got, info = ctx.leverage(xin, 6, 1024, 32)
+    r = 1024 if d < 512 else 2 * d
+    got, info = ctx.leverage(xin, 6, r, 32)
     got = host(got)
-    ref = olv.sketched_leverage(xval, 6, 1024, 32)
+    ref = olv.sketched_leverage(xval, 6, r, 32)
     assert info["rank"] == ref["rank"]
     assert _report(f"countsketch lev {kind} d={d} ld={d + pad}", got,
                    ref["scores"]) < 1e-5

@@ -99,8 +99,13 @@ def test_countsketch_dense_f64_bit_exact(slso, ctx):
 
 
 @pytest.mark.parametrize("n,d,r", [(3000, 100, 1024), (1, 1, 1), (777, 300, 1000),
-                                   (5000, 784, 2048), (40, 3, 5)])
+                                   (5000, 784, 2048), (40, 3, 5),
+                                   (20011, 256, 300), (9000, 512, 700),
+                                   (4000, 1032, 1100), (50000, 64, 64)])
 def test_countsketch_dense_f32_bit_exact(slso, ctx, n, d, r):
+    """Bit-exact FP64 sums in ascending row order, for each width form of
+    the fused kernel (one, two or four 4-element vectors per lane, 16, 8 or
+    4 rows in flight) and for buckets of many rows (n / r near 800)."""
     if d >= 50:
         x = synth.image_like(n, d, seed=n + d)
     else:
@@ -109,12 +114,13 @@ def test_countsketch_dense_f32_bit_exact(slso, ctx, n, d, r):
     assert np.array_equal(sx, osk.countsketch_dense(x, 5, r))
 
 
-def test_countsketch_bf16_bit_exact(slso, ctx):
-    x = synth.config0(n=4000, d=48, seed=9)
+@pytest.mark.parametrize("n,d,r", [(4000, 48, 256), (7001, 600, 700)])
+def test_countsketch_bf16_bit_exact(slso, ctx, n, d, r):
+    x = synth.config0(n=n, d=d, seed=9)
     bits = synth.to_bf16_bits(x)
     xt = dev(bits.view(np.int16)).view(torch.bfloat16)
-    sx = host(ctx.sketch(xt, 21, 256))
-    ref = osk.countsketch_dense(synth.bf16_bits_to_f64(bits), 21, 256)
+    sx = host(ctx.sketch(xt, 21, r))
+    ref = osk.countsketch_dense(synth.bf16_bits_to_f64(bits), 21, r)
     assert np.array_equal(sx, ref)
 
 

@@ -58,9 +58,9 @@ def test_config0_full(slso, ctx):
     got = host(got)
     ref = olv.sketched_leverage(x, seed, 4096, 32)
     assert info["rank"] == 64 and info["screen_full"]
-    # kappa(S X D) is about 10: one Cholesky-QR pass (the bound 4 kappa^2
-    # sqrt(r d) 2^-53 is near 5e-11)
-    assert info["flags"] & slso.INFO_QR_ONE_PASS
+    # 2 r d^2 = 3.4e7 flop, far below 2^31: the condition estimate would cost
+    # more than the second Cholesky-QR pass, so both passes run
+    assert not info["flags"] & slso.INFO_QR_ONE_PASS
     err, _ = _report("c0", got, ref["scores"])
     assert err < 1e-5
     exact, _ = olv.exact_leverage(x)
@@ -71,12 +71,13 @@ def test_config0_full(slso, ctx):
 
 @pytest.mark.parametrize("kappa,one", [(30.0, True), (3e3, False), (1e6, False)])
 def test_one_pass_taken_only_when_its_bound_holds(slso, ctx, kappa, one):
-    """FP64 X (n = 40000, d = 160) with singular values spread over kappa:
-    one Cholesky-QR pass exactly when 4 kappa_est^2 sqrt(r d) 2^-53 <= 1e-7
-    (kappa 30: about 2e-10; 3e3: 2e-6; 1e6: 0.25), and the scores within the
+    """FP64 X (n = 30000, d = 576, r = 4096: 2 r d^2 = 2.7e9 >= 2^31, so the
+    one-pass test is tried) with singular values spread over kappa: one
+    Cholesky-QR pass exactly when 4 kappa_est^2 sqrt(r d) 2^-53 <= 1e-7
+    (kappa 30: about 6e-10; 3e3: 6e-6; 1e6: 0.6), and the scores within the
     FP32 gate either way (FP64 input, so well inside it)."""
     rng = np.random.default_rng(int(kappa))
-    n, d, r = 40000, 160, 2048
+    n, d, r = 30000, 576, 4096
     u, _ = np.linalg.qr(rng.standard_normal((n, d)))
     v, _ = np.linalg.qr(rng.standard_normal((d, d)))
     x = (u * np.logspace(0, -np.log10(kappa), d)) @ v.T

@@ -96,8 +96,9 @@ def _case(slso, name):
         return _csr(slso, synth.text_like_csr(30000, 800, seed=6)), 9, 4096, \
             64, {}
     if name.startswith("kappa"):
+        # 2 r d^2 >= 2^31: the one-pass test is tried
         kappa = float(name.split()[1])
-        return dev(_spread(40000, 160, kappa, int(kappa))), 11, 2048, 32, {}
+        return dev(_spread(30000, 576, kappa, int(kappa))), 11, 4096, 32, {}
     raise ValueError(name)
 
 
