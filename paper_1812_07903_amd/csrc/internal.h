@@ -331,10 +331,15 @@ void launch_gauss_entries(uint64_t seed, int64_t r, int64_t n, int64_t row0,
 void solve_upper_trans(const double* r, int64_t d, double* b, int64_t k,
                        hipStream_t s, double* scratch = nullptr);
 void launch_transpose(const double* a, int64_t d, double* out, hipStream_t s);
-// Upper Cholesky factor of symmetric positive definite g (d x d, overwritten)
-// into r (zeros below the diagonal); *flag (device int) set to 1 on a
-// non-positive pivot.
-void cholesky(double* g, int64_t d, double* r, int* flag, hipStream_t s);
+// Upper Cholesky factor of symmetric positive definite g (d x d row-major,
+// upper triangle read, not modified) into r (zeros below the diagonal) by
+// the tiled blocked Cholesky of the sketch's QR (k_cholqr.hip: 64 x 64
+// tiles, one launch per block step, MFMA products); *flag (device int, 0 on
+// entry) set to 1 when a pivot falls to 1e-13 of its diagonal entry.
+// scratch: chol_tiled_scratch_bytes(d) bytes of device memory.
+size_t chol_tiled_scratch_bytes(int64_t d);
+void chol_tiled(const double* g, int64_t d, double* r, void* scratch,
+                int* flag, hipStream_t s);
 // c = a b for upper-triangular a, b (d x d)
 void launch_trmm_upper(const double* a, const double* b, int64_t d, double* c,
                        hipStream_t s);

@@ -1524,7 +1524,46 @@ void bchol(const Cq2& c, double* R, double* X, int* flag, hipStream_t s) {
   prof_end(kKCq2Chol, s);
 }
 
+// G's upper triangle (row-major d x d) into tiles (I, J), I <= J, one
+// workgroup each (blockIdx.x in the order of upper_tile), padded with the
+// identity past d; gdiag receives the diagonal
+__global__ void __launch_bounds__(256)
+    tile_pack_kernel(const double* __restrict__ g, int64_t d, int64_t nb,
+                     double* __restrict__ G, double* __restrict__ gdiag) {
+  int64_t I, J;
+  upper_tile(blockIdx.x, nb, I, J);
+  for (int e = threadIdx.x; e < kT2; e += 256) {
+    const int64_t gi = I * kP + e / kP, gj = J * kP + e % kP;
+    double v = gi == gj ? 1.0 : 0.0;
+    if (gi < d && gj < d) v = gi <= gj ? g[gi * d + gj] : g[gj * d + gi];
+    G[tix(I, J, nb) + e] = v;
+    if (gi == gj) gdiag[gi] = v;
+  }
+}
+
 }  // namespace
+
+size_t chol_tiled_scratch_bytes(int64_t d) {
+  const int64_t nb = (d + kP - 1) / kP;
+  return static_cast<size_t>(2 * nb * nb * kT2 + nb * kT2 + nb * kP) *
+         sizeof(double);
+}
+
+void chol_tiled(const double* g, int64_t d, double* r, void* scratch,
+                int* flag, hipStream_t s) {
+  Cq2 c{};
+  c.d = d;
+  c.nb = (d + kP - 1) / kP;
+  double* p = static_cast<double*>(scratch);
+  c.G = p;     p += c.nb * c.nb * kT2;
+  c.R1 = p;    p += c.nb * c.nb * kT2;
+  c.Dinv = p;  p += c.nb * kT2;
+  c.gdiag = p;
+  const unsigned nb = static_cast<unsigned>(c.nb);
+  tile_pack_kernel<<<nb * (nb + 1) / 2, 256, 0, s>>>(g, d, c.nb, c.G, c.gdiag);
+  bchol(c, c.R1, nullptr, flag, s);
+  r_copy_kernel<<<nb * nb, 256, 0, s>>>(c.R1, c.nb, d, nullptr, r);
+}
 
 size_t cholqr2_scratch_bytes(int64_t m, int64_t d) {
   const Cq2 c = cq2_shape(m, d);

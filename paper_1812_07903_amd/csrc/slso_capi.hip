@@ -421,8 +421,10 @@ size_t leverage_ws_bytes(const slso_matrix* X, int64_t r, int64_t k,
   z.take<char>(gemm_partial_bytes(X, r, gauss, gram));
   z.take<char>(qr_scratch_bytes(r, d));
   z.take<double>(d * d);           // R_D of the sketch
-  if (gram)
+  if (gram) {
     for (int i = 0; i < 3; ++i) z.take<double>(d * d);  // G, R1, refined R
+    z.take<char>(chol_tiled_scratch_bytes(d));            // its Cholesky
+  }
   z.take<double>(d * kk);          // Pi_2 -> M'
   z.take<double>(d * kk);          // M (FP64)
   z.take<float>(d * kk);           // M (FP32)
@@ -858,10 +860,12 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
   void* qws = a.take<char>(qr_scratch_bytes(r, d));
   double* RS = a.take<double>(d * d);
   double *G = nullptr, *R1 = nullptr, *RR = nullptr;
+  void* ctws = nullptr;
   if (gram) {
     G = a.take<double>(d * d);
     R1 = a.take<double>(d * d);
     RR = a.take<double>(d * d);
+    ctws = a.take<char>(chol_tiled_scratch_bytes(d));
   }
   double* pi = a.take<double>(d * kk);
   double* m64 = a.take<double>(d * kk);
@@ -970,7 +974,7 @@ int slso_leverage(slso_ctx* c, const slso_matrix* X, uint64_t seed, int64_t r,
       solve_upper_trans(RS, d, G, d, s, tws);     // W = R_S^-T G
       launch_transpose(G, d, R1, s);         // W^T
       solve_upper_trans(RS, d, R1, d, s, tws);    // R_S^-T W^T = G'
-      cholesky(R1, d, G, flags + 1, s);      // G (reused) = R1
+      chol_tiled(R1, d, G, ctws, flags + 1, s);  // G (reused) = R1
       launch_trmm_upper(G, RS, d, RR, s);    // R = R1 R_S
       launch_diag_stats(RR, d, dstat + 2, s);
     }
