@@ -70,7 +70,7 @@ PMC_SUMMARIES = {
         "cq2_gram": "gram_block_kernel<false,true>",
         "cq2_solve": "stripe_solve_kernel<64>",
         "score": "score_mfma_kernel<3,true>",
-        "countsketch": "countsketch_colmax_kernel<float,false>"}),
+        "countsketch": "countsketch_colmax_kernel<float,false,4,4>"}),
     "precision_bf16": ("pmc_traffic_precision_n4000000_d512.txt", {
         "gauss_sketch": "gauss_q_kernel<1,true>",
         "gram": "gram_q_kernel<1,true>",
