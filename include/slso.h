@@ -188,9 +188,16 @@ typedef struct {
 
 /* ---- context ------------------------------------------------------------ */
 
-/* Create a context on HIP device ``device``. EINVAL: ctx NULL or no such
- * device; EDEVICE: HIP failure. */
-int slso_create(slso_ctx** ctx, int device);
+/* Create a context on HIP device ``device``. workspace_bytes = 0: the
+ * context's device workspace grows on demand (a call that needs more than
+ * the context holds waits for the context's earlier work, frees the old
+ * buffer and allocates a larger one). workspace_bytes > 0: that much is
+ * allocated here (rounded up to 2 MiB) and never again; a call that needs
+ * more (slso_workspace_size) fails with SLSO_ENOMEM and enqueues nothing,
+ * so no call of the context allocates device memory. EINVAL: ctx NULL or
+ * no such device; ENOMEM: the workspace allocation failed; EDEVICE: HIP
+ * failure. */
+int slso_create(slso_ctx** ctx, int device, size_t workspace_bytes);
 
 /* Release the context and its workspace (synchronises the device first). */
 int slso_destroy(slso_ctx* ctx);

@@ -120,7 +120,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib = ctypes.CDLL(path)
     vp, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
     sig = {
-        "slso_create": ([ctypes.POINTER(vp), ctypes.c_int], ctypes.c_int),
+        "slso_create": ([ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t],
+                        ctypes.c_int),
         "slso_destroy": ([vp], ctypes.c_int),
         "slso_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "slso_last_error": ([vp], ctypes.c_char_p),
@@ -324,12 +325,14 @@ def _check(st: int, ctx=None):
 
 
 class Context:
-    """Owns a library context (device workspace) on one HIP device."""
+    """Owns a library context (device workspace) on one HIP device.
+    ``workspace_bytes`` > 0 allocates that workspace once (calls that need
+    more fail with ENOMEM); 0 lets it grow on demand."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, workspace_bytes: int = 0):
         lib = load_library()
         h = ctypes.c_void_p()
-        _check(lib.slso_create(ctypes.byref(h), device))
+        _check(lib.slso_create(ctypes.byref(h), device, workspace_bytes))
         self._h = h
         self.device = device
 

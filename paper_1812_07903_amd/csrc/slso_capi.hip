@@ -32,6 +32,7 @@ struct slso_ctx {
   void* scratch = nullptr;  // this device's address of the scoring scratch
   void* ws = nullptr;       // device workspace
   size_t ws_bytes = 0;
+  bool ws_fixed = false;    // allocated once by slso_create, never grown
   hipEvent_t ws_done = nullptr;  // recorded after the last work using ws
   hipEvent_t side_done = nullptr;  // joins the side stream into a call's stream
   slso::QrStreams qs;            // QR look-ahead stream and events
@@ -197,6 +198,12 @@ struct WsMark {
 
 int ensure_ws(slso_ctx* c, size_t bytes) {
   if (bytes <= c->ws_bytes) return SLSO_OK;
+  if (c->ws_fixed)
+    return set_err(c, SLSO_ENOMEM,
+                   "the call needs " + std::to_string(bytes) +
+                       " bytes of workspace; the context was created with a "
+                       "fixed workspace of " +
+                       std::to_string(c->ws_bytes) + " bytes");
   SLSO_HIP(c, hipSetDevice(c->device));
   if (c->ws) {
     // only this context's own earlier work can still be using the buffer
@@ -492,7 +499,7 @@ const char* slso_last_error(const slso_ctx* ctx) {
   return ctx ? ctx->err.c_str() : "";
 }
 
-int slso_create(slso_ctx** out, int device) {
+int slso_create(slso_ctx** out, int device, size_t workspace_bytes) {
   if (!out) return SLSO_EINVAL;
   *out = nullptr;
   int count = 0;
@@ -517,6 +524,13 @@ int slso_create(slso_ctx** out, int device) {
     if (c->host_buf) (void)hipHostFree(c->host_buf);
     delete c;
     return SLSO_EDEVICE;
+  }
+  if (workspace_bytes > 0) {
+    if (ensure_ws(c, workspace_bytes) != SLSO_OK) {
+      (void)slso_destroy(c);
+      return SLSO_ENOMEM;
+    }
+    c->ws_fixed = true;
   }
   *out = c;
   return SLSO_OK;

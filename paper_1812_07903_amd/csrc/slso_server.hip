@@ -221,7 +221,7 @@ int slso_server_create(slso_server** out, int device, int slots,
   S->slots.resize(static_cast<size_t>(slots));
   int st = SLSO_OK;
   for (Slot& sl : S->slots) {
-    st = slso_create(&sl.ctx, device);
+    st = slso_create(&sl.ctx, device, 0);
     if (st) break;
     if (hipSetDevice(device) != hipSuccess ||
         hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) {

@@ -53,9 +53,10 @@ def test_invalid_arguments_rejected_without_device(lib):
     assert lib.slso_hash(1, 0, 0, 10, None, None, None) == slso.EINVAL
     assert lib.slso_hash(1, 16, -1, 10, None, None, None) == slso.EINVAL
     assert lib.slso_gaussian(1, 3, -1, 2, None, None) == slso.EINVAL
-    assert lib.slso_create(None, 0) == slso.EINVAL
+    assert lib.slso_create(None, 0, 0) == slso.EINVAL
     h = ctypes.c_void_p()
-    assert lib.slso_create(ctypes.byref(h), -1) == slso.EINVAL
+    assert lib.slso_create(ctypes.byref(h), -1, 0) == slso.EINVAL
+    assert lib.slso_create(ctypes.byref(h), -1, 1 << 20) == slso.EINVAL
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

@@ -349,3 +349,30 @@ def test_eps_hat_matches_oracle(slso, ctx, kind, sketch, refine, r, tol):
     # the report changes nothing else: same scores as without it
     base, _ = ctx.leverage(xin, 17, r, 16, sketch=sk, refine=refine)
     np.testing.assert_allclose(host(got), host(base), rtol=1e-6)
+
+
+def test_fixed_workspace_context(slso):
+    """A context created with a workspace size allocates it once: calls that
+    fit give the same bits as on a context whose workspace grows, and a call
+    that needs more fails with ENOMEM, enqueues nothing and leaves the
+    context usable."""
+    x = dev(synth.config0(n=20000, d=64, seed=3))
+    need = slso.workspace_size(x, 4096, 32)
+    auto = slso.Context(0)
+    ref, _ = auto.leverage(x, 5, 4096, 32)
+    pref = host(auto.order(ref)).copy()
+    ref = host(ref).copy()
+    auto.close()
+    fixed = slso.Context(0, workspace_bytes=need)
+    got, info = fixed.leverage(x, 5, 4096, 32)
+    perm = host(fixed.order(got))
+    assert info["rank"] == 64
+    assert np.array_equal(host(got).view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(perm, pref)
+    big = dev(synth.config0(n=40000, d=128, seed=4))
+    with pytest.raises(slso.SlsoError) as ei:
+        fixed.leverage(big, 5, 8192, 32)
+    assert ei.value.status == slso.ENOMEM
+    again, _ = fixed.leverage(x, 5, 4096, 32)
+    assert np.array_equal(host(again).view(np.uint32), ref.view(np.uint32))
+    fixed.close()
