@@ -135,6 +135,19 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t b) {
   return __uint_as_float(static_cast<uint32_t>(b) << 16);
 }
 
+// Two OCP e4m3fn codes, bytes 0 and 1 of the low (HI false) or high 16-bit
+// half of w, as two BF16 values packed low / high. gfx950's packed FP8 ->
+// FP32 conversion decodes e4m3fn exactly (all 256 codes checked against the
+// decoding below, subnormals and NaN included); an e4m3 value has at most
+// four significant bits, so the FP32 result's low 16 bits are zero and its
+// high half is the BF16 value.
+template <bool HI>
+__device__ __forceinline__ uint32_t e4m3x2_to_bf16x2(uint32_t w) {
+  const auto f = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(w), HI);
+  return __builtin_amdgcn_perm(__float_as_uint(f[1]), __float_as_uint(f[0]),
+                               0x07060302u);
+}
+
 // OCP fp8 e4m3fn: sign, 4 exponent bits (bias 7), 3 mantissa bits; the
 // all-ones exponent with all-ones mantissa is NaN, there is no infinity.
 __device__ __forceinline__ float e4m3_to_f32(uint8_t q) {

@@ -168,11 +168,6 @@ __device__ __forceinline__ void entries8(const uint32_t (&o4)[4],
   }
 }
 
-// e4m3 code -> BF16 bits of its value (exact; NaN codes give a NaN)
-__device__ __forceinline__ uint32_t e4m3_bf16_bits(uint32_t q) {
-  return __float_as_uint(e4m3_to_f32(static_cast<uint8_t>(q))) >> 16;
-}
-
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 // Column maxima of the eight row groups of a column chunk (lanes 8 c ..
@@ -222,11 +217,6 @@ __device__ __forceinline__ unsigned xcd_logical() {
   return xcd * q + (xcd < rem ? xcd : rem) + (b >> 3);
 }
 
-template <int IT>
-__device__ __forceinline__ void load_dec8(uint16_t* dec8, int t) {
-  if (IT == 2 && t < 256) dec8[t] = static_cast<uint16_t>(e4m3_bf16_bits(t));
-}
-
 // ---- staging of X (shared by the sketch and the Gram pass) ------------------
 // A step takes 16 data rows; a thread stages rows row, row + 1 and columns
 // gcol .. gcol + 7 of X. The loads are issued unconditionally (rows past
@@ -234,7 +224,7 @@ __device__ __forceinline__ void load_dec8(uint16_t* dec8, int t) {
 // step or two later, so nothing waits for them at the issue point; rows at or
 // past i_end are zeroed when the block is unpacked (pair_unpack) into BF16
 // pairs xr[u][v] = row + u, columns 2 v (low half) and 2 v + 1. FP8 codes
-// are decoded through the 256-entry table dec8 (exact in BF16).
+// are decoded by the hardware conversion (e4m3x2_to_bf16x2, exact in BF16).
 template <int IT>
 struct RawPair;
 template <>
@@ -280,7 +270,6 @@ __device__ __forceinline__ void pair_issue(
 template <int IT>
 __device__ __forceinline__ void pair_unpack(const RawPair<IT>& raw,
                                             int64_t nvalid,
-                                            const uint16_t* dec8,
                                             uint32_t (&xr)[2][4]) {
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
@@ -291,13 +280,10 @@ __device__ __forceinline__ void pair_unpack(const RawPair<IT>& raw,
       v4[2] = raw.q[u].z;
       v4[3] = raw.q[u].w;
     } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const uint32_t w = v < 2 ? raw.q[u].x : raw.q[u].y;
-        const int sh = 16 * (v & 1);
-        v4[v] = static_cast<uint32_t>(dec8[(w >> sh) & 0xFFu]) |
-                (static_cast<uint32_t>(dec8[(w >> (sh + 8)) & 0xFFu]) << 16);
-      }
+      v4[0] = e4m3x2_to_bf16x2<false>(raw.q[u].x);
+      v4[1] = e4m3x2_to_bf16x2<true>(raw.q[u].x);
+      v4[2] = e4m3x2_to_bf16x2<false>(raw.q[u].y);
+      v4[3] = e4m3x2_to_bf16x2<true>(raw.q[u].y);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) xr[u][v] = u < nvalid ? v4[v] : 0u;
@@ -378,7 +364,6 @@ __device__ __forceinline__ void quad_issue(
 template <int IT>
 __device__ __forceinline__ void quad_unpack(const RawQuad<IT>& raw,
                                             int64_t nvalid,
-                                            const uint16_t* dec8,
                                             uint32_t (&xr)[4][4]) {
   RawPair<IT> lo, hi;
   lo.q[0] = raw.q[0];
@@ -386,8 +371,8 @@ __device__ __forceinline__ void quad_unpack(const RawQuad<IT>& raw,
   hi.q[0] = raw.q[2];
   hi.q[1] = raw.q[3];
   uint32_t a[2][4], b[2][4];
-  pair_unpack<IT>(lo, nvalid, dec8, a);
-  pair_unpack<IT>(hi, nvalid - 2, dec8, b);
+  pair_unpack<IT>(lo, nvalid, a);
+  pair_unpack<IT>(hi, nvalid - 2, b);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     xr[0][v] = a[0][v];
@@ -428,7 +413,6 @@ __device__ __forceinline__ void quad_issue_fast(
 
 template <int IT>
 __device__ __forceinline__ void quad_unpack_fast(const RawQuad<IT>& raw,
-                                                 const uint16_t* dec8,
                                                  uint32_t (&xr)[4][4]) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -438,13 +422,10 @@ __device__ __forceinline__ void quad_unpack_fast(const RawQuad<IT>& raw,
       xr[u][2] = raw.q[u].z;
       xr[u][3] = raw.q[u].w;
     } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const uint32_t w = v < 2 ? raw.q[u].x : raw.q[u].y;
-        const int sh = 16 * (v & 1);
-        xr[u][v] = static_cast<uint32_t>(dec8[(w >> sh) & 0xFFu]) |
-                   (static_cast<uint32_t>(dec8[(w >> (sh + 8)) & 0xFFu]) << 16);
-      }
+      xr[u][0] = e4m3x2_to_bf16x2<false>(raw.q[u].x);
+      xr[u][1] = e4m3x2_to_bf16x2<true>(raw.q[u].x);
+      xr[u][2] = e4m3x2_to_bf16x2<false>(raw.q[u].y);
+      xr[u][3] = e4m3x2_to_bf16x2<true>(raw.q[u].y);
     }
   }
 }
@@ -482,7 +463,6 @@ __global__ void __launch_bounds__(kQThreads)
   __shared__ __attribute__((aligned(16))) uint16_t tab[kQCells];
   __shared__ __attribute__((aligned(16))) uint16_t XT[2][kQD * kSK];
   __shared__ __attribute__((aligned(16))) uint16_t GT[2][kQR * kSK];
-  __shared__ uint16_t dec8[256];
   const int t = threadIdx.x;
   // consecutive logical ids share a slice of rows
   const unsigned L = xcd_logical();
@@ -501,7 +481,6 @@ __global__ void __launch_bounds__(kQThreads)
     const uint4* src = reinterpret_cast<const uint4*>(g_qtab[IT == 2 ? 1 : 0]);
     uint4* dst = reinterpret_cast<uint4*>(tab);
     for (int e = t; e < kQCells / 8; e += kQThreads) dst[e] = src[e];
-    load_dec8<IT>(dec8, t);
   }
 
   // staging role: rows 4 rg .. 4 rg + 3 of a step, columns col0 + 8 cc ..;
@@ -578,9 +557,9 @@ __global__ void __launch_bounds__(kQThreads)
       entries8(o4, tab, gw);
       uint32_t xr[4][4];
       if constexpr (SAFE)
-        quad_unpack<IT>(raw, i_end - (krow(st) + 4 * rg), dec8, xr);
+        quad_unpack<IT>(raw, i_end - (krow(st) + 4 * rg), xr);
       else
-        quad_unpack_fast<IT>(raw, dec8, xr);
+        quad_unpack_fast<IT>(raw, xr);
       if (colmax && st % nrt == rt) {
 #pragma unroll
         for (int v = 0; v < 4; ++v)
@@ -671,7 +650,6 @@ __global__ void __launch_bounds__(kQThreads)
                   int64_t rows_per_split, float* __restrict__ partial) {
   __shared__ __attribute__((aligned(16))) uint16_t TA[2][kGB * kQP];
   __shared__ __attribute__((aligned(16))) uint16_t TB[2][kGB * kQP];
-  __shared__ uint16_t dec8[256];
   const int t = threadIdx.x;
   const unsigned L = xcd_logical();
   int rem = static_cast<int>(L % static_cast<unsigned>(ntiles));
@@ -686,7 +664,6 @@ __global__ void __launch_bounds__(kQThreads)
   int64_t i_end = i_begin + rows_per_split;
   if (i_end > n) i_end = n;
   const int nsteps = static_cast<int>((i_end - i_begin + kQK - 1) / kQK);
-  load_dec8<IT>(dec8, t);
 
   constexpr int kNC = kGB / 8;  // 32 chunks of 8 columns
   const int side = t >> 8, ts = t & 255;
@@ -707,7 +684,7 @@ __global__ void __launch_bounds__(kQThreads)
   auto krow = [&](int st) { return i_begin + static_cast<int64_t>(st) * kQK; };
   auto write_step = [&](int st, const RawPair<IT>& raw) {
     uint32_t xr[2][4];
-    pair_unpack<IT>(raw, i_end - (krow(st) + 2 * rp), dec8, xr);
+    pair_unpack<IT>(raw, i_end - (krow(st) + 2 * rp), xr);
     pair_store<kNC>(side ? TB[st & 1] : TA[st & 1], cc, 2 * rp, xr);
   };
   auto mma = [&](int st) {
@@ -731,7 +708,6 @@ __global__ void __launch_bounds__(kQThreads)
   };
 
   RawPair<IT> ra, rb, rc, rd;
-  __syncthreads();  // dec8
   // four register buffers: step s is loaded into buffer s mod 4, five steps
   // (80 rows) ahead of its products
   pair_issue<IT, VEC>(x, ld, d, gcol, krow(0) + 2 * rp, i_end, ra);

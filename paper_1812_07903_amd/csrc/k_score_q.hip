@@ -9,7 +9,7 @@
 // (M to 2^-17 of each entry), for 352 < d <= 512 (133 KB at d = 512). X goes from HBM straight into MFMA operand
 // registers: for v_mfma_f32_32x32x16_bf16 lane l takes row l % 32 and 8
 // consecutive columns, which are 16 contiguous bytes of a row-major BF16 row
-// (8 bytes of FP8 codes, decoded through a 256-entry LDS table). A wave
+// (8 bytes of FP8 codes, decoded by the packed FP8 conversion). A wave
 // owns blocks of 32 rows (persistent: blocks wave, wave + W, ...), each
 // taken in two halves of at most 16 K-steps whose loads are issued one half
 // ahead. Sums are FP32 (products exact); the epilogue squares and adds the
@@ -80,10 +80,6 @@ struct SQIn<2> {
   using T = uint8_t;
 };
 
-__device__ __forceinline__ uint32_t e4m3_to_bf16(uint32_t q) {
-  return __float_as_uint(e4m3_to_f32(static_cast<uint8_t>(q))) >> 16;
-}
-
 // A operand (8 BF16) of K-step s for this lane: row `row`, columns
 // 16 s + 8 h .. + 7 (raw: 16 bytes of BF16, or 8 bytes of FP8 codes)
 template <int IT>
@@ -108,24 +104,15 @@ __device__ __forceinline__ Raw<IT> load_raw(const typename SQIn<IT>::T* p) {
 }
 
 template <int IT>
-__device__ __forceinline__ bf16x8 operand(const Raw<IT>& r,
-                                          const uint16_t* dec8) {
+__device__ __forceinline__ bf16x8 operand(const Raw<IT>& r) {
   if constexpr (IT == 1) {
     return __builtin_bit_cast(bf16x8, r.v);
   } else {
     uint4 o;
-    uint32_t w[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t src = q < 2 ? r.v.x : r.v.y;
-      const int sh = 16 * (q & 1);
-      w[q] = static_cast<uint32_t>(dec8[(src >> sh) & 0xFFu]) |
-             (static_cast<uint32_t>(dec8[(src >> (sh + 8)) & 0xFFu]) << 16);
-    }
-    o.x = w[0];
-    o.y = w[1];
-    o.z = w[2];
-    o.w = w[3];
+    o.x = e4m3x2_to_bf16x2<false>(r.v.x);
+    o.y = e4m3x2_to_bf16x2<true>(r.v.x);
+    o.z = e4m3x2_to_bf16x2<false>(r.v.y);
+    o.w = e4m3x2_to_bf16x2<true>(r.v.y);
     return __builtin_bit_cast(bf16x8, o);
   }
 }
@@ -137,12 +124,11 @@ __global__ void __launch_bounds__(kSQThreads)
                    int64_t d, int64_t ld, const uint16_t* __restrict__ mh,
                    const uint16_t* __restrict__ mm,
                    const uint16_t* __restrict__ ml, float* __restrict__ out) {
-  __shared__ __attribute__((aligned(16))) uint16_t sm[kSQLds + 256];
+  __shared__ __attribute__((aligned(16))) uint16_t sm[kSQLds];
   const int pm = static_cast<int>(d) + 8;  // LDS pitch of M (elements)
   uint16_t* Mh = sm;
   uint16_t* Mm = sm + 64 * pm;             // NP == 3 only
   uint16_t* Ml = sm + (NP - 1) * 64 * pm;
-  uint16_t* dec8 = sm + NP * 64 * pm;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int l32 = lane & 31, h = lane >> 5;
   const int steps = static_cast<int>(d / 16);
@@ -157,7 +143,6 @@ __global__ void __launch_bounds__(kSQThreads)
       *reinterpret_cast<uint4*>(&Mm[c * pm + j]) =
           *reinterpret_cast<const uint4*>(&mm[c * d + j]);
   }
-  if (IT == 2 && t < 256) dec8[t] = static_cast<uint16_t>(e4m3_to_bf16(t));
   __syncthreads();
 
   const int64_t nblk = (n + 31) / 32;
@@ -193,7 +178,7 @@ __global__ void __launch_bounds__(kSQThreads)
 #pragma unroll
     for (int s = 0; s < kSQHalf; ++s) {
       if (s < steps) {
-        const bf16x8 a = operand<IT>(A0[s], dec8);
+        const bf16x8 a = operand<IT>(A0[s]);
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
           const int o = (32 * ct + l32) * pm + 16 * s + 8 * h;
@@ -217,7 +202,7 @@ __global__ void __launch_bounds__(kSQThreads)
 #pragma unroll
     for (int s = 0; s < kSQHalf; ++s) {
       if (kSQHalf + s < steps) {
-        const bf16x8 a = operand<IT>(A1[s], dec8);
+        const bf16x8 a = operand<IT>(A1[s]);
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
           const int o = (32 * ct + l32) * pm + 16 * (kSQHalf + s) + 8 * h;

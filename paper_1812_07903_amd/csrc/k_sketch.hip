@@ -226,11 +226,16 @@ __device__ __forceinline__ void load4(const uint16_t* p, float (&v)[4]) {
   v[2] = bf16_to_f32(static_cast<uint16_t>(q.y & 0xffffu));
   v[3] = bf16_to_f32(static_cast<uint16_t>(q.y >> 16));
 }
+// four e4m3fn codes by gfx950's packed FP8 -> FP32 conversion (exact for
+// every code, as e4m3_to_f32)
 __device__ __forceinline__ void load4(const uint8_t* p, float (&v)[4]) {
-  const uint32_t q = *reinterpret_cast<const uint32_t*>(p);
-#pragma unroll
-  for (int e = 0; e < 4; ++e)
-    v[e] = e4m3_to_f32(static_cast<uint8_t>((q >> (8 * e)) & 0xffu));
+  const int q = *reinterpret_cast<const int*>(p);
+  const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(q, false);
+  const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(q, true);
+  v[0] = lo[0];
+  v[1] = lo[1];
+  v[2] = hi[0];
+  v[3] = hi[1];
 }
 __device__ __forceinline__ float elem_f(const float* p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float elem_f(const uint16_t* p, int64_t i) {
