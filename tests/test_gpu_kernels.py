@@ -369,6 +369,39 @@ def test_scores_dense(slso, ctx, dtype, k):
         assert np.all(np.abs(got - ref) <= tol * bound)
 
 
+def _fp8_every_code(ncols):
+    """254 rows: every finite e4m3fn code once per column (rotated)."""
+    finite = np.array([c for c in range(256) if (c & 0x7F) != 0x7F],
+                      dtype=np.uint8)
+    return np.stack([np.roll(finite, 17 * j) for j in range(ncols)], axis=1)
+
+
+def test_fp8_every_code_countsketch_bit_exact(slso, ctx):
+    """Every finite e4m3fn code in each of 16 columns with unit column
+    scales: the decoded values are multiples of 2^-9 below 2^9, so the
+    CountSketch's FP64 sums are exact and equal the oracle's bit for bit
+    (pins the packed FP8 conversion of the CountSketch loads)."""
+    codes = _fp8_every_code(16)
+    cs = np.ones(16, np.float32)
+    sx = host(ctx.sketch(slso.Fp8Matrix(dev(codes), dev(cs)), 3, 64))
+    ref = osk.countsketch_dense(synth.fp8_e4m3_to_f64(codes, cs), 3, 64)
+    assert np.array_equal(sx, ref)
+
+
+@pytest.mark.parametrize("j", [0, 5, 15])
+def test_fp8_every_code_scores_exact(slso, ctx, j):
+    """The MFMA scoring path of FP8 input (d = 16, k = 1, M = e_j): l_i =
+    x_ij^2, exact in FP32 (four significant bits squared), for every finite
+    code (pins the packed FP8 conversion of the MFMA operands)."""
+    codes = _fp8_every_code(16)
+    cs = np.ones(16, np.float32)
+    m = np.zeros((16, 1))
+    m[j, 0] = 1.0
+    got = host(ctx.scores(slso.Fp8Matrix(dev(codes), dev(cs)), dev(m)))
+    xref = synth.fp8_e4m3_to_f64(codes, cs)
+    assert np.array_equal(got.astype(np.float64), xref[:, j] ** 2)
+
+
 @pytest.mark.parametrize("dtype,n,d,k", [
     ("bf16", 4099, 512, 64), ("bf16", 31, 16, 1), ("bf16", 70001, 496, 37),
     ("fp8", 5003, 512, 64), ("fp8", 1000, 272, 64), ("bf16", 300, 64, 64),
