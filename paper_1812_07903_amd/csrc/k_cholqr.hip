@@ -1259,7 +1259,8 @@ __device__ double inv_norm(const double* __restrict__ x, int64_t n,
 
 // y = T (x / |x|) (TRANS: T^T (x / |x|)) for T = R1 (y 0) or X1 (y 1);
 // workgroup blockIdx.x forms the 64 entries of row block I (TRANS: column
-// block J)
+// block J). One launch per product: the form for nb <= kPowOne, where the
+// longest row of tiles is short.
 template <bool TRANS>
 __global__ void __launch_bounds__(256)
     pow_step_kernel(const double* __restrict__ R1, const double* __restrict__ X1,
@@ -1309,6 +1310,112 @@ __global__ void __launch_bounds__(256)
     red[t] = acc;
     __syncthreads();
     if (t < kP) y[B * kP + t] = (red[t] + red[t + 64] + red[t + 128] + red[t + 192]) * inv;
+  }
+}
+
+// y = T (x / |x|) (TRANS: T^T (x / |x|)) for T = R1 (y 0) or X1 (y 1), in
+// two launches so that every tile product has a workgroup of its own (nb >
+// kPowOne: a row of up to nb tiles on one workgroup would take most of the
+// step): the
+// products of row block B (TRANS: column block B) are cut into chunks of
+// kPowC tiles, one workgroup each (blockIdx.x over all chunks, blockIdx.y the
+// matrix), writing 64 partial sums of T x; pow_fin_kernel then adds a
+// block's chunks in order and scales by 1 / |x|.
+constexpr int64_t kPowC = 4;
+constexpr int64_t kPowOne = 16;
+
+__host__ __device__ inline int64_t pow_chunks(int64_t len) {
+  return (len + kPowC - 1) / kPowC;
+}
+// chunks of all blocks (the same for both orientations)
+__host__ __device__ inline int64_t pow_chunks_total(int64_t nb) {
+  int64_t n = 0;
+  for (int64_t B = 0; B < nb; ++B) n += pow_chunks(nb - B);
+  return n;
+}
+
+template <bool TRANS>
+__global__ void __launch_bounds__(256)
+    pow_part_kernel(const double* __restrict__ R1, const double* __restrict__ X1,
+                    int64_t nb, const double* __restrict__ xin,
+                    double* __restrict__ part, const int* __restrict__ skip) {
+  __shared__ double red[4][kP];
+  if (*skip) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t n = nb * kP;
+  const int mat = blockIdx.y;
+  const double* T = mat ? X1 : R1;
+  const double* x = xin + mat * n;
+  // chunk blockIdx.x -> block B, chunk c of its products
+  int64_t B = 0, c = blockIdx.x;
+  for (;;) {
+    const int64_t len = TRANS ? B + 1 : nb - B;
+    if (c < pow_chunks(len)) break;
+    c -= pow_chunks(len);
+    ++B;
+  }
+  const int64_t maxc = pow_chunks(nb);
+  double* out = part + ((mat * nb + B) * maxc + c) * kP;
+  if (!TRANS) {
+    // y_B[a] += sum_b T_BJ[a][b] x_J[b] over J = B + kPowC c ..; lane b,
+    // rows w + 4 u
+    const int64_t J0 = B + kPowC * c;
+    const int64_t J1 = J0 + kPowC < nb ? J0 + kPowC : nb;
+    double acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+    for (int64_t J = J0; J < J1; ++J) {
+      const double* tile = T + tix(B, J, nb);
+      const double xb = x[J * kP + lane];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[u] += tile[(w + 4 * u) * kP + lane] * xb;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      double a = acc[u];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+      if (lane == 0) out[w + 4 * u] = a;
+    }
+  } else {
+    // y_B[b] += sum_a T_IB[a][b] x_I[a] over I = kPowC c ..; lane b, rows
+    // w + 4 u
+    const int64_t I0 = kPowC * c;
+    const int64_t I1 = I0 + kPowC < B + 1 ? I0 + kPowC : B + 1;
+    double acc = 0.0;
+    for (int64_t I = I0; I < I1; ++I) {
+      const double* tile = T + tix(I, B, nb);
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        acc += tile[(w + 4 * u) * kP + lane] * x[I * kP + w + 4 * u];
+    }
+    red[w][lane] = acc;
+    __syncthreads();
+    if (t < kP) out[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  }
+}
+
+// y_B = (sum of block B's chunks, in order) / |x|; one workgroup per block
+// and matrix
+template <bool TRANS>
+__global__ void __launch_bounds__(256)
+    pow_fin_kernel(int64_t nb, const double* __restrict__ xin,
+                   const double* __restrict__ part, double* __restrict__ yout,
+                   const int* __restrict__ skip) {
+  __shared__ double red[256];
+  if (*skip) return;
+  const int t = threadIdx.x;
+  const int64_t n = nb * kP;
+  const int mat = blockIdx.y;
+  const int64_t B = blockIdx.x;
+  const double inv = inv_norm(xin + mat * n, n, red);
+  const int64_t len = TRANS ? B + 1 : nb - B;
+  const int64_t maxc = pow_chunks(nb);
+  if (t < kP) {
+    const double* pp = part + (mat * nb + B) * maxc * kP + t;
+    double y = 0.0;
+    for (int64_t c = 0; c < pow_chunks(len); ++c) y += pp[c * kP];
+    yout[mat * n + B * kP + t] = y * inv;
   }
 }
 
@@ -1410,7 +1517,8 @@ struct Cq2 {
   int64_t C, Q, nwg;  // stream-K full blocks (Q > 0): units per block and
                       // per workgroup, workgroups; S: slots per block
   bool fe;  // edge products formed by the diagonal blocks (no edge launch)
-  double *part, *G, *R1, *R2, *X1, *X2, *P, *Dinv, *gdiag, *apart, *pv, *kest;
+  double *part, *G, *R1, *R2, *X1, *X2, *P, *Dinv, *gdiag, *apart, *pv, *kest,
+      *pp;
   unsigned long long* emax;
 };
 
@@ -1476,7 +1584,8 @@ Cq2 cq2_carve(void* base, int64_t m, int64_t d) {
   c.emax = reinterpret_cast<unsigned long long*>(p);  // nt * 16 entries
   p += c.nt * 16;
   c.pv = p;    p += 4 * c.nb * kP;  // power-iteration vectors, two per matrix
-  c.kest = p;
+  c.kest = p;  p += 8;
+  c.pp = p;    // their partial products: 2 nb pow_chunks(nb) kP
   return c;
 }
 
@@ -1571,7 +1680,8 @@ size_t cholqr2_scratch_bytes(int64_t m, int64_t d) {
                              6 * c.nb * c.nb * kT2 +
                              tri_parts(c.nb) * c.nb * kT2 +
                              c.nb * kT2 + c.nb * kP + c.nt * 16 +
-                             4 * c.nb * kP + 8) *
+                             4 * c.nb * kP + 8 +
+                             2 * c.nb * pow_chunks(c.nb) * kP) *
          sizeof(double);
 }
 
@@ -1616,14 +1726,32 @@ void cholqr2_factor(double* a, int64_t m, int64_t d, double* r_out,
     cq1_precheck_kernel<<<1, 256, 0, s>>>(c.R1, c.gdiag, va, c.nb, m, d, bound,
                                           status, skip);
     pow_init_kernel<<<8, 256, 0, s>>>(c.nb, d, va, skip);
+    const unsigned nch = static_cast<unsigned>(pow_chunks_total(c.nb));
+    auto step = [&](bool trans, const double* xi, double* yo) {
+      if (c.nb <= kPowOne) {
+        if (trans)
+          pow_step_kernel<true><<<dim3(nb, 2), 256, 0, s>>>(c.R1, c.X1, c.nb,
+                                                            xi, yo, skip);
+        else
+          pow_step_kernel<false><<<dim3(nb, 2), 256, 0, s>>>(c.R1, c.X1, c.nb,
+                                                             xi, yo, skip);
+      } else if (trans) {
+        pow_part_kernel<true><<<dim3(nch, 2), 256, 0, s>>>(c.R1, c.X1, c.nb,
+                                                           xi, c.pp, skip);
+        pow_fin_kernel<true><<<dim3(nb, 2), 256, 0, s>>>(c.nb, xi, c.pp, yo,
+                                                         skip);
+      } else {
+        pow_part_kernel<false><<<dim3(nch, 2), 256, 0, s>>>(c.R1, c.X1, c.nb,
+                                                            xi, c.pp, skip);
+        pow_fin_kernel<false><<<dim3(nb, 2), 256, 0, s>>>(c.nb, xi, c.pp, yo,
+                                                          skip);
+      }
+    };
     for (int it = 0; it < kPowIters; ++it) {
-      pow_step_kernel<false><<<dim3(nb, 2), 256, 0, s>>>(c.R1, c.X1, c.nb, va,
-                                                         vb, skip);
-      pow_step_kernel<true><<<dim3(nb, 2), 256, 0, s>>>(c.R1, c.X1, c.nb, vb,
-                                                        va, skip);
+      step(false, va, vb);
+      step(true, vb, va);
     }
-    pow_step_kernel<false><<<dim3(nb, 2), 256, 0, s>>>(c.R1, c.X1, c.nb, va, vb,
-                                                       skip);
+    step(false, va, vb);
     cq1_decide_kernel<<<1, 256, 0, s>>>(c.R1, c.nb, m, d, vb, bound, skip,
                                         want_r ? nullptr : dstat, c.kest,
                                         status);
