@@ -285,8 +285,9 @@ int slso_leverage(slso_ctx* ctx, const slso_matrix* X, uint64_t seed,
  * fills info (host, may be NULL) and returns its status; when the device
  * path did not apply (see SLSO_OPT_NO_SYNC) the job is rerun on the
  * synchronous path into the same scores, info->flags then has
- * SLSO_INFO_RERUN and the call's stream holds the rerun's work. EINVAL when
- * the context made no such call. */
+ * SLSO_INFO_RERUN and the call's stream holds the rerun's work (that stream
+ * must still exist; its input and output buffers too). EINVAL when the
+ * context made no such call. */
 int slso_leverage_finish(slso_ctx* ctx, slso_info* info);
 
 /* "dec" ordering (Sec. 5.2): perm[0] is the row of the largest score; equal
