@@ -164,7 +164,8 @@ struct QrStreams {
 size_t qr_scratch_bytes(int64_t m, int64_t d);
 // R factor of a (m x d, lda = d, m >= d) into r_out (d x d, positive
 // diagonal, zeros below it) by Cholesky-QR2 (k_cholqr.hip); a is overwritten
-// by the first-pass Q1. *status (device int): 0 done; 2: r_out not yet
+// by the first-pass Q1 (left as it was when R is not wanted and m d <= 2^24:
+// Q1 is then formed out of place). *status (device int): 0 done; 2: r_out not yet
 // written, call qr_factor_finish; 1: Cholesky-QR2 does not apply (a too
 // ill-conditioned or rank deficient): a and r_out are unusable, the caller
 // factors the original matrix with qr_factor_panel; 3: one pass taken (R =

@@ -150,6 +150,10 @@ __device__ __forceinline__ void tile_to_global(double* g, const double* T,
 // and wave 2 of block (0, 0) also the corner A_e^T A_e; S_e = S.
 constexpr int kGK = 16;    // rows per step
 constexpr int64_t kGMin = 64;  // fewest rows of a workgroup's chunk
+// Q1 out of place (q1_gemm_kernel) up to this many entries (128 MB): the
+// sketches of the dense and serving workloads; above it the stripe solve
+// works in place
+constexpr int64_t kQ1Max = int64_t{1} << 24;
 constexpr int kGS = 144;   // LDS row stride: rows 4 apart fall on the other
                            // half of the banks
 constexpr int64_t kB2 = 128 * 128;
@@ -910,6 +914,65 @@ __global__ void __launch_bounds__(8 * kR)
   }
 }
 
+// ---- Q1 = (A diag(dsc)) X1 out of place, by 64 x 64 tiles --------------------
+// When R^{-1} is kept in factored form (no R wanted), the second pass may take
+// Q1 as A times the tiled X1 = R1^{-1} that the blocked Cholesky built, not as
+// a triangular solve: the second Gram is then that of exactly this product,
+// and R^{-1} = X1 R2^{-1} (or X1 (I - F)) is applied with the same X1, so X1's
+// own rounding cancels. Tile (R, J) of Q1 = sum over I <= J of A_RI X1_IJ,
+// one workgroup each (blockIdx.x the row block, blockIdx.y = J), the K loop
+// through one pair of LDS tiles (66 KB: two workgroups per CU) with the next
+// term's tiles loaded into registers while the current one multiplies.
+// Unlike the stripe solve the terms do not depend on each other, so every
+// tile of Q1 runs at once.
+__global__ void __launch_bounds__(256)
+    q1_gemm_kernel(const double* __restrict__ A, int64_t m, int64_t d,
+                   int64_t nb, const double* __restrict__ X,
+                   const double* __restrict__ dsc, double* __restrict__ Q,
+                   const int* __restrict__ flag) {
+  __shared__ double TA[kTile];
+  __shared__ double TB[kTile];
+  if (*flag) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t R = blockIdx.x, J = blockIdx.y;
+  const int64_t r0 = R * kP;
+  const int64_t nr = m - r0 < kP ? m - r0 : kP;
+  dbl4 acc[4];
+  zero4(acc);
+  Stage va, vb;
+  auto issue = [&](int64_t I) {
+    const int64_t c0 = I * kP;
+    const int64_t nc = d - c0 < kP ? d - c0 : kP;
+    stage_load(va, A + r0 * d + c0, d, nr, nc, t);
+    stage_load(vb, X + tix(I, J, nb), kP, kP, kP, t);
+  };
+  issue(0);
+  for (int64_t I = 0; I <= J; ++I) {
+    if (dsc) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int64_t col = I * kP + ((t + 256 * u) & 63);
+        va.v[u] *= dsc[col < d ? col : 0];
+      }
+    }
+    if (I > 0) __syncthreads();  // every wave is done with the last term
+    stage_store(TA, va, t);
+    stage_store(TB, vb, t);
+    __syncthreads();
+    if (I < J) issue(I + 1);
+    mm64<false>(TA, TB, acc, lane, w);
+  }
+  const int p = lane & 15, q = lane >> 4;
+  const int64_t c0 = J * kP;
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = 16 * w + 4 * v + q, col = 16 * bj + p;
+      if (row < nr && c0 + col < d) Q[(r0 + row) * d + c0 + col] = acc[bj][v];
+    }
+}
+
 // ---- R = R2 R1 into r_out (d x d row-major) ------------------------------------
 // NEAR: F = G2 holds the second Gram matrix; after the checks of the header,
 // R_ij = R1_ij + sum_{i<=l<=j} up(E)_il R1_lj. Otherwise F holds R2 (tiled,
@@ -1518,7 +1581,7 @@ struct Cq2 {
                       // per workgroup, workgroups; S: slots per block
   bool fe;  // edge products formed by the diagonal blocks (no edge launch)
   double *part, *G, *R1, *R2, *X1, *X2, *P, *Dinv, *gdiag, *apart, *pv, *kest,
-      *pp;
+      *pp, *qo;  // qo: Q1 out of place (nullptr above kQ1Max entries)
   unsigned long long* emax;
 };
 
@@ -1585,7 +1648,8 @@ Cq2 cq2_carve(void* base, int64_t m, int64_t d) {
   p += c.nt * 16;
   c.pv = p;    p += 4 * c.nb * kP;  // power-iteration vectors, two per matrix
   c.kest = p;  p += 8;
-  c.pp = p;    // their partial products: 2 nb pow_chunks(nb) kP
+  c.pp = p;    p += 2 * c.nb * pow_chunks(c.nb) * kP;  // their partial products
+  c.qo = m * d <= kQ1Max ? p : nullptr;
   return c;
 }
 
@@ -1681,7 +1745,8 @@ size_t cholqr2_scratch_bytes(int64_t m, int64_t d) {
                              tri_parts(c.nb) * c.nb * kT2 +
                              c.nb * kT2 + c.nb * kP + c.nt * 16 +
                              4 * c.nb * kP + 8 +
-                             2 * c.nb * pow_chunks(c.nb) * kP) *
+                             2 * c.nb * pow_chunks(c.nb) * kP +
+                             (m * d <= kQ1Max ? m * d : 0)) *
          sizeof(double);
 }
 
@@ -1760,11 +1825,19 @@ void cholqr2_factor(double* a, int64_t m, int64_t d, double* r_out,
           c.R1, c.nb, d, status, r_out);
     prof_end(kKCq2R, s);
   }
+  // Q1: with R^{-1} kept factored (X1 built, no R wanted), the product with
+  // X1 out of place when the buffer exists; otherwise the stripe solve
+  const bool gemm = !want_r && c.qo != nullptr;
   prof_begin(kKCq2Solve, s);
-  stripe_solve_kernel<kStripeRows><<<cdivu(m, kStripeRows), 8 * kStripeRows, 0, s>>>(
-      a, d, m, d, c.nb, c.R1, c.Dinv, dsc, status);
+  if (gemm)
+    q1_gemm_kernel<<<dim3(cdivu(m, kP), static_cast<unsigned>(c.nb)), 256, 0,
+                     s>>>(a, m, d, c.nb, c.X1, dsc, c.qo, status);
+  else
+    stripe_solve_kernel<kStripeRows><<<cdivu(m, kStripeRows), 8 * kStripeRows,
+                                       0, s>>>(a, d, m, d, c.nb, c.R1, c.Dinv,
+                                               dsc, status);
   prof_end(kKCq2Solve, s);
-  gram_tiles(a, m, d, c, true, nullptr, status, s);
+  gram_tiles(gemm ? c.qo : a, m, d, c, true, nullptr, status, s);
   prof_begin(kKCq2R, s);
   if (want_r)
     r_final_kernel<true><<<static_cast<unsigned>(c.nb * c.nb), 256, 0, s>>>(
