@@ -68,7 +68,7 @@ def log(msg: str) -> None:
 PMC_SUMMARIES = {
     "image": ("pmc_traffic_image_like_n60000_d784.txt", {
         "cq2_gram": "gram_block_kernel<false,true>",
-        "cq2_solve": "stripe_solve_kernel<64>",
+        "cq2_solve": "q1_gemm_kernel",
         "score": "score_mfma_kernel<3,true>",
         "countsketch": "countsketch_colmax_kernel<float,false,4,4>"}),
     "precision_bf16": ("pmc_traffic_precision_n4000000_d512.txt", {
