@@ -218,15 +218,28 @@ def blas_threads() -> int:
 
 
 # ---- one job, timed --------------------------------------------------------------
+def tune_job(slso, ctx, x, r, k, sketch, nnz=0) -> dict:
+    """slso_tune on the job's input (outside any timed region): the launch
+    shape recorded per tunable pass for (d, dtype), -1 where the input does
+    not take the pass."""
+    ctx.tune(x, r, k, sketch=sketch, nnz=nnz)
+    m = slso._matrix(x)
+    return {"score_ring": slso.tune_get(slso.TUNE_SCORE, m.d, m.dtype),
+            "countsketch_rows": slso.tune_get(slso.TUNE_COUNTSKETCH, m.d,
+                                              m.dtype)}
+
+
 def time_job(slso, ctx, x, n, seed, r, k, steps, warmup, sketch, refine=False,
              nnz=0, label=""):
-    """Warm-up, a per-kernel breakdown pass, then ``steps`` timed steps with
-    HIP events around the dominant kernel's launches only."""
+    """Launch shapes tuned on the input, warm-up, a per-kernel breakdown
+    pass, then ``steps`` timed steps with HIP events around the dominant
+    kernel's launches only."""
     import numpy as np
     import torch
     scores = torch.empty(n, dtype=torch.float32, device="cuda")
     perm = torch.empty(n, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
+    tuned = tune_job(slso, ctx, x, r, k, sketch, nnz)
 
     def step():
         _, info = ctx.leverage(x, seed, r, k, out=scores, stream=stream,
@@ -275,6 +288,7 @@ def time_job(slso, ctx, x, n, seed, r, k, steps, warmup, sketch, refine=False,
             "dominant_ms_per_launch": dms / max(dcount, 1),
             "dominant_launches_per_step": dcount / steps,
             "rank": int(info["rank"]), "flags": int(info["flags"]),
+            "tuned": tuned,
             "perm_matches_stable_sort": perm_ok, "scores": got}
 
 
@@ -346,7 +360,7 @@ def precision_bench(args, slso, ctx) -> dict:
                        "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"],
                        "steps": side_steps, "rank": res["rank"],
                        "kernels": res["kernels"], "roofline": rf,
-                       "roofline_other": ro,
+                       "roofline_other": ro, "tuned": res["tuned"],
                        "perm_matches_stable_sort":
                            res["perm_matches_stable_sort"]}
     # property that holds at any size: with the refinement R is the R factor
@@ -367,7 +381,7 @@ def precision_bench(args, slso, ctx) -> dict:
                    "refine": True, "rank": bf["rank"]},
         "perm_matches_stable_sort": bf["perm_matches_stable_sort"],
         "kernels": bf["kernels"], "roofline": roof,
-        "roofline_other": roof_other, "paths": paths,
+        "roofline_other": roof_other, "paths": paths, "tuned": bf["tuned"],
     }
     if not args.no_cpu_baseline:
         out.update(precision_check(args, slso, ctx, xb, x8, xf, bf, f8))
@@ -488,7 +502,7 @@ def text_bench(args, slso, ctx, steps=None, warmup=None) -> dict:
                                   "scores + dec ordering",
                       "n": n, "d": d, "r": r, "k": k, "seed": seed,
                       "nnz": c.nnz, "rank": res["rank"]},
-           "flags": res["flags"],
+           "flags": res["flags"], "tuned": res["tuned"],
            "perm_matches_stable_sort": res["perm_matches_stable_sort"],
            "kernels": res["kernels"], "roofline": roof,
            "roofline_other": other}
@@ -528,6 +542,7 @@ def image_bench(args, slso, ctx) -> dict:
                    "rank": res["rank"]},
         "perm_matches_stable_sort": res["perm_matches_stable_sort"],
         "kernels": res["kernels"], "roofline": roof, "roofline_other": other,
+        "tuned": res["tuned"],
     }
     if not args.no_cpu_baseline:
         import numpy as np
@@ -569,6 +584,17 @@ def serving_run(args, slso) -> dict:
     torch.cuda.synchronize()
     log(f"serving pool of {len(pool)} base matrices ready in "
         f"{time.perf_counter() - t_gen:.1f} s")
+    # launch shapes tuned per (d, dtype) of the pool before the stream, on a
+    # job of the geometric-mean size (141421 rows, r = 6 d, k = 32); the
+    # server's contexts read the same table
+    tctx = slso.Context(0)
+    tuned = {}
+    for (dv, dt), xp in sorted(pool.items(), key=lambda kv: str(kv[0])):
+        tuned[f"{dv}/{dt}"] = tune_job(slso, tctx, xp[:141421], 6 * dv, 32,
+                                       slso.COUNTSKETCH)
+    tctx.close()
+    torch.cuda.synchronize()
+    log(f"serving launch shapes tuned: {tuned}")
     per_rate = {}
     checked = None
     for rate in rates:
@@ -614,7 +640,7 @@ def serving_run(args, slso) -> dict:
             checked = (max(errs), min(taus), len(picked))
         del tickets, res
     out = {"per_rate": per_rate, "jobs_per_rate": args.jobs,
-           "slots": args.slots, "pool_rows": args.pool_n,
+           "slots": args.slots, "pool_rows": args.pool_n, "tuned": tuned,
            "config": {"workload": "serving: Poisson stream of leverage jobs, "
                                   "n log-uniform [1e4, 2e6], d in {64..1024}, "
                                   "FP32/BF16, CountSketch r=4d..8d, k=32, "

@@ -290,6 +290,35 @@ int slso_leverage(slso_ctx* ctx, const slso_matrix* X, uint64_t seed,
  * context made no such call. */
 int slso_leverage_finish(slso_ctx* ctx, slso_info* info);
 
+/* ---- tuned launch shapes ---------------------------------------------------
+ * Two passes of slso_leverage have launch shapes whose best choice depends on
+ * d, the input type and the device; every choice sums the same terms in the
+ * same order, so results are bit-identical whatever is chosen. A table shared
+ * by all contexts of the process holds the choice per (pass, d, dtype); a
+ * launch without an entry takes the default.
+ *   SLSO_TUNE_SCORE: scoring of dense BF16 / FP8 input (d a multiple of 16 up
+ *     to 512, k <= 64), rows taken through a ring of 2, 4 or 8 register
+ *     buffers per 32-row block (choices 0, 1, 2; default 0 for BF16, 1 for
+ *     FP8).
+ *   SLSO_TUNE_COUNTSKETCH: the CountSketch / OSNAP gather of dense F32, BF16
+ *     or FP8 input with rows on 4-element boundaries, rows in flight per
+ *     bucket wave (choice 0 fewer, 1 more; default 1). */
+#define SLSO_TUNE_SCORE 0
+#define SLSO_TUNE_COUNTSKETCH 1
+
+/* Times every choice of each tunable pass that X takes with these arguments
+ * (one untimed and three timed runs each, on `stream`, which the call
+ * synchronises) on X itself, and records the fastest for (pass, X->d,
+ * X->dtype). Arguments as for slso_leverage; nothing is written that the
+ * caller owns. Calls that overlap with this one on the same context are
+ * ordered after it. */
+int slso_tune(slso_ctx* ctx, const slso_matrix* X, int64_t r, int64_t k,
+              const slso_options* opt, void* stream);
+/* The recorded choice (-1: none); record one by hand (-1 removes it). EINVAL:
+ * unknown pass, d < 1, choice out of range, choice NULL. Host only. */
+int slso_tune_get(int pass, int64_t d, int dtype, int* choice);
+int slso_tune_set(int pass, int64_t d, int dtype, int choice);
+
 /* "dec" ordering (Sec. 5.2): perm[0] is the row of the largest score; equal
  * scores keep ascending row index (stable). scores (device) n floats,
  * perm (device) n int32. EINVAL for n < 1 or n >= 2^31. */

@@ -29,6 +29,7 @@ DENSE, CSR = 0, 1
 COUNTSKETCH, GAUSSIAN, OSNAP, SRHT = 0, 1, 2, 3
 OPT_SVD_RANK, OPT_EPS_HAT, OPT_NO_SYNC = 1, 2, 4
 ORDER_DEC, ORDER_SWR, ORDER_SWOR = 0, 1, 2
+TUNE_SCORE, TUNE_COUNTSKETCH = 0, 1
 STREAM_GAUSS_S, STREAM_PI2 = 3, 4
 
 EXPORTED = (
@@ -41,6 +42,7 @@ EXPORTED = (
     "slso_gaussian_sketch_entries_q", "slso_qr_r", "slso_qr_r_path",
     "slso_solve_upper", "slso_scores", "slso_scores_noalloc",
     "slso_workspace_size",
+    "slso_tune", "slso_tune_get", "slso_tune_set",
     "slso_server_create", "slso_server_submit", "slso_server_poll",
     "slso_server_wait", "slso_server_stats", "slso_server_destroy",
     "slso_profile_enable", "slso_profile_read", "slso_profile_name",
@@ -152,6 +154,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "slso_workspace_size": ([ctypes.POINTER(_Matrix), i64, i64,
                                  ctypes.POINTER(_Options),
                                  ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "slso_tune": ([vp, ctypes.POINTER(_Matrix), i64, i64,
+                       ctypes.POINTER(_Options), vp], ctypes.c_int),
+        "slso_tune_get": ([ctypes.c_int, i64, ctypes.c_int,
+                           ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "slso_tune_set": ([ctypes.c_int, i64, ctypes.c_int, ctypes.c_int],
+                          ctypes.c_int),
         "slso_server_create": ([ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
                                 ctypes.c_size_t], ctypes.c_int),
         "slso_server_submit": ([vp, ctypes.POINTER(_Job),
@@ -397,6 +405,18 @@ class Context:
             return out, None
         return out, _info_dict(info, st)
 
+    def tune(self, x, r: int, k: int, sketch: int = COUNTSKETCH, nnz: int = 0,
+             stream=None):
+        """Time the tunable launch shapes of slso_leverage on x and record
+        the fastest per (pass, d, dtype) (slso_tune; results do not depend
+        on the choice)."""
+        m = _matrix(x)
+        self._here(_device(x))
+        opt = _Options(sketch, 0, 0.0, nnz, 0)
+        _check(load_library().slso_tune(self._h, ctypes.byref(m), r, k,
+                                        ctypes.byref(opt), _stream(stream)),
+               self._h)
+
     def leverage_finish(self):
         """Info dict of the pending no-sync leverage call (waits for its
         stream; a case the device path does not take is rerun there)."""
@@ -519,6 +539,18 @@ def _info_dict(info, st):
             "refined": bool(info.flags & INFO_REFINED),
             "diag_min": info.diag_min, "diag_max": info.diag_max,
             "eps_hat": info.eps_hat}
+
+
+def tune_get(pass_: int, d: int, dtype: int) -> int:
+    """The recorded launch-shape choice for (pass, d, slso dtype), or -1."""
+    ch = ctypes.c_int()
+    _check(load_library().slso_tune_get(pass_, d, dtype, ctypes.byref(ch)))
+    return ch.value
+
+
+def tune_set(pass_: int, d: int, dtype: int, choice: int) -> None:
+    """Record a launch-shape choice by hand (-1 removes it)."""
+    _check(load_library().slso_tune_set(pass_, d, dtype, choice))
 
 
 def workspace_size(x, r: int, k: int, sketch: int = COUNTSKETCH,

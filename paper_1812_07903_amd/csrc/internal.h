@@ -51,6 +51,16 @@ enum KernelId : int {
 void prof_begin(int kid, hipStream_t s);
 void prof_end(int kid, hipStream_t s);
 
+// ---- tuned launch shapes (slso_capi.hip) -------------------------------------
+// Passes with launch shapes chosen per (d, dtype) by slso_tune (the values
+// of SLSO_TUNE_*); every choice gives bit-identical results.
+constexpr int kTuneScore = 0;        // score_q register ring: 2, 4, 8 units
+constexpr int kScoreRingChoices = 3;
+constexpr int kTuneCountSketch = 1;  // CountSketch rows in flight: less, more
+constexpr int kCsChoices = 2;
+// The recorded choice for (pass, d, dtype), or -1. Thread-safe.
+int tune_choice(int pass, int64_t d, int dtype);
+
 // ---- context internals used by the serving loop (slso_capi.hip) -------------
 // Wait for the context's last use of its workspace and free it.
 int ctx_release_workspace(::slso_ctx* c);
@@ -144,12 +154,16 @@ void launch_countsketch(const void* x, int dtype, int format, int64_t n,
 // not qualify.
 int64_t countsketch_colmax_groups(int64_t r);
 bool countsketch_colmax_ok(const void* x, int dtype, int format, int64_t ld);
+// choice: the launch shape (rows in flight per bucket wave, see
+// kTuneCountSketch); -1 takes the tuned choice for (d, dtype), else the
+// default.
 bool launch_countsketch_colmax(const void* x, int dtype, int64_t d, int64_t ld,
                                const float* col_scale,
                                const uint32_t* sorted_vals,
                                const int32_t* offsets, int64_t r, float* parts,
                                int* nonfinite, double* dscale, double* sx,
-                               hipStream_t s, double sscale = 1.0);
+                               hipStream_t s, double sscale = 1.0,
+                               int choice = -1);
 
 // ---- QR (k_qr.hip) -----------------------------------------------------------
 // A second stream and two events that let the QR overlap one panel's
@@ -353,9 +367,11 @@ bool score_q_ok(const void* x, int dtype, int format, int64_t d, int64_t ld,
 size_t score_q_scratch_bytes(int64_t d);
 // scores[i] = ||x_i M||^2 with M = m64 (d x k FP64, row-major; FP8: the
 // column scales already folded into its rows); scratch: score_q_scratch_bytes
+// choice: the register ring (kTuneScore); -1 takes the tuned choice for
+// (d, dtype), else the default
 void launch_score_q(const void* x, int dtype, int64_t n, int64_t d, int64_t ld,
                     const double* m64, int64_t k, void* scratch, float* scores,
-                    hipStream_t s);
+                    hipStream_t s, int choice = -1);
 
 // ---- scoring (k_score.hip) ---------------------------------------------------
 void launch_scores(const void* x, int dtype, int format, int64_t n, int64_t d,

@@ -117,8 +117,9 @@ __device__ __forceinline__ bf16x8 operand(const Raw<IT>& r) {
   }
 }
 
-// NP parts of M: mp[0] = Mh, mp[NP - 1] = the smallest part
-template <int IT, int NP>
+// NP parts of M: mp[0] = Mh, mp[NP - 1] = the smallest part; KU register
+// buffers (units of 32 / KU K-steps) per 32-row block
+template <int IT, int NP, int KU>
 __global__ void __launch_bounds__(kSQThreads)
     score_q_kernel(const typename SQIn<IT>::T* __restrict__ x, int64_t n,
                    int64_t d, int64_t ld, const uint16_t* __restrict__ mh,
@@ -160,8 +161,9 @@ __global__ void __launch_bounds__(kSQThreads)
   // last reads the last block, a K-step past d reads the last K-step), so no
   // wait is placed at a branch. Measured at the precision shape: BF16 halves
   // (0.72 ms; quarters 0.73, eighths 0.77), FP8 quarters (0.55 ms; halves
-  // 0.63, eighths 0.58).
-  constexpr int kU = IT == 1 ? 2 : 4;
+  // 0.63, eighths 0.58): the defaults; slso_tune chooses per (d, dtype).
+  // Every choice gives the same bits (the K-steps are summed in one order).
+  constexpr int kU = KU;
   constexpr int kUS = 2 * kSQHalf / kU;  // K-steps per unit
   const int64_t blk0 = blk;
   Raw<IT> Q[kU][kUS];
@@ -252,7 +254,7 @@ size_t score_q_scratch_bytes(int64_t d) {
 
 void launch_score_q(const void* x, int dtype, int64_t n, int64_t d, int64_t ld,
                     const double* m64, int64_t k, void* scratch, float* scores,
-                    hipStream_t s) {
+                    hipStream_t s, int choice) {
   uint16_t* mh = static_cast<uint16_t*>(scratch);
   uint16_t* mm = mh + 64 * d;
   uint16_t* ml = mm + 64 * d;
@@ -266,20 +268,35 @@ void launch_score_q(const void* x, int dtype, int64_t n, int64_t d, int64_t ld,
   int64_t grid = (nblk + 7) / 8;
   if (grid > 256) grid = 256;
   const unsigned g = static_cast<unsigned>(grid);
+  // register ring: choice 0, 1, 2 = 2, 4, 8 units per block
+  if (choice < 0 || choice >= kScoreRingChoices) choice = tune_choice(kTuneScore, d, dtype);
+  if (choice < 0) choice = dtype == 2 ? 0 : 1;
   prof_begin(kKScore, s);
+#define SLSO_SQ(IT_, T_, NP_)                                                    \
+  do {                                                                           \
+    const T_* xp = static_cast<const T_*>(x);                                    \
+    if (choice == 0)                                                             \
+      score_q_kernel<IT_, NP_, 2><<<g, kSQThreads, 0, s>>>(xp, n, d, ld, mh, mm, \
+                                                           ml, scores);          \
+    else if (choice == 1)                                                        \
+      score_q_kernel<IT_, NP_, 4><<<g, kSQThreads, 0, s>>>(xp, n, d, ld, mh, mm, \
+                                                           ml, scores);          \
+    else                                                                         \
+      score_q_kernel<IT_, NP_, 8><<<g, kSQThreads, 0, s>>>(xp, n, d, ld, mh, mm, \
+                                                           ml, scores);          \
+  } while (0)
   if (dtype == 2) {
-    const uint16_t* xp = static_cast<const uint16_t*>(x);
     if (three)
-      score_q_kernel<1, 3><<<g, kSQThreads, 0, s>>>(xp, n, d, ld, mh, mm, ml, scores);
+      SLSO_SQ(1, uint16_t, 3);
     else
-      score_q_kernel<1, 2><<<g, kSQThreads, 0, s>>>(xp, n, d, ld, mh, mm, ml, scores);
+      SLSO_SQ(1, uint16_t, 2);
   } else {
-    const uint8_t* xp = static_cast<const uint8_t*>(x);
     if (three)
-      score_q_kernel<2, 3><<<g, kSQThreads, 0, s>>>(xp, n, d, ld, mh, mm, ml, scores);
+      SLSO_SQ(2, uint8_t, 3);
     else
-      score_q_kernel<2, 2><<<g, kSQThreads, 0, s>>>(xp, n, d, ld, mh, mm, ml, scores);
+      SLSO_SQ(2, uint8_t, 2);
   }
+#undef SLSO_SQ
   prof_end(kKScore, s);
 }
 

@@ -551,29 +551,40 @@ bool launch_countsketch_colmax(const void* x, int dtype, int64_t d, int64_t ld,
                                const uint32_t* sorted_vals,
                                const int32_t* offsets, int64_t r, float* parts,
                                int* nonfinite, double* dscale, double* sx,
-                               hipStream_t s, double sscale) {
+                               hipStream_t s, double sscale, int choice) {
   if (!countsketch_colmax_ok(x, dtype, 0, ld) || d <= 0 || r <= 0) return false;
   const int64_t groups = countsketch_colmax_groups(r);
   const unsigned g = static_cast<unsigned>(groups);
   prof_begin(kKSketch, s);
   const bool tail = d % 4 != 0;
-  // chunk width 256 U: one chunk for d up to 1024
+  // chunk width 256 U: one chunk for d up to 1024. Rows in flight per
+  // bucket wave: choice 0 or 1 (default 1) = 8 or 16 (U = 1), 4 or 8
+  // (U = 2), 2 or 4 (U = 4); every choice sums the same rows in the same
+  // order, so the bits do not depend on it
   const int U = d <= 256 ? 1 : (d <= 512 ? 2 : 4);
+  if (choice < 0 || choice >= kCsChoices) choice = tune_choice(kTuneCountSketch, d, dtype);
+  if (choice < 0) choice = 1;
+  const bool big = choice == 1;
 #define SLSO_CS_GO(T, CS, TL, UU, NR)                                           \
   countsketch_colmax_kernel<T, TL, UU, NR><<<g, 256, 0, s>>>(                   \
       static_cast<const T*>(x), d, ld, CS, sorted_vals, offsets, r, parts,     \
       nonfinite, sx, sscale)
+#define SLSO_CS_TL(T, CS, TL)                                                   \
+  do {                                                                          \
+    if (U == 1) {                                                               \
+      if (big) SLSO_CS_GO(T, CS, TL, 1, 16); else SLSO_CS_GO(T, CS, TL, 1, 8);  \
+    } else if (U == 2) {                                                        \
+      if (big) SLSO_CS_GO(T, CS, TL, 2, 8); else SLSO_CS_GO(T, CS, TL, 2, 4);   \
+    } else {                                                                    \
+      if (big) SLSO_CS_GO(T, CS, TL, 4, 4); else SLSO_CS_GO(T, CS, TL, 4, 2);   \
+    }                                                                           \
+  } while (0)
 #define SLSO_CS_LAUNCH(T, CS)                                                   \
   do {                                                                          \
-    if (tail) {                                                                 \
-      if (U == 1) SLSO_CS_GO(T, CS, true, 1, 16);                               \
-      else if (U == 2) SLSO_CS_GO(T, CS, true, 2, 8);                           \
-      else SLSO_CS_GO(T, CS, true, 4, 4);                                       \
-    } else {                                                                    \
-      if (U == 1) SLSO_CS_GO(T, CS, false, 1, 16);                              \
-      else if (U == 2) SLSO_CS_GO(T, CS, false, 2, 8);                          \
-      else SLSO_CS_GO(T, CS, false, 4, 4);                                      \
-    }                                                                           \
+    if (tail)                                                                   \
+      SLSO_CS_TL(T, CS, true);                                                  \
+    else                                                                        \
+      SLSO_CS_TL(T, CS, false);                                                 \
   } while (0)
   if (dtype == 1)
     SLSO_CS_LAUNCH(float, nullptr);
@@ -582,6 +593,7 @@ bool launch_countsketch_colmax(const void* x, int dtype, int64_t d, int64_t ld,
   else
     SLSO_CS_LAUNCH(uint8_t, col_scale);
 #undef SLSO_CS_LAUNCH
+#undef SLSO_CS_TL
 #undef SLSO_CS_GO
   prof_end(kKSketch, s);
   colmax_parts_kernel<<<grid1(d, 4), 256, 0, s>>>(

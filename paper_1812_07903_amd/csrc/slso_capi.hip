@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
 #include <optional>
 #include <string>
 #include <vector>
@@ -1190,6 +1191,161 @@ int slso_leverage_finish(slso_ctx* c, slso_info* info) {
     info->eps_hat = std::nan("");
   }
   return SLSO_OK;
+}
+
+}  // extern "C"
+
+// ---- tuned launch shapes ---------------------------------------------------
+namespace {
+std::mutex g_tune_mu;
+std::unordered_map<uint64_t, int> g_tune;  // (pass, dtype, d) -> choice
+
+uint64_t tune_key(int pass, int64_t d, int dtype) {
+  return (static_cast<uint64_t>(pass) << 56) |
+         (static_cast<uint64_t>(dtype & 0xff) << 48) |
+         (static_cast<uint64_t>(d) & ((uint64_t{1} << 48) - 1));
+}
+int tune_choices(int pass) {
+  return pass == kTuneScore ? kScoreRingChoices
+                            : (pass == kTuneCountSketch ? kCsChoices : 0);
+}
+
+// the tuner's buffers (also sized by a Sizer)
+struct TuneBufs {
+  double* m64 = nullptr;
+  void* sq = nullptr;
+  float* out = nullptr;
+  SketchBufs sb{};
+  float* parts = nullptr;
+  int* flags = nullptr;
+  double* dscale = nullptr;
+  double* sx = nullptr;
+};
+template <typename A>
+TuneBufs tune_layout(A& a, const slso_matrix* X, int64_t r, bool score,
+                     int nnz) {
+  TuneBufs b;
+  if (score) {
+    b.m64 = a.template take<double>(X->d * 64);
+    b.sq = a.template take<char>(score_q_scratch_bytes(X->d));
+    b.out = a.template take<float>(X->n);
+  }
+  if (nnz > 0) {
+    b.sb = take_sketch_bufs(a, X->n * nnz, r);
+    b.parts = a.template take<float>(countsketch_colmax_groups(r) * X->d);
+    b.flags = a.template take<int>(64);
+    b.dscale = a.template take<double>(X->d);
+    b.sx = a.template take<double>(r * X->d);
+  }
+  return b;
+}
+}  // namespace
+
+namespace slso {
+int tune_choice(int pass, int64_t d, int dtype) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  const auto it = g_tune.find(tune_key(pass, d, dtype));
+  return it == g_tune.end() ? -1 : it->second;
+}
+}  // namespace slso
+
+extern "C" {
+
+int slso_tune_get(int pass, int64_t d, int dtype, int* choice) {
+  if (!choice || tune_choices(pass) == 0 || d < 1) return SLSO_EINVAL;
+  *choice = tune_choice(pass, d, dtype);
+  return SLSO_OK;
+}
+
+int slso_tune_set(int pass, int64_t d, int dtype, int choice) {
+  const int nc = tune_choices(pass);
+  if (nc == 0 || d < 1 || choice < -1 || choice >= nc) return SLSO_EINVAL;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  if (choice < 0)
+    g_tune.erase(tune_key(pass, d, dtype));
+  else
+    g_tune[tune_key(pass, d, dtype)] = choice;
+  return SLSO_OK;
+}
+
+int slso_tune(slso_ctx* c, const slso_matrix* X, int64_t r, int64_t k,
+              const slso_options* opt, void* stream) {
+  if (!c) return SLSO_EINVAL;
+  slso_options o{};
+  int st = check_leverage(c, X, r, k, opt, &o);
+  if (st) return st;
+  const int nnz = sketch_nnz(o);
+  const int64_t kk = k == 0 ? X->d : k;
+  const bool score =
+      score_q_ok(X->values, X->dtype, X->format, X->d, X->ld, kk);
+  const bool cs = nnz > 0 && countsketch_colmax_ok(X->values, X->dtype,
+                                                   X->format, X->ld);
+  if (!score && !cs) return SLSO_OK;
+  Sizer z;
+  tune_layout(z, X, r, score, cs ? nnz : 0);
+  SLSO_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = ensure_ws(c, z.off))) return st;
+  WsMark mark_{c, s};
+  Arena a{static_cast<char*>(c->ws)};
+  const TuneBufs b = tune_layout(a, X, r, score, cs ? nnz : 0);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  SLSO_HIP(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return set_err(c, SLSO_EDEVICE, "hipEventCreate failed");
+  }
+  // mean of three runs after one untimed run
+  auto timed = [&](const auto& launch) -> float {
+    launch();
+    float ms = 1e30f;
+    if (hipEventRecord(e0, s) != hipSuccess) return ms;
+    for (int i = 0; i < 3; ++i) launch();
+    if (hipEventRecord(e1, s) != hipSuccess ||
+        hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return 1e30f;
+    return ms / 3.0f;
+  };
+  if (score) {
+    // M's values do not change the time: zeros
+    launch_fill_u64(reinterpret_cast<uint64_t*>(b.m64), X->d * 64, 0, s);
+    int best = -1;
+    float bt = 1e30f;
+    for (int ch = 0; ch < kScoreRingChoices; ++ch) {
+      const float t = timed([&]() {
+        launch_score_q(X->values, X->dtype, X->n, X->d, X->ld, b.m64, kk, b.sq,
+                       b.out, s, ch);
+      });
+      if (t < bt) {
+        bt = t;
+        best = ch;
+      }
+    }
+    if (best >= 0) (void)slso_tune_set(kTuneScore, X->d, X->dtype, best);
+  }
+  if (cs) {
+    enqueue_partition(X->n, nnz, 1, r, b.sb, s);
+    launch_fill_i32(b.flags, 64, 0, s);
+    int best = -1;
+    float bt = 1e30f;
+    for (int ch = 0; ch < kCsChoices; ++ch) {
+      const float t = timed([&]() {
+        (void)launch_countsketch_colmax(X->values, X->dtype, X->d, X->ld,
+                                        X->col_scale, b.sb.vals_s, b.sb.off, r,
+                                        b.parts, b.flags, b.dscale, b.sx, s,
+                                        sketch_scale(nnz), ch);
+      });
+      if (t < bt) {
+        bt = t;
+        best = ch;
+      }
+    }
+    if (best >= 0) (void)slso_tune_set(kTuneCountSketch, X->d, X->dtype, best);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return check_launch(c, "slso_tune");
 }
 
 int slso_workspace_size(const slso_matrix* X, int64_t r, int64_t k,

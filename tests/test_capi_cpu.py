@@ -200,3 +200,28 @@ def test_binding_checks_outputs():
         slso._scores_in(torch.empty(5, dtype=torch.float32))
     with pytest.raises(ValueError):
         slso._f64_matrix(torch.empty((3, 3), dtype=torch.float64), "R")
+
+
+def test_tune_table(lib):
+    """The table of tuned launch shapes (host only): range checks, one entry
+    per (pass, d, dtype), -1 removes."""
+    ch = ctypes.c_int()
+    assert lib.slso_tune_get(9, 64, 2, ctypes.byref(ch)) == slso.EINVAL
+    assert lib.slso_tune_get(slso.TUNE_SCORE, 0, 2, ctypes.byref(ch)) == slso.EINVAL
+    assert lib.slso_tune_get(slso.TUNE_SCORE, 64, 2, None) == slso.EINVAL
+    assert lib.slso_tune_set(slso.TUNE_SCORE, 123, 2, 3) == slso.EINVAL
+    assert lib.slso_tune_set(slso.TUNE_COUNTSKETCH, 123, 2, 2) == slso.EINVAL
+    assert lib.slso_tune_set(slso.TUNE_SCORE, 123, 2, -2) == slso.EINVAL
+    assert slso.tune_get(slso.TUNE_SCORE, 123, 2) == -1
+    slso.tune_set(slso.TUNE_SCORE, 123, 2, 2)
+    slso.tune_set(slso.TUNE_SCORE, 123, 3, 1)
+    slso.tune_set(slso.TUNE_COUNTSKETCH, 123, 2, 0)
+    assert slso.tune_get(slso.TUNE_SCORE, 123, 2) == 2
+    assert slso.tune_get(slso.TUNE_SCORE, 123, 3) == 1
+    assert slso.tune_get(slso.TUNE_COUNTSKETCH, 123, 2) == 0
+    assert slso.tune_get(slso.TUNE_SCORE, 124, 2) == -1
+    for p, dt in ((slso.TUNE_SCORE, 2), (slso.TUNE_SCORE, 3),
+                  (slso.TUNE_COUNTSKETCH, 2)):
+        slso.tune_set(p, 123, dt, -1)
+        assert slso.tune_get(p, 123, dt) == -1
+    assert lib.slso_tune(None, None, 16, 4, None, None) == slso.EINVAL
