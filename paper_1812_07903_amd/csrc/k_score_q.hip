@@ -5,29 +5,30 @@
 // M (d x 64, zero past k) enters the BF16 MFMA as BF16 parts held in LDS
 // for the whole kernel, so a workgroup reads M once: three parts
 // Mh = bf16(M), Mm = bf16(M - Mh), Ml = bf16(M - Mh - Mm) (M to FP32
-// precision) while they fit, d <= 352 (138 KB); two, Mh and bf16(M - Mh)
-// (M to 2^-17 of each entry), for 352 < d <= 512 (133 KB at d = 512). X goes from HBM straight into MFMA operand
-// registers: for v_mfma_f32_32x32x16_bf16 lane l takes row l % 32 and 8
-// consecutive columns, which are 16 contiguous bytes of a row-major BF16 row
-// (8 bytes of FP8 codes, decoded by the packed FP8 conversion). A wave
-// owns blocks of 32 rows (persistent: blocks wave, wave + W, ...), each
-// taken in units of K-steps through a ring of register buffers (two halves
-// for BF16, four quarters for FP8), each unit's loads issued one ring ahead. Sums are FP32 (products exact); the epilogue squares and adds the
-// 64 columns in FP32.
+// precision) while they fit, d <= 352 (at most 151 KB); two, Mh and
+// bf16(M - Mh) (M to 2^-17 of each entry), for 352 < d <= 512 (133 KB at
+// d = 512). X goes from HBM straight into MFMA operand registers: for
+// v_mfma_f32_16x16x32_bf16 lane l takes row l % 16 and 8 K-values, here 16
+// contiguous bytes of a row-major row (8 BF16, or 16 FP8 codes for two
+// K-steps, decoded by the packed FP8 conversion). A wave owns blocks of 32
+// rows (persistent: blocks wave, wave + W, ...), each taken in units of load
+// steps through a ring of register buffers, each unit's loads issued one
+// ring ahead. Sums are FP32 (products exact); the epilogue squares and adds
+// the 64 columns in FP32.
 #include "internal.h"
 
 namespace slso {
 namespace {
 
-typedef float f16v __attribute__((ext_vector_type(16)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kSQThreads = 512;  // eight waves
-constexpr int kSQHalf = 16;      // K-steps per half block
-constexpr int kSQMaxD = 512;     // largest d (two halves of 16 K-steps)
+constexpr int kSQMaxD = 512;     // largest d
 constexpr int kSQMaxD3 = 352;    // largest d with three parts of M
-constexpr int kSQLds = 3 * 64 * (kSQMaxD3 + 8) > 2 * 64 * (kSQMaxD + 8)
-                           ? 3 * 64 * (kSQMaxD3 + 8)
+// M's depth in LDS is d rounded up to a load step (64 columns for FP8)
+constexpr int kSQLds = 3 * 64 * (384 + 8) > 2 * 64 * (kSQMaxD + 8)
+                           ? 3 * 64 * (384 + 8)
                            : 2 * 64 * (kSQMaxD + 8);
 
 __device__ __forceinline__ uint16_t bf16_bits_rne(float f) {
@@ -80,45 +81,30 @@ struct SQIn<2> {
   using T = uint8_t;
 };
 
-// A operand (8 BF16) of K-step s for this lane: row `row`, columns
-// 16 s + 8 h .. + 7 (raw: 16 bytes of BF16, or 8 bytes of FP8 codes)
+// MFMA operand (8 BF16) from a lane's 16 loaded bytes: BF16 as is; FP8
+// codes 8 e .. 8 e + 7 decoded by the packed conversion
 template <int IT>
-struct Raw;
-template <>
-struct Raw<1> {
-  uint4 v;
-};
-template <>
-struct Raw<2> {
-  uint2 v;
-};
-
-template <int IT>
-__device__ __forceinline__ Raw<IT> load_raw(const typename SQIn<IT>::T* p) {
-  Raw<IT> r;
-  if constexpr (IT == 1)
-    r.v = *reinterpret_cast<const uint4*>(p);
-  else
-    r.v = *reinterpret_cast<const uint2*>(p);
-  return r;
-}
-
-template <int IT>
-__device__ __forceinline__ bf16x8 operand(const Raw<IT>& r) {
+__device__ __forceinline__ bf16x8 operand(const uint4& r, int e) {
   if constexpr (IT == 1) {
-    return __builtin_bit_cast(bf16x8, r.v);
+    (void)e;
+    return __builtin_bit_cast(bf16x8, r);
   } else {
+    const uint32_t w0 = e == 0 ? r.x : r.z, w1 = e == 0 ? r.y : r.w;
     uint4 o;
-    o.x = e4m3x2_to_bf16x2<false>(r.v.x);
-    o.y = e4m3x2_to_bf16x2<true>(r.v.x);
-    o.z = e4m3x2_to_bf16x2<false>(r.v.y);
-    o.w = e4m3x2_to_bf16x2<true>(r.v.y);
+    o.x = e4m3x2_to_bf16x2<false>(w0);
+    o.y = e4m3x2_to_bf16x2<true>(w0);
+    o.z = e4m3x2_to_bf16x2<false>(w1);
+    o.w = e4m3x2_to_bf16x2<true>(w1);
     return __builtin_bit_cast(bf16x8, o);
   }
 }
 
+__device__ __forceinline__ f4v mfma16(bf16x8 a, bf16x8 b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
 // NP parts of M: mp[0] = Mh, mp[NP - 1] = the smallest part; KU register
-// buffers (units of 32 / KU K-steps) per 32-row block
+// buffers (units of load steps) per 32-row block
 template <int IT, int NP, int KU>
 __global__ void __launch_bounds__(kSQThreads)
     score_q_kernel(const typename SQIn<IT>::T* __restrict__ x, int64_t n,
@@ -126,113 +112,149 @@ __global__ void __launch_bounds__(kSQThreads)
                    const uint16_t* __restrict__ mm,
                    const uint16_t* __restrict__ ml, float* __restrict__ out) {
   __shared__ __attribute__((aligned(16))) uint16_t sm[kSQLds];
-  const int pm = static_cast<int>(d) + 8;  // LDS pitch of M (elements)
+  using T = typename SQIn<IT>::T;
+  constexpr int kLW = IT == 1 ? 32 : 64;  // columns of X per load step
+  constexpr int kCW = kLW / 4;            // of them per lane (16 bytes)
+  const int nls = static_cast<int>((d + kLW - 1) / kLW);
+  const int dp = nls * kLW;               // depth of M in LDS, zero past d
+  const int pm = dp + 8;                  // LDS pitch of M (elements)
   uint16_t* Mh = sm;
-  uint16_t* Mm = sm + 64 * pm;             // NP == 3 only
+  uint16_t* Mm = sm + 64 * pm;            // NP == 3 only
   uint16_t* Ml = sm + (NP - 1) * 64 * pm;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int l32 = lane & 31, h = lane >> 5;
-  const int steps = static_cast<int>(d / 16);
+  const int r16 = lane & 15, g = lane >> 4;
   // M into LDS, 8 elements per access (d is a multiple of 16)
-  for (int64_t e = t; e < 8 * d; e += kSQThreads) {
-    const int64_t c = e / (d / 8), j = 8 * (e % (d / 8));
-    *reinterpret_cast<uint4*>(&Mh[c * pm + j]) =
-        *reinterpret_cast<const uint4*>(&mh[c * d + j]);
-    *reinterpret_cast<uint4*>(&Ml[c * pm + j]) =
-        *reinterpret_cast<const uint4*>(&ml[c * d + j]);
-    if (NP == 3)
-      *reinterpret_cast<uint4*>(&Mm[c * pm + j]) =
-          *reinterpret_cast<const uint4*>(&mm[c * d + j]);
+  for (int e = t; e < 8 * dp; e += kSQThreads) {
+    const int c = e / (dp / 8), j = 8 * (e % (dp / 8));
+    uint4 vh = {0u, 0u, 0u, 0u}, vm = vh, vl = vh;
+    if (j < d) {
+      vh = *reinterpret_cast<const uint4*>(&mh[c * d + j]);
+      vl = *reinterpret_cast<const uint4*>(&ml[c * d + j]);
+      if (NP == 3) vm = *reinterpret_cast<const uint4*>(&mm[c * d + j]);
+    }
+    *reinterpret_cast<uint4*>(&Mh[c * pm + j]) = vh;
+    *reinterpret_cast<uint4*>(&Ml[c * pm + j]) = vl;
+    if (NP == 3) *reinterpret_cast<uint4*>(&Mm[c * pm + j]) = vm;
   }
   __syncthreads();
 
+  // A wave owns blocks of 32 rows as two 16-row MFMA tiles. Load step s
+  // gives lane (row r16, group g) 16 contiguous bytes of its row, columns
+  // kLW s + kCW g .. + kCW - 1, so one load instruction reads 64 contiguous
+  // bytes of each of 16 rows (a read pattern that streams about a tenth
+  // faster than 32 bytes of each of 32 rows). The MFMA pairs element i of
+  // lane group g in A with the same element of the same group in B, so any
+  // assignment of columns to (step, group, element) gives x_i M as long as M
+  // is read with it: BF16 step s is one K-step (columns 32 s + 8 g + i), an
+  // FP8 step two (columns 64 s + 16 g + 8 e + i, e = 0, 1).
   const int64_t nblk = (n + 31) / 32;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * 8;
   int64_t blk = static_cast<int64_t>(blockIdx.x) * 8 + w;
-  using T = typename SQIn<IT>::T;
-  auto rowptr = [&](int64_t b) -> const T* {
-    int64_t row = b * 32 + l32;
+  const int clast = static_cast<int>(d) - kCW;
+  auto rowptr = [&](int64_t b, int rb) -> const T* {
+    int64_t row = b * 32 + 16 * rb + r16;
     if (row >= n) row = n - 1;  // in bounds; the score is not written
-    return x + row * ld + 8 * h;
+    return x + row * ld;
   };
-  // units of kUS K-steps (a block of at most 32 K-steps has kU of them)
-  // through a ring of kU register buffers: a unit's loads are issued kU - 1
-  // units ahead of its products. Loads are unconditional (a block past the
-  // last reads the last block, a K-step past d reads the last K-step), so no
-  // wait is placed at a branch. Measured at the precision shape: BF16 halves
-  // (0.72 ms; quarters 0.73, eighths 0.77), FP8 quarters (0.55 ms; halves
-  // 0.63, eighths 0.58): the defaults; slso_tune chooses per (d, dtype).
-  // Every choice gives the same bits (the K-steps are summed in one order).
-  constexpr int kU = KU;
-  constexpr int kUS = 2 * kSQHalf / kU;  // K-steps per unit
+  // units of kUS load steps through a ring of KU register buffers: a unit's
+  // loads are issued KU - 1 units ahead of its products. Loads are
+  // unconditional (a block past the last reads the last block, a step past
+  // d the last columns of the row), so no wait is placed at a branch; a
+  // lane's columns past d enter the MFMA as zeros. slso_tune chooses KU per
+  // (d, dtype); every choice gives the same bits (the K-steps are summed in
+  // one order).
+  constexpr int kMaxLS = kSQMaxD / kLW;   // load steps at the largest d
+  constexpr int kUS = kMaxLS / KU;        // load steps per unit
   const int64_t blk0 = blk;
-  Raw<IT> Q[kU][kUS];
-  auto issue = [&](Raw<IT> (&buf)[kUS], int64_t u, int q) {
-    int64_t b = blk0 + (u / kU) * stride;
+  uint4 Q[KU][kUS][2];
+  auto issue = [&](uint4 (&buf)[kUS][2], int64_t u, int q) {
+    int64_t b = blk0 + (u / KU) * stride;
     if (b >= nblk) b = nblk - 1;
-    const T* p = rowptr(b);
+    const T* p0 = rowptr(b, 0);
+    const T* p1 = rowptr(b, 1);
 #pragma unroll
     for (int s = 0; s < kUS; ++s) {
-      const int ks = kUS * q + s < steps ? kUS * q + s : steps - 1;
-      buf[s] = load_raw<IT>(p + 16 * ks);
+      int c = kLW * (kUS * q + s) + kCW * g;
+      c = c < clast ? c : clast;
+      buf[s][0] = *reinterpret_cast<const uint4*>(p0 + c);
+      buf[s][1] = *reinterpret_cast<const uint4*>(p1 + c);
     }
   };
-  f16v acc[2];
-  auto compute = [&](const Raw<IT> (&buf)[kUS], int q) {
+  f4v acc[2][4];
+  auto compute = [&](const uint4 (&buf)[kUS][2], int q) {
 #pragma unroll
     for (int s = 0; s < kUS; ++s) {
-      const int ks = kUS * q + s;
-      if (ks < steps) {
-        const bf16x8 a = operand<IT>(buf[s]);
+      const int ls = kUS * q + s;
+      if (ls < nls) {
+        const bool in = kLW * ls + kCW * g + kCW <= d;
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-          const int o = (32 * ct + l32) * pm + 16 * ks + 8 * h;
-          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Ml[o]);
-          acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, acc[ct], 0, 0, 0);
-          if constexpr (NP == 3) {
-            const bf16x8 bm = *reinterpret_cast<const bf16x8*>(&Mm[o]);
-            acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bm, acc[ct], 0, 0, 0);
+        for (int e = 0; e < (IT == 1 ? 1 : 2); ++e) {
+          bf16x8 a0 = operand<IT>(buf[s][0], e);
+          bf16x8 a1 = operand<IT>(buf[s][1], e);
+          if (!in) {
+            a0 = bf16x8{};
+            a1 = bf16x8{};
           }
-          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Mh[o]);
-          acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, acc[ct], 0, 0, 0);
+          const int kb = kLW * ls + kCW * g + 8 * e;
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) {
+            const int o = (16 * ct + r16) * pm + kb;
+            const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Ml[o]);
+            acc[0][ct] = mfma16(a0, bl, acc[0][ct]);
+            acc[1][ct] = mfma16(a1, bl, acc[1][ct]);
+            if constexpr (NP == 3) {
+              const bf16x8 bm = *reinterpret_cast<const bf16x8*>(&Mm[o]);
+              acc[0][ct] = mfma16(a0, bm, acc[0][ct]);
+              acc[1][ct] = mfma16(a1, bm, acc[1][ct]);
+            }
+            const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Mh[o]);
+            acc[0][ct] = mfma16(a0, bh, acc[0][ct]);
+            acc[1][ct] = mfma16(a1, bh, acc[1][ct]);
+          }
         }
       }
     }
   };
   if (blk0 < nblk) {
 #pragma unroll
-    for (int j = 0; j + 1 < kU; ++j) issue(Q[j], j, j);
+    for (int j = 0; j + 1 < KU; ++j) issue(Q[j], j, j);
   }
   int64_t u0 = 0;
-  for (; blk < nblk; blk += stride, u0 += kU) {
+  for (; blk < nblk; blk += stride, u0 += KU) {
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct)
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[ct][e] = 0.0f;
+      for (int ct = 0; ct < 4; ++ct) acc[rb][ct] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int q = 0; q < kU; ++q) {
-      // the buffer the previous unit used takes the unit kU - 1 ahead
-      constexpr int kLast = kU - 1;
-      const int nb = (q + kLast) % kU;
+    for (int q = 0; q < KU; ++q) {
+      // the buffer the previous unit used takes the unit KU - 1 ahead
+      constexpr int kLast = KU - 1;
+      const int nb = (q + kLast) % KU;
       issue(Q[nb], u0 + q + kLast, nb);
       compute(Q[q], q);
     }
-    // l_i = sum over the 64 columns of the squares: register e of lane l
-    // holds row (e % 4) + 8 (e / 4) + 4 h, column l % 32 (+ 32 ct)
-    float v[16];
+    // l_i = sum over the 64 columns of the squares: register v of lane l
+    // of tile (rb, ct) holds row 16 rb + 4 (l / 16) + v, column 16 ct + l % 16
+    float v[8];
 #pragma unroll
-    for (int e = 0; e < 16; ++e)
-      v[e] = acc[0][e] * acc[0][e] + acc[1][e] * acc[1][e];
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int o = 1; o < 32; o <<= 1)
+      for (int e = 0; e < 4; ++e) {
+        float sq = acc[rb][0][e] * acc[rb][0][e];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) v[e] += __shfl_xor(v[e], o, 64);
-    if (l32 < 16) {
-      const int e = l32;
-      const int64_t row = blk * 32 + (e % 4) + 8 * (e / 4) + 4 * h;
+        for (int ct = 1; ct < 4; ++ct) sq += acc[rb][ct][e] * acc[rb][ct][e];
+        v[4 * rb + e] = sq;
+      }
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] += __shfl_xor(v[e], o, 64);
+    if (r16 < 8) {
+      const int e = r16;
+      const int64_t row = blk * 32 + 16 * (e >> 2) + 4 * g + (e & 3);
       float val = v[0];
 #pragma unroll
-      for (int q = 1; q < 16; ++q) val = e == q ? v[q] : val;
+      for (int q = 1; q < 8; ++q) val = e == q ? v[q] : val;
       if (row < n) out[row] = val;
     }
   }
@@ -243,9 +265,9 @@ __global__ void __launch_bounds__(kSQThreads)
 bool score_q_ok(const void* x, int dtype, int format, int64_t d, int64_t ld,
                 int64_t k) {
   if (format != 0 || (dtype != 2 && dtype != 3) || k > 64 || k < 1) return false;
-  if (d % 16 != 0 || d > kSQMaxD || ld % 8 != 0) return false;
-  const uintptr_t a = reinterpret_cast<uintptr_t>(x);
-  return a % (dtype == 2 ? 16 : 8) == 0;
+  // 16-byte loads: 8 BF16 or 16 FP8 codes at a multiple of as many columns
+  if (d % 16 != 0 || d > kSQMaxD || ld % (dtype == 2 ? 8 : 16) != 0) return false;
+  return reinterpret_cast<uintptr_t>(x) % 16 == 0;
 }
 
 size_t score_q_scratch_bytes(int64_t d) {
