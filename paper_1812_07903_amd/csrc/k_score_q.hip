@@ -103,9 +103,10 @@ __device__ __forceinline__ f4v mfma16(bf16x8 a, bf16x8 b, f4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// NP parts of M: mp[0] = Mh, mp[NP - 1] = the smallest part; KU register
-// buffers (units of load steps) per 32-row block
-template <int IT, int NP, int KU>
+// NP parts of M: mp[0] = Mh, mp[NP - 1] = the smallest part; d <= MAXD
+// (sizes the register ring); KU register buffers (units of load steps) per
+// 32-row block
+template <int IT, int NP, int MAXD, int KU>
 __global__ void __launch_bounds__(kSQThreads)
     score_q_kernel(const typename SQIn<IT>::T* __restrict__ x, int64_t n,
                    int64_t d, int64_t ld, const uint16_t* __restrict__ mh,
@@ -163,8 +164,8 @@ __global__ void __launch_bounds__(kSQThreads)
   // lane's columns past d enter the MFMA as zeros. slso_tune chooses KU per
   // (d, dtype); every choice gives the same bits (the K-steps are summed in
   // one order).
-  constexpr int kMaxLS = kSQMaxD / kLW;   // load steps at the largest d
-  constexpr int kUS = kMaxLS / KU;        // load steps per unit
+  constexpr int kMaxLS = (MAXD + kLW - 1) / kLW;  // load steps at d = MAXD
+  constexpr int kUS = (kMaxLS + KU - 1) / KU;      // load steps per unit
   const int64_t blk0 = blk;
   uint4 Q[KU][kUS][2];
   auto issue = [&](uint4 (&buf)[kUS][2], int64_t u, int q) {
@@ -181,36 +182,47 @@ __global__ void __launch_bounds__(kSQThreads)
     }
   };
   f4v acc[2][4];
+  // the products of a unit as a sequence of (step, half, column tile)
+  // items; each item's NP LDS reads of M are issued one item ahead, so their
+  // latency runs under the previous item's MFMAs. Per accumulator the parts
+  // are added smallest first.
+  constexpr int kE = IT == 1 ? 1 : 2;  // K-steps per load step
+  constexpr int kJ = kUS * kE * 4;
+  struct BOp {
+    bf16x8 p[NP];
+  };
+  auto read_b = [&](int j, int q, BOp& b) {
+    const int s = j / (4 * kE), e = (j / 4) % kE, ct = j % 4;
+    const int o = (16 * ct + r16) * pm + kLW * (kUS * q + s) + kCW * g + 8 * e;
+    b.p[0] = *reinterpret_cast<const bf16x8*>(&Ml[o]);
+    if constexpr (NP == 3) b.p[1] = *reinterpret_cast<const bf16x8*>(&Mm[o]);
+    b.p[NP - 1] = *reinterpret_cast<const bf16x8*>(&Mh[o]);
+  };
   auto compute = [&](const uint4 (&buf)[kUS][2], int q) {
+    BOp bb[2];
+    read_b(0, q, bb[0]);
+    bf16x8 a0 = bf16x8{}, a1 = bf16x8{};
 #pragma unroll
-    for (int s = 0; s < kUS; ++s) {
+    for (int j = 0; j < kJ; ++j) {
+      const int s = j / (4 * kE), e = (j / 4) % kE, ct = j % 4;
       const int ls = kUS * q + s;
+      // (nothing moves across: the scheduler would otherwise hoist every
+      // item's reads and run out of registers)
+      __builtin_amdgcn_sched_barrier(0);
+      if (j + 1 < kJ) read_b(j + 1, q, bb[(j + 1) & 1]);
+      if (ct == 0) {
+        a0 = operand<IT>(buf[s][0], e);
+        a1 = operand<IT>(buf[s][1], e);
+        if (kLW * ls + kCW * g + kCW > d) {
+          a0 = bf16x8{};
+          a1 = bf16x8{};
+        }
+      }
       if (ls < nls) {
-        const bool in = kLW * ls + kCW * g + kCW <= d;
 #pragma unroll
-        for (int e = 0; e < (IT == 1 ? 1 : 2); ++e) {
-          bf16x8 a0 = operand<IT>(buf[s][0], e);
-          bf16x8 a1 = operand<IT>(buf[s][1], e);
-          if (!in) {
-            a0 = bf16x8{};
-            a1 = bf16x8{};
-          }
-          const int kb = kLW * ls + kCW * g + 8 * e;
-#pragma unroll
-          for (int ct = 0; ct < 4; ++ct) {
-            const int o = (16 * ct + r16) * pm + kb;
-            const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Ml[o]);
-            acc[0][ct] = mfma16(a0, bl, acc[0][ct]);
-            acc[1][ct] = mfma16(a1, bl, acc[1][ct]);
-            if constexpr (NP == 3) {
-              const bf16x8 bm = *reinterpret_cast<const bf16x8*>(&Mm[o]);
-              acc[0][ct] = mfma16(a0, bm, acc[0][ct]);
-              acc[1][ct] = mfma16(a1, bm, acc[1][ct]);
-            }
-            const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Mh[o]);
-            acc[0][ct] = mfma16(a0, bh, acc[0][ct]);
-            acc[1][ct] = mfma16(a1, bh, acc[1][ct]);
-          }
+        for (int pp = 0; pp < NP; ++pp) {
+          acc[0][ct] = mfma16(a0, bb[j & 1].p[pp], acc[0][ct]);
+          acc[1][ct] = mfma16(a1, bb[j & 1].p[pp], acc[1][ct]);
         }
       }
     }
@@ -294,29 +306,35 @@ void launch_score_q(const void* x, int dtype, int64_t n, int64_t d, int64_t ld,
   if (choice < 0 || choice >= kScoreRingChoices) choice = tune_choice(kTuneScore, d, dtype);
   if (choice < 0) choice = dtype == 2 ? 0 : 1;
   prof_begin(kKScore, s);
-#define SLSO_SQ(IT_, T_, NP_)                                                    \
+#define SLSO_SQ(IT_, T_, NP_, MAXD_)                                             \
   do {                                                                           \
     const T_* xp = static_cast<const T_*>(x);                                    \
     if (choice == 0)                                                             \
-      score_q_kernel<IT_, NP_, 2><<<g, kSQThreads, 0, s>>>(xp, n, d, ld, mh, mm, \
-                                                           ml, scores);          \
+      score_q_kernel<IT_, NP_, MAXD_, 2><<<g, kSQThreads, 0, s>>>(               \
+          xp, n, d, ld, mh, mm, ml, scores);                                     \
     else if (choice == 1)                                                        \
-      score_q_kernel<IT_, NP_, 4><<<g, kSQThreads, 0, s>>>(xp, n, d, ld, mh, mm, \
-                                                           ml, scores);          \
+      score_q_kernel<IT_, NP_, MAXD_, 4><<<g, kSQThreads, 0, s>>>(               \
+          xp, n, d, ld, mh, mm, ml, scores);                                     \
     else                                                                         \
-      score_q_kernel<IT_, NP_, 8><<<g, kSQThreads, 0, s>>>(xp, n, d, ld, mh, mm, \
-                                                           ml, scores);          \
+      score_q_kernel<IT_, NP_, MAXD_, 8><<<g, kSQThreads, 0, s>>>(               \
+          xp, n, d, ld, mh, mm, ml, scores);                                     \
   } while (0)
+  // the ring holds a block's loads at the class's largest d: d <= 128 and
+  // d <= 352 (three parts of M), d <= 512 (two)
   if (dtype == 2) {
-    if (three)
-      SLSO_SQ(1, uint16_t, 3);
+    if (d <= 128)
+      SLSO_SQ(1, uint16_t, 3, 128);
+    else if (three)
+      SLSO_SQ(1, uint16_t, 3, kSQMaxD3);
     else
-      SLSO_SQ(1, uint16_t, 2);
+      SLSO_SQ(1, uint16_t, 2, kSQMaxD);
   } else {
-    if (three)
-      SLSO_SQ(2, uint8_t, 3);
+    if (d <= 128)
+      SLSO_SQ(2, uint8_t, 3, 128);
+    else if (three)
+      SLSO_SQ(2, uint8_t, 3, kSQMaxD3);
     else
-      SLSO_SQ(2, uint8_t, 2);
+      SLSO_SQ(2, uint8_t, 2, kSQMaxD);
   }
 #undef SLSO_SQ
   prof_end(kKScore, s);
