@@ -579,21 +579,23 @@ __global__ void __launch_bounds__(256)
 // so each wave does 40 of the 64 MFMA blocks), then G_k+1,k+1 - X^T X on the
 // upper 16 x 16 blocks only (the factorisation reads no others): three or
 // two blocks per wave. TI holds R_kk^{-1}, TA G_k,k+1; TC receives the
-// updated tile (lower blocks undefined).
+// updated tile (lower blocks undefined) and may be TI, which is read only
+// before the first barrier.
 __device__ __forceinline__ void bchol_lead(const double* TI, double* TA, double* TC,
                                            const double* __restrict__ Gd,
                                            double* __restrict__ Rg, int lane, int w) {
   const int p = lane & 15, q = lane >> 4;
-  // the tile's own blocks, (rb, cb) = kUp[w + 4 u]
-  constexpr int kUpR[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
-  constexpr int kUpC[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+  // the tile's own blocks: upper block w + 4 u of the wave
+  // (rb, cb) of upper block b in row order: (0,0) .. (0,3), (1,1) .. (3,3)
+  auto up_r = [](int b) { return b < 4 ? 0 : b < 7 ? 1 : b < 9 ? 2 : 3; };
+  auto up_c = [](int b) { return b < 4 ? b : b < 7 ? b - 3 : b < 9 ? b - 5 : 3; };
   dbl4 g[3];
 #pragma unroll
   for (int u = 0; u < 3; ++u) {
     const int b = w + 4 * u < 10 ? w + 4 * u : 9;
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      g[u][v] = Gd[(16 * kUpR[b] + 4 * v + q) * kP + 16 * kUpC[b] + p];
+      g[u][v] = Gd[(16 * up_r(b) + 4 * v + q) * kP + 16 * up_c(b) + p];
   }
   dbl4 x[4];
 #pragma unroll
@@ -628,7 +630,7 @@ __device__ __forceinline__ void bchol_lead(const double* TI, double* TA, double*
 #pragma unroll
   for (int u = 0; u < 3; ++u) {
     if (w + 4 * u >= 10) break;
-    const int rb = kUpR[w + 4 * u], cb = kUpC[w + 4 * u];
+    const int rb = up_r(w + 4 * u), cb = up_c(w + 4 * u);
 #pragma unroll
     for (int k0 = 0; k0 < 16; k0 += 8) {
       double a[8], b[8];
@@ -655,10 +657,10 @@ __global__ void __launch_bounds__(256)
                       double* __restrict__ R, double* __restrict__ Dinv,
                       double* __restrict__ X, double* __restrict__ P,
                       int* __restrict__ flag) {
-  __shared__ double TI[kTile];
-  __shared__ double TA[kTile];
-  __shared__ double TB[kTile];
-  __shared__ double TC[kTile];
+  // two tiles of LDS (76 KB with the factorisation's scratch), so two
+  // workgroups share a CU
+  __shared__ double T0[kTile];
+  __shared__ double T1[kTile];
   __shared__ double tmp[4][16][17];
   __shared__ double lim[kP];
   __shared__ int bad;
@@ -669,9 +671,9 @@ __global__ void __launch_bounds__(256)
   if (blockIdx.x >= ntile) {
     const int64_t b = blockIdx.x - ntile;
     if (b < k)
-      xinv_finish(b, k, nb, R, Dinv, X, P, TA, TB, t);
+      xinv_finish(b, k, nb, R, Dinv, X, P, T0, T1, t);
     else
-      xinv_term((b - k) / n, k + 1 + (b - k) % n, k, nb, R, X, P, TA, TB, t);
+      xinv_term((b - k) / n, k + 1 + (b - k) % n, k, nb, R, X, P, T0, T1, t);
     return;
   }
   int64_t i, j;
@@ -680,39 +682,47 @@ __global__ void __launch_bounds__(256)
   j += k + 1;
   const bool diag = i == j;
   if (diag && i == k + 1) {
-    load_tile(TI, Dinv + k * kT2, kP, kP, kP, t);
-    load_tile(TA, G + tix(k, i, nb), kP, kP, kP, t);
+    // T0 = R_kk^{-1}, then the updated tile (R after the factorisation);
+    // T1 = G_k,k+1, then X, then R^{-1} of the tile
+    load_tile(T0, Dinv + k * kT2, kP, kP, kP, t);
+    load_tile(T1, G + tix(k, i, nb), kP, kP, kP, t);
     if (t < kP) lim[t] = tol * gdiag[i * kP + t];
     __syncthreads();
-    bchol_lead(TI, TA, TC, G + tix(i, i, nb), R + tix(k, i, nb), lane, w);
+    bchol_lead(T0, T1, T0, G + tix(i, i, nb), R + tix(k, i, nb), lane, w);
     __syncthreads();
     const int64_t nv = d - i * kP;  // columns of the tile inside the matrix
     const int nblk = nv >= kP ? 4 : static_cast<int>((nv + 15) / 16);
-    if (!chol64b(TC, TI, lim, &bad, tmp, t, nblk)) {
+    if (!chol64b(T0, T1, lim, &bad, tmp, t, nblk)) {
       if (t == 0) *flag = 1;
       return;
     }
-    tile_to_global(R + tix(i, i, nb), TC, t);
-    tile_to_global(Dinv + i * kT2, TI, t);
-    if (X) tile_to_global(X + tix(i, i, nb), TI, t);
+    tile_to_global(R + tix(i, i, nb), T0, t);
+    tile_to_global(Dinv + i * kT2, T1, t);
+    if (X) tile_to_global(X + tix(i, i, nb), T1, t);
     return;
   }
-  load_tile(TI, Dinv + k * kT2, kP, kP, kP, t);
-  load_tile(TA, G + tix(k, i, nb), kP, kP, kP, t);
-  if (!diag) load_tile(TB, G + tix(k, j, nb), kP, kP, kP, t);
+  // G_kj staged in registers while X_i = R_kk^-T G_ki is formed; T1 then
+  // takes it for X_j
+  Stage sb;
+  if (!diag) stage_load(sb, G + tix(k, j, nb), kP, kP, kP, t);
+  load_tile(T0, Dinv + k * kT2, kP, kP, kP, t);
+  load_tile(T1, G + tix(k, i, nb), kP, kP, kP, t);
   dbl4 acc[4];
   ld_acc(acc, G + tix(i, j, nb), lane, w);
   __syncthreads();
   dbl4 xa[4], xb[4];
   zero4(xa);
-  mm64<true>(TI, TA, xa, lane, w);  // X_i = R_kk^{-T} G_ki = R_ki
+  mm64<true>(T0, T1, xa, lane, w);  // X_i = R_kk^{-T} G_ki = R_ki
   if (!diag) {
+    __syncthreads();
+    stage_store(T1, sb, t);
+    __syncthreads();
     zero4(xb);
-    mm64<true>(TI, TB, xb, lane, w);
+    mm64<true>(T0, T1, xb, lane, w);
   }
   __syncthreads();
-  store_acc(TA, xa, 1.0, lane, w);
-  if (!diag) store_acc(TB, xb, 1.0, lane, w);
+  store_acc(T0, xa, 1.0, lane, w);
+  if (!diag) store_acc(T1, xb, 1.0, lane, w);
   if (i == k + 1) {
     if (diag)
       store_acc_global(R + tix(k, j, nb), kP, xa, 1.0, lane, w);
@@ -720,7 +730,7 @@ __global__ void __launch_bounds__(256)
       store_acc_global(R + tix(k, j, nb), kP, xb, 1.0, lane, w);
   }
   __syncthreads();
-  mm64_sub<true>(TA, diag ? TA : TB, acc, lane, w);  // G_ij -= X_i^T X_j
+  mm64_sub<true>(T0, diag ? T0 : T1, acc, lane, w);  // G_ij -= X_i^T X_j
   store_acc_global(G + tix(i, j, nb), kP, acc, 1.0, lane, w);
 }
 
