@@ -147,44 +147,94 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// One wave per bucket; LDS accumulator covering kChunk columns at a time.
+// One wave per bucket, a workgroup of one wave with an LDS accumulator of
+// kCsrChunk FP64 columns (8 KB, so up to twenty workgroups per CU); wider
+// matrices take the columns in chunks, each reading the bucket's rows again
+// (from L2; at d = 4096, 1024 columns measured faster than 512, 2048 or all
+// 4096 at once). Lane q first reads the extent and sign of the
+// bucket's row p0 + q (the rows in groups of 64), so the rows' CSR offsets
+// arrive in one round trip; the first 64 entries of eight rows (one per
+// lane) are loaded together, then added row by row, so every column
+// receives its rows' values in bucket order (the columns of one row are
+// distinct, and the wave's LDS updates take effect in program order).
 constexpr int kCsrChunk = 1024;
 
-__global__ void __launch_bounds__(256)
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int l) {
+  const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(v), l);
+  const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(v >> 32), l);
+  return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+__global__ void __launch_bounds__(64)
     countsketch_csr_kernel(const int64_t* __restrict__ row_ptr,
                            const int32_t* __restrict__ col_idx,
-                           const float* __restrict__ val, int64_t d,
-                           const uint32_t* __restrict__ sorted_vals,
+                           const float* __restrict__ val, int64_t n,
+                           int64_t d, const uint32_t* __restrict__ sorted_vals,
                            const int32_t* __restrict__ off, int64_t r,
                            const double* __restrict__ dscale,
                            double* __restrict__ sx, double sscale) {
-  __shared__ double acc_all[4][kCsrChunk];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  double* acc = acc_all[wave];
-  const int64_t b = static_cast<int64_t>(blockIdx.x) * 4 + wave;
+  __shared__ double acc[kCsrChunk];
+  const int lane = threadIdx.x;
+  const int64_t b = blockIdx.x;
   if (b >= r) return;
   const int p0 = off[b], p1 = off[b + 1];
+  // with no entries at all there is no index to clamp the loads to
+  const bool any = row_ptr[n] > 0;
   for (int64_t c0 = 0; c0 < d; c0 += kCsrChunk) {
-    const int64_t c1 = c0 + kCsrChunk < d ? c0 + kCsrChunk : d;
-    for (int c = lane; c < kCsrChunk; c += 64) acc[c] = 0.0;
-    for (int p = p0; p < p1; ++p) {
-      const uint32_t v = sorted_vals[p];
-      const int64_t row = static_cast<int64_t>(v & 0x7fffffffu);
-      const bool neg = (v >> 31) != 0;
-      const int64_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
-      // columns are distinct within a row: no two lanes of one pass collide,
-      // and successive rows are applied in program order by this wave
-      for (int64_t e = e0 + lane; e < e1; e += 64) {
-        const int64_t c = col_idx[e];
-        if (c >= c0 && c < c1) {
-          const double xv = static_cast<double>(val[e]);
-          acc[c - c0] += neg ? -xv : xv;
+    const int nc = static_cast<int>(d - c0 < kCsrChunk ? d - c0 : kCsrChunk);
+    for (int c = lane; c < nc; c += 64) acc[c] = 0.0;
+    for (int pg = p0; any && pg < p1; pg += 64) {
+      const int np = p1 - pg < 64 ? p1 - pg : 64;
+      int64_t e0 = 0, e1 = 0;
+      uint32_t sg = 0;
+      if (lane < np) {
+        const uint32_t v = sorted_vals[pg + lane];
+        const int64_t row = static_cast<int64_t>(v & 0x7fffffffu);
+        sg = v >> 31;
+        e0 = row_ptr[row];
+        e1 = row_ptr[row + 1];
+      }
+      // entry e0_q + lane of row q (clamped into the row, or to entry 0 for
+      // an empty row; lanes past its length add nothing); rows in batches of
+      // eight, the batch's loads issued together, then its rows added in order
+      constexpr int kB = 8;
+      for (int qb = 0; qb < np; qb += kB) {
+        int32_t cb[kB];
+        float xb[kB];
+        bool ib[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          const int q = qb + u < np ? qb + u : np - 1;
+          const int64_t qe0 = readlane_i64(e0, q), qe1 = readlane_i64(e1, q);
+          const int64_t e = qe0 + lane;
+          ib[u] = qb + u < np && e < qe1;
+          const int64_t ec = e < qe1 ? e : (qe1 > qe0 ? qe1 - 1 : 0);
+          cb[u] = col_idx[ec];
+          xb[u] = val[ec];
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          const int q = qb + u;
+          if (q >= np) break;
+          const bool neg = __builtin_amdgcn_readlane(sg, q) != 0u;
+          if (ib[u] && cb[u] >= c0 && cb[u] < c0 + nc) {
+            const double xv = static_cast<double>(xb[u]);
+            acc[cb[u] - c0] += neg ? -xv : xv;
+          }
+          // a row longer than 64 entries: the rest in order
+          const int64_t qe0 = readlane_i64(e0, q), qe1 = readlane_i64(e1, q);
+          for (int64_t e = qe0 + 64 + lane; e < qe1; e += 64) {
+            const int64_t c = col_idx[e];
+            if (c >= c0 && c < c0 + nc) {
+              const double xv = static_cast<double>(val[e]);
+              acc[c - c0] += neg ? -xv : xv;
+            }
+          }
         }
       }
     }
-    for (int64_t c = c0 + lane; c < c1; c += 64)
-      sx[b * d + c] = acc[c - c0] * sscale * (dscale ? dscale[c] : 1.0);
+    for (int c = lane; c < nc; c += 64)
+      sx[b * d + c0 + c] = acc[c] * sscale * (dscale ? dscale[c0 + c] : 1.0);
   }
 }
 
@@ -489,15 +539,14 @@ void launch_countsketch(const void* x, int dtype, int format, int64_t n,
                         const int32_t* offsets, int64_t r,
                         const double* dscale, double* sx, hipStream_t s,
                         double sscale) {
-  (void)n;
   (void)col_scale;
   (void)row_scale;
   const unsigned grid = grid1(r, 4);
   if (format == 1) {
     prof_begin(kKSketch, s);
-    countsketch_csr_kernel<<<grid, 256, 0, s>>>(
-        row_ptr, col_idx, static_cast<const float*>(x), d, sorted_vals, offsets,
-        r, dscale, sx, sscale);
+    countsketch_csr_kernel<<<static_cast<unsigned>(r), 64, 0, s>>>(
+        row_ptr, col_idx, static_cast<const float*>(x), n, d, sorted_vals,
+        offsets, r, dscale, sx, sscale);
     prof_end(kKSketch, s);
     return;
   }

@@ -131,6 +131,42 @@ def test_countsketch_csr_bit_exact(slso, ctx, n, d, r):
     assert np.array_equal(sx, osk.countsketch_csr(c, 8, r))
 
 
+def _csr_rows(n, d, lengths, seed):
+    """CSR with the given row lengths (distinct sorted columns per row)."""
+    rng = np.random.default_rng(seed)
+    cols = [np.sort(rng.choice(d, int(m), replace=False)) for m in lengths]
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum([len(c) for c in cols], out=row_ptr[1:])
+    col_idx = np.concatenate(cols).astype(np.int32) if row_ptr[-1] else \
+        np.zeros(0, np.int32)
+    val = rng.standard_normal(col_idx.size).astype(np.float32)
+    return synth.Csr(n, d, row_ptr, col_idx, val)
+
+
+@pytest.mark.parametrize("n,d", [(9000, 4500), (8192, 4096), (30000, 300)])
+def test_countsketch_csr_long_and_empty_rows(slso, ctx, n, d):
+    """Rows of 0, 1, 63-65 and up to 300 entries (r = d); columns in one
+    chunk (d <= 4096) or two (d = 4500, ragged second chunk); at d = 300
+    about 100 rows per bucket (more than one group of 64): the sketch equals
+    the oracle's bit for bit."""
+    rng = np.random.default_rng(d)
+    lengths = rng.choice([0, 1, 5, 63, 64, 65, 129, 300], size=n,
+                         p=[0.15, 0.2, 0.25, 0.1, 0.1, 0.1, 0.05, 0.05])
+    c = _csr_rows(n, d, np.minimum(lengths, d), seed=d + 1)
+    sx = host(ctx.sketch(csr_dev(slso, c), 8, d))
+    assert np.array_equal(sx, osk.countsketch_csr(c, 8, d))
+
+
+def test_countsketch_csr_all_rows_empty(slso, ctx):
+    """row_ptr all zero (one unused entry so that col_idx is not null): the
+    sketch is zero and no entry is read."""
+    n, d = 1000, 50
+    x = slso.CsrMatrix(n, d, dev(np.zeros(n + 1, np.int64)),
+                       dev(np.zeros(1, np.int32)), dev(np.ones(1, np.float32)))
+    sx = host(ctx.sketch(x, 8, 64))
+    assert sx.shape == (64, d) and not sx.any()
+
+
 # ---- OSNAP ---------------------------------------------------------------------
 @pytest.mark.parametrize("n,d,r,nnz", [(5000, 64, 512, 2), (3001, 33, 510, 3),
                                        (2000, 70, 1024, 4), (1, 1, 16, 16),
