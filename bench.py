@@ -64,7 +64,8 @@ def log(msg: str) -> None:
 
 # ---- rooflines ----------------------------------------------------------------
 # per workload: the committed PMC summary and, per profiler name, the kernel
-# symbol in it (the BF16 / FP32 form that the bench line's roofline times)
+# symbol in it (the BF16 / FP32 form that the bench line's roofline times;
+# for the scoring the two-buffer ring: every ring reads the same bytes)
 PMC_SUMMARIES = {
     "image": ("pmc_traffic_image_like_n60000_d784.txt", {
         "cq2_gram": "gram_block_kernel<false,true>",
@@ -74,11 +75,11 @@ PMC_SUMMARIES = {
     "precision_bf16": ("pmc_traffic_precision_n4000000_d512.txt", {
         "gauss_sketch": "gauss_q_kernel<1,true>",
         "gram": "gram_q_kernel<1,true>",
-        "score": "score_q_kernel<1,2>"}),
+        "score": "score_q_kernel<1,2,512,2>"}),
     "precision_fp8": ("pmc_traffic_precision_n4000000_d512.txt", {
         "gauss_sketch": "gauss_q_kernel<2,true>",
         "gram": "gram_q_kernel<2,true>",
-        "score": "score_q_kernel<2,2>"}),
+        "score": "score_q_kernel<2,2,512,2>"}),
     "precision_f32": ("pmc_traffic_precision_n4000000_d512.txt", {
         "gauss_sketch": "gauss_sketch_kernel",
         "score": "score_mfma_kernel<3,true>"}),
