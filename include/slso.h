@@ -298,8 +298,7 @@ int slso_leverage_finish(slso_ctx* ctx, slso_info* info);
  * launch without an entry takes the default.
  *   SLSO_TUNE_SCORE: scoring of dense BF16 / FP8 input (d a multiple of 16 up
  *     to 512, k <= 64), rows taken through a ring of 2, 4 or 8 register
- *     buffers per 32-row block (choices 0, 1, 2; default 0 for BF16, 1 for
- *     FP8).
+ *     buffers per 32-row block (choices 0, 1, 2; default 0).
  *   SLSO_TUNE_COUNTSKETCH: the CountSketch / OSNAP gather of dense F32, BF16
  *     or FP8 input with rows on 4-element boundaries, rows in flight per
  *     bucket wave (choice 0 fewer, 1 more; default 1). */

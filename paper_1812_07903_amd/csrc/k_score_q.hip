@@ -302,9 +302,11 @@ void launch_score_q(const void* x, int dtype, int64_t n, int64_t d, int64_t ld,
   int64_t grid = (nblk + 7) / 8;
   if (grid > 256) grid = 256;
   const unsigned g = static_cast<unsigned>(grid);
-  // register ring: choice 0, 1, 2 = 2, 4, 8 units per block
+  // register ring: choice 0, 1, 2 = 2, 4, 8 units per block; untuned, two
+  // (the fastest for BF16 and FP8 at the precision shape: 0.75 / 0.50 ms
+  // against 0.80-0.84 / 0.56 ms)
   if (choice < 0 || choice >= kScoreRingChoices) choice = tune_choice(kTuneScore, d, dtype);
-  if (choice < 0) choice = dtype == 2 ? 0 : 1;
+  if (choice < 0) choice = 0;
   prof_begin(kKScore, s);
 #define SLSO_SQ(IT_, T_, NP_, MAXD_)                                             \
   do {                                                                           \
