@@ -479,6 +479,29 @@ def test_scores_csr(slso, ctx):
     assert omet.max_rel_err(got, ref) < 1e-6
 
 
+@pytest.mark.parametrize("k", [1, 64, 100])
+def test_scores_csr_long_and_empty_rows(slso, ctx, k):
+    """CSR rows of 0 to 500 entries (several groups of 64 per row) and k
+    over one or two groups of 64 columns: each score is a sum of FP64
+    products of the FP32 entries and M in FP32, so the error is M's rounding
+    to FP32: |l - l_ref| <= 1e-6 sum_c (sum_j |x_ij M_jc|)^2 (a single
+    column can cancel, so relative error is bounded only for k >= 16);
+    empty rows score exactly zero."""
+    n, d = 3000, 500
+    rng = np.random.default_rng(k)
+    lengths = rng.choice([0, 1, 63, 64, 65, 128, 300, 500], size=n)
+    c = _csr_rows(n, d, lengths, seed=k + 7)
+    m = rng.standard_normal((d, k)) / np.sqrt(d)
+    got = host(ctx.scores(csr_dev(slso, c), dev(m)))
+    ref = olv.row_scores(c, m)
+    empty = np.diff(c.row_ptr) == 0
+    assert np.all(got[empty] == 0.0)
+    bound = ((np.abs(c.to_dense()) @ np.abs(m)) ** 2).sum(axis=1)
+    assert np.all(np.abs(got - ref) <= 1e-6 * bound)
+    if k >= 16:
+        assert omet.max_rel_err(got[~empty], ref[~empty]) < 1e-6
+
+
 # ---- sampling policies (Algorithm 4 step 4) ---------------------------------------
 @pytest.mark.parametrize("n", [1, 2, 3000, 65537])
 @pytest.mark.parametrize("epoch", [0, 7])
